@@ -1,0 +1,216 @@
+"""Benchmark of the TU-fRG right-hand side on one MI355X.
+
+Workload: lattice Rashba model (t=1, mu=-0.4, alpha=0.3, onsite U=2.5), 9 form
+factors (bundle dimension 36), 24x24 q-mesh refined 24x per cell (576^2 fine
+k-points), Omega cutoff; loops and bundle products in FP32, state in FP64.
+
+One step = one explicit Euler step of the flow through the C ABI: regulator
+values, both loop channels, the real-space transform, gathers and assembly of
+the projected vertices, both bundle products, the FP64 state update and the
+max-coupling readback (tufrg_flow with n_steps = K).  Inputs are resident in
+HBM before the timed region.
+
+Printed: one JSON line with the headline value (loop entries/s over the whole
+step), flow steps/s, the same for the FP64-plain form and the relative error of
+the FP32 state against it, the roofline of the loop kernel (event-timed inside
+the library over the timed region), the production Dormand-Prince flow, and a
+CPU baseline of the FP64 oracle on a sample of q points.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "loop entries/s + flow steps/s, mixed/surrogate vs FP64-plain at ≤1e-4 rel err"
+WORKLOAD = "rashba_s9_L24"
+# algorithmic FP32 flops of the loop kernel per (q, k, channel) for two
+# spin-orbitals and the 3 x 5 (dx >= 0, dy) phase box; derivation in the design doc
+LOOP_FLOPS_PER_PAIR = 368
+PEAK_FP32_VECTOR = 157.3e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "loop_kernel_traffic_rashba_s9_L24.json")
+
+
+def _loop_source_hash():
+    h = hashlib.sha256()
+    for f in ("k_loop.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_1710_08830_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _traffic(launches_per_step):
+    """HBM bytes per loop-kernel launch from committed rocprofv3 counters, or
+    None when the kernel source changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != _loop_source_hash():
+        return None
+    return float(t["hbm_bytes_per_launch"])
+
+
+def cpu_baseline(w, n_sample=4):
+    """FP64 oracle (single thread) on a sample of q points: both loop channels,
+    the projections of the whole state (charged pro rata) and the bundle
+    products at the sampled q."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import tufrg as otu
+
+    with threadpool_limits(limits=1):
+        st = otu.TUSetup.from_workload(w)
+        rng = np.random.default_rng(0)
+        qs = sorted(rng.choice(st.Nq, size=n_sample, replace=False).tolist())
+        P = np.zeros((st.Nq, st.n_ff, st.n_ff) + (st.n_o,) * 4, dtype=np.complex128)
+        C = np.zeros_like(P)
+        lam = 1.0
+        t0 = time.perf_counter()
+        VP, VC = otu.projected_vertices(st, P, C)
+        t_proj = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        Lpp = otu.loops(st, "pp", lam, q_list=qs)
+        Lph = otu.loops(st, "ph", lam, q_list=qs)
+        otu.bundle_pp(VP[qs], Lpp)
+        otu.bundle_ph(VC[qs], Lph)
+        t_q = time.perf_counter() - t0
+    B = st.n_ff * st.n_o ** 2
+    t_eff = t_q + t_proj * n_sample / st.Nq
+    return {"value": 2.0 * B * B * n_sample / t_eff, "unit": "loop entries/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_sample} of {st.Nq} q points (both channels, loops + bundle), "
+                      f"projections of all q charged pro rata; {t_eff:.1f} s of CPU time"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the FP32 steps only (for profiler runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (scales HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the q-sharded multi-GPU "
+              "path is a design, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1710_08830_amd import tufrg as T
+    from synth import workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = 1 << 30
+        x = torch.ones(n // 8, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}))
+        return
+    w = workload(WORKLOAD)
+    K, W = args.steps, args.warmup
+    lam0, lam_mid = 10.0, 1.0
+
+    def make(prec):
+        ctx = T.Context.from_workload(w, precision=prec)
+        P = torch.zeros((ctx.Nq, ctx.B, ctx.B), dtype=torch.complex128, device=dev)
+        return ctx, P, torch.zeros_like(P)
+
+    def timed_steps(ctx, P, C, timing):
+        # warmup: W steps of the same grid; then K steps from the start state
+        if W > 0:
+            T.tufrg_flow(ctx, P, C, lam0, lam_mid, n_steps=W, v_max=1e30)
+        P.zero_()
+        C.zero_()
+        torch.cuda.synchronize()
+        if timing:
+            T.tufrg_timing(ctx, True)
+        t0 = time.perf_counter()
+        res = T.tufrg_flow(ctx, P, C, lam0, lam_mid, n_steps=K, v_max=1e30)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        loop_ms = loop_n = None
+        if timing:
+            loop_ms, loop_n = T.tufrg_timing_read(ctx, T.TIMER_LOOP)
+            T.tufrg_timing(ctx, False)
+        return dt, res, loop_ms, loop_n
+
+    ctx32, P32, C32 = make("fp32")
+    dt32, res32, loop_ms, loop_n = timed_steps(ctx32, P32, C32, timing=True)
+    B, Nq, Nf = ctx32.B, ctx32.Nq, ctx32.Nf
+    entries = 2.0 * Nq * B * B
+    value = entries * K / dt32
+    loop_avg_s = loop_ms / loop_n * 1e-3
+    flops_launch = 2.0 * Nq * Nf * LOOP_FLOPS_PER_PAIR
+    achieved = flops_launch / loop_avg_s
+    traffic = _traffic(1)
+    out = {
+        "metric": METRIC, "value": value, "unit": "loop entries/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": dt32 / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "model": "lattice Rashba t=1 mu=-0.4 alpha=0.3 U=2.5",
+                   "n_orb": 2, "n_ff": 9, "B": B, "Lq": 24, "n_ref": 24, "Nq": Nq, "Nf": Nf,
+                   "cutoff": "omega", "step": "Euler step: loops + projections + bundles + update",
+                   "parallelism": "single GPU"},
+        "flow_steps_per_s": K / dt32,
+        "loop_kernel_ms": loop_avg_s * 1e3,
+        "loop_entries_per_s_kernel": entries / loop_avg_s,
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
+                     "traffic": traffic},
+    }
+    if not args.no_extras:
+        ctx64, P64, C64 = make("fp64")
+        dt64, res64, l64_ms, l64_n = timed_steps(ctx64, P64, C64, timing=True)
+        ref = P64.abs().max().item(), C64.abs().max().item()
+        err = max((P32 - P64).abs().max().item() / ref[0], (C32 - C64).abs().max().item() / ref[1])
+        out["fp64_plain"] = {"value": entries * K / dt64, "ms_per_step": dt64 / K * 1e3,
+                             "loop_kernel_ms": l64_ms / l64_n, "flow_steps_per_s": K / dt64}
+        out["speedup_fp32_vs_fp64"] = dt64 / dt32
+        out["rel_err_fp32_vs_fp64"] = err
+        # production integrator: Dormand-Prince 5(4), rtol = atol = 1e-6, 10 -> 1e-4
+        dp = {}
+        for name, (ctx, P, C) in (("fp32", (ctx32, P32, C32)), ("fp64", (ctx64, P64, C64))):
+            P.zero_()
+            C.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = T.tufrg_flow(ctx, P, C, w["lam0"], w["lam_end"], n_steps=0, rtol=w["rtol"],
+                             atol=w["atol"], v_max=w["v_max"], max_steps=400)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            dp[name] = dict(r, seconds=dt, flow_steps_per_s=r["n_steps"] / dt,
+                            rhs_per_s=r["n_rhs"] / dt)
+        refP, refC = P64.abs().max().item(), C64.abs().max().item()
+        same_stop = dp["fp32"]["n_steps"] == dp["fp64"]["n_steps"]
+        if same_stop:
+            dp["rel_err_fp32_vs_fp64"] = max((P32 - P64).abs().max().item() / refP,
+                                             (C32 - C64).abs().max().item() / refC)
+        if dp["fp64"]["diverged"] and dp["fp32"]["diverged"]:
+            dp["lambda_c_rel_err"] = abs(dp["fp32"]["lambda_c"] / dp["fp64"]["lambda_c"] - 1.0)
+        out["dp54_flow"] = dp
+        ctx64.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w)
+    ctx32.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

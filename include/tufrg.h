@@ -1,0 +1,195 @@
+/*
+ * tufrg.h -- C ABI of the MI355X truncated-unity fRG right-hand side.
+ *
+ * The library evaluates the right-hand side of the truncated-unity fRG flow
+ * of multiband systems without SU(2) symmetry (Schober, Ehrlich, Reckling,
+ * Honerkamp, arXiv:1710.08830) in the orbital/spin basis, and integrates it:
+ *
+ *   dP(s)/dLambda = VP(s) Lpp(s) VP(s)            (Sec. 3.1 matrix RGE for P,
+ *   dC(u)/dLambda = 2 VC(u) Lph(u) VC(u)           orbital form of Sec. 4.2)
+ *
+ * with the projected vertices VP = P[V0] + P + P[V^C] + P[V^D] and
+ * VC = C[V0] + C[V^P] + C + C[V^D] of Sec. 3.3, and D = -C with the last two
+ * orbital indices exchanged (Sec. 3.2), so only P and C are stored.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions
+ *
+ * Meshes.  Momentum transfers q run over the coarse mesh q = 2 pi (mx, my)/Lq,
+ * linear index mx * Lq + my, Nq = Lq^2.  Loops average over the refined mesh
+ * k = 2 pi (kx, ky) / Lf with Lf = n_ref * Lq (coarse point m is fine point
+ * n_ref * m, so k +- q stays on the fine mesh), Nf = Lf^2.
+ *
+ * Form factors.  Plane waves f_R(k) = exp(-i k.R) (Sec. 2 and Sec. 3.3), labelled
+ * by the bond vectors R of the list ff_R; ff_R[0] must be (0, 0), the list must
+ * be closed under R -> -R, and |R_x|, |R_y| <= 2.
+ *
+ * Bundle layout.  With n_o spin-orbitals and n_ff form factors the bundle
+ * dimension is B = n_ff * n_o^2, and a row or column index is
+ * i = r * n_o^2 + a * n_o + b (form factor r, orbitals a, b).  The exchange
+ * propagators are complex B x B matrices per coarse q:
+ *     P[q][(R,a,b)][(R',c,d)] = P^{RR'}_{a b d c}(q)    rows n1 n2, columns n4 n3
+ *     C[q][(R,a,b)][(R',c,d)] = C^{RR'}_{a d b c}(q)    rows n1 n3, columns n4 n2
+ * so that the matrix RGE above is a plain product of B x B matrices, and the
+ * hermiticity of the projections (Sec. 2, property 3) is matrix hermiticity.
+ * Arrays are row-major [Nq][B][B] of tufrg_c64.
+ *
+ * Loops.  Lpp and Lph are the orbital loop matrices
+ *   Lpp(s)[(R1,a,b),(R2,c,d)] = 1/Nf sum_k e^{-ik.(R1-R2)}
+ *        sum_mn Pi_m(k)_ac Pi_n(s-k)_bd L-(e_m(k), e_n(s-k))
+ *   Lph(u)[(R1,a,b),(R2,c,d)] = 1/Nf sum_k e^{-ik.(R1-R2)}
+ *        sum_mn Pi_m(k)_ac Pi_n(k-u)_db L+(e_m(k), e_n(k-u))
+ * with e_m = E_m - mu and Pi_m(k) = U_m U_m^dagger the band projectors of H(k)
+ * (Sec. 4.1).  L-/+ = d/dLambda of the regulated bubbles F-/+ of Sec. 3.1:
+ * the temperature flow (Lambda = T) or the Omega scheme at T = 0 (propagator
+ * times w^2 / (w^2 + Omega^2)).
+ *
+ * Interaction.  V0 is the antisymmetric onsite initial vertex V0[n1][n2][n3][n4]
+ * in the normalisation H_int = 1/2 sum V0_{1234} c+_1 c+_2 c_4 c_3 (the onsite
+ * Hubbard vertex of Sec. 5 is U/2 (d13 d24 - d14 d23)).  Its projections fill
+ * the (0,0) form-factor block only.
+ *
+ * ---------------------------------------------------------------------------
+ * Ownership, execution, errors
+ *
+ * Model and setup arrays are host memory, read during tufrg_create only.
+ * Every P, C, VP, VC, L, dP, dC argument is DEVICE memory allocated by the
+ * caller (e.g. a torch tensor of dtype complex128); the library never frees
+ * caller memory.  A host pointer is rejected with TUFRG_E_INVAL.  The context
+ * owns its band data, tables and workspaces.
+ *
+ * All calls are enqueued on the stream given to tufrg_create and are
+ * asynchronous, except tufrg_create (synchronous) and tufrg_flow, which
+ * synchronises once per step to read back the stop test (a few bytes).
+ * A context must be used by one host thread at a time.  No exception or abort
+ * crosses the ABI: failures return a status, and tufrg_last_error() returns a
+ * message (per context, or the calling thread's last create failure for NULL).
+ * Divergence of a flow is a result (diverged = 1), not an error.
+ */
+#ifndef TUFRG_H
+#define TUFRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tufrg_ctx tufrg_ctx;
+
+/* binary-compatible with C99 double _Complex and torch.complex128 */
+typedef struct {
+  double re, im;
+} tufrg_c64;
+
+typedef enum {
+  TUFRG_OK = 0,
+  TUFRG_E_INVAL = 1,       /* bad argument (null, host pointer, unsupported shape) */
+  TUFRG_E_NOMEM = 2,       /* device allocation failed */
+  TUFRG_E_HIP = 3,         /* a HIP runtime call failed */
+  TUFRG_E_NONFINITE = 4,   /* NaN or Inf in the state during a flow */
+  TUFRG_E_STEPSIZE = 5,    /* adaptive step size underflow */
+  TUFRG_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+} tufrg_status;
+
+typedef enum { TUFRG_CUT_TEMPERATURE = 0, TUFRG_CUT_OMEGA = 1 } tufrg_cutoff;
+
+/* Arithmetic of the loops and bundle products; the state and its updates are
+ * always FP64.  TUFRG_FP32 accumulates each loop k-chunk in FP32 and sums
+ * chunks in FP64. */
+typedef enum { TUFRG_FP64 = 0, TUFRG_FP32 = 1 } tufrg_precision;
+
+typedef enum { TUFRG_PP = 0, TUFRG_PH = 1 } tufrg_channel;
+
+typedef struct {
+  int32_t n_orb;           /* spin-orbitals n_o (this build: 2) */
+  int32_t n_hop;           /* hopping vectors */
+  const int32_t *hop_R;    /* [n_hop][2] lattice vectors R */
+  const tufrg_c64 *hop_t;  /* [n_hop][n_o][n_o]: H(k) = sum_R t(R) e^{i k.R}; t(-R) = t(R)^dagger */
+  double mu;               /* chemical potential */
+  const tufrg_c64 *V0;     /* [n_o]^4 antisymmetric onsite vertex, order n1 n2 n3 n4 */
+} tufrg_model;
+
+typedef struct {
+  int32_t n_ff;            /* number of form factors */
+  const int32_t *ff_R;     /* [n_ff][2], ff_R[0] = (0,0), closed under negation, |R_x|,|R_y| <= 2 */
+  int32_t Lq;              /* coarse mesh; must exceed 4 max|R| (no aliasing in R'' = R1 - R2) */
+  int32_t n_ref;           /* refinement of the loop mesh, Lf = n_ref Lq <= 4096 */
+  int32_t cutoff;          /* tufrg_cutoff */
+  int32_t precision;       /* tufrg_precision */
+} tufrg_setup;
+
+/* Builds meshes, tables and the band data (eigendecomposition of H(k) - mu on
+ * the fine mesh, FP64, on the device).  stream: a hipStream_t or NULL. */
+tufrg_status tufrg_create(const tufrg_model *model, const tufrg_setup *setup, void *stream, tufrg_ctx **out);
+tufrg_status tufrg_destroy(tufrg_ctx *ctx);
+const char *tufrg_last_error(const tufrg_ctx *ctx);
+
+/* Sizes: B, Nq, Nf, and the number of distinct R1 - R2 differences. */
+tufrg_status tufrg_dims(const tufrg_ctx *ctx, int32_t *B, int32_t *Nq, int32_t *Nf, int32_t *n_dR);
+
+/* Band data (row a0 of the hot path, built by tufrg_create): e[m][k] = E_m(k) - mu
+ * (ascending in m) and the projectors Pi[m][k][a][c] = U_am(k) conj(U_cm(k)),
+ * k = kx * Lf + ky.  Device arrays of n_o * Nf doubles and n_o * Nf * n_o^2
+ * tufrg_c64. */
+tufrg_status tufrg_band_data(tufrg_ctx *ctx, double *e, tufrg_c64 *Pi);
+
+/* Loop matrices of one channel at scale lambda for every coarse q:
+ * L[q][B][B] in the bundle layout (see above).  deriv = 1: L-/+ = dF/dLambda
+ * (the loops of the RGE); deriv = 0: the bubbles F-/+ themselves. */
+tufrg_status tufrg_bubble(tufrg_ctx *ctx, int32_t channel, double lambda, int32_t deriv, tufrg_c64 *L);
+
+/* Projected vertices VP, VC [Nq][B][B] of the state P, C [Nq][B][B] (Sec. 3.3). */
+tufrg_status tufrg_project(tufrg_ctx *ctx, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,
+                           tufrg_c64 *VC);
+
+/* Right-hand side dP/dLambda, dC/dLambda [Nq][B][B] at scale lambda.
+ * P, C and dP, dC must not overlap. */
+tufrg_status tufrg_rhs(tufrg_ctx *ctx, double lambda, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *dP,
+                       tufrg_c64 *dC);
+
+typedef struct {
+  double lambda0, lambda_end; /* flow from lambda0 down to lambda_end > 0 */
+  int32_t n_steps;            /* > 0: explicit Euler in Lambda on the log grid
+                                 Lambda_i = lambda0 (lambda_end/lambda0)^(i/n); 0: Dormand-Prince 5(4)
+                                 in ln Lambda with the error norm
+                                 max |err| / (atol + rtol max(|X|, |X_new|)) over real and imaginary
+                                 parts, step factor clip(0.9 err^-1/5, 0.2, 5), first |h| = h0 */
+  double rtol, atol, h0;
+  double v_max;               /* stop when max(|P|, |C|) > v_max */
+  uint32_t channel_mask;      /* bit 0: flow P, bit 1: flow C (a masked channel keeps its value) */
+  int32_t max_steps;          /* 0: no limit */
+  /* optional per-step callback (accepted steps); a nonzero return stops the
+   * flow cleanly with the state of that step */
+  int32_t (*on_step)(void *user, int32_t step, double lambda, double max_coupling);
+  void *user;
+} tufrg_flow_opts;
+
+typedef struct {
+  double lambda_stop;   /* scale of the returned state */
+  double lambda_c;      /* where max(|P|,|C|) crossed v_max, linear in ln Lambda between the
+                           bracketing accepted steps; 0 if the flow did not diverge */
+  double max_coupling;  /* max(|P|, |C|) of the returned state */
+  int32_t diverged, n_steps, n_rhs, n_reject, stopped_by_callback;
+} tufrg_flow_result;
+
+/* Integrates P, C [Nq][B][B] (device, in place) from opts->lambda0. */
+tufrg_status tufrg_flow(tufrg_ctx *ctx, const tufrg_flow_opts *opts, tufrg_c64 *P, tufrg_c64 *C,
+                        tufrg_flow_result *result);
+
+/* Optional per-kernel timing with HIP events recorded on the context stream
+ * around the launches of one part of the right-hand side:
+ *   TUFRG_TIMER_LOOP     the loop kernel launch (both channels in one launch)
+ *   TUFRG_TIMER_PROJECT  real-space transform, gathers and assembly
+ *   TUFRG_TIMER_BUNDLE   the two bundle products
+ * tufrg_timing(ctx, 1) synchronises, clears and enables; tufrg_timing_read
+ * synchronises and returns the accumulated milliseconds and interval count. */
+enum { TUFRG_TIMER_LOOP = 0, TUFRG_TIMER_PROJECT = 1, TUFRG_TIMER_BUNDLE = 2, TUFRG_TIMER_COUNT = 3 };
+tufrg_status tufrg_timing(tufrg_ctx *ctx, int32_t enable);
+tufrg_status tufrg_timing_read(tufrg_ctx *ctx, int32_t timer, double *total_ms, int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TUFRG_H */

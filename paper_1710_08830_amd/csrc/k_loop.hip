@@ -1,0 +1,356 @@
+// Form-factor projected orbital loops (hot path).
+//
+// Loop matrices in the orbital basis (the paper's Sec. 3.1 loop matrices with
+// the orbital-basis loop of Sec. 4.2, written as a direct k-sum on the refined
+// mesh), in the bundle layout of the library:
+//
+//   Lpp(s)[(R1,a,b),(R2,c,d)] = 1/Nf sum_k e^{-ik.(R1-R2)}
+//        sum_mn Pi_m(k)_ac Pi_n(s-k)_bd L-(e_m(k), e_n(s-k))
+//   Lph(u)[(R1,a,b),(R2,c,d)] = 1/Nf sum_k e^{-ik.(R1-R2)}
+//        sum_mn Pi_m(k)_ac Pi_n(k-u)_db L+(e_m(k), e_n(k-u))
+//
+// Both depend on R1, R2 only through dR = R1 - R2, so the kernel produces the
+// compact loop  Lc(q)[dR][tau],  tau = (a, b, c, d) flattened.
+//
+// Two spin-orbitals (this kernel):
+// * Completeness, Pi_1 = 1 - Pi_0, gives with X_n the projector at k' (its
+//   transpose for ph) and alpha_m = L_m0 - L_m1:
+//     W_m = sum_n L_mn X_n = alpha_m X_0 + L_m1 1,  M = sum_m Pi_m (x) W_m
+//         = Pi_0 (x) (W_0 - W_1) + 1 (x) W_1,
+//   so only e_0, e_1, K_0, K_1 and the four reals of Pi_0 are read per point.
+// * M[(c,d,a,b)] = conj(M[(a,b,c,d)]): only 10 entries are distinct (4 real).
+//   With the phase p = c + i s the accumulation of p M and p conj(M) needs only
+//   A = sum c M and B = sum s M; the pair is rebuilt at the end as
+//   A + iB and (A.re + B.im) + i (B.re - A.im).
+// * The phase is separable, e^{-ik.dR} = e^{-i kx dx} e^{-i ky dy}: every lane
+//   owns one ky and walks kx, so the kx phases are wave-uniform; accumulators
+//   cover dx >= 0 only (dx < 0 follows from hermiticity,
+//   Lc[dR][(ab,cd)] = conj(Lc[-dR][(cd,ab)])).  At the end of a kx chunk the
+//   lanes' values are transposed through LDS and contracted with e^{-i ky dy}.
+// Partial sums per (ky block, kx chunk) go to HBM in FP64; a finalising kernel
+// adds them in a fixed order (deterministic, no atomics).
+#include "common.h"
+#include "kernels.h"
+
+namespace tufrg {
+
+namespace {
+
+// distinct entries: 4 real (tau = 0, 5, 10, 15) and 6 complex representatives
+// (tau = 1, 11, 2, 7, 3, 6) with partners (4, 14, 8, 13, 12, 9)
+constexpr int NREAL = 4, NCPLX = 6;
+__device__ constexpr int REAL_TAU[NREAL] = {0, 5, 10, 15};
+__device__ constexpr int CPLX_TAU[NCPLX] = {1, 11, 2, 7, 3, 6};
+__device__ constexpr int CPLX_PARTNER[NCPLX] = {4, 14, 8, 13, 12, 9};
+
+template <typename T, int SCHEME>
+__device__ inline bool nondegenerate(T den, T x, T y, T lam) {
+  if constexpr (SCHEME == CUT_TEMPERATURE)
+    return fabs(den) > degen_rel<T>::v * lam;
+  else
+    return fabs(den) > degen_rel<T>::v * (lam + fabs(x) + fabs(y));
+}
+
+}  // namespace
+
+template <typename T>
+__device__ inline T ldb(const T *base, unsigned byte_off) {
+  // base pointer is wave-uniform, the offset a 32-bit lane value
+  return *(const T *)((const char *)base + byte_off);
+}
+
+// Loop body of one channel (CH = 0: pp, k' = q - k; CH = 1: ph, k' = k - q).
+template <typename T, int NDX, int SCHEME, int CH>
+__device__ inline void loop_no2_body(const T *__restrict__ band, const T *__restrict__ kv,
+                                     const double *__restrict__ tw, int Lf, int qfx, int qfy, int ky, int x0,
+                                     int x1, T lam, int deriv, T (&Sr)[NREAL], T (&Sc)[NCPLX][2],
+                                     T (&Ar)[NDX - 1][NREAL], T (&Br)[NDX - 1][NREAL],
+                                     T (&Ac)[NDX - 1][NCPLX][2], T (&Bc)[NDX - 1][NCPLX][2]) {
+  constexpr T sg = (CH == 0) ? T(1) : T(-1);
+  const unsigned Nf = (unsigned)Lf * (unsigned)Lf;
+  // component bases (uniform): e0 e1 | Pi_0: d0 d1 r im | Pi_1 (unused) ; K0 K1
+  const T *e0 = band, *e1 = band + Nf;
+  const T *p00 = band + 2 * Nf, *p11 = band + 3 * Nf, *p0r = band + 4 * Nf, *p0i = band + 5 * Nf;
+  const T *K0 = kv, *K1 = kv + Nf;
+  int kpy = (CH == 0) ? (qfy - ky) : (ky - qfy);
+  kpy = ((kpy % Lf) + Lf) % Lf;
+  int kpx = (CH == 0) ? (qfx - x0) : (x0 - qfx);
+  kpx = ((kpx % Lf) + Lf) % Lf;
+  unsigned kb = ((unsigned)x0 * Lf + ky) * (unsigned)sizeof(T);
+  const unsigned rowb = (unsigned)Lf * (unsigned)sizeof(T);
+  for (int kx = x0; kx < x1; ++kx, kb += rowb) {
+    const unsigned kpb = ((unsigned)kpx * Lf + kpy) * (unsigned)sizeof(T);
+    kpx += (CH == 0) ? -1 : 1;
+    kpx = kpx < 0 ? kpx + Lf : (kpx >= Lf ? kpx - Lf : kpx);
+    const T ekm[2] = {ldb(e0, kb), ldb(e1, kb)}, Kkm[2] = {ldb(K0, kb), ldb(K1, kb)};
+    const T P0 = ldb(p00, kb), P1 = ldb(p11, kb), Pr = ldb(p0r, kb), Pi = ldb(p0i, kb);
+    const T epn[2] = {ldb(e0, kpb), ldb(e1, kpb)}, Kpn[2] = {ldb(K0, kpb), ldb(K1, kpb)};
+    const T X0 = ldb(p00, kpb), X1 = ldb(p11, kpb), Xr = ldb(p0r, kpb), Xi = sg * ldb(p0i, kpb);
+    // loop kernels L_mn: pp (K(e1)+K(e2))/(e1+e2), ph -(K(e1)-K(e2))/(e1-e2); divided
+    // difference of K at x = e_m(k), y = -sg e_n(k'); one branch for the rare near-degenerate lanes
+    T L[2][2];
+    bool ok = true;
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int n = 0; n < 2; ++n) {
+        const T den = ekm[m] + sg * epn[n];
+        ok = ok && nondegenerate<T, SCHEME>(den, ekm[m], sg * epn[n], lam);
+        L[m][n] = sg * (Kkm[m] + sg * Kpn[n]) * rcp_fast(den);
+      }
+    if (__builtin_expect(!ok, 0)) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+          L[m][n] = sg * divided_difference(ekm[m], -sg * epn[n], Kkm[m], -sg * Kpn[n], lam, SCHEME, deriv);
+    }
+    // W_1 = alpha_1 X_0 + L_11 1, D = W_0 - W_1 = (alpha_0 - alpha_1) X_0 + (L_01 - L_11) 1
+    const T al0 = L[0][0] - L[0][1], al1 = L[1][0] - L[1][1];
+    const T dal = al0 - al1, dl = L[0][1] - L[1][1];
+    const T W1d0 = fma(al1, X0, L[1][1]), W1d1 = fma(al1, X1, L[1][1]);
+    const T W1r = al1 * Xr, W1i = al1 * Xi;
+    const T Dd0 = fma(dal, X0, dl), Dd1 = fma(dal, X1, dl);
+    const T Dr = dal * Xr, Di = dal * Xi;
+    // the 10 distinct entries of M = Pi_0 (x) D + 1 (x) W_1
+    T mr[NREAL], mc[NCPLX][2];
+    mr[0] = fma(P0, Dd0, W1d0);  // (0,0,0,0)
+    mr[1] = fma(P0, Dd1, W1d1);  // (0,1,0,1)
+    mr[2] = fma(P1, Dd0, W1d0);  // (1,0,1,0)
+    mr[3] = fma(P1, Dd1, W1d1);  // (1,1,1,1)
+    mc[0][0] = fma(P0, Dr, W1r);  // (0,0,0,1)
+    mc[0][1] = fma(P0, Di, W1i);
+    mc[1][0] = fma(P1, Dr, W1r);  // (1,0,1,1)
+    mc[1][1] = fma(P1, Di, W1i);
+    mc[2][0] = Pr * Dd0;  // (0,0,1,0)
+    mc[2][1] = Pi * Dd0;
+    mc[3][0] = Pr * Dd1;  // (0,1,1,1)
+    mc[3][1] = Pi * Dd1;
+    mc[4][0] = fma(Pr, Dr, -Pi * Di);  // (0,0,1,1): Pi_0[01] D[01]
+    mc[4][1] = fma(Pr, Di, Pi * Dr);
+    mc[5][0] = fma(Pr, Dr, Pi * Di);  // (0,1,1,0): Pi_0[01] D[10] = Pi_0[01] conj(D[01])
+    mc[5][1] = fma(Pi, Dr, -Pr * Di);
+#pragma unroll
+    for (int t = 0; t < NREAL; ++t) Sr[t] += mr[t];
+#pragma unroll
+    for (int t = 0; t < NCPLX; ++t) {
+      Sc[t][0] += mc[t][0];
+      Sc[t][1] += mc[t][1];
+    }
+#pragma unroll
+    for (int d = 0; d < NDX - 1; ++d) {
+      const int j = (kx * (d + 1)) % Lf;
+      const T c = (T)tw[2 * j], s = (T)tw[2 * j + 1];  // e^{-i 2 pi kx dx / Lf}, wave-uniform
+#pragma unroll
+      for (int t = 0; t < NREAL; ++t) {
+        Ar[d][t] = fma(c, mr[t], Ar[d][t]);
+        Br[d][t] = fma(s, mr[t], Br[d][t]);
+      }
+#pragma unroll
+      for (int t = 0; t < NCPLX; ++t) {
+        Ac[d][t][0] = fma(c, mc[t][0], Ac[d][t][0]);
+        Ac[d][t][1] = fma(c, mc[t][1], Ac[d][t][1]);
+        Bc[d][t][0] = fma(s, mc[t][0], Bc[d][t][0]);
+        Bc[d][t][1] = fma(s, mc[t][1], Bc[d][t][1]);
+      }
+    }
+  }
+}
+
+// One wave per (ky block, kx chunk, q, channel).
+template <typename T, int NDX, int NDY, int SCHEME>
+__global__ __launch_bounds__(64) void loop_no2_kernel(const T *__restrict__ band, const T *__restrict__ kv,
+                                                      const double *__restrict__ tw, int Lq, int n_ref, int Lf,
+                                                      int nkyb, int kxper, int q_first, int ch_first, T lam,
+                                                      int deriv, double *__restrict__ partial) {
+  constexpr int NDY2 = 2 * NDY + 1;
+  const int tid = threadIdx.x;
+  const int kyb = blockIdx.x % nkyb, kxc = blockIdx.x / nkyb;
+  const int nparts = gridDim.x;
+  const int qrel = blockIdx.y, qi = q_first + qrel;
+  const int chrel = blockIdx.z, ch = ch_first + chrel;
+  const int qfx = (qi / Lq) * n_ref, qfy = (qi % Lq) * n_ref;
+  const int ky_raw = kyb * 64 + tid;
+  const bool active = ky_raw < Lf;
+  const int ky = active ? ky_raw : Lf - 1;
+  const int x0 = kxc * kxper;
+  const int x1 = min(Lf, x0 + kxper);
+
+  // S: dx = 0 sums; A/B: sum of cos/sin parts for dx >= 1
+  T Sr[NREAL], Sc[NCPLX][2], Ar[NDX - 1][NREAL], Br[NDX - 1][NREAL];
+  T Ac[NDX - 1][NCPLX][2], Bc[NDX - 1][NCPLX][2];
+#pragma unroll
+  for (int t = 0; t < NREAL; ++t) Sr[t] = T(0);
+#pragma unroll
+  for (int t = 0; t < NCPLX; ++t) Sc[t][0] = Sc[t][1] = T(0);
+#pragma unroll
+  for (int d = 0; d < NDX - 1; ++d) {
+#pragma unroll
+    for (int t = 0; t < NREAL; ++t) Ar[d][t] = Br[d][t] = T(0);
+#pragma unroll
+    for (int t = 0; t < NCPLX; ++t) Ac[d][t][0] = Ac[d][t][1] = Bc[d][t][0] = Bc[d][t][1] = T(0);
+  }
+  if (ch == 0)
+    loop_no2_body<T, NDX, SCHEME, 0>(band, kv, tw, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac, Bc);
+  else
+    loop_no2_body<T, NDX, SCHEME, 1>(band, kv, tw, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac, Bc);
+
+  // rebuild all 16 entries per dx, transpose through LDS, contract with e^{-i 2 pi ky dy / Lf}
+  __shared__ T buf[32][65];
+  __shared__ T phy[NDY2][2][64];
+#pragma unroll
+  for (int i = 0; i < NDY2; ++i) {
+    int dy = i - NDY;
+    int j = (int)(((long long)ky_raw * dy) % Lf);
+    if (j < 0) j += Lf;
+    phy[i][0][tid] = (T)tw[2 * j];
+    phy[i][1][tid] = (T)tw[2 * j + 1];
+  }
+  const T on = active ? T(1) : T(0);
+  const size_t pbase = (((size_t)chrel * gridDim.y + qrel) * nparts + blockIdx.x) * (size_t)(NDX * NDY2 * 16);
+#pragma unroll
+  for (int dx = 0; dx < NDX; ++dx) {
+    __syncthreads();
+    if (dx == 0) {
+#pragma unroll
+      for (int t = 0; t < NREAL; ++t) {
+        buf[2 * REAL_TAU[t]][tid] = on * Sr[t];
+        buf[2 * REAL_TAU[t] + 1][tid] = T(0);
+      }
+#pragma unroll
+      for (int t = 0; t < NCPLX; ++t) {
+        buf[2 * CPLX_TAU[t]][tid] = on * Sc[t][0];
+        buf[2 * CPLX_TAU[t] + 1][tid] = on * Sc[t][1];
+        buf[2 * CPLX_PARTNER[t]][tid] = on * Sc[t][0];
+        buf[2 * CPLX_PARTNER[t] + 1][tid] = -on * Sc[t][1];
+      }
+    } else {
+      const int d = dx - 1;
+#pragma unroll
+      for (int t = 0; t < NREAL; ++t) {
+        buf[2 * REAL_TAU[t]][tid] = on * Ar[d][t];
+        buf[2 * REAL_TAU[t] + 1][tid] = on * Br[d][t];
+      }
+#pragma unroll
+      for (int t = 0; t < NCPLX; ++t) {
+        const T ar = Ac[d][t][0], ai = Ac[d][t][1], br = Bc[d][t][0], bi = Bc[d][t][1];
+        buf[2 * CPLX_TAU[t]][tid] = on * (ar - bi);
+        buf[2 * CPLX_TAU[t] + 1][tid] = on * (ai + br);
+        buf[2 * CPLX_PARTNER[t]][tid] = on * (ar + bi);
+        buf[2 * CPLX_PARTNER[t] + 1][tid] = on * (br - ai);
+      }
+    }
+    __syncthreads();
+    for (int o = tid; o < NDY2 * 16; o += 64) {
+      const int t = o & 15;
+      const int dyi = o >> 4;
+      T sr = T(0), si = T(0);
+#pragma unroll 4
+      for (int l = 0; l < 64; ++l) {
+        const T ar = buf[2 * t][l], ai = buf[2 * t + 1][l];
+        const T pr = phy[dyi][0][l], pim = phy[dyi][1][l];
+        sr = fma(pr, ar, sr);
+        sr = fma(-pim, ai, sr);
+        si = fma(pr, ai, si);
+        si = fma(pim, ar, si);
+      }
+      const size_t idx = pbase + ((size_t)(dx * NDY2 + dyi) * 16 + t);
+      partial[2 * idx] = (double)sr;
+      partial[2 * idx + 1] = (double)si;
+    }
+  }
+}
+
+template <typename T, int NDX, int NDY>
+static hipError_t launch_no2(const LoopArgs &a, hipStream_t st) {
+  const int kxper = (a.Lf + a.nkxc - 1) / a.nkxc;
+  dim3 grid(a.nkyb * a.nkxc, a.n_q, a.n_ch), block(64);
+  const T *band = (const T *)a.band;
+  const T *kv = (const T *)a.kv;
+  if (a.scheme == CUT_TEMPERATURE)
+    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_TEMPERATURE>), grid, block, 0, st, band, kv, a.tw, a.Lq,
+                       a.n_ref, a.Lf, a.nkyb, kxper, a.q_first, a.ch_first, (T)a.lam, a.deriv, a.partial);
+  else
+    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_OMEGA>), grid, block, 0, st, band, kv, a.tw, a.Lq,
+                       a.n_ref, a.Lf, a.nkyb, kxper, a.q_first, a.ch_first, (T)a.lam, a.deriv, a.partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_loop(const LoopArgs &a, hipStream_t st) {
+  if (a.n_o != 2) return hipErrorInvalidValue;
+  const bool f64 = (a.prec == 0);
+  if (a.ndx == 3 && a.ndy == 2) return f64 ? launch_no2<double, 3, 2>(a, st) : launch_no2<float, 3, 2>(a, st);
+  if (a.ndx == 5 && a.ndy == 4) return f64 ? launch_no2<double, 5, 4>(a, st) : launch_no2<float, 5, 4>(a, st);
+  if (a.ndx == 2 && a.ndy == 1) return f64 ? launch_no2<double, 2, 1>(a, st) : launch_no2<float, 2, 1>(a, st);
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ void loop_finalize_kernel(int n_o, int n_ch, int n_q, int nparts, int ndx, int ndy, int nD,
+                                     const int *__restrict__ dlist, double inv_nf, const double *__restrict__ partial,
+                                     double *__restrict__ compact) {
+  const int no2 = n_o * n_o, no4 = no2 * no2;
+  const long long total = (long long)n_ch * n_q * nD * no4;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int tau = (int)(i % no4);
+  const int iD = (int)((i / no4) % nD);
+  const long long cq = i / ((long long)no4 * nD);  // chrel * n_q + qrel
+  int dx = dlist[2 * iD], dy = dlist[2 * iD + 1];
+  int t = tau;
+  bool cj = false;
+  if (dx < 0) {
+    dx = -dx;
+    dy = -dy;
+    t = (tau % no2) * no2 + tau / no2;
+    cj = true;
+  }
+  const int ndy2 = 2 * ndy + 1;
+  const size_t per = (size_t)ndx * ndy2 * no4;
+  const double *p = partial + (size_t)cq * nparts * per * 2 + ((size_t)(dx * ndy2 + dy + ndy) * no4 + t) * 2;
+  double sr = 0.0, si = 0.0;
+  for (int k = 0; k < nparts; ++k) {
+    sr += p[(size_t)k * per * 2];
+    si += p[(size_t)k * per * 2 + 1];
+  }
+  compact[2 * i] = sr * inv_nf;
+  compact[2 * i + 1] = (cj ? -si : si) * inv_nf;
+}
+
+hipError_t launch_loop_finalize(const LoopArgs &a, int nD, const int *dlist, double *compact, hipStream_t st) {
+  const int no4 = a.n_o * a.n_o * a.n_o * a.n_o;
+  const long long total = (long long)a.n_ch * a.n_q * nD * no4;
+  const int nparts = a.nkyb * a.nkxc;
+  const double inv = 1.0 / ((double)a.Lf * a.Lf);
+  hipLaunchKernelGGL(loop_finalize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a.n_o, a.n_ch,
+                     a.n_q, nparts, a.ndx, a.ndy, nD, dlist, inv, (const double *)a.partial, compact);
+  return hipGetLastError();
+}
+
+__global__ void loop_expand_kernel(int n_o, int n_ff, int nD, int n_q, const int *__restrict__ didx,
+                                   const double *__restrict__ compact, double *__restrict__ out) {
+  const int no2 = n_o * n_o, no4 = no2 * no2;
+  const int B = n_ff * no2;
+  const long long total = (long long)n_q * B * B;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int col = (int)(i % B), row = (int)((i / B) % B);
+  const long long q = i / ((long long)B * B);
+  const int r1 = row / no2, ab = row % no2, r2 = col / no2, cd = col % no2;
+  const int iD = didx[r1 * n_ff + r2];
+  const size_t src = ((size_t)q * nD + iD) * no4 + (size_t)ab * no2 + cd;
+  out[2 * i] = compact[2 * src];
+  out[2 * i + 1] = compact[2 * src + 1];
+}
+
+hipError_t launch_loop_expand(int n_o, int n_ff, int nD, int n_q, const int *didx, const double *compact,
+                              double *out, hipStream_t st) {
+  const int B = n_ff * n_o * n_o;
+  const long long total = (long long)n_q * B * B;
+  hipLaunchKernelGGL(loop_expand_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n_o, n_ff, nD,
+                     n_q, didx, compact, out);
+  return hipGetLastError();
+}
+
+}  // namespace tufrg

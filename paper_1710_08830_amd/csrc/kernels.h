@@ -1,0 +1,65 @@
+// Host-side launchers of the TU-fRG kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace tufrg {
+
+// a0: band data on the fine mesh (eigenvalues minus mu, packed projectors)
+hipError_t launch_band(int n_o, int Lf, int n_hop, const int *hop_R, const double *hop_t, double mu,
+                       double *e, double *pi, float *e32, float *pi32, hipStream_t st);
+hipError_t launch_kval(int n, const double *e, double lam, int scheme, int deriv, double *kv, float *kv32,
+                       hipStream_t st);
+
+// a1-a3: form-factor projected orbital loops
+struct LoopArgs {
+  int n_o, Lq, n_ref, Lf, Nq;
+  int ndx, ndy;        // computed box: dx in [0, ndx), dy in [-ndy, ndy]
+  int nkyb, nkxc;      // ky blocks of 64 lanes, kx chunks
+  int ch_first, n_ch;  // channels 0 (pp) and/or 1 (ph)
+  int q_first, n_q;    // coarse q range
+  int scheme, deriv, prec;
+  double lam;
+  const void *band;    // SoA band data (FP64 or FP32 by prec)
+  const void *kv;      // regulator values [n_o][Nf]
+  const double *tw;    // exp(-2 pi i j / Lf), [Lf][2]
+  double *partial;     // [n_ch][n_q][nkyb * nkxc][ndx][2 ndy + 1][n_o^4][2]
+};
+hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
+// sums partials, applies 1/Nf, fills dx < 0 by hermiticity
+hipError_t launch_loop_finalize(const LoopArgs &a, int nD, const int *dlist, double *compact, hipStream_t st);
+// compact [n_ch][n_q][nD][n_o^4] -> full [n_q][B][B] for one channel
+hipError_t launch_loop_expand(int n_o, int n_ff, int nD, int n_q, const int *didx, const double *compact,
+                              double *out, hipStream_t st);
+
+// a4-a5: real-space transform, gathers, assembly of projected vertices
+struct ProjArgs {
+  int n_o, n_ff, B, Lq, Nq, nD;
+  const int *dlist;    // [nD][2]
+  const int *ffgrid;   // [17][17] form-factor index of (x, y) in [-8, 8]^2, -1 outside S
+  const int *dgrid;    // [17][17] index into dlist, -1 outside D
+  const int *ff;       // [n_ff][2]
+  const double *twq;   // exp(+2 pi i j / Lq), [Lq][2]
+};
+hipError_t launch_ft(const ProjArgs &a, const double *P, const double *C, double *part, int nqc, double *real,
+                     hipStream_t st);
+hipError_t launch_gather(const ProjArgs &a, const double *real, double *G, hipStream_t st);
+hipError_t launch_assemble(const ProjArgs &a, const double *P, const double *C, const double *G,
+                           const double *v0p, const double *v0c, double *VP, double *VC, hipStream_t st);
+
+// a6: bundle products  out = f * V L V  per q, L expanded from compact form
+hipError_t launch_bundle(int prec, int n_o, int n_ff, int B, int nD, int n_q, const int *didx, const double *V,
+                         const double *Lc, double factor, double *out, hipStream_t st);
+
+// a7: ODE updates and reductions
+hipError_t launch_axpy_max(long long n, const double *x, double h, const double *dx, double *y,
+                           unsigned long long *maxbits, unsigned int *flag, hipStream_t st);
+hipError_t launch_lincomb(long long n, const double *x, int nk, const double *const *k, const double *coef,
+                          double h, double *y, hipStream_t st);
+hipError_t launch_dp_error(long long n, const double *x0, const double *x1, int nk, const double *const *k,
+                           const double *ecoef, double h, double rtol, double atol, unsigned long long *errbits,
+                           unsigned int *flag, hipStream_t st);
+hipError_t launch_clear_reduce(unsigned long long *bits, unsigned int *flag, hipStream_t st);
+hipError_t launch_scale(long long n, const double *x, double s, double *y, hipStream_t st);
+
+}  // namespace tufrg

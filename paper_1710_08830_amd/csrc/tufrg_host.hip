@@ -1,0 +1,671 @@
+// Host orchestration behind the C ABI of include/tufrg.h: context set-up,
+// argument checks, the right-hand-side pipeline and the flow integrators.
+//
+// Right-hand side at scale Lambda (one evaluation, all on the context stream):
+//   kval      regulator K(e_m(k)) for every band and fine k
+//   loop      compact loops of both channels (partials per k-chunk)
+//   finalize  fixed-order FP64 sum of the partials, hermitian completion
+//   ft        P(q), C(q) -> P(rho), C(rho) for rho in D = S - S
+//   gather    rho-space gathers of the four cross projections
+//   assemble  VP(q), VC(q)
+//   bundle    dP = VP Lpp VP, dC = 2 VC Lph VC
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/tufrg.h"
+#include "common.h"
+#include "kernels.h"
+
+namespace tufrg {
+hipError_t launch_unpack_pi(int n_o, int Nf, const double *pi, double *out, hipStream_t st);
+}
+
+using namespace tufrg;
+
+struct tufrg_ctx {
+  hipStream_t st = nullptr;
+  int n_o = 0, n_ff = 0, B = 0, Lq = 0, n_ref = 0, Lf = 0, Nq = 0, Nf = 0, no2 = 0, no4 = 0;
+  int nD = 0, ndx = 0, ndy = 0, scheme = 0, prec = 0, nkyb = 0, nkxc = 0, nqc = 0;
+  std::vector<int> ff, dlist, didx, ffgrid, dgrid;
+  int *d_ff = nullptr, *d_dlist = nullptr, *d_didx = nullptr, *d_ffgrid = nullptr, *d_dgrid = nullptr;
+  int *d_hopR = nullptr;
+  double *d_hopt = nullptr;
+  double *d_band64 = nullptr;
+  float *d_band32 = nullptr;
+  double *d_kv64 = nullptr;
+  float *d_kv32 = nullptr;
+  double *d_twf = nullptr, *d_twq = nullptr;
+  double *d_partial = nullptr;
+  double *d_loop = nullptr;
+  double *d_ftpart = nullptr, *d_real = nullptr, *d_G = nullptr;
+  double *d_v0p = nullptr, *d_v0c = nullptr, *d_VP = nullptr, *d_VC = nullptr;
+  unsigned long long *d_bits = nullptr;
+  unsigned int *d_flag = nullptr;
+  unsigned long long *h_bits = nullptr;  // pinned
+  unsigned int *h_flag = nullptr;        // pinned
+  // flow workspace (lazy)
+  double *d_dP = nullptr, *d_dC = nullptr;
+  std::vector<double *> d_stage;  // DP5: 7 k's per channel + stage state per channel
+  std::string err;
+  std::vector<void *> allocs;
+  // optional per-kernel timing with HIP events on the context stream
+  struct Timer {
+    std::vector<hipEvent_t> ev;
+    size_t used = 0;
+    double ms = 0.0;
+    int count = 0;
+  };
+  bool timing = false;
+  Timer timers[TUFRG_TIMER_COUNT];
+};
+
+static thread_local std::string g_err;
+
+static tufrg_status fail(tufrg_ctx *c, tufrg_status s, const std::string &m) {
+  if (c)
+    c->err = m;
+  else
+    g_err = m;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) {                                                                 \
+      (void)hipGetLastError();                                                              \
+      return fail(ctx, TUFRG_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
+    }                                                                                       \
+  } while (0)
+
+template <typename T>
+static tufrg_status dalloc(tufrg_ctx *c, T **p, size_t n) {
+  void *v = nullptr;
+  hipError_t e = hipMalloc(&v, std::max<size_t>(n, 1) * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, TUFRG_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+  }
+  c->allocs.push_back(v);
+  *p = (T *)v;
+  return TUFRG_OK;
+}
+
+#define TRY(x)                         \
+  do {                                 \
+    tufrg_status s_ = (x);             \
+    if (s_ != TUFRG_OK) return s_;     \
+  } while (0)
+
+static bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+static hipError_t timer_mark(tufrg_ctx *c, int id) {
+  if (!c->timing) return hipSuccess;
+  auto &t = c->timers[id];
+  if (t.used == t.ev.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    t.ev.push_back(e);
+  }
+  return hipEventRecord(t.ev[t.used++], c->st);
+}
+
+static void destroy_all(tufrg_ctx *c) {
+  for (auto &t : c->timers)
+    for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
+  for (void *p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->h_bits) (void)hipHostFree(c->h_bits);
+  if (c->h_flag) (void)hipHostFree(c->h_flag);
+  c->h_bits = nullptr;
+  c->h_flag = nullptr;
+}
+
+extern "C" const char *tufrg_last_error(const tufrg_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s, void *stream, tufrg_ctx **out) {
+  if (!m || !s || !out) return fail(nullptr, TUFRG_E_INVAL, "null argument");
+  *out = nullptr;
+  if (m->n_orb != 2)
+    return fail(nullptr, TUFRG_E_UNSUPPORTED, "this build supports n_orb = 2 spin-orbitals");
+  if (m->n_hop < 1 || !m->hop_R || !m->hop_t || !m->V0) return fail(nullptr, TUFRG_E_INVAL, "empty model");
+  if (s->n_ff < 1 || !s->ff_R) return fail(nullptr, TUFRG_E_INVAL, "empty form-factor set");
+  if (s->ff_R[0] != 0 || s->ff_R[1] != 0) return fail(nullptr, TUFRG_E_INVAL, "ff_R[0] must be (0,0)");
+  if (s->cutoff != TUFRG_CUT_TEMPERATURE && s->cutoff != TUFRG_CUT_OMEGA)
+    return fail(nullptr, TUFRG_E_INVAL, "unknown cutoff");
+  if (s->precision != TUFRG_FP64 && s->precision != TUFRG_FP32)
+    return fail(nullptr, TUFRG_E_INVAL, "unknown precision");
+  if (s->n_ref < 1 || s->Lq < 1 || (long long)s->Lq * s->n_ref > 4096)
+    return fail(nullptr, TUFRG_E_INVAL, "mesh sizes out of range");
+  int rmax = 0;
+  std::vector<std::pair<int, int>> ffv;
+  for (int i = 0; i < s->n_ff; ++i) {
+    int x = s->ff_R[2 * i], y = s->ff_R[2 * i + 1];
+    if (std::abs(x) > 2 || std::abs(y) > 2) return fail(nullptr, TUFRG_E_INVAL, "form factor beyond |R| <= 2");
+    rmax = std::max(rmax, std::max(std::abs(x), std::abs(y)));
+    for (auto &p : ffv)
+      if (p.first == x && p.second == y) return fail(nullptr, TUFRG_E_INVAL, "duplicate form factor");
+    ffv.push_back({x, y});
+  }
+  for (auto &p : ffv) {
+    bool found = false;
+    for (auto &q : ffv) found |= (q.first == -p.first && q.second == -p.second);
+    if (!found) return fail(nullptr, TUFRG_E_INVAL, "form-factor set not closed under R -> -R");
+  }
+  if (s->Lq <= 4 * rmax) return fail(nullptr, TUFRG_E_INVAL, "Lq must exceed 4 max|R| (aliasing)");
+
+  tufrg_ctx *c = new tufrg_ctx();
+  c->st = (hipStream_t)stream;
+  c->n_o = m->n_orb;
+  c->no2 = c->n_o * c->n_o;
+  c->no4 = c->no2 * c->no2;
+  c->n_ff = s->n_ff;
+  c->B = c->n_ff * c->no2;
+  c->Lq = s->Lq;
+  c->n_ref = s->n_ref;
+  c->Lf = s->Lq * s->n_ref;
+  c->Nq = c->Lq * c->Lq;
+  c->Nf = c->Lf * c->Lf;
+  c->scheme = s->cutoff;
+  c->prec = s->precision;
+  c->ff.assign(s->ff_R, s->ff_R + 2 * s->n_ff);
+  // D = S - S, sorted; lookup grids over [-8, 8]^2
+  std::map<std::pair<int, int>, int> dmap;
+  for (int i = 0; i < c->n_ff; ++i)
+    for (int j = 0; j < c->n_ff; ++j) dmap[{c->ff[2 * i] - c->ff[2 * j], c->ff[2 * i + 1] - c->ff[2 * j + 1]}] = 0;
+  int idx = 0, mdx = 0, mdy = 0;
+  for (auto &kv : dmap) {
+    kv.second = idx++;
+    c->dlist.push_back(kv.first.first);
+    c->dlist.push_back(kv.first.second);
+    mdx = std::max(mdx, std::abs(kv.first.first));
+    mdy = std::max(mdy, std::abs(kv.first.second));
+  }
+  c->nD = idx;
+  c->ffgrid.assign(17 * 17, -1);
+  c->dgrid.assign(17 * 17, -1);
+  for (int i = 0; i < c->n_ff; ++i) c->ffgrid[(c->ff[2 * i] + 8) * 17 + c->ff[2 * i + 1] + 8] = i;
+  for (auto &kv : dmap) c->dgrid[(kv.first.first + 8) * 17 + kv.first.second + 8] = kv.second;
+  c->didx.resize(c->n_ff * c->n_ff);
+  for (int i = 0; i < c->n_ff; ++i)
+    for (int j = 0; j < c->n_ff; ++j)
+      c->didx[i * c->n_ff + j] = dmap[{c->ff[2 * i] - c->ff[2 * j], c->ff[2 * i + 1] - c->ff[2 * j + 1]}];
+  // computed box of the loop kernel: dx in [0, ndx), dy in [-ndy, ndy]
+  if (mdx <= 1 && mdy <= 1) {
+    c->ndx = 2;
+    c->ndy = 1;
+  } else if (mdx <= 2 && mdy <= 2) {
+    c->ndx = 3;
+    c->ndy = 2;
+  } else {
+    c->ndx = 5;
+    c->ndy = 4;
+  }
+  c->nkyb = (c->Lf + 63) / 64;
+  {
+    long long base = 2LL * c->Nq * c->nkyb;
+    int want = (int)std::max<long long>(1, (4096 + base - 1) / base);
+    c->nkxc = std::max(1, std::min(want, std::max(1, c->Lf / 8)));
+  }
+  {
+    long long BB2 = 2LL * c->B * c->B;
+    int want = (int)std::max<long long>(1, (2048LL * 256 + BB2 - 1) / BB2);
+    c->nqc = std::max(1, std::min(want, c->Nq));
+  }
+  auto bail = [&](tufrg_status st) {
+    g_err = c->err;
+    destroy_all(c);
+    delete c;
+    return st;
+  };
+#define CTRY(x)                          \
+  do {                                   \
+    tufrg_status s_ = (x);               \
+    if (s_ != TUFRG_OK) return bail(s_); \
+  } while (0)
+#define CHIP(x)                                                                       \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess) {                                                           \
+      (void)hipGetLastError();                                                        \
+      c->err = std::string(#x) + ": " + hipGetErrorString(e_);                         \
+      return bail(TUFRG_E_HIP);                                                       \
+    }                                                                                 \
+  } while (0)
+
+  const size_t Nf = c->Nf, BB = (size_t)c->B * c->B;
+  CTRY(dalloc(c, &c->d_ff, c->ff.size()));
+  CTRY(dalloc(c, &c->d_dlist, c->dlist.size()));
+  CTRY(dalloc(c, &c->d_didx, c->didx.size()));
+  CTRY(dalloc(c, &c->d_ffgrid, c->ffgrid.size()));
+  CTRY(dalloc(c, &c->d_dgrid, c->dgrid.size()));
+  CTRY(dalloc(c, &c->d_hopR, 2 * (size_t)m->n_hop));
+  CTRY(dalloc(c, &c->d_hopt, 2 * (size_t)m->n_hop * c->no2));
+  CTRY(dalloc(c, &c->d_band64, Nf * (c->n_o + c->n_o * c->no2)));
+  CTRY(dalloc(c, &c->d_band32, Nf * (c->n_o + c->n_o * c->no2)));
+  CTRY(dalloc(c, &c->d_kv64, Nf * c->n_o));
+  CTRY(dalloc(c, &c->d_kv32, Nf * c->n_o));
+  CTRY(dalloc(c, &c->d_twf, 2 * (size_t)c->Lf));
+  CTRY(dalloc(c, &c->d_twq, 2 * (size_t)c->Lq));
+  const size_t nparts = (size_t)c->nkyb * c->nkxc;
+  CTRY(dalloc(c, &c->d_partial, 2 * 2 * (size_t)c->Nq * nparts * c->ndx * (2 * c->ndy + 1) * c->no4));
+  CTRY(dalloc(c, &c->d_loop, 2 * 2 * (size_t)c->Nq * c->nD * c->no4));
+  CTRY(dalloc(c, &c->d_ftpart, 2 * 2 * (size_t)c->nqc * c->nD * BB));
+  CTRY(dalloc(c, &c->d_real, 2 * 2 * (size_t)c->nD * BB));
+  CTRY(dalloc(c, &c->d_G, 2 * 2 * (size_t)c->nD * BB));
+  CTRY(dalloc(c, &c->d_v0p, 2 * BB));
+  CTRY(dalloc(c, &c->d_v0c, 2 * BB));
+  CTRY(dalloc(c, &c->d_VP, 2 * BB * c->Nq));
+  CTRY(dalloc(c, &c->d_VC, 2 * BB * c->Nq));
+  CTRY(dalloc(c, &c->d_bits, 4));
+  CTRY(dalloc(c, &c->d_flag, 4));
+  CHIP(hipHostMalloc((void **)&c->h_bits, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+  CHIP(hipHostMalloc((void **)&c->h_flag, 4 * sizeof(unsigned int), hipHostMallocDefault));
+
+  // tables
+  std::vector<double> twf(2 * c->Lf), twq(2 * c->Lq);
+  for (int j = 0; j < c->Lf; ++j) {
+    const double a = 2.0 * M_PI * (double)j / (double)c->Lf;
+    twf[2 * j] = std::cos(a);
+    twf[2 * j + 1] = -std::sin(a);
+  }
+  for (int j = 0; j < c->Lq; ++j) {
+    const double a = 2.0 * M_PI * (double)j / (double)c->Lq;
+    twq[2 * j] = std::cos(a);
+    twq[2 * j + 1] = std::sin(a);
+  }
+  std::vector<double> v0p(2 * BB, 0.0), v0c(2 * BB, 0.0);
+  const int n = c->n_o;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      for (int cc = 0; cc < n; ++cc)
+        for (int d = 0; d < n; ++d) {
+          const size_t e = (size_t)(a * n + b) * c->B + (cc * n + d);
+          const tufrg_c64 vp = m->V0[((a * n + b) * n + d) * n + cc];  // V0_{a b d c}
+          const tufrg_c64 vc = m->V0[((a * n + d) * n + b) * n + cc];  // V0_{a d b c}
+          v0p[2 * e] = vp.re;
+          v0p[2 * e + 1] = vp.im;
+          v0c[2 * e] = vc.re;
+          v0c[2 * e + 1] = vc.im;
+        }
+  hipStream_t st = c->st;
+  CHIP(hipMemcpyAsync(c->d_ff, c->ff.data(), c->ff.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  CHIP(hipMemcpyAsync(c->d_dlist, c->dlist.data(), c->dlist.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  CHIP(hipMemcpyAsync(c->d_didx, c->didx.data(), c->didx.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  CHIP(hipMemcpyAsync(c->d_ffgrid, c->ffgrid.data(), c->ffgrid.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  CHIP(hipMemcpyAsync(c->d_dgrid, c->dgrid.data(), c->dgrid.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  CHIP(hipMemcpyAsync(c->d_hopR, m->hop_R, 2 * (size_t)m->n_hop * sizeof(int), hipMemcpyHostToDevice, st));
+  CHIP(hipMemcpyAsync(c->d_hopt, m->hop_t, (size_t)m->n_hop * c->no2 * sizeof(tufrg_c64), hipMemcpyHostToDevice,
+                      st));
+  CHIP(hipMemcpyAsync(c->d_twf, twf.data(), twf.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  CHIP(hipMemcpyAsync(c->d_twq, twq.data(), twq.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  CHIP(hipMemcpyAsync(c->d_v0p, v0p.data(), v0p.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  CHIP(hipMemcpyAsync(c->d_v0c, v0c.data(), v0c.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  CHIP(launch_band(c->n_o, c->Lf, m->n_hop, c->d_hopR, c->d_hopt, m->mu, c->d_band64, c->d_band64 + Nf * c->n_o,
+                   c->d_band32, c->d_band32 + Nf * c->n_o, st));
+  CHIP(hipStreamSynchronize(st));
+  *out = c;
+  return TUFRG_OK;
+#undef CTRY
+#undef CHIP
+}
+
+extern "C" tufrg_status tufrg_destroy(tufrg_ctx *c) {
+  if (!c) return TUFRG_OK;
+  (void)hipStreamSynchronize(c->st);
+  destroy_all(c);
+  delete c;
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_dims(const tufrg_ctx *c, int32_t *B, int32_t *Nq, int32_t *Nf, int32_t *n_dR) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (B) *B = c->B;
+  if (Nq) *Nq = c->Nq;
+  if (Nf) *Nf = c->Nf;
+  if (n_dR) *n_dR = c->nD;
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_band_data(tufrg_ctx *c, double *e, tufrg_c64 *Pi) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!is_device_ptr(e) || !is_device_ptr(Pi)) return fail(c, TUFRG_E_INVAL, "e and Pi must be device pointers");
+  HIPCHK(c, hipMemcpyAsync(e, c->d_band64, sizeof(double) * c->n_o * (size_t)c->Nf, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(c, launch_unpack_pi(c->n_o, c->Nf, c->d_band64 + (size_t)c->Nf * c->n_o, (double *)Pi, c->st));
+  return TUFRG_OK;
+}
+
+static LoopArgs loop_args(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch) {
+  LoopArgs a;
+  a.n_o = c->n_o;
+  a.Lq = c->Lq;
+  a.n_ref = c->n_ref;
+  a.Lf = c->Lf;
+  a.Nq = c->Nq;
+  a.ndx = c->ndx;
+  a.ndy = c->ndy;
+  a.nkyb = c->nkyb;
+  a.nkxc = c->nkxc;
+  a.ch_first = ch_first;
+  a.n_ch = n_ch;
+  a.q_first = 0;
+  a.n_q = c->Nq;
+  a.scheme = c->scheme;
+  a.deriv = deriv;
+  a.prec = c->prec;
+  a.lam = lam;
+  a.band = c->prec == 0 ? (const void *)c->d_band64 : (const void *)c->d_band32;
+  a.kv = c->prec == 0 ? (const void *)c->d_kv64 : (const void *)c->d_kv32;
+  a.tw = c->d_twf;
+  a.partial = c->d_partial;
+  return a;
+}
+
+static ProjArgs proj_args(tufrg_ctx *c) {
+  ProjArgs a;
+  a.n_o = c->n_o;
+  a.n_ff = c->n_ff;
+  a.B = c->B;
+  a.Lq = c->Lq;
+  a.Nq = c->Nq;
+  a.nD = c->nD;
+  a.dlist = c->d_dlist;
+  a.ffgrid = c->d_ffgrid;
+  a.dgrid = c->d_dgrid;
+  a.ff = c->d_ff;
+  a.twq = c->d_twq;
+  return a;
+}
+
+// loops of channels [ch_first, ch_first + n_ch) into the compact buffer
+static tufrg_status compute_loops(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch) {
+  HIPCHK(c, launch_kval(c->n_o * c->Nf, c->d_band64, lam, c->scheme, deriv, c->d_kv64, c->d_kv32, c->st));
+  LoopArgs a = loop_args(c, lam, deriv, ch_first, n_ch);
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
+  HIPCHK(c, launch_loop(a, c->st));
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
+  double *dst = c->d_loop + 2 * (size_t)ch_first * c->Nq * c->nD * c->no4;
+  HIPCHK(c, launch_loop_finalize(a, c->nD, c->d_dlist, dst, c->st));
+  return TUFRG_OK;
+}
+
+static tufrg_status project_internal(tufrg_ctx *c, const double *P, const double *C, double *VP, double *VC) {
+  ProjArgs a = proj_args(c);
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_PROJECT));
+  HIPCHK(c, launch_ft(a, P, C, c->d_ftpart, c->nqc, c->d_real, c->st));
+  HIPCHK(c, launch_gather(a, c->d_real, c->d_G, c->st));
+  HIPCHK(c, launch_assemble(a, P, C, c->d_G, c->d_v0p, c->d_v0c, VP, VC, c->st));
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_PROJECT));
+  return TUFRG_OK;
+}
+
+// dP = scale VP Lpp VP, dC = 2 scale VC Lph VC; a masked channel gets zero
+static tufrg_status rhs_internal(tufrg_ctx *c, double lam, const double *P, const double *C, double *dP, double *dC,
+                                 double scale, unsigned mask) {
+  const size_t BB = (size_t)c->B * c->B;
+  if ((mask & 3u) == 3u)
+    TRY(compute_loops(c, lam, 1, 0, 2));
+  else if (mask & 1u)
+    TRY(compute_loops(c, lam, 1, 0, 1));
+  else if (mask & 2u)
+    TRY(compute_loops(c, lam, 1, 1, 1));
+  TRY(project_internal(c, P, C, c->d_VP, c->d_VC));
+  const size_t lsz = 2 * (size_t)c->Nq * c->nD * c->no4;
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_BUNDLE));
+  if (mask & 1u)
+    HIPCHK(c, launch_bundle(c->prec, c->n_o, c->n_ff, c->B, c->nD, c->Nq, c->d_didx, c->d_VP, c->d_loop, scale, dP,
+                            c->st));
+  else
+    HIPCHK(c, hipMemsetAsync(dP, 0, 2 * sizeof(double) * BB * c->Nq, c->st));
+  if (mask & 2u)
+    HIPCHK(c, launch_bundle(c->prec, c->n_o, c->n_ff, c->B, c->nD, c->Nq, c->d_didx, c->d_VC, c->d_loop + lsz,
+                            2.0 * scale, dC, c->st));
+  else
+    HIPCHK(c, hipMemsetAsync(dC, 0, 2 * sizeof(double) * BB * c->Nq, c->st));
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_BUNDLE));
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_timing(tufrg_ctx *c, int32_t enable) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->timing = enable != 0;
+  for (auto &t : c->timers) {
+    t.used = 0;
+    t.ms = 0.0;
+    t.count = 0;
+  }
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_timing_read(tufrg_ctx *c, int32_t timer, double *total_ms, int32_t *count) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (timer < 0 || timer >= TUFRG_TIMER_COUNT || !total_ms || !count) return fail(c, TUFRG_E_INVAL, "bad timer query");
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (auto &t : c->timers) {
+    for (size_t i = 0; i + 1 < t.used; i += 2) {
+      float ms = 0.f;
+      HIPCHK(c, hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]));
+      t.ms += ms;
+      t.count += 1;
+    }
+    t.used = 0;
+  }
+  *total_ms = c->timers[timer].ms;
+  *count = c->timers[timer].count;
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_bubble(tufrg_ctx *c, int32_t channel, double lambda, int32_t deriv, tufrg_c64 *L) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (channel != TUFRG_PP && channel != TUFRG_PH) return fail(c, TUFRG_E_INVAL, "channel must be PP or PH");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, TUFRG_E_INVAL, "lambda must be positive");
+  if (!is_device_ptr(L)) return fail(c, TUFRG_E_INVAL, "L must be a device pointer");
+  TRY(compute_loops(c, lambda, deriv ? 1 : 0, channel, 1));
+  const double *src = c->d_loop + 2 * (size_t)channel * c->Nq * c->nD * c->no4;
+  HIPCHK(c, launch_loop_expand(c->n_o, c->n_ff, c->nD, c->Nq, c->d_didx, src, (double *)L, c->st));
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_project(tufrg_ctx *c, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,
+                                      tufrg_c64 *VC) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!is_device_ptr(P) || !is_device_ptr(C) || !is_device_ptr(VP) || !is_device_ptr(VC))
+    return fail(c, TUFRG_E_INVAL, "P, C, VP, VC must be device pointers");
+  return project_internal(c, (const double *)P, (const double *)C, (double *)VP, (double *)VC);
+}
+
+extern "C" tufrg_status tufrg_rhs(tufrg_ctx *c, double lambda, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *dP,
+                                  tufrg_c64 *dC) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, TUFRG_E_INVAL, "lambda must be positive");
+  if (!is_device_ptr(P) || !is_device_ptr(C) || !is_device_ptr(dP) || !is_device_ptr(dC))
+    return fail(c, TUFRG_E_INVAL, "P, C, dP, dC must be device pointers");
+  return rhs_internal(c, lambda, (const double *)P, (const double *)C, (double *)dP, (double *)dC, 1.0, 3u);
+}
+
+// ---------------------------------------------------------------------------
+// flow
+
+static tufrg_status read_reduce(tufrg_ctx *c, double *val, bool *bad) {
+  HIPCHK(c, hipMemcpyAsync(c->h_bits, c->d_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->h_flag, c->d_flag, sizeof(unsigned int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  unsigned long long b = c->h_bits[0];
+  double v;
+  std::memcpy(&v, &b, sizeof(v));
+  *val = v;
+  *bad = c->h_flag[0] != 0;
+  return TUFRG_OK;
+}
+
+static tufrg_status state_max(tufrg_ctx *c, const double *P, const double *C, double *m, bool *bad) {
+  const long long n = (long long)c->Nq * c->B * c->B;
+  HIPCHK(c, launch_clear_reduce(c->d_bits, c->d_flag, c->st));
+  HIPCHK(c, launch_axpy_max(n, P, 0.0, nullptr, nullptr, c->d_bits, c->d_flag, c->st));
+  HIPCHK(c, launch_axpy_max(n, C, 0.0, nullptr, nullptr, c->d_bits, c->d_flag, c->st));
+  return read_reduce(c, m, bad);
+}
+
+static double lambda_c_interp(double l0, double m0, double l1, double m1, double vmax) {
+  const double t = (vmax - m0) / (m1 - m0);
+  return std::exp(std::log(l0) + t * (std::log(l1) - std::log(l0)));
+}
+
+static const double DP_C[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+static const double DP_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+static const double DP_B5[7] = {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84, 0.0};
+static const double DP_B4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200, 187.0 / 2100,
+                                1.0 / 40};
+
+extern "C" tufrg_status tufrg_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg_c64 *Pu, tufrg_c64 *Cu,
+                                   tufrg_flow_result *res) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!o || !res) return fail(c, TUFRG_E_INVAL, "null options or result");
+  if (!is_device_ptr(Pu) || !is_device_ptr(Cu)) return fail(c, TUFRG_E_INVAL, "P, C must be device pointers");
+  if (!(o->lambda0 > 0.0) || !(o->lambda_end > 0.0) || !(o->lambda_end < o->lambda0))
+    return fail(c, TUFRG_E_INVAL, "need lambda0 > lambda_end > 0");
+  if (o->n_steps < 0) return fail(c, TUFRG_E_INVAL, "n_steps must be >= 0");
+  const unsigned mask = o->channel_mask & 3u;
+  if (!mask) return fail(c, TUFRG_E_INVAL, "channel_mask selects no channel");
+  double *P = (double *)Pu, *C = (double *)Cu;
+  const size_t BB = (size_t)c->B * c->B;
+  const size_t ns = 2 * BB * c->Nq;  // doubles per state
+  const long long ncx = (long long)BB * c->Nq;
+  std::memset(res, 0, sizeof(*res));
+  res->lambda_stop = o->lambda_end;
+  double m_prev = 0.0;
+  bool bad = false;
+  TRY(state_max(c, P, C, &m_prev, &bad));
+  if (bad) return fail(c, TUFRG_E_NONFINITE, "non-finite initial state");
+  double lam_prev = o->lambda0;
+
+  if (o->n_steps > 0) {
+    if (!c->d_dP) {
+      TRY(dalloc(c, &c->d_dP, ns));
+      TRY(dalloc(c, &c->d_dC, ns));
+    }
+    const int n = o->n_steps;
+    for (int i = 0; i < n; ++i) {
+      const double l0 = o->lambda0 * std::pow(o->lambda_end / o->lambda0, (double)i / n);
+      const double l1 = (i + 1 == n) ? o->lambda_end : o->lambda0 * std::pow(o->lambda_end / o->lambda0, (double)(i + 1) / n);
+      TRY(rhs_internal(c, l0, P, C, c->d_dP, c->d_dC, 1.0, mask));
+      res->n_rhs++;
+      HIPCHK(c, launch_clear_reduce(c->d_bits, c->d_flag, c->st));
+      HIPCHK(c, launch_axpy_max(ncx, P, l1 - l0, c->d_dP, P, c->d_bits, c->d_flag, c->st));
+      HIPCHK(c, launch_axpy_max(ncx, C, l1 - l0, c->d_dC, C, c->d_bits, c->d_flag, c->st));
+      double mx;
+      TRY(read_reduce(c, &mx, &bad));
+      if (bad) return fail(c, TUFRG_E_NONFINITE, "non-finite state after Euler step " + std::to_string(i));
+      res->n_steps++;
+      res->lambda_stop = l1;
+      res->max_coupling = mx;
+      if (mx > o->v_max) {
+        res->diverged = 1;
+        res->lambda_c = lambda_c_interp(lam_prev, m_prev, l1, mx, o->v_max);
+        break;
+      }
+      if (o->on_step && o->on_step(o->user, i, l1, mx)) {
+        res->stopped_by_callback = 1;
+        break;
+      }
+      if (o->max_steps > 0 && res->n_steps >= o->max_steps) break;
+      lam_prev = l1;
+      m_prev = mx;
+    }
+    return TUFRG_OK;
+  }
+
+  // Dormand-Prince 5(4) in l = ln Lambda, dX/dl = Lambda dX/dLambda
+  if (c->d_stage.empty()) {
+    for (int i = 0; i < 16; ++i) {
+      double *p = nullptr;
+      TRY(dalloc(c, &p, ns));
+      c->d_stage.push_back(p);
+    }
+  }
+  double *kP[7], *kC[7];
+  for (int j = 0; j < 7; ++j) {
+    kP[j] = c->d_stage[j];
+    kC[j] = c->d_stage[7 + j];
+  }
+  double *YP = c->d_stage[14], *YC = c->d_stage[15];
+  double l = std::log(o->lambda0);
+  const double l_end = std::log(o->lambda_end);
+  double h = -std::fabs(o->h0 > 0 ? o->h0 : 0.05);
+  TRY(rhs_internal(c, std::exp(l), P, C, kP[0], kC[0], std::exp(l), mask));
+  res->n_rhs++;
+  double ecoef[7];
+  for (int j = 0; j < 7; ++j) ecoef[j] = DP_B5[j] - DP_B4[j];
+  while (l - l_end > 1e-14) {
+    if (l + h < l_end) h = l_end - l;
+    for (int s = 1; s < 7; ++s) {
+      HIPCHK(c, launch_lincomb((long long)ns, P, s, kP, DP_A[s], h, YP, c->st));
+      HIPCHK(c, launch_lincomb((long long)ns, C, s, kC, DP_A[s], h, YC, c->st));
+      const double ls = std::exp(l + DP_C[s] * h);
+      TRY(rhs_internal(c, ls, YP, YC, kP[s], kC[s], ls, mask));
+      res->n_rhs++;
+    }
+    HIPCHK(c, launch_clear_reduce(c->d_bits, c->d_flag, c->st));
+    HIPCHK(c, launch_dp_error((long long)ns, P, YP, 7, kP, ecoef, h, o->rtol, o->atol, c->d_bits, c->d_flag, c->st));
+    HIPCHK(c, launch_dp_error((long long)ns, C, YC, 7, kC, ecoef, h, o->rtol, o->atol, c->d_bits, c->d_flag, c->st));
+    double err;
+    TRY(read_reduce(c, &err, &bad));
+    if (bad) return fail(c, TUFRG_E_NONFINITE, "non-finite error estimate at step " + std::to_string(res->n_steps));
+    const double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(err, -0.2)));
+    if (err <= 1.0) {
+      l += h;
+      HIPCHK(c, hipMemcpyAsync(P, YP, ns * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+      HIPCHK(c, hipMemcpyAsync(C, YC, ns * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+      std::swap(kP[0], kP[6]);
+      std::swap(kC[0], kC[6]);
+      double mx;
+      TRY(state_max(c, P, C, &mx, &bad));
+      if (bad) return fail(c, TUFRG_E_NONFINITE, "non-finite state after step " + std::to_string(res->n_steps));
+      const double lam = std::exp(l);
+      res->n_steps++;
+      res->lambda_stop = lam;
+      res->max_coupling = mx;
+      if (mx > o->v_max) {
+        res->diverged = 1;
+        res->lambda_c = lambda_c_interp(lam_prev, m_prev, lam, mx, o->v_max);
+        break;
+      }
+      if (o->on_step && o->on_step(o->user, res->n_steps - 1, lam, mx)) {
+        res->stopped_by_callback = 1;
+        break;
+      }
+      if (o->max_steps > 0 && res->n_steps >= o->max_steps) break;
+      lam_prev = lam;
+      m_prev = mx;
+    } else {
+      res->n_reject++;
+    }
+    h *= fac;
+    if (std::fabs(h) < 1e-12) return fail(c, TUFRG_E_STEPSIZE, "step size underflow");
+  }
+  if (l - l_end <= 1e-14) res->lambda_stop = o->lambda_end;
+  return TUFRG_OK;
+}

@@ -1,0 +1,208 @@
+"""Thin ctypes binding of libtufrg.so (the C ABI of include/tufrg.h).
+
+Argument marshalling only: every step of the right-hand side runs in the HIP
+library.  Device arrays are torch tensors of dtype complex128 on a ROCm device
+(contiguous, [Nq][B][B] unless stated); the library reads their data pointers.
+If the library has not been built, importing this module raises.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtufrg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`"
+    )
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+TUFRG_OK = 0
+STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NONFINITE", 5: "E_STEPSIZE",
+          6: "E_UNSUPPORTED"}
+CUT_TEMPERATURE, CUT_OMEGA = 0, 1
+FP64, FP32 = 0, 1
+PP, PH = 0, 1
+
+SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "tufrg_band_data",
+           "tufrg_bubble", "tufrg_project", "tufrg_rhs", "tufrg_flow", "tufrg_timing",
+           "tufrg_timing_read"]
+TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE = 0, 1, 2
+
+
+class c64(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("im", ctypes.c_double)]
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("n_orb", ctypes.c_int32), ("n_hop", ctypes.c_int32),
+                ("hop_R", ctypes.POINTER(ctypes.c_int32)), ("hop_t", ctypes.POINTER(c64)),
+                ("mu", ctypes.c_double), ("V0", ctypes.POINTER(c64))]
+
+
+class Setup(ctypes.Structure):
+    _fields_ = [("n_ff", ctypes.c_int32), ("ff_R", ctypes.POINTER(ctypes.c_int32)),
+                ("Lq", ctypes.c_int32), ("n_ref", ctypes.c_int32), ("cutoff", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
+
+
+STEP_CB = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                           ctypes.c_double)
+
+
+class FlowOpts(ctypes.Structure):
+    _fields_ = [("lambda0", ctypes.c_double), ("lambda_end", ctypes.c_double),
+                ("n_steps", ctypes.c_int32), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("h0", ctypes.c_double), ("v_max", ctypes.c_double),
+                ("channel_mask", ctypes.c_uint32), ("max_steps", ctypes.c_int32),
+                ("on_step", STEP_CB), ("user", ctypes.c_void_p)]
+
+
+class FlowResult(ctypes.Structure):
+    _fields_ = [("lambda_stop", ctypes.c_double), ("lambda_c", ctypes.c_double),
+                ("max_coupling", ctypes.c_double), ("diverged", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
+                ("n_reject", ctypes.c_int32), ("stopped_by_callback", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_lib.tufrg_create.argtypes = [ctypes.POINTER(Model), ctypes.POINTER(Setup), _vp, ctypes.POINTER(_vp)]
+_lib.tufrg_destroy.argtypes = [_vp]
+_lib.tufrg_last_error.argtypes = [_vp]
+_lib.tufrg_last_error.restype = ctypes.c_char_p
+_lib.tufrg_dims.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int32)] * 4
+_lib.tufrg_band_data.argtypes = [_vp, _vp, _vp]
+_lib.tufrg_bubble.argtypes = [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp]
+_lib.tufrg_project.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.tufrg_rhs.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
+_lib.tufrg_flow.argtypes = [_vp, ctypes.POINTER(FlowOpts), _vp, _vp, ctypes.POINTER(FlowResult)]
+_lib.tufrg_timing.argtypes = [_vp, ctypes.c_int32]
+_lib.tufrg_timing_read.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_int32)]
+for _f in ("tufrg_create", "tufrg_destroy", "tufrg_dims", "tufrg_band_data", "tufrg_bubble",
+           "tufrg_project", "tufrg_rhs", "tufrg_flow", "tufrg_timing", "tufrg_timing_read"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+
+class TufrgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status, ctx=None):
+    if status != TUFRG_OK:
+        msg = _lib.tufrg_last_error(ctx).decode(errors="replace")
+        raise TufrgError(status, msg)
+
+
+def _ptr(t):
+    """Data pointer of a device tensor (the library checks it is device memory)."""
+    if hasattr(t, "data_ptr"):
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return ctypes.c_void_p(t.data_ptr())
+    return ctypes.c_void_p(int(t))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+class Context:
+    """Owns a tufrg_ctx.  ``model``/``setup`` are host-side numpy inputs."""
+
+    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, cutoff, precision, stream=None):
+        hop_R = np.ascontiguousarray(hop_R, dtype=np.int32).reshape(-1, 2)
+        hop_t = np.ascontiguousarray(hop_t, dtype=np.complex128)
+        V0 = np.ascontiguousarray(V0, dtype=np.complex128)
+        ff = np.ascontiguousarray(ff, dtype=np.int32).reshape(-1, 2)
+        n_o = hop_t.shape[1]
+        self._keep = (hop_R, hop_t, V0, ff)
+        m = Model(n_o, hop_R.shape[0], hop_R.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                  hop_t.ctypes.data_as(ctypes.POINTER(c64)), float(mu),
+                  V0.ctypes.data_as(ctypes.POINTER(c64)))
+        cut = {"temperature": CUT_TEMPERATURE, "omega": CUT_OMEGA}.get(cutoff, cutoff)
+        prec = {"fp64": FP64, "fp32": FP32}.get(precision, precision)
+        s = Setup(ff.shape[0], ff.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(Lq), int(n_ref),
+                  int(cut), int(prec))
+        h = ctypes.c_void_p()
+        _check(_lib.tufrg_create(ctypes.byref(m), ctypes.byref(s), _stream_handle(stream),
+                                 ctypes.byref(h)))
+        self.handle = h
+        B, Nq, Nf, nD = (ctypes.c_int32() for _ in range(4))
+        _check(_lib.tufrg_dims(h, ctypes.byref(B), ctypes.byref(Nq), ctypes.byref(Nf),
+                               ctypes.byref(nD)), h)
+        self.B, self.Nq, self.Nf, self.n_dR = B.value, Nq.value, Nf.value, nD.value
+        self.n_o, self.n_ff = n_o, ff.shape[0]
+
+    @classmethod
+    def from_workload(cls, w, precision=None, stream=None, **over):
+        kw = dict(hop_R=w["hop_R"], hop_t=w["hop_t"], mu=w["mu"], V0=w["V0"], ff=w["ff"],
+                  Lq=w["Lq"], n_ref=w["n_ref"], cutoff=w["cutoff"],
+                  precision=precision if precision is not None else w["prec"])
+        kw.update(over)
+        return cls(stream=stream, **kw)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _lib.tufrg_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tufrg_band_data(ctx, e, Pi):
+    _check(_lib.tufrg_band_data(ctx.handle, _ptr(e), _ptr(Pi)), ctx.handle)
+
+
+def tufrg_bubble(ctx, channel, lam, deriv, L):
+    _check(_lib.tufrg_bubble(ctx.handle, int(channel), float(lam), int(deriv), _ptr(L)), ctx.handle)
+
+
+def tufrg_project(ctx, P, C, VP, VC):
+    _check(_lib.tufrg_project(ctx.handle, _ptr(P), _ptr(C), _ptr(VP), _ptr(VC)), ctx.handle)
+
+
+def tufrg_rhs(ctx, lam, P, C, dP, dC):
+    _check(_lib.tufrg_rhs(ctx.handle, float(lam), _ptr(P), _ptr(C), _ptr(dP), _ptr(dC)), ctx.handle)
+
+
+def tufrg_flow(ctx, P, C, lambda0, lambda_end, n_steps=0, rtol=1e-6, atol=1e-6, h0=0.05,
+               v_max=50.0, channel_mask=3, max_steps=0, on_step=None):
+    """Integrates P, C in place; returns the result as a dict."""
+    cb = STEP_CB(on_step) if on_step is not None else STEP_CB()
+    o = FlowOpts(float(lambda0), float(lambda_end), int(n_steps), float(rtol), float(atol),
+                 float(h0), float(v_max), int(channel_mask), int(max_steps), cb, None)
+    r = FlowResult()
+    _check(_lib.tufrg_flow(ctx.handle, ctypes.byref(o), _ptr(P), _ptr(C), ctypes.byref(r)),
+           ctx.handle)
+    return r.as_dict()
+
+
+def tufrg_timing(ctx, enable):
+    _check(_lib.tufrg_timing(ctx.handle, int(bool(enable))), ctx.handle)
+
+
+def tufrg_timing_read(ctx, timer):
+    """(total milliseconds, number of timed intervals) of one timer."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int32()
+    _check(_lib.tufrg_timing_read(ctx.handle, int(timer), ctypes.byref(ms), ctypes.byref(n)),
+           ctx.handle)
+    return ms.value, n.value

@@ -1,0 +1,229 @@
+"""Parity of the HIP library against the FP64 oracle (GPU).
+
+Every call goes through the C ABI (ctypes binding).  Tolerances: FP64 paths
+1e-10 relative (max-norm over all entries relative to the largest reference
+entry; the oracle and the kernels sum in different orders and the kernels use
+a two-point rule for near-degenerate divided differences), FP32 loops 1e-5.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import bands as obands  # noqa: E402
+from oracle import tufrg as otu  # noqa: E402
+from synth import ff_shell, hubbard_hoppings, onsite_V0, random_exchange_state, rashba_hoppings, workload  # noqa: E402
+from tests._layout import (c_to_matrix, p_to_matrix, ph_loop_to_matrix,  # noqa: E402
+                           pp_loop_to_matrix)
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_08830_amd import tufrg
+    return tufrg
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _case(name):
+    """Small cases: ragged fine meshes (Lf not a multiple of 64), several ky
+    blocks and kx chunks, both cutoffs, the 5-, 9- and 13-vector shells."""
+    if name == "hub5":
+        return dict(hop=hubbard_hoppings(1.0, -0.25), mu=-0.6, V0=onsite_V0(3.0), ff=ff_shell(5),
+                    Lq=6, n_ref=3, cutoff="temperature")
+    if name == "ras9":
+        return dict(hop=rashba_hoppings(1.0, 0.3), mu=-0.4, V0=onsite_V0(2.5), ff=ff_shell(9),
+                    Lq=5, n_ref=15, cutoff="omega")
+    if name == "ras13":
+        return dict(hop=rashba_hoppings(1.0, 0.45, tp=0.1), mu=-0.2, V0=onsite_V0(2.0), ff=ff_shell(13),
+                    Lq=9, n_ref=8, cutoff="temperature")
+    raise KeyError(name)
+
+
+def _ctx(T, c, prec):
+    return T.Context(c["hop"][0], c["hop"][1], c["mu"], c["V0"], c["ff"], c["Lq"], c["n_ref"],
+                     c["cutoff"], prec)
+
+
+def _setup(c):
+    return otu.TUSetup(*c["hop"], c["mu"], c["V0"], c["ff"], c["Lq"], c["n_ref"], c["cutoff"])
+
+
+def _zeros(ctx):
+    return torch.zeros((ctx.Nq, ctx.B, ctx.B), dtype=torch.complex128, device=dev())
+
+
+@pytest.mark.parametrize("name", ["hub5", "ras9"])
+def test_band_data_matches_oracle(T, name):
+    c = _case(name)
+    ctx = _ctx(T, c, "fp64")
+    n = ctx.n_o
+    e = torch.zeros((n, ctx.Nf), dtype=torch.float64, device=dev())
+    Pi = torch.zeros((n, ctx.Nf, n, n), dtype=torch.complex128, device=dev())
+    T.tufrg_band_data(ctx, e, Pi)
+    torch.cuda.synchronize()
+    e_ref, U_ref = obands.band_data(*c["hop"], c["mu"], c["Lq"] * c["n_ref"])
+    assert np.abs(e.cpu().numpy().T - e_ref).max() < 1e-12
+    Pi = Pi.cpu().numpy()
+    # gauge-invariant: sum_m g(e_m) Pi_m for a generic g, and completeness
+    g = lambda x: np.exp(-0.7 * x) + x ** 3  # noqa: E731
+    got = np.einsum("mk,mkab->kab", g(e.cpu().numpy()), Pi)
+    Pi_ref = obands.projectors(U_ref)
+    ref = np.einsum("km,kmab->kab", g(e_ref), Pi_ref)
+    assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
+    assert np.abs(Pi.sum(axis=0) - np.eye(n)[None]).max() < 1e-13
+
+
+@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("channel", ["pp", "ph"])
+@pytest.mark.parametrize("deriv", [1, 0])
+def test_bubble_matches_oracle(T, name, prec, channel, deriv):
+    c = _case(name)
+    ctx = _ctx(T, c, prec)
+    st = _setup(c)
+    lam = 0.35
+    L = _zeros(ctx)
+    T.tufrg_bubble(ctx, T.PP if channel == "pp" else T.PH, lam, deriv, L)
+    torch.cuda.synchronize()
+    got = L.cpu().numpy()
+    ref_t = otu.loops(st, channel, lam, deriv=bool(deriv))
+    ref = pp_loop_to_matrix(ref_t) if channel == "pp" else ph_loop_to_matrix(ref_t)
+    assert rel(got, ref) < TOL[prec]
+
+
+@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13"])
+def test_project_matches_oracle(T, name):
+    c = _case(name)
+    ctx = _ctx(T, c, "fp64")
+    st = _setup(c)
+    P = random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=5)
+    C = random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=6)
+    Pd = torch.from_numpy(p_to_matrix(P)).to(dev())
+    Cd = torch.from_numpy(c_to_matrix(C)).to(dev())
+    VP, VC = _zeros(ctx), _zeros(ctx)
+    T.tufrg_project(ctx, Pd, Cd, VP, VC)
+    torch.cuda.synchronize()
+    rVP, rVC = otu.projected_vertices(st, P, C)
+    assert rel(VP.cpu().numpy(), p_to_matrix(rVP)) < 1e-12
+    assert rel(VC.cpu().numpy(), c_to_matrix(rVC)) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rhs_matches_oracle(T, name, prec):
+    c = _case(name)
+    ctx = _ctx(T, c, prec)
+    st = _setup(c)
+    P = 0.2 * random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=7)
+    C = 0.2 * random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=8)
+    Pd = torch.from_numpy(p_to_matrix(P)).to(dev())
+    Cd = torch.from_numpy(c_to_matrix(C)).to(dev())
+    dP, dC = _zeros(ctx), _zeros(ctx)
+    lam = 0.4
+    T.tufrg_rhs(ctx, lam, Pd, Cd, dP, dC)
+    torch.cuda.synchronize()
+    rP, rC = otu.rhs(st, lam, P, C)
+    tol = TOL[prec] * (1 if prec == "fp64" else 3)
+    assert rel(dP.cpu().numpy(), p_to_matrix(rP)) < tol
+    assert rel(dC.cpu().numpy(), c_to_matrix(rC)) < tol
+
+
+def test_rhs_is_deterministic(T):
+    c = _case("ras9")
+    ctx = _ctx(T, c, "fp32")
+    st = _setup(c)
+    P = torch.from_numpy(p_to_matrix(random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=9))).to(dev())
+    C = torch.from_numpy(c_to_matrix(random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=10))).to(dev())
+    outs = []
+    for _ in range(2):
+        dP, dC = _zeros(ctx), _zeros(ctx)
+        T.tufrg_rhs(ctx, 0.3, P, C, dP, dC)
+        torch.cuda.synchronize()
+        outs.append((dP.cpu().numpy(), dC.cpu().numpy()))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_euler_flow_matches_oracle(T, prec):
+    w = workload("hubbard_s5_small")
+    ctx = T.Context.from_workload(w, precision=prec)
+    st = otu.TUSetup.from_workload(w)
+    n = 12
+    Pr, Cr, rr = otu.flow_euler(st, w["lam0"], 0.05, n, v_max=w["v_max"])
+    P, C = _zeros(ctx), _zeros(ctx)
+    res = T.tufrg_flow(ctx, P, C, w["lam0"], 0.05, n_steps=n, v_max=w["v_max"])
+    torch.cuda.synchronize()
+    assert res["n_steps"] == rr["n_steps"] and res["diverged"] == rr["diverged"]
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert rel(P.cpu().numpy(), p_to_matrix(Pr)) < tol
+    assert rel(C.cpu().numpy(), c_to_matrix(Cr)) < tol
+    assert res["max_coupling"] == pytest.approx(rr["max_coupling"], rel=tol)
+
+
+def test_euler_flow_divergence_and_critical_scale(T):
+    # attractive Hubbard: the pp channel diverges at a finite scale
+    hop = hubbard_hoppings(1.0, -0.25)
+    args = (*hop, -0.5, onsite_V0(-4.0), ff_shell(5), 6, 2, "temperature")
+    st = otu.TUSetup(*args)
+    Pr, Cr, rr = otu.flow_euler(st, 5.0, 0.01, 30, v_max=20.0)
+    assert rr["diverged"] == 1
+    ctx = T.Context(*args, "fp64")
+    P, C = _zeros(ctx), _zeros(ctx)
+    res = T.tufrg_flow(ctx, P, C, 5.0, 0.01, n_steps=30, v_max=20.0)
+    assert res["diverged"] == 1 and res["n_steps"] == rr["n_steps"]
+    assert res["lambda_c"] == pytest.approx(rr["lambda_c"], rel=1e-9)
+    assert rel(P.cpu().numpy(), p_to_matrix(Pr)) < 1e-10
+
+
+def test_dp54_flow_matches_oracle(T):
+    c = _case("ras9")
+    ctx = _ctx(T, c, "fp64")
+    st = _setup(c)
+    Pr, Cr, rr = otu.flow_dp54(st, 10.0, 0.5, rtol=1e-6, atol=1e-6)
+    P, C = _zeros(ctx), _zeros(ctx)
+    res = T.tufrg_flow(ctx, P, C, 10.0, 0.5, n_steps=0, rtol=1e-6, atol=1e-6)
+    torch.cuda.synchronize()
+    assert res["n_steps"] == rr["n_steps"] and res["n_reject"] == rr["n_reject"]
+    assert rel(P.cpu().numpy(), p_to_matrix(Pr)) < 1e-9
+    assert rel(C.cpu().numpy(), c_to_matrix(Cr)) < 1e-9
+
+
+def test_host_pointer_rejected(T):
+    c = _case("hub5")
+    ctx = _ctx(T, c, "fp64")
+    host = torch.zeros((ctx.Nq, ctx.B, ctx.B), dtype=torch.complex128)
+    with pytest.raises(T.TufrgError) as ei:
+        T.tufrg_bubble(ctx, T.PP, 0.3, 1, host)
+    assert ei.value.status == 1
+
+
+def test_full_size_rashba_loops_on_sampled_q(T):
+    """The 24x24 q-mesh refined 24x (Omega cutoff) at the benchmark's launch
+    shape; the oracle recomputes a sample of q points one by one."""
+    w = workload("rashba_s9_L24")
+    st = otu.TUSetup.from_workload(w)
+    lam = 0.2
+    for prec in ("fp64", "fp32"):
+        ctx = T.Context.from_workload(w, precision=prec)
+        for channel, code, conv in (("pp", T.PP, pp_loop_to_matrix), ("ph", T.PH, ph_loop_to_matrix)):
+            L = _zeros(ctx)
+            T.tufrg_bubble(ctx, code, lam, 1, L)
+            torch.cuda.synchronize()
+            for qi in (0, 37, 300, 575):
+                ref = conv(otu.loops(st, channel, lam, q_list=[qi]))[0]
+                assert rel(L[qi].cpu().numpy(), ref) < TOL[prec], (prec, channel, qi)
+        ctx.close()

@@ -31,7 +31,7 @@ METRIC = "loop entries/s + flow steps/s, mixed/surrogate vs FP64-plain at ≤1e-
 WORKLOAD = "rashba_s9_L24"
 # algorithmic FP32 flops of the loop kernel per (q, k, channel) for two
 # spin-orbitals and the 3 x 5 (dx >= 0, dy) phase box; derivation in the design doc
-LOOP_FLOPS_PER_PAIR = 368
+LOOP_FLOPS_PER_PAIR = 204
 PEAK_FP32_VECTOR = 157.3e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "loop_kernel_traffic_rashba_s9_L24.json")
 

@@ -78,14 +78,44 @@ __device__ inline void loop_no2_body(const T *__restrict__ band, const T *__rest
   kpx = ((kpx % Lf) + Lf) % Lf;
   unsigned kb = ((unsigned)x0 * Lf + ky) * (unsigned)sizeof(T);
   const unsigned rowb = (unsigned)Lf * (unsigned)sizeof(T);
+  // software pipeline: the 16 loads of iteration kx + 1 are issued before the
+  // arithmetic of iteration kx
+  struct Pt {
+    T e[2], K[2], d0, d1, r, i;
+  };
+  auto load = [&](unsigned b, Pt &p) {
+    p.e[0] = ldb(e0, b);
+    p.e[1] = ldb(e1, b);
+    p.K[0] = ldb(K0, b);
+    p.K[1] = ldb(K1, b);
+    p.d0 = ldb(p00, b);
+    p.d1 = ldb(p11, b);
+    p.r = ldb(p0r, b);
+    p.i = ldb(p0i, b);
+  };
+  Pt ck, cp, nk, np;
+  unsigned kpb_cur = ((unsigned)kpx * Lf + kpy) * (unsigned)sizeof(T);
+  load(kb, ck);
+  load(kpb_cur, cp);
+  // FP64 keeps the plain order: its register budget is already at one or two waves per SIMD
+  constexpr bool PIPE = sizeof(T) == 4;
   for (int kx = x0; kx < x1; ++kx, kb += rowb) {
-    const unsigned kpb = ((unsigned)kpx * Lf + kpy) * (unsigned)sizeof(T);
     kpx += (CH == 0) ? -1 : 1;
     kpx = kpx < 0 ? kpx + Lf : (kpx >= Lf ? kpx - Lf : kpx);
-    const T ekm[2] = {ldb(e0, kb), ldb(e1, kb)}, Kkm[2] = {ldb(K0, kb), ldb(K1, kb)};
-    const T P0 = ldb(p00, kb), P1 = ldb(p11, kb), Pr = ldb(p0r, kb), Pi = ldb(p0i, kb);
-    const T epn[2] = {ldb(e0, kpb), ldb(e1, kpb)}, Kpn[2] = {ldb(K0, kpb), ldb(K1, kpb)};
-    const T X0 = ldb(p00, kpb), X1 = ldb(p11, kpb), Xr = ldb(p0r, kpb), Xi = sg * ldb(p0i, kpb);
+    if constexpr (PIPE) {
+      // the last prefetch re-reads a valid row and is not used
+      const unsigned kbn = (kx + 1 < x1) ? kb + rowb : kb;
+      load(kbn, nk);
+      load(((unsigned)kpx * Lf + kpy) * (unsigned)sizeof(T), np);
+    } else if (kx > x0) {
+      load(kb, ck);
+      load(kpb_cur, cp);
+    }
+    const unsigned kpb_next = ((unsigned)kpx * Lf + kpy) * (unsigned)sizeof(T);
+    const T ekm[2] = {ck.e[0], ck.e[1]}, Kkm[2] = {ck.K[0], ck.K[1]};
+    const T P0 = ck.d0, P1 = ck.d1, Pr = ck.r, Pi = ck.i;
+    const T epn[2] = {cp.e[0], cp.e[1]}, Kpn[2] = {cp.K[0], cp.K[1]};
+    const T X0 = cp.d0, X1 = cp.d1, Xr = cp.r, Xi = sg * cp.i;
     // loop kernels L_mn: pp (K(e1)+K(e2))/(e1+e2), ph -(K(e1)-K(e2))/(e1-e2); divided
     // difference of K at x = e_m(k), y = -sg e_n(k'); one branch for the rare near-degenerate lanes
     T L[2][2];
@@ -154,21 +184,54 @@ __device__ inline void loop_no2_body(const T *__restrict__ band, const T *__rest
         Bc[d][t][1] = fma(s, mc[t][1], Bc[d][t][1]);
       }
     }
+    if constexpr (PIPE) {
+      ck = nk;
+      cp = np;
+    }
+    kpb_cur = kpb_next;
   }
 }
 
-// One wave per (ky block, kx chunk, q, channel).
-template <typename T, int NDX, int NDY, int SCHEME>
-__global__ __launch_bounds__(64) void loop_no2_kernel(const T *__restrict__ band, const T *__restrict__ kv,
-                                                      const double *__restrict__ tw, int Lq, int n_ref, int Lf,
-                                                      int nkyb, int kxper, int q_first, int ch_first, T lam,
-                                                      int deriv, double *__restrict__ partial) {
+// A workgroup holds QW waves that share the ky block, q_x, kx chunk and
+// channel and take QW consecutive q_y: they read the same k addresses and
+// overlapping k -/+ q rows at the same time.  Workgroups are handed to the 8
+// XCDs round-robin by linear id; each XCD is given a contiguous slice of the
+// work items, ordered (ky block, q_y group, q_x, kx chunk, channel) from
+// fastest to slowest, so that co-resident workgroups share rows in its L2.
+constexpr int N_XCD = 8;
+
+template <typename T>
+struct loop_waves {
+  static constexpr int v = (sizeof(T) == 4) ? 4 : 2;
+};
+
+// QW waves per work item (ky block, q_y group, q_x, kx chunk, channel).
+template <typename T, int NDX, int NDY, int SCHEME, int QW>
+__global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 2 : 3))) void loop_no2_kernel(const T *__restrict__ band, const T *__restrict__ kv,
+                                                           const double *__restrict__ tw, int Lq, int n_ref, int Lf,
+                                                           int nkyb, int nkxc, int kxper, int q_first, int n_q,
+                                                           int ch_first, int n_items, T lam, int deriv,
+                                                           double *__restrict__ partial) {
   constexpr int NDY2 = 2 * NDY + 1;
-  const int tid = threadIdx.x;
-  const int kyb = blockIdx.x % nkyb, kxc = blockIdx.x / nkyb;
-  const int nparts = gridDim.x;
-  const int qrel = blockIdx.y, qi = q_first + qrel;
-  const int chrel = blockIdx.z, ch = ch_first + chrel;
+  const int tid = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int xcd = blockIdx.x % N_XCD, slot = blockIdx.x / N_XCD;
+  const int base = n_items / N_XCD, rem = n_items % N_XCD;
+  if (slot >= base + (xcd < rem ? 1 : 0)) return;  // padding workgroup, no work
+  int w = xcd * base + min(xcd, rem) + slot;
+  const int kyb = w % nkyb;
+  w /= nkyb;
+  const int nqyg = (Lq + QW - 1) / QW;
+  const int qyg = w % nqyg;
+  w /= nqyg;
+  const bool qvalid = qyg * QW + wv < Lq;
+  const int qy = qvalid ? qyg * QW + wv : Lq - 1;
+  const int nqx = n_q / Lq;
+  const int qx = w % nqx;
+  w /= nqx;
+  const int kxc = w % nkxc;
+  const int chrel = w / nkxc, ch = ch_first + chrel;
+  const int qrel = qx * Lq + qy, qi = q_first + qrel;
+  const int nparts = nkyb * nkxc;
   const int qfx = (qi / Lq) * n_ref, qfy = (qi % Lq) * n_ref;
   const int ky_raw = kyb * 64 + tid;
   const bool active = ky_raw < Lf;
@@ -196,18 +259,21 @@ __global__ __launch_bounds__(64) void loop_no2_kernel(const T *__restrict__ band
     loop_no2_body<T, NDX, SCHEME, 1>(band, kv, tw, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac, Bc);
 
   // rebuild all 16 entries per dx, transpose through LDS, contract with e^{-i 2 pi ky dy / Lf}
-  __shared__ T buf[32][65];
+  __shared__ T bufs[QW][32][65];
   __shared__ T phy[NDY2][2][64];
+  T(&buf)[32][65] = bufs[wv];
+  if (wv == 0) {
 #pragma unroll
-  for (int i = 0; i < NDY2; ++i) {
-    int dy = i - NDY;
-    int j = (int)(((long long)ky_raw * dy) % Lf);
-    if (j < 0) j += Lf;
-    phy[i][0][tid] = (T)tw[2 * j];
-    phy[i][1][tid] = (T)tw[2 * j + 1];
+    for (int i = 0; i < NDY2; ++i) {
+      int dy = i - NDY;
+      int j = (int)(((long long)ky_raw * dy) % Lf);
+      if (j < 0) j += Lf;
+      phy[i][0][tid] = (T)tw[2 * j];
+      phy[i][1][tid] = (T)tw[2 * j + 1];
+    }
   }
   const T on = active ? T(1) : T(0);
-  const size_t pbase = (((size_t)chrel * gridDim.y + qrel) * nparts + blockIdx.x) * (size_t)(NDX * NDY2 * 16);
+  const size_t pbase = (((size_t)chrel * n_q + qrel) * nparts + (kyb + nkyb * kxc)) * (size_t)(NDX * NDY2 * 16);
 #pragma unroll
   for (int dx = 0; dx < NDX; ++dx) {
     __syncthreads();
@@ -255,24 +321,33 @@ __global__ __launch_bounds__(64) void loop_no2_kernel(const T *__restrict__ band
         si = fma(pim, ar, si);
       }
       const size_t idx = pbase + ((size_t)(dx * NDY2 + dyi) * 16 + t);
-      partial[2 * idx] = (double)sr;
-      partial[2 * idx + 1] = (double)si;
+      if (qvalid) {
+        partial[2 * idx] = (double)sr;
+        partial[2 * idx + 1] = (double)si;
+      }
     }
   }
 }
 
 template <typename T, int NDX, int NDY>
 static hipError_t launch_no2(const LoopArgs &a, hipStream_t st) {
+  if (a.q_first % a.Lq != 0 || a.n_q % a.Lq != 0) return hipErrorInvalidValue;  // whole q_x rows
+  constexpr int QW = loop_waves<T>::v;
   const int kxper = (a.Lf + a.nkxc - 1) / a.nkxc;
-  dim3 grid(a.nkyb * a.nkxc, a.n_q, a.n_ch), block(64);
+  const int nqyg = (a.Lq + QW - 1) / QW;
+  const int n_items = a.nkyb * a.nkxc * nqyg * (a.n_q / a.Lq) * a.n_ch;
+  const int n_wg = ((n_items + N_XCD - 1) / N_XCD) * N_XCD;
+  dim3 grid(n_wg), block(64 * QW);
   const T *band = (const T *)a.band;
   const T *kv = (const T *)a.kv;
   if (a.scheme == CUT_TEMPERATURE)
-    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_TEMPERATURE>), grid, block, 0, st, band, kv, a.tw, a.Lq,
-                       a.n_ref, a.Lf, a.nkyb, kxper, a.q_first, a.ch_first, (T)a.lam, a.deriv, a.partial);
+    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_TEMPERATURE, QW>), grid, block, 0, st, band, kv, a.tw, a.Lq,
+                       a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.ch_first, n_items, (T)a.lam,
+                       a.deriv, a.partial);
   else
-    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_OMEGA>), grid, block, 0, st, band, kv, a.tw, a.Lq,
-                       a.n_ref, a.Lf, a.nkyb, kxper, a.q_first, a.ch_first, (T)a.lam, a.deriv, a.partial);
+    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_OMEGA, QW>), grid, block, 0, st, band, kv, a.tw, a.Lq,
+                       a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.ch_first, n_items, (T)a.lam,
+                       a.deriv, a.partial);
   return hipGetLastError();
 }
 

@@ -5,6 +5,9 @@
 // Small-bundle variant (B <= 64): one workgroup per q, the compact loop and the
 // intermediate L.V staged in LDS, and the vertex too when it fits (VLDS);
 // arithmetic in T (FP64 or FP32), inputs and outputs in FP64.
+// Large bundles: two batched complex GEMMs per q (tmp = L.V, out = f V.tmp),
+// 64 x 64 output tiles with 16-wide k panels staged in LDS, the loop matrix
+// expanded from its compact form while its panel is loaded.
 #include "common.h"
 #include "kernels.h"
 
@@ -59,14 +62,103 @@ __global__ __launch_bounds__(256) void bundle_small_kernel(int n_o, int n_ff, in
   }
 }
 
+// C[q] = alpha A[q] Bm[q]; A is the loop expanded from compact form (AL) or dense
+template <typename T, bool AL>
+__global__ __launch_bounds__(256) void bundle_gemm_kernel(int B, int n_o, int n_ff, int nD,
+                                                          const int *__restrict__ didx,
+                                                          const double *__restrict__ A,
+                                                          const double *__restrict__ Bm, double alpha,
+                                                          double *__restrict__ C) {
+  constexpr int TM = 64, TN = 64, TK = 16;
+  __shared__ cx<T> sA[TK][TM + 1];
+  __shared__ cx<T> sB[TK][TN + 1];
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int j0 = blockIdx.x * TN, i0 = blockIdx.y * TM;
+  const size_t q = blockIdx.z;
+  const int no2 = n_o * n_o, no4 = no2 * no2;
+  const size_t BB = (size_t)B * B;
+  const double *Aq = AL ? A + 2 * q * (size_t)nD * no4 : A + 2 * q * BB;
+  const double *Bq = Bm + 2 * q * BB;
+  cx<T> acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = cmake(T(0), T(0));
+  for (int k0 = 0; k0 < B; k0 += TK) {
+    for (int e = tid; e < TM * TK; e += 256) {
+      const int ii = e / TK, kk = e % TK;
+      const int i = i0 + ii, k = k0 + kk;
+      cx<T> v = cmake(T(0), T(0));
+      if (i < B && k < B) {
+        size_t src;
+        if (AL) {
+          const int ri = i / no2, rk = k / no2;
+          src = (size_t)didx[ri * n_ff + rk] * no4 + (size_t)(i % no2) * no2 + (k % no2);
+        } else {
+          src = (size_t)i * B + k;
+        }
+        v = cmake((T)Aq[2 * src], (T)Aq[2 * src + 1]);
+      }
+      sA[kk][ii] = v;
+    }
+    for (int e = tid; e < TK * TN; e += 256) {
+      const int kk = e / TN, jj = e % TN;
+      const int k = k0 + kk, j = j0 + jj;
+      cx<T> v = cmake(T(0), T(0));
+      if (k < B && j < B) v = cmake((T)Bq[2 * ((size_t)k * B + j)], (T)Bq[2 * ((size_t)k * B + j) + 1]);
+      sB[kk][jj] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < TK; ++kk) {
+      cx<T> a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = sA[kk][ty * 4 + r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = sB[kk][tx * 4 + c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cfma(acc[r][c], a[r], b[c]);
+    }
+    __syncthreads();
+  }
+  double *Cq = C + 2 * q * BB;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + ty * 4 + r, j = j0 + tx * 4 + c;
+      if (i < B && j < B) {
+        Cq[2 * ((size_t)i * B + j)] = alpha * (double)acc[r][c].re;
+        Cq[2 * ((size_t)i * B + j) + 1] = alpha * (double)acc[r][c].im;
+      }
+    }
+}
+
 hipError_t launch_bundle(int prec, int n_o, int n_ff, int B, int nD, int n_q, const int *didx, const double *V,
-                         const double *Lc, double factor, double *out, hipStream_t st) {
+                         const double *Lc, double factor, double *out, double *tmp, hipStream_t st) {
   const int no4 = n_o * n_o * n_o * n_o;
   const size_t csz = (prec == 0) ? 16 : 8;
   const size_t base = csz * ((size_t)B * B + (size_t)nD * no4) + sizeof(int) * ((n_ff * n_ff + 3) & ~3);
   const size_t withV = base + csz * (size_t)B * B;
   const size_t limit = 64 * 1024;
-  if (base > limit) return hipErrorInvalidValue;
+  if (B > 64 || base > limit) {
+    if (!tmp) return hipErrorInvalidValue;
+    dim3 grid((B + 63) / 64, (B + 63) / 64, n_q), block(256);
+    if (prec == 0) {
+      hipLaunchKernelGGL((bundle_gemm_kernel<double, true>), grid, block, 0, st, B, n_o, n_ff, nD, didx, Lc, V, 1.0,
+                         tmp);
+      hipLaunchKernelGGL((bundle_gemm_kernel<double, false>), grid, block, 0, st, B, n_o, n_ff, nD, didx, V, tmp,
+                         factor, out);
+    } else {
+      hipLaunchKernelGGL((bundle_gemm_kernel<float, true>), grid, block, 0, st, B, n_o, n_ff, nD, didx, Lc, V, 1.0,
+                         tmp);
+      hipLaunchKernelGGL((bundle_gemm_kernel<float, false>), grid, block, 0, st, B, n_o, n_ff, nD, didx, V, tmp,
+                         factor, out);
+    }
+    return hipGetLastError();
+  }
   const bool vlds = withV <= limit;
   const size_t lds = vlds ? withV : base;
   if (prec == 0) {

@@ -352,6 +352,7 @@ static hipError_t launch_no2(const LoopArgs &a, hipStream_t st) {
 }
 
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st) {
+  if (a.n_o == 6) return launch_loop_gen(a, st);
   if (a.n_o != 2) return hipErrorInvalidValue;
   const bool f64 = (a.prec == 0);
   if (a.ndx == 3 && a.ndy == 2) return f64 ? launch_no2<double, 3, 2>(a, st) : launch_no2<float, 3, 2>(a, st);

@@ -26,6 +26,8 @@ struct LoopArgs {
   double *partial;     // [n_ch][n_q][nkyb * nkxc][ndx][2 ndy + 1][n_o^4][2]
 };
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
+// more than two spin-orbitals (six: t2g with spin-orbit coupling)
+hipError_t launch_loop_gen(const LoopArgs &a, hipStream_t st);
 // sums partials, applies 1/Nf, fills dx < 0 by hermiticity
 hipError_t launch_loop_finalize(const LoopArgs &a, int nD, const int *dlist, double *compact, hipStream_t st);
 // compact [n_ch][n_q][nD][n_o^4] -> full [n_q][B][B] for one channel
@@ -47,9 +49,10 @@ hipError_t launch_gather(const ProjArgs &a, const double *real, double *G, hipSt
 hipError_t launch_assemble(const ProjArgs &a, const double *P, const double *C, const double *G,
                            const double *v0p, const double *v0c, double *VP, double *VC, hipStream_t st);
 
-// a6: bundle products  out = f * V L V  per q, L expanded from compact form
+// a6: bundle products  out = f * V L V  per q, L expanded from compact form;
+// bundles larger than 64 need a workspace tmp of n_q * B * B complex
 hipError_t launch_bundle(int prec, int n_o, int n_ff, int B, int nD, int n_q, const int *didx, const double *V,
-                         const double *Lc, double factor, double *out, hipStream_t st);
+                         const double *Lc, double factor, double *out, double *tmp, hipStream_t st);
 
 // a7: ODE updates and reductions
 hipError_t launch_axpy_max(long long n, const double *x, double h, const double *dx, double *y,

@@ -50,6 +50,7 @@ struct tufrg_ctx {
   unsigned int *h_flag = nullptr;        // pinned
   // flow workspace (lazy)
   double *d_dP = nullptr, *d_dC = nullptr;
+  double *d_btmp = nullptr;  // bundle workspace for B > 64
   std::vector<double *> d_stage;  // DP5: 7 k's per channel + stage state per channel
   std::string err;
   std::vector<void *> allocs;
@@ -141,8 +142,8 @@ extern "C" const char *tufrg_last_error(const tufrg_ctx *ctx) { return ctx ? ctx
 extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s, void *stream, tufrg_ctx **out) {
   if (!m || !s || !out) return fail(nullptr, TUFRG_E_INVAL, "null argument");
   *out = nullptr;
-  if (m->n_orb != 2)
-    return fail(nullptr, TUFRG_E_UNSUPPORTED, "this build supports n_orb = 2 spin-orbitals");
+  if (m->n_orb != 2 && m->n_orb != 6)
+    return fail(nullptr, TUFRG_E_UNSUPPORTED, "this build supports n_orb = 2 or 6 spin-orbitals");
   if (m->n_hop < 1 || !m->hop_R || !m->hop_t || !m->V0) return fail(nullptr, TUFRG_E_INVAL, "empty model");
   if (s->n_ff < 1 || !s->ff_R) return fail(nullptr, TUFRG_E_INVAL, "empty form-factor set");
   if (s->ff_R[0] != 0 || s->ff_R[1] != 0) return fail(nullptr, TUFRG_E_INVAL, "ff_R[0] must be (0,0)");
@@ -216,11 +217,19 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     c->ndx = 5;
     c->ndy = 4;
   }
-  c->nkyb = (c->Lf + 63) / 64;
-  {
+  if (c->n_o == 2) {
+    c->nkyb = (c->Lf + 63) / 64;
     long long base = 2LL * c->Nq * c->nkyb;
     int want = (int)std::max<long long>(1, (4096 + base - 1) / base);
     c->nkxc = std::max(1, std::min(want, std::max(1, c->Lf / 8)));
+  } else {
+    // the multi-orbital loop kernel sums every k of a (q, channel) in one workgroup
+    c->nkyb = 1;
+    c->nkxc = 1;
+    if (!(c->ndx == 5 && c->ndy == 4) && !(c->ndx == 3 && c->ndy == 2)) {
+      c->ndx = 3;
+      c->ndy = 2;
+    }
   }
   {
     long long BB2 = 2LL * c->B * c->B;
@@ -272,6 +281,7 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CTRY(dalloc(c, &c->d_v0c, 2 * BB));
   CTRY(dalloc(c, &c->d_VP, 2 * BB * c->Nq));
   CTRY(dalloc(c, &c->d_VC, 2 * BB * c->Nq));
+  if (c->B > 64) CTRY(dalloc(c, &c->d_btmp, 2 * BB * c->Nq));
   CTRY(dalloc(c, &c->d_bits, 4));
   CTRY(dalloc(c, &c->d_flag, 4));
   CHIP(hipHostMalloc((void **)&c->h_bits, 4 * sizeof(unsigned long long), hipHostMallocDefault));
@@ -429,12 +439,12 @@ static tufrg_status rhs_internal(tufrg_ctx *c, double lam, const double *P, cons
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_BUNDLE));
   if (mask & 1u)
     HIPCHK(c, launch_bundle(c->prec, c->n_o, c->n_ff, c->B, c->nD, c->Nq, c->d_didx, c->d_VP, c->d_loop, scale, dP,
-                            c->st));
+                            c->d_btmp, c->st));
   else
     HIPCHK(c, hipMemsetAsync(dP, 0, 2 * sizeof(double) * BB * c->Nq, c->st));
   if (mask & 2u)
     HIPCHK(c, launch_bundle(c->prec, c->n_o, c->n_ff, c->B, c->nD, c->Nq, c->d_didx, c->d_VC, c->d_loop + lsz,
-                            2.0 * scale, dC, c->st));
+                            2.0 * scale, dC, c->d_btmp, c->st));
   else
     HIPCHK(c, hipMemsetAsync(dC, 0, 2 * sizeof(double) * BB * c->Nq, c->st));
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_BUNDLE));

@@ -15,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 from oracle import bands as obands  # noqa: E402
 from oracle import tufrg as otu  # noqa: E402
-from synth import ff_shell, hubbard_hoppings, onsite_V0, random_exchange_state, rashba_hoppings, workload  # noqa: E402
+from synth import (ff_shell, hubbard_hoppings, kanamori_V0, onsite_V0, random_exchange_state,  # noqa: E402
+                   rashba_hoppings, t2g_soc_hoppings, workload)
 from tests._layout import (c_to_matrix, p_to_matrix, ph_loop_to_matrix,  # noqa: E402
                            pp_loop_to_matrix)
 
@@ -50,6 +51,12 @@ def _case(name):
     if name == "ras13":
         return dict(hop=rashba_hoppings(1.0, 0.45, tp=0.1), mu=-0.2, V0=onsite_V0(2.0), ff=ff_shell(13),
                     Lq=9, n_ref=8, cutoff="temperature")
+    if name == "t2g13":
+        return dict(hop=t2g_soc_hoppings(0.2, seed=1), mu=0.35, V0=kanamori_V0(2.0, 0.3), ff=ff_shell(13),
+                    Lq=9, n_ref=2, cutoff="temperature")
+    if name == "t2g9":
+        return dict(hop=t2g_soc_hoppings(0.2, seed=1), mu=0.35, V0=kanamori_V0(2.0, 0.3), ff=ff_shell(9),
+                    Lq=6, n_ref=3, cutoff="omega")
     raise KeyError(name)
 
 
@@ -66,7 +73,7 @@ def _zeros(ctx):
     return torch.zeros((ctx.Nq, ctx.B, ctx.B), dtype=torch.complex128, device=dev())
 
 
-@pytest.mark.parametrize("name", ["hub5", "ras9"])
+@pytest.mark.parametrize("name", ["hub5", "ras9", "t2g13"])
 def test_band_data_matches_oracle(T, name):
     c = _case(name)
     ctx = _ctx(T, c, "fp64")
@@ -87,7 +94,7 @@ def test_band_data_matches_oracle(T, name):
     assert np.abs(Pi.sum(axis=0) - np.eye(n)[None]).max() < 1e-13
 
 
-@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13"])
+@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13", "t2g13", "t2g9"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("channel", ["pp", "ph"])
 @pytest.mark.parametrize("deriv", [1, 0])
@@ -105,7 +112,7 @@ def test_bubble_matches_oracle(T, name, prec, channel, deriv):
     assert rel(got, ref) < TOL[prec]
 
 
-@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13"])
+@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13", "t2g13"])
 def test_project_matches_oracle(T, name):
     c = _case(name)
     ctx = _ctx(T, c, "fp64")
@@ -122,7 +129,7 @@ def test_project_matches_oracle(T, name):
     assert rel(VC.cpu().numpy(), c_to_matrix(rVC)) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13"])
+@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13", "t2g9"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_rhs_matches_oracle(T, name, prec):
     c = _case(name)
@@ -227,3 +234,21 @@ def test_full_size_rashba_loops_on_sampled_q(T):
                 ref = conv(otu.loops(st, channel, lam, q_list=[qi]))[0]
                 assert rel(L[qi].cpu().numpy(), ref) < TOL[prec], (prec, channel, qi)
         ctx.close()
+
+
+def test_full_size_t2g_loops_on_sampled_q(T):
+    """t2g + SOC on the 32x32 q-mesh refined 16x (13 form factors, B = 468):
+    the loops of every q on the GPU, two q recomputed by the oracle."""
+    w = workload("t2g_s13_L32")
+    st = otu.TUSetup.from_workload(w)
+    lam = 0.3
+    ctx = T.Context.from_workload(w, precision="fp32")
+    for channel, code, conv in (("pp", T.PP, pp_loop_to_matrix), ("ph", T.PH, ph_loop_to_matrix)):
+        L = _zeros(ctx)
+        T.tufrg_bubble(ctx, code, lam, 1, L)
+        torch.cuda.synchronize()
+        for qi in (0, 531):
+            ref = conv(otu.loops(st, channel, lam, q_list=[qi]))[0]
+            assert rel(L[qi].cpu().numpy(), ref) < TOL["fp32"], (channel, qi)
+        del L
+    ctx.close()

@@ -29,26 +29,39 @@ sys.path.insert(0, ROOT)
 
 METRIC = "loop entries/s + flow steps/s, mixed/surrogate vs FP64-plain at ≤1e-4 rel err"
 WORKLOAD = "rashba_s9_L24"
-# algorithmic FP32 flops of the loop kernel per (q, k, channel) for two
-# spin-orbitals and the 3 x 5 (dx >= 0, dy) phase box; derivation in the design doc
-LOOP_FLOPS_PER_PAIR = 204
 PEAK_FP32_VECTOR = 157.3e12
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "loop_kernel_traffic_rashba_s9_L24.json")
+
+
+def loop_flops_per_pair(n_o, ndx, ndy):
+    """Algorithmic FP32 flops of the loop kernel per (q, k, channel); the
+    derivation is in the design doc.  Two spin-orbitals: 12 for the four divided
+    differences, 16 for W_1 and D, 32 for the 10 distinct block entries, 16 for
+    the dx = 0 sums and 64 per further dx.  n_o > 2: per block entry 48 for
+    sum_m Pi_m W_m and 8 per dy, plus 2 n_o^3 for W_m and 3 n_o^2 for the loop
+    kernels."""
+    if n_o == 2:
+        return 12 + 16 + 32 + 16 + 64 * (ndx - 1)
+    return n_o ** 4 * (48 + 8 * (2 * ndy + 1)) + 2 * n_o ** 3 * n_o + 3 * n_o ** 2
+
+
+def _box(ff):
+    m = max(max(abs(x), abs(y)) for x, y in ff)
+    return (3, 2) if m <= 1 else (5, 4)
 
 
 def _loop_source_hash():
     h = hashlib.sha256()
-    for f in ("k_loop.hip", "common.h"):
+    for f in ("k_loop.hip", "k_loop_gen.hip", "common.h"):
         with open(os.path.join(ROOT, "paper_1710_08830_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def _traffic(launches_per_step):
+def _traffic(workload):
     """HBM bytes per loop-kernel launch from committed rocprofv3 counters, or
     None when the kernel source changed since they were taken."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(os.path.join(ROOT, "profiles", f"loop_kernel_traffic_{workload}.json")) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -100,6 +113,9 @@ def main():
                     help="time the FP32 steps only (for profiler runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scales HBM counters)")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="synthetic workload (the headline line uses the default)")
+    ap.add_argument("--no-dp", action="store_true", help="skip the Dormand-Prince flows")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the q-sharded multi-GPU "
@@ -123,7 +139,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}))
         return
-    w = workload(WORKLOAD)
+    w = workload(args.workload)
     K, W = args.steps, args.warmup
     lam0, lam_mid = 10.0, 1.0
 
@@ -157,16 +173,17 @@ def main():
     entries = 2.0 * Nq * B * B
     value = entries * K / dt32
     loop_avg_s = loop_ms / loop_n * 1e-3
-    flops_launch = 2.0 * Nq * Nf * LOOP_FLOPS_PER_PAIR
+    ndx, ndy = _box(w["ff"])
+    flops_launch = 2.0 * Nq * Nf * loop_flops_per_pair(w["n_o"], ndx, ndy)
     achieved = flops_launch / loop_avg_s
-    traffic = _traffic(1)
+    traffic = _traffic(args.workload)
     out = {
         "metric": METRIC, "value": value, "unit": "loop entries/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": dt32 / K * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-        "config": {"workload": WORKLOAD, "model": "lattice Rashba t=1 mu=-0.4 alpha=0.3 U=2.5",
-                   "n_orb": 2, "n_ff": 9, "B": B, "Lq": 24, "n_ref": 24, "Nq": Nq, "Nf": Nf,
-                   "cutoff": "omega", "step": "Euler step: loops + projections + bundles + update",
+        "config": {"workload": args.workload, "n_orb": w["n_o"], "n_ff": len(w["ff"]), "B": B,
+                   "Lq": w["Lq"], "n_ref": w["n_ref"], "Nq": Nq, "Nf": Nf, "cutoff": w["cutoff"],
+                   "step": "Euler step: loops + projections + bundles + update",
                    "parallelism": "single GPU"},
         "flow_steps_per_s": K / dt32,
         "loop_kernel_ms": loop_avg_s * 1e3,
@@ -184,6 +201,7 @@ def main():
                              "loop_kernel_ms": l64_ms / l64_n, "flow_steps_per_s": K / dt64}
         out["speedup_fp32_vs_fp64"] = dt64 / dt32
         out["rel_err_fp32_vs_fp64"] = err
+    if not args.no_extras and not args.no_dp:
         # production integrator: Dormand-Prince 5(4), rtol = atol = 1e-6, 10 -> 1e-4
         dp = {}
         for name, (ctx, P, C) in (("fp32", (ctx32, P32, C32)), ("fp64", (ctx64, P64, C64))):
@@ -205,9 +223,10 @@ def main():
         if dp["fp64"]["diverged"] and dp["fp32"]["diverged"]:
             dp["lambda_c_rel_err"] = abs(dp["fp32"]["lambda_c"] / dp["fp64"]["lambda_c"] - 1.0)
         out["dp54_flow"] = dp
+    if not args.no_extras:
         ctx64.close()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"] = cpu_baseline(w, n_sample=4 if w["n_o"] == 2 else 1)
     ctx32.close()
     print(json.dumps(out))
 

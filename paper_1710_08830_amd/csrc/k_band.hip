@@ -197,19 +197,41 @@ hipError_t launch_band(int n_o, int Lf, int n_hop, const int *hop_R, const doubl
   return hipGetLastError();
 }
 
-// Regulator value per band and fine k at one scale: K (deriv) or J.
-__global__ void kval_kernel(int n, const double *__restrict__ e, double lam, int scheme, int deriv,
-                            double *__restrict__ kv, float *__restrict__ kv32) {
+// Regulator value per band and fine k at one scale: K (deriv) or J.  The
+// input e is band-major [n_o][Nf]; the output is band-major too (aos_no = 0)
+// or k-major [Nf][n_o] (aos_no = n_o).
+__global__ void kval_kernel(int n, int Nf, int aos_no, const double *__restrict__ e, double lam, int scheme,
+                            int deriv, double *__restrict__ kv, float *__restrict__ kv32) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double v = cut_val(e[i], lam, scheme, deriv);
-  kv[i] = v;
-  kv32[i] = (float)v;
+  const int o = aos_no ? (i % Nf) * aos_no + i / Nf : i;
+  kv[o] = v;
+  kv32[o] = (float)v;
 }
 
-hipError_t launch_kval(int n, const double *e, double lam, int scheme, int deriv, double *kv, float *kv32,
-                       hipStream_t st) {
-  hipLaunchKernelGGL(kval_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, e, lam, scheme, deriv, kv, kv32);
+hipError_t launch_kval(int n, int Nf, int aos_no, const double *e, double lam, int scheme, int deriv, double *kv,
+                       float *kv32, hipStream_t st) {
+  hipLaunchKernelGGL(kval_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, Nf, aos_no, e, lam, scheme, deriv, kv,
+                     kv32);
+  return hipGetLastError();
+}
+
+// component-major [nc][Nf] -> k-major [Nf][nc], FP64 and FP32 copies
+__global__ void to_kmajor_kernel(int nc, int Nf, const double *__restrict__ src, double *__restrict__ dst,
+                                 float *__restrict__ dst32) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)nc * Nf) return;
+  const int r = (int)(i % nc);
+  const long long k = i / nc;
+  const double v = src[(size_t)r * Nf + k];
+  dst[i] = v;
+  dst32[i] = (float)v;
+}
+
+hipError_t launch_to_kmajor(int nc, int Nf, const double *src, double *dst, float *dst32, hipStream_t st) {
+  const long long n = (long long)nc * Nf;
+  hipLaunchKernelGGL(to_kmajor_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, nc, Nf, src, dst, dst32);
   return hipGetLastError();
 }
 

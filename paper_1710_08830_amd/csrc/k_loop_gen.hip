@@ -49,6 +49,7 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
                                                         int n_ch, T lam, int deriv, double *__restrict__ partial) {
   constexpr int NO2 = NO * NO, NO4 = NO2 * NO2, NDY2 = 2 * NDY + 1;
   constexpr int PK = NO * NO2;  // packed reals of all bands' projectors at one k
+  constexpr int NC = NO + PK;   // band values per k-point: e_m, then the packed projectors
   const int tid = threadIdx.x;
   int w = blockIdx.x;
   const int part = w % nparts_tau;
@@ -65,8 +66,6 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
   float psg, wsg;
   herm_slot<NO>(a, c, pre, pim, psg);
   herm_slot<NO>(b, d, wre, wim, wsg);
-  const unsigned Nf = (unsigned)Lf * (unsigned)Lf;
-  const T *e = band, *pi = band + (size_t)NO * Nf;
 
   __shared__ T sP[KT][PK];     // Pi_m(k) packed
   __shared__ T sW[KT][PK];     // W_m(k) packed
@@ -91,27 +90,29 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
     for (int j = 0; j < NDY2; ++j) Y[j] = cmake(T(0), T(0));
     for (int ky0 = 0; ky0 < Lf; ky0 += KT) {
       __syncthreads();
-      // stage band data of the tile
-      for (int i = tid; i < KT * (2 * NO + PK); i += NTHR) {
-        const int j = i / (2 * NO + PK), r = i % (2 * NO + PK);
+      // stage band data of the tile: per k-point NC contiguous values (k-major layout)
+      for (int i = tid; i < KT * 2 * (NC + NO); i += NTHR) {
+        const int r = i % (NC + NO), t2 = i / (NC + NO);
+        const int side = t2 & 1, j = t2 >> 1;
         const int ky = ky0 + j < Lf ? ky0 + j : Lf - 1;
         int kpy = (ch == 0) ? (qfy - ky) : (ky - qfy);
         kpy = ((kpy % Lf) + Lf) % Lf;
-        const unsigned k = (unsigned)kx * Lf + ky, kp = (unsigned)kpx * Lf + kpy;
+        const unsigned kk = side ? (unsigned)kpx * Lf + kpy : (unsigned)kx * Lf + ky;
         if (r < NO) {
-          sE[j][0][r] = e[(size_t)r * Nf + k];
-          sE[j][1][r] = e[(size_t)r * Nf + kp];
-        } else if (r < 2 * NO) {
-          sK[j][0][r - NO] = kv[(size_t)(r - NO) * Nf + k];
-          sK[j][1][r - NO] = kv[(size_t)(r - NO) * Nf + kp];
+          sE[j][side][r] = band[(size_t)kk * NC + r];
+        } else if (r < NC) {
+          const int p = r - NO;
+          T x = band[(size_t)kk * NC + r];
+          if (side == 0) {
+            sP[j][p] = x;
+          } else {
+            // ph uses the transpose of Pi_n(k'): flip the imaginary parts
+            const int pl = p % NO2;
+            if (ch == 1 && pl >= NO && ((pl - NO) & 1)) x = -x;
+            sX[j][p] = x;
+          }
         } else {
-          const int p = r - 2 * NO;
-          sP[j][p] = pi[(size_t)p * Nf + k];
-          T x = pi[(size_t)p * Nf + kp];
-          // ph uses the transpose of Pi_n(k'): flip the imaginary parts
-          const int pl = p % NO2;
-          if (ch == 1 && pl >= NO && ((pl - NO) & 1)) x = -x;
-          sX[j][p] = x;
+          sK[j][side][r - NC] = kv[(size_t)kk * NO + (r - NC)];
         }
       }
       for (int i = tid; i < KT * NDY2; i += NTHR) {

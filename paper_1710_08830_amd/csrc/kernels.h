@@ -8,8 +8,10 @@ namespace tufrg {
 // a0: band data on the fine mesh (eigenvalues minus mu, packed projectors)
 hipError_t launch_band(int n_o, int Lf, int n_hop, const int *hop_R, const double *hop_t, double mu,
                        double *e, double *pi, float *e32, float *pi32, hipStream_t st);
-hipError_t launch_kval(int n, const double *e, double lam, int scheme, int deriv, double *kv, float *kv32,
-                       hipStream_t st);
+hipError_t launch_kval(int n, int Nf, int aos_no, const double *e, double lam, int scheme, int deriv, double *kv,
+                       float *kv32, hipStream_t st);
+// component-major [nc][Nf] -> k-major [Nf][nc] (FP64 and FP32)
+hipError_t launch_to_kmajor(int nc, int Nf, const double *src, double *dst, float *dst32, hipStream_t st);
 
 // a1-a3: form-factor projected orbital loops
 struct LoopArgs {
@@ -20,8 +22,9 @@ struct LoopArgs {
   int q_first, n_q;    // coarse q range
   int scheme, deriv, prec;
   double lam;
-  const void *band;    // SoA band data (FP64 or FP32 by prec)
-  const void *kv;      // regulator values [n_o][Nf]
+  const void *band;    // band data (FP64 or FP32 by prec): two orbitals component-major
+                       // [n_o + n_o^3][Nf], more orbitals k-major [Nf][n_o + n_o^3]
+  const void *kv;      // regulator values, [n_o][Nf] or [Nf][n_o] like the band data
   const double *tw;    // exp(-2 pi i j / Lf), [Lf][2]
   double *partial;     // [n_ch][n_q][nkyb * nkxc][ndx][2 ndy + 1][n_o^4][2]
 };

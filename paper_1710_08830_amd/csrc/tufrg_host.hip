@@ -37,6 +37,8 @@ struct tufrg_ctx {
   double *d_hopt = nullptr;
   double *d_band64 = nullptr;
   float *d_band32 = nullptr;
+  double *d_bandk64 = nullptr;  // k-major copies for more than two orbitals
+  float *d_bandk32 = nullptr;
   double *d_kv64 = nullptr;
   float *d_kv32 = nullptr;
   double *d_twf = nullptr, *d_twq = nullptr;
@@ -267,6 +269,10 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CTRY(dalloc(c, &c->d_hopt, 2 * (size_t)m->n_hop * c->no2));
   CTRY(dalloc(c, &c->d_band64, Nf * (c->n_o + c->n_o * c->no2)));
   CTRY(dalloc(c, &c->d_band32, Nf * (c->n_o + c->n_o * c->no2)));
+  if (c->n_o > 2) {
+    CTRY(dalloc(c, &c->d_bandk64, Nf * (c->n_o + c->n_o * c->no2)));
+    CTRY(dalloc(c, &c->d_bandk32, Nf * (c->n_o + c->n_o * c->no2)));
+  }
   CTRY(dalloc(c, &c->d_kv64, Nf * c->n_o));
   CTRY(dalloc(c, &c->d_kv32, Nf * c->n_o));
   CTRY(dalloc(c, &c->d_twf, 2 * (size_t)c->Lf));
@@ -328,6 +334,7 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CHIP(hipMemcpyAsync(c->d_v0c, v0c.data(), v0c.size() * sizeof(double), hipMemcpyHostToDevice, st));
   CHIP(launch_band(c->n_o, c->Lf, m->n_hop, c->d_hopR, c->d_hopt, m->mu, c->d_band64, c->d_band64 + Nf * c->n_o,
                    c->d_band32, c->d_band32 + Nf * c->n_o, st));
+  if (c->n_o > 2) CHIP(launch_to_kmajor(c->n_o + c->n_o * c->no2, (int)Nf, c->d_band64, c->d_bandk64, c->d_bandk32, st));
   CHIP(hipStreamSynchronize(st));
   *out = c;
   return TUFRG_OK;
@@ -379,7 +386,10 @@ static LoopArgs loop_args(tufrg_ctx *c, double lam, int deriv, int ch_first, int
   a.deriv = deriv;
   a.prec = c->prec;
   a.lam = lam;
-  a.band = c->prec == 0 ? (const void *)c->d_band64 : (const void *)c->d_band32;
+  if (c->n_o > 2)
+    a.band = c->prec == 0 ? (const void *)c->d_bandk64 : (const void *)c->d_bandk32;
+  else
+    a.band = c->prec == 0 ? (const void *)c->d_band64 : (const void *)c->d_band32;
   a.kv = c->prec == 0 ? (const void *)c->d_kv64 : (const void *)c->d_kv32;
   a.tw = c->d_twf;
   a.partial = c->d_partial;
@@ -404,7 +414,8 @@ static ProjArgs proj_args(tufrg_ctx *c) {
 
 // loops of channels [ch_first, ch_first + n_ch) into the compact buffer
 static tufrg_status compute_loops(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch) {
-  HIPCHK(c, launch_kval(c->n_o * c->Nf, c->d_band64, lam, c->scheme, deriv, c->d_kv64, c->d_kv32, c->st));
+  HIPCHK(c, launch_kval(c->n_o * c->Nf, c->Nf, c->n_o > 2 ? c->n_o : 0, c->d_band64, lam, c->scheme, deriv,
+                        c->d_kv64, c->d_kv32, c->st));
   LoopArgs a = loop_args(c, lam, deriv, ch_first, n_ch);
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
   HIPCHK(c, launch_loop(a, c->st));

@@ -36,12 +36,14 @@ def loop_flops_per_pair(n_o, ndx, ndy):
     """Algorithmic FP32 flops of the loop kernel per (q, k, channel); the
     derivation is in the design doc.  Two spin-orbitals: 12 for the four divided
     differences, 16 for W_1 and D, 32 for the 10 distinct block entries, 16 for
-    the dx = 0 sums and 64 per further dx.  n_o > 2: per block entry 48 for
-    sum_m Pi_m W_m and 8 per dy, plus 2 n_o^3 for W_m and 3 n_o^2 for the loop
-    kernels."""
+    the dx = 0 sums and 64 per further dx.  n_o > 2 (one entry of each
+    Hermitian pair, U = (n_o^4 + n_o^2) / 2 of them): 8 n_o flops for
+    sum_m Pi_m W_m, 2 + 8 ndy for the separable ky transform, plus 2 n_o^4 for
+    W_m and 3 n_o^2 for the loop kernels."""
     if n_o == 2:
         return 12 + 16 + 32 + 16 + 64 * (ndx - 1)
-    return n_o ** 4 * (48 + 8 * (2 * ndy + 1)) + 2 * n_o ** 3 * n_o + 3 * n_o ** 2
+    u = (n_o ** 4 + n_o ** 2) // 2
+    return u * (8 * n_o + 2 + 8 * ndy) + 2 * n_o ** 4 + 3 * n_o ** 2
 
 
 def _box(ff):

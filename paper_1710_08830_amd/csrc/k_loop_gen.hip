@@ -6,14 +6,22 @@
 //   M_q(k)[a,b,c,d] = sum_m Pi_m(k)_ac W_m(k)_bd,  W_m = sum_n L_mn X_n,
 // with X_n = Pi_n(k') (pp, k' = q - k) or its transpose (ph, k' = k - q).
 //
-// With NO^4 = 1296 entries per (q, channel) the entries are spread over the
-// threads of a workgroup (one entry per thread, NPART workgroups per
-// (q, channel)).  Per tile of KT consecutive ky the workgroup stages in LDS the
-// band projectors Pi_m(k) and W_m(k) (both Hermitian, packed as NO^2 reals per
-// band), computed once per tile from the band data at k and k'.  Each thread
-// then forms its entry of M and accumulates Y[dy] = sum_ky e^{-i ky dy} M over
-// the kx row; at the end of the row Z[dx][dy] += e^{-i kx dx} Y[dy] for dx >= 0
-// (dx < 0 follows from hermiticity in the finalising kernel).
+// Entry pairs.  Pi_m and W_m are Hermitian, so M[(c,d,a,b)] = conj M[(a,b,c,d)]
+// and Lc[dR][(c,d,a,b)] = conj Lc[-dR][(a,b,c,d)].  A thread owns one pair of
+// such entries (or a self-conjugate entry), listed by the host: it forms M for
+// the first entry at every k and keeps its loop for every dR of the
+// difference set D of the form factors; the partner follows at the end.
+//
+// Separable phases.  Over one kx row the thread accumulates S = sum M and, for
+// dy = 1..NDY, A = sum cos(theta) M and B = sum -sin(theta) M with
+// theta = 2 pi ky dy / Lf, so that the row transform at +dy is A + iB and at
+// -dy is A - iB.  At the end of the row Lc[(dx, dy)] += e^{-i kx dx} Y(dy) for
+// every (dx, dy) in D.
+//
+// Staging.  Per tile of KT consecutive ky the workgroup writes to LDS the
+// projectors Pi_m(k) as full complex NO x NO matrices, the packed X_n(k'), the
+// loop kernels L_mn and then W_m(k) as full complex matrices, so that the
+// inner loop reads one complex value of Pi and one of W per band.
 #include "common.h"
 #include "kernels.h"
 
@@ -21,93 +29,138 @@ namespace tufrg {
 
 namespace {
 
-// offset of entry (a, c) in a packed Hermitian NO x NO matrix and the sign of
-// its imaginary part: diagonal a -> a; a < c -> NO + 2 p(a, c) (Re), +1 (Im)
+template <typename T>
+struct alignas(2 * sizeof(T)) c2 {
+  T re, im;
+};
+
+// points (dx, dy) of the difference set: the 9-vector shell gives the 5 x 5
+// box (R = 2), the 13-vector shell the diamond |dx| + |dy| <= 4 (R = 4)
+template <int R>
+struct Shape;
+template <>
+struct Shape<2> {
+  static constexpr int N = 25;
+  __device__ static constexpr int dx(int i) { return i / 5 - 2; }
+  __device__ static constexpr int dy(int i) { return i % 5 - 2; }
+};
+template <>
+struct Shape<4> {
+  static constexpr int N = 41;
+  __device__ static constexpr int row_len(int x) { return 2 * (4 - (x < 0 ? -x : x)) + 1; }
+  __device__ static constexpr int row_start(int x) {
+    int s = 0;
+    for (int r = -4; r < x; ++r) s += row_len(r);
+    return s;
+  }
+  __device__ static constexpr int dx(int i) {
+    int x = -4;
+    while (x < 4 && row_start(x + 1) <= i) ++x;
+    return x;
+  }
+  __device__ static constexpr int dy(int i) { return i - row_start(dx(i)) - (row_len(dx(i)) - 1) / 2; }
+};
+
+// packed Hermitian NO x NO matrix: NO diagonal reals, then Re and Im of (lo, hi)
+// for lo < hi in row-major order; slot -> (lo, hi) of an off-diagonal pair
 template <int NO>
-__device__ inline void herm_slot(int a, int c, int &re, int &im, float &imsign) {
-  if (a == c) {
-    re = a;
-    im = -1;
-    imsign = 0.f;
+__device__ inline void pair_of(int p, int &lo, int &hi) {
+  lo = 0;
+  while (p >= NO - 1 - lo) {
+    p -= NO - 1 - lo;
+    ++lo;
+  }
+  hi = lo + 1 + p;
+}
+
+// writes packed value x of slot pl into the full complex matrix dst[NO][NO]
+template <typename T, int NO>
+__device__ inline void unpack_store(c2<T> *dst, int pl, T x) {
+  if (pl < NO) {
+    c2<T> v;
+    v.re = x;
+    v.im = T(0);
+    dst[pl * NO + pl] = v;
     return;
   }
-  const int lo = a < c ? a : c, hi = a < c ? c : a;
-  int p = 0;
-  for (int x = 0; x < lo; ++x) p += NO - 1 - x;
-  p += hi - lo - 1;
-  re = NO + 2 * p;
-  im = re + 1;
-  imsign = (a < c) ? 1.f : -1.f;
+  const int q = pl - NO;
+  int lo, hi;
+  pair_of<NO>(q >> 1, lo, hi);
+  if (q & 1) {
+    dst[lo * NO + hi].im = x;
+    dst[hi * NO + lo].im = -x;
+  } else {
+    dst[lo * NO + hi].re = x;
+    dst[hi * NO + lo].re = x;
+  }
 }
 
 }  // namespace
 
-template <typename T, int NO, int NDX, int NDY, int SCHEME, int NTHR, int KT>
+// One workgroup per (part, channel, q); part selects NTHR of the entry pairs.
+template <typename T, int NO, int NDY, int SCHEME, int NTHR, int KT>
 __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ band, const T *__restrict__ kv,
-                                                        const double *__restrict__ tw, int Lq, int n_ref, int Lf,
-                                                        int nparts_tau, int q_first, int n_q, int ch_first,
-                                                        int n_ch, T lam, int deriv, double *__restrict__ partial) {
-  constexpr int NO2 = NO * NO, NO4 = NO2 * NO2, NDY2 = 2 * NDY + 1;
-  constexpr int PK = NO * NO2;  // packed reals of all bands' projectors at one k
-  constexpr int NC = NO + PK;   // band values per k-point: e_m, then the packed projectors
+                                                        const double *__restrict__ tw, const int *__restrict__ pairs,
+                                                        int n_pairs, int Lq, int n_ref, int Lf, int nparts,
+                                                        int q_first, int n_q, int ch_first, int n_ch, int ndx_out,
+                                                        T lam, int deriv, double *__restrict__ partial) {
+  using SH = Shape<NDY>;
+  constexpr int NPT = SH::N;
+  constexpr int NO2 = NO * NO, NO4 = NO2 * NO2;
+  constexpr int PK = NO * NO2;      // packed reals of all bands' projectors at one k
+  constexpr int NC = NO + PK;       // band values per k-point: e_m, then the packed projectors
+  constexpr int NIT = NC + NO;      // staged values per k-point: band values and regulator values
   const int tid = threadIdx.x;
   int w = blockIdx.x;
-  const int part = w % nparts_tau;
-  w /= nparts_tau;
+  const int part = w % nparts;
+  w /= nparts;
   const int chrel = w % n_ch, qrel = w / n_ch;
   const int qi = q_first + qrel, ch = ch_first + chrel;
   const int qfx = (qi / Lq) * n_ref, qfy = (qi % Lq) * n_ref;
-  const int per_part = (NO4 + nparts_tau - 1) / nparts_tau;
-  const int tau = part * per_part + tid;
-  const bool active = (tid < per_part) && (tau < NO4);
-  const int tt = active ? tau : 0;
-  const int a = tt / (NO * NO2), b = (tt / NO2) % NO, c = (tt / NO) % NO, d = tt % NO;
-  int pre, pim, wre, wim;
-  float psg, wsg;
-  herm_slot<NO>(a, c, pre, pim, psg);
-  herm_slot<NO>(b, d, wre, wim, wsg);
+  const int pidx = part * NTHR + tid;
+  const bool active = pidx < n_pairs;
+  const int tau = active ? pairs[2 * pidx] : 0, taub = active ? pairs[2 * pidx + 1] : 0;
+  const int xo = (tau / (NO * NO2)) * NO + (tau / NO) % NO;  // (a, c)
+  const int yo = ((tau / NO2) % NO) * NO + tau % NO;        // (b, d)
 
-  __shared__ T sP[KT][PK];     // Pi_m(k) packed
-  __shared__ T sW[KT][PK];     // W_m(k) packed
-  __shared__ T sX[KT][PK];     // X_n(k') packed
-  __shared__ T sE[KT][2][NO];  // e at k and k'
-  __shared__ T sK[KT][2][NO];  // regulator at k and k'
+  __shared__ c2<T> sP[KT][NO][NO2];  // Pi_m(k)
+  __shared__ c2<T> sW[KT][NO][NO2];  // W_m(k)
+  __shared__ T sX[KT][PK];           // X_n(k') packed
+  __shared__ T sE[KT][2][NO];        // e at k and k'
+  __shared__ T sK[KT][2][NO];        // regulator at k and k'
   __shared__ T sL[KT][NO][NO];
-  __shared__ T sPh[KT][NDY2][2];
-
-  cx<T> Z[NDX][NDY2];
-#pragma unroll
-  for (int i = 0; i < NDX; ++i)
-#pragma unroll
-    for (int j = 0; j < NDY2; ++j) Z[i][j] = cmake(T(0), T(0));
+  __shared__ c2<T> sPh[KT][NDY];     // cos and -sin of 2 pi ky dy / Lf, dy = 1..NDY
   const T sg = (ch == 0) ? T(1) : T(-1);
+
+  cx<T> Z[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) Z[i] = cmake(T(0), T(0));
 
   for (int kx = 0; kx < Lf; ++kx) {
     int kpx = (ch == 0) ? (qfx - kx) : (kx - qfx);
-    kpx = ((kpx % Lf) + Lf) % Lf;
-    cx<T> Y[NDY2];
+    kpx += kpx < 0 ? Lf : 0;
+    cx<T> S = cmake(T(0), T(0)), A[NDY], B[NDY];
 #pragma unroll
-    for (int j = 0; j < NDY2; ++j) Y[j] = cmake(T(0), T(0));
+    for (int j = 0; j < NDY; ++j) A[j] = B[j] = cmake(T(0), T(0));
     for (int ky0 = 0; ky0 < Lf; ky0 += KT) {
       __syncthreads();
-      // stage band data of the tile: per k-point NC contiguous values (k-major layout)
-      for (int i = tid; i < KT * 2 * (NC + NO); i += NTHR) {
-        const int r = i % (NC + NO), t2 = i / (NC + NO);
-        const int side = t2 & 1, j = t2 >> 1;
+#pragma unroll 1
+      for (int i = tid; i < KT * 2 * NIT; i += NTHR) {
+        const int r = i % NIT, t2 = i / NIT;
+        const int j = t2 >> 1, side = t2 & 1;
         const int ky = ky0 + j < Lf ? ky0 + j : Lf - 1;
         int kpy = (ch == 0) ? (qfy - ky) : (ky - qfy);
-        kpy = ((kpy % Lf) + Lf) % Lf;
+        kpy += kpy < 0 ? Lf : 0;
         const unsigned kk = side ? (unsigned)kpx * Lf + kpy : (unsigned)kx * Lf + ky;
         if (r < NO) {
           sE[j][side][r] = band[(size_t)kk * NC + r];
         } else if (r < NC) {
-          const int p = r - NO;
+          const int p = r - NO, m = p / NO2, pl = p % NO2;
           T x = band[(size_t)kk * NC + r];
           if (side == 0) {
-            sP[j][p] = x;
+            unpack_store<T, NO>(&sP[j][m][0], pl, x);
           } else {
             // ph uses the transpose of Pi_n(k'): flip the imaginary parts
-            const int pl = p % NO2;
             if (ch == 1 && pl >= NO && ((pl - NO) & 1)) x = -x;
             sX[j][p] = x;
           }
@@ -115,28 +168,28 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
           sK[j][side][r - NC] = kv[(size_t)kk * NO + (r - NC)];
         }
       }
-      for (int i = tid; i < KT * NDY2; i += NTHR) {
-        const int j = i / NDY2, dyi = i % NDY2;
-        int jj = (int)(((long long)(ky0 + j) * (dyi - NDY)) % Lf);
-        if (jj < 0) jj += Lf;
-        sPh[j][dyi][0] = (T)tw[2 * jj];
-        sPh[j][dyi][1] = (T)tw[2 * jj + 1];
+      if (tid < KT * NDY) {
+        const int j = tid / NDY, dy = tid % NDY + 1;
+        const int jj = (int)(((long long)(ky0 + j) * dy) % Lf);
+        sPh[j][dy - 1].re = (T)tw[2 * jj];
+        sPh[j][dy - 1].im = (T)tw[2 * jj + 1];
       }
       __syncthreads();
       // loop kernels L_mn = sg * DD[K](e_m(k), -sg e_n(k'))
-      for (int i = tid; i < KT * NO2; i += NTHR) {
-        const int j = i / NO2, m = (i / NO) % NO, n = i % NO;
+      if (tid < KT * NO2) {
+        const int j = tid / NO2, m = (tid / NO) % NO, n = tid % NO;
         const T x = sE[j][0][m], y = -sg * sE[j][1][n];
         sL[j][m][n] = sg * divided_difference(x, y, sK[j][0][m], -sg * sK[j][1][n], lam, SCHEME, deriv);
       }
       __syncthreads();
-      // W_m = sum_n L_mn X_n (packed)
+      // W_m = sum_n L_mn X_n, packed sums written as full complex matrices
+#pragma unroll 1
       for (int i = tid; i < KT * PK; i += NTHR) {
-        const int j = i / PK, m = (i / NO2) % NO, p = i % NO2;
-        T s = T(0);
+        const int j = i / PK, mp = i % PK, m = mp / NO2, pl = mp % NO2;
+        T acc = T(0);
 #pragma unroll
-        for (int n = 0; n < NO; ++n) s = fma(sL[j][m][n], sX[j][n * NO2 + p], s);
-        sW[j][m * NO2 + p] = s;
+        for (int n = 0; n < NO; ++n) acc = fma(sL[j][m][n], sX[j][n * NO2 + pl], acc);
+        unpack_store<T, NO>(&sW[j][m][0], pl, acc);
       }
       __syncthreads();
       const int kt = min(KT, Lf - ky0);
@@ -144,58 +197,90 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
         cx<T> M = cmake(T(0), T(0));
 #pragma unroll
         for (int m = 0; m < NO; ++m) {
-          const cx<T> P = cmake(sP[j][m * NO2 + pre], pim >= 0 ? (T)psg * sP[j][m * NO2 + pim] : T(0));
-          const cx<T> W = cmake(sW[j][m * NO2 + wre], wim >= 0 ? (T)wsg * sW[j][m * NO2 + wim] : T(0));
-          cfma(M, P, W);
+          const c2<T> P = sP[j][m][xo], Wv = sW[j][m][yo];
+          cfma(M, cmake(P.re, P.im), cmake(Wv.re, Wv.im));
         }
+        S.re += M.re;
+        S.im += M.im;
 #pragma unroll
-        for (int dyi = 0; dyi < NDY2; ++dyi) cfma(Y[dyi], cmake(sPh[j][dyi][0], sPh[j][dyi][1]), M);
+        for (int dy = 0; dy < NDY; ++dy) {
+          const c2<T> ph = sPh[j][dy];
+          const T cs = ph.re, sn = ph.im;
+          A[dy].re = fma(cs, M.re, A[dy].re);
+          A[dy].im = fma(cs, M.im, A[dy].im);
+          B[dy].re = fma(sn, M.re, B[dy].re);
+          B[dy].im = fma(sn, M.im, B[dy].im);
+        }
       }
     }
-    // kx phases for dx >= 0
+    // row transform at +dy: A + iB, at -dy: A - iB; then the kx phase,
+    // one |dx| at a time
 #pragma unroll
-    for (int dx = 0; dx < NDX; ++dx) {
-      const int jj = (kx * dx) % Lf;
+    for (int adx = 0; adx <= NDY; ++adx) {
+      const int jj = (kx * adx) % Lf;
       const cx<T> p = cmake((T)tw[2 * jj], (T)tw[2 * jj + 1]);
 #pragma unroll
-      for (int dyi = 0; dyi < NDY2; ++dyi) cfma(Z[dx][dyi], p, Y[dyi]);
+      for (int i = 0; i < NPT; ++i) {
+        const int dx = SH::dx(i), dy = SH::dy(i);
+        if ((dx < 0 ? -dx : dx) != adx) continue;
+        cx<T> Yv;
+        if (dy == 0) {
+          Yv = S;
+        } else {
+          const cx<T> Av = A[(dy > 0 ? dy : -dy) - 1], Bv = B[(dy > 0 ? dy : -dy) - 1];
+          Yv = dy > 0 ? cmake(Av.re - Bv.im, Av.im + Bv.re) : cmake(Av.re + Bv.im, Av.im - Bv.re);
+        }
+        cfma(Z[i], dx < 0 ? cmake(p.re, -p.im) : p, Yv);
+      }
     }
   }
   if (!active) return;
-  const size_t pbase = ((size_t)chrel * n_q + qrel) * (size_t)(NDX * NDY2 * NO4);
+  // partial[ch][q][dx][dy + NDY][tau] for dx >= 0; the partner entry from
+  // Lc[dR][partner] = conj Lc[-dR][tau]
+  const int ndy2 = 2 * NDY + 1;
+  const size_t pbase = ((size_t)chrel * n_q + qrel) * (size_t)(ndx_out * ndy2 * NO4);
 #pragma unroll
-  for (int dx = 0; dx < NDX; ++dx)
-#pragma unroll
-    for (int dyi = 0; dyi < NDY2; ++dyi) {
-      const size_t idx = pbase + (size_t)(dx * NDY2 + dyi) * NO4 + tau;
-      partial[2 * idx] = (double)Z[dx][dyi].re;
-      partial[2 * idx + 1] = (double)Z[dx][dyi].im;
+  for (int i = 0; i < NPT; ++i) {
+    const int dx = SH::dx(i), dy = SH::dy(i);
+    if (dx >= 0) {
+      const size_t idx = pbase + (size_t)(dx * ndy2 + dy + NDY) * NO4 + tau;
+      partial[2 * idx] = (double)Z[i].re;
+      partial[2 * idx + 1] = (double)Z[i].im;
     }
+    if (dx <= 0 && taub != tau) {
+      const size_t idx = pbase + (size_t)(-dx * ndy2 - dy + NDY) * NO4 + taub;
+      partial[2 * idx] = (double)Z[i].re;
+      partial[2 * idx + 1] = -(double)Z[i].im;
+    }
+  }
 }
 
-template <typename T, int NDX, int NDY>
+template <typename T, int NDY>
 static hipError_t launch_gen(const LoopArgs &a, hipStream_t st) {
-  // 1296 entries per (q, channel): 3 workgroups of 432 (7 waves); the FP64
-  // 5 x 9 phase box needs the whole register file of a wave: 6 x 216 (4 waves)
-  constexpr bool big = sizeof(T) == 8 && NDX > 3;
-  constexpr int NTHR = big ? 256 : 448, KT = 8, NP = big ? 6 : 3;
+  // FP32: every pair of a (q, channel) in one workgroup of 11 waves (three
+  // per SIMD); FP64 needs twice the registers: workgroups of 6 waves
+  constexpr bool f64 = sizeof(T) == 8;
+  constexpr int NTHR = f64 ? 384 : 704, KT = f64 ? 8 : 16;
+  if (a.ndx != NDY + 1) return hipErrorInvalidValue;
+  const int NP = (a.n_pairs + NTHR - 1) / NTHR;
   dim3 grid(a.n_q * a.n_ch * NP), block(NTHR);
   const T *band = (const T *)a.band, *kv = (const T *)a.kv;
   if (a.scheme == CUT_TEMPERATURE)
-    hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDX, NDY, CUT_TEMPERATURE, NTHR, KT>), grid, block, 0, st, band, kv,
-                       a.tw, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.ch_first, a.n_ch, (T)a.lam, a.deriv,
-                       a.partial);
+    hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, CUT_TEMPERATURE, NTHR, KT>), grid, block, 0, st, band, kv, a.tw,
+                       a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.ch_first, a.n_ch, a.ndx,
+                       (T)a.lam, a.deriv, a.partial);
   else
-    hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDX, NDY, CUT_OMEGA, NTHR, KT>), grid, block, 0, st, band, kv, a.tw,
-                       a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.ch_first, a.n_ch, (T)a.lam, a.deriv, a.partial);
+    hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, CUT_OMEGA, NTHR, KT>), grid, block, 0, st, band, kv, a.tw,
+                       a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.ch_first, a.n_ch, a.ndx,
+                       (T)a.lam, a.deriv, a.partial);
   return hipGetLastError();
 }
 
 hipError_t launch_loop_gen(const LoopArgs &a, hipStream_t st) {
-  if (a.n_o != 6) return hipErrorInvalidValue;
+  if (a.n_o != 6 || !a.pairs || a.n_pairs <= 0) return hipErrorInvalidValue;
   const bool f64 = (a.prec == 0);
-  if (a.ndx == 5 && a.ndy == 4) return f64 ? launch_gen<double, 5, 4>(a, st) : launch_gen<float, 5, 4>(a, st);
-  if (a.ndx == 3 && a.ndy == 2) return f64 ? launch_gen<double, 3, 2>(a, st) : launch_gen<float, 3, 2>(a, st);
+  if (a.ndx == 5 && a.ndy == 4) return f64 ? launch_gen<double, 4>(a, st) : launch_gen<float, 4>(a, st);
+  if (a.ndx == 3 && a.ndy == 2) return f64 ? launch_gen<double, 2>(a, st) : launch_gen<float, 2>(a, st);
   return hipErrorInvalidValue;
 }
 

@@ -27,6 +27,8 @@ struct LoopArgs {
   const void *kv;      // regulator values, [n_o][Nf] or [Nf][n_o] like the band data
   const double *tw;    // exp(-2 pi i j / Lf), [Lf][2]
   double *partial;     // [n_ch][n_q][nkyb * nkxc][ndx][2 ndy + 1][n_o^4][2]
+  const int *pairs = nullptr;  // more than two orbitals: [n_pairs][2] entry and its conjugate partner
+  int n_pairs = 0;
 };
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
 // more than two spin-orbitals (six: t2g with spin-orbit coupling)

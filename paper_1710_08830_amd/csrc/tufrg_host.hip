@@ -31,9 +31,11 @@ struct tufrg_ctx {
   hipStream_t st = nullptr;
   int n_o = 0, n_ff = 0, B = 0, Lq = 0, n_ref = 0, Lf = 0, Nq = 0, Nf = 0, no2 = 0, no4 = 0;
   int nD = 0, ndx = 0, ndy = 0, scheme = 0, prec = 0, nkyb = 0, nkxc = 0, nqc = 0;
-  std::vector<int> ff, dlist, didx, ffgrid, dgrid;
+  std::vector<int> ff, dlist, didx, ffgrid, dgrid, pairs;
   int *d_ff = nullptr, *d_dlist = nullptr, *d_didx = nullptr, *d_ffgrid = nullptr, *d_dgrid = nullptr;
   int *d_hopR = nullptr;
+  int *d_pairs = nullptr;  // loop entry pairs (tau, conjugate partner) for more than two orbitals
+  int n_pairs = 0;
   double *d_hopt = nullptr;
   double *d_band64 = nullptr;
   float *d_band32 = nullptr;
@@ -272,6 +274,17 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   if (c->n_o > 2) {
     CTRY(dalloc(c, &c->d_bandk64, Nf * (c->n_o + c->n_o * c->no2)));
     CTRY(dalloc(c, &c->d_bandk32, Nf * (c->n_o + c->n_o * c->no2)));
+    // entry (a,b,c,d) and its partner (c,d,a,b): one of each pair, in entry order
+    const int no2 = c->no2;
+    for (int t = 0; t < c->no4; ++t) {
+      const int tb = (t % no2) * no2 + t / no2;
+      if (t <= tb) {
+        c->pairs.push_back(t);
+        c->pairs.push_back(tb);
+      }
+    }
+    c->n_pairs = (int)c->pairs.size() / 2;
+    CTRY(dalloc(c, &c->d_pairs, c->pairs.size()));
   }
   CTRY(dalloc(c, &c->d_kv64, Nf * c->n_o));
   CTRY(dalloc(c, &c->d_kv32, Nf * c->n_o));
@@ -321,6 +334,8 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
         }
   hipStream_t st = c->st;
   CHIP(hipMemcpyAsync(c->d_ff, c->ff.data(), c->ff.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  if (c->n_pairs)
+    CHIP(hipMemcpyAsync(c->d_pairs, c->pairs.data(), c->pairs.size() * sizeof(int), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_dlist, c->dlist.data(), c->dlist.size() * sizeof(int), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_didx, c->didx.data(), c->didx.size() * sizeof(int), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_ffgrid, c->ffgrid.data(), c->ffgrid.size() * sizeof(int), hipMemcpyHostToDevice, st));
@@ -393,6 +408,8 @@ static LoopArgs loop_args(tufrg_ctx *c, double lam, int deriv, int ch_first, int
   a.kv = c->prec == 0 ? (const void *)c->d_kv64 : (const void *)c->d_kv32;
   a.tw = c->d_twf;
   a.partial = c->d_partial;
+  a.pairs = c->d_pairs;
+  a.n_pairs = c->n_pairs;
   return a;
 }
 

@@ -14,7 +14,7 @@
 //
 // Separable phases.  Over one kx row the thread accumulates S = sum M and, for
 // dy = 1..NDY, A = sum cos(theta) M and B = sum -sin(theta) M with
-// theta = 2 pi ky dy / Lf, so that the row transform at +dy is A + iB and at
+// theta = 2 pi ky dy / Lf (table phy[ky][dy - 1], read by scalar loads), so that the row transform at +dy is A + iB and at
 // -dy is A - iB.  At the end of the row Lc[(dx, dy)] += e^{-i kx dx} Y(dy) for
 // every (dx, dy) in D.
 //
@@ -100,7 +100,8 @@ __device__ inline void unpack_store(c2<T> *dst, int pl, T x) {
 // One workgroup per (part, channel, q); part selects NTHR of the entry pairs.
 template <typename T, int NO, int NDY, int SCHEME, int NTHR, int KT>
 __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ band, const T *__restrict__ kv,
-                                                        const double *__restrict__ tw, const int *__restrict__ pairs,
+                                                        const double *__restrict__ tw, const T *__restrict__ phy,
+                                                        const int *__restrict__ pairs,
                                                         int n_pairs, int Lq, int n_ref, int Lf, int nparts,
                                                         int q_first, int n_q, int ch_first, int n_ch, int ndx_out,
                                                         T lam, int deriv, double *__restrict__ partial) {
@@ -129,7 +130,6 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
   __shared__ T sE[KT][2][NO];        // e at k and k'
   __shared__ T sK[KT][2][NO];        // regulator at k and k'
   __shared__ T sL[KT][NO][NO];
-  __shared__ c2<T> sPh[KT][NDY];     // cos and -sin of 2 pi ky dy / Lf, dy = 1..NDY
   const T sg = (ch == 0) ? T(1) : T(-1);
 
   cx<T> Z[NPT];
@@ -168,12 +168,6 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
           sK[j][side][r - NC] = kv[(size_t)kk * NO + (r - NC)];
         }
       }
-      if (tid < KT * NDY) {
-        const int j = tid / NDY, dy = tid % NDY + 1;
-        const int jj = (int)(((long long)(ky0 + j) * dy) % Lf);
-        sPh[j][dy - 1].re = (T)tw[2 * jj];
-        sPh[j][dy - 1].im = (T)tw[2 * jj + 1];
-      }
       __syncthreads();
       // loop kernels L_mn = sg * DD[K](e_m(k), -sg e_n(k'))
       if (tid < KT * NO2) {
@@ -194,6 +188,8 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
       __syncthreads();
       const int kt = min(KT, Lf - ky0);
       for (int j = 0; j < kt; ++j) {
+        // the same for every lane: scalar loads
+        const T *ph = phy + (size_t)(ky0 + j) * (2 * NDY);
         cx<T> M = cmake(T(0), T(0));
 #pragma unroll
         for (int m = 0; m < NO; ++m) {
@@ -204,8 +200,7 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
         S.im += M.im;
 #pragma unroll
         for (int dy = 0; dy < NDY; ++dy) {
-          const c2<T> ph = sPh[j][dy];
-          const T cs = ph.re, sn = ph.im;
+          const T cs = ph[2 * dy], sn = ph[2 * dy + 1];
           A[dy].re = fma(cs, M.re, A[dy].re);
           A[dy].im = fma(cs, M.im, A[dy].im);
           B[dy].re = fma(sn, M.re, B[dy].re);
@@ -264,14 +259,14 @@ static hipError_t launch_gen(const LoopArgs &a, hipStream_t st) {
   if (a.ndx != NDY + 1) return hipErrorInvalidValue;
   const int NP = (a.n_pairs + NTHR - 1) / NTHR;
   dim3 grid(a.n_q * a.n_ch * NP), block(NTHR);
-  const T *band = (const T *)a.band, *kv = (const T *)a.kv;
+  const T *band = (const T *)a.band, *kv = (const T *)a.kv, *phy = (const T *)a.phy;
   if (a.scheme == CUT_TEMPERATURE)
     hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, CUT_TEMPERATURE, NTHR, KT>), grid, block, 0, st, band, kv, a.tw,
-                       a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.ch_first, a.n_ch, a.ndx,
+                       phy, a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.ch_first, a.n_ch, a.ndx,
                        (T)a.lam, a.deriv, a.partial);
   else
     hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, CUT_OMEGA, NTHR, KT>), grid, block, 0, st, band, kv, a.tw,
-                       a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.ch_first, a.n_ch, a.ndx,
+                       phy, a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.ch_first, a.n_ch, a.ndx,
                        (T)a.lam, a.deriv, a.partial);
   return hipGetLastError();
 }

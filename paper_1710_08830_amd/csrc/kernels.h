@@ -29,6 +29,7 @@ struct LoopArgs {
   double *partial;     // [n_ch][n_q][nkyb * nkxc][ndx][2 ndy + 1][n_o^4][2]
   const int *pairs = nullptr;  // more than two orbitals: [n_pairs][2] entry and its conjugate partner
   int n_pairs = 0;
+  const void *phy = nullptr;   // more than two orbitals: exp(-2 pi i ky dy / Lf), [Lf][ndy][2], like band
 };
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
 // more than two spin-orbitals (six: t2g with spin-orbit coupling)

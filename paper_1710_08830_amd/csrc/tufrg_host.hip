@@ -36,6 +36,8 @@ struct tufrg_ctx {
   int *d_hopR = nullptr;
   int *d_pairs = nullptr;  // loop entry pairs (tau, conjugate partner) for more than two orbitals
   int n_pairs = 0;
+  double *d_phy64 = nullptr;  // ky phases of the multi-orbital loop kernel, [Lf][ndy][2]
+  float *d_phy32 = nullptr;
   double *d_hopt = nullptr;
   double *d_band64 = nullptr;
   float *d_band32 = nullptr;
@@ -285,6 +287,8 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     }
     c->n_pairs = (int)c->pairs.size() / 2;
     CTRY(dalloc(c, &c->d_pairs, c->pairs.size()));
+    CTRY(dalloc(c, &c->d_phy64, 2 * (size_t)c->Lf * c->ndy));
+    CTRY(dalloc(c, &c->d_phy32, 2 * (size_t)c->Lf * c->ndy));
   }
   CTRY(dalloc(c, &c->d_kv64, Nf * c->n_o));
   CTRY(dalloc(c, &c->d_kv32, Nf * c->n_o));
@@ -318,6 +322,17 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     twq[2 * j] = std::cos(a);
     twq[2 * j + 1] = std::sin(a);
   }
+  std::vector<double> phy64;
+  std::vector<float> phy32;
+  if (c->n_o > 2) {
+    for (int ky = 0; ky < c->Lf; ++ky)
+      for (int dy = 1; dy <= c->ndy; ++dy) {
+        const int j = (int)(((long long)ky * dy) % c->Lf);
+        phy64.push_back(twf[2 * j]);
+        phy64.push_back(twf[2 * j + 1]);
+      }
+    phy32.assign(phy64.begin(), phy64.end());
+  }
   std::vector<double> v0p(2 * BB, 0.0), v0c(2 * BB, 0.0);
   const int n = c->n_o;
   for (int a = 0; a < n; ++a)
@@ -345,6 +360,10 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
                       st));
   CHIP(hipMemcpyAsync(c->d_twf, twf.data(), twf.size() * sizeof(double), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_twq, twq.data(), twq.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  if (c->n_o > 2) {
+    CHIP(hipMemcpyAsync(c->d_phy64, phy64.data(), phy64.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    CHIP(hipMemcpyAsync(c->d_phy32, phy32.data(), phy32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  }
   CHIP(hipMemcpyAsync(c->d_v0p, v0p.data(), v0p.size() * sizeof(double), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_v0c, v0c.data(), v0c.size() * sizeof(double), hipMemcpyHostToDevice, st));
   CHIP(launch_band(c->n_o, c->Lf, m->n_hop, c->d_hopR, c->d_hopt, m->mu, c->d_band64, c->d_band64 + Nf * c->n_o,
@@ -410,6 +429,7 @@ static LoopArgs loop_args(tufrg_ctx *c, double lam, int deriv, int ch_first, int
   a.partial = c->d_partial;
   a.pairs = c->d_pairs;
   a.n_pairs = c->n_pairs;
+  a.phy = c->prec == 0 ? (const void *)c->d_phy64 : (const void *)c->d_phy32;
   return a;
 }
 

@@ -18,4 +18,8 @@ bruteforce  momentum-space vertex on tiny lattices: the channel projections of
             Sec. 2 as double sums, their converse expansions, and the band-basis
             one-loop right-hand side of Sec. 3.1 (the plain definition that TU
             reproduces exactly with a complete form-factor set).
+mlp         the loop surrogate: features of a loop block, a GELU multilayer
+            perceptron, its mean-squared loss, gradient and Adam update (no
+            counterpart in the paper; pinned by finite differences and closed
+            forms).
 """

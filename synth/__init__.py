@@ -18,5 +18,8 @@ from .models import (  # noqa: F401
     kanamori_V0,
     chemical_potential,
     random_exchange_state,
+    mlp_shape,
+    mlp_init,
+    mlp_batch,
 )
 from .workloads import workload, WORKLOADS  # noqa: F401

@@ -200,3 +200,29 @@ def random_exchange_state(n_q, n_ff, n_o, seed, scale=1.0):
     rng = np.random.default_rng(seed)
     shape = (n_q, n_ff, n_ff, n_o, n_o, n_o, n_o)
     return scale * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+
+
+def mlp_shape(n_in, width=256, n_out=2 * 6 ** 4, n_hidden=3):
+    """Layer sizes of the loop surrogate: n_in -> width (x n_hidden) -> n_out."""
+    return [int(n_in)] + [int(width)] * int(n_hidden) + [int(n_out)]
+
+
+def mlp_init(sizes, seed=3):
+    """Seeded initial parameters of an MLP with layer sizes ``sizes``, one flat
+    FP32 vector: for each layer the weight matrix W[out][in] (row-major) then
+    the bias b[out].  W ~ U(-a, a) with a = sqrt(6 / (in + out)), b = 0."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for n_i, n_o in zip(sizes[:-1], sizes[1:]):
+        a = np.sqrt(6.0 / (n_i + n_o))
+        parts.append(rng.uniform(-a, a, size=n_o * n_i))
+        parts.append(np.zeros(n_o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_batch(n, n_in, n_out, seed):
+    """Seeded probe batch (inputs, targets) for surrogate parity tests."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, n_in)).astype(np.float32)
+    T = (0.5 * rng.standard_normal((n, n_out))).astype(np.float32)
+    return X, T

@@ -102,7 +102,7 @@ typedef enum { TUFRG_FP64 = 0, TUFRG_FP32 = 1 } tufrg_precision;
 typedef enum { TUFRG_PP = 0, TUFRG_PH = 1 } tufrg_channel;
 
 typedef struct {
-  int32_t n_orb;           /* spin-orbitals n_o (this build: 2) */
+  int32_t n_orb;           /* spin-orbitals n_o: 2 or 6 */
   int32_t n_hop;           /* hopping vectors */
   const int32_t *hop_R;    /* [n_hop][2] lattice vectors R */
   const tufrg_c64 *hop_t;  /* [n_hop][n_o][n_o]: H(k) = sum_R t(R) e^{i k.R}; t(-R) = t(R)^dagger */
@@ -163,6 +163,17 @@ typedef struct {
    * flow cleanly with the state of that step */
   int32_t (*on_step)(void *user, int32_t step, double lambda, double max_coupling);
   void *user;
+  /* Loop surrogate (see tufrg_sur_attach).  surrogate = 1: each right-hand
+   * side takes its loops from the attached network, recomputes the plain loops
+   * on sample_frac of the coarse q_x rows (at least one row; rows chosen by a
+   * counter-based hash of sample_seed and the evaluation index) and replaces
+   * the network's values there; if the sampled relative error
+   * max|L_net - L| / max|L| exceeds sur_tol, or the current max coupling
+   * exceeds plain_above, the plain loops are used everywhere for that
+   * evaluation.  surrogate = 0: plain loops only. */
+  int32_t surrogate;
+  double sample_frac, sur_tol, plain_above;
+  uint64_t sample_seed;
 } tufrg_flow_opts;
 
 typedef struct {
@@ -171,6 +182,10 @@ typedef struct {
                            bracketing accepted steps; 0 if the flow did not diverge */
   double max_coupling;  /* max(|P|, |C|) of the returned state */
   int32_t diverged, n_steps, n_rhs, n_reject, stopped_by_callback;
+  int32_t n_plain;        /* right-hand sides with plain loops everywhere */
+  int32_t n_surrogate;    /* right-hand sides with network loops (sampled rows plain) */
+  int32_t n_fallback;     /* of n_plain: evaluations where the sampled error exceeded sur_tol */
+  double max_sample_err;  /* largest sampled relative error seen */
 } tufrg_flow_result;
 
 /* Integrates P, C [Nq][B][B] (device, in place) from opts->lambda0. */
@@ -184,9 +199,83 @@ tufrg_status tufrg_flow(tufrg_ctx *ctx, const tufrg_flow_opts *opts, tufrg_c64 *
  *   TUFRG_TIMER_BUNDLE   the two bundle products
  * tufrg_timing(ctx, 1) synchronises, clears and enables; tufrg_timing_read
  * synchronises and returns the accumulated milliseconds and interval count. */
-enum { TUFRG_TIMER_LOOP = 0, TUFRG_TIMER_PROJECT = 1, TUFRG_TIMER_BUNDLE = 2, TUFRG_TIMER_COUNT = 3 };
+enum {
+  TUFRG_TIMER_LOOP = 0,
+  TUFRG_TIMER_PROJECT = 1,
+  TUFRG_TIMER_BUNDLE = 2,
+  TUFRG_TIMER_SURROGATE = 3,
+  TUFRG_TIMER_COUNT = 4
+};
 tufrg_status tufrg_timing(tufrg_ctx *ctx, int32_t enable);
 tufrg_status tufrg_timing_read(tufrg_ctx *ctx, int32_t timer, double *total_ms, int32_t *count);
+
+/* ---------------------------------------------------------------------------
+ * Compact loops and the learned loop surrogate.
+ *
+ * The loops depend on R1 - R2 only: the compact form holds, per channel and
+ * coarse q, one block of n_o^4 complex entries for each difference vector dR
+ * of the list returned by tufrg_dR (n_dR of them, sorted):
+ *     Lc[ch][q][iD][(a*n_o + b)*n_o^2 + c*n_o + d] = L(q)[(R1,a,b),(R2,c,d)]
+ * for any R1, R2 with R1 - R2 = dR[iD] (channel 0 = pp, 1 = ph).
+ *
+ * The surrogate is a multilayer perceptron (tufrg_mlp) with GELU activations
+ * after every layer but the last, GELU(x) = x Phi(x).  It maps the features
+ *   [sin qx, cos qx, sin qy, cos qy, sin 2qx, cos 2qx, sin 2qy, cos 2qy,
+ *    ln(Lambda)/5, ch == 0, ch == 1, one-hot(iD)]   (11 + n_dR values)
+ * of a block to Lambda^power * Lc / y_scale, real and imaginary parts
+ * interleaved (2 n_o^4 values).  The paper has no learned component; this
+ * accelerates the loops of Sec. 3.1 / Sec. 4.2 and is always checked against
+ * them during a flow (tufrg_flow_opts.surrogate). */
+
+/* Compact loops of both channels at lambda (deriv as in tufrg_bubble):
+ * device [2][Nq][n_dR][n_o^4] tufrg_c64. */
+tufrg_status tufrg_loops_compact(tufrg_ctx *ctx, double lambda, int32_t deriv, tufrg_c64 *Lc);
+/* The difference vectors of the compact blocks: host [n_dR][2]. */
+tufrg_status tufrg_dR(const tufrg_ctx *ctx, int32_t *dR);
+
+/* Surrogate network.  sizes[0..n_sizes): input, hidden..., output widths.
+ * params: host array of the initial parameters (per layer W[out][in]
+ * row-major, then b[out]), or NULL for zeros; float32. */
+typedef struct tufrg_mlp tufrg_mlp;
+tufrg_status tufrg_mlp_create(int32_t n_sizes, const int32_t *sizes, const float *params, void *stream,
+                              tufrg_mlp **out);
+tufrg_status tufrg_mlp_destroy(tufrg_mlp *net);
+const char *tufrg_mlp_last_error(const tufrg_mlp *net);
+tufrg_status tufrg_mlp_n_params(const tufrg_mlp *net, int64_t *n);
+/* copy parameters out to / in from device memory (set also resets Adam) */
+tufrg_status tufrg_mlp_params(tufrg_mlp *net, float *params);
+tufrg_status tufrg_mlp_set_params(tufrg_mlp *net, const float *params);
+/* Y[n][n_out] = net(X[n][n_in]); device arrays */
+tufrg_status tufrg_mlp_forward(tufrg_mlp *net, int64_t n, const float *X, float *Y);
+/* mean squared error over the batch and outputs and its gradient with respect
+ * to the parameters (device, n_params floats; NULL: internal buffer used by
+ * tufrg_mlp_adam_step with grad = NULL); loss: host, may be NULL.  n <= 65536. */
+tufrg_status tufrg_mlp_loss_grad(tufrg_mlp *net, int32_t n, const float *X, const float *T, float *grad,
+                                 double *loss);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with learning rate lr */
+tufrg_status tufrg_mlp_adam_step(tufrg_mlp *net, const float *grad, float lr);
+/* epochs of shuffled minibatch Adam over rows X[n], T[n] (device); the mean
+ * batch loss of the last epoch is returned in last_epoch_loss (host, may be NULL) */
+tufrg_status tufrg_mlp_train(tufrg_mlp *net, int64_t n, const float *X, const float *T, int32_t batch,
+                             int32_t epochs, float lr, uint64_t seed, double *last_epoch_loss);
+
+/* Features and targets of n blocks (q, ch, iD device int32 lists) at lambda;
+ * with all three lists NULL the blocks are all 2 Nq n_dR in compact order.
+ * X: device [n][11 + n_dR]; T: device [n][2 n_o^4] from Lc (device
+ * [2][Nq][n_dR][n_o^4]) scaled by lambda^power / y_scale; max_abs (host, may
+ * be NULL) returns the largest |lambda^power Lc| over the listed blocks. */
+tufrg_status tufrg_sur_features(tufrg_ctx *ctx, int64_t n, const int32_t *q, const int32_t *ch, const int32_t *iD,
+                                double lambda, float *X);
+tufrg_status tufrg_sur_targets(tufrg_ctx *ctx, int64_t n, const int32_t *q, const int32_t *ch, const int32_t *iD,
+                               double lambda, double power, double y_scale, const tufrg_c64 *Lc, float *T,
+                               double *max_abs);
+/* Attach a network (NULL detaches; the context does not own it) with the
+ * scaling of its targets.  Input width must be 11 + n_dR, output 2 n_o^4, and
+ * the network must have been created on the context's stream.  Invalid block
+ * indices in tufrg_sur_targets give NaN targets. */
+tufrg_status tufrg_sur_attach(tufrg_ctx *ctx, tufrg_mlp *net, double power, double y_scale);
+/* Compact loops of both channels from the attached network (as tufrg_loops_compact). */
+tufrg_status tufrg_sur_loops(tufrg_ctx *ctx, double lambda, tufrg_c64 *Lc);
 
 #ifdef __cplusplus
 }

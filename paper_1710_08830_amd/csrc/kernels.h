@@ -71,4 +71,22 @@ hipError_t launch_dp_error(long long n, const double *x0, const double *x1, int 
 hipError_t launch_clear_reduce(unsigned long long *bits, unsigned int *flag, hipStream_t st);
 hipError_t launch_scale(long long n, const double *x, double s, double *y, hipStream_t st);
 
+// loop surrogate network (k_mlp.hip)
+hipError_t launch_gemm_f32(int M, int N, int K, const float *A, int lda, int tA, const float *B, int ldb, int tB,
+                           const float *bias, int epi, float *C, int ldc, float *Z, hipStream_t st);
+hipError_t launch_gelu_bwd(long long n, const float *Z, float *dA, hipStream_t st);
+hipError_t launch_colsum(int rows, int cols, const float *dZ, float *db, hipStream_t st);
+hipError_t launch_mse_grad(long long n, const float *Y, const float *T, float *dY, double *loss, hipStream_t st);
+hipError_t launch_adam(long long n, float *p, const float *g, float *m, float *v, float lr, float b1, float b2,
+                       float eps, int t, hipStream_t st);
+hipError_t launch_gather_rows(int rows, int len, const int *idx, const float *src, float *dst, hipStream_t st);
+hipError_t launch_sur_features(long long n, const int *ql, const int *cl, const int *dl, int Lq, int nD, double lam,
+                               float *X, hipStream_t st);
+hipError_t launch_sur_targets(long long n, const int *ql, const int *cl, const int *dl, int Nq, int nD, int no4,
+                              double s, const double *Lc, float *T, hipStream_t st);
+hipError_t launch_sur_scatter(long long n, int no4, double s, const float *Y, double *Lc, hipStream_t st);
+hipError_t launch_sur_compare(long long n, const double *a, const double *b, unsigned long long *bits,
+                              hipStream_t st);
+hipError_t launch_absmax_f32(long long n, const float *x, unsigned int *bits, hipStream_t st);
+
 }  // namespace tufrg

@@ -27,6 +27,13 @@ hipError_t launch_unpack_pi(int n_o, int Nf, const double *pi, double *out, hipS
 
 using namespace tufrg;
 
+namespace tufrg {
+tufrg_status mlp_forward_internal(tufrg_mlp *m, long long n, const float *X, float *Y);
+int mlp_n_in(const tufrg_mlp *m);
+int mlp_n_out(const tufrg_mlp *m);
+hipStream_t mlp_stream(const tufrg_mlp *m);
+}  // namespace tufrg
+
 struct tufrg_ctx {
   hipStream_t st = nullptr;
   int n_o = 0, n_ff = 0, B = 0, Lq = 0, n_ref = 0, Lf = 0, Nq = 0, Nf = 0, no2 = 0, no4 = 0;
@@ -69,6 +76,18 @@ struct tufrg_ctx {
   };
   bool timing = false;
   Timer timers[TUFRG_TIMER_COUNT];
+  // loop surrogate
+  tufrg_mlp *sur = nullptr;
+  double sur_power = 1.0, sur_yscale = 1.0;
+  float *d_surX = nullptr, *d_surY = nullptr;  // features of all blocks, network rows of a chunk
+  double *d_samp = nullptr;                    // plain loops of sampled q_x rows, [row][2][Lq][nD][no4]
+  int samp_rows = 0;
+  unsigned long long *d_sbits = nullptr;       // max |diff|, max |ref|, float max
+  unsigned long long *h_sbits = nullptr;       // pinned
+  // set during tufrg_flow
+  const tufrg_flow_opts *fopts = nullptr;
+  tufrg_flow_result *fres = nullptr;
+  double cur_max = 0.0;
 };
 
 static thread_local std::string g_err;
@@ -139,8 +158,10 @@ static void destroy_all(tufrg_ctx *c) {
   c->allocs.clear();
   if (c->h_bits) (void)hipHostFree(c->h_bits);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
+  if (c->h_sbits) (void)hipHostFree(c->h_sbits);
   c->h_bits = nullptr;
   c->h_flag = nullptr;
+  c->h_sbits = nullptr;
 }
 
 extern "C" const char *tufrg_last_error(const tufrg_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
@@ -309,6 +330,8 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CTRY(dalloc(c, &c->d_flag, 4));
   CHIP(hipHostMalloc((void **)&c->h_bits, 4 * sizeof(unsigned long long), hipHostMallocDefault));
   CHIP(hipHostMalloc((void **)&c->h_flag, 4 * sizeof(unsigned int), hipHostMallocDefault));
+  CTRY(dalloc(c, &c->d_sbits, 4));
+  CHIP(hipHostMalloc((void **)&c->h_sbits, 4 * sizeof(unsigned long long), hipHostMallocDefault));
 
   // tables
   std::vector<double> twf(2 * c->Lf), twq(2 * c->Lq);
@@ -449,16 +472,117 @@ static ProjArgs proj_args(tufrg_ctx *c) {
   return a;
 }
 
-// loops of channels [ch_first, ch_first + n_ch) into the compact buffer
-static tufrg_status compute_loops(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch) {
+static tufrg_status compute_kval(tufrg_ctx *c, double lam, int deriv) {
   HIPCHK(c, launch_kval(c->n_o * c->Nf, c->Nf, c->n_o > 2 ? c->n_o : 0, c->d_band64, lam, c->scheme, deriv,
                         c->d_kv64, c->d_kv32, c->st));
+  return TUFRG_OK;
+}
+
+// loops of channels [ch_first, ch_first + n_ch) and coarse q [q_first, q_first + n_q)
+// (whole q_x rows) into dst, compact [n_ch][n_q][nD][no4]; regulator values
+// must be current (compute_kval)
+static tufrg_status loops_range(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch, int q_first, int n_q,
+                                double *dst) {
   LoopArgs a = loop_args(c, lam, deriv, ch_first, n_ch);
+  a.q_first = q_first;
+  a.n_q = n_q;
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
   HIPCHK(c, launch_loop(a, c->st));
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
-  double *dst = c->d_loop + 2 * (size_t)ch_first * c->Nq * c->nD * c->no4;
   HIPCHK(c, launch_loop_finalize(a, c->nD, c->d_dlist, dst, c->st));
+  return TUFRG_OK;
+}
+
+// loops of channels [ch_first, ch_first + n_ch) into the compact buffer
+static tufrg_status compute_loops(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch) {
+  TRY(compute_kval(c, lam, deriv));
+  double *dst = c->d_loop + 2 * (size_t)ch_first * c->Nq * c->nD * c->no4;
+  return loops_range(c, lam, deriv, ch_first, n_ch, 0, c->Nq, dst);
+}
+
+// network loops of all 2 Nq nD blocks into dst (compact, both channels)
+static const long long SUR_CHUNK = 16384;
+static tufrg_status sur_loops_internal(tufrg_ctx *c, double lam, double *dst) {
+  const long long nb = 2LL * c->Nq * c->nD;
+  const int nin = 11 + c->nD, nout = 2 * c->no4;
+  if (!c->d_surX) {
+    TRY(dalloc(c, &c->d_surX, (size_t)nb * nin));
+    TRY(dalloc(c, &c->d_surY, (size_t)SUR_CHUNK * nout));
+  }
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_SURROGATE));
+  HIPCHK(c, launch_sur_features(nb, nullptr, nullptr, nullptr, c->Lq, c->nD, lam, c->d_surX, c->st));
+  const double s = c->sur_yscale / std::pow(lam, c->sur_power);
+  for (long long b0 = 0; b0 < nb; b0 += SUR_CHUNK) {
+    const long long rows = std::min(SUR_CHUNK, nb - b0);
+    TRY(mlp_forward_internal(c->sur, rows, c->d_surX + b0 * nin, c->d_surY));
+    HIPCHK(c, launch_sur_scatter(rows, c->no4, s, c->d_surY, dst + b0 * nout, c->st));
+  }
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_SURROGATE));
+  return TUFRG_OK;
+}
+
+static uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// loops of both channels for a right-hand side inside a flow with the
+// surrogate: network everywhere, plain on sampled q_x rows, plain everywhere
+// when the sampled error or the coupling is too large
+static tufrg_status surrogate_loops(tufrg_ctx *c, double lam) {
+  const tufrg_flow_opts *o = c->fopts;
+  tufrg_flow_result *r = c->fres;
+  const size_t blk = (size_t)c->nD * c->no4;  // complex values per (channel, q)
+  if (c->cur_max > o->plain_above) {
+    TRY(compute_loops(c, lam, 1, 0, 2));
+    r->n_plain++;
+    return TUFRG_OK;
+  }
+  TRY(sur_loops_internal(c, lam, c->d_loop));
+  // sampled rows: distinct q_x rows from a counter-based hash
+  int nr = (int)std::llround(o->sample_frac * c->Lq);
+  nr = std::max(1, std::min(c->Lq, nr));
+  std::vector<int> rows;
+  const uint64_t ctr = (uint64_t)(r->n_plain + r->n_surrogate);
+  for (uint64_t j = 0; (int)rows.size() < nr; ++j) {
+    const int row = (int)(splitmix64(o->sample_seed ^ splitmix64(ctr * 0x100000001B3ull + j)) % (uint64_t)c->Lq);
+    if (std::find(rows.begin(), rows.end(), row) == rows.end()) rows.push_back(row);
+  }
+  const size_t rowsz = 2 * (size_t)c->Lq * blk * 2;  // doubles of one sampled row, both channels
+  if (nr > c->samp_rows) {
+    TRY(dalloc(c, &c->d_samp, rowsz * nr));
+    c->samp_rows = nr;
+  }
+  TRY(compute_kval(c, lam, 1));
+  for (int j = 0; j < nr; ++j)
+    TRY(loops_range(c, lam, 1, 0, 2, rows[j] * c->Lq, c->Lq, c->d_samp + j * rowsz));
+  HIPCHK(c, hipMemsetAsync(c->d_sbits, 0, 2 * sizeof(unsigned long long), c->st));
+  for (int j = 0; j < nr; ++j)
+    for (int ch = 0; ch < 2; ++ch)
+      HIPCHK(c, launch_sur_compare((long long)c->Lq * blk,
+                                   c->d_loop + 2 * (((size_t)ch * c->Nq + (size_t)rows[j] * c->Lq) * blk),
+                                   c->d_samp + j * rowsz + 2 * (size_t)ch * c->Lq * blk, c->d_sbits, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->h_sbits, c->d_sbits, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  double dmax, rmax;
+  std::memcpy(&dmax, &c->h_sbits[0], sizeof(double));
+  std::memcpy(&rmax, &c->h_sbits[1], sizeof(double));
+  const double err = rmax > 0.0 ? dmax / rmax : (dmax > 0.0 ? INFINITY : 0.0);
+  r->max_sample_err = std::max(r->max_sample_err, err);
+  if (!(err <= o->sur_tol)) {
+    TRY(loops_range(c, lam, 1, 0, 2, 0, c->Nq, c->d_loop));
+    r->n_plain++;
+    r->n_fallback++;
+    return TUFRG_OK;
+  }
+  for (int j = 0; j < nr; ++j)
+    for (int ch = 0; ch < 2; ++ch)
+      HIPCHK(c, hipMemcpyAsync(c->d_loop + 2 * (((size_t)ch * c->Nq + (size_t)rows[j] * c->Lq) * blk),
+                               c->d_samp + j * rowsz + 2 * (size_t)ch * c->Lq * blk,
+                               2 * sizeof(double) * c->Lq * blk, hipMemcpyDeviceToDevice, c->st));
+  r->n_surrogate++;
   return TUFRG_OK;
 }
 
@@ -476,12 +600,17 @@ static tufrg_status project_internal(tufrg_ctx *c, const double *P, const double
 static tufrg_status rhs_internal(tufrg_ctx *c, double lam, const double *P, const double *C, double *dP, double *dC,
                                  double scale, unsigned mask) {
   const size_t BB = (size_t)c->B * c->B;
-  if ((mask & 3u) == 3u)
-    TRY(compute_loops(c, lam, 1, 0, 2));
-  else if (mask & 1u)
-    TRY(compute_loops(c, lam, 1, 0, 1));
-  else if (mask & 2u)
-    TRY(compute_loops(c, lam, 1, 1, 1));
+  if (c->fopts && c->fopts->surrogate && (mask & 3u) == 3u) {
+    TRY(surrogate_loops(c, lam));
+  } else {
+    if ((mask & 3u) == 3u)
+      TRY(compute_loops(c, lam, 1, 0, 2));
+    else if (mask & 1u)
+      TRY(compute_loops(c, lam, 1, 0, 1));
+    else if (mask & 2u)
+      TRY(compute_loops(c, lam, 1, 1, 1));
+    if (c->fres) c->fres->n_plain++;
+  }
   TRY(project_internal(c, P, C, c->d_VP, c->d_VC));
   const size_t lsz = 2 * (size_t)c->Nq * c->nD * c->no4;
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_BUNDLE));
@@ -557,6 +686,85 @@ extern "C" tufrg_status tufrg_rhs(tufrg_ctx *c, double lambda, const tufrg_c64 *
   return rhs_internal(c, lambda, (const double *)P, (const double *)C, (double *)dP, (double *)dC, 1.0, 3u);
 }
 
+extern "C" tufrg_status tufrg_loops_compact(tufrg_ctx *c, double lambda, int32_t deriv, tufrg_c64 *Lc) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, TUFRG_E_INVAL, "lambda must be positive");
+  if (!is_device_ptr(Lc)) return fail(c, TUFRG_E_INVAL, "Lc must be a device pointer");
+  TRY(compute_kval(c, lambda, deriv ? 1 : 0));
+  return loops_range(c, lambda, deriv ? 1 : 0, 0, 2, 0, c->Nq, (double *)Lc);
+}
+
+extern "C" tufrg_status tufrg_dR(const tufrg_ctx *c, int32_t *dR) {
+  if (!c || !dR) return fail(nullptr, TUFRG_E_INVAL, "null argument");
+  for (size_t i = 0; i < c->dlist.size(); ++i) dR[i] = c->dlist[i];
+  return TUFRG_OK;
+}
+
+static tufrg_status check_blocks(tufrg_ctx *c, int64_t n, const int32_t *q, const int32_t *ch, const int32_t *iD) {
+  if (n < 0) return fail(c, TUFRG_E_INVAL, "negative block count");
+  const bool lists = q || ch || iD;
+  if (lists && (!is_device_ptr(q) || !is_device_ptr(ch) || !is_device_ptr(iD)))
+    return fail(c, TUFRG_E_INVAL, "q, ch, iD must all be device pointers or all NULL");
+  if (!lists && n > 2LL * c->Nq * c->nD) return fail(c, TUFRG_E_INVAL, "more blocks than 2 Nq n_dR");
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_sur_features(tufrg_ctx *c, int64_t n, const int32_t *q, const int32_t *ch,
+                                          const int32_t *iD, double lambda, float *X) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  TRY(check_blocks(c, n, q, ch, iD));
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, TUFRG_E_INVAL, "lambda must be positive");
+  if (n > 0 && !is_device_ptr(X)) return fail(c, TUFRG_E_INVAL, "X must be a device pointer");
+  HIPCHK(c, launch_sur_features(n, q, ch, iD, c->Lq, c->nD, lambda, X, c->st));
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_sur_targets(tufrg_ctx *c, int64_t n, const int32_t *q, const int32_t *ch,
+                                         const int32_t *iD, double lambda, double power, double y_scale,
+                                         const tufrg_c64 *Lc, float *T, double *max_abs) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  TRY(check_blocks(c, n, q, ch, iD));
+  if (!(lambda > 0.0) || !(y_scale > 0.0)) return fail(c, TUFRG_E_INVAL, "lambda and y_scale must be positive");
+  if (n > 0 && (!is_device_ptr(Lc) || !is_device_ptr(T))) return fail(c, TUFRG_E_INVAL, "Lc, T must be device pointers");
+  const double s = std::pow(lambda, power) / y_scale;
+  HIPCHK(c, launch_sur_targets(n, q, ch, iD, c->Nq, c->nD, c->no4, s, (const double *)Lc, T, c->st));
+  if (max_abs) {
+    HIPCHK(c, hipMemsetAsync(c->d_sbits, 0, sizeof(unsigned long long), c->st));
+    HIPCHK(c, launch_absmax_f32(n * 2 * c->no4, T, (unsigned int *)c->d_sbits, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->h_sbits, c->d_sbits, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    float f;
+    const unsigned int u = (unsigned int)(c->h_sbits[0] & 0xffffffffu);
+    std::memcpy(&f, &u, sizeof(f));
+    *max_abs = (double)f * y_scale;
+  }
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_sur_attach(tufrg_ctx *c, tufrg_mlp *net, double power, double y_scale) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!net) {
+    c->sur = nullptr;
+    return TUFRG_OK;
+  }
+  if (mlp_n_in(net) != 11 + c->nD || mlp_n_out(net) != 2 * c->no4)
+    return fail(c, TUFRG_E_INVAL, "network widths must be 11 + n_dR inputs and 2 n_o^4 outputs");
+  if (!(y_scale > 0.0) || !std::isfinite(power)) return fail(c, TUFRG_E_INVAL, "bad target scaling");
+  if (mlp_stream(net) != c->st) return fail(c, TUFRG_E_INVAL, "network and context must share one stream");
+  c->sur = net;
+  c->sur_power = power;
+  c->sur_yscale = y_scale;
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_sur_loops(tufrg_ctx *c, double lambda, tufrg_c64 *Lc) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!c->sur) return fail(c, TUFRG_E_INVAL, "no network attached");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, TUFRG_E_INVAL, "lambda must be positive");
+  if (!is_device_ptr(Lc)) return fail(c, TUFRG_E_INVAL, "Lc must be a device pointer");
+  return sur_loops_internal(c, lambda, (double *)Lc);
+}
+
 // ---------------------------------------------------------------------------
 // flow
 
@@ -608,6 +816,18 @@ extern "C" tufrg_status tufrg_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg
   if (o->n_steps < 0) return fail(c, TUFRG_E_INVAL, "n_steps must be >= 0");
   const unsigned mask = o->channel_mask & 3u;
   if (!mask) return fail(c, TUFRG_E_INVAL, "channel_mask selects no channel");
+  if (o->surrogate) {
+    if (!c->sur) return fail(c, TUFRG_E_INVAL, "surrogate requested but no network attached");
+    if (!(o->sample_frac > 0.0 && o->sample_frac <= 1.0)) return fail(c, TUFRG_E_INVAL, "sample_frac must be in (0, 1]");
+    if (!(o->sur_tol > 0.0)) return fail(c, TUFRG_E_INVAL, "sur_tol must be positive");
+  }
+  struct FlowGuard {
+    tufrg_ctx *c;
+    ~FlowGuard() {
+      c->fopts = nullptr;
+      c->fres = nullptr;
+    }
+  } guard{c};
   double *P = (double *)Pu, *C = (double *)Cu;
   const size_t BB = (size_t)c->B * c->B;
   const size_t ns = 2 * BB * c->Nq;  // doubles per state
@@ -619,6 +839,9 @@ extern "C" tufrg_status tufrg_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg
   TRY(state_max(c, P, C, &m_prev, &bad));
   if (bad) return fail(c, TUFRG_E_NONFINITE, "non-finite initial state");
   double lam_prev = o->lambda0;
+  c->fopts = o;
+  c->fres = res;
+  c->cur_max = m_prev;
 
   if (o->n_steps > 0) {
     if (!c->d_dP) {
@@ -640,6 +863,7 @@ extern "C" tufrg_status tufrg_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg
       res->n_steps++;
       res->lambda_stop = l1;
       res->max_coupling = mx;
+      c->cur_max = mx;
       if (mx > o->v_max) {
         res->diverged = 1;
         res->lambda_c = lambda_c_interp(lam_prev, m_prev, l1, mx, o->v_max);
@@ -706,6 +930,7 @@ extern "C" tufrg_status tufrg_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg
       res->n_steps++;
       res->lambda_stop = lam;
       res->max_coupling = mx;
+      c->cur_max = mx;
       if (mx > o->v_max) {
         res->diverged = 1;
         res->lambda_c = lambda_c_interp(lam_prev, m_prev, lam, mx, o->v_max);

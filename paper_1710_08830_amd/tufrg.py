@@ -30,8 +30,12 @@ PP, PH = 0, 1
 
 SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "tufrg_band_data",
            "tufrg_bubble", "tufrg_project", "tufrg_rhs", "tufrg_flow", "tufrg_timing",
-           "tufrg_timing_read"]
-TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE = 0, 1, 2
+           "tufrg_timing_read", "tufrg_loops_compact", "tufrg_dR", "tufrg_mlp_create",
+           "tufrg_mlp_destroy", "tufrg_mlp_last_error", "tufrg_mlp_n_params", "tufrg_mlp_params",
+           "tufrg_mlp_set_params", "tufrg_mlp_forward", "tufrg_mlp_loss_grad", "tufrg_mlp_adam_step",
+           "tufrg_mlp_train", "tufrg_sur_features", "tufrg_sur_targets", "tufrg_sur_attach",
+           "tufrg_sur_loops"]
+TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE, TIMER_SURROGATE = 0, 1, 2, 3
 
 
 class c64(ctypes.Structure):
@@ -59,14 +63,19 @@ class FlowOpts(ctypes.Structure):
                 ("n_steps", ctypes.c_int32), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
                 ("h0", ctypes.c_double), ("v_max", ctypes.c_double),
                 ("channel_mask", ctypes.c_uint32), ("max_steps", ctypes.c_int32),
-                ("on_step", STEP_CB), ("user", ctypes.c_void_p)]
+                ("on_step", STEP_CB), ("user", ctypes.c_void_p),
+                ("surrogate", ctypes.c_int32), ("sample_frac", ctypes.c_double),
+                ("sur_tol", ctypes.c_double), ("plain_above", ctypes.c_double),
+                ("sample_seed", ctypes.c_uint64)]
 
 
 class FlowResult(ctypes.Structure):
     _fields_ = [("lambda_stop", ctypes.c_double), ("lambda_c", ctypes.c_double),
                 ("max_coupling", ctypes.c_double), ("diverged", ctypes.c_int32),
                 ("n_steps", ctypes.c_int32), ("n_rhs", ctypes.c_int32),
-                ("n_reject", ctypes.c_int32), ("stopped_by_callback", ctypes.c_int32)]
+                ("n_reject", ctypes.c_int32), ("stopped_by_callback", ctypes.c_int32),
+                ("n_plain", ctypes.c_int32), ("n_surrogate", ctypes.c_int32),
+                ("n_fallback", ctypes.c_int32), ("max_sample_err", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -86,8 +95,32 @@ _lib.tufrg_flow.argtypes = [_vp, ctypes.POINTER(FlowOpts), _vp, _vp, ctypes.POIN
 _lib.tufrg_timing.argtypes = [_vp, ctypes.c_int32]
 _lib.tufrg_timing_read.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int32)]
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_lib.tufrg_loops_compact.argtypes = [_vp, ctypes.c_double, ctypes.c_int32, _vp]
+_lib.tufrg_dR.argtypes = [_vp, _i32p]
+_lib.tufrg_mlp_create.argtypes = [ctypes.c_int32, _i32p, _vp, _vp, ctypes.POINTER(_vp)]
+_lib.tufrg_mlp_destroy.argtypes = [_vp]
+_lib.tufrg_mlp_last_error.argtypes = [_vp]
+_lib.tufrg_mlp_last_error.restype = ctypes.c_char_p
+_lib.tufrg_mlp_n_params.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
+_lib.tufrg_mlp_params.argtypes = [_vp, _vp]
+_lib.tufrg_mlp_set_params.argtypes = [_vp, _vp]
+_lib.tufrg_mlp_forward.argtypes = [_vp, ctypes.c_int64, _vp, _vp]
+_lib.tufrg_mlp_loss_grad.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
+_lib.tufrg_mlp_adam_step.argtypes = [_vp, _vp, ctypes.c_float]
+_lib.tufrg_mlp_train.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_float, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
+_lib.tufrg_sur_features.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_double, _vp]
+_lib.tufrg_sur_targets.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_double, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
+_lib.tufrg_sur_attach.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_double]
+_lib.tufrg_sur_loops.argtypes = [_vp, ctypes.c_double, _vp]
 for _f in ("tufrg_create", "tufrg_destroy", "tufrg_dims", "tufrg_band_data", "tufrg_bubble",
-           "tufrg_project", "tufrg_rhs", "tufrg_flow", "tufrg_timing", "tufrg_timing_read"):
+           "tufrg_project", "tufrg_rhs", "tufrg_flow", "tufrg_timing", "tufrg_timing_read",
+           "tufrg_loops_compact", "tufrg_dR", "tufrg_mlp_create", "tufrg_mlp_destroy",
+           "tufrg_mlp_n_params", "tufrg_mlp_params", "tufrg_mlp_set_params", "tufrg_mlp_forward",
+           "tufrg_mlp_loss_grad", "tufrg_mlp_adam_step", "tufrg_mlp_train", "tufrg_sur_features",
+           "tufrg_sur_targets", "tufrg_sur_attach", "tufrg_sur_loops"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -184,11 +217,14 @@ def tufrg_rhs(ctx, lam, P, C, dP, dC):
 
 
 def tufrg_flow(ctx, P, C, lambda0, lambda_end, n_steps=0, rtol=1e-6, atol=1e-6, h0=0.05,
-               v_max=50.0, channel_mask=3, max_steps=0, on_step=None):
+               v_max=50.0, channel_mask=3, max_steps=0, on_step=None, surrogate=False,
+               sample_frac=0.05, sur_tol=1e-3, plain_above=20.0, sample_seed=3):
     """Integrates P, C in place; returns the result as a dict."""
     cb = STEP_CB(on_step) if on_step is not None else STEP_CB()
     o = FlowOpts(float(lambda0), float(lambda_end), int(n_steps), float(rtol), float(atol),
-                 float(h0), float(v_max), int(channel_mask), int(max_steps), cb, None)
+                 float(h0), float(v_max), int(channel_mask), int(max_steps), cb, None,
+                 int(bool(surrogate)), float(sample_frac), float(sur_tol), float(plain_above),
+                 int(sample_seed))
     r = FlowResult()
     _check(_lib.tufrg_flow(ctx.handle, ctypes.byref(o), _ptr(P), _ptr(C), ctypes.byref(r)),
            ctx.handle)
@@ -206,3 +242,108 @@ def tufrg_timing_read(ctx, timer):
     _check(_lib.tufrg_timing_read(ctx.handle, int(timer), ctypes.byref(ms), ctypes.byref(n)),
            ctx.handle)
     return ms.value, n.value
+
+
+def tufrg_loops_compact(ctx, lam, deriv, Lc):
+    """Compact loops of both channels, Lc: complex128 [2][Nq][n_dR][n_o^4]."""
+    _check(_lib.tufrg_loops_compact(ctx.handle, float(lam), int(deriv), _ptr(Lc)), ctx.handle)
+
+
+def tufrg_dR(ctx):
+    """Difference vectors of the compact loop blocks, int32 [n_dR][2]."""
+    out = np.zeros((ctx.n_dR, 2), dtype=np.int32)
+    _check(_lib.tufrg_dR(ctx.handle, out.ctypes.data_as(_i32p)), ctx.handle)
+    return out
+
+
+class Mlp:
+    """Owns a tufrg_mlp (the loop surrogate network)."""
+
+    def __init__(self, sizes, params=None, stream=None):
+        sz = np.ascontiguousarray(sizes, dtype=np.int32)
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        h = ctypes.c_void_p()
+        st = _lib.tufrg_mlp_create(len(sz), sz.ctypes.data_as(_i32p),
+                                   None if p is None else p.ctypes.data_as(ctypes.c_void_p),
+                                   _stream_handle(stream), ctypes.byref(h))
+        if st != TUFRG_OK:
+            raise TufrgError(st, _lib.tufrg_mlp_last_error(None).decode(errors="replace"))
+        self.handle = h
+        self.sizes = [int(x) for x in sz]
+        n = ctypes.c_int64()
+        self._check(_lib.tufrg_mlp_n_params(h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    def _check(self, status):
+        if status != TUFRG_OK:
+            raise TufrgError(status, _lib.tufrg_mlp_last_error(self.handle).decode(errors="replace"))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _lib.tufrg_mlp_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tufrg_mlp_params(net, out):
+    net._check(_lib.tufrg_mlp_params(net.handle, _ptr(out)))
+
+
+def tufrg_mlp_set_params(net, params):
+    net._check(_lib.tufrg_mlp_set_params(net.handle, _ptr(params)))
+
+
+def tufrg_mlp_forward(net, X, Y):
+    net._check(_lib.tufrg_mlp_forward(net.handle, int(X.shape[0]), _ptr(X), _ptr(Y)))
+
+
+def tufrg_mlp_loss_grad(net, X, T, grad=None):
+    """Mean squared error of the batch (returned) and its gradient into grad."""
+    loss = ctypes.c_double()
+    net._check(_lib.tufrg_mlp_loss_grad(net.handle, int(X.shape[0]), _ptr(X), _ptr(T),
+                                        None if grad is None else _ptr(grad), ctypes.byref(loss)))
+    return loss.value
+
+
+def tufrg_mlp_adam_step(net, grad, lr):
+    net._check(_lib.tufrg_mlp_adam_step(net.handle, None if grad is None else _ptr(grad), float(lr)))
+
+
+def tufrg_mlp_train(net, X, T, batch, epochs, lr, seed=0):
+    """Minibatch Adam epochs; returns the mean batch loss of the last epoch."""
+    loss = ctypes.c_double()
+    net._check(_lib.tufrg_mlp_train(net.handle, int(X.shape[0]), _ptr(X), _ptr(T), int(batch),
+                                    int(epochs), float(lr), int(seed), ctypes.byref(loss)))
+    return loss.value
+
+
+def _opt(t):
+    return None if t is None else _ptr(t)
+
+
+def tufrg_sur_features(ctx, n, lam, X, q=None, ch=None, iD=None):
+    _check(_lib.tufrg_sur_features(ctx.handle, int(n), _opt(q), _opt(ch), _opt(iD), float(lam),
+                                   _ptr(X)), ctx.handle)
+
+
+def tufrg_sur_targets(ctx, n, lam, power, y_scale, Lc, T, q=None, ch=None, iD=None):
+    """Writes the scaled targets; returns max |lambda^power Lc| over the blocks."""
+    mx = ctypes.c_double()
+    _check(_lib.tufrg_sur_targets(ctx.handle, int(n), _opt(q), _opt(ch), _opt(iD), float(lam),
+                                  float(power), float(y_scale), _ptr(Lc), _ptr(T), ctypes.byref(mx)),
+           ctx.handle)
+    return mx.value
+
+
+def tufrg_sur_attach(ctx, net, power, y_scale):
+    _check(_lib.tufrg_sur_attach(ctx.handle, None if net is None else net.handle, float(power),
+                                 float(y_scale)), ctx.handle)
+
+
+def tufrg_sur_loops(ctx, lam, Lc):
+    _check(_lib.tufrg_sur_loops(ctx.handle, float(lam), _ptr(Lc)), ctx.handle)

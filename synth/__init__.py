@@ -21,5 +21,6 @@ from .models import (  # noqa: F401
     mlp_shape,
     mlp_init,
     mlp_batch,
+    probe_vector,
 )
 from .workloads import workload, WORKLOADS  # noqa: F401

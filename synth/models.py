@@ -226,3 +226,9 @@ def mlp_batch(n, n_in, n_out, seed):
     X = rng.standard_normal((n, n_in)).astype(np.float32)
     T = (0.5 * rng.standard_normal((n, n_out))).astype(np.float32)
     return X, T
+
+
+def probe_vector(n, seed, scale=1.0):
+    """Seeded FP32 probe vector (e.g. a gradient fed to an optimiser step)."""
+    rng = np.random.default_rng(seed)
+    return (scale * rng.standard_normal(n)).astype(np.float32)

@@ -13,7 +13,7 @@ LIB = os.path.join(ROOT, "paper_1710_08830_amd", "libtufrg.so")
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tufrg_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(tufrg_[A-Za-z_0-9]+)\s*\(", text)))
 
 
 def test_header_declares_the_boundary():

@@ -1,0 +1,265 @@
+"""Loop surrogate on the GPU against the FP64 oracle (oracle/mlp.py) and
+against the plain loops, through the C ABI.
+
+Tolerances: the network runs in FP32 with FP32 accumulation, so outputs and
+gradients are compared at 1e-5 relative (max-norm over all entries relative
+to the largest reference entry); Adam updates at 1e-6.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import mlp as omlp  # noqa: E402
+from oracle import tufrg as otu  # noqa: E402
+from synth import (ff_shell, hubbard_hoppings, kanamori_V0, mlp_batch, mlp_init, mlp_shape,  # noqa: E402
+                   onsite_V0, probe_vector, t2g_soc_hoppings)
+from tests._layout import ph_loop_to_matrix, pp_loop_to_matrix  # noqa: E402
+
+SMALL = [23, 64, 64, 64, 40]
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_08830_amd import tufrg
+    return tufrg
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def f32(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev())
+
+
+def _hub5():
+    return dict(hop=hubbard_hoppings(1.0, -0.25), mu=-0.6, V0=onsite_V0(3.0), ff=ff_shell(5), Lq=6, n_ref=3,
+                cutoff="temperature")
+
+
+def _t2g9():
+    return dict(hop=t2g_soc_hoppings(0.2, seed=1), mu=0.35, V0=kanamori_V0(2.0, 0.3), ff=ff_shell(9), Lq=6,
+                n_ref=3, cutoff="omega")
+
+
+def _ctx(T, c, prec="fp64"):
+    return T.Context(c["hop"][0], c["hop"][1], c["mu"], c["V0"], c["ff"], c["Lq"], c["n_ref"], c["cutoff"], prec)
+
+
+@pytest.mark.parametrize("sizes,n", [(SMALL, 37), (mlp_shape(52), 70)])
+def test_forward_matches_oracle(T, sizes, n):
+    p = mlp_init(sizes, seed=3)
+    X, _ = mlp_batch(n, sizes[0], sizes[-1], seed=7)
+    net = T.Mlp(sizes, p)
+    Y = torch.zeros((n, sizes[-1]), dtype=torch.float32, device=dev())
+    T.tufrg_mlp_forward(net, f32(X), Y)
+    torch.cuda.synchronize()
+    ref, _, _ = omlp.forward(p, sizes, X)
+    assert rel(Y.cpu().numpy(), ref) < 1e-5
+
+
+@pytest.mark.parametrize("sizes,n", [(SMALL, 37), (SMALL, 130), (mlp_shape(52), 20)])
+def test_gradient_matches_oracle(T, sizes, n):
+    p = mlp_init(sizes, seed=4)
+    X, Tt = mlp_batch(n, sizes[0], sizes[-1], seed=8)
+    net = T.Mlp(sizes, p)
+    g = torch.zeros(net.n_params, dtype=torch.float32, device=dev())
+    loss = T.tufrg_mlp_loss_grad(net, f32(X), f32(Tt), g)
+    torch.cuda.synchronize()
+    loss_ref, g_ref = omlp.loss_and_grad(p, sizes, X, Tt)
+    assert abs(loss / loss_ref - 1) < 1e-6
+    g = g.cpu().numpy()
+    assert rel(g, g_ref) < 1e-5
+    # per layer as well, so a small layer cannot hide behind a large one
+    o = 0
+    for ni, no in zip(sizes[:-1], sizes[1:]):
+        for sz in (ni * no, no):
+            assert rel(g[o:o + sz], g_ref[o:o + sz]) < 1e-4
+            o += sz
+
+
+def test_adam_steps_match_oracle(T):
+    p = mlp_init(SMALL, seed=5)
+    net = T.Mlp(SMALL, p)
+    g1 = probe_vector(net.n_params, seed=11, scale=0.1)
+    g2 = probe_vector(net.n_params, seed=12, scale=0.1)
+    T.tufrg_mlp_adam_step(net, f32(g1), 1e-3)
+    T.tufrg_mlp_adam_step(net, f32(g2), 1e-3)
+    out = torch.zeros(net.n_params, dtype=torch.float32, device=dev())
+    T.tufrg_mlp_params(net, out)
+    torch.cuda.synchronize()
+    m = v = np.zeros(net.n_params)
+    q, m, v = omlp.adam_step(p.astype(np.float64), g1.astype(np.float64), m, v, 1, 1e-3)
+    q, m, v = omlp.adam_step(q, g2.astype(np.float64), m, v, 2, 1e-3)
+    assert np.abs(out.cpu().numpy() - q).max() < 1e-6
+
+
+def test_training_lowers_the_loss(T):
+    sizes = [12, 64, 64, 64, 6]
+    X, Tt = mlp_batch(512, 12, 6, seed=9)
+    net = T.Mlp(sizes, mlp_init(sizes, seed=6))
+    Xd, Td = f32(X), f32(Tt)
+    l0 = T.tufrg_mlp_loss_grad(net, Xd, Td)
+    last = T.tufrg_mlp_train(net, Xd, Td, batch=64, epochs=40, lr=3e-3, seed=1)
+    l1 = T.tufrg_mlp_loss_grad(net, Xd, Td)
+    assert np.isfinite(last) and l1 < 0.5 * l0
+
+
+def _blocks(ctx, seed):
+    rng = np.random.default_rng(seed)
+    n = 57
+    q = rng.integers(0, ctx.Nq, n).astype(np.int32)
+    ch = rng.integers(0, 2, n).astype(np.int32)
+    iD = rng.integers(0, ctx.n_dR, n).astype(np.int32)
+    return q, ch, iD
+
+
+def test_features_match_oracle(T):
+    c = _hub5()
+    ctx = _ctx(T, c)
+    nin = 11 + ctx.n_dR
+    q, ch, iD = _blocks(ctx, 1)
+    X = torch.zeros((len(q), nin), dtype=torch.float32, device=dev())
+    ti = lambda a: torch.from_numpy(a).to(dev())  # noqa: E731
+    T.tufrg_sur_features(ctx, len(q), 0.37, X, ti(q), ti(ch), ti(iD))
+    nb = 2 * ctx.Nq * ctx.n_dR
+    Xa = torch.zeros((nb, nin), dtype=torch.float32, device=dev())
+    T.tufrg_sur_features(ctx, nb, 0.37, Xa)
+    torch.cuda.synchronize()
+    ref = omlp.features(q, c["Lq"], 0.37, ch, iD, ctx.n_dR)
+    assert np.abs(X.cpu().numpy() - ref).max() < 1e-6
+    b = np.arange(nb)
+    ref_a = omlp.features((b // ctx.n_dR) % ctx.Nq, c["Lq"], 0.37, b // (ctx.n_dR * ctx.Nq), b % ctx.n_dR,
+                          ctx.n_dR)
+    assert np.abs(Xa.cpu().numpy() - ref_a).max() < 1e-6
+
+
+def _compact_ref(T, ctx, c, lam):
+    """Oracle loops of both channels in the compact layout of the library."""
+    st = otu.TUSetup(*c["hop"], c["mu"], c["V0"], c["ff"], c["Lq"], c["n_ref"], c["cutoff"])
+    ff = [tuple(r) for r in np.asarray(c["ff"])]
+    dR = T.tufrg_dR(ctx)
+    no2 = ctx.n_o ** 2
+    out = np.zeros((2, ctx.Nq, ctx.n_dR, no2 * no2), dtype=np.complex128)
+    for chn, conv in ((0, pp_loop_to_matrix), (1, ph_loop_to_matrix)):
+        M = conv(otu.loops(st, "pp" if chn == 0 else "ph", lam))
+        for i, (dx, dy) in enumerate(dR):
+            r1, r2 = next((a, b) for a in range(len(ff)) for b in range(len(ff))
+                          if ff[a][0] - ff[b][0] == dx and ff[a][1] - ff[b][1] == dy)
+            blk = M[:, r1 * no2:(r1 + 1) * no2, r2 * no2:(r2 + 1) * no2]
+            out[chn, :, i, :] = blk.reshape(ctx.Nq, no2 * no2)
+    return out
+
+
+@pytest.mark.parametrize("case", ["hub5", "t2g9"])
+def test_compact_loops_and_targets_match_oracle(T, case):
+    c = _hub5() if case == "hub5" else _t2g9()
+    ctx = _ctx(T, c)
+    lam = 0.41
+    no4 = ctx.n_o ** 4
+    Lc = torch.zeros((2, ctx.Nq, ctx.n_dR, no4), dtype=torch.complex128, device=dev())
+    T.tufrg_loops_compact(ctx, lam, 1, Lc)
+    q, ch, iD = _blocks(ctx, 2)
+    ti = lambda a: torch.from_numpy(a).to(dev())  # noqa: E731
+    Tt = torch.zeros((len(q), 2 * no4), dtype=torch.float32, device=dev())
+    mx = T.tufrg_sur_targets(ctx, len(q), lam, 1.0, 0.5, Lc, Tt, ti(q), ti(ch), ti(iD))
+    torch.cuda.synchronize()
+    ref = _compact_ref(T, ctx, c, lam)
+    assert rel(Lc.cpu().numpy(), ref) < 1e-10
+    sel = ref[ch, q, iD] * lam / 0.5
+    want = np.stack([sel.real, sel.imag], axis=-1).reshape(len(q), 2 * no4)
+    assert rel(Tt.cpu().numpy(), want) < 1e-6
+    assert abs(mx / (np.abs(want).max() * 0.5) - 1) < 1e-6
+
+
+def test_surrogate_loops_are_the_network(T):
+    c = _hub5()
+    ctx = _ctx(T, c)
+    no4 = ctx.n_o ** 4
+    sizes = [11 + ctx.n_dR, 64, 64, 64, 2 * no4]
+    p = mlp_init(sizes, seed=8)
+    net = T.Mlp(sizes, p)
+    T.tufrg_sur_attach(ctx, net, 1.0, 2.5)
+    lam = 0.6
+    Lc = torch.zeros((2, ctx.Nq, ctx.n_dR, no4), dtype=torch.complex128, device=dev())
+    T.tufrg_sur_loops(ctx, lam, Lc)
+    torch.cuda.synchronize()
+    nb = 2 * ctx.Nq * ctx.n_dR
+    b = np.arange(nb)
+    X = omlp.features((b // ctx.n_dR) % ctx.Nq, c["Lq"], lam, b // (ctx.n_dR * ctx.Nq), b % ctx.n_dR, ctx.n_dR)
+    Y, _, _ = omlp.forward(p, sizes, X)
+    Y = Y.reshape(nb, no4, 2) * 2.5 / lam
+    ref = (Y[..., 0] + 1j * Y[..., 1]).reshape(2, ctx.Nq, ctx.n_dR, no4)
+    assert rel(Lc.cpu().numpy(), ref) < 1e-5
+    with pytest.raises(T.TufrgError):
+        T.tufrg_sur_attach(ctx, T.Mlp([5, 8, 2 * no4]), 1.0, 1.0)
+
+
+def _flow(T, ctx, **kw):
+    P = torch.zeros((ctx.Nq, ctx.B, ctx.B), dtype=torch.complex128, device=dev())
+    C = torch.zeros_like(P)
+    r = T.tufrg_flow(ctx, P, C, 10.0, 1.0, n_steps=10, v_max=1e30, **kw)
+    torch.cuda.synchronize()
+    return r, P.cpu().numpy(), C.cpu().numpy()
+
+
+def test_untrained_surrogate_falls_back_to_the_plain_flow(T):
+    c = _hub5()
+    ctx = _ctx(T, c)
+    sizes = [11 + ctx.n_dR, 32, 32, 32, 2 * ctx.n_o ** 4]
+    net = T.Mlp(sizes, mlp_init(sizes, seed=2))
+    T.tufrg_sur_attach(ctx, net, 1.0, 1.0)
+    r0, P0, C0 = _flow(T, ctx)
+    r1, P1, C1 = _flow(T, ctx, surrogate=True, sample_frac=0.2, sur_tol=1e-3)
+    assert r0["n_plain"] == r0["n_rhs"] and r0["n_surrogate"] == 0
+    assert r1["n_fallback"] == r1["n_rhs"] == r1["n_plain"] and r1["n_surrogate"] == 0
+    assert r1["max_sample_err"] > 1e-3
+    # fallback recomputes the plain loops with the same kernels: identical states
+    assert np.array_equal(P0, P1) and np.array_equal(C0, C1)
+    r2, P2, _ = _flow(T, ctx, surrogate=True, sample_frac=0.2, sur_tol=1e-3, plain_above=-1.0)
+    assert r2["n_plain"] == r2["n_rhs"] and r2["n_fallback"] == 0 and np.array_equal(P0, P2)
+
+
+def test_trained_surrogate_replaces_plain_loops(T):
+    """Trained on the loops of the flow's own scale grid, the network supplies
+    the loops of most right-hand sides; the final couplings stay close to the
+    plain flow.  This is what the network gains over the plain method."""
+    c = _hub5()
+    ctx = _ctx(T, c)
+    no4 = ctx.n_o ** 4
+    nb = 2 * ctx.Nq * ctx.n_dR
+    lams = 10.0 * 0.1 ** (np.arange(10) / 10)
+    sizes = [11 + ctx.n_dR, 256, 256, 256, 2 * no4]
+    X = torch.zeros((len(lams) * nb, sizes[0]), dtype=torch.float32, device=dev())
+    Y = torch.zeros((len(lams) * nb, sizes[-1]), dtype=torch.float32, device=dev())
+    Lc = torch.zeros((2, ctx.Nq, ctx.n_dR, no4), dtype=torch.complex128, device=dev())
+    ymax = 0.0
+    for i, lam in enumerate(lams):
+        T.tufrg_loops_compact(ctx, lam, 1, Lc)
+        ymax = max(ymax, T.tufrg_sur_targets(ctx, nb, lam, 1.0, 1.0, Lc, Y[i * nb:(i + 1) * nb]))
+    for i, lam in enumerate(lams):
+        T.tufrg_loops_compact(ctx, lam, 1, Lc)
+        T.tufrg_sur_features(ctx, nb, lam, X[i * nb:(i + 1) * nb])
+        T.tufrg_sur_targets(ctx, nb, lam, 1.0, ymax, Lc, Y[i * nb:(i + 1) * nb])
+    net = T.Mlp(sizes, mlp_init(sizes, seed=3))
+    for lr in (1e-3, 3e-4, 1e-4):
+        T.tufrg_mlp_train(net, X, Y, batch=256, epochs=150, lr=lr, seed=4)
+    T.tufrg_sur_attach(ctx, net, 1.0, ymax)
+    r0, P0, C0 = _flow(T, ctx)
+    r1, P1, C1 = _flow(T, ctx, surrogate=True, sample_frac=0.2, sur_tol=2e-2)
+    print("surrogate flow:", r1)
+    assert r1["n_surrogate"] >= r1["n_rhs"] // 2
+    err = max(rel(P1, P0), rel(C1, C0))
+    print("relative error of the couplings vs the plain flow:", err)
+    assert err < 2e-2

@@ -105,6 +105,137 @@ def cpu_baseline(w, n_sample=4):
                       f"projections of all q charged pro rata; {t_eff:.1f} s of CPU time"}
 
 
+def surrogate_leg(T, torch, ctx, P, C, P64, C64, dp, w, K, t_plain_step, n_lam=24, n_rows=200000,
+                  epochs=(40, 40, 40)):
+    """Loop surrogate: train the network on plain loops at n_lam scales spread
+    over the flow range (random blocks, at most n_rows rows), then run the
+    timed Euler steps and the production Dormand-Prince flow with the surrogate
+    (5 % of the q_x rows recomputed plainly per right-hand side, fallback above
+    the sampled-error tolerance or coupling 20), each compared with its
+    FP64-plain counterpart."""
+    import numpy as np
+
+    from synth import mlp_init, mlp_shape
+
+    dev = torch.device("cuda:0")
+    no4 = ctx.n_o ** 4
+    nb = 2 * ctx.Nq * ctx.n_dR
+    per = min(nb, n_rows // n_lam)
+    lams = np.exp(np.linspace(np.log(w["lam0"]), np.log(w["lam_end"]), n_lam))
+    sizes = mlp_shape(11 + ctx.n_dR, 256, 2 * no4)
+    rng = np.random.default_rng(3)
+    t0 = time.perf_counter()
+    X = torch.zeros((n_lam * per, sizes[0]), dtype=torch.float32, device=dev)
+    Y = torch.zeros((n_lam * per, sizes[-1]), dtype=torch.float32, device=dev)
+    Lc = torch.zeros((2, ctx.Nq, ctx.n_dR, no4), dtype=torch.complex128, device=dev)
+    Yall = torch.zeros((nb, sizes[-1]), dtype=torch.float32, device=dev)
+    scales = []
+    for i, lam in enumerate(lams):
+        b = rng.choice(nb, size=per, replace=False)
+        q, ch, iD = ((b // ctx.n_dR) % ctx.Nq, b // (ctx.n_dR * ctx.Nq), b % ctx.n_dR)
+        q, ch, iD = (torch.from_numpy(a.astype(np.int32)).to(dev) for a in (q, ch, iD))
+        T.tufrg_loops_compact(ctx, lam, 1, Lc)
+        # scale of this Lambda: the largest |Lc| over all blocks
+        scales.append(T.tufrg_sur_targets(ctx, nb, 1.0, Lc, Yall))
+        T.tufrg_sur_features(ctx, per, lam, X[i * per:(i + 1) * per], q, ch, iD)
+        T.tufrg_sur_targets(ctx, per, scales[-1], Lc, Y[i * per:(i + 1) * per], q, ch, iD)
+    del Yall
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = T.Mlp(sizes, mlp_init(sizes, seed=3))
+    t0 = time.perf_counter()
+    loss = None
+    for ep, lr in zip(epochs, (1e-3, 3e-4, 1e-4)):
+        loss = T.tufrg_mlp_train(net, X, Y, batch=2048, epochs=ep, lr=lr, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    T.tufrg_sur_attach(ctx, net, lams, scales)
+    res = dict(train_rows=int(n_lam * per), train_scales=int(n_lam), train_data_seconds=t_data,
+               train_seconds=t_train, final_train_loss=loss, net=sizes)
+
+    def rel_to(Pr, Cr):
+        return max((P - Pr).abs().max().item() / Pr.abs().max().item(),
+                   (C - Cr).abs().max().item() / Cr.abs().max().item())
+
+    # (1) the headline step: Euler steps 10 -> 1 of the timed window, against
+    # the FP64-plain Euler flow over the same grid
+    ctx64 = T.Context.from_workload(w, precision="fp64")
+    Pe, Ce = torch.zeros_like(P), torch.zeros_like(C)
+    T.tufrg_flow(ctx64, Pe, Ce, w["lam0"], 1.0, n_steps=K, v_max=1e30)
+    ctx64.close()
+    for key, tol in (("euler_tol_1e-3", 1e-3), ("euler_tol_5e-2", 5e-2)):
+        P.zero_()
+        C.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = T.tufrg_flow(ctx, P, C, w["lam0"], 1.0, n_steps=K, v_max=1e30, surrogate=True, sample_frac=0.05,
+                         sur_tol=tol, plain_above=20.0, sample_seed=3)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[key] = dict(r, seconds=dt, ms_per_step=dt / K * 1e3, rel_err_vs_fp64_plain=rel_to(Pe, Ce),
+                        speedup_vs_fp32_plain_step=t_plain_step / (dt / K))
+    # (2) the production Dormand-Prince flow 10 -> 1e-4 at the stated tolerance
+    P.zero_()
+    C.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = T.tufrg_flow(ctx, P, C, w["lam0"], w["lam_end"], n_steps=0, rtol=w["rtol"], atol=w["atol"],
+                     v_max=w["v_max"], max_steps=400, surrogate=True, sample_frac=0.05, sur_tol=1e-3,
+                     plain_above=20.0, sample_seed=3)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e = dict(r, seconds=dt, flow_steps_per_s=r["n_steps"] / dt, rhs_per_s=r["n_rhs"] / dt,
+             speedup_vs_fp32_plain=dp["fp32"]["seconds"] / dt, speedup_vs_fp64_plain=dp["fp64"]["seconds"] / dt)
+    if r["n_steps"] == dp["fp64"]["n_steps"]:
+        e["rel_err_vs_fp64_plain"] = rel_to(P64, C64)
+    res["dp54_tol_1e-3"] = e
+    T.tufrg_sur_attach(ctx, None)
+    net.close()
+    return res
+
+
+def batch_bench(T, torch, K, W):
+    """32 independent Rashba/Hubbard instances of uneven size (seed 2), FP32
+    loops and products, lockstep Euler steps 10 -> 1 through tufrg_batch_flow;
+    the same batch on one stream for comparison."""
+    from synth.workloads import batch_instances
+
+    dev = torch.device("cuda:0")
+    ws = batch_instances(32, seed=2, n_ref=12)
+    out = {}
+    for n_streams in (4, 1):
+        b = T.Batch(ws, precision="fp32", n_streams=n_streams)
+        Ps, Cs = [], []
+        for d in b.dims:
+            Ps.append(torch.zeros((d["Nq"], d["B"], d["B"]), dtype=torch.complex128, device=dev))
+            Cs.append(torch.zeros_like(Ps[-1]))
+        if W > 0:
+            T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=W, v_max=1e30)
+        for x in Ps + Cs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=K, v_max=1e30)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        entries = sum(2.0 * d["Nq"] * d["B"] ** 2 for d in b.dims)
+        out[n_streams] = dict(seconds=dt, value=entries * K / dt, ms_per_step=dt / K * 1e3,
+                              steps=min(r["n_steps"] for r in res))
+        b.close()
+    best = out[4]
+    return {
+        "metric": METRIC, "value": best["value"], "unit": "loop entries/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": best["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "rashba_batch32", "instances": len(ws),
+                   "Lq": sorted({w["Lq"] for w in ws}), "n_ff": sorted({len(w["ff"]) for w in ws}),
+                   "n_ref": 12, "step": "lockstep Euler step of every instance", "parallelism": "single GPU"},
+        "flow_steps_per_s": K / best["seconds"],
+        "one_stream": out[1], "speedup_4_streams_vs_1": out[1]["seconds"] / best["seconds"],
+        "roofline": None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +249,7 @@ def main():
     ap.add_argument("--workload", default=WORKLOAD,
                     help="synthetic workload (the headline line uses the default)")
     ap.add_argument("--no-dp", action="store_true", help="skip the Dormand-Prince flows")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-assisted flow")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the q-sharded multi-GPU "
@@ -141,8 +273,11 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}))
         return
-    w = workload(args.workload)
     K, W = args.steps, args.warmup
+    if args.workload == "rashba_batch32":
+        print(json.dumps(batch_bench(T, torch, K, W)))
+        return
+    w = workload(args.workload)
     lam0, lam_mid = 10.0, 1.0
 
     def make(prec):
@@ -225,6 +360,8 @@ def main():
         if dp["fp64"]["diverged"] and dp["fp32"]["diverged"]:
             dp["lambda_c_rel_err"] = abs(dp["fp32"]["lambda_c"] / dp["fp64"]["lambda_c"] - 1.0)
         out["dp54_flow"] = dp
+    if not args.no_extras and not args.no_dp and not args.no_surrogate:
+        out["surrogate_flow"] = surrogate_leg(T, torch, ctx32, P32, C32, P64, C64, dp, w, K, dt32 / K)
     if not args.no_extras:
         ctx64.close()
     if not args.no_cpu:

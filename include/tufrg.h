@@ -168,7 +168,8 @@ typedef struct {
    * on sample_frac of the coarse q_x rows (at least one row; rows chosen by a
    * counter-based hash of sample_seed and the evaluation index) and replaces
    * the network's values there; if the sampled relative error
-   * max|L_net - L| / max|L| exceeds sur_tol, or the current max coupling
+   * max|L_net - L| / max(max|L|, s(Lambda)) (maxima over the sampled blocks,
+   * s the network's target scale) exceeds sur_tol, or the current max coupling
    * exceeds plain_above, the plain loops are used everywhere for that
    * evaluation.  surrogate = 0: plain loops only. */
   int32_t surrogate;
@@ -222,8 +223,10 @@ tufrg_status tufrg_timing_read(tufrg_ctx *ctx, int32_t timer, double *total_ms, 
  * after every layer but the last, GELU(x) = x Phi(x).  It maps the features
  *   [sin qx, cos qx, sin qy, cos qy, sin 2qx, cos 2qx, sin 2qy, cos 2qy,
  *    ln(Lambda)/5, ch == 0, ch == 1, one-hot(iD)]   (11 + n_dR values)
- * of a block to Lambda^power * Lc / y_scale, real and imaginary parts
- * interleaved (2 n_o^4 values).  The paper has no learned component; this
+ * of a block to Lc / s(Lambda), real and imaginary parts interleaved
+ * (2 n_o^4 values), where s(Lambda) is a positive scale given as a table
+ * (typically the largest |Lc| at that scale) and interpolated linearly in
+ * (ln Lambda, ln s).  The paper has no learned component; this
  * accelerates the loops of Sec. 3.1 / Sec. 4.2 and is always checked against
  * them during a flow (tufrg_flow_opts.surrogate). */
 
@@ -259,23 +262,44 @@ tufrg_status tufrg_mlp_adam_step(tufrg_mlp *net, const float *grad, float lr);
 tufrg_status tufrg_mlp_train(tufrg_mlp *net, int64_t n, const float *X, const float *T, int32_t batch,
                              int32_t epochs, float lr, uint64_t seed, double *last_epoch_loss);
 
-/* Features and targets of n blocks (q, ch, iD device int32 lists) at lambda;
- * with all three lists NULL the blocks are all 2 Nq n_dR in compact order.
- * X: device [n][11 + n_dR]; T: device [n][2 n_o^4] from Lc (device
- * [2][Nq][n_dR][n_o^4]) scaled by lambda^power / y_scale; max_abs (host, may
- * be NULL) returns the largest |lambda^power Lc| over the listed blocks. */
+/* Features and targets of n blocks (q, ch, iD device int32 lists); with all
+ * three lists NULL the blocks are all 2 Nq n_dR in compact order.
+ * X: device [n][11 + n_dR] at lambda; T: device [n][2 n_o^4] = Lc / scale
+ * from Lc (device [2][Nq][n_dR][n_o^4]); max_abs (host, may be NULL) returns
+ * the largest |Lc| over the listed blocks.  Invalid block indices give NaN
+ * targets. */
 tufrg_status tufrg_sur_features(tufrg_ctx *ctx, int64_t n, const int32_t *q, const int32_t *ch, const int32_t *iD,
                                 double lambda, float *X);
 tufrg_status tufrg_sur_targets(tufrg_ctx *ctx, int64_t n, const int32_t *q, const int32_t *ch, const int32_t *iD,
-                               double lambda, double power, double y_scale, const tufrg_c64 *Lc, float *T,
-                               double *max_abs);
-/* Attach a network (NULL detaches; the context does not own it) with the
- * scaling of its targets.  Input width must be 11 + n_dR, output 2 n_o^4, and
- * the network must have been created on the context's stream.  Invalid block
- * indices in tufrg_sur_targets give NaN targets. */
-tufrg_status tufrg_sur_attach(tufrg_ctx *ctx, tufrg_mlp *net, double power, double y_scale);
+                               double scale, const tufrg_c64 *Lc, float *T, double *max_abs);
+/* Attach a network (NULL detaches; the context does not own it) with its
+ * target scale table (host arrays of n_scale positive lambda and s values).
+ * Input width must be 11 + n_dR, output 2 n_o^4, and the network must have
+ * been created on the context's stream. */
+tufrg_status tufrg_sur_attach(tufrg_ctx *ctx, tufrg_mlp *net, int32_t n_scale, const double *lambda,
+                              const double *scale);
 /* Compact loops of both channels from the attached network (as tufrg_loops_compact). */
 tufrg_status tufrg_sur_loops(tufrg_ctx *ctx, double lambda, tufrg_c64 *Lc);
+
+/* ---------------------------------------------------------------------------
+ * Batches of independent instances (several models, form-factor sets and
+ * meshes at once).  Each instance is a context as above; the batch runs them
+ * on n_streams concurrent streams (default priority) and steps all of them in
+ * lockstep on one Euler grid, with one host synchronisation per step for all
+ * stop tests.  An instance that diverges stops; the others continue. */
+typedef struct tufrg_batch tufrg_batch;
+tufrg_status tufrg_batch_create(int32_t n_inst, const tufrg_model *models, const tufrg_setup *setups,
+                                int32_t n_streams, tufrg_batch **out);
+tufrg_status tufrg_batch_destroy(tufrg_batch *batch);
+const char *tufrg_batch_last_error(const tufrg_batch *batch);
+tufrg_status tufrg_batch_dims(const tufrg_batch *batch, int32_t inst, int32_t *B, int32_t *Nq, int32_t *Nf,
+                              int32_t *n_dR);
+/* P[i], C[i]: device [Nq_i][B_i][B_i] of instance i, integrated in place;
+ * results[i] per instance.  opts->n_steps must be > 0 (Euler) and
+ * opts->surrogate 0; the callback is not used.  The call synchronises the
+ * device before it starts and all its streams when it returns. */
+tufrg_status tufrg_batch_flow(tufrg_batch *batch, const tufrg_flow_opts *opts, tufrg_c64 *const *P,
+                              tufrg_c64 *const *C, tufrg_flow_result *results);
 
 #ifdef __cplusplus
 }

@@ -10,8 +10,9 @@ possible:
   difference vector index iD of nD):
     [sin qx, cos qx, sin qy, cos qy, sin 2qx, cos 2qx, sin 2qy, cos 2qy,
      ln(Lambda) / 5, c == 0, c == 1, one-hot(iD)]       (11 + nD values)
-* target: Lambda^p * Lc(q)[dR] / y_scale, real and imaginary parts interleaved
-  in the compact entry order (2 n_o^4 values);
+* target: Lc(q)[dR] / s(Lambda), real and imaginary parts interleaved in the
+  compact entry order (2 n_o^4 values), with s(Lambda) a positive scale table
+  interpolated linearly in (ln Lambda, ln s) and constant beyond its ends;
 * network: affine layers with GELU(x) = x Phi(x) (Phi the standard normal
   distribution function) after every layer but the last;
 * loss: mean of squared errors over batch and outputs;
@@ -51,9 +52,12 @@ def features(q_idx, Lq, lam, ch, iD, nD):
     return X
 
 
-def target_scale(lam, power):
-    """Factor Lambda^power applied to loop blocks before division by y_scale."""
-    return np.asarray(lam, dtype=np.float64) ** power
+def scale_interp(lam, lam_tab, s_tab):
+    """s(Lambda) from the table: piecewise linear in (ln Lambda, ln s)."""
+    x = np.log(np.asarray(lam_tab, dtype=np.float64))
+    y = np.log(np.asarray(s_tab, dtype=np.float64))
+    o = np.argsort(x)
+    return np.exp(np.interp(np.log(lam), x[o], y[o]))
 
 
 def unpack(params, sizes):

@@ -123,17 +123,31 @@ hipError_t launch_gelu_bwd(long long n, const float *Z, float *dA, hipStream_t s
   return hipGetLastError();
 }
 
-// db[o] = sum_r dZ[r][o]
-__global__ void colsum_kernel(int rows, int cols, const float *__restrict__ dZ, float *__restrict__ db) {
+// db[o] = sum_r dZ[r][o]: partial sums over chunks of CS rows (one thread per
+// column and chunk), then a fixed-order sum of the chunks
+constexpr int CS = 64;
+
+__global__ void colsum_part_kernel(int rows, int cols, const float *__restrict__ dZ, float *__restrict__ part) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x, ck = blockIdx.y;
+  if (o >= cols) return;
+  const int r0 = ck * CS, r1 = min(rows, r0 + CS);
+  float s = 0.f;
+  for (int r = r0; r < r1; ++r) s += dZ[(size_t)r * cols + o];
+  part[(size_t)ck * cols + o] = s;
+}
+
+__global__ void colsum_final_kernel(int nck, int cols, const float *__restrict__ part, float *__restrict__ db) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o >= cols) return;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += dZ[(size_t)r * cols + o];
+  for (int k = 0; k < nck; ++k) s += part[(size_t)k * cols + o];
   db[o] = s;
 }
 
-hipError_t launch_colsum(int rows, int cols, const float *dZ, float *db, hipStream_t st) {
-  hipLaunchKernelGGL(colsum_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, rows, cols, dZ, db);
+hipError_t launch_colsum(int rows, int cols, const float *dZ, float *part, float *db, hipStream_t st) {
+  const int nck = (rows + CS - 1) / CS;
+  hipLaunchKernelGGL(colsum_part_kernel, dim3((cols + 63) / 64, nck), dim3(64), 0, st, rows, cols, dZ, part);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, nck, cols, part, db);
   return hipGetLastError();
 }
 

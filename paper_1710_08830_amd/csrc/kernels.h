@@ -75,7 +75,8 @@ hipError_t launch_scale(long long n, const double *x, double s, double *y, hipSt
 hipError_t launch_gemm_f32(int M, int N, int K, const float *A, int lda, int tA, const float *B, int ldb, int tB,
                            const float *bias, int epi, float *C, int ldc, float *Z, hipStream_t st);
 hipError_t launch_gelu_bwd(long long n, const float *Z, float *dA, hipStream_t st);
-hipError_t launch_colsum(int rows, int cols, const float *dZ, float *db, hipStream_t st);
+// part: workspace of ceil(rows / 64) * cols floats
+hipError_t launch_colsum(int rows, int cols, const float *dZ, float *part, float *db, hipStream_t st);
 hipError_t launch_mse_grad(long long n, const float *Y, const float *T, float *dY, double *loss, hipStream_t st);
 hipError_t launch_adam(long long n, float *p, const float *g, float *m, float *v, float lr, float b1, float b2,
                        float eps, int t, hipStream_t st);

@@ -24,7 +24,7 @@ struct tufrg_mlp {
   // workspaces for a chunk of rows
   int cap = 0;
   std::vector<float *> act, pre;  // per hidden layer [cap][width]
-  float *d_y = nullptr, *d_dy = nullptr, *d_da = nullptr;
+  float *d_y = nullptr, *d_dy = nullptr, *d_da = nullptr, *d_part = nullptr;
   double *d_loss = nullptr, *h_loss = nullptr;
   int *d_idx = nullptr, *h_idx = nullptr;
   long long idx_cap = 0;
@@ -100,6 +100,7 @@ tufrg_status reserve(tufrg_mlp *m, int rows) {
   free_one(m, m->d_y);
   free_one(m, m->d_dy);
   free_one(m, m->d_da);
+  free_one(m, m->d_part);
   m->act.clear();
   m->pre.clear();
   const int L = (int)m->sizes.size() - 1;
@@ -113,6 +114,7 @@ tufrg_status reserve(tufrg_mlp *m, int rows) {
   MTRY(malloc_d(m, &m->d_y, (size_t)rows * m->sizes[L]));
   MTRY(malloc_d(m, &m->d_dy, (size_t)rows * m->maxw));
   MTRY(malloc_d(m, &m->d_da, (size_t)rows * m->maxw));
+  MTRY(malloc_d(m, &m->d_part, (size_t)((rows + 63) / 64) * m->maxw));
   m->cap = rows;
   return TUFRG_OK;
 }
@@ -147,7 +149,7 @@ tufrg_status loss_grad_internal(tufrg_mlp *m, int n, const float *X, const float
     const float *ain = l == 0 ? X : m->act[l - 1];
     // dW[o][i] = sum_r dz[r][o] a[r][i]
     MHIP(m, launch_gemm_f32(no, ni, n, dz, no, 1, ain, ni, 0, nullptr, 0, grad + m->woff[l], ni, nullptr, m->st));
-    MHIP(m, launch_colsum(n, no, dz, grad + m->boff[l], m->st));
+    MHIP(m, launch_colsum(n, no, dz, m->d_part, grad + m->boff[l], m->st));
     if (l > 0) {
       // dA[r][i] = sum_o dz[r][o] W[o][i], then times GELU'(z) of layer l - 1
       MHIP(m, launch_gemm_f32(n, ni, no, dz, no, 0, m->d_p + m->woff[l], ni, 0, nullptr, 0, spare, ni, nullptr,

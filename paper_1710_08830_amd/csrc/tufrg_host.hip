@@ -78,7 +78,7 @@ struct tufrg_ctx {
   Timer timers[TUFRG_TIMER_COUNT];
   // loop surrogate
   tufrg_mlp *sur = nullptr;
-  double sur_power = 1.0, sur_yscale = 1.0;
+  std::vector<double> sur_lnlam, sur_lns;  // target scale table, ln Lambda ascending -> ln s
   float *d_surX = nullptr, *d_surY = nullptr;  // features of all blocks, network rows of a chunk
   double *d_samp = nullptr;                    // plain loops of sampled q_x rows, [row][2][Lq][nD][no4]
   int samp_rows = 0;
@@ -500,6 +500,18 @@ static tufrg_status compute_loops(tufrg_ctx *c, double lam, int deriv, int ch_fi
   return loops_range(c, lam, deriv, ch_first, n_ch, 0, c->Nq, dst);
 }
 
+// target scale s(Lambda): the table interpolated linearly in (ln Lambda, ln s),
+// constant beyond its ends
+static double sur_scale_at(const tufrg_ctx *c, double lam) {
+  const std::vector<double> &x = c->sur_lnlam, &y = c->sur_lns;
+  const double l = std::log(lam);
+  if (x.size() == 1 || l <= x.front()) return std::exp(y.front());
+  if (l >= x.back()) return std::exp(y.back());
+  const size_t i = std::upper_bound(x.begin(), x.end(), l) - x.begin();
+  const double t = (l - x[i - 1]) / (x[i] - x[i - 1]);
+  return std::exp(y[i - 1] + t * (y[i] - y[i - 1]));
+}
+
 // network loops of all 2 Nq nD blocks into dst (compact, both channels)
 static const long long SUR_CHUNK = 16384;
 static tufrg_status sur_loops_internal(tufrg_ctx *c, double lam, double *dst) {
@@ -511,7 +523,7 @@ static tufrg_status sur_loops_internal(tufrg_ctx *c, double lam, double *dst) {
   }
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_SURROGATE));
   HIPCHK(c, launch_sur_features(nb, nullptr, nullptr, nullptr, c->Lq, c->nD, lam, c->d_surX, c->st));
-  const double s = c->sur_yscale / std::pow(lam, c->sur_power);
+  const double s = sur_scale_at(c, lam);
   for (long long b0 = 0; b0 < nb; b0 += SUR_CHUNK) {
     const long long rows = std::min(SUR_CHUNK, nb - b0);
     TRY(mlp_forward_internal(c->sur, rows, c->d_surX + b0 * nin, c->d_surY));
@@ -569,7 +581,10 @@ static tufrg_status surrogate_loops(tufrg_ctx *c, double lam) {
   double dmax, rmax;
   std::memcpy(&dmax, &c->h_sbits[0], sizeof(double));
   std::memcpy(&rmax, &c->h_sbits[1], sizeof(double));
-  const double err = rmax > 0.0 ? dmax / rmax : (dmax > 0.0 ? INFINITY : 0.0);
+  // relative to the loop scale at lam: the larger of the sampled plain maximum
+  // and the network's target scale s(lam)
+  const double ref = std::max(rmax, sur_scale_at(c, lam));
+  const double err = ref > 0.0 ? dmax / ref : (dmax > 0.0 ? INFINITY : 0.0);
   r->max_sample_err = std::max(r->max_sample_err, err);
   if (!(err <= o->sur_tol)) {
     TRY(loops_range(c, lam, 1, 0, 2, 0, c->Nq, c->d_loop));
@@ -720,14 +735,13 @@ extern "C" tufrg_status tufrg_sur_features(tufrg_ctx *c, int64_t n, const int32_
 }
 
 extern "C" tufrg_status tufrg_sur_targets(tufrg_ctx *c, int64_t n, const int32_t *q, const int32_t *ch,
-                                         const int32_t *iD, double lambda, double power, double y_scale,
-                                         const tufrg_c64 *Lc, float *T, double *max_abs) {
+                                         const int32_t *iD, double scale, const tufrg_c64 *Lc, float *T,
+                                         double *max_abs) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
   TRY(check_blocks(c, n, q, ch, iD));
-  if (!(lambda > 0.0) || !(y_scale > 0.0)) return fail(c, TUFRG_E_INVAL, "lambda and y_scale must be positive");
+  if (!(scale > 0.0) || !std::isfinite(scale)) return fail(c, TUFRG_E_INVAL, "scale must be positive");
   if (n > 0 && (!is_device_ptr(Lc) || !is_device_ptr(T))) return fail(c, TUFRG_E_INVAL, "Lc, T must be device pointers");
-  const double s = std::pow(lambda, power) / y_scale;
-  HIPCHK(c, launch_sur_targets(n, q, ch, iD, c->Nq, c->nD, c->no4, s, (const double *)Lc, T, c->st));
+  HIPCHK(c, launch_sur_targets(n, q, ch, iD, c->Nq, c->nD, c->no4, 1.0 / scale, (const double *)Lc, T, c->st));
   if (max_abs) {
     HIPCHK(c, hipMemsetAsync(c->d_sbits, 0, sizeof(unsigned long long), c->st));
     HIPCHK(c, launch_absmax_f32(n * 2 * c->no4, T, (unsigned int *)c->d_sbits, c->st));
@@ -736,12 +750,13 @@ extern "C" tufrg_status tufrg_sur_targets(tufrg_ctx *c, int64_t n, const int32_t
     float f;
     const unsigned int u = (unsigned int)(c->h_sbits[0] & 0xffffffffu);
     std::memcpy(&f, &u, sizeof(f));
-    *max_abs = (double)f * y_scale;
+    *max_abs = (double)f * scale;
   }
   return TUFRG_OK;
 }
 
-extern "C" tufrg_status tufrg_sur_attach(tufrg_ctx *c, tufrg_mlp *net, double power, double y_scale) {
+extern "C" tufrg_status tufrg_sur_attach(tufrg_ctx *c, tufrg_mlp *net, int32_t n_scale, const double *lam_tab,
+                                        const double *scale_tab) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
   if (!net) {
     c->sur = nullptr;
@@ -749,11 +764,24 @@ extern "C" tufrg_status tufrg_sur_attach(tufrg_ctx *c, tufrg_mlp *net, double po
   }
   if (mlp_n_in(net) != 11 + c->nD || mlp_n_out(net) != 2 * c->no4)
     return fail(c, TUFRG_E_INVAL, "network widths must be 11 + n_dR inputs and 2 n_o^4 outputs");
-  if (!(y_scale > 0.0) || !std::isfinite(power)) return fail(c, TUFRG_E_INVAL, "bad target scaling");
   if (mlp_stream(net) != c->st) return fail(c, TUFRG_E_INVAL, "network and context must share one stream");
+  if (n_scale < 1 || !lam_tab || !scale_tab) return fail(c, TUFRG_E_INVAL, "need a scale table");
+  std::vector<std::pair<double, double>> tab;
+  for (int i = 0; i < n_scale; ++i) {
+    if (!(lam_tab[i] > 0.0) || !(scale_tab[i] > 0.0) || !std::isfinite(lam_tab[i]) || !std::isfinite(scale_tab[i]))
+      return fail(c, TUFRG_E_INVAL, "scale table entries must be positive and finite");
+    tab.emplace_back(std::log(lam_tab[i]), std::log(scale_tab[i]));
+  }
+  std::sort(tab.begin(), tab.end());
+  for (size_t i = 1; i < tab.size(); ++i)
+    if (tab[i].first == tab[i - 1].first) return fail(c, TUFRG_E_INVAL, "repeated scale in the table");
+  c->sur_lnlam.clear();
+  c->sur_lns.clear();
+  for (auto &t : tab) {
+    c->sur_lnlam.push_back(t.first);
+    c->sur_lns.push_back(t.second);
+  }
   c->sur = net;
-  c->sur_power = power;
-  c->sur_yscale = y_scale;
   return TUFRG_OK;
 }
 
@@ -950,5 +978,166 @@ extern "C" tufrg_status tufrg_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg
     if (std::fabs(h) < 1e-12) return fail(c, TUFRG_E_STEPSIZE, "step size underflow");
   }
   if (l - l_end <= 1e-14) res->lambda_stop = o->lambda_end;
+  return TUFRG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches of independent instances (lockstep Euler)
+
+struct tufrg_batch {
+  std::vector<tufrg_ctx *> ctx;
+  std::vector<hipStream_t> streams;  // owned, default priority
+  std::string err;
+};
+
+static thread_local std::string g_batch_err;
+
+static tufrg_status bfail(tufrg_batch *b, tufrg_status s, const std::string &m) {
+  if (b)
+    b->err = m;
+  else
+    g_batch_err = m;
+  return s;
+}
+
+static void batch_free(tufrg_batch *b) {
+  for (tufrg_ctx *c : b->ctx) tufrg_destroy(c);
+  for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
+  b->ctx.clear();
+  b->streams.clear();
+}
+
+extern "C" const char *tufrg_batch_last_error(const tufrg_batch *b) {
+  return b ? b->err.c_str() : g_batch_err.c_str();
+}
+
+extern "C" tufrg_status tufrg_batch_create(int32_t n_inst, const tufrg_model *models, const tufrg_setup *setups,
+                                           int32_t n_streams, tufrg_batch **out) {
+  if (!out) return bfail(nullptr, TUFRG_E_INVAL, "null output pointer");
+  *out = nullptr;
+  if (n_inst < 1 || !models || !setups) return bfail(nullptr, TUFRG_E_INVAL, "need n_inst >= 1 models and setups");
+  if (n_streams < 1 || n_streams > 8) return bfail(nullptr, TUFRG_E_INVAL, "n_streams must be in [1, 8]");
+  tufrg_batch *b = new tufrg_batch();
+  for (int i = 0; i < std::min(n_streams, n_inst); ++i) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      batch_free(b);
+      delete b;
+      return bfail(nullptr, TUFRG_E_HIP, "hipStreamCreate failed");
+    }
+    b->streams.push_back(s);
+  }
+  for (int i = 0; i < n_inst; ++i) {
+    tufrg_ctx *c = nullptr;
+    const tufrg_status s = tufrg_create(&models[i], &setups[i], b->streams[i % b->streams.size()], &c);
+    if (s != TUFRG_OK) {
+      const std::string m = "instance " + std::to_string(i) + ": " + tufrg_last_error(nullptr);
+      batch_free(b);
+      delete b;
+      return bfail(nullptr, s, m);
+    }
+    b->ctx.push_back(c);
+  }
+  *out = b;
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_batch_destroy(tufrg_batch *b) {
+  if (!b) return TUFRG_OK;
+  batch_free(b);
+  delete b;
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_batch_dims(const tufrg_batch *b, int32_t inst, int32_t *B, int32_t *Nq, int32_t *Nf,
+                                         int32_t *n_dR) {
+  if (!b || inst < 0 || inst >= (int)b->ctx.size()) return bfail(nullptr, TUFRG_E_INVAL, "bad instance");
+  return tufrg_dims(b->ctx[inst], B, Nq, Nf, n_dR);
+}
+
+extern "C" tufrg_status tufrg_batch_flow(tufrg_batch *b, const tufrg_flow_opts *o, tufrg_c64 *const *P,
+                                         tufrg_c64 *const *C, tufrg_flow_result *res) {
+  if (!b) return bfail(nullptr, TUFRG_E_INVAL, "null batch");
+  if (!o || !P || !C || !res) return bfail(b, TUFRG_E_INVAL, "null argument");
+  if (o->n_steps <= 0) return bfail(b, TUFRG_E_UNSUPPORTED, "batched flows are lockstep Euler (n_steps > 0)");
+  if (o->surrogate) return bfail(b, TUFRG_E_UNSUPPORTED, "no surrogate in batched flows");
+  if (!(o->lambda0 > 0.0) || !(o->lambda_end > 0.0) || !(o->lambda_end < o->lambda0))
+    return bfail(b, TUFRG_E_INVAL, "need lambda0 > lambda_end > 0");
+  const unsigned mask = o->channel_mask & 3u;
+  if (!mask) return bfail(b, TUFRG_E_INVAL, "channel_mask selects no channel");
+  const int n = (int)b->ctx.size();
+  for (int i = 0; i < n; ++i)
+    if (!is_device_ptr(P[i]) || !is_device_ptr(C[i])) return bfail(b, TUFRG_E_INVAL, "P, C must be device pointers");
+  auto inst_fail = [&](int i) {
+    return bfail(b, TUFRG_E_HIP, "instance " + std::to_string(i) + ": " + b->ctx[i]->err);
+  };
+  // the caller's writes to P, C are complete before the instances' streams start
+  if (hipDeviceSynchronize() != hipSuccess) {
+    (void)hipGetLastError();
+    return bfail(b, TUFRG_E_HIP, "hipDeviceSynchronize failed");
+  }
+  std::vector<char> active(n, 1);
+  std::vector<double> m_prev(n, 0.0), lam_prev(n, o->lambda0);
+  for (int i = 0; i < n; ++i) {
+    std::memset(&res[i], 0, sizeof(res[i]));
+    res[i].lambda_stop = o->lambda0;
+    bool bad = false;
+    if (state_max(b->ctx[i], (const double *)P[i], (const double *)C[i], &m_prev[i], &bad) != TUFRG_OK)
+      return inst_fail(i);
+    if (bad) return bfail(b, TUFRG_E_NONFINITE, "non-finite initial state of instance " + std::to_string(i));
+  }
+  const int ns = o->n_steps;
+  for (int s = 0; s < ns; ++s) {
+    const double l0 = o->lambda0 * std::pow(o->lambda_end / o->lambda0, (double)s / ns);
+    const double l1 = (s + 1 == ns) ? o->lambda_end : o->lambda0 * std::pow(o->lambda_end / o->lambda0, (double)(s + 1) / ns);
+    // enqueue every active instance, then one wait for all
+    for (int i = 0; i < n; ++i) {
+      if (!active[i]) continue;
+      tufrg_ctx *c = b->ctx[i];
+      double *Pi = (double *)P[i], *Ci = (double *)C[i];
+      const size_t ns_d = 2 * (size_t)c->B * c->B * c->Nq;
+      const long long ncx = (long long)c->B * c->B * c->Nq;
+      if (!c->d_dP && (dalloc(c, &c->d_dP, ns_d) != TUFRG_OK || dalloc(c, &c->d_dC, ns_d) != TUFRG_OK))
+        return bfail(b, TUFRG_E_NOMEM, "instance " + std::to_string(i) + ": " + c->err);
+      if (rhs_internal(c, l0, Pi, Ci, c->d_dP, c->d_dC, 1.0, mask) != TUFRG_OK) return inst_fail(i);
+      if (launch_clear_reduce(c->d_bits, c->d_flag, c->st) != hipSuccess ||
+          launch_axpy_max(ncx, Pi, l1 - l0, c->d_dP, Pi, c->d_bits, c->d_flag, c->st) != hipSuccess ||
+          launch_axpy_max(ncx, Ci, l1 - l0, c->d_dC, Ci, c->d_bits, c->d_flag, c->st) != hipSuccess ||
+          hipMemcpyAsync(c->h_bits, c->d_bits, sizeof(unsigned long long), hipMemcpyDeviceToHost, c->st) !=
+              hipSuccess ||
+          hipMemcpyAsync(c->h_flag, c->d_flag, sizeof(unsigned int), hipMemcpyDeviceToHost, c->st) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, TUFRG_E_HIP, "instance " + std::to_string(i) + ": launch failed");
+      }
+      res[i].n_rhs++;
+      res[i].n_plain++;
+    }
+    for (hipStream_t st : b->streams)
+      if (hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, TUFRG_E_HIP, "stream synchronisation failed");
+      }
+    for (int i = 0; i < n; ++i) {
+      if (!active[i]) continue;
+      tufrg_ctx *c = b->ctx[i];
+      double mx;
+      std::memcpy(&mx, &c->h_bits[0], sizeof(mx));
+      if (c->h_flag[0]) return bfail(b, TUFRG_E_NONFINITE, "non-finite state of instance " + std::to_string(i));
+      res[i].n_steps++;
+      res[i].lambda_stop = l1;
+      res[i].max_coupling = mx;
+      if (mx > o->v_max) {
+        res[i].diverged = 1;
+        res[i].lambda_c = lambda_c_interp(lam_prev[i], m_prev[i], l1, mx, o->v_max);
+        active[i] = 0;
+        continue;
+      }
+      if (o->max_steps > 0 && res[i].n_steps >= o->max_steps) active[i] = 0;
+      lam_prev[i] = l1;
+      m_prev[i] = mx;
+    }
+    if (std::none_of(active.begin(), active.end(), [](char a) { return a != 0; })) break;
+  }
   return TUFRG_OK;
 }

@@ -34,7 +34,8 @@ SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "t
            "tufrg_mlp_destroy", "tufrg_mlp_last_error", "tufrg_mlp_n_params", "tufrg_mlp_params",
            "tufrg_mlp_set_params", "tufrg_mlp_forward", "tufrg_mlp_loss_grad", "tufrg_mlp_adam_step",
            "tufrg_mlp_train", "tufrg_sur_features", "tufrg_sur_targets", "tufrg_sur_attach",
-           "tufrg_sur_loops"]
+           "tufrg_sur_loops", "tufrg_batch_create", "tufrg_batch_destroy", "tufrg_batch_last_error",
+           "tufrg_batch_dims", "tufrg_batch_flow"]
 TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE, TIMER_SURROGATE = 0, 1, 2, 3
 
 
@@ -111,16 +112,26 @@ _lib.tufrg_mlp_adam_step.argtypes = [_vp, _vp, ctypes.c_float]
 _lib.tufrg_mlp_train.argtypes = [_vp, ctypes.c_int64, _vp, _vp, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_float, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double)]
 _lib.tufrg_sur_features.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_double, _vp]
-_lib.tufrg_sur_targets.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_double, ctypes.c_double,
-                                   ctypes.c_double, _vp, _vp, ctypes.POINTER(ctypes.c_double)]
-_lib.tufrg_sur_attach.argtypes = [_vp, _vp, ctypes.c_double, ctypes.c_double]
+_lib.tufrg_sur_targets.argtypes = [_vp, ctypes.c_int64, _vp, _vp, _vp, ctypes.c_double, _vp, _vp,
+                                   ctypes.POINTER(ctypes.c_double)]
+_f64p = ctypes.POINTER(ctypes.c_double)
+_lib.tufrg_sur_attach.argtypes = [_vp, _vp, ctypes.c_int32, _f64p, _f64p]
 _lib.tufrg_sur_loops.argtypes = [_vp, ctypes.c_double, _vp]
+_lib.tufrg_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Model), ctypes.POINTER(Setup), ctypes.c_int32,
+                                    ctypes.POINTER(_vp)]
+_lib.tufrg_batch_destroy.argtypes = [_vp]
+_lib.tufrg_batch_last_error.argtypes = [_vp]
+_lib.tufrg_batch_last_error.restype = ctypes.c_char_p
+_lib.tufrg_batch_dims.argtypes = [_vp, ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4
+_lib.tufrg_batch_flow.argtypes = [_vp, ctypes.POINTER(FlowOpts), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                  ctypes.POINTER(FlowResult)]
 for _f in ("tufrg_create", "tufrg_destroy", "tufrg_dims", "tufrg_band_data", "tufrg_bubble",
            "tufrg_project", "tufrg_rhs", "tufrg_flow", "tufrg_timing", "tufrg_timing_read",
            "tufrg_loops_compact", "tufrg_dR", "tufrg_mlp_create", "tufrg_mlp_destroy",
            "tufrg_mlp_n_params", "tufrg_mlp_params", "tufrg_mlp_set_params", "tufrg_mlp_forward",
            "tufrg_mlp_loss_grad", "tufrg_mlp_adam_step", "tufrg_mlp_train", "tufrg_sur_features",
-           "tufrg_sur_targets", "tufrg_sur_attach", "tufrg_sur_loops"):
+           "tufrg_sur_targets", "tufrg_sur_attach", "tufrg_sur_loops", "tufrg_batch_create",
+           "tufrg_batch_destroy", "tufrg_batch_dims", "tufrg_batch_flow"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 
@@ -331,19 +342,85 @@ def tufrg_sur_features(ctx, n, lam, X, q=None, ch=None, iD=None):
                                    _ptr(X)), ctx.handle)
 
 
-def tufrg_sur_targets(ctx, n, lam, power, y_scale, Lc, T, q=None, ch=None, iD=None):
-    """Writes the scaled targets; returns max |lambda^power Lc| over the blocks."""
+def tufrg_sur_targets(ctx, n, scale, Lc, T, q=None, ch=None, iD=None):
+    """Writes the targets Lc / scale; returns max |Lc| over the blocks."""
     mx = ctypes.c_double()
-    _check(_lib.tufrg_sur_targets(ctx.handle, int(n), _opt(q), _opt(ch), _opt(iD), float(lam),
-                                  float(power), float(y_scale), _ptr(Lc), _ptr(T), ctypes.byref(mx)),
-           ctx.handle)
+    _check(_lib.tufrg_sur_targets(ctx.handle, int(n), _opt(q), _opt(ch), _opt(iD), float(scale),
+                                  _ptr(Lc), _ptr(T), ctypes.byref(mx)), ctx.handle)
     return mx.value
 
 
-def tufrg_sur_attach(ctx, net, power, y_scale):
-    _check(_lib.tufrg_sur_attach(ctx.handle, None if net is None else net.handle, float(power),
-                                 float(y_scale)), ctx.handle)
+def tufrg_sur_attach(ctx, net, lambdas=(1.0,), scales=(1.0,)):
+    """Attach net with its target scale table (None detaches)."""
+    lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+    sc = np.ascontiguousarray(scales, dtype=np.float64)
+    if lam.shape != sc.shape:
+        raise ValueError("scale table arrays differ in length")
+    _check(_lib.tufrg_sur_attach(ctx.handle, None if net is None else net.handle, len(lam),
+                                 lam.ctypes.data_as(_f64p), sc.ctypes.data_as(_f64p)), ctx.handle)
 
 
 def tufrg_sur_loops(ctx, lam, Lc):
     _check(_lib.tufrg_sur_loops(ctx.handle, float(lam), _ptr(Lc)), ctx.handle)
+
+
+class Batch:
+    """Owns a tufrg_batch of independent instances given as workload dicts
+    (keys as in synth.workloads) and a common arithmetic precision."""
+
+    def __init__(self, workloads, precision="fp32", n_streams=4):
+        n = len(workloads)
+        models, setups = (Model * n)(), (Setup * n)()
+        self._keep = []
+        for i, w in enumerate(workloads):
+            hop_R = np.ascontiguousarray(w["hop_R"], dtype=np.int32).reshape(-1, 2)
+            hop_t = np.ascontiguousarray(w["hop_t"], dtype=np.complex128)
+            V0 = np.ascontiguousarray(w["V0"], dtype=np.complex128)
+            ff = np.ascontiguousarray(w["ff"], dtype=np.int32).reshape(-1, 2)
+            self._keep.append((hop_R, hop_t, V0, ff))
+            models[i] = Model(hop_t.shape[1], hop_R.shape[0], hop_R.ctypes.data_as(_i32p),
+                              hop_t.ctypes.data_as(ctypes.POINTER(c64)), float(w["mu"]),
+                              V0.ctypes.data_as(ctypes.POINTER(c64)))
+            cut = {"temperature": CUT_TEMPERATURE, "omega": CUT_OMEGA}.get(w["cutoff"], w["cutoff"])
+            prec = {"fp64": FP64, "fp32": FP32}.get(precision, precision)
+            setups[i] = Setup(ff.shape[0], ff.ctypes.data_as(_i32p), int(w["Lq"]), int(w["n_ref"]), int(cut),
+                              int(prec))
+        h = ctypes.c_void_p()
+        st = _lib.tufrg_batch_create(n, models, setups, int(n_streams), ctypes.byref(h))
+        if st != TUFRG_OK:
+            raise TufrgError(st, _lib.tufrg_batch_last_error(None).decode(errors="replace"))
+        self.handle = h
+        self.n = n
+        self.dims = []
+        for i in range(n):
+            B, Nq, Nf, nD = (ctypes.c_int32() for _ in range(4))
+            self._check(_lib.tufrg_batch_dims(h, i, ctypes.byref(B), ctypes.byref(Nq), ctypes.byref(Nf),
+                                              ctypes.byref(nD)))
+            self.dims.append(dict(B=B.value, Nq=Nq.value, Nf=Nf.value, n_dR=nD.value))
+
+    def _check(self, status):
+        if status != TUFRG_OK:
+            raise TufrgError(status, _lib.tufrg_batch_last_error(self.handle).decode(errors="replace"))
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _lib.tufrg_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tufrg_batch_flow(batch, Ps, Cs, lambda0, lambda_end, n_steps, v_max=50.0, channel_mask=3, max_steps=0):
+    """Lockstep Euler flow of every instance (P, C in place); list of result dicts."""
+    n = batch.n
+    pp = (_vp * n)(*[_ptr(x) for x in Ps])
+    cp = (_vp * n)(*[_ptr(x) for x in Cs])
+    o = FlowOpts(float(lambda0), float(lambda_end), int(n_steps), 0.0, 0.0, 0.0, float(v_max),
+                 int(channel_mask), int(max_steps), STEP_CB(), None, 0, 0.0, 0.0, 0.0, 0)
+    res = (FlowResult * n)()
+    batch._check(_lib.tufrg_batch_flow(batch.handle, ctypes.byref(o), pp, cp, res))
+    return [r.as_dict() for r in res]

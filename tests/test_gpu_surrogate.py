@@ -173,11 +173,11 @@ def test_compact_loops_and_targets_match_oracle(T, case):
     q, ch, iD = _blocks(ctx, 2)
     ti = lambda a: torch.from_numpy(a).to(dev())  # noqa: E731
     Tt = torch.zeros((len(q), 2 * no4), dtype=torch.float32, device=dev())
-    mx = T.tufrg_sur_targets(ctx, len(q), lam, 1.0, 0.5, Lc, Tt, ti(q), ti(ch), ti(iD))
+    mx = T.tufrg_sur_targets(ctx, len(q), 0.5, Lc, Tt, ti(q), ti(ch), ti(iD))
     torch.cuda.synchronize()
     ref = _compact_ref(T, ctx, c, lam)
     assert rel(Lc.cpu().numpy(), ref) < 1e-10
-    sel = ref[ch, q, iD] * lam / 0.5
+    sel = ref[ch, q, iD] / 0.5
     want = np.stack([sel.real, sel.imag], axis=-1).reshape(len(q), 2 * no4)
     assert rel(Tt.cpu().numpy(), want) < 1e-6
     assert abs(mx / (np.abs(want).max() * 0.5) - 1) < 1e-6
@@ -190,7 +190,8 @@ def test_surrogate_loops_are_the_network(T):
     sizes = [11 + ctx.n_dR, 64, 64, 64, 2 * no4]
     p = mlp_init(sizes, seed=8)
     net = T.Mlp(sizes, p)
-    T.tufrg_sur_attach(ctx, net, 1.0, 2.5)
+    tab_l, tab_s = [2.0, 0.5, 0.1], [1.5, 2.5, 7.0]
+    T.tufrg_sur_attach(ctx, net, tab_l, tab_s)
     lam = 0.6
     Lc = torch.zeros((2, ctx.Nq, ctx.n_dR, no4), dtype=torch.complex128, device=dev())
     T.tufrg_sur_loops(ctx, lam, Lc)
@@ -199,11 +200,11 @@ def test_surrogate_loops_are_the_network(T):
     b = np.arange(nb)
     X = omlp.features((b // ctx.n_dR) % ctx.Nq, c["Lq"], lam, b // (ctx.n_dR * ctx.Nq), b % ctx.n_dR, ctx.n_dR)
     Y, _, _ = omlp.forward(p, sizes, X)
-    Y = Y.reshape(nb, no4, 2) * 2.5 / lam
+    Y = Y.reshape(nb, no4, 2) * omlp.scale_interp(lam, tab_l, tab_s)
     ref = (Y[..., 0] + 1j * Y[..., 1]).reshape(2, ctx.Nq, ctx.n_dR, no4)
     assert rel(Lc.cpu().numpy(), ref) < 1e-5
     with pytest.raises(T.TufrgError):
-        T.tufrg_sur_attach(ctx, T.Mlp([5, 8, 2 * no4]), 1.0, 1.0)
+        T.tufrg_sur_attach(ctx, T.Mlp([5, 8, 2 * no4]))
 
 
 def _flow(T, ctx, **kw):
@@ -219,7 +220,7 @@ def test_untrained_surrogate_falls_back_to_the_plain_flow(T):
     ctx = _ctx(T, c)
     sizes = [11 + ctx.n_dR, 32, 32, 32, 2 * ctx.n_o ** 4]
     net = T.Mlp(sizes, mlp_init(sizes, seed=2))
-    T.tufrg_sur_attach(ctx, net, 1.0, 1.0)
+    T.tufrg_sur_attach(ctx, net)
     r0, P0, C0 = _flow(T, ctx)
     r1, P1, C1 = _flow(T, ctx, surrogate=True, sample_frac=0.2, sur_tol=1e-3)
     assert r0["n_plain"] == r0["n_rhs"] and r0["n_surrogate"] == 0
@@ -244,18 +245,16 @@ def test_trained_surrogate_replaces_plain_loops(T):
     X = torch.zeros((len(lams) * nb, sizes[0]), dtype=torch.float32, device=dev())
     Y = torch.zeros((len(lams) * nb, sizes[-1]), dtype=torch.float32, device=dev())
     Lc = torch.zeros((2, ctx.Nq, ctx.n_dR, no4), dtype=torch.complex128, device=dev())
-    ymax = 0.0
+    scales = []
     for i, lam in enumerate(lams):
         T.tufrg_loops_compact(ctx, lam, 1, Lc)
-        ymax = max(ymax, T.tufrg_sur_targets(ctx, nb, lam, 1.0, 1.0, Lc, Y[i * nb:(i + 1) * nb]))
-    for i, lam in enumerate(lams):
-        T.tufrg_loops_compact(ctx, lam, 1, Lc)
+        scales.append(T.tufrg_sur_targets(ctx, nb, 1.0, Lc, Y[i * nb:(i + 1) * nb]))
         T.tufrg_sur_features(ctx, nb, lam, X[i * nb:(i + 1) * nb])
-        T.tufrg_sur_targets(ctx, nb, lam, 1.0, ymax, Lc, Y[i * nb:(i + 1) * nb])
+        T.tufrg_sur_targets(ctx, nb, scales[-1], Lc, Y[i * nb:(i + 1) * nb])
     net = T.Mlp(sizes, mlp_init(sizes, seed=3))
     for lr in (1e-3, 3e-4, 1e-4):
         T.tufrg_mlp_train(net, X, Y, batch=256, epochs=150, lr=lr, seed=4)
-    T.tufrg_sur_attach(ctx, net, 1.0, ymax)
+    T.tufrg_sur_attach(ctx, net, lams, scales)
     r0, P0, C0 = _flow(T, ctx)
     r1, P1, C1 = _flow(T, ctx, surrogate=True, sample_frac=0.2, sur_tol=2e-2)
     print("surrogate flow:", r1)

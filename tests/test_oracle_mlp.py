@@ -118,3 +118,16 @@ def test_adam_training_lowers_the_loss():
         _, g = mlp.loss_and_grad(p, sizes, X, T)
         p, m, v = mlp.adam_step(p, g, m, v, t, 3e-3)
     assert mlp.loss(p, sizes, X, T) < 0.5 * l0
+
+
+def test_scale_table_interpolation():
+    lam = np.array([10.0, 1.0, 0.1, 1e-3])
+    s = 3.0 * lam ** -1.5
+    # nodes are reproduced and a power law is exact between them
+    for l, v in zip(lam, s):
+        assert abs(mlp.scale_interp(l, lam, s) / v - 1) < 1e-14
+    for l in (5.0, 0.37, 2e-3):
+        assert abs(mlp.scale_interp(l, lam, s) / (3.0 * l ** -1.5) - 1) < 1e-12
+    # constant beyond the ends
+    assert mlp.scale_interp(100.0, lam, s) == pytest.approx(s[0])
+    assert mlp.scale_interp(1e-6, lam, s) == pytest.approx(s[-1])

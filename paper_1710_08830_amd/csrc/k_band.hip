@@ -217,6 +217,46 @@ hipError_t launch_kval(int n, int Nf, int aos_no, const double *e, double lam, i
   return hipGetLastError();
 }
 
+// two orbitals, band layout [e_0][e_1][Pi_0 d0][Pi_0 d1][Pi_0 re][Pi_0 im]...:
+// per k the 4-vector (e_0, e_1, K(e_0), K(e_1)) at scale lam
+__global__ void ekv4_kernel(int Nf, const double *__restrict__ band, double lam, int scheme, int deriv,
+                            double *__restrict__ ekv, float *__restrict__ ekv32) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= Nf) return;
+  const double e0 = band[k], e1 = band[(size_t)Nf + k];
+  const double v[4] = {e0, e1, cut_val(e0, lam, scheme, deriv), cut_val(e1, lam, scheme, deriv)};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    ekv[4 * (size_t)k + j] = v[j];
+    ekv32[4 * (size_t)k + j] = (float)v[j];
+  }
+}
+
+hipError_t launch_ekv4(int Nf, const double *band, double lam, int scheme, int deriv, double *ekv, float *ekv32,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(ekv4_kernel, dim3((Nf + 255) / 256), dim3(256), 0, st, Nf, band, lam, scheme, deriv, ekv,
+                     ekv32);
+  return hipGetLastError();
+}
+
+// per k the 4-vector (Pi_0[00], Pi_0[11], Re Pi_0[01], Im Pi_0[01])
+__global__ void pi4_kernel(int Nf, const double *__restrict__ band, double *__restrict__ pi4,
+                           float *__restrict__ pi4_32) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= Nf) return;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const double v = band[(size_t)(2 + j) * Nf + k];
+    pi4[4 * (size_t)k + j] = v;
+    pi4_32[4 * (size_t)k + j] = (float)v;
+  }
+}
+
+hipError_t launch_pi4(int Nf, const double *band, double *pi4, float *pi4_32, hipStream_t st) {
+  hipLaunchKernelGGL(pi4_kernel, dim3((Nf + 255) / 256), dim3(256), 0, st, Nf, band, pi4, pi4_32);
+  return hipGetLastError();
+}
+
 // component-major [nc][Nf] -> k-major [Nf][nc], FP64 and FP32 copies
 __global__ void to_kmajor_kernel(int nc, int Nf, const double *__restrict__ src, double *__restrict__ dst,
                                  float *__restrict__ dst32) {

@@ -17,7 +17,8 @@
 //   transpose for ph) and alpha_m = L_m0 - L_m1:
 //     W_m = sum_n L_mn X_n = alpha_m X_0 + L_m1 1,  M = sum_m Pi_m (x) W_m
 //         = Pi_0 (x) (W_0 - W_1) + 1 (x) W_1,
-//   so only e_0, e_1, K_0, K_1 and the four reals of Pi_0 are read per point.
+//   so only e_0, e_1, K_0, K_1 and the four reals of Pi_0 are read per point,
+//   as two 4-vectors (k-major arrays ekv and pi4).
 // * M[(c,d,a,b)] = conj(M[(a,b,c,d)]): only 10 entries are distinct (4 real).
 //   With the phase p = c + i s the accumulation of p M and p conj(M) needs only
 //   A = sum c M and B = sum s M; the pair is rebuilt at the end as
@@ -59,136 +60,158 @@ __device__ inline T ldb(const T *base, unsigned byte_off) {
   return *(const T *)((const char *)base + byte_off);
 }
 
+// four consecutive values at index i of a k-major array of 4-vectors
+template <typename T>
+struct V4 {
+  T x, y, z, w;
+};
+__device__ inline V4<float> ld4(const float *base, unsigned i) {
+  const float4 v = *(const float4 *)((const char *)base + (size_t)i * 16u);
+  return {v.x, v.y, v.z, v.w};
+}
+__device__ inline V4<double> ld4(const double *base, unsigned i) {
+  const double2 *p = (const double2 *)((const char *)base + (size_t)i * 32u);
+  const double2 a = p[0], b = p[1];
+  return {a.x, a.y, b.x, b.y};
+}
+
 // Loop body of one channel (CH = 0: pp, k' = q - k; CH = 1: ph, k' = k - q).
+// ekv[k] = (e_0, e_1, K(e_0), K(e_1)), pi4[k] = (Pi_0[00], Pi_0[11], Re Pi_0[01], Im Pi_0[01]);
+// twk: exp(-2 pi i j / Lf) in the arithmetic type.
 template <typename T, int NDX, int SCHEME, int CH>
-__device__ inline void loop_no2_body(const T *__restrict__ band, const T *__restrict__ kv,
-                                     const double *__restrict__ tw, int Lf, int qfx, int qfy, int ky, int x0,
+__device__ inline void loop_no2_body(const T *__restrict__ ekv, const T *__restrict__ pi4,
+                                     const T *__restrict__ twk, int Lf, int qfx, int qfy, int ky, int x0,
                                      int x1, T lam, int deriv, T (&Sr)[NREAL], T (&Sc)[NCPLX][2],
                                      T (&Ar)[NDX - 1][NREAL], T (&Br)[NDX - 1][NREAL],
                                      T (&Ac)[NDX - 1][NCPLX][2], T (&Bc)[NDX - 1][NCPLX][2]) {
   constexpr T sg = (CH == 0) ? T(1) : T(-1);
-  const unsigned Nf = (unsigned)Lf * (unsigned)Lf;
-  // component bases (uniform): e0 e1 | Pi_0: d0 d1 r im | Pi_1 (unused) ; K0 K1
-  const T *e0 = band, *e1 = band + Nf;
-  const T *p00 = band + 2 * Nf, *p11 = band + 3 * Nf, *p0r = band + 4 * Nf, *p0i = band + 5 * Nf;
-  const T *K0 = kv, *K1 = kv + Nf;
   int kpy = (CH == 0) ? (qfy - ky) : (ky - qfy);
   kpy = ((kpy % Lf) + Lf) % Lf;
   int kpx = (CH == 0) ? (qfx - x0) : (x0 - qfx);
   kpx = ((kpx % Lf) + Lf) % Lf;
-  unsigned kb = ((unsigned)x0 * Lf + ky) * (unsigned)sizeof(T);
-  const unsigned rowb = (unsigned)Lf * (unsigned)sizeof(T);
-  // software pipeline: the 16 loads of iteration kx + 1 are issued before the
-  // arithmetic of iteration kx
+  // phase indices (kx (d + 1)) mod Lf, advanced with kx (wave-uniform)
+  int jd[NDX - 1];
+#pragma unroll
+  for (int d = 0; d < NDX - 1; ++d) jd[d] = (int)(((long long)x0 * (d + 1)) % Lf);
   struct Pt {
-    T e[2], K[2], d0, d1, r, i;
+    V4<T> ek, pk;
   };
-  auto load = [&](unsigned b, Pt &p) {
-    p.e[0] = ldb(e0, b);
-    p.e[1] = ldb(e1, b);
-    p.K[0] = ldb(K0, b);
-    p.K[1] = ldb(K1, b);
-    p.d0 = ldb(p00, b);
-    p.d1 = ldb(p11, b);
-    p.r = ldb(p0r, b);
-    p.i = ldb(p0i, b);
+  auto load = [&](unsigned i, Pt &p) {
+    p.ek = ld4(ekv, i);
+    p.pk = ld4(pi4, i);
   };
-  Pt ck, cp, nk, np;
-  unsigned kpb_cur = ((unsigned)kpx * Lf + kpy) * (unsigned)sizeof(T);
-  load(kb, ck);
-  load(kpb_cur, cp);
-  // FP64 keeps the plain order: its register budget is already at one or two waves per SIMD
-  constexpr bool PIPE = sizeof(T) == 4;
-  for (int kx = x0; kx < x1; ++kx, kb += rowb) {
+  // k' row of the next kx
+  auto next_kpx = [&]() {
     kpx += (CH == 0) ? -1 : 1;
     kpx = kpx < 0 ? kpx + Lf : (kpx >= Lf ? kpx - Lf : kpx);
-    if constexpr (PIPE) {
-      // the last prefetch re-reads a valid row and is not used
-      const unsigned kbn = (kx + 1 < x1) ? kb + rowb : kb;
-      load(kbn, nk);
-      load(((unsigned)kpx * Lf + kpy) * (unsigned)sizeof(T), np);
-    } else if (kx > x0) {
-      load(kb, ck);
-      load(kpb_cur, cp);
-    }
-    const unsigned kpb_next = ((unsigned)kpx * Lf + kpy) * (unsigned)sizeof(T);
-    const T ekm[2] = {ck.e[0], ck.e[1]}, Kkm[2] = {ck.K[0], ck.K[1]};
-    const T P0 = ck.d0, P1 = ck.d1, Pr = ck.r, Pi = ck.i;
-    const T epn[2] = {cp.e[0], cp.e[1]}, Kpn[2] = {cp.K[0], cp.K[1]};
-    const T X0 = cp.d0, X1 = cp.d1, Xr = cp.r, Xi = sg * cp.i;
-    // loop kernels L_mn: pp (K(e1)+K(e2))/(e1+e2), ph -(K(e1)-K(e2))/(e1-e2); divided
-    // difference of K at x = e_m(k), y = -sg e_n(k'); one branch for the rare near-degenerate lanes
-    T L[2][2];
-    bool ok = true;
-#pragma unroll
-    for (int m = 0; m < 2; ++m)
-#pragma unroll
-      for (int n = 0; n < 2; ++n) {
-        const T den = ekm[m] + sg * epn[n];
-        ok = ok && nondegenerate<T, SCHEME>(den, ekm[m], sg * epn[n], lam);
-        L[m][n] = sg * (Kkm[m] + sg * Kpn[n]) * rcp_fast(den);
-      }
-    if (__builtin_expect(!ok, 0)) {
+  };
+  // arithmetic of one k-point (k data ck, k' data cp), in kx order
+  auto point = [&](const Pt &ck, const Pt &cp) {
+      const T ekm[2] = {ck.ek.x, ck.ek.y}, Kkm[2] = {ck.ek.z, ck.ek.w};
+      const T P0 = ck.pk.x, P1 = ck.pk.y, Pr = ck.pk.z, Pi = ck.pk.w;
+      const T epn[2] = {cp.ek.x, cp.ek.y}, Kpn[2] = {cp.ek.z, cp.ek.w};
+      const T X0 = cp.pk.x, X1 = cp.pk.y, Xr = cp.pk.z, Xi = sg * cp.pk.w;
+      // loop kernels L_mn: pp (K(e1)+K(e2))/(e1+e2), ph -(K(e1)-K(e2))/(e1-e2); divided
+      // difference of K at x = e_m(k), y = -sg e_n(k'); one branch for the rare near-degenerate lanes
+      T L[2][2];
+      bool ok = true;
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int n = 0; n < 2; ++n)
-          L[m][n] = sg * divided_difference(ekm[m], -sg * epn[n], Kkm[m], -sg * Kpn[n], lam, SCHEME, deriv);
-    }
-    // W_1 = alpha_1 X_0 + L_11 1, D = W_0 - W_1 = (alpha_0 - alpha_1) X_0 + (L_01 - L_11) 1
-    const T al0 = L[0][0] - L[0][1], al1 = L[1][0] - L[1][1];
-    const T dal = al0 - al1, dl = L[0][1] - L[1][1];
-    const T W1d0 = fma(al1, X0, L[1][1]), W1d1 = fma(al1, X1, L[1][1]);
-    const T W1r = al1 * Xr, W1i = al1 * Xi;
-    const T Dd0 = fma(dal, X0, dl), Dd1 = fma(dal, X1, dl);
-    const T Dr = dal * Xr, Di = dal * Xi;
-    // the 10 distinct entries of M = Pi_0 (x) D + 1 (x) W_1
-    T mr[NREAL], mc[NCPLX][2];
-    mr[0] = fma(P0, Dd0, W1d0);  // (0,0,0,0)
-    mr[1] = fma(P0, Dd1, W1d1);  // (0,1,0,1)
-    mr[2] = fma(P1, Dd0, W1d0);  // (1,0,1,0)
-    mr[3] = fma(P1, Dd1, W1d1);  // (1,1,1,1)
-    mc[0][0] = fma(P0, Dr, W1r);  // (0,0,0,1)
-    mc[0][1] = fma(P0, Di, W1i);
-    mc[1][0] = fma(P1, Dr, W1r);  // (1,0,1,1)
-    mc[1][1] = fma(P1, Di, W1i);
-    mc[2][0] = Pr * Dd0;  // (0,0,1,0)
-    mc[2][1] = Pi * Dd0;
-    mc[3][0] = Pr * Dd1;  // (0,1,1,1)
-    mc[3][1] = Pi * Dd1;
-    mc[4][0] = fma(Pr, Dr, -Pi * Di);  // (0,0,1,1): Pi_0[01] D[01]
-    mc[4][1] = fma(Pr, Di, Pi * Dr);
-    mc[5][0] = fma(Pr, Dr, Pi * Di);  // (0,1,1,0): Pi_0[01] D[10] = Pi_0[01] conj(D[01])
-    mc[5][1] = fma(Pi, Dr, -Pr * Di);
+        for (int n = 0; n < 2; ++n) {
+          const T den = ekm[m] + sg * epn[n];
+          ok = ok && nondegenerate<T, SCHEME>(den, ekm[m], sg * epn[n], lam);
+          L[m][n] = sg * (Kkm[m] + sg * Kpn[n]) * rcp_fast(den);
+        }
+      if (__builtin_expect(!ok, 0)) {
 #pragma unroll
-    for (int t = 0; t < NREAL; ++t) Sr[t] += mr[t];
+        for (int m = 0; m < 2; ++m)
 #pragma unroll
-    for (int t = 0; t < NCPLX; ++t) {
-      Sc[t][0] += mc[t][0];
-      Sc[t][1] += mc[t][1];
-    }
-#pragma unroll
-    for (int d = 0; d < NDX - 1; ++d) {
-      const int j = (kx * (d + 1)) % Lf;
-      const T c = (T)tw[2 * j], s = (T)tw[2 * j + 1];  // e^{-i 2 pi kx dx / Lf}, wave-uniform
-#pragma unroll
-      for (int t = 0; t < NREAL; ++t) {
-        Ar[d][t] = fma(c, mr[t], Ar[d][t]);
-        Br[d][t] = fma(s, mr[t], Br[d][t]);
+          for (int n = 0; n < 2; ++n)
+            L[m][n] = sg * divided_difference(ekm[m], -sg * epn[n], Kkm[m], -sg * Kpn[n], lam, SCHEME, deriv);
       }
+      // W_1 = alpha_1 X_0 + L_11 1, D = W_0 - W_1 = (alpha_0 - alpha_1) X_0 + (L_01 - L_11) 1
+      const T al0 = L[0][0] - L[0][1], al1 = L[1][0] - L[1][1];
+      const T dal = al0 - al1, dl = L[0][1] - L[1][1];
+      const T W1d0 = fma(al1, X0, L[1][1]), W1d1 = fma(al1, X1, L[1][1]);
+      const T W1r = al1 * Xr, W1i = al1 * Xi;
+      const T Dd0 = fma(dal, X0, dl), Dd1 = fma(dal, X1, dl);
+      const T Dr = dal * Xr, Di = dal * Xi;
+      // the 10 distinct entries of M = Pi_0 (x) D + 1 (x) W_1
+      T mr[NREAL], mc[NCPLX][2];
+      mr[0] = fma(P0, Dd0, W1d0);  // (0,0,0,0)
+      mr[1] = fma(P0, Dd1, W1d1);  // (0,1,0,1)
+      mr[2] = fma(P1, Dd0, W1d0);  // (1,0,1,0)
+      mr[3] = fma(P1, Dd1, W1d1);  // (1,1,1,1)
+      mc[0][0] = fma(P0, Dr, W1r);  // (0,0,0,1)
+      mc[0][1] = fma(P0, Di, W1i);
+      mc[1][0] = fma(P1, Dr, W1r);  // (1,0,1,1)
+      mc[1][1] = fma(P1, Di, W1i);
+      mc[2][0] = Pr * Dd0;  // (0,0,1,0)
+      mc[2][1] = Pi * Dd0;
+      mc[3][0] = Pr * Dd1;  // (0,1,1,1)
+      mc[3][1] = Pi * Dd1;
+      mc[4][0] = fma(Pr, Dr, -Pi * Di);  // (0,0,1,1): Pi_0[01] D[01]
+      mc[4][1] = fma(Pr, Di, Pi * Dr);
+      mc[5][0] = fma(Pr, Dr, Pi * Di);  // (0,1,1,0): Pi_0[01] D[10] = Pi_0[01] conj(D[01])
+      mc[5][1] = fma(Pi, Dr, -Pr * Di);
+#pragma unroll
+      for (int t = 0; t < NREAL; ++t) Sr[t] += mr[t];
 #pragma unroll
       for (int t = 0; t < NCPLX; ++t) {
-        Ac[d][t][0] = fma(c, mc[t][0], Ac[d][t][0]);
-        Ac[d][t][1] = fma(c, mc[t][1], Ac[d][t][1]);
-        Bc[d][t][0] = fma(s, mc[t][0], Bc[d][t][0]);
-        Bc[d][t][1] = fma(s, mc[t][1], Bc[d][t][1]);
+        Sc[t][0] += mc[t][0];
+        Sc[t][1] += mc[t][1];
       }
+#pragma unroll
+      for (int d = 0; d < NDX - 1; ++d) {
+        const int j = jd[d];
+        jd[d] = j + d + 1 >= Lf ? j + d + 1 - Lf : j + d + 1;
+        const T c = twk[2 * j], s = twk[2 * j + 1];  // e^{-i 2 pi kx dx / Lf}, wave-uniform
+#pragma unroll
+        for (int t = 0; t < NREAL; ++t) {
+          Ar[d][t] = fma(c, mr[t], Ar[d][t]);
+          Br[d][t] = fma(s, mr[t], Br[d][t]);
+        }
+#pragma unroll
+        for (int t = 0; t < NCPLX; ++t) {
+          Ac[d][t][0] = fma(c, mc[t][0], Ac[d][t][0]);
+          Ac[d][t][1] = fma(c, mc[t][1], Ac[d][t][1]);
+          Bc[d][t][0] = fma(s, mc[t][0], Bc[d][t][0]);
+          Bc[d][t][1] = fma(s, mc[t][1], Bc[d][t][1]);
+        }
+      }
+  };
+  const unsigned row = (unsigned)Lf;
+  unsigned kk = (unsigned)x0 * Lf + ky;
+  if constexpr (sizeof(T) == 4) {
+    // software pipeline with two register sets: the loads of point kx + 1 are
+    // issued before the arithmetic of point kx; a prefetch past the chunk
+    // re-reads the current point and is not used
+    Pt ak, ap, bk, bp;
+    load(kk, ak);
+    load((unsigned)kpx * Lf + kpy, ap);
+    int kx = x0;
+    for (; kx + 1 < x1; kx += 2, kk += 2 * row) {
+      next_kpx();
+      load(kk + row, bk);
+      load((unsigned)kpx * Lf + kpy, bp);
+      point(ak, ap);
+      const bool more = kx + 2 < x1;
+      if (more) next_kpx();
+      load(more ? kk + 2 * row : kk + row, ak);
+      load((unsigned)kpx * Lf + kpy, ap);
+      point(bk, bp);
     }
-    if constexpr (PIPE) {
-      ck = nk;
-      cp = np;
+    if (kx < x1) point(ak, ap);
+  } else {
+    // FP64 keeps the plain order: its register budget is already at one or two waves per SIMD
+    for (int kx = x0; kx < x1; ++kx, kk += row) {
+      Pt ck, cp;
+      load(kk, ck);
+      load((unsigned)kpx * Lf + kpy, cp);
+      point(ck, cp);
+      next_kpx();
     }
-    kpb_cur = kpb_next;
   }
 }
 
@@ -207,8 +230,9 @@ struct loop_waves {
 
 // QW waves per work item (ky block, q_y group, q_x, kx chunk, channel).
 template <typename T, int NDX, int NDY, int SCHEME, int QW>
-__global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 2 : 3))) void loop_no2_kernel(const T *__restrict__ band, const T *__restrict__ kv,
-                                                           const double *__restrict__ tw, int Lq, int n_ref, int Lf,
+__global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 2 : 3))) void loop_no2_kernel(const T *__restrict__ ekv, const T *__restrict__ pi4,
+                                                           const double *__restrict__ tw, const T *__restrict__ twk,
+                                                           int Lq, int n_ref, int Lf,
                                                            int nkyb, int nkxc, int kxper, int q_first, int n_q,
                                                            int ch_first, int n_items, T lam, int deriv,
                                                            double *__restrict__ partial) {
@@ -254,9 +278,9 @@ __global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (siz
     for (int t = 0; t < NCPLX; ++t) Ac[d][t][0] = Ac[d][t][1] = Bc[d][t][0] = Bc[d][t][1] = T(0);
   }
   if (ch == 0)
-    loop_no2_body<T, NDX, SCHEME, 0>(band, kv, tw, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac, Bc);
+    loop_no2_body<T, NDX, SCHEME, 0>(ekv, pi4, twk, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac, Bc);
   else
-    loop_no2_body<T, NDX, SCHEME, 1>(band, kv, tw, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac, Bc);
+    loop_no2_body<T, NDX, SCHEME, 1>(ekv, pi4, twk, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac, Bc);
 
   // rebuild all 16 entries per dx, transpose through LDS, contract with e^{-i 2 pi ky dy / Lf}
   __shared__ T bufs[QW][32][65];
@@ -338,14 +362,16 @@ static hipError_t launch_no2(const LoopArgs &a, hipStream_t st) {
   const int n_items = a.nkyb * a.nkxc * nqyg * (a.n_q / a.Lq) * a.n_ch;
   const int n_wg = ((n_items + N_XCD - 1) / N_XCD) * N_XCD;
   dim3 grid(n_wg), block(64 * QW);
-  const T *band = (const T *)a.band;
-  const T *kv = (const T *)a.kv;
+  const T *ekv = (const T *)a.ekv;
+  const T *pi4 = (const T *)a.pi4;
+  const T *twk = (const T *)(sizeof(T) == 8 ? (const void *)a.tw : a.tw32);
+  if (!ekv || !pi4 || !twk) return hipErrorInvalidValue;
   if (a.scheme == CUT_TEMPERATURE)
-    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_TEMPERATURE, QW>), grid, block, 0, st, band, kv, a.tw, a.Lq,
+    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_TEMPERATURE, QW>), grid, block, 0, st, ekv, pi4, a.tw, twk, a.Lq,
                        a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.ch_first, n_items, (T)a.lam,
                        a.deriv, a.partial);
   else
-    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_OMEGA, QW>), grid, block, 0, st, band, kv, a.tw, a.Lq,
+    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_OMEGA, QW>), grid, block, 0, st, ekv, pi4, a.tw, twk, a.Lq,
                        a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.ch_first, n_items, (T)a.lam,
                        a.deriv, a.partial);
   return hipGetLastError();

@@ -10,6 +10,10 @@ hipError_t launch_band(int n_o, int Lf, int n_hop, const int *hop_R, const doubl
                        double *e, double *pi, float *e32, float *pi32, hipStream_t st);
 hipError_t launch_kval(int n, int Nf, int aos_no, const double *e, double lam, int scheme, int deriv, double *kv,
                        float *kv32, hipStream_t st);
+// two orbitals: ekv[k] = (e_0, e_1, K(e_0), K(e_1)) and the static pi4[k], k-major 4-vectors
+hipError_t launch_ekv4(int Nf, const double *band, double lam, int scheme, int deriv, double *ekv, float *ekv32,
+                       hipStream_t st);
+hipError_t launch_pi4(int Nf, const double *band, double *pi4, float *pi4_32, hipStream_t st);
 // component-major [nc][Nf] -> k-major [Nf][nc] (FP64 and FP32)
 hipError_t launch_to_kmajor(int nc, int Nf, const double *src, double *dst, float *dst32, hipStream_t st);
 
@@ -26,10 +30,13 @@ struct LoopArgs {
                        // [n_o + n_o^3][Nf], more orbitals k-major [Nf][n_o + n_o^3]
   const void *kv;      // regulator values, [n_o][Nf] or [Nf][n_o] like the band data
   const double *tw;    // exp(-2 pi i j / Lf), [Lf][2]
+  const float *tw32 = nullptr;  // the same in FP32
   double *partial;     // [n_ch][n_q][nkyb * nkxc][ndx][2 ndy + 1][n_o^4][2]
   const int *pairs = nullptr;  // more than two orbitals: [n_pairs][2] entry and its conjugate partner
   int n_pairs = 0;
   const void *phy = nullptr;   // more than two orbitals: exp(-2 pi i ky dy / Lf), [Lf][ndy][2], like band
+  const void *ekv = nullptr;   // two orbitals: [Nf][4] = (e_0, e_1, K(e_0), K(e_1)), like band
+  const void *pi4 = nullptr;   // two orbitals: [Nf][4] = (Pi_0[00], Pi_0[11], Re Pi_0[01], Im Pi_0[01])
 };
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
 // more than two spin-orbitals (six: t2g with spin-orbit coupling)

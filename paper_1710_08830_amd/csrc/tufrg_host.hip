@@ -43,6 +43,8 @@ struct tufrg_ctx {
   int *d_hopR = nullptr;
   int *d_pairs = nullptr;  // loop entry pairs (tau, conjugate partner) for more than two orbitals
   int n_pairs = 0;
+  double *d_ekv64 = nullptr, *d_pi4_64 = nullptr;  // two orbitals: k-major 4-vectors of the loop kernel
+  float *d_ekv32 = nullptr, *d_pi4_32 = nullptr;
   double *d_phy64 = nullptr;  // ky phases of the multi-orbital loop kernel, [Lf][ndy][2]
   float *d_phy32 = nullptr;
   double *d_hopt = nullptr;
@@ -53,6 +55,7 @@ struct tufrg_ctx {
   double *d_kv64 = nullptr;
   float *d_kv32 = nullptr;
   double *d_twf = nullptr, *d_twq = nullptr;
+  float *d_twf32 = nullptr;
   double *d_partial = nullptr;
   double *d_loop = nullptr;
   double *d_ftpart = nullptr, *d_real = nullptr, *d_G = nullptr;
@@ -294,6 +297,12 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CTRY(dalloc(c, &c->d_hopt, 2 * (size_t)m->n_hop * c->no2));
   CTRY(dalloc(c, &c->d_band64, Nf * (c->n_o + c->n_o * c->no2)));
   CTRY(dalloc(c, &c->d_band32, Nf * (c->n_o + c->n_o * c->no2)));
+  if (c->n_o == 2) {
+    CTRY(dalloc(c, &c->d_ekv64, 4 * Nf));
+    CTRY(dalloc(c, &c->d_ekv32, 4 * Nf));
+    CTRY(dalloc(c, &c->d_pi4_64, 4 * Nf));
+    CTRY(dalloc(c, &c->d_pi4_32, 4 * Nf));
+  }
   if (c->n_o > 2) {
     CTRY(dalloc(c, &c->d_bandk64, Nf * (c->n_o + c->n_o * c->no2)));
     CTRY(dalloc(c, &c->d_bandk32, Nf * (c->n_o + c->n_o * c->no2)));
@@ -314,6 +323,7 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CTRY(dalloc(c, &c->d_kv64, Nf * c->n_o));
   CTRY(dalloc(c, &c->d_kv32, Nf * c->n_o));
   CTRY(dalloc(c, &c->d_twf, 2 * (size_t)c->Lf));
+  CTRY(dalloc(c, &c->d_twf32, 2 * (size_t)c->Lf));
   CTRY(dalloc(c, &c->d_twq, 2 * (size_t)c->Lq));
   const size_t nparts = (size_t)c->nkyb * c->nkxc;
   CTRY(dalloc(c, &c->d_partial, 2 * 2 * (size_t)c->Nq * nparts * c->ndx * (2 * c->ndy + 1) * c->no4));
@@ -382,6 +392,8 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CHIP(hipMemcpyAsync(c->d_hopt, m->hop_t, (size_t)m->n_hop * c->no2 * sizeof(tufrg_c64), hipMemcpyHostToDevice,
                       st));
   CHIP(hipMemcpyAsync(c->d_twf, twf.data(), twf.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  std::vector<float> twf32(twf.begin(), twf.end());
+  CHIP(hipMemcpyAsync(c->d_twf32, twf32.data(), twf32.size() * sizeof(float), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_twq, twq.data(), twq.size() * sizeof(double), hipMemcpyHostToDevice, st));
   if (c->n_o > 2) {
     CHIP(hipMemcpyAsync(c->d_phy64, phy64.data(), phy64.size() * sizeof(double), hipMemcpyHostToDevice, st));
@@ -392,6 +404,7 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CHIP(launch_band(c->n_o, c->Lf, m->n_hop, c->d_hopR, c->d_hopt, m->mu, c->d_band64, c->d_band64 + Nf * c->n_o,
                    c->d_band32, c->d_band32 + Nf * c->n_o, st));
   if (c->n_o > 2) CHIP(launch_to_kmajor(c->n_o + c->n_o * c->no2, (int)Nf, c->d_band64, c->d_bandk64, c->d_bandk32, st));
+  if (c->n_o == 2) CHIP(launch_pi4((int)Nf, c->d_band64, c->d_pi4_64, c->d_pi4_32, st));
   CHIP(hipStreamSynchronize(st));
   *out = c;
   return TUFRG_OK;
@@ -449,10 +462,13 @@ static LoopArgs loop_args(tufrg_ctx *c, double lam, int deriv, int ch_first, int
     a.band = c->prec == 0 ? (const void *)c->d_band64 : (const void *)c->d_band32;
   a.kv = c->prec == 0 ? (const void *)c->d_kv64 : (const void *)c->d_kv32;
   a.tw = c->d_twf;
+  a.tw32 = c->d_twf32;
   a.partial = c->d_partial;
   a.pairs = c->d_pairs;
   a.n_pairs = c->n_pairs;
   a.phy = c->prec == 0 ? (const void *)c->d_phy64 : (const void *)c->d_phy32;
+  a.ekv = c->prec == 0 ? (const void *)c->d_ekv64 : (const void *)c->d_ekv32;
+  a.pi4 = c->prec == 0 ? (const void *)c->d_pi4_64 : (const void *)c->d_pi4_32;
   return a;
 }
 
@@ -473,8 +489,11 @@ static ProjArgs proj_args(tufrg_ctx *c) {
 }
 
 static tufrg_status compute_kval(tufrg_ctx *c, double lam, int deriv) {
-  HIPCHK(c, launch_kval(c->n_o * c->Nf, c->Nf, c->n_o > 2 ? c->n_o : 0, c->d_band64, lam, c->scheme, deriv,
-                        c->d_kv64, c->d_kv32, c->st));
+  if (c->n_o == 2)
+    HIPCHK(c, launch_ekv4(c->Nf, c->d_band64, lam, c->scheme, deriv, c->d_ekv64, c->d_ekv32, c->st));
+  else
+    HIPCHK(c, launch_kval(c->n_o * c->Nf, c->Nf, c->n_o, c->d_band64, lam, c->scheme, deriv, c->d_kv64, c->d_kv32,
+                          c->st));
   return TUFRG_OK;
 }
 

@@ -19,20 +19,26 @@ struct KList {
 };
 
 __device__ inline void block_max_flag(double v, bool bad, unsigned long long *bits, unsigned int *flag) {
-  __shared__ double sm[256];
-  __shared__ int sb;
-  if (threadIdx.x == 0) sb = 0;
-  __syncthreads();
-  sm[threadIdx.x] = v;
-  if (bad) sb = 1;
-  __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + s]);
-    __syncthreads();
+  // wave maximum by shuffles, then one value per wave through LDS
+  __shared__ double sm[4];
+  __shared__ int sb[4];
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+  const int anybad = __any(bad);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sm[wv] = v;
+    sb[wv] = anybad;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    atomicMax(bits, (unsigned long long)__double_as_longlong(sm[0]));
-    if (sb) atomicOr(flag, 1u);
+    double m = sm[0];
+    int b = sb[0];
+    for (int i = 1; i < (int)(blockDim.x >> 6); ++i) {
+      m = fmax(m, sm[i]);
+      b |= sb[i];
+    }
+    atomicMax(bits, (unsigned long long)__double_as_longlong(m));
+    if (b) atomicOr(flag, 1u);
   }
 }
 }  // namespace
@@ -42,17 +48,17 @@ __global__ __launch_bounds__(256) void axpy_max_kernel(long long n, const double
                                                        unsigned long long *bits, unsigned int *flag) {
   double m = 0.0;
   bool bad = false;
+  const double2 *x2 = (const double2 *)x, *d2 = (const double2 *)dx;
+  double2 *y2 = (double2 *)y;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    double r = x[2 * i], im = x[2 * i + 1];
+    double2 v = x2[i];
     if (dx) {
-      r = fma(h, dx[2 * i], r);
-      im = fma(h, dx[2 * i + 1], im);
+      const double2 d = d2[i];
+      v.x = fma(h, d.x, v.x);
+      v.y = fma(h, d.y, v.y);
     }
-    if (y) {
-      y[2 * i] = r;
-      y[2 * i + 1] = im;
-    }
-    const double a = sqrt(r * r + im * im);
+    if (y) y2[i] = v;
+    const double a = sqrt(v.x * v.x + v.y * v.y);
     if (!isfinite(a)) bad = true;
     else m = fmax(m, a);
   }
@@ -62,7 +68,7 @@ __global__ __launch_bounds__(256) void axpy_max_kernel(long long n, const double
 hipError_t launch_axpy_max(long long n, const double *x, double h, const double *dx, double *y,
                            unsigned long long *maxbits, unsigned int *flag, hipStream_t st) {
   long long blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 512) blocks = 512;  // few blocks: one atomic per block
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(axpy_max_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n, x, h, dx, y, maxbits, flag);
   return hipGetLastError();

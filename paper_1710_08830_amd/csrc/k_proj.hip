@@ -21,9 +21,9 @@
 namespace tufrg {
 
 // part[qc][w][iD][e] = sum_{q in chunk qc} e^{iq.rho_iD} X_w(q)[e]
+// phq[q][iD] = e^{i q.rho_iD} (table, read with wave-uniform loads)
 template <int NDP>
-__global__ __launch_bounds__(256) void ft_kernel(int BB, int Lq, int Nq, int nD, int qper,
-                                                 const int *__restrict__ dlist, const double *__restrict__ twq,
+__global__ __launch_bounds__(256) void ft_kernel(int BB, int Nq, int nD, int qper, const double *__restrict__ phq,
                                                  const double *__restrict__ P, const double *__restrict__ C,
                                                  double *__restrict__ part) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -39,16 +39,14 @@ __global__ __launch_bounds__(256) void ft_kernel(int BB, int Lq, int Nq, int nD,
   }
   const int q0 = qc * qper, q1 = min(Nq, q0 + qper);
   for (int q = q0; q < q1; ++q) {
-    const int mx = q / Lq, my = q - mx * Lq;
-    const double xr = X[2 * ((size_t)q * BB + e)], xi = X[2 * ((size_t)q * BB + e) + 1];
+    const double2 x = *(const double2 *)(X + 2 * ((size_t)q * BB + e));
+    const double *ph = phq + 2 * (size_t)q * nD;
 #pragma unroll
     for (int i = 0; i < NDP; ++i) {
       if (i < nD) {
-        int j = (mx * dlist[2 * i] + my * dlist[2 * i + 1]) % Lq;
-        if (j < 0) j += Lq;
-        const double c = twq[2 * j], s = twq[2 * j + 1];
-        ar[i] = fma(c, xr, fma(-s, xi, ar[i]));
-        ai[i] = fma(c, xi, fma(s, xr, ai[i]));
+        const double c = ph[2 * i], s = ph[2 * i + 1];
+        ar[i] = fma(c, x.x, fma(-s, x.y, ar[i]));
+        ai[i] = fma(c, x.y, fma(s, x.x, ai[i]));
       }
     }
   }
@@ -76,11 +74,11 @@ hipError_t launch_ft(const ProjArgs &a, const double *P, const double *C, double
   const int qper = (a.Nq + nqc - 1) / nqc;
   dim3 grid((BB + 255) / 256, 2, nqc), block(256);
   if (a.nD <= 13)
-    hipLaunchKernelGGL(ft_kernel<13>, grid, block, 0, st, BB, a.Lq, a.Nq, a.nD, qper, a.dlist, a.twq, P, C, part);
+    hipLaunchKernelGGL(ft_kernel<13>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, part);
   else if (a.nD <= 25)
-    hipLaunchKernelGGL(ft_kernel<25>, grid, block, 0, st, BB, a.Lq, a.Nq, a.nD, qper, a.dlist, a.twq, P, C, part);
+    hipLaunchKernelGGL(ft_kernel<25>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, part);
   else if (a.nD <= 41)
-    hipLaunchKernelGGL(ft_kernel<41>, grid, block, 0, st, BB, a.Lq, a.Nq, a.nD, qper, a.dlist, a.twq, P, C, part);
+    hipLaunchKernelGGL(ft_kernel<41>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, part);
   else
     return hipErrorInvalidValue;
   const long long n = 2LL * 2 * a.nD * BB;  // doubles per chunk
@@ -158,8 +156,7 @@ hipError_t launch_gather(const ProjArgs &a, const double *real, double *G, hipSt
 
 // VX(q)[e] = X(q)[e] + X[V0][e] + sum_rho e^{iq.rho} G_X(rho)[e]
 template <int NDP>
-__global__ __launch_bounds__(256) void assemble_kernel(int BB, int Lq, int Nq, int nD, int qper,
-                                                       const int *__restrict__ dlist, const double *__restrict__ twq,
+__global__ __launch_bounds__(256) void assemble_kernel(int BB, int Nq, int nD, int qper, const double *__restrict__ phq,
                                                        const double *__restrict__ P, const double *__restrict__ C,
                                                        const double *__restrict__ G, const double *__restrict__ v0p,
                                                        const double *__restrict__ v0c, double *__restrict__ VP,
@@ -185,20 +182,21 @@ __global__ __launch_bounds__(256) void assemble_kernel(int BB, int Lq, int Nq, i
   const double v0r = v0[2 * e], v0i = v0[2 * e + 1];
   const int q0 = qc * qper, q1 = min(Nq, q0 + qper);
   for (int q = q0; q < q1; ++q) {
-    const int mx = q / Lq, my = q - mx * Lq;
-    double sr = X[2 * ((size_t)q * BB + e)] + v0r, si = X[2 * ((size_t)q * BB + e) + 1] + v0i;
+    const double2 x = *(const double2 *)(X + 2 * ((size_t)q * BB + e));
+    const double *ph = phq + 2 * (size_t)q * nD;
+    double sr = x.x + v0r, si = x.y + v0i;
 #pragma unroll
     for (int i = 0; i < NDP; ++i) {
       if (i < nD) {
-        int j = (mx * dlist[2 * i] + my * dlist[2 * i + 1]) % Lq;
-        if (j < 0) j += Lq;
-        const double c = twq[2 * j], s = twq[2 * j + 1];
+        const double c = ph[2 * i], s = ph[2 * i + 1];
         sr = fma(c, gr[i], fma(-s, gi[i], sr));
         si = fma(c, gi[i], fma(s, gr[i], si));
       }
     }
-    out[2 * ((size_t)q * BB + e)] = sr;
-    out[2 * ((size_t)q * BB + e) + 1] = si;
+    double2 o;
+    o.x = sr;
+    o.y = si;
+    *(double2 *)(out + 2 * ((size_t)q * BB + e)) = o;
   }
 }
 
@@ -206,20 +204,20 @@ hipError_t launch_assemble(const ProjArgs &a, const double *P, const double *C, 
                            const double *v0p, const double *v0c, double *VP, double *VC, hipStream_t st) {
   const int BB = a.B * a.B;
   // enough q chunks to give every CU work
-  int nqc = (int)((2048LL * 256 + 2LL * BB - 1) / (2LL * BB));
+  int nqc = (int)((1024LL * 256 + 2LL * BB - 1) / (2LL * BB));
   nqc = max(1, min(nqc, a.Nq));
   const int qper = (a.Nq + nqc - 1) / nqc;
   nqc = (a.Nq + qper - 1) / qper;
   dim3 grid((BB + 255) / 256, 2, nqc), block(256);
   if (a.nD <= 13)
-    hipLaunchKernelGGL(assemble_kernel<13>, grid, block, 0, st, BB, a.Lq, a.Nq, a.nD, qper, a.dlist, a.twq, P, C, G,
-                       v0p, v0c, VP, VC);
+    hipLaunchKernelGGL(assemble_kernel<13>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, G, v0p, v0c,
+                       VP, VC);
   else if (a.nD <= 25)
-    hipLaunchKernelGGL(assemble_kernel<25>, grid, block, 0, st, BB, a.Lq, a.Nq, a.nD, qper, a.dlist, a.twq, P, C, G,
-                       v0p, v0c, VP, VC);
+    hipLaunchKernelGGL(assemble_kernel<25>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, G, v0p, v0c,
+                       VP, VC);
   else if (a.nD <= 41)
-    hipLaunchKernelGGL(assemble_kernel<41>, grid, block, 0, st, BB, a.Lq, a.Nq, a.nD, qper, a.dlist, a.twq, P, C, G,
-                       v0p, v0c, VP, VC);
+    hipLaunchKernelGGL(assemble_kernel<41>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, G, v0p, v0c,
+                       VP, VC);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -55,6 +55,7 @@ struct ProjArgs {
   const int *dgrid;    // [17][17] index into dlist, -1 outside D
   const int *ff;       // [n_ff][2]
   const double *twq;   // exp(+2 pi i j / Lq), [Lq][2]
+  const double *phq;   // exp(+i q.rho) for every coarse q and rho in dlist, [Nq][nD][2]
 };
 hipError_t launch_ft(const ProjArgs &a, const double *P, const double *C, double *part, int nqc, double *real,
                      hipStream_t st);

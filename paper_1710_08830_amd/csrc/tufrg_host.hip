@@ -54,7 +54,7 @@ struct tufrg_ctx {
   float *d_bandk32 = nullptr;
   double *d_kv64 = nullptr;
   float *d_kv32 = nullptr;
-  double *d_twf = nullptr, *d_twq = nullptr;
+  double *d_twf = nullptr, *d_twq = nullptr, *d_phq = nullptr;
   float *d_twf32 = nullptr;
   double *d_partial = nullptr;
   double *d_loop = nullptr;
@@ -263,7 +263,7 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   }
   {
     long long BB2 = 2LL * c->B * c->B;
-    int want = (int)std::max<long long>(1, (2048LL * 256 + BB2 - 1) / BB2);
+    int want = (int)std::max<long long>(1, (512LL * 256 + BB2 - 1) / BB2);
     c->nqc = std::max(1, std::min(want, c->Nq));
   }
   auto bail = [&](tufrg_status st) {
@@ -325,6 +325,7 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CTRY(dalloc(c, &c->d_twf, 2 * (size_t)c->Lf));
   CTRY(dalloc(c, &c->d_twf32, 2 * (size_t)c->Lf));
   CTRY(dalloc(c, &c->d_twq, 2 * (size_t)c->Lq));
+  CTRY(dalloc(c, &c->d_phq, 2 * (size_t)c->Nq * c->nD));
   const size_t nparts = (size_t)c->nkyb * c->nkxc;
   CTRY(dalloc(c, &c->d_partial, 2 * 2 * (size_t)c->Nq * nparts * c->ndx * (2 * c->ndy + 1) * c->no4));
   CTRY(dalloc(c, &c->d_loop, 2 * 2 * (size_t)c->Nq * c->nD * c->no4));
@@ -395,6 +396,16 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   std::vector<float> twf32(twf.begin(), twf.end());
   CHIP(hipMemcpyAsync(c->d_twf32, twf32.data(), twf32.size() * sizeof(float), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_twq, twq.data(), twq.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  // e^{i q.rho} from exact integer phases (mx dx + my dy) mod Lq
+  std::vector<double> phq(2 * (size_t)c->Nq * c->nD);
+  for (int q = 0; q < c->Nq; ++q)
+    for (int i = 0; i < c->nD; ++i) {
+      int j = ((q / c->Lq) * c->dlist[2 * i] + (q % c->Lq) * c->dlist[2 * i + 1]) % c->Lq;
+      if (j < 0) j += c->Lq;
+      phq[2 * ((size_t)q * c->nD + i)] = twq[2 * j];
+      phq[2 * ((size_t)q * c->nD + i) + 1] = twq[2 * j + 1];
+    }
+  CHIP(hipMemcpyAsync(c->d_phq, phq.data(), phq.size() * sizeof(double), hipMemcpyHostToDevice, st));
   if (c->n_o > 2) {
     CHIP(hipMemcpyAsync(c->d_phy64, phy64.data(), phy64.size() * sizeof(double), hipMemcpyHostToDevice, st));
     CHIP(hipMemcpyAsync(c->d_phy32, phy32.data(), phy32.size() * sizeof(float), hipMemcpyHostToDevice, st));
@@ -485,6 +496,7 @@ static ProjArgs proj_args(tufrg_ctx *c) {
   a.dgrid = c->d_dgrid;
   a.ff = c->d_ff;
   a.twq = c->d_twq;
+  a.phq = c->d_phq;
   return a;
 }
 

@@ -126,7 +126,7 @@ hipError_t launch_dp_error(long long n, const double *x0, const double *x1, int 
     kl.c[j] = j < nk ? ecoef[j] : 0.0;
   }
   long long blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 512) blocks = 512;  // few blocks: one atomic per block
   hipLaunchKernelGGL(dp_error_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n, x0, x1, nk, kl, h, rtol, atol,
                      errbits, flag);
   return hipGetLastError();

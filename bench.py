@@ -194,6 +194,109 @@ def surrogate_leg(T, torch, ctx, P, C, P64, C64, dp, w, K, t_plain_step, n_lam=2
     return res
 
 
+def surrogate_bench(T, torch, w, K, n_rows=200000, epochs=(20, 20, 20)):
+    """Surrogate-assisted flow of the six-orbital model on the 48 x 48 q-mesh:
+    the first K steps of its 200-step Euler grid with plain FP32 loops; the
+    network trained on n_rows random blocks of the plain loops at the scales of
+    those steps (the loops a plain flow produces); then the same K steps with
+    the network (5 % of the q_x rows recomputed plainly, fallback above 1e-3
+    sampled error or coupling 20)."""
+    import numpy as np
+
+    from synth import mlp_init, mlp_shape
+
+    dev = torch.device("cuda:0")
+    ctx = T.Context.from_workload(w, precision="fp32")
+    no4 = ctx.n_o ** 4
+    nb = 2 * ctx.Nq * ctx.n_dR
+    lam0, n = w["lam0"], w["n_steps"]
+    lam_k = lam0 * (w["lam_end"] / lam0) ** (K / n)
+    P = torch.zeros((ctx.Nq, ctx.B, ctx.B), dtype=torch.complex128, device=dev)
+    C = torch.zeros_like(P)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r0 = T.tufrg_flow(ctx, P, C, lam0, lam_k, n_steps=K, v_max=w["v_max"])
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    P0, C0 = P.clone(), C.clone()
+    # training data from plain loops at the scales of the K steps
+    n_lam = K
+    per = min(nb, n_rows // n_lam)
+    lams = lam0 * (w["lam_end"] / lam0) ** (np.arange(K) / n)
+    sizes = mlp_shape(11 + ctx.n_dR, 256, 2 * no4)
+    rng = np.random.default_rng(3)
+    X = torch.zeros((n_lam * per, sizes[0]), dtype=torch.float32, device=dev)
+    Y = torch.zeros((n_lam * per, sizes[-1]), dtype=torch.float32, device=dev)
+    Lc = torch.zeros((2, ctx.Nq, ctx.n_dR, no4), dtype=torch.complex128, device=dev)
+    t0 = time.perf_counter()
+    scales = []
+    for i, lam in enumerate(lams):
+        b = rng.choice(nb, size=per, replace=False)
+        q, ch, iD = ((b // ctx.n_dR) % ctx.Nq, b // (ctx.n_dR * ctx.Nq), b % ctx.n_dR)
+        q, ch, iD = (torch.from_numpy(a.astype(np.int32)).to(dev) for a in (q, ch, iD))
+        T.tufrg_loops_compact(ctx, lam, 1, Lc)
+        ys = Y[i * per:(i + 1) * per]
+        scales.append(T.tufrg_sur_targets(ctx, per, 1.0, Lc, ys, q, ch, iD))
+        T.tufrg_sur_features(ctx, per, lam, X[i * per:(i + 1) * per], q, ch, iD)
+        T.tufrg_sur_targets(ctx, per, scales[-1], Lc, ys, q, ch, iD)
+    del Lc
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = T.Mlp(sizes, mlp_init(sizes, seed=3))
+    t0 = time.perf_counter()
+    loss = None
+    for ep, lr in zip(epochs, (1e-3, 3e-4, 1e-4)):
+        loss = T.tufrg_mlp_train(net, X, Y, batch=2048, epochs=ep, lr=lr, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del X, Y
+    T.tufrg_sur_attach(ctx, net, lams, scales)
+    P.zero_()
+    C.zero_()
+    torch.cuda.synchronize()
+    T.tufrg_timing(ctx, True)
+    t0 = time.perf_counter()
+    r1 = T.tufrg_flow(ctx, P, C, lam0, lam_k, n_steps=K, v_max=w["v_max"], surrogate=True, sample_frac=0.05,
+                      sur_tol=1e-3, plain_above=20.0, sample_seed=3)
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    sur_ms, sur_n = T.tufrg_timing_read(ctx, T.TIMER_SURROGATE)
+    T.tufrg_timing(ctx, False)
+    err = max((P - P0).abs().max().item() / P0.abs().max().item(),
+              (C - C0).abs().max().item() / C0.abs().max().item())
+    # the same window at a looser sampled tolerance: what the network replaces when accepted
+    P.zero_()
+    C.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r2 = T.tufrg_flow(ctx, P, C, lam0, lam_k, n_steps=K, v_max=w["v_max"], surrogate=True, sample_frac=0.05,
+                      sur_tol=5e-2, plain_above=20.0, sample_seed=3)
+    torch.cuda.synchronize()
+    t_loose = time.perf_counter() - t0
+    err_loose = max((P - P0).abs().max().item() / P0.abs().max().item(),
+                    (C - C0).abs().max().item() / C0.abs().max().item())
+    entries = 2.0 * ctx.Nq * ctx.B ** 2
+    out = {
+        "metric": METRIC, "value": entries * K / t_sur, "unit": "loop entries/s", "n_gpus": 1, "steps": K,
+        "warmup": 0, "ms_per_step": t_sur / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": w["name"], "n_orb": w["n_o"], "n_ff": len(w["ff"]), "B": ctx.B, "Lq": w["Lq"],
+                   "n_ref": w["n_ref"], "Nq": ctx.Nq, "Nf": ctx.Nf,
+                   "step": f"first {K} of {n} Euler steps with the loop surrogate", "parallelism": "single GPU"},
+        "plain_fp32": {"ms_per_step": t_plain / K * 1e3, "value": entries * K / t_plain, "result": r0},
+        "surrogate": dict(r1, seconds=t_sur, network_ms=sur_ms, network_calls=sur_n),
+        "speedup_vs_plain_fp32": t_plain / t_sur, "rel_err_vs_plain_fp32": err,
+        "surrogate_tol_5e-2": dict(r2, seconds=t_loose, ms_per_step=t_loose / K * 1e3,
+                                   speedup_vs_plain_fp32=t_plain / t_loose, rel_err_vs_plain_fp32=err_loose),
+        "training": {"rows": n_lam * per, "scales": [float(x) for x in lams], "data_seconds": t_data,
+                     "train_seconds": t_train, "final_loss": loss, "net": sizes},
+        "roofline": None,
+    }
+    net.close()
+    ctx.close()
+    return out
+
+
 def batch_bench(T, torch, K, W):
     """32 independent Rashba/Hubbard instances of uneven size (seed 2), FP32
     loops and products, lockstep Euler steps 10 -> 1 through tufrg_batch_flow;
@@ -276,6 +379,9 @@ def main():
     K, W = args.steps, args.warmup
     if args.workload == "rashba_batch32":
         print(json.dumps(batch_bench(T, torch, K, W)))
+        return
+    if args.workload == "t2g_s13_L48":
+        print(json.dumps(surrogate_bench(T, torch, workload(args.workload), K)))
         return
     w = workload(args.workload)
     lam0, lam_mid = 10.0, 1.0

@@ -234,6 +234,7 @@ __global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (siz
                                                            const double *__restrict__ tw, const T *__restrict__ twk,
                                                            int Lq, int n_ref, int Lf,
                                                            int nkyb, int nkxc, int kxper, int q_first, int n_q,
+                                                           const int *__restrict__ rows,
                                                            int ch_first, int n_items, T lam, int deriv,
                                                            double *__restrict__ partial) {
   constexpr int NDY2 = 2 * NDY + 1;
@@ -254,7 +255,8 @@ __global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (siz
   w /= nqx;
   const int kxc = w % nkxc;
   const int chrel = w / nkxc, ch = ch_first + chrel;
-  const int qrel = qx * Lq + qy, qi = q_first + qrel;
+  // coarse q: consecutive from q_first, or whole q_x rows from a list
+  const int qrel = qx * Lq + qy, qi = rows ? rows[qx] * Lq + qy : q_first + qrel;
   const int nparts = nkyb * nkxc;
   const int qfx = (qi / Lq) * n_ref, qfy = (qi % Lq) * n_ref;
   const int ky_raw = kyb * 64 + tid;
@@ -368,11 +370,11 @@ static hipError_t launch_no2(const LoopArgs &a, hipStream_t st) {
   if (!ekv || !pi4 || !twk) return hipErrorInvalidValue;
   if (a.scheme == CUT_TEMPERATURE)
     hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_TEMPERATURE, QW>), grid, block, 0, st, ekv, pi4, a.tw, twk, a.Lq,
-                       a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.ch_first, n_items, (T)a.lam,
+                       a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.rows, a.ch_first, n_items, (T)a.lam,
                        a.deriv, a.partial);
   else
     hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_OMEGA, QW>), grid, block, 0, st, ekv, pi4, a.tw, twk, a.Lq,
-                       a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.ch_first, n_items, (T)a.lam,
+                       a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.rows, a.ch_first, n_items, (T)a.lam,
                        a.deriv, a.partial);
   return hipGetLastError();
 }

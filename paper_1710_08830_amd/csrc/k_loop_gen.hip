@@ -103,7 +103,8 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
                                                         const double *__restrict__ tw, const T *__restrict__ phy,
                                                         const int *__restrict__ pairs,
                                                         int n_pairs, int Lq, int n_ref, int Lf, int nparts,
-                                                        int q_first, int n_q, int ch_first, int n_ch, int ndx_out,
+                                                        int q_first, int n_q, const int *__restrict__ rows,
+                                                        int ch_first, int n_ch, int ndx_out,
                                                         T lam, int deriv, double *__restrict__ partial) {
   using SH = Shape<NDY>;
   constexpr int NPT = SH::N;
@@ -116,7 +117,8 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
   const int part = w % nparts;
   w /= nparts;
   const int chrel = w % n_ch, qrel = w / n_ch;
-  const int qi = q_first + qrel, ch = ch_first + chrel;
+  // coarse q: consecutive from q_first, or whole q_x rows from a list
+  const int qi = rows ? rows[qrel / Lq] * Lq + qrel % Lq : q_first + qrel, ch = ch_first + chrel;
   const int qfx = (qi / Lq) * n_ref, qfy = (qi % Lq) * n_ref;
   const int pidx = part * NTHR + tid;
   const bool active = pidx < n_pairs;
@@ -262,11 +264,11 @@ static hipError_t launch_gen(const LoopArgs &a, hipStream_t st) {
   const T *band = (const T *)a.band, *kv = (const T *)a.kv, *phy = (const T *)a.phy;
   if (a.scheme == CUT_TEMPERATURE)
     hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, CUT_TEMPERATURE, NTHR, KT>), grid, block, 0, st, band, kv, a.tw,
-                       phy, a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.ch_first, a.n_ch, a.ndx,
+                       phy, a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.rows, a.ch_first, a.n_ch, a.ndx,
                        (T)a.lam, a.deriv, a.partial);
   else
     hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, CUT_OMEGA, NTHR, KT>), grid, block, 0, st, band, kv, a.tw,
-                       phy, a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.ch_first, a.n_ch, a.ndx,
+                       phy, a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.rows, a.ch_first, a.n_ch, a.ndx,
                        (T)a.lam, a.deriv, a.partial);
   return hipGetLastError();
 }

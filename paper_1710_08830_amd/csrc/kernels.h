@@ -24,6 +24,7 @@ struct LoopArgs {
   int nkyb, nkxc;      // ky blocks of 64 lanes, kx chunks
   int ch_first, n_ch;  // channels 0 (pp) and/or 1 (ph)
   int q_first, n_q;    // coarse q range
+  const int *rows = nullptr;  // if set: q = whole q_x rows rows[0 .. n_q / Lq) (q_first unused)
   int scheme, deriv, prec;
   double lam;
   const void *band;    // band data (FP64 or FP32 by prec): two orbitals component-major

@@ -86,6 +86,7 @@ struct tufrg_ctx {
   double *d_samp = nullptr;                    // plain loops of sampled q_x rows, [row][2][Lq][nD][no4]
   int samp_rows = 0;
   unsigned long long *d_sbits = nullptr;       // max |diff|, max |ref|, float max
+  int *d_rows = nullptr, *h_rows = nullptr;    // sampled q_x rows (device, pinned host)
   unsigned long long *h_sbits = nullptr;       // pinned
   // set during tufrg_flow
   const tufrg_flow_opts *fopts = nullptr;
@@ -162,6 +163,8 @@ static void destroy_all(tufrg_ctx *c) {
   if (c->h_bits) (void)hipHostFree(c->h_bits);
   if (c->h_flag) (void)hipHostFree(c->h_flag);
   if (c->h_sbits) (void)hipHostFree(c->h_sbits);
+  if (c->h_rows) (void)hipHostFree(c->h_rows);
+  c->h_rows = nullptr;
   c->h_bits = nullptr;
   c->h_flag = nullptr;
   c->h_sbits = nullptr;
@@ -343,6 +346,8 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CHIP(hipHostMalloc((void **)&c->h_flag, 4 * sizeof(unsigned int), hipHostMallocDefault));
   CTRY(dalloc(c, &c->d_sbits, 4));
   CHIP(hipHostMalloc((void **)&c->h_sbits, 4 * sizeof(unsigned long long), hipHostMallocDefault));
+  CTRY(dalloc(c, &c->d_rows, c->Lq));
+  CHIP(hipHostMalloc((void **)&c->h_rows, c->Lq * sizeof(int), hipHostMallocDefault));
 
   // tables
   std::vector<double> twf(2 * c->Lf), twq(2 * c->Lq);
@@ -513,10 +518,11 @@ static tufrg_status compute_kval(tufrg_ctx *c, double lam, int deriv) {
 // (whole q_x rows) into dst, compact [n_ch][n_q][nD][no4]; regulator values
 // must be current (compute_kval)
 static tufrg_status loops_range(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch, int q_first, int n_q,
-                                double *dst) {
+                                double *dst, const int *rows = nullptr) {
   LoopArgs a = loop_args(c, lam, deriv, ch_first, n_ch);
   a.q_first = q_first;
   a.n_q = n_q;
+  a.rows = rows;
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
   HIPCHK(c, launch_loop(a, c->st));
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
@@ -593,20 +599,24 @@ static tufrg_status surrogate_loops(tufrg_ctx *c, double lam) {
     const int row = (int)(splitmix64(o->sample_seed ^ splitmix64(ctr * 0x100000001B3ull + j)) % (uint64_t)c->Lq);
     if (std::find(rows.begin(), rows.end(), row) == rows.end()) rows.push_back(row);
   }
+  // plain loops of the sampled rows in one launch: [2][nr * Lq][nD][no4]
   const size_t rowsz = 2 * (size_t)c->Lq * blk * 2;  // doubles of one sampled row, both channels
   if (nr > c->samp_rows) {
     TRY(dalloc(c, &c->d_samp, rowsz * nr));
     c->samp_rows = nr;
   }
+  for (int j = 0; j < nr; ++j) c->h_rows[j] = rows[j];
+  HIPCHK(c, hipMemcpyAsync(c->d_rows, c->h_rows, nr * sizeof(int), hipMemcpyHostToDevice, c->st));
   TRY(compute_kval(c, lam, 1));
-  for (int j = 0; j < nr; ++j)
-    TRY(loops_range(c, lam, 1, 0, 2, rows[j] * c->Lq, c->Lq, c->d_samp + j * rowsz));
+  TRY(loops_range(c, lam, 1, 0, 2, 0, nr * c->Lq, c->d_samp, c->d_rows));
+  auto net_at = [&](int ch, int j) { return c->d_loop + 2 * (((size_t)ch * c->Nq + (size_t)rows[j] * c->Lq) * blk); };
+  auto plain_at = [&](int ch, int j) {
+    return c->d_samp + 2 * (((size_t)ch * nr * c->Lq + (size_t)j * c->Lq) * blk);
+  };
   HIPCHK(c, hipMemsetAsync(c->d_sbits, 0, 2 * sizeof(unsigned long long), c->st));
   for (int j = 0; j < nr; ++j)
     for (int ch = 0; ch < 2; ++ch)
-      HIPCHK(c, launch_sur_compare((long long)c->Lq * blk,
-                                   c->d_loop + 2 * (((size_t)ch * c->Nq + (size_t)rows[j] * c->Lq) * blk),
-                                   c->d_samp + j * rowsz + 2 * (size_t)ch * c->Lq * blk, c->d_sbits, c->st));
+      HIPCHK(c, launch_sur_compare((long long)c->Lq * blk, net_at(ch, j), plain_at(ch, j), c->d_sbits, c->st));
   HIPCHK(c, hipMemcpyAsync(c->h_sbits, c->d_sbits, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   double dmax, rmax;
@@ -625,9 +635,8 @@ static tufrg_status surrogate_loops(tufrg_ctx *c, double lam) {
   }
   for (int j = 0; j < nr; ++j)
     for (int ch = 0; ch < 2; ++ch)
-      HIPCHK(c, hipMemcpyAsync(c->d_loop + 2 * (((size_t)ch * c->Nq + (size_t)rows[j] * c->Lq) * blk),
-                               c->d_samp + j * rowsz + 2 * (size_t)ch * c->Lq * blk,
-                               2 * sizeof(double) * c->Lq * blk, hipMemcpyDeviceToDevice, c->st));
+      HIPCHK(c, hipMemcpyAsync(net_at(ch, j), plain_at(ch, j), 2 * sizeof(double) * c->Lq * blk,
+                               hipMemcpyDeviceToDevice, c->st));
   r->n_surrogate++;
   return TUFRG_OK;
 }

@@ -353,6 +353,8 @@ def main():
                     help="synthetic workload (the headline line uses the default)")
     ap.add_argument("--no-dp", action="store_true", help="skip the Dormand-Prince flows")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-assisted flow")
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16x3"],
+                    help="arithmetic of the timed loops (bf16x3: six spin-orbitals, matrix cores)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the q-sharded multi-GPU "
@@ -410,7 +412,7 @@ def main():
             T.tufrg_timing(ctx, False)
         return dt, res, loop_ms, loop_n
 
-    ctx32, P32, C32 = make("fp32")
+    ctx32, P32, C32 = make(args.prec)
     dt32, res32, loop_ms, loop_n = timed_steps(ctx32, P32, C32, timing=True)
     B, Nq, Nf = ctx32.B, ctx32.Nq, ctx32.Nf
     entries = 2.0 * Nq * B * B
@@ -423,7 +425,7 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "loop entries/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": dt32 / K * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
         "config": {"workload": args.workload, "n_orb": w["n_o"], "n_ff": len(w["ff"]), "B": B,
                    "Lq": w["Lq"], "n_ref": w["n_ref"], "Nq": Nq, "Nf": Nf, "cutoff": w["cutoff"],
                    "step": "Euler step: loops + projections + bundles + update",

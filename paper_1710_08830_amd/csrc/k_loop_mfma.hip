@@ -1,0 +1,408 @@
+// Form-factor projected orbital loops for six spin-orbitals on the matrix
+// cores (BF16 split products, FP32 accumulation).
+//
+// Same quantity as the vector-unit kernel (k_loop_gen.hip):
+//   Lc(q)[dR][(a,b,c,d)] = 1/Nf sum_k e^{-ik.dR} sum_m Pi_m(k)_ac W_m(k)_bd,
+// with W_m = sum_n L_mn X_n.  Along one kx row the ky sum and the separable ky
+// phases form one dense contraction per row:
+//   Y[(phi, x)][y] = sum_{ky, m} phi(ky) Pi_m(ky)_x W_m(ky)_y,
+// x = (a, c) with a <= c (the other half follows from hermiticity),
+// y = (b, d), phi in {1, cos(theta dy), -sin(theta dy)}, theta = 2 pi ky / Lf.
+// Written over the reals (K index = (ky, m, re/im)), it is a GEMM of
+// (NPHI * 21) x (12 per ky) by (12 per ky) x 72 per row, done with
+// v_mfma_f32_16x16x32_bf16 on operands split as v = hi + lo (both BF16) and
+// the three products hi*hi + hi*lo + lo*hi accumulated in FP32 (about 16
+// significant bits per product).
+//
+// loop_mfma_kernel: one workgroup (4 waves) per coarse q of one channel; per
+//   tile of KT ky it stages Pi, the loop kernels and W in LDS, writes the B
+//   operand (W, split) in the lane order of the instruction, and each wave
+//   accumulates 3 of the 12 row tiles by 5 column tiles.  At the end of a row
+//   the 16 x 16 tiles go to a row buffer Y in HBM.
+// loop_rowsum_kernel: per entry pair, Lc[(dx, dy)] = sum_kx e^{-i kx dx} Y(dy)
+//   with Y(+-dy) = A +- iB from the cos and -sin rows; writes the same partial
+//   layout as the vector-unit kernel.
+#include "common.h"
+#include "kernels.h"
+
+namespace tufrg {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int NO = 6, NO2 = 36, PK = NO * NO2, NC = NO + PK, NIT = NC + NO;
+constexpr int XC = 21;               // x = (a, c), a <= c
+constexpr int NCOL = 72, NT = 5;     // columns (y, re/im); 16-wide column tiles
+constexpr int KT = 8;                // ky per tile
+constexpr int KS = 12 * KT / 32;     // K steps of 32 per tile
+constexpr int NW = 4, NTHR = 64 * NW;
+constexpr int BFRAG = KS * NT * 64 * 8;  // BF16 values of the B operand of one tile
+
+// x index -> (a, c)
+__device__ constexpr int XA[XC] = {0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 2, 2, 2, 2, 3, 3, 3, 4, 4, 5};
+__device__ constexpr int XCc[XC] = {0, 1, 2, 3, 4, 5, 1, 2, 3, 4, 5, 2, 3, 4, 5, 3, 4, 5, 4, 5, 5};
+
+// packed Hermitian slot of (a, c): diagonal reals first, then Re, Im of lo < hi
+__device__ inline void packed_slot(int a, int c, int &re, int &im, float &sgn) {
+  if (a == c) {
+    re = a;
+    im = -1;
+    sgn = 0.f;
+    return;
+  }
+  const int lo = a < c ? a : c, hi = a < c ? c : a;
+  int p = 0;
+  for (int x = 0; x < lo; ++x) p += NO - 1 - x;
+  p += hi - lo - 1;
+  re = NO + 2 * p;
+  im = re + 1;
+  sgn = a < c ? 1.f : -1.f;
+}
+
+__device__ inline void split(float v, __bf16 &hi, __bf16 &lo) {
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
+
+}  // namespace
+
+template <int NDY, int SCHEME>
+__global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restrict__ band,
+                                                            const float *__restrict__ kv,
+                                                            const float *__restrict__ phy, int Lq, int n_ref,
+                                                            int Lf, int q_first, const int *__restrict__ rows,
+                                                            int ch, float lam, int deriv, float *__restrict__ Y) {
+  constexpr int NPHI = 2 * NDY + 1, ROWS = NPHI * XC, MT = (ROWS + 15) / 16, MTW = (MT + NW - 1) / NW;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4;
+  const int qrel = blockIdx.x;
+  const int qi = rows ? rows[qrel / Lq] * Lq + qrel % Lq : q_first + qrel;
+  const int qfx = (qi / Lq) * n_ref, qfy = (qi % Lq) * n_ref;
+  const float sg = ch == 0 ? 1.f : -1.f;
+
+  __shared__ float sE[KT][2][NO], sK[KT][2][NO], sL[KT][NO][NO];
+  __shared__ float sPk[KT][PK];            // Pi_m(k) packed
+  __shared__ float sX[KT][PK];             // X_n(k') packed (transposed for ph)
+  __shared__ float sW[KT][PK];             // W_m(k) packed
+  __shared__ float2 sPc[KT * NO][XC];      // Pi_m(k)_x for x = (a <= c)
+  __shared__ float sPh[KT][NPHI];          // 1, cos, -sin
+  __shared__ __align__(16) __bf16 sBh[BFRAG], sBl[BFRAG];
+  __shared__ int sSlotY[NO2][2];           // packed slots (Re, Im) of y = (b, d); Im < 0 on the diagonal
+  __shared__ float sSgnY[NO2];
+  __shared__ int sSlotX[XC][2];
+  __shared__ float sSgnX[XC];
+  if (tid < NO2) {
+    int re, im;
+    float sgn;
+    packed_slot(tid / NO, tid % NO, re, im, sgn);
+    sSlotY[tid][0] = re;
+    sSlotY[tid][1] = im;
+    sSgnY[tid] = sgn;
+  } else if (tid < NO2 + XC) {
+    const int xi = tid - NO2;
+    int re, im;
+    float sgn;
+    packed_slot(XA[xi], XCc[xi], re, im, sgn);
+    sSlotX[xi][0] = re;
+    sSlotX[xi][1] = im;
+    sSgnX[xi] = sgn;
+  }
+
+  // padding columns 72..79 of the last column tile stay zero
+  for (int i = tid; i < KS * 64 * 8; i += NTHR) {
+    const int s = i / (64 * 8), l = (i / 8) % 64, r = i % 8;
+    if ((l & 15) >= 8) {
+      const int idx = ((s * NT + (NT - 1)) * 64 + l) * 8 + r;
+      sBh[idx] = (__bf16)0.f;
+      sBl[idx] = (__bf16)0.f;
+    }
+  }
+
+  f32x4 acc[MTW][NT];
+  float *Yq = Y + (size_t)qrel * Lf * ROWS * NCOL;
+  for (int kx = 0; kx < Lf; ++kx) {
+    int kpx = ch == 0 ? qfx - kx : kx - qfx;
+    kpx += kpx < 0 ? Lf : 0;
+#pragma unroll
+    for (int j = 0; j < MTW; ++j)
+#pragma unroll
+      for (int n = 0; n < NT; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ky0 = 0; ky0 < Lf; ky0 += KT) {
+      const int kt = min(KT, Lf - ky0);
+      __syncthreads();
+      // band values of k and k' = q - k (pp) or k - q (ph)
+      for (int i = tid; i < KT * 2 * NIT; i += NTHR) {
+        const int r = i % NIT, t2 = i / NIT, j = t2 >> 1, side = t2 & 1;
+        const int ky = ky0 + j < Lf ? ky0 + j : Lf - 1;
+        int kpy = ch == 0 ? qfy - ky : ky - qfy;
+        kpy += kpy < 0 ? Lf : 0;
+        const unsigned kk = side ? (unsigned)kpx * Lf + kpy : (unsigned)kx * Lf + ky;
+        if (r < NO) {
+          sE[j][side][r] = band[(size_t)kk * NC + r];
+        } else if (r < NC) {
+          const int p = r - NO, pl = p % NO2;
+          float x = band[(size_t)kk * NC + r];
+          if (side == 0) {
+            sPk[j][p] = x;
+          } else {
+            if (ch == 1 && pl >= NO && ((pl - NO) & 1)) x = -x;
+            sX[j][p] = x;
+          }
+        } else {
+          sK[j][side][r - NC] = kv[(size_t)kk * NO + (r - NC)];
+        }
+      }
+      for (int i = tid; i < KT * NPHI; i += NTHR) {
+        const int j = i / NPHI, f = i % NPHI;
+        const int ky = ky0 + j < Lf ? ky0 + j : Lf - 1;
+        float v = 1.f;
+        if (f > 0) v = phy[((size_t)ky * NDY + ((f - 1) % NDY)) * 2 + (f > NDY ? 1 : 0)];
+        sPh[j][f] = j < kt ? v : 0.f;  // ky beyond the mesh contributes nothing
+      }
+      __syncthreads();
+      for (int i = tid; i < KT * NO2; i += NTHR) {
+        const int j = i / NO2, m = (i / NO) % NO, n = i % NO;
+        const float x = sE[j][0][m], y = -sg * sE[j][1][n];
+        sL[j][m][n] = sg * divided_difference(x, y, sK[j][0][m], -sg * sK[j][1][n], lam, SCHEME, deriv);
+      }
+      for (int i = tid; i < KT * NO * XC; i += NTHR) {
+        const int jm = i / XC, xi = i % XC, j = jm / NO, m = jm % NO;
+        const int re = sSlotX[xi][0], im = sSlotX[xi][1];
+        sPc[jm][xi] = make_float2(sPk[j][m * NO2 + re], im >= 0 ? sSgnX[xi] * sPk[j][m * NO2 + im] : 0.f);
+      }
+      __syncthreads();
+      for (int i = tid; i < KT * PK; i += NTHR) {
+        const int j = i / PK, mp = i % PK, m = mp / NO2, pl = mp % NO2;
+        float a = 0.f;
+#pragma unroll
+        for (int n = 0; n < NO; ++n) a = fmaf(sL[j][m][n], sX[j][n * NO2 + pl], a);
+        sW[j][mp] = a;
+      }
+      __syncthreads();
+      // B operand: rows k = (ky, m, re/im), columns (y, re/im), split and in
+      // lane order.  For W = wr + i wi the 2 x 2 block of (k re, k im) x
+      // (col re, col im) is [[wr, wi], [-wi, wr]]: the two k of one column are
+      // adjacent slots of one lane, so each column is one 32-bit store.
+      for (int i = tid; i < KT * NO * NO2; i += NTHR) {
+        const int jm = i / NO2, y = i % NO2, j = jm / NO, m = jm % NO;
+        const int re = sSlotY[y][0], im = sSlotY[y][1];
+        const float wr = sW[j][m * NO2 + re], wi = im >= 0 ? sSgnY[y] * sW[j][m * NO2 + im] : 0.f;
+        const int k = 2 * jm, s = k >> 5, kk = k & 31, col = 2 * y, n = col >> 4;
+        const int idx = ((s * NT + n) * 64 + (kk >> 3) * 16 + (col & 15)) * 8 + (kk & 7);  // even
+        __bf16 hr, lr, hi, li;
+        split(wr, hr, lr);
+        split(wi, hi, li);
+        // column re: (wr, -wi); column im (next lane, 8 values on): (wi, wr)
+        *(unsigned *)&sBh[idx] = (unsigned)__builtin_bit_cast(unsigned short, hr) |
+                                 ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16) ^ 0x80000000u;
+        *(unsigned *)&sBl[idx] = (unsigned)__builtin_bit_cast(unsigned short, lr) |
+                                 ((unsigned)__builtin_bit_cast(unsigned short, li) << 16) ^ 0x80000000u;
+        *(unsigned *)&sBh[idx + 8] = (unsigned)__builtin_bit_cast(unsigned short, hi) |
+                                     ((unsigned)__builtin_bit_cast(unsigned short, hr) << 16);
+        *(unsigned *)&sBl[idx + 8] = (unsigned)__builtin_bit_cast(unsigned short, li) |
+                                     ((unsigned)__builtin_bit_cast(unsigned short, lr) << 16);
+      }
+      __syncthreads();
+      // A operand from Pi and the phases, then 3 products per tile pair
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        bf16x8 bh[NT], bl[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+          bh[n] = *(const bf16x8 *)&sBh[((s * NT + n) * 64 + lane) * 8];
+          bl[n] = *(const bf16x8 *)&sBl[((s * NT + n) * 64 + lane) * 8];
+        }
+#pragma unroll
+        for (int jt = 0; jt < MTW; ++jt) {
+          const int mt = wv + NW * jt;
+          if (mt >= MT) break;
+          const int row = mt * 16 + (lane & 15);
+          const bool rv = row < ROWS;
+          const int f = rv ? row / XC : 0, xi = rv ? row % XC : 0;
+          bf16x8 ah, al;
+#pragma unroll
+          for (int r = 0; r < 8; r += 2) {
+            const int k = 32 * s + 8 * g + r;  // even: (ky, m) = k / 2, re and im
+            const int jm = k >> 1, j = jm / NO;
+            const float2 p = sPc[jm][xi];
+            const float ph = rv ? sPh[j][f] : 0.f;
+            __bf16 h0, l0, h1, l1;
+            split(ph * p.x, h0, l0);
+            split(ph * p.y, h1, l1);
+            ah[r] = h0;
+            al[r] = l0;
+            ah[r + 1] = h1;
+            al[r + 1] = l1;
+          }
+          // independent accumulators back to back
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[n], acc[jt][n], 0, 0, 0);
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[n], acc[jt][n], 0, 0, 0);
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[n], acc[jt][n], 0, 0, 0);
+        }
+      }
+    }
+    // row tile (mt, n): lane holds rows 4 g + r, column lane % 16
+    float *Yr = Yq + (size_t)kx * ROWS * NCOL;
+#pragma unroll
+    for (int jt = 0; jt < MTW; ++jt) {
+      const int mt = wv + NW * jt;
+      if (mt >= MT) break;
+#pragma unroll
+      for (int n = 0; n < NT; ++n) {
+        const int col = n * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = mt * 16 + 4 * g + r;
+          if (row < ROWS && col < NCOL) Yr[(size_t)row * NCOL + col] = acc[jt][n][r];
+        }
+      }
+    }
+  }
+}
+
+// Lc[(dx, dy)] of each entry pair from the rows of Y (see the vector-unit kernel
+// for the pair and partial conventions)
+template <int NDY>
+__global__ __launch_bounds__(256) void loop_rowsum_kernel(const float *__restrict__ Y, const double *__restrict__ tw,
+                                                          const int *__restrict__ pairs, int n_pairs, int Lf,
+                                                          int nparts, int slot0, int n_slots, int ndx_out,
+                                                          double *__restrict__ partial) {
+  constexpr int NPHI = 2 * NDY + 1, ROWS = NPHI * XC;
+  constexpr int NPT = (NDY == 4) ? 41 : 25;
+  const int part = blockIdx.x % nparts, qrel = blockIdx.x / nparts;
+  const int pidx = part * blockDim.x + threadIdx.x;
+  if (pidx >= n_pairs) return;
+  const int tau = pairs[2 * pidx], taub = pairs[2 * pidx + 1];
+  constexpr int NO3 = NO * NO2, NO4 = NO2 * NO2;
+  const int a = tau / NO3, b = (tau / NO2) % NO, c = (tau / NO) % NO, d = tau % NO;
+  int xi = 0;
+  for (int x = 0; x < XC; ++x)
+    if (XA[x] == a && XCc[x] == c) xi = x;
+  const int y = b * NO + d;
+  const float *Yq = Y + (size_t)qrel * Lf * ROWS * NCOL;
+  float zr[NPT], zi[NPT];
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) zr[i] = zi[i] = 0.f;
+  for (int kx = 0; kx < Lf; ++kx) {
+    const float *Yr = Yq + (size_t)kx * ROWS * NCOL + 2 * y;
+    float vr[NPHI], vi[NPHI];
+#pragma unroll
+    for (int f = 0; f < NPHI; ++f) {
+      const float2 v = *(const float2 *)(Yr + (size_t)(f * XC + xi) * NCOL);
+      vr[f] = v.x;
+      vi[f] = v.y;
+    }
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+      int dx, dy;
+      if (NDY == 4) {
+        // diamond |dx| + |dy| <= 4, rows dx = -4..4
+        int x = -4, s0 = 0;
+        while (x < 4 && s0 + 2 * (4 - (x < 0 ? -x : x)) + 1 <= i) {
+          s0 += 2 * (4 - (x < 0 ? -x : x)) + 1;
+          ++x;
+        }
+        dx = x;
+        dy = i - s0 - (4 - (x < 0 ? -x : x));
+      } else {
+        dx = i / 5 - 2;
+        dy = i % 5 - 2;
+      }
+      float yr, yi;
+      if (dy == 0) {
+        yr = vr[0];
+        yi = vi[0];
+      } else {
+        const int ad = dy > 0 ? dy : -dy;
+        const float ar = vr[ad], ai = vi[ad], br = vr[NDY + ad], bi = vi[NDY + ad];
+        yr = dy > 0 ? ar - bi : ar + bi;
+        yi = dy > 0 ? ai + br : ai - br;
+      }
+      const int adx = dx < 0 ? -dx : dx;
+      const int jj = (kx * adx) % Lf;
+      const float pr = (float)tw[2 * jj], pi = dx < 0 ? -(float)tw[2 * jj + 1] : (float)tw[2 * jj + 1];
+      zr[i] = fmaf(pr, yr, fmaf(-pi, yi, zr[i]));
+      zi[i] = fmaf(pr, yi, fmaf(pi, yr, zi[i]));
+    }
+  }
+  const int ndy2 = 2 * NDY + 1;
+  const size_t pbase = (size_t)(slot0 + qrel) * (size_t)(ndx_out * ndy2 * NO4);
+  (void)n_slots;
+#pragma unroll
+  for (int i = 0; i < NPT; ++i) {
+    int dx, dy;
+    if (NDY == 4) {
+      int x = -4, s0 = 0;
+      while (x < 4 && s0 + 2 * (4 - (x < 0 ? -x : x)) + 1 <= i) {
+        s0 += 2 * (4 - (x < 0 ? -x : x)) + 1;
+        ++x;
+      }
+      dx = x;
+      dy = i - s0 - (4 - (x < 0 ? -x : x));
+    } else {
+      dx = i / 5 - 2;
+      dy = i % 5 - 2;
+    }
+    if (dx >= 0) {
+      const size_t idx = pbase + (size_t)(dx * ndy2 + dy + NDY) * NO4 + tau;
+      partial[2 * idx] = (double)zr[i];
+      partial[2 * idx + 1] = (double)zi[i];
+    }
+    if (dx <= 0 && taub != tau) {
+      const size_t idx = pbase + (size_t)(-dx * ndy2 - dy + NDY) * NO4 + taub;
+      partial[2 * idx] = (double)zr[i];
+      partial[2 * idx + 1] = -(double)zi[i];
+    }
+  }
+}
+
+size_t loop_mfma_rowbuf_floats(int ndy, int Lf) {
+  const int rows = (2 * ndy + 1) * XC;
+  return (size_t)Lf * rows * NCOL;
+}
+
+// one channel, coarse q [q_first, q_first + n_q) (or rows); Y holds n_q row buffers;
+// the partials go to slot (q index within the launch) of a one-channel LoopArgs layout
+hipError_t launch_loop_mfma(const LoopArgs &a, int ch, float *Y, hipStream_t st) {
+  if (a.n_o != 6 || !a.pairs || a.n_pairs <= 0 || !Y) return hipErrorInvalidValue;
+  const float *band = (const float *)a.band, *kv = (const float *)a.kv, *phy = (const float *)a.phy;
+  dim3 grid(a.n_q), block(NTHR);
+  const float lam = (float)a.lam;
+  if (a.ndx == 5 && a.ndy == 4) {
+    if (a.scheme == CUT_TEMPERATURE)
+      hipLaunchKernelGGL((loop_mfma_kernel<4, CUT_TEMPERATURE>), grid, block, 0, st, band, kv, phy, a.Lq, a.n_ref,
+                         a.Lf, a.q_first, a.rows, ch, lam, a.deriv, Y);
+    else
+      hipLaunchKernelGGL((loop_mfma_kernel<4, CUT_OMEGA>), grid, block, 0, st, band, kv, phy, a.Lq, a.n_ref, a.Lf,
+                         a.q_first, a.rows, ch, lam, a.deriv, Y);
+  } else if (a.ndx == 3 && a.ndy == 2) {
+    if (a.scheme == CUT_TEMPERATURE)
+      hipLaunchKernelGGL((loop_mfma_kernel<2, CUT_TEMPERATURE>), grid, block, 0, st, band, kv, phy, a.Lq, a.n_ref,
+                         a.Lf, a.q_first, a.rows, ch, lam, a.deriv, Y);
+    else
+      hipLaunchKernelGGL((loop_mfma_kernel<2, CUT_OMEGA>), grid, block, 0, st, band, kv, phy, a.Lq, a.n_ref, a.Lf,
+                         a.q_first, a.rows, ch, lam, a.deriv, Y);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int np = (a.n_pairs + 255) / 256;
+  dim3 g2(a.n_q * np), b2(256);
+  if (a.ndy == 4)
+    hipLaunchKernelGGL(loop_rowsum_kernel<4>, g2, b2, 0, st, Y, a.tw, a.pairs, a.n_pairs, a.Lf, np, 0, a.n_q, a.ndx,
+                       a.partial);
+  else
+    hipLaunchKernelGGL(loop_rowsum_kernel<2>, g2, b2, 0, st, Y, a.tw, a.pairs, a.n_pairs, a.Lf, np, 0, a.n_q, a.ndx,
+                       a.partial);
+  return hipGetLastError();
+}
+
+}  // namespace tufrg

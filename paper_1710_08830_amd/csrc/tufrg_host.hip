@@ -87,6 +87,8 @@ struct tufrg_ctx {
   int samp_rows = 0;
   unsigned long long *d_sbits = nullptr;       // max |diff|, max |ref|, float max
   int *d_rows = nullptr, *h_rows = nullptr;    // sampled q_x rows (device, pinned host)
+  float *d_yrow = nullptr;                     // BF16X3 loops: row buffers of a chunk of coarse q
+  int mfma_chunk = 0;
   unsigned long long *h_sbits = nullptr;       // pinned
   // set during tufrg_flow
   const tufrg_flow_opts *fopts = nullptr;
@@ -182,8 +184,10 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   if (s->ff_R[0] != 0 || s->ff_R[1] != 0) return fail(nullptr, TUFRG_E_INVAL, "ff_R[0] must be (0,0)");
   if (s->cutoff != TUFRG_CUT_TEMPERATURE && s->cutoff != TUFRG_CUT_OMEGA)
     return fail(nullptr, TUFRG_E_INVAL, "unknown cutoff");
-  if (s->precision != TUFRG_FP64 && s->precision != TUFRG_FP32)
+  if (s->precision != TUFRG_FP64 && s->precision != TUFRG_FP32 && s->precision != TUFRG_BF16X3)
     return fail(nullptr, TUFRG_E_INVAL, "unknown precision");
+  if (s->precision == TUFRG_BF16X3 && m->n_orb != 6)
+    return fail(nullptr, TUFRG_E_UNSUPPORTED, "BF16X3 loops are built for six spin-orbitals");
   if (s->n_ref < 1 || s->Lq < 1 || (long long)s->Lq * s->n_ref > 4096)
     return fail(nullptr, TUFRG_E_INVAL, "mesh sizes out of range");
   int rmax = 0;
@@ -517,8 +521,34 @@ static tufrg_status compute_kval(tufrg_ctx *c, double lam, int deriv) {
 // loops of channels [ch_first, ch_first + n_ch) and coarse q [q_first, q_first + n_q)
 // (whole q_x rows) into dst, compact [n_ch][n_q][nD][no4]; regulator values
 // must be current (compute_kval)
+static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch, int q_first,
+                                     int n_q, double *dst, const int *rows) {
+  if (!c->d_yrow) {
+    // whole q_x rows per chunk, about 512 coarse q (two workgroups per compute unit)
+    c->mfma_chunk = std::max(1, 512 / c->Lq) * c->Lq;
+    TRY(dalloc(c, &c->d_yrow, (size_t)c->mfma_chunk * loop_mfma_rowbuf_floats(c->ndy, c->Lf)));
+  }
+  const size_t blk = (size_t)c->nD * c->no4;
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
+  for (int chi = 0; chi < n_ch; ++chi) {
+    const int ch = ch_first + chi;
+    for (int q0 = 0; q0 < n_q; q0 += c->mfma_chunk) {
+      const int nq = std::min(c->mfma_chunk, n_q - q0);
+      LoopArgs a = loop_args(c, lam, deriv, ch, 1);
+      a.q_first = rows ? 0 : q_first + q0;
+      a.n_q = nq;
+      a.rows = rows ? rows + q0 / c->Lq : nullptr;
+      HIPCHK(c, launch_loop_mfma(a, ch, c->d_yrow, c->st));
+      HIPCHK(c, launch_loop_finalize(a, c->nD, c->d_dlist, dst + 2 * ((size_t)chi * n_q + q0) * blk, c->st));
+    }
+  }
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
+  return TUFRG_OK;
+}
+
 static tufrg_status loops_range(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch, int q_first, int n_q,
                                 double *dst, const int *rows = nullptr) {
+  if (c->prec == TUFRG_BF16X3) return loops_range_mfma(c, lam, deriv, ch_first, n_ch, q_first, n_q, dst, rows);
   LoopArgs a = loop_args(c, lam, deriv, ch_first, n_ch);
   a.q_first = q_first;
   a.n_q = n_q;

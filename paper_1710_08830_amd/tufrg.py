@@ -25,7 +25,7 @@ TUFRG_OK = 0
 STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NONFINITE", 5: "E_STEPSIZE",
           6: "E_UNSUPPORTED"}
 CUT_TEMPERATURE, CUT_OMEGA = 0, 1
-FP64, FP32 = 0, 1
+FP64, FP32, BF16X3 = 0, 1, 2
 PP, PH = 0, 1
 
 SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "tufrg_band_data",
@@ -178,7 +178,7 @@ class Context:
                   hop_t.ctypes.data_as(ctypes.POINTER(c64)), float(mu),
                   V0.ctypes.data_as(ctypes.POINTER(c64)))
         cut = {"temperature": CUT_TEMPERATURE, "omega": CUT_OMEGA}.get(cutoff, cutoff)
-        prec = {"fp64": FP64, "fp32": FP32}.get(precision, precision)
+        prec = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}.get(precision, precision)
         s = Setup(ff.shape[0], ff.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(Lq), int(n_ref),
                   int(cut), int(prec))
         h = ctypes.c_void_p()
@@ -382,7 +382,7 @@ class Batch:
                               hop_t.ctypes.data_as(ctypes.POINTER(c64)), float(w["mu"]),
                               V0.ctypes.data_as(ctypes.POINTER(c64)))
             cut = {"temperature": CUT_TEMPERATURE, "omega": CUT_OMEGA}.get(w["cutoff"], w["cutoff"])
-            prec = {"fp64": FP64, "fp32": FP32}.get(precision, precision)
+            prec = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}.get(precision, precision)
             setups[i] = Setup(ff.shape[0], ff.ctypes.data_as(_i32p), int(w["Lq"]), int(w["n_ref"]), int(cut),
                               int(prec))
         h = ctypes.c_void_p()

@@ -40,6 +40,12 @@ def test_create_rejects_bad_setups(T, over, status, text):
     assert text in str(ei.value)
 
 
+def test_bf16x3_needs_six_orbitals(T):
+    with pytest.raises(T.TufrgError) as ei:
+        T.Context(**_args(precision="bf16x3"))
+    assert ei.value.status == 6
+
+
 def test_create_rejects_unsupported_orbital_count(T):
     hop_R = np.array([[1, 0], [-1, 0]])
     hop_t = np.zeros((2, 3, 3), dtype=np.complex128)

@@ -3,7 +3,9 @@
 Every call goes through the C ABI (ctypes binding).  Tolerances: FP64 paths
 1e-10 relative (max-norm over all entries relative to the largest reference
 entry; the oracle and the kernels sum in different orders and the kernels use
-a two-point rule for near-degenerate divided differences), FP32 loops 1e-5.
+a two-point rule for near-degenerate divided differences), FP32 loops 1e-5,
+BF16-split loops on the matrix cores 1e-4 (each product carries about 16
+significant bits).
 """
 
 import numpy as np
@@ -20,7 +22,7 @@ from synth import (ff_shell, hubbard_hoppings, kanamori_V0, onsite_V0, random_ex
 from tests._layout import (c_to_matrix, p_to_matrix, ph_loop_to_matrix,  # noqa: E402
                            pp_loop_to_matrix)
 
-TOL = {"fp64": 1e-10, "fp32": 1e-5}
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "bf16x3": 1e-4}
 
 
 @pytest.fixture(scope="module")
@@ -250,5 +252,55 @@ def test_full_size_t2g_loops_on_sampled_q(T):
         for qi in (0, 531):
             ref = conv(otu.loops(st, channel, lam, q_list=[qi]))[0]
             assert rel(L[qi].cpu().numpy(), ref) < TOL["fp32"], (channel, qi)
+        del L
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["t2g13", "t2g9"])
+@pytest.mark.parametrize("channel", ["pp", "ph"])
+@pytest.mark.parametrize("deriv", [1, 0])
+def test_bf16x3_bubble_matches_oracle(T, name, channel, deriv):
+    c = _case(name)
+    ctx = _ctx(T, c, "bf16x3")
+    st = _setup(c)
+    lam = 0.35
+    L = _zeros(ctx)
+    T.tufrg_bubble(ctx, T.PP if channel == "pp" else T.PH, lam, deriv, L)
+    torch.cuda.synchronize()
+    ref_t = otu.loops(st, channel, lam, deriv=bool(deriv))
+    ref = pp_loop_to_matrix(ref_t) if channel == "pp" else ph_loop_to_matrix(ref_t)
+    assert rel(L.cpu().numpy(), ref) < TOL["bf16x3"]
+
+
+def test_bf16x3_rhs_matches_oracle(T):
+    c = _case("t2g9")
+    ctx = _ctx(T, c, "bf16x3")
+    st = _setup(c)
+    P = 0.2 * random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=7)
+    C = 0.2 * random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=8)
+    Pd = torch.from_numpy(p_to_matrix(P)).to(dev())
+    Cd = torch.from_numpy(c_to_matrix(C)).to(dev())
+    dP, dC = _zeros(ctx), _zeros(ctx)
+    T.tufrg_rhs(ctx, 0.4, Pd, Cd, dP, dC)
+    torch.cuda.synchronize()
+    rP, rC = otu.rhs(st, 0.4, P, C)
+    assert rel(dP.cpu().numpy(), p_to_matrix(rP)) < 3 * TOL["bf16x3"]
+    assert rel(dC.cpu().numpy(), c_to_matrix(rC)) < 3 * TOL["bf16x3"]
+
+
+def test_bf16x3_full_size_t2g_loops_on_sampled_q(T):
+    """The six-orbital 32x32 workload in its own arithmetic (BF16 split on the
+    matrix cores), two q recomputed by the oracle."""
+    w = workload("t2g_s13_L32")
+    st = otu.TUSetup.from_workload(w)
+    lam = 0.3
+    ctx = T.Context.from_workload(w, precision="bf16x3")
+    for channel, code, conv in (("pp", T.PP, pp_loop_to_matrix), ("ph", T.PH, ph_loop_to_matrix)):
+        L = _zeros(ctx)
+        T.tufrg_bubble(ctx, code, lam, 1, L)
+        torch.cuda.synchronize()
+        for qi in (0, 531):
+            ref = conv(otu.loops(st, channel, lam, q_list=[qi]))[0]
+            assert rel(L[qi].cpu().numpy(), ref) < TOL["bf16x3"], (channel, qi)
         del L
     ctx.close()

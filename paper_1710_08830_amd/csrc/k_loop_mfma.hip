@@ -119,47 +119,76 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
     }
   }
 
+  // staged values of one tile: band values of k and k' = q - k (pp) or k - q
+  // (ph), regulator values, and the phases.  They are loaded into registers
+  // during the matrix-core phase of the previous tile and written to LDS when
+  // it is done, so the load latency hides behind the products.
+  // thread -> one (ky, side) of the tile and values r = rl + 16 u of it
+  static_assert(KT * 2 * 16 == NTHR, "staging map");
+  constexpr int SPT = (NIT + 15) / 16;
+  const int sj = tid >> 5, sside = (tid >> 4) & 1, rl = tid & 15;
+  float pre[SPT], preph = 0.f;
+  auto fetch = [&](int kxn, int ky0n) {
+    const int ky = ky0n + sj < Lf ? ky0n + sj : Lf - 1;
+    unsigned kk;
+    if (sside) {
+      int kpxn = ch == 0 ? qfx - kxn : kxn - qfx;
+      kpxn += kpxn < 0 ? Lf : 0;
+      int kpy = ch == 0 ? qfy - ky : ky - qfy;
+      kpy += kpy < 0 ? Lf : 0;
+      kk = (unsigned)kpxn * Lf + kpy;
+    } else {
+      kk = (unsigned)kxn * Lf + ky;
+    }
+    const float *bp = band + (size_t)kk * NC, *kp = kv + (size_t)kk * NO;
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int r = rl + 16 * u;
+      if (r < NC)
+        pre[u] = bp[r];
+      else if (r < NIT)
+        pre[u] = kp[r - NC];
+    }
+    if (tid < KT * NPHI) {
+      const int j = tid / NPHI, f = tid % NPHI;
+      const int kyp = ky0n + j < Lf ? ky0n + j : Lf - 1;
+      const float v = f > 0 ? phy[((size_t)kyp * NDY + ((f - 1) % NDY)) * 2 + (f > NDY ? 1 : 0)] : 1.f;
+      preph = ky0n + j < Lf ? v : 0.f;  // ky beyond the mesh contributes nothing
+    }
+  };
+  auto deposit = [&]() {
+#pragma unroll
+    for (int u = 0; u < SPT; ++u) {
+      const int r = rl + 16 * u;
+      float x = pre[u];
+      if (r < NO) {
+        sE[sj][sside][r] = x;
+      } else if (r < NC) {
+        const int p = r - NO, pl = p % NO2;
+        if (sside == 0) {
+          sPk[sj][p] = x;
+        } else {
+          if (ch == 1 && pl >= NO && ((pl - NO) & 1)) x = -x;
+          sX[sj][p] = x;
+        }
+      } else if (r < NIT) {
+        sK[sj][sside][r - NC] = x;
+      }
+    }
+    if (tid < KT * NPHI) sPh[tid / NPHI][tid % NPHI] = preph;
+  };
+
   f32x4 acc[MTW][NT];
   float *Yq = Y + (size_t)qrel * Lf * ROWS * NCOL;
+  fetch(0, 0);
   for (int kx = 0; kx < Lf; ++kx) {
-    int kpx = ch == 0 ? qfx - kx : kx - qfx;
-    kpx += kpx < 0 ? Lf : 0;
 #pragma unroll
     for (int j = 0; j < MTW; ++j)
 #pragma unroll
       for (int n = 0; n < NT; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int ky0 = 0; ky0 < Lf; ky0 += KT) {
-      const int kt = min(KT, Lf - ky0);
       __syncthreads();
-      // band values of k and k' = q - k (pp) or k - q (ph)
-      for (int i = tid; i < KT * 2 * NIT; i += NTHR) {
-        const int r = i % NIT, t2 = i / NIT, j = t2 >> 1, side = t2 & 1;
-        const int ky = ky0 + j < Lf ? ky0 + j : Lf - 1;
-        int kpy = ch == 0 ? qfy - ky : ky - qfy;
-        kpy += kpy < 0 ? Lf : 0;
-        const unsigned kk = side ? (unsigned)kpx * Lf + kpy : (unsigned)kx * Lf + ky;
-        if (r < NO) {
-          sE[j][side][r] = band[(size_t)kk * NC + r];
-        } else if (r < NC) {
-          const int p = r - NO, pl = p % NO2;
-          float x = band[(size_t)kk * NC + r];
-          if (side == 0) {
-            sPk[j][p] = x;
-          } else {
-            if (ch == 1 && pl >= NO && ((pl - NO) & 1)) x = -x;
-            sX[j][p] = x;
-          }
-        } else {
-          sK[j][side][r - NC] = kv[(size_t)kk * NO + (r - NC)];
-        }
-      }
-      for (int i = tid; i < KT * NPHI; i += NTHR) {
-        const int j = i / NPHI, f = i % NPHI;
-        const int ky = ky0 + j < Lf ? ky0 + j : Lf - 1;
-        float v = 1.f;
-        if (f > 0) v = phy[((size_t)ky * NDY + ((f - 1) % NDY)) * 2 + (f > NDY ? 1 : 0)];
-        sPh[j][f] = j < kt ? v : 0.f;  // ky beyond the mesh contributes nothing
-      }
+      deposit();
       __syncthreads();
       for (int i = tid; i < KT * NO2; i += NTHR) {
         const int j = i / NO2, m = (i / NO) % NO, n = i % NO;
@@ -204,23 +233,22 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
                                      ((unsigned)__builtin_bit_cast(unsigned short, lr) << 16);
       }
       __syncthreads();
-      // A operand from Pi and the phases, then 3 products per tile pair
-#pragma unroll
+      // the next tile (the next row's first after the last) is loaded during the products
+      if (ky0 + KT < Lf)
+        fetch(kx, ky0 + KT);
+      else if (kx + 1 < Lf)
+        fetch(kx + 1, 0);
+      // A operand (phases times Pi) of this wave's row tiles, then per column
+      // tile the 3 products hi*hi, hi*lo, lo*hi
+#pragma unroll 1
       for (int s = 0; s < KS; ++s) {
-        bf16x8 bh[NT], bl[NT];
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-          bh[n] = *(const bf16x8 *)&sBh[((s * NT + n) * 64 + lane) * 8];
-          bl[n] = *(const bf16x8 *)&sBl[((s * NT + n) * 64 + lane) * 8];
-        }
+        bf16x8 ah[MTW], al[MTW];
 #pragma unroll
         for (int jt = 0; jt < MTW; ++jt) {
           const int mt = wv + NW * jt;
-          if (mt >= MT) break;
           const int row = mt * 16 + (lane & 15);
-          const bool rv = row < ROWS;
+          const bool rv = mt < MT && row < ROWS;
           const int f = rv ? row / XC : 0, xi = rv ? row % XC : 0;
-          bf16x8 ah, al;
 #pragma unroll
           for (int r = 0; r < 8; r += 2) {
             const int k = 32 * s + 8 * g + r;  // even: (ky, m) = k / 2, re and im
@@ -230,21 +258,25 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
             __bf16 h0, l0, h1, l1;
             split(ph * p.x, h0, l0);
             split(ph * p.y, h1, l1);
-            ah[r] = h0;
-            al[r] = l0;
-            ah[r + 1] = h1;
-            al[r + 1] = l1;
+            ah[jt][r] = h0;
+            al[jt][r] = l0;
+            ah[jt][r + 1] = h1;
+            al[jt][r + 1] = l1;
           }
-          // independent accumulators back to back
+        }
 #pragma unroll
-          for (int n = 0; n < NT; ++n)
-            acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[n], acc[jt][n], 0, 0, 0);
+        for (int n = 0; n < NT; ++n) {
+          const bf16x8 bh = *(const bf16x8 *)&sBh[((s * NT + n) * 64 + lane) * 8];
+          const bf16x8 bl = *(const bf16x8 *)&sBl[((s * NT + n) * 64 + lane) * 8];
 #pragma unroll
-          for (int n = 0; n < NT; ++n)
-            acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[n], acc[jt][n], 0, 0, 0);
+          for (int jt = 0; jt < MTW; ++jt)
+            if (wv + NW * jt < MT) acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[jt], bh, acc[jt][n], 0, 0, 0);
 #pragma unroll
-          for (int n = 0; n < NT; ++n)
-            acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[n], acc[jt][n], 0, 0, 0);
+          for (int jt = 0; jt < MTW; ++jt)
+            if (wv + NW * jt < MT) acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[jt], bl, acc[jt][n], 0, 0, 0);
+#pragma unroll
+          for (int jt = 0; jt < MTW; ++jt)
+            if (wv + NW * jt < MT) acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[jt], bh, acc[jt][n], 0, 0, 0);
         }
       }
     }

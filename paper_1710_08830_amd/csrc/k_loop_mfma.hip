@@ -32,7 +32,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int NO = 6, NO2 = 36, PK = NO * NO2, NC = NO + PK, NIT = NC + NO;
+constexpr int NO = 6, NO2 = 36, PK = NO * NO2, NC = NO + PK;
 constexpr int XC = 21;               // x = (a, c), a <= c
 constexpr int NCOL = 72, NT = 5;     // columns (y, re/im); 16-wide column tiles
 constexpr int KT = 8;                // ky per tile
@@ -81,33 +81,24 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
   const int qfx = (qi / Lq) * n_ref, qfy = (qi % Lq) * n_ref;
   const float sg = ch == 0 ? 1.f : -1.f;
 
-  __shared__ float sE[KT][2][NO], sK[KT][2][NO], sL[KT][NO][NO];
-  __shared__ float sPk[KT][PK];            // Pi_m(k) packed
+  __shared__ float sL[KT][NO][NO];         // loop kernels L_mn of each ky
   __shared__ float sX[KT][PK];             // X_n(k') packed (transposed for ph)
-  __shared__ float sW[KT][PK];             // W_m(k) packed
   __shared__ float2 sPc[KT * NO][XC];      // Pi_m(k)_x for x = (a <= c)
   __shared__ float sPh[KT][NPHI];          // 1, cos, -sin
   __shared__ __align__(16) __bf16 sBh[BFRAG], sBl[BFRAG];
-  __shared__ int sSlotY[NO2][2];           // packed slots (Re, Im) of y = (b, d); Im < 0 on the diagonal
-  __shared__ float sSgnY[NO2];
-  __shared__ int sSlotX[XC][2];
-  __shared__ float sSgnX[XC];
-  if (tid < NO2) {
+  __shared__ int sSlotX[XC][2];            // packed slots (Re, Im) of x = (a <= c); Im < 0 on the diagonal
+  __shared__ int sPcOf[NO2];               // packed slot -> float index into sPc[jm]
+  if (tid < XC) {
     int re, im;
     float sgn;
-    packed_slot(tid / NO, tid % NO, re, im, sgn);
-    sSlotY[tid][0] = re;
-    sSlotY[tid][1] = im;
-    sSgnY[tid] = sgn;
-  } else if (tid < NO2 + XC) {
-    const int xi = tid - NO2;
-    int re, im;
-    float sgn;
-    packed_slot(XA[xi], XCc[xi], re, im, sgn);
-    sSlotX[xi][0] = re;
-    sSlotX[xi][1] = im;
-    sSgnX[xi] = sgn;
+    packed_slot(XA[tid], XCc[tid], re, im, sgn);
+    sSlotX[tid][0] = re;
+    sSlotX[tid][1] = im;
+    sPcOf[re] = 2 * tid;
+    if (im >= 0) sPcOf[im] = 2 * tid + 1;
   }
+  // the imaginary parts of the diagonal x stay zero
+  for (int i = tid; i < KT * NO * XC; i += NTHR) ((float *)sPc)[2 * i + 1] = 0.f;
 
   // padding columns 72..79 of the last column tile stay zero
   for (int i = tid; i < KS * 64 * 8; i += NTHR) {
@@ -119,36 +110,47 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
     }
   }
 
-  // staged values of one tile: band values of k and k' = q - k (pp) or k - q
-  // (ph), regulator values, and the phases.  They are loaded into registers
-  // during the matrix-core phase of the previous tile and written to LDS when
-  // it is done, so the load latency hides behind the products.
-  // thread -> one (ky, side) of the tile and values r = rl + 16 u of it
+  // Staged values of one tile: the packed Pi of k, the packed X of k' = q - k
+  // (pp) or k - q (ph), the phases, and per (ky, m, n) the band energies and
+  // regulator values that enter the loop kernel L_mn.  They are loaded into
+  // registers during the matrix-core phase of the previous tile and written to
+  // LDS (the loop kernels evaluated on the way) when it is done, so the load
+  // latency hides behind the products.
+  // thread -> one (ky, side) of the tile and packed values p = pl + 16 u of it
   static_assert(KT * 2 * 16 == NTHR, "staging map");
-  constexpr int SPT = (NIT + 15) / 16;
-  const int sj = tid >> 5, sside = (tid >> 4) & 1, rl = tid & 15;
-  float pre[SPT], preph = 0.f;
+  constexpr int SPT = (PK + 15) / 16, NDD = KT * NO2;
+  static_assert(NDD >= NTHR, "one loop kernel item per thread at least");
+  const int sj = tid >> 5, sside = (tid >> 4) & 1, pl0 = tid & 15;
+  float pre[SPT], preph = 0.f, pe[4];
+  auto kidx = [&](int kxn, int ky, int side) -> unsigned {
+    if (side == 0) return (unsigned)kxn * Lf + ky;
+    int kpx = ch == 0 ? qfx - kxn : kxn - qfx;
+    kpx += kpx < 0 ? Lf : 0;
+    int kpy = ch == 0 ? qfy - ky : ky - qfy;
+    kpy += kpy < 0 ? Lf : 0;
+    return (unsigned)kpx * Lf + kpy;
+  };
+  // inputs of loop kernel item i = (ky, m, n): E_m(k), K_m(k), E_n(k'), K_n(k')
+  auto dd_inputs = [&](int kxn, int ky0n, int i, float *e) {
+    const int j = i / NO2, m = (i / NO) % NO, n = i % NO;
+    const int ky = ky0n + j < Lf ? ky0n + j : Lf - 1;
+    const unsigned k0 = kidx(kxn, ky, 0), k1 = kidx(kxn, ky, 1);
+    e[0] = band[(size_t)k0 * NC + m];
+    e[1] = kv[(size_t)k0 * NO + m];
+    e[2] = band[(size_t)k1 * NC + n];
+    e[3] = kv[(size_t)k1 * NO + n];
+  };
   auto fetch = [&](int kxn, int ky0n) {
-    const int ky = ky0n + sj < Lf ? ky0n + sj : Lf - 1;
-    unsigned kk;
-    if (sside) {
-      int kpxn = ch == 0 ? qfx - kxn : kxn - qfx;
-      kpxn += kpxn < 0 ? Lf : 0;
-      int kpy = ch == 0 ? qfy - ky : ky - qfy;
-      kpy += kpy < 0 ? Lf : 0;
-      kk = (unsigned)kpxn * Lf + kpy;
-    } else {
-      kk = (unsigned)kxn * Lf + ky;
-    }
-    const float *bp = band + (size_t)kk * NC, *kp = kv + (size_t)kk * NO;
+    {
+      const int ky = ky0n + sj < Lf ? ky0n + sj : Lf - 1;
+      const float *bp = band + (size_t)kidx(kxn, ky, sside) * NC + NO;
 #pragma unroll
-    for (int u = 0; u < SPT; ++u) {
-      const int r = rl + 16 * u;
-      if (r < NC)
-        pre[u] = bp[r];
-      else if (r < NIT)
-        pre[u] = kp[r - NC];
+      for (int u = 0; u < SPT; ++u) {
+        const int p = pl0 + 16 * u;
+        if (p < PK) pre[u] = bp[p];
+      }
     }
+    dd_inputs(kxn, ky0n, tid, pe);
     if (tid < KT * NPHI) {
       const int j = tid / NPHI, f = tid % NPHI;
       const int kyp = ky0n + j < Lf ? ky0n + j : Lf - 1;
@@ -156,24 +158,28 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
       preph = ky0n + j < Lf ? v : 0.f;  // ky beyond the mesh contributes nothing
     }
   };
-  auto deposit = [&]() {
+  auto deposit = [&](int kxd, int ky0d) {
 #pragma unroll
     for (int u = 0; u < SPT; ++u) {
-      const int r = rl + 16 * u;
-      float x = pre[u];
-      if (r < NO) {
-        sE[sj][sside][r] = x;
-      } else if (r < NC) {
-        const int p = r - NO, pl = p % NO2;
+      const int p = pl0 + 16 * u;
+      if (p < PK) {
+        const int m = p / NO2, pl = p % NO2;
+        float x = pre[u];
         if (sside == 0) {
-          sPk[sj][p] = x;
+          ((float *)sPc[sj * NO + m])[sPcOf[pl]] = x;
         } else {
           if (ch == 1 && pl >= NO && ((pl - NO) & 1)) x = -x;
           sX[sj][p] = x;
         }
-      } else if (r < NIT) {
-        sK[sj][sside][r - NC] = x;
       }
+    }
+    (&sL[0][0][0])[tid] = sg * divided_difference(pe[0], -sg * pe[2], pe[1], -sg * pe[3], lam, SCHEME, deriv);
+    // the items beyond one per thread read their inputs now (cache hits: the
+    // same rows were just fetched)
+    for (int i = tid + NTHR; i < NDD; i += NTHR) {
+      float e[4];
+      dd_inputs(kxd, ky0d, i, e);
+      (&sL[0][0][0])[i] = sg * divided_difference(e[0], -sg * e[2], e[1], -sg * e[3], lam, SCHEME, deriv);
     }
     if (tid < KT * NPHI) sPh[tid / NPHI][tid % NPHI] = preph;
   };
@@ -188,49 +194,50 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
       for (int n = 0; n < NT; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int ky0 = 0; ky0 < Lf; ky0 += KT) {
       __syncthreads();
-      deposit();
+      deposit(kx, ky0);
       __syncthreads();
-      for (int i = tid; i < KT * NO2; i += NTHR) {
-        const int j = i / NO2, m = (i / NO) % NO, n = i % NO;
-        const float x = sE[j][0][m], y = -sg * sE[j][1][n];
-        sL[j][m][n] = sg * divided_difference(x, y, sK[j][0][m], -sg * sK[j][1][n], lam, SCHEME, deriv);
-      }
+      // W_m = sum_n L_mn X_n, written straight into the B operand: rows
+      // k = (ky, m, re/im), columns (y, re/im), split and in lane order.  For
+      // W = wr + i wi the 2 x 2 block of (k re, k im) x (col re, col im) is
+      // [[wr, wi], [-wi, wr]]: the two k of one column are adjacent slots of
+      // one lane, so each column is one 32-bit store.  W is Hermitian: one
+      // item computes the pair y = (b, d), b <= d, and fills (d, b) with the
+      // conjugate.
       for (int i = tid; i < KT * NO * XC; i += NTHR) {
-        const int jm = i / XC, xi = i % XC, j = jm / NO, m = jm % NO;
-        const int re = sSlotX[xi][0], im = sSlotX[xi][1];
-        sPc[jm][xi] = make_float2(sPk[j][m * NO2 + re], im >= 0 ? sSgnX[xi] * sPk[j][m * NO2 + im] : 0.f);
-      }
-      __syncthreads();
-      for (int i = tid; i < KT * PK; i += NTHR) {
-        const int j = i / PK, mp = i % PK, m = mp / NO2, pl = mp % NO2;
-        float a = 0.f;
+        const int jm = i / XC, yp = i % XC, j = jm / NO, m = jm % NO;
+        const int re = sSlotX[yp][0], im = sSlotX[yp][1];
+        float wr = 0.f, wi = 0.f;
 #pragma unroll
-        for (int n = 0; n < NO; ++n) a = fmaf(sL[j][m][n], sX[j][n * NO2 + pl], a);
-        sW[j][mp] = a;
-      }
-      __syncthreads();
-      // B operand: rows k = (ky, m, re/im), columns (y, re/im), split and in
-      // lane order.  For W = wr + i wi the 2 x 2 block of (k re, k im) x
-      // (col re, col im) is [[wr, wi], [-wi, wr]]: the two k of one column are
-      // adjacent slots of one lane, so each column is one 32-bit store.
-      for (int i = tid; i < KT * NO * NO2; i += NTHR) {
-        const int jm = i / NO2, y = i % NO2, j = jm / NO, m = jm % NO;
-        const int re = sSlotY[y][0], im = sSlotY[y][1];
-        const float wr = sW[j][m * NO2 + re], wi = im >= 0 ? sSgnY[y] * sW[j][m * NO2 + im] : 0.f;
-        const int k = 2 * jm, s = k >> 5, kk = k & 31, col = 2 * y, n = col >> 4;
-        const int idx = ((s * NT + n) * 64 + (kk >> 3) * 16 + (col & 15)) * 8 + (kk & 7);  // even
+        for (int n = 0; n < NO; ++n) {
+          const float l = sL[j][m][n];
+          wr = fmaf(l, sX[j][n * NO2 + re], wr);
+          if (im >= 0) wi = fmaf(l, sX[j][n * NO2 + im], wi);
+        }
         __bf16 hr, lr, hi, li;
         split(wr, hr, lr);
         split(wi, hi, li);
-        // column re: (wr, -wi); column im (next lane, 8 values on): (wi, wr)
-        *(unsigned *)&sBh[idx] = (unsigned)__builtin_bit_cast(unsigned short, hr) |
-                                 ((unsigned)__builtin_bit_cast(unsigned short, hi) << 16) ^ 0x80000000u;
-        *(unsigned *)&sBl[idx] = (unsigned)__builtin_bit_cast(unsigned short, lr) |
-                                 ((unsigned)__builtin_bit_cast(unsigned short, li) << 16) ^ 0x80000000u;
-        *(unsigned *)&sBh[idx + 8] = (unsigned)__builtin_bit_cast(unsigned short, hi) |
-                                     ((unsigned)__builtin_bit_cast(unsigned short, hr) << 16);
-        *(unsigned *)&sBl[idx + 8] = (unsigned)__builtin_bit_cast(unsigned short, li) |
-                                     ((unsigned)__builtin_bit_cast(unsigned short, lr) << 16);
+        const unsigned ur = __builtin_bit_cast(unsigned short, hr), vr = __builtin_bit_cast(unsigned short, lr);
+        const unsigned ui = __builtin_bit_cast(unsigned short, hi), vi = __builtin_bit_cast(unsigned short, li);
+        const int k = 2 * jm, s = k >> 5, kk = k & 31;
+        const int b = XA[yp], d = XCc[yp];
+        {
+          // y = (b, d): column re (wr, -wi), column im (next lane, 8 values on) (wi, wr)
+          const int col = 2 * (b * NO + d), n = col >> 4;
+          const int idx = ((s * NT + n) * 64 + (kk >> 3) * 16 + (col & 15)) * 8 + (kk & 7);  // even
+          *(unsigned *)&sBh[idx] = (ur | (ui << 16)) ^ 0x80000000u;
+          *(unsigned *)&sBl[idx] = (vr | (vi << 16)) ^ 0x80000000u;
+          *(unsigned *)&sBh[idx + 8] = ui | (ur << 16);
+          *(unsigned *)&sBl[idx + 8] = vi | (vr << 16);
+        }
+        if (b != d) {
+          // y = (d, b) holds the conjugate: column re (wr, wi), column im (-wi, wr)
+          const int col = 2 * (d * NO + b), n = col >> 4;
+          const int idx = ((s * NT + n) * 64 + (kk >> 3) * 16 + (col & 15)) * 8 + (kk & 7);
+          *(unsigned *)&sBh[idx] = ur | (ui << 16);
+          *(unsigned *)&sBl[idx] = vr | (vi << 16);
+          *(unsigned *)&sBh[idx + 8] = (ui | (ur << 16)) ^ 0x8000u;
+          *(unsigned *)&sBl[idx + 8] = (vi | (vr << 16)) ^ 0x8000u;
+        }
       }
       __syncthreads();
       // the next tile (the next row's first after the last) is loaded during the products

@@ -75,7 +75,8 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
                                                             int Lf, int q_first, const int *__restrict__ rows,
                                                             int ch, float lam, int deriv, float *__restrict__ Y) {
   constexpr int NPHI = 2 * NDY + 1, ROWS = NPHI * XC, MT = (ROWS + 15) / 16, MTW = (MT + NW - 1) / NW;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, g = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index: uniform, keeps the tile guards scalar
   const int qrel = blockIdx.x;
   const int qi = rows ? rows[qrel / Lq] * Lq + qrel % Lq : q_first + qrel;
   const int qfx = (qi / Lq) * n_ref, qfy = (qi % Lq) * n_ref;
@@ -199,44 +200,69 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
       // W_m = sum_n L_mn X_n, written straight into the B operand: rows
       // k = (ky, m, re/im), columns (y, re/im), split and in lane order.  For
       // W = wr + i wi the 2 x 2 block of (k re, k im) x (col re, col im) is
-      // [[wr, wi], [-wi, wr]]: the two k of one column are adjacent slots of
-      // one lane, so each column is one 32-bit store.  W is Hermitian: one
-      // item computes the pair y = (b, d), b <= d, and fills (d, b) with the
-      // conjugate.
-      for (int i = tid; i < KT * NO * XC; i += NTHR) {
-        const int jm = i / XC, yp = i % XC, j = jm / NO, m = jm % NO;
+      // [[wr, wi], [-wi, wr]].  One item is one chunk of 8 k (4 (ky, m), the 8
+      // values one lane holds for one column) and one pair y = (b, d), b <= d:
+      // W is Hermitian, so (d, b) takes the conjugate.  Each column is one
+      // 16-byte store per operand half.
+      static_assert(KT * NO % 4 == 0, "chunks of 4 (ky, m)");
+      if (tid < KT * NO / 4 * XC) {
+        const int t = tid / XC, yp = tid % XC;
         const int re = sSlotX[yp][0], im = sSlotX[yp][1];
-        float wr = 0.f, wi = 0.f;
+        unsigned ur[4], ui[4], vr[4], vi[4];
 #pragma unroll
-        for (int n = 0; n < NO; ++n) {
-          const float l = sL[j][m][n];
-          wr = fmaf(l, sX[j][n * NO2 + re], wr);
-          if (im >= 0) wi = fmaf(l, sX[j][n * NO2 + im], wi);
+        for (int c = 0; c < 4; ++c) {
+          const int jm = 4 * t + c, j = jm / NO, m = jm % NO;
+          float wr = 0.f, wi = 0.f;
+#pragma unroll
+          for (int n = 0; n < NO; ++n) {
+            const float l = sL[j][m][n];
+            wr = fmaf(l, sX[j][n * NO2 + re], wr);
+            if (im >= 0) wi = fmaf(l, sX[j][n * NO2 + im], wi);
+          }
+          __bf16 hr, lr, hi, li;
+          split(wr, hr, lr);
+          split(wi, hi, li);
+          ur[c] = __builtin_bit_cast(unsigned short, hr);
+          vr[c] = __builtin_bit_cast(unsigned short, lr);
+          ui[c] = __builtin_bit_cast(unsigned short, hi);
+          vi[c] = __builtin_bit_cast(unsigned short, li);
         }
-        __bf16 hr, lr, hi, li;
-        split(wr, hr, lr);
-        split(wi, hi, li);
-        const unsigned ur = __builtin_bit_cast(unsigned short, hr), vr = __builtin_bit_cast(unsigned short, lr);
-        const unsigned ui = __builtin_bit_cast(unsigned short, hi), vi = __builtin_bit_cast(unsigned short, li);
-        const int k = 2 * jm, s = k >> 5, kk = k & 31;
-        const int b = XA[yp], d = XCc[yp];
+        const int b = XA[yp], d = XCc[yp], s = t >> 2, g4 = t & 3;
         {
-          // y = (b, d): column re (wr, -wi), column im (next lane, 8 values on) (wi, wr)
+          // y = (b, d): column re (wr, -wi), column im (wi, wr)
           const int col = 2 * (b * NO + d), n = col >> 4;
-          const int idx = ((s * NT + n) * 64 + (kk >> 3) * 16 + (col & 15)) * 8 + (kk & 7);  // even
-          *(unsigned *)&sBh[idx] = (ur | (ui << 16)) ^ 0x80000000u;
-          *(unsigned *)&sBl[idx] = (vr | (vi << 16)) ^ 0x80000000u;
-          *(unsigned *)&sBh[idx + 8] = ui | (ur << 16);
-          *(unsigned *)&sBl[idx + 8] = vi | (vr << 16);
+          const int idx = ((s * NT + n) * 64 + g4 * 16 + (col & 15)) * 8;
+          uint4 h0, l0, h1, l1;
+          unsigned *ph0 = (unsigned *)&h0, *pl0 = (unsigned *)&l0, *ph1 = (unsigned *)&h1, *pl1 = (unsigned *)&l1;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            ph0[c] = (ur[c] | (ui[c] << 16)) ^ 0x80000000u;
+            pl0[c] = (vr[c] | (vi[c] << 16)) ^ 0x80000000u;
+            ph1[c] = ui[c] | (ur[c] << 16);
+            pl1[c] = vi[c] | (vr[c] << 16);
+          }
+          *(uint4 *)&sBh[idx] = h0;
+          *(uint4 *)&sBl[idx] = l0;
+          *(uint4 *)&sBh[idx + 8] = h1;
+          *(uint4 *)&sBl[idx + 8] = l1;
         }
         if (b != d) {
           // y = (d, b) holds the conjugate: column re (wr, wi), column im (-wi, wr)
           const int col = 2 * (d * NO + b), n = col >> 4;
-          const int idx = ((s * NT + n) * 64 + (kk >> 3) * 16 + (col & 15)) * 8 + (kk & 7);
-          *(unsigned *)&sBh[idx] = ur | (ui << 16);
-          *(unsigned *)&sBl[idx] = vr | (vi << 16);
-          *(unsigned *)&sBh[idx + 8] = (ui | (ur << 16)) ^ 0x8000u;
-          *(unsigned *)&sBl[idx + 8] = (vi | (vr << 16)) ^ 0x8000u;
+          const int idx = ((s * NT + n) * 64 + g4 * 16 + (col & 15)) * 8;
+          uint4 h0, l0, h1, l1;
+          unsigned *ph0 = (unsigned *)&h0, *pl0 = (unsigned *)&l0, *ph1 = (unsigned *)&h1, *pl1 = (unsigned *)&l1;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            ph0[c] = ur[c] | (ui[c] << 16);
+            pl0[c] = vr[c] | (vi[c] << 16);
+            ph1[c] = (ui[c] | (ur[c] << 16)) ^ 0x8000u;
+            pl1[c] = (vi[c] | (vr[c] << 16)) ^ 0x8000u;
+          }
+          *(uint4 *)&sBh[idx] = h0;
+          *(uint4 *)&sBl[idx] = l0;
+          *(uint4 *)&sBh[idx + 8] = h1;
+          *(uint4 *)&sBl[idx + 8] = l1;
         }
       }
       __syncthreads();
@@ -246,7 +272,8 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
       else if (kx + 1 < Lf)
         fetch(kx + 1, 0);
       // A operand (phases times Pi) of this wave's row tiles, then per column
-      // tile the 3 products hi*hi, hi*lo, lo*hi
+      // tile the 3 products hi*hi, hi*lo, lo*hi.  A row tile past the last
+      // (possible for the 3 x 3 box) has a zero A operand and is not written.
 #pragma unroll 1
       for (int s = 0; s < KS; ++s) {
         bf16x8 ah[MTW], al[MTW];
@@ -277,13 +304,13 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
           const bf16x8 bl = *(const bf16x8 *)&sBl[((s * NT + n) * 64 + lane) * 8];
 #pragma unroll
           for (int jt = 0; jt < MTW; ++jt)
-            if (wv + NW * jt < MT) acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[jt], bh, acc[jt][n], 0, 0, 0);
+            acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[jt], bh, acc[jt][n], 0, 0, 0);
 #pragma unroll
           for (int jt = 0; jt < MTW; ++jt)
-            if (wv + NW * jt < MT) acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[jt], bl, acc[jt][n], 0, 0, 0);
+            acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[jt], bl, acc[jt][n], 0, 0, 0);
 #pragma unroll
           for (int jt = 0; jt < MTW; ++jt)
-            if (wv + NW * jt < MT) acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[jt], bh, acc[jt][n], 0, 0, 0);
+            acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[jt], bh, acc[jt][n], 0, 0, 0);
         }
       }
     }

@@ -31,6 +31,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int NO = 6, NO2 = 36, PK = NO * NO2, NC = NO + PK;
 constexpr int XC = 21;               // x = (a, c), a <= c
@@ -64,6 +65,15 @@ __device__ inline void packed_slot(int a, int c, int &re, int &im, float &sgn) {
 __device__ inline void split(float v, __bf16 &hi, __bf16 &lo) {
   hi = (__bf16)v;
   lo = (__bf16)(v - (float)hi);
+}
+
+// the same for two values, packed as (first | second << 16) for hi and lo
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ inline void split2(float a, float b, unsigned &hi, unsigned &lo) {
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){a, b}, bf16x2));
+  const float ra = a - __uint_as_float(hi << 16), rb = b - __uint_as_float(hi & 0xffff0000u);
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){ra, rb}, bf16x2));
 }
 
 }  // namespace
@@ -207,7 +217,7 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
       static_assert(KT * NO % 4 == 0, "chunks of 4 (ky, m)");
       if (tid < KT * NO / 4 * XC) {
         const int t = tid / XC, yp = tid % XC;
-        const int re = sSlotX[yp][0], im = sSlotX[yp][1];
+        const int re = sSlotX[yp][0], im = sSlotX[yp][1], imr = im >= 0 ? im : re;
         unsigned ur[4], ui[4], vr[4], vi[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -217,8 +227,9 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
           for (int n = 0; n < NO; ++n) {
             const float l = sL[j][m][n];
             wr = fmaf(l, sX[j][n * NO2 + re], wr);
-            if (im >= 0) wi = fmaf(l, sX[j][n * NO2 + im], wi);
+            wi = fmaf(l, sX[j][n * NO2 + imr], wi);
           }
+          wi = im >= 0 ? wi : 0.f;
           __bf16 hr, lr, hi, li;
           split(wr, hr, lr);
           split(wi, hi, li);
@@ -281,22 +292,19 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
         for (int jt = 0; jt < MTW; ++jt) {
           const int mt = wv + NW * jt;
           const int row = mt * 16 + (lane & 15);
-          const bool rv = mt < MT && row < ROWS;
+          const bool rv = row < ROWS;
           const int f = rv ? row / XC : 0, xi = rv ? row % XC : 0;
+          unsigned hp[4], lp[4];
 #pragma unroll
-          for (int r = 0; r < 8; r += 2) {
-            const int k = 32 * s + 8 * g + r;  // even: (ky, m) = k / 2, re and im
-            const int jm = k >> 1, j = jm / NO;
+          for (int r = 0; r < 4; ++r) {
+            const int jm = 16 * s + 4 * g + r;  // (ky, m) of k = 2 jm (re) and 2 jm + 1 (im)
             const float2 p = sPc[jm][xi];
-            const float ph = rv ? sPh[j][f] : 0.f;
-            __bf16 h0, l0, h1, l1;
-            split(ph * p.x, h0, l0);
-            split(ph * p.y, h1, l1);
-            ah[jt][r] = h0;
-            al[jt][r] = l0;
-            ah[jt][r + 1] = h1;
-            al[jt][r + 1] = l1;
+            float ph = sPh[jm / NO][f];
+            ph = rv ? ph : 0.f;
+            split2(ph * p.x, ph * p.y, hp[r], lp[r]);
           }
+          ah[jt] = __builtin_bit_cast(bf16x8, (u32x4){hp[0], hp[1], hp[2], hp[3]});
+          al[jt] = __builtin_bit_cast(bf16x8, (u32x4){lp[0], lp[1], lp[2], lp[3]});
         }
 #pragma unroll
         for (int n = 0; n < NT; ++n) {

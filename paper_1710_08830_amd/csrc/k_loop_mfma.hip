@@ -93,8 +93,11 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
   const float sg = ch == 0 ? 1.f : -1.f;
 
   __shared__ float sL[KT][NO][NO];         // loop kernels L_mn of each ky
-  __shared__ float sX[KT][PK];             // X_n(k') packed (transposed for ph)
-  __shared__ float2 sPc[KT * NO][XC];      // Pi_m(k)_x for x = (a <= c)
+  // X_n(k') packed (transposed for ph), then Pi_m(k)_x for x = (a <= c), in one
+  // array so that a store of either is one address computation
+  __shared__ __align__(16) float sStage[KT * PK + KT * NO * XC * 2];
+  float(*sX)[PK] = (float(*)[PK])sStage;
+  float2(*sPc)[XC] = (float2(*)[XC])(sStage + KT * PK);
   __shared__ float sPh[KT][NPHI];          // 1, cos, -sin
   __shared__ __align__(16) __bf16 sBh[BFRAG], sBl[BFRAG];
   __shared__ int sSlotX[XC][2];            // packed slots (Re, Im) of x = (a <= c); Im < 0 on the diagonal
@@ -170,18 +173,16 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
     }
   };
   auto deposit = [&](int kxd, int ky0d) {
+    // one LDS store per value, its address chosen per lane: the two sides of
+    // a wave go to different arrays
 #pragma unroll
     for (int u = 0; u < SPT; ++u) {
       const int p = pl0 + 16 * u;
-      if (p < PK) {
-        const int m = p / NO2, pl = p % NO2;
-        float x = pre[u];
-        if (sside == 0) {
-          ((float *)sPc[sj * NO + m])[sPcOf[pl]] = x;
-        } else {
-          if (ch == 1 && pl >= NO && ((pl - NO) & 1)) x = -x;
-          sX[sj][p] = x;
-        }
+      if (16 * u + 15 < PK || p < PK) {
+        const int m = p / NO2, pl = p - NO2 * m;
+        const bool flip = sside && ch == 1 && pl >= NO && ((pl - NO) & 1);
+        const int po = KT * PK + 2 * XC * (sj * NO + m) + sPcOf[pl], xo = sj * PK + p;
+        sStage[po + ((xo - po) & -sside)] = flip ? -pre[u] : pre[u];
       }
     }
     (&sL[0][0][0])[tid] = sg * divided_difference(pe[0], -sg * pe[2], pe[1], -sg * pe[3], lam, SCHEME, deriv);
@@ -257,8 +258,10 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
           *(uint4 *)&sBh[idx + 8] = h1;
           *(uint4 *)&sBl[idx + 8] = l1;
         }
-        if (b != d) {
-          // y = (d, b) holds the conjugate: column re (wr, wi), column im (-wi, wr)
+        {
+          // y = (d, b) holds the conjugate: column re (wr, wi), column im (-wi, wr).
+          // On the diagonal (wi = 0) this rewrites the same two columns with
+          // the same values up to the sign of zero.
           const int col = 2 * (d * NO + b), n = col >> 4;
           const int idx = ((s * NT + n) * 64 + g4 * 16 + (col & 15)) * 8;
           uint4 h0, l0, h1, l1;

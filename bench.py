@@ -30,20 +30,29 @@ sys.path.insert(0, ROOT)
 METRIC = "loop entries/s + flow steps/s, mixed/surrogate vs FP64-plain at ≤1e-4 rel err"
 WORKLOAD = "rashba_s9_L24"
 PEAK_FP32_VECTOR = 157.3e12
+PEAK_BF16_MFMA = 2.5e15
 
 
 def loop_flops_per_pair(n_o, ndx, ndy):
-    """Algorithmic FP32 flops of the loop kernel per (q, k, channel); the
-    derivation is in the design doc.  Two spin-orbitals: 12 for the four divided
-    differences, 16 for W_1 and D, 32 for the 10 distinct block entries, 16 for
-    the dx = 0 sums and 64 per further dx.  n_o > 2 (one entry of each
-    Hermitian pair, U = (n_o^4 + n_o^2) / 2 of them): 8 n_o flops for
-    sum_m Pi_m W_m, 2 + 8 ndy for the separable ky transform, plus 2 n_o^4 for
-    W_m and 3 n_o^2 for the loop kernels."""
+    """Algorithmic FP32 flops of the loop kernel per (q, k, channel).  Two
+    spin-orbitals: 12 for the four divided differences, 16 for W_1 and D, 32
+    for the 10 distinct block entries, 16 for the dx = 0 sums and 64 per
+    further dx.  n_o > 2 (one entry of each Hermitian pair, U = (n_o^4 + n_o^2)
+    / 2 of them): 8 n_o flops for sum_m Pi_m W_m, 2 + 8 ndy for the separable
+    ky transform, plus 2 n_o^4 for W_m and 3 n_o^2 for the loop kernels."""
     if n_o == 2:
         return 12 + 16 + 32 + 16 + 64 * (ndx - 1)
     u = (n_o ** 4 + n_o ** 2) // 2
     return u * (8 * n_o + 2 + 8 * ndy) + 2 * n_o ** 4 + 3 * n_o ** 2
+
+
+def mfma_flops_per_pair(ndy, n_o=6):
+    """Matrix-core flops of the BF16X3 loop per (q, k, channel): one k adds
+    K = 2 n_o (band, re/im) to the per-row product of the (2 ndy + 1) *
+    n_o (n_o + 1) / 2 phase-weighted projector rows with the 2 n_o^2 real
+    columns, done as three BF16 products (hi*hi, hi*lo, lo*hi)."""
+    rows = (2 * ndy + 1) * n_o * (n_o + 1) // 2
+    return 3 * 2 * rows * (2 * n_o * n_o) * (2 * n_o)
 
 
 def _box(ff):
@@ -51,23 +60,27 @@ def _box(ff):
     return (3, 2) if m <= 1 else (5, 4)
 
 
-def _loop_source_hash():
+# sources of the loop kernel per precision, with the host code that sets its launch shape
+LOOP_SOURCES = {"bf16x3": ("k_loop_mfma.hip", "common.h", "tufrg_host.hip")}
+
+
+def _loop_source_hash(prec):
     h = hashlib.sha256()
-    for f in ("k_loop.hip", "k_loop_gen.hip", "common.h"):
+    for f in LOOP_SOURCES.get(prec, ("k_loop.hip", "k_loop_gen.hip", "common.h", "tufrg_host.hip")):
         with open(os.path.join(ROOT, "paper_1710_08830_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def _traffic(workload):
+def _traffic(workload, prec):
     """HBM bytes per loop-kernel launch from committed rocprofv3 counters, or
     None when the kernel source changed since they were taken."""
     try:
-        with open(os.path.join(ROOT, "profiles", f"loop_kernel_traffic_{workload}.json")) as fh:
+        with open(os.path.join(ROOT, "profiles", f"loop_kernel_traffic_{workload}_{prec}.json")) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != _loop_source_hash():
+    if t.get("source_sha256") != _loop_source_hash(prec):
         return None
     return float(t["hbm_bytes_per_launch"])
 
@@ -417,11 +430,20 @@ def main():
     B, Nq, Nf = ctx32.B, ctx32.Nq, ctx32.Nf
     entries = 2.0 * Nq * B * B
     value = entries * K / dt32
+    # the loop timer brackets each launch of the dominant loop kernel: one
+    # per step (both channels) on the vector units, one per channel and chunk
+    # of coarse q on the matrix cores
     loop_avg_s = loop_ms / loop_n * 1e-3
+    launches = loop_n / K
     ndx, ndy = _box(w["ff"])
-    flops_launch = 2.0 * Nq * Nf * loop_flops_per_pair(w["n_o"], ndx, ndy)
-    achieved = flops_launch / loop_avg_s
-    traffic = _traffic(args.workload)
+    if args.prec == "bf16x3":
+        flops_step = 2.0 * Nq * Nf * mfma_flops_per_pair(ndy, w["n_o"])
+        bound, peak = "mfma", PEAK_BF16_MFMA
+    else:
+        flops_step = 2.0 * Nq * Nf * loop_flops_per_pair(w["n_o"], ndx, ndy)
+        bound, peak = "alu", PEAK_FP32_VECTOR
+    achieved = flops_step / launches / loop_avg_s
+    traffic = _traffic(args.workload, args.prec)
     out = {
         "metric": METRIC, "value": value, "unit": "loop entries/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": dt32 / K * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -432,10 +454,10 @@ def main():
                    "parallelism": "single GPU"},
         "flow_steps_per_s": K / dt32,
         "loop_kernel_ms": loop_avg_s * 1e3,
-        "loop_entries_per_s_kernel": entries / loop_avg_s,
-        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
-                     "traffic": traffic},
+        "loop_launches_per_step": launches,
+        "loop_entries_per_s_kernel": entries / (loop_avg_s * launches),
+        "roofline": {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic},
     }
     if not args.no_extras:
         ctx64, P64, C64 = make("fp64")

@@ -197,7 +197,9 @@ tufrg_status tufrg_flow(tufrg_ctx *ctx, const tufrg_flow_opts *opts, tufrg_c64 *
 
 /* Optional per-kernel timing with HIP events recorded on the context stream
  * around the launches of one part of the right-hand side:
- *   TUFRG_TIMER_LOOP     the loop kernel launch (both channels in one launch)
+ *   TUFRG_TIMER_LOOP     the loop kernel launch (both channels in one launch; with
+ *                        TUFRG_BF16X3 one interval per matrix-core launch, one per
+ *                        channel and chunk of coarse q)
  *   TUFRG_TIMER_PROJECT  real-space transform, gathers and assembly
  *   TUFRG_TIMER_BUNDLE   the two bundle products
  * tufrg_timing(ctx, 1) synchronises, clears and enables; tufrg_timing_read

@@ -445,8 +445,9 @@ size_t loop_mfma_rowbuf_floats(int ndy, int Lf) {
   return (size_t)Lf * rows * NCOL;
 }
 
-// one channel, coarse q [q_first, q_first + n_q) (or rows); Y holds n_q row buffers;
-// the partials go to slot (q index within the launch) of a one-channel LoopArgs layout
+// one channel, coarse q [q_first, q_first + n_q) (or rows): the row buffers Y
+// (n_q of them); launch_loop_rowsum then writes the partials to slot (q index
+// within the launch) of a one-channel LoopArgs layout
 hipError_t launch_loop_mfma(const LoopArgs &a, int ch, float *Y, hipStream_t st) {
   if (a.n_o != 6 || !a.pairs || a.n_pairs <= 0 || !Y) return hipErrorInvalidValue;
   const float *band = (const float *)a.band, *kv = (const float *)a.kv, *phy = (const float *)a.phy;
@@ -469,16 +470,21 @@ hipError_t launch_loop_mfma(const LoopArgs &a, int ch, float *Y, hipStream_t st)
   } else {
     return hipErrorInvalidValue;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_loop_rowsum(const LoopArgs &a, const float *Y, hipStream_t st) {
+  if (a.n_o != 6 || !a.pairs || a.n_pairs <= 0 || !Y) return hipErrorInvalidValue;
   const int np = (a.n_pairs + 255) / 256;
   dim3 g2(a.n_q * np), b2(256);
   if (a.ndy == 4)
     hipLaunchKernelGGL(loop_rowsum_kernel<4>, g2, b2, 0, st, Y, a.tw, a.pairs, a.n_pairs, a.Lf, np, 0, a.n_q, a.ndx,
                        a.partial);
-  else
+  else if (a.ndy == 2)
     hipLaunchKernelGGL(loop_rowsum_kernel<2>, g2, b2, 0, st, Y, a.tw, a.pairs, a.n_pairs, a.Lf, np, 0, a.n_q, a.ndx,
                        a.partial);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -43,8 +43,9 @@ hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
 // more than two spin-orbitals (six: t2g with spin-orbit coupling)
 hipError_t launch_loop_gen(const LoopArgs &a, hipStream_t st);
 // six spin-orbitals on the matrix cores (one channel): row buffers Y of
-// loop_mfma_rowbuf_floats(ndy, Lf) floats per coarse q, then the partials
+// loop_mfma_rowbuf_floats(ndy, Lf) floats per coarse q, then (rowsum) the partials
 hipError_t launch_loop_mfma(const LoopArgs &a, int ch, float *Y, hipStream_t st);
+hipError_t launch_loop_rowsum(const LoopArgs &a, const float *Y, hipStream_t st);
 size_t loop_mfma_rowbuf_floats(int ndy, int Lf);
 // sums partials, applies 1/Nf, fills dx < 0 by hermiticity
 hipError_t launch_loop_finalize(const LoopArgs &a, int nD, const int *dlist, double *compact, hipStream_t st);

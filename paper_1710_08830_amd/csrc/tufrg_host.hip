@@ -257,7 +257,13 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   if (c->n_o == 2) {
     c->nkyb = (c->Lf + 63) / 64;
     long long base = 2LL * c->Nq * c->nkyb;
-    int want = (int)std::max<long long>(1, (4096 + base - 1) / base);
+    // enough work items to fill the chip, and kx chunks short enough that the
+    // k rows of one chunk (each XCD sweeps one chunk over many q at a time)
+    // take about 3 MB of its 4 MB L2
+    const long long row_bytes = (long long)c->Lf * 8 * (c->prec == 0 ? 8 : 4);
+    const long long fill = (4096 + base - 1) / base;
+    const long long l2 = ((long long)c->Lf * row_bytes + 3000000 - 1) / 3000000;
+    int want = (int)std::max<long long>(1, std::max(fill, l2));
     c->nkxc = std::max(1, std::min(want, std::max(1, c->Lf / 8)));
   } else {
     // the multi-orbital loop kernel sums every k of a (q, channel) in one workgroup
@@ -529,7 +535,6 @@ static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch
     TRY(dalloc(c, &c->d_yrow, (size_t)c->mfma_chunk * loop_mfma_rowbuf_floats(c->ndy, c->Lf)));
   }
   const size_t blk = (size_t)c->nD * c->no4;
-  HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
   for (int chi = 0; chi < n_ch; ++chi) {
     const int ch = ch_first + chi;
     for (int q0 = 0; q0 < n_q; q0 += c->mfma_chunk) {
@@ -538,11 +543,14 @@ static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch
       a.q_first = rows ? 0 : q_first + q0;
       a.n_q = nq;
       a.rows = rows ? rows + q0 / c->Lq : nullptr;
+      // the loop timer covers the matrix-core kernel of each chunk
+      HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
       HIPCHK(c, launch_loop_mfma(a, ch, c->d_yrow, c->st));
+      HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
+      HIPCHK(c, launch_loop_rowsum(a, c->d_yrow, c->st));
       HIPCHK(c, launch_loop_finalize(a, c->nD, c->d_dlist, dst + 2 * ((size_t)chi * n_q + q0) * blk, c->st));
     }
   }
-  HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
   return TUFRG_OK;
 }
 

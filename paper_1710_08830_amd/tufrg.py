@@ -10,6 +10,7 @@ import ctypes
 import os
 
 import numpy as np
+import torch  # noqa: F401  (torch's HIP runtime is loaded before the library's: the order the library is tested in)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtufrg.so")

@@ -155,11 +155,13 @@ def surrogate_leg(T, torch, ctx, P, C, P64, C64, dp, w, K, t_plain_step, n_lam=2
     del Yall
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
+    print(f"surrogate bench: {n_lam * per} training rows in {t_data:.1f} s", file=sys.stderr, flush=True)
     net = T.Mlp(sizes, mlp_init(sizes, seed=3))
     t0 = time.perf_counter()
     loss = None
     for ep, lr in zip(epochs, (1e-3, 3e-4, 1e-4)):
         loss = T.tufrg_mlp_train(net, X, Y, batch=2048, epochs=ep, lr=lr, seed=3)
+        print(f"surrogate bench: {ep} epochs at lr {lr:g}, loss {loss:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     T.tufrg_sur_attach(ctx, net, lams, scales)
@@ -207,9 +209,10 @@ def surrogate_leg(T, torch, ctx, P, C, P64, C64, dp, w, K, t_plain_step, n_lam=2
     return res
 
 
-def surrogate_bench(T, torch, w, K, n_rows=200000, epochs=(20, 20, 20)):
+def surrogate_bench(T, torch, w, K, prec, n_rows=200000, epochs=(20, 20, 20)):
     """Surrogate-assisted flow of the six-orbital model on the 48 x 48 q-mesh:
-    the first K steps of its 200-step Euler grid with plain FP32 loops; the
+    the first K steps of its 200-step Euler grid with plain loops (FP32 on the
+    vector units or BF16X3 on the matrix cores); the
     network trained on n_rows random blocks of the plain loops at the scales of
     those steps (the loops a plain flow produces); then the same K steps with
     the network (5 % of the q_x rows recomputed plainly, fallback above 1e-3
@@ -219,7 +222,7 @@ def surrogate_bench(T, torch, w, K, n_rows=200000, epochs=(20, 20, 20)):
     from synth import mlp_init, mlp_shape
 
     dev = torch.device("cuda:0")
-    ctx = T.Context.from_workload(w, precision="fp32")
+    ctx = T.Context.from_workload(w, precision=prec)
     no4 = ctx.n_o ** 4
     nb = 2 * ctx.Nq * ctx.n_dR
     lam0, n = w["lam0"], w["n_steps"]
@@ -231,6 +234,7 @@ def surrogate_bench(T, torch, w, K, n_rows=200000, epochs=(20, 20, 20)):
     r0 = T.tufrg_flow(ctx, P, C, lam0, lam_k, n_steps=K, v_max=w["v_max"])
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
+    print(f"surrogate bench: {K} plain steps in {t_plain:.1f} s", file=sys.stderr, flush=True)
     P0, C0 = P.clone(), C.clone()
     # training data from plain loops at the scales of the K steps
     n_lam = K
@@ -255,11 +259,13 @@ def surrogate_bench(T, torch, w, K, n_rows=200000, epochs=(20, 20, 20)):
     del Lc
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
+    print(f"surrogate bench: {n_lam * per} training rows in {t_data:.1f} s", file=sys.stderr, flush=True)
     net = T.Mlp(sizes, mlp_init(sizes, seed=3))
     t0 = time.perf_counter()
     loss = None
     for ep, lr in zip(epochs, (1e-3, 3e-4, 1e-4)):
         loss = T.tufrg_mlp_train(net, X, Y, batch=2048, epochs=ep, lr=lr, seed=3)
+        print(f"surrogate bench: {ep} epochs at lr {lr:g}, loss {loss:.3e}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del X, Y
@@ -273,6 +279,7 @@ def surrogate_bench(T, torch, w, K, n_rows=200000, epochs=(20, 20, 20)):
                       sur_tol=1e-3, plain_above=20.0, sample_seed=3)
     torch.cuda.synchronize()
     t_sur = time.perf_counter() - t0
+    print(f"surrogate bench: {K} surrogate steps in {t_sur:.1f} s", file=sys.stderr, flush=True)
     sur_ms, sur_n = T.tufrg_timing_read(ctx, T.TIMER_SURROGATE)
     T.tufrg_timing(ctx, False)
     err = max((P - P0).abs().max().item() / P0.abs().max().item(),
@@ -292,15 +299,16 @@ def surrogate_bench(T, torch, w, K, n_rows=200000, epochs=(20, 20, 20)):
     out = {
         "metric": METRIC, "value": entries * K / t_sur, "unit": "loop entries/s", "n_gpus": 1, "steps": K,
         "warmup": 0, "ms_per_step": t_sur / K * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "vs_baseline": None, "dtype": prec, "data": "synthetic",
         "config": {"workload": w["name"], "n_orb": w["n_o"], "n_ff": len(w["ff"]), "B": ctx.B, "Lq": w["Lq"],
                    "n_ref": w["n_ref"], "Nq": ctx.Nq, "Nf": ctx.Nf,
                    "step": f"first {K} of {n} Euler steps with the loop surrogate", "parallelism": "single GPU"},
-        "plain_fp32": {"ms_per_step": t_plain / K * 1e3, "value": entries * K / t_plain, "result": r0},
+        "plain": {"precision": prec, "ms_per_step": t_plain / K * 1e3, "value": entries * K / t_plain,
+                  "result": r0},
         "surrogate": dict(r1, seconds=t_sur, network_ms=sur_ms, network_calls=sur_n),
-        "speedup_vs_plain_fp32": t_plain / t_sur, "rel_err_vs_plain_fp32": err,
+        "speedup_vs_plain": t_plain / t_sur, "rel_err_vs_plain": err,
         "surrogate_tol_5e-2": dict(r2, seconds=t_loose, ms_per_step=t_loose / K * 1e3,
-                                   speedup_vs_plain_fp32=t_plain / t_loose, rel_err_vs_plain_fp32=err_loose),
+                                   speedup_vs_plain=t_plain / t_loose, rel_err_vs_plain=err_loose),
         "training": {"rows": n_lam * per, "scales": [float(x) for x in lams], "data_seconds": t_data,
                      "train_seconds": t_train, "final_loss": loss, "net": sizes},
         "roofline": None,
@@ -396,7 +404,7 @@ def main():
         print(json.dumps(batch_bench(T, torch, K, W)))
         return
     if args.workload == "t2g_s13_L48":
-        print(json.dumps(surrogate_bench(T, torch, workload(args.workload), K)))
+        print(json.dumps(surrogate_bench(T, torch, workload(args.workload), K, args.prec)))
         return
     w = workload(args.workload)
     lam0, lam_mid = 10.0, 1.0

@@ -38,7 +38,7 @@ constexpr int XC = 21;               // x = (a, c), a <= c
 constexpr int NCOL = 72, NT = 5;     // columns (y, re/im); 16-wide column tiles
 constexpr int KT = 8;                // ky per tile
 constexpr int KS = 12 * KT / 32;     // K steps of 32 per tile
-constexpr int NW = 4, NTHR = 64 * NW;
+constexpr int NW = 4, NWP = 4, NTHR = 64 * (NW + NWP);  // matrix-core waves, staging waves
 constexpr int BFRAG = KS * NT * 64 * 8;  // BF16 values of the B operand of one tile
 
 // x index -> (a, c)
@@ -79,29 +79,32 @@ __device__ inline void split2(float a, float b, unsigned &hi, unsigned &lo) {
 }  // namespace
 
 template <int NDY, int SCHEME>
-__global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restrict__ band,
+__global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restrict__ band,
                                                             const float *__restrict__ kv,
                                                             const float *__restrict__ phy, int Lq, int n_ref,
                                                             int Lf, int q_first, const int *__restrict__ rows,
                                                             int ch, float lam, int deriv, float *__restrict__ Y) {
   constexpr int NPHI = 2 * NDY + 1, ROWS = NPHI * XC, MT = (ROWS + 15) / 16, MTW = (MT + NW - 1) / NW;
+  constexpr int SPC = KT * NO * XC * 2;  // floats of one Pi buffer
   const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index: uniform, keeps the tile guards scalar
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index: uniform, keeps the role branches scalar
   const int qrel = blockIdx.x;
   const int qi = rows ? rows[qrel / Lq] * Lq + qrel % Lq : q_first + qrel;
   const int qfx = (qi / Lq) * n_ref, qfy = (qi % Lq) * n_ref;
   const float sg = ch == 0 ? 1.f : -1.f;
 
+  // Two operand buffers (b = tile parity): the Pi values in the A-side layout,
+  // the phases and the split B operand.  X and the loop kernels are private to
+  // the producer wave that owns their ky and need one buffer.
   __shared__ float sL[KT][NO][NO];         // loop kernels L_mn of each ky
-  // X_n(k') packed (transposed for ph), then Pi_m(k)_x for x = (a <= c), in one
-  // array so that a store of either is one address computation
-  __shared__ __align__(16) float sStage[KT * PK + KT * NO * XC * 2];
+  // X_n(k') packed (transposed for ph), then Pi_m(k)_x for x = (a <= c) of the
+  // two buffers, in one array so that a store of either is one address
+  __shared__ __align__(16) float sStage[KT * PK + 2 * SPC];
   float(*sX)[PK] = (float(*)[PK])sStage;
-  float2(*sPc)[XC] = (float2(*)[XC])(sStage + KT * PK);
-  __shared__ float sPh[KT][NPHI];          // 1, cos, -sin
-  __shared__ __align__(16) __bf16 sBh[BFRAG], sBl[BFRAG];
+  __shared__ float sPh[2][KT][NPHI];       // 1, cos, -sin
+  __shared__ __align__(16) __bf16 sBh[2][BFRAG], sBl[2][BFRAG];
   __shared__ int sSlotX[XC][2];            // packed slots (Re, Im) of x = (a <= c); Im < 0 on the diagonal
-  __shared__ int sPcOf[NO2];               // packed slot -> float index into sPc[jm]
+  __shared__ int sPcOf[NO2];               // packed slot -> float index into the Pi row of (ky, m)
   if (tid < XC) {
     int re, im;
     float sgn;
@@ -112,117 +115,112 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
     if (im >= 0) sPcOf[im] = 2 * tid + 1;
   }
   // the imaginary parts of the diagonal x stay zero
-  for (int i = tid; i < KT * NO * XC; i += NTHR) ((float *)sPc)[2 * i + 1] = 0.f;
-
+  for (int i = tid; i < 2 * KT * NO * XC; i += NTHR) sStage[KT * PK + 2 * i + 1] = 0.f;
   // padding columns 72..79 of the last column tile stay zero
-  for (int i = tid; i < KS * 64 * 8; i += NTHR) {
-    const int s = i / (64 * 8), l = (i / 8) % 64, r = i % 8;
+  for (int i = tid; i < 2 * KS * 64 * 8; i += NTHR) {
+    const int bb = i / (KS * 64 * 8), s = (i / (64 * 8)) % KS, l = (i / 8) % 64, r = i % 8;
     if ((l & 15) >= 8) {
       const int idx = ((s * NT + (NT - 1)) * 64 + l) * 8 + r;
-      sBh[idx] = (__bf16)0.f;
-      sBl[idx] = (__bf16)0.f;
+      sBh[bb][idx] = (__bf16)0.f;
+      sBl[bb][idx] = (__bf16)0.f;
     }
   }
+  __syncthreads();
 
-  // Staged values of one tile: the packed Pi of k, the packed X of k' = q - k
-  // (pp) or k - q (ph), the phases, and per (ky, m, n) the band energies and
-  // regulator values that enter the loop kernel L_mn.  They are loaded into
-  // registers during the matrix-core phase of the previous tile and written to
-  // LDS (the loop kernels evaluated on the way) when it is done, so the load
-  // latency hides behind the products.
-  // thread -> one (ky, side) of the tile and packed values p = pl + 16 u of it
-  static_assert(KT * 2 * 16 == NTHR, "staging map");
-  constexpr int SPT = (PK + 15) / 16, NDD = KT * NO2;
-  static_assert(NDD >= NTHR, "one loop kernel item per thread at least");
-  const int sj = tid >> 5, sside = (tid >> 4) & 1, pl0 = tid & 15;
-  float pre[SPT], preph = 0.f, pe[4];
-  auto kidx = [&](int kxn, int ky, int side) -> unsigned {
-    if (side == 0) return (unsigned)kxn * Lf + ky;
-    int kpx = ch == 0 ? qfx - kxn : kxn - qfx;
-    kpx += kpx < 0 ? Lf : 0;
-    int kpy = ch == 0 ? qfy - ky : ky - qfy;
-    kpy += kpy < 0 ? Lf : 0;
-    return (unsigned)kpx * Lf + kpy;
-  };
-  // inputs of loop kernel item i = (ky, m, n): E_m(k), K_m(k), E_n(k'), K_n(k')
-  auto dd_inputs = [&](int kxn, int ky0n, int i, float *e) {
-    const int j = i / NO2, m = (i / NO) % NO, n = i % NO;
-    const int ky = ky0n + j < Lf ? ky0n + j : Lf - 1;
-    const unsigned k0 = kidx(kxn, ky, 0), k1 = kidx(kxn, ky, 1);
-    e[0] = band[(size_t)k0 * NC + m];
-    e[1] = kv[(size_t)k0 * NO + m];
-    e[2] = band[(size_t)k1 * NC + n];
-    e[3] = kv[(size_t)k1 * NO + n];
-  };
-  auto fetch = [&](int kxn, int ky0n) {
-    {
-      const int ky = ky0n + sj < Lf ? ky0n + sj : Lf - 1;
-      const float *bp = band + (size_t)kidx(kxn, ky, sside) * NC + NO;
+  const int ntk = (Lf + KT - 1) / KT, ntile = Lf * ntk;
+  float *Yq = Y + (size_t)qrel * Lf * ROWS * NCOL;
+
+  if (wv >= NW) {
+    // ------------------------------------------------------------------
+    // Producer wave p: ky rows 2p, 2p + 1 of each tile.  For tile t + 1 it
+    // writes Pi and the phases into buffer (t + 1) & 1, evaluates the loop
+    // kernels, forms W and writes the B operand; the loads of tile t + 2 are
+    // then issued and land while the consumers work on tile t + 1.
+    // lane -> one (ky, side) of the wave's rows and packed values p = pl + 16 u
+    static_assert(KT == 2 * NWP, "two ky per producer wave");
+    const int p = wv - NW;
+    constexpr int SPT = (PK + 15) / 16, NDDW = 2 * NO2;  // loop kernel items of one wave
+    const int sj = 2 * p + (lane >> 5), sside = (lane >> 4) & 1, pl0 = lane & 15;
+    float pre[SPT], preph = 0.f, pe[2][4];
+    auto kidx = [&](int kxn, int ky, int side) -> unsigned {
+      if (side == 0) return (unsigned)kxn * Lf + ky;
+      int kpx = ch == 0 ? qfx - kxn : kxn - qfx;
+      kpx += kpx < 0 ? Lf : 0;
+      int kpy = ch == 0 ? qfy - ky : ky - qfy;
+      kpy += kpy < 0 ? Lf : 0;
+      return (unsigned)kpx * Lf + kpy;
+    };
+    auto fetch = [&](int t) {
+      const int kxn = t / ntk, ky0n = (t - kxn * ntk) * KT;
+      {
+        const int ky = ky0n + sj < Lf ? ky0n + sj : Lf - 1;
+        const float *bp = band + (size_t)kidx(kxn, ky, sside) * NC + NO;
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+          const int pk = pl0 + 16 * u;
+          if (pk < PK) pre[u] = bp[pk];
+        }
+      }
+      // loop kernel item i = (ky, m, n) of the wave: E_m(k), K_m(k), E_n(k'), K_n(k')
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int i = lane + 64 * v;
+        if (i < NDDW) {
+          const int j = 2 * p + i / NO2, m = (i / NO) % NO, n = i % NO;
+          const int ky = ky0n + j < Lf ? ky0n + j : Lf - 1;
+          const unsigned k0 = kidx(kxn, ky, 0), k1 = kidx(kxn, ky, 1);
+          pe[v][0] = band[(size_t)k0 * NC + m];
+          pe[v][1] = kv[(size_t)k0 * NO + m];
+          pe[v][2] = band[(size_t)k1 * NC + n];
+          pe[v][3] = kv[(size_t)k1 * NO + n];
+        }
+      }
+      if (lane < 2 * NPHI) {
+        const int j = 2 * p + lane / NPHI, f = lane % NPHI;
+        const int kyp = ky0n + j < Lf ? ky0n + j : Lf - 1;
+        const float v = f > 0 ? phy[((size_t)kyp * NDY + ((f - 1) % NDY)) * 2 + (f > NDY ? 1 : 0)] : 1.f;
+        preph = ky0n + j < Lf ? v : 0.f;  // ky beyond the mesh contributes nothing
+      }
+    };
+    auto stage = [&](int bb) {
+      // deposit: one LDS store per value, its address chosen per lane (the
+      // two sides of the wave go to different arrays)
 #pragma unroll
       for (int u = 0; u < SPT; ++u) {
-        const int p = pl0 + 16 * u;
-        if (p < PK) pre[u] = bp[p];
+        const int pk = pl0 + 16 * u;
+        if (16 * u + 15 < PK || pk < PK) {
+          const int m = pk / NO2, pl = pk - NO2 * m;
+          const bool flip = sside && ch == 1 && pl >= NO && ((pl - NO) & 1);
+          const int po = KT * PK + bb * SPC + 2 * XC * (sj * NO + m) + sPcOf[pl], xo = sj * PK + pk;
+          sStage[po + ((xo - po) & -sside)] = flip ? -pre[u] : pre[u];
+        }
       }
-    }
-    dd_inputs(kxn, ky0n, tid, pe);
-    if (tid < KT * NPHI) {
-      const int j = tid / NPHI, f = tid % NPHI;
-      const int kyp = ky0n + j < Lf ? ky0n + j : Lf - 1;
-      const float v = f > 0 ? phy[((size_t)kyp * NDY + ((f - 1) % NDY)) * 2 + (f > NDY ? 1 : 0)] : 1.f;
-      preph = ky0n + j < Lf ? v : 0.f;  // ky beyond the mesh contributes nothing
-    }
-  };
-  auto deposit = [&](int kxd, int ky0d) {
-    // one LDS store per value, its address chosen per lane: the two sides of
-    // a wave go to different arrays
 #pragma unroll
-    for (int u = 0; u < SPT; ++u) {
-      const int p = pl0 + 16 * u;
-      if (16 * u + 15 < PK || p < PK) {
-        const int m = p / NO2, pl = p - NO2 * m;
-        const bool flip = sside && ch == 1 && pl >= NO && ((pl - NO) & 1);
-        const int po = KT * PK + 2 * XC * (sj * NO + m) + sPcOf[pl], xo = sj * PK + p;
-        sStage[po + ((xo - po) & -sside)] = flip ? -pre[u] : pre[u];
+      for (int v = 0; v < 2; ++v) {
+        const int i = lane + 64 * v;
+        if (i < NDDW)
+          (&sL[2 * p][0][0])[i] =
+              sg * divided_difference(pe[v][0], -sg * pe[v][2], pe[v][1], -sg * pe[v][3], lam, SCHEME, deriv);
       }
-    }
-    (&sL[0][0][0])[tid] = sg * divided_difference(pe[0], -sg * pe[2], pe[1], -sg * pe[3], lam, SCHEME, deriv);
-    // the items beyond one per thread read their inputs now (cache hits: the
-    // same rows were just fetched)
-    for (int i = tid + NTHR; i < NDD; i += NTHR) {
-      float e[4];
-      dd_inputs(kxd, ky0d, i, e);
-      (&sL[0][0][0])[i] = sg * divided_difference(e[0], -sg * e[2], e[1], -sg * e[3], lam, SCHEME, deriv);
-    }
-    if (tid < KT * NPHI) sPh[tid / NPHI][tid % NPHI] = preph;
-  };
-
-  f32x4 acc[MTW][NT];
-  float *Yq = Y + (size_t)qrel * Lf * ROWS * NCOL;
-  fetch(0, 0);
-  for (int kx = 0; kx < Lf; ++kx) {
-#pragma unroll
-    for (int j = 0; j < MTW; ++j)
-#pragma unroll
-      for (int n = 0; n < NT; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int ky0 = 0; ky0 < Lf; ky0 += KT) {
-      __syncthreads();
-      deposit(kx, ky0);
-      __syncthreads();
+      if (lane < 2 * NPHI) sPh[bb][2 * p + lane / NPHI][lane % NPHI] = preph;
+      // X and the loop kernels of these rows were written by this wave
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       // W_m = sum_n L_mn X_n, written straight into the B operand: rows
       // k = (ky, m, re/im), columns (y, re/im), split and in lane order.  For
       // W = wr + i wi the 2 x 2 block of (k re, k im) x (col re, col im) is
-      // [[wr, wi], [-wi, wr]].  One item is one chunk of 8 k (4 (ky, m), the 8
-      // values one lane holds for one column) and one pair y = (b, d), b <= d:
-      // W is Hermitian, so (d, b) takes the conjugate.  Each column is one
-      // 16-byte store per operand half.
-      static_assert(KT * NO % 4 == 0, "chunks of 4 (ky, m)");
-      if (tid < KT * NO / 4 * XC) {
-        const int t = tid / XC, yp = tid % XC;
+      // [[wr, wi], [-wi, wr]].  One item is one chunk of 8 k (4 (ky, m), the
+      // 8 values one lane holds for one column; the wave's 12 (ky, m) are
+      // chunks 3p .. 3p + 2) and one pair y = (b, d), b <= d: W is Hermitian,
+      // so (d, b) takes the conjugate.  Each column is one 16-byte store per
+      // operand half.
+      static_assert(2 * NO == 3 * 4, "three chunks of 4 (ky, m) per producer wave");
+      if (lane < 3 * XC) {
+        const int tc = 3 * p + lane / XC, yp = lane % XC;
         const int re = sSlotX[yp][0], im = sSlotX[yp][1], imr = im >= 0 ? im : re;
         unsigned ur[4], ui[4], vr[4], vi[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const int jm = 4 * t + c, j = jm / NO, m = jm % NO;
+          const int jm = 4 * tc + c, j = jm / NO, m = jm % NO;
           float wr = 0.f, wi = 0.f;
 #pragma unroll
           for (int n = 0; n < NO; ++n) {
@@ -239,24 +237,24 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
           ui[c] = __builtin_bit_cast(unsigned short, hi);
           vi[c] = __builtin_bit_cast(unsigned short, li);
         }
-        const int b = XA[yp], d = XCc[yp], s = t >> 2, g4 = t & 3;
+        const int b = XA[yp], d = XCc[yp], s = tc >> 2, g4 = tc & 3;
         {
           // y = (b, d): column re (wr, -wi), column im (wi, wr)
           const int col = 2 * (b * NO + d), n = col >> 4;
           const int idx = ((s * NT + n) * 64 + g4 * 16 + (col & 15)) * 8;
           uint4 h0, l0, h1, l1;
-          unsigned *ph0 = (unsigned *)&h0, *pl0 = (unsigned *)&l0, *ph1 = (unsigned *)&h1, *pl1 = (unsigned *)&l1;
+          unsigned *ph0 = (unsigned *)&h0, *pl0_ = (unsigned *)&l0, *ph1 = (unsigned *)&h1, *pl1 = (unsigned *)&l1;
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             ph0[c] = (ur[c] | (ui[c] << 16)) ^ 0x80000000u;
-            pl0[c] = (vr[c] | (vi[c] << 16)) ^ 0x80000000u;
+            pl0_[c] = (vr[c] | (vi[c] << 16)) ^ 0x80000000u;
             ph1[c] = ui[c] | (ur[c] << 16);
             pl1[c] = vi[c] | (vr[c] << 16);
           }
-          *(uint4 *)&sBh[idx] = h0;
-          *(uint4 *)&sBl[idx] = l0;
-          *(uint4 *)&sBh[idx + 8] = h1;
-          *(uint4 *)&sBl[idx + 8] = l1;
+          *(uint4 *)&sBh[bb][idx] = h0;
+          *(uint4 *)&sBl[bb][idx] = l0;
+          *(uint4 *)&sBh[bb][idx + 8] = h1;
+          *(uint4 *)&sBl[bb][idx + 8] = l1;
         }
         {
           // y = (d, b) holds the conjugate: column re (wr, wi), column im (-wi, wr).
@@ -265,32 +263,53 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
           const int col = 2 * (d * NO + b), n = col >> 4;
           const int idx = ((s * NT + n) * 64 + g4 * 16 + (col & 15)) * 8;
           uint4 h0, l0, h1, l1;
-          unsigned *ph0 = (unsigned *)&h0, *pl0 = (unsigned *)&l0, *ph1 = (unsigned *)&h1, *pl1 = (unsigned *)&l1;
+          unsigned *ph0 = (unsigned *)&h0, *pl0_ = (unsigned *)&l0, *ph1 = (unsigned *)&h1, *pl1 = (unsigned *)&l1;
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
             ph0[c] = ur[c] | (ui[c] << 16);
-            pl0[c] = vr[c] | (vi[c] << 16);
+            pl0_[c] = vr[c] | (vi[c] << 16);
             ph1[c] = (ui[c] | (ur[c] << 16)) ^ 0x8000u;
             pl1[c] = (vi[c] | (vr[c] << 16)) ^ 0x8000u;
           }
-          *(uint4 *)&sBh[idx] = h0;
-          *(uint4 *)&sBl[idx] = l0;
-          *(uint4 *)&sBh[idx + 8] = h1;
-          *(uint4 *)&sBl[idx + 8] = l1;
+          *(uint4 *)&sBh[bb][idx] = h0;
+          *(uint4 *)&sBl[bb][idx] = l0;
+          *(uint4 *)&sBh[bb][idx + 8] = h1;
+          *(uint4 *)&sBl[bb][idx + 8] = l1;
         }
       }
+      // the next stage of this wave rewrites X and the loop kernels
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    };
+    fetch(0);
+    stage(0);
+    if (1 < ntile) fetch(1);
+    __syncthreads();
+    for (int t = 0; t < ntile; ++t) {
+      if (t + 1 < ntile) {
+        stage((t + 1) & 1);
+        if (t + 2 < ntile) fetch(t + 2);
+      }
       __syncthreads();
-      // the next tile (the next row's first after the last) is loaded during the products
-      if (ky0 + KT < Lf)
-        fetch(kx, ky0 + KT);
-      else if (kx + 1 < Lf)
-        fetch(kx + 1, 0);
-      // A operand (phases times Pi) of this wave's row tiles, then per column
-      // tile the 3 products hi*hi, hi*lo, lo*hi.  A row tile past the last
-      // (possible for the 3 x 3 box) has a zero A operand and is not written.
-#pragma unroll 1
-      for (int s = 0; s < KS; ++s) {
-        bf16x8 ah[MTW], al[MTW];
+    }
+  } else {
+    // ------------------------------------------------------------------
+    // Consumer wave: 3 of the 12 row tiles (phase x Pi rows) by the 5 column
+    // tiles, accumulated over a kx row and written to the row buffer at its end
+    f32x4 acc[MTW][NT];
+    __syncthreads();
+    for (int t = 0; t < ntile; ++t) {
+      const int bb = t & 1, kx = t / ntk, tk = t - kx * ntk;
+      if (tk == 0) {
+#pragma unroll
+        for (int j = 0; j < MTW; ++j)
+#pragma unroll
+          for (int n = 0; n < NT; ++n) acc[j][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+      }
+      const float2(*sPc)[XC] = (const float2(*)[XC])(sStage + KT * PK + bb * SPC);
+      // A operand (phases times Pi) of this wave's row tiles for k-step s; a
+      // row tile past the last (possible for the 3 x 3 box) has a zero A
+      // operand and is not written
+      auto build_a = [&](int s, bf16x8 (&ah)[MTW], bf16x8 (&al)[MTW]) {
 #pragma unroll
         for (int jt = 0; jt < MTW; ++jt) {
           const int mt = wv + NW * jt;
@@ -301,18 +320,21 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int jm = 16 * s + 4 * g + r;  // (ky, m) of k = 2 jm (re) and 2 jm + 1 (im)
-            const float2 p = sPc[jm][xi];
-            float ph = sPh[jm / NO][f];
+            const float2 pv = sPc[jm][xi];
+            float ph = sPh[bb][jm / NO][f];
             ph = rv ? ph : 0.f;
-            split2(ph * p.x, ph * p.y, hp[r], lp[r]);
+            split2(ph * pv.x, ph * pv.y, hp[r], lp[r]);
           }
           ah[jt] = __builtin_bit_cast(bf16x8, (u32x4){hp[0], hp[1], hp[2], hp[3]});
           al[jt] = __builtin_bit_cast(bf16x8, (u32x4){lp[0], lp[1], lp[2], lp[3]});
         }
+      };
+      // per column tile the 3 products hi*hi, hi*lo, lo*hi
+      auto products = [&](int s, const bf16x8 (&ah)[MTW], const bf16x8 (&al)[MTW]) {
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-          const bf16x8 bh = *(const bf16x8 *)&sBh[((s * NT + n) * 64 + lane) * 8];
-          const bf16x8 bl = *(const bf16x8 *)&sBl[((s * NT + n) * 64 + lane) * 8];
+          const bf16x8 bh = *(const bf16x8 *)&sBh[bb][((s * NT + n) * 64 + lane) * 8];
+          const bf16x8 bl = *(const bf16x8 *)&sBl[bb][((s * NT + n) * 64 + lane) * 8];
 #pragma unroll
           for (int jt = 0; jt < MTW; ++jt)
             acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[jt], bh, acc[jt][n], 0, 0, 0);
@@ -323,23 +345,36 @@ __global__ __launch_bounds__(NTHR, 2) void loop_mfma_kernel(const float *__restr
           for (int jt = 0; jt < MTW; ++jt)
             acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[jt], bh, acc[jt][n], 0, 0, 0);
         }
-      }
-    }
-    // row tile (mt, n): lane holds rows 4 g + r, column lane % 16
-    float *Yr = Yq + (size_t)kx * ROWS * NCOL;
+      };
+      // software pipeline over the k-steps: the operand of step s + 1 is built
+      // while the matrix ops of step s run
+      static_assert(KS == 3, "three k-steps per tile");
+      bf16x8 ah0[MTW], al0[MTW], ah1[MTW], al1[MTW];
+      build_a(0, ah0, al0);
+      build_a(1, ah1, al1);
+      products(0, ah0, al0);
+      build_a(2, ah0, al0);
+      products(1, ah1, al1);
+      products(2, ah0, al0);
+      if (tk == ntk - 1) {
+        // row tile (mt, n): lane holds rows 4 g + r, column lane % 16
+        float *Yr = Yq + (size_t)kx * ROWS * NCOL;
 #pragma unroll
-    for (int jt = 0; jt < MTW; ++jt) {
-      const int mt = wv + NW * jt;
-      if (mt >= MT) break;
+        for (int jt = 0; jt < MTW; ++jt) {
+          const int mt = wv + NW * jt;
+          if (mt >= MT) break;
 #pragma unroll
-      for (int n = 0; n < NT; ++n) {
-        const int col = n * 16 + (lane & 15);
+          for (int n = 0; n < NT; ++n) {
+            const int col = n * 16 + (lane & 15);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = mt * 16 + 4 * g + r;
-          if (row < ROWS && col < NCOL) Yr[(size_t)row * NCOL + col] = acc[jt][n][r];
+            for (int r = 0; r < 4; ++r) {
+              const int row = mt * 16 + 4 * g + r;
+              if (row < ROWS && col < NCOL) Yr[(size_t)row * NCOL + col] = acc[jt][n][r];
+            }
+          }
         }
       }
+      __syncthreads();
     }
   }
 }

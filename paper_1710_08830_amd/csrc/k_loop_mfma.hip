@@ -141,7 +141,10 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
     const int p = wv - NW;
     constexpr int SPT = (PK + 15) / 16, NDDW = 2 * NO2;  // loop kernel items of one wave
     const int sj = 2 * p + (lane >> 5), sside = (lane >> 4) & 1, pl0 = lane & 15;
-    float pre[SPT], preph = 0.f, pe[2][4];
+    // values of one tile in flight: packed Pi or X, loop kernel inputs, phase
+    struct Pre {
+      float v[SPT], e[2][4], ph;
+    };
     auto kidx = [&](int kxn, int ky, int side) -> unsigned {
       if (side == 0) return (unsigned)kxn * Lf + ky;
       int kpx = ch == 0 ? qfx - kxn : kxn - qfx;
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
       kpy += kpy < 0 ? Lf : 0;
       return (unsigned)kpx * Lf + kpy;
     };
-    auto fetch = [&](int t) {
+    auto fetch = [&](int t, Pre &pr) {
       const int kxn = t / ntk, ky0n = (t - kxn * ntk) * KT;
       {
         const int ky = ky0n + sj < Lf ? ky0n + sj : Lf - 1;
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
 #pragma unroll
         for (int u = 0; u < SPT; ++u) {
           const int pk = pl0 + 16 * u;
-          if (pk < PK) pre[u] = bp[pk];
+          if (pk < PK) pr.v[u] = bp[pk];
         }
       }
       // loop kernel item i = (ky, m, n) of the wave: E_m(k), K_m(k), E_n(k'), K_n(k')
@@ -169,20 +172,20 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
           const int j = 2 * p + i / NO2, m = (i / NO) % NO, n = i % NO;
           const int ky = ky0n + j < Lf ? ky0n + j : Lf - 1;
           const unsigned k0 = kidx(kxn, ky, 0), k1 = kidx(kxn, ky, 1);
-          pe[v][0] = band[(size_t)k0 * NC + m];
-          pe[v][1] = kv[(size_t)k0 * NO + m];
-          pe[v][2] = band[(size_t)k1 * NC + n];
-          pe[v][3] = kv[(size_t)k1 * NO + n];
+          pr.e[v][0] = band[(size_t)k0 * NC + m];
+          pr.e[v][1] = kv[(size_t)k0 * NO + m];
+          pr.e[v][2] = band[(size_t)k1 * NC + n];
+          pr.e[v][3] = kv[(size_t)k1 * NO + n];
         }
       }
       if (lane < 2 * NPHI) {
         const int j = 2 * p + lane / NPHI, f = lane % NPHI;
         const int kyp = ky0n + j < Lf ? ky0n + j : Lf - 1;
         const float v = f > 0 ? phy[((size_t)kyp * NDY + ((f - 1) % NDY)) * 2 + (f > NDY ? 1 : 0)] : 1.f;
-        preph = ky0n + j < Lf ? v : 0.f;  // ky beyond the mesh contributes nothing
+        pr.ph = ky0n + j < Lf ? v : 0.f;  // ky beyond the mesh contributes nothing
       }
     };
-    auto stage = [&](int bb) {
+    auto stage = [&](int bb, const Pre &pr) {
       // deposit: one LDS store per value, its address chosen per lane (the
       // two sides of the wave go to different arrays)
 #pragma unroll
@@ -192,7 +195,7 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
           const int m = pk / NO2, pl = pk - NO2 * m;
           const bool flip = sside && ch == 1 && pl >= NO && ((pl - NO) & 1);
           const int po = KT * PK + bb * SPC + 2 * XC * (sj * NO + m) + sPcOf[pl], xo = sj * PK + pk;
-          sStage[po + ((xo - po) & -sside)] = flip ? -pre[u] : pre[u];
+          sStage[po + ((xo - po) & -sside)] = flip ? -pr.v[u] : pr.v[u];
         }
       }
 #pragma unroll
@@ -200,9 +203,9 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
         const int i = lane + 64 * v;
         if (i < NDDW)
           (&sL[2 * p][0][0])[i] =
-              sg * divided_difference(pe[v][0], -sg * pe[v][2], pe[v][1], -sg * pe[v][3], lam, SCHEME, deriv);
+              sg * divided_difference(pr.e[v][0], -sg * pr.e[v][2], pr.e[v][1], -sg * pr.e[v][3], lam, SCHEME, deriv);
       }
-      if (lane < 2 * NPHI) sPh[bb][2 * p + lane / NPHI][lane % NPHI] = preph;
+      if (lane < 2 * NPHI) sPh[bb][2 * p + lane / NPHI][lane % NPHI] = pr.ph;
       // X and the loop kernels of these rows were written by this wave
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       // W_m = sum_n L_mn X_n, written straight into the B operand: rows
@@ -280,16 +283,27 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
       // the next stage of this wave rewrites X and the loop kernels
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     };
-    fetch(0);
-    stage(0);
-    if (1 < ntile) fetch(1);
+    // two register sets: the loads of a tile are issued two tiles before it
+    // is staged (even tiles in pa, odd tiles in pb)
+    Pre pa, pb;
+    fetch(0, pa);
+    if (1 < ntile) fetch(1, pb);
+    stage(0, pa);
+    if (2 < ntile) fetch(2, pa);
     __syncthreads();
-    for (int t = 0; t < ntile; ++t) {
+    for (int t = 0; t < ntile; t += 2) {
       if (t + 1 < ntile) {
-        stage((t + 1) & 1);
-        if (t + 2 < ntile) fetch(t + 2);
+        stage(1, pb);
+        if (t + 3 < ntile) fetch(t + 3, pb);
       }
       __syncthreads();
+      if (t + 1 < ntile) {
+        if (t + 2 < ntile) {
+          stage(0, pa);
+          if (t + 4 < ntile) fetch(t + 4, pa);
+        }
+        __syncthreads();
+      }
     }
   } else {
     // ------------------------------------------------------------------

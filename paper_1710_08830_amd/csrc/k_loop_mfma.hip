@@ -76,6 +76,13 @@ __device__ inline void split2(float a, float b, unsigned &hi, unsigned &lo) {
   lo = __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2){ra, rb}, bf16x2));
 }
 
+// Physical 16-byte granule of the B operand: block blk = (k-step, column tile)
+// of 64 granules, granule l = the lane that reads it.  The low four bits of l
+// are XOR-ed with a hash of (blk, l / 16): a reading lane group of 16 still
+// covers 16 distinct granules, while the stores of the staging waves (scattered
+// over columns) spread over more LDS banks.
+__device__ inline int bgran(int blk, int l) { return blk * 64 + (l ^ ((7 * blk + 10 * (l >> 4)) & 15)); }
+
 }  // namespace
 
 template <int NDY, int SCHEME>
@@ -120,7 +127,7 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
   for (int i = tid; i < 2 * KS * 64 * 8; i += NTHR) {
     const int bb = i / (KS * 64 * 8), s = (i / (64 * 8)) % KS, l = (i / 8) % 64, r = i % 8;
     if ((l & 15) >= 8) {
-      const int idx = ((s * NT + (NT - 1)) * 64 + l) * 8 + r;
+      const int idx = bgran(s * NT + (NT - 1), l) * 8 + r;
       sBh[bb][idx] = (__bf16)0.f;
       sBl[bb][idx] = (__bf16)0.f;
     }
@@ -220,16 +227,27 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
       if (lane < 3 * XC) {
         const int tc = 3 * p + lane / XC, yp = lane % XC;
         const int re = sSlotX[yp][0], im = sSlotX[yp][1], imr = im >= 0 ? im : re;
+        // X of this slot for both ky rows of the wave, read once (each read
+        // instruction stays within one row)
+        float xr[2][NO], xi[2][NO];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+          for (int n = 0; n < NO; ++n) {
+            xr[jj][n] = sX[2 * p + jj][n * NO2 + re];
+            xi[jj][n] = sX[2 * p + jj][n * NO2 + imr];
+          }
         unsigned ur[4], ui[4], vr[4], vi[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int jm = 4 * tc + c, j = jm / NO, m = jm % NO;
+          const bool j1 = j != 2 * p;
           float wr = 0.f, wi = 0.f;
 #pragma unroll
           for (int n = 0; n < NO; ++n) {
             const float l = sL[j][m][n];
-            wr = fmaf(l, sX[j][n * NO2 + re], wr);
-            wi = fmaf(l, sX[j][n * NO2 + imr], wi);
+            wr = fmaf(l, j1 ? xr[1][n] : xr[0][n], wr);
+            wi = fmaf(l, j1 ? xi[1][n] : xi[0][n], wi);
           }
           wi = im >= 0 ? wi : 0.f;
           __bf16 hr, lr, hi, li;
@@ -244,7 +262,8 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
         {
           // y = (b, d): column re (wr, -wi), column im (wi, wr)
           const int col = 2 * (b * NO + d), n = col >> 4;
-          const int idx = ((s * NT + n) * 64 + g4 * 16 + (col & 15)) * 8;
+          const int idx = bgran(s * NT + n, g4 * 16 + (col & 15)) * 8;
+          const int idx1 = bgran(s * NT + n, g4 * 16 + (col & 15) + 1) * 8;  // column im
           uint4 h0, l0, h1, l1;
           unsigned *ph0 = (unsigned *)&h0, *pl0_ = (unsigned *)&l0, *ph1 = (unsigned *)&h1, *pl1 = (unsigned *)&l1;
 #pragma unroll
@@ -256,15 +275,16 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
           }
           *(uint4 *)&sBh[bb][idx] = h0;
           *(uint4 *)&sBl[bb][idx] = l0;
-          *(uint4 *)&sBh[bb][idx + 8] = h1;
-          *(uint4 *)&sBl[bb][idx + 8] = l1;
+          *(uint4 *)&sBh[bb][idx1] = h1;
+          *(uint4 *)&sBl[bb][idx1] = l1;
         }
         {
           // y = (d, b) holds the conjugate: column re (wr, wi), column im (-wi, wr).
           // On the diagonal (wi = 0) this rewrites the same two columns with
           // the same values up to the sign of zero.
           const int col = 2 * (d * NO + b), n = col >> 4;
-          const int idx = ((s * NT + n) * 64 + g4 * 16 + (col & 15)) * 8;
+          const int idx = bgran(s * NT + n, g4 * 16 + (col & 15)) * 8;
+          const int idx1 = bgran(s * NT + n, g4 * 16 + (col & 15) + 1) * 8;  // column im
           uint4 h0, l0, h1, l1;
           unsigned *ph0 = (unsigned *)&h0, *pl0_ = (unsigned *)&l0, *ph1 = (unsigned *)&h1, *pl1 = (unsigned *)&l1;
 #pragma unroll
@@ -276,8 +296,8 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
           }
           *(uint4 *)&sBh[bb][idx] = h0;
           *(uint4 *)&sBl[bb][idx] = l0;
-          *(uint4 *)&sBh[bb][idx + 8] = h1;
-          *(uint4 *)&sBl[bb][idx + 8] = l1;
+          *(uint4 *)&sBh[bb][idx1] = h1;
+          *(uint4 *)&sBl[bb][idx1] = l1;
         }
       }
       // the next stage of this wave rewrites X and the loop kernels
@@ -347,8 +367,9 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
       auto products = [&](int s, const bf16x8 (&ah)[MTW], const bf16x8 (&al)[MTW]) {
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
-          const bf16x8 bh = *(const bf16x8 *)&sBh[bb][((s * NT + n) * 64 + lane) * 8];
-          const bf16x8 bl = *(const bf16x8 *)&sBl[bb][((s * NT + n) * 64 + lane) * 8];
+          const int gi = bgran(s * NT + n, lane) * 8;
+          const bf16x8 bh = *(const bf16x8 *)&sBh[bb][gi];
+          const bf16x8 bl = *(const bf16x8 *)&sBl[bb][gi];
 #pragma unroll
           for (int jt = 0; jt < MTW; ++jt)
             acc[jt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[jt], bh, acc[jt][n], 0, 0, 0);

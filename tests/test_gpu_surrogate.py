@@ -262,3 +262,26 @@ def test_trained_surrogate_replaces_plain_loops(T):
     err = max(rel(P1, P0), rel(C1, C0))
     print("relative error of the couplings vs the plain flow:", err)
     assert err < 2e-2
+
+
+def _t2g13():
+    return dict(hop=t2g_soc_hoppings(0.2, seed=1), mu=0.35, V0=kanamori_V0(2.0, 0.3), ff=ff_shell(13), Lq=9,
+                n_ref=2, cutoff="temperature")
+
+
+@pytest.mark.parametrize("case,prec", [("hub5", "fp32"), ("t2g9", "fp32"), ("t2g9", "bf16x3"),
+                                       ("t2g13", "bf16x3")])
+def test_all_rows_sampled_reproduce_the_plain_flow(T, case, prec):
+    """With every q_x row sampled and any sampled error accepted, the plain
+    loops of the sampled rows (computed in one launch through the row list, in
+    the hash's row order) replace all of the network's: the flow equals the
+    plain flow bit for bit.  Covers the row-list launch of each loop kernel."""
+    c = {"hub5": _hub5, "t2g9": _t2g9, "t2g13": _t2g13}[case]()
+    ctx = _ctx(T, c, prec)
+    sizes = [11 + ctx.n_dR, 32, 32, 2 * ctx.n_o ** 4]
+    net = T.Mlp(sizes, mlp_init(sizes, seed=5))
+    T.tufrg_sur_attach(ctx, net)
+    r0, P0, C0 = _flow(T, ctx)
+    r1, P1, C1 = _flow(T, ctx, surrogate=True, sample_frac=1.0, sur_tol=1e30, plain_above=1e30)
+    assert r1["n_surrogate"] == r1["n_rhs"] == r0["n_rhs"] and r1["n_fallback"] == 0
+    assert np.array_equal(P0, P1) and np.array_equal(C0, C1)

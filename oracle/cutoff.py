@@ -18,6 +18,18 @@ Omega scheme at T = 0 (propagator multiplied by w^2 / (w^2 + Omega^2)) the
 frequency integral gives J = e (2|e| + Omega) / (4 (|e| + Omega)^2).  The loops
 are the same divided differences of K = dJ/dLambda.
 
+The paper's own regulator (Sec. 3.1) suppresses momenta in a shell of
+thickness Lambda around the Fermi surfaces, at a fixed temperature T: each
+propagator is multiplied by chi_Lambda(e), so the bubbles become
+chi(e1) chi(e2) F-/+_T(e1, e2) and the loops their Lambda derivative,
+
+    L-/+ = [chi'(e1) chi(e2) + chi(e1) chi'(e2)] F-/+_T(e1, e2),
+
+chi' = d chi / d Lambda.  The paper does not fix the shape of chi; the reading
+here is the smooth shell chi_Lambda(e) = e^2 / (e^2 + Lambda^2) (zero on the
+Fermi surface, one half at |e| = Lambda, one far from it).  F_T is the
+temperature scheme's bubble at Lambda = T.
+
 Continuity at coinciding arguments (the paper is silent): when
 |x - y| <= DEGEN_REL * (Lambda + |x| + |y|) the divided difference is taken as
 the mean of g' over [x, y] by 4-point Gauss-Legendre quadrature, split at 0
@@ -28,6 +40,43 @@ import numpy as np
 
 TEMPERATURE = "temperature"
 OMEGA = "omega"
+SHELL = "shell"
+
+
+class Shell:
+    """Momentum-shell scheme at fixed temperature T (see the module text)."""
+
+    def __init__(self, T):
+        self.T = float(T)
+        if not self.T > 0.0:
+            raise ValueError("the shell scheme needs a temperature T > 0")
+
+    def __eq__(self, other):
+        return isinstance(other, Shell) and other.T == self.T
+
+    def __repr__(self):
+        return f"Shell(T={self.T!r})"
+
+
+def chi(e, lam):
+    """Shell regulator chi_Lambda(e) = e^2 / (e^2 + Lambda^2)."""
+    e = np.asarray(e, dtype=np.float64)
+    return e * e / (e * e + lam * lam)
+
+
+def dchi(e, lam):
+    """d chi_Lambda(e) / d Lambda."""
+    e = np.asarray(e, dtype=np.float64)
+    d = e * e + lam * lam
+    return -2.0 * lam * e * e / (d * d)
+
+
+def _shell_factor(e1, e2, lam, deriv):
+    """chi(e1) chi(e2) (bubble) or its Lambda derivative (loop)."""
+    if deriv:
+        return dchi(e1, lam) * chi(e2, lam) + chi(e1, lam) * dchi(e2, lam)
+    return chi(e1, lam) * chi(e2, lam)
+
 
 DEGEN_REL = 1e-3
 
@@ -116,6 +165,9 @@ def divided_difference(g, gp, x, y, lam, scheme):
 
 def loop_pp(e1, e2, lam, scheme, deriv=True):
     """Particle-particle loop L-(e1, e2) (deriv) or bubble F-(e1, e2)."""
+    if isinstance(scheme, Shell):
+        F = divided_difference(J, dJ_de, e1, -np.asarray(e2), scheme.T, TEMPERATURE)
+        return _shell_factor(e1, e2, lam, deriv) * F
     if deriv:
         return divided_difference(K, dK_de, e1, -np.asarray(e2), lam, scheme)
     return divided_difference(J, dJ_de, e1, -np.asarray(e2), lam, scheme)
@@ -123,6 +175,9 @@ def loop_pp(e1, e2, lam, scheme, deriv=True):
 
 def loop_ph(e1, e2, lam, scheme, deriv=True):
     """Particle-hole loop L+(e1, e2) (deriv) or bubble F+(e1, e2)."""
+    if isinstance(scheme, Shell):
+        F = -divided_difference(J, dJ_de, e1, e2, scheme.T, TEMPERATURE)
+        return _shell_factor(e1, e2, lam, deriv) * F
     if deriv:
         return -divided_difference(K, dK_de, e1, e2, lam, scheme)
     return -divided_difference(J, dJ_de, e1, e2, lam, scheme)

@@ -61,7 +61,7 @@ _DP_B4 = np.array([5179 / 57600, 0.0, 7571 / 16695, 393 / 640, -92097 / 339200,
 class TUSetup:
     """Meshes, form factors, band data and the initial interaction."""
 
-    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, scheme):
+    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, scheme, temperature=None):
         self.hop_R = np.asarray(hop_R)
         self.hop_t = np.asarray(hop_t)
         self.mu = float(mu)
@@ -74,7 +74,8 @@ class TUSetup:
         self.Lf = self.Lq * self.n_ref
         self.Nq = self.Lq ** 2
         self.Nf = self.Lf ** 2
-        self.scheme = scheme
+        # "temperature", "omega", or "shell" at the fixed temperature given
+        self.scheme = cutoff.Shell(temperature) if scheme == cutoff.SHELL else scheme
         self.coarse = bands.mesh(self.Lq)
         self.fine = bands.mesh(self.Lf)
         self.e, self.U = bands.band_data(self.hop_R, self.hop_t, self.mu, self.Lf)
@@ -95,7 +96,8 @@ class TUSetup:
     @classmethod
     def from_workload(cls, w, **over):
         kw = dict(hop_R=w["hop_R"], hop_t=w["hop_t"], mu=w["mu"], V0=w["V0"],
-                  ff=w["ff"], Lq=w["Lq"], n_ref=w["n_ref"], scheme=w["cutoff"])
+                  ff=w["ff"], Lq=w["Lq"], n_ref=w["n_ref"], scheme=w["cutoff"],
+                  temperature=w.get("temperature"))
         kw.update(over)
         return cls(**kw)
 

@@ -12,6 +12,7 @@ from scipy import integrate
 from oracle import cutoff
 
 T_SCHEME, O_SCHEME = cutoff.TEMPERATURE, cutoff.OMEGA
+S_SCHEME = cutoff.Shell(0.13)  # momentum shell at a fixed temperature
 
 PAIRS = [(0.3, -0.7), (-0.2, -0.45), (1.3, 0.4), (0.05, 0.11), (-2.0, 1.5), (0.8, -0.8001)]
 
@@ -65,7 +66,7 @@ def test_omega_bubbles_match_frequency_integrals(e1, e2, Om):
     assert fph == pytest.approx(_omega_integral(e1, e2, Om, "ph"), rel=1e-8, abs=1e-11)
 
 
-@pytest.mark.parametrize("scheme", [T_SCHEME, O_SCHEME])
+@pytest.mark.parametrize("scheme", [T_SCHEME, O_SCHEME, S_SCHEME])
 @pytest.mark.parametrize("e1,e2", PAIRS + [(0.4, 0.4), (0.4, -0.4), (0.0, 0.0)])
 def test_loop_integrates_to_bubble_difference(scheme, e1, e2):
     """int_{L1}^{L2} L dLambda = F(L2) - F(L1) (Gauss-Legendre in Lambda)."""
@@ -104,9 +105,46 @@ def test_divided_difference_is_continuous_across_threshold(scheme, x):
         assert abs(inside - exact) <= 2 * thr / lam * scale + 1e-12
 
 
-@pytest.mark.parametrize("scheme", [T_SCHEME, O_SCHEME])
+@pytest.mark.parametrize("scheme", [T_SCHEME, O_SCHEME, S_SCHEME])
 def test_loops_symmetric_in_band_arguments(scheme):
     rng = np.random.default_rng(5)
     e1, e2 = rng.uniform(-2, 2, 50), rng.uniform(-2, 2, 50)
     for loop in (cutoff.loop_pp, cutoff.loop_ph):
         assert np.allclose(loop(e1, e2, 0.3, scheme), loop(e2, e1, 0.3, scheme), rtol=1e-13, atol=0)
+
+
+def test_shell_regulator_shape():
+    """chi vanishes on the Fermi surface, is one half at |e| = Lambda and one far
+    from it; chi' is its Lambda derivative (central differences)."""
+    lam = 0.4
+    assert cutoff.chi(0.0, lam) == 0.0
+    assert cutoff.chi(lam, lam) == pytest.approx(0.5, rel=1e-15)
+    assert cutoff.chi(-lam, lam) == pytest.approx(0.5, rel=1e-15)
+    assert cutoff.chi(1e4 * lam, lam) == pytest.approx(1.0, abs=1e-7)
+    e = np.array([-1.2, -0.3, 0.05, 0.4, 2.0])
+    h = 1e-5
+    fd = (cutoff.chi(e, lam + h) - cutoff.chi(e, lam - h)) / (2 * h)
+    assert np.allclose(cutoff.dchi(e, lam), fd, rtol=1e-8, atol=1e-12)
+
+
+@pytest.mark.parametrize("e1,e2", PAIRS)
+@pytest.mark.parametrize("lam", [0.02, 0.25, 1.7])
+def test_shell_bubbles_are_regulated_matsubara_sums(e1, e2, lam):
+    """Each propagator multiplied by chi: the bubble is chi(e1) chi(e2) times
+    the Matsubara sum at the fixed temperature."""
+    w = cutoff.chi(e1, lam) * cutoff.chi(e2, lam)
+    fpp = cutoff.loop_pp(e1, e2, lam, S_SCHEME, deriv=False)[0]
+    fph = cutoff.loop_ph(e1, e2, lam, S_SCHEME, deriv=False)[0]
+    assert fpp == pytest.approx(w * _matsubara(e1, e2, S_SCHEME.T, "pp"), rel=1e-10, abs=1e-12)
+    assert fph == pytest.approx(w * _matsubara(e1, e2, S_SCHEME.T, "ph"), rel=1e-10, abs=1e-12)
+
+
+def test_shell_loop_on_and_far_from_the_fermi_surface():
+    """chi(0) = chi'(0) = 0: a pair with both energies on the Fermi surface has no
+    loop.  Far outside the shell (|e| >> Lambda) chi' = -2 Lambda / e^2 to
+    leading order, so L / F -> -2 Lambda (1 / e1^2 + 1 / e2^2)."""
+    for loop in (cutoff.loop_pp, cutoff.loop_ph):
+        assert loop(0.0, 0.0, 0.3, S_SCHEME)[0] == 0.0
+        e1, e2, lam = 5.0, -4.0, 1e-3
+        ratio = loop(e1, e2, lam, S_SCHEME)[0] / loop(e1, e2, lam, S_SCHEME, deriv=False)[0]
+        assert ratio == pytest.approx(-2 * lam * (1 / e1 ** 2 + 1 / e2 ** 2), rel=1e-6)

@@ -64,7 +64,7 @@ def test_orbital_loop_equals_U_matrix_product_complete_set(qi):
 
 
 @pytest.mark.parametrize("channel", ["pp", "ph"])
-@pytest.mark.parametrize("scheme", ["temperature", "omega"])
+@pytest.mark.parametrize("scheme", ["temperature", "omega", "shell"])
 def test_orbital_loop_reduces_to_band_loop_for_unit_U(channel, scheme):
     # two decoupled bands far apart: U(k) = 1 (up to signs of the columns)
     Lq, n_ref = 4, 3
@@ -74,7 +74,7 @@ def test_orbital_loop_reduces_to_band_loop_for_unit_U(channel, scheme):
     hop_t[1:, 0, 0] = -1.0
     hop_t[1:, 1, 1] = -0.6
     st = tufrg.TUSetup(hop_R, hop_t, 0.1, np.zeros((2,) * 4), [(0, 0), (1, 0), (-1, 0)],
-                       Lq, n_ref, scheme)
+                       Lq, n_ref, scheme, temperature=0.07)
     assert np.allclose(np.abs(st.U), np.eye(2)[None])
     lam = 0.3
     for qi in (0, 6):

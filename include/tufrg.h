@@ -92,7 +92,13 @@ typedef enum {
   TUFRG_E_UNSUPPORTED = 6  /* valid request this build does not implement */
 } tufrg_status;
 
-typedef enum { TUFRG_CUT_TEMPERATURE = 0, TUFRG_CUT_OMEGA = 1 } tufrg_cutoff;
+/* Regulators (Sec. 3.1: the loops are the Lambda derivatives of regulated
+ * bubbles).  TEMPERATURE: Lambda = T.  OMEGA: frequency cutoff
+ * w^2 / (w^2 + Lambda^2) at T = 0.  SHELL: the paper's momentum-shell
+ * regulator at a fixed temperature (tufrg_setup.temperature): each propagator
+ * times chi_Lambda(e) = e^2 / (e^2 + Lambda^2), a smooth shell of width Lambda
+ * around the Fermi surface (the paper leaves the shape open). */
+typedef enum { TUFRG_CUT_TEMPERATURE = 0, TUFRG_CUT_OMEGA = 1, TUFRG_CUT_SHELL = 2 } tufrg_cutoff;
 
 /* Arithmetic of the loops and bundle products; the state and its updates are
  * always FP64.  TUFRG_FP32 accumulates each loop k-chunk in FP32 and sums
@@ -119,6 +125,7 @@ typedef struct {
   int32_t n_ref;           /* refinement of the loop mesh, Lf = n_ref Lq <= 4096 */
   int32_t cutoff;          /* tufrg_cutoff */
   int32_t precision;       /* tufrg_precision */
+  double temperature;      /* TUFRG_CUT_SHELL: the fixed temperature T > 0 of its bubbles; ignored otherwise */
 } tufrg_setup;
 
 /* Builds meshes, tables and the band data (eigendecomposition of H(k) - mu on

@@ -17,7 +17,28 @@
 
 namespace tufrg {
 
-enum { CUT_TEMPERATURE = 0, CUT_OMEGA = 1 };
+enum { CUT_TEMPERATURE = 0, CUT_OMEGA = 1, CUT_SHELL = 2 };
+
+// The momentum-shell scheme (Sec. 3.1 regulator) takes its bubbles at a fixed
+// temperature: its divided differences are those of the temperature scheme,
+// evaluated at Lambda = T, and the loop kernels carry a shell factor.
+__host__ __device__ constexpr int dd_scheme(int scheme) { return scheme == CUT_SHELL ? CUT_TEMPERATURE : scheme; }
+
+// Shell factor of a band value: the loop kernel of a pair is the fixed-T
+// divided difference times a_m b_n + b_m a_n, with chi = e^2 / (e^2 + Lambda^2)
+// and (a, b) = (d chi / d Lambda, chi) for the loop (deriv) or
+// (chi, chi) / sqrt 2 for the bubble.
+template <typename T>
+__device__ inline void shell_ab(T e, T lam, int deriv, T &a, T &b) {
+  const T e2 = e * e, d = e2 + lam * lam;
+  const T chi = e2 / d;
+  if (deriv) {
+    a = -T(2) * lam * e2 / (d * d);
+    b = chi;
+  } else {
+    a = b = chi * T(0.70710678118654752440);
+  }
+}
 
 template <typename T>
 struct cx {

@@ -239,6 +239,29 @@ hipError_t launch_ekv4(int Nf, const double *band, double lam, int scheme, int d
   return hipGetLastError();
 }
 
+// shell factors (a, b) of band m at k (see shell_ab)
+__global__ void shell_ab_kernel(int n_o, int Nf, const double *__restrict__ e, double lam, int deriv,
+                                double *__restrict__ cv, float *__restrict__ cv32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // i = m * Nf + k
+  if (i >= n_o * Nf) return;
+  const int m = i / Nf, k = i - m * Nf;
+  double a, b;
+  shell_ab(e[i], lam, deriv, a, b);
+  const size_t ia = n_o == 2 ? 4 * (size_t)k + m : 2 * ((size_t)k * n_o + m);
+  const size_t ib = n_o == 2 ? ia + 2 : ia + 1;
+  cv[ia] = a;
+  cv[ib] = b;
+  cv32[ia] = (float)a;
+  cv32[ib] = (float)b;
+}
+
+hipError_t launch_shell_ab(int n_o, int Nf, const double *e, double lam, int deriv, double *cv, float *cv32,
+                           hipStream_t st) {
+  const int n = n_o * Nf;
+  hipLaunchKernelGGL(shell_ab_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n_o, Nf, e, lam, deriv, cv, cv32);
+  return hipGetLastError();
+}
+
 // per k the 4-vector (Pi_0[00], Pi_0[11], Re Pi_0[01], Im Pi_0[01])
 __global__ void pi4_kernel(int Nf, const double *__restrict__ band, double *__restrict__ pi4,
                            float *__restrict__ pi4_32) {

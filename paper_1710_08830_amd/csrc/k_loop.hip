@@ -46,7 +46,7 @@ __device__ constexpr int CPLX_PARTNER[NCPLX] = {4, 14, 8, 13, 12, 9};
 
 template <typename T, int SCHEME>
 __device__ inline bool nondegenerate(T den, T x, T y, T lam) {
-  if constexpr (SCHEME == CUT_TEMPERATURE)
+  if constexpr (dd_scheme(SCHEME) == CUT_TEMPERATURE)
     return fabs(den) > degen_rel<T>::v * lam;
   else
     return fabs(den) > degen_rel<T>::v * (lam + fabs(x) + fabs(y));
@@ -77,9 +77,11 @@ __device__ inline V4<double> ld4(const double *base, unsigned i) {
 
 // Loop body of one channel (CH = 0: pp, k' = q - k; CH = 1: ph, k' = k - q).
 // ekv[k] = (e_0, e_1, K(e_0), K(e_1)), pi4[k] = (Pi_0[00], Pi_0[11], Re Pi_0[01], Im Pi_0[01]);
-// twk: exp(-2 pi i j / Lf) in the arithmetic type.
+// shell scheme: K is the fixed-temperature J and cv[k] = (a_0, a_1, b_0, b_1)
+// the shell factors; twk: exp(-2 pi i j / Lf) in the arithmetic type.
 template <typename T, int NDX, int SCHEME, int CH>
 __device__ inline void loop_no2_body(const T *__restrict__ ekv, const T *__restrict__ pi4,
+                                     const T *__restrict__ cvp,
                                      const T *__restrict__ twk, int Lf, int qfx, int qfy, int ky, int x0,
                                      int x1, T lam, int deriv, T (&Sr)[NREAL], T (&Sc)[NCPLX][2],
                                      T (&Ar)[NDX - 1][NREAL], T (&Br)[NDX - 1][NREAL],
@@ -93,12 +95,14 @@ __device__ inline void loop_no2_body(const T *__restrict__ ekv, const T *__restr
   int jd[NDX - 1];
 #pragma unroll
   for (int d = 0; d < NDX - 1; ++d) jd[d] = (int)(((long long)x0 * (d + 1)) % Lf);
+  constexpr bool SHELL = SCHEME == CUT_SHELL;
   struct Pt {
-    V4<T> ek, pk;
+    V4<T> ek, pk, cv;
   };
   auto load = [&](unsigned i, Pt &p) {
     p.ek = ld4(ekv, i);
     p.pk = ld4(pi4, i);
+    if constexpr (SHELL) p.cv = ld4(cvp, i);
   };
   // k' row of the next kx
   auto next_kpx = [&]() {
@@ -128,7 +132,17 @@ __device__ inline void loop_no2_body(const T *__restrict__ ekv, const T *__restr
         for (int m = 0; m < 2; ++m)
 #pragma unroll
           for (int n = 0; n < 2; ++n)
-            L[m][n] = sg * divided_difference(ekm[m], -sg * epn[n], Kkm[m], -sg * Kpn[n], lam, SCHEME, deriv);
+            L[m][n] = sg * divided_difference(ekm[m], -sg * epn[n], Kkm[m], -sg * Kpn[n], lam, dd_scheme(SCHEME),
+                                              deriv);
+      }
+      if constexpr (SHELL) {
+        // shell factor a_m(k) b_n(k') + b_m(k) a_n(k')
+        const T ak[2] = {ck.cv.x, ck.cv.y}, bk[2] = {ck.cv.z, ck.cv.w};
+        const T ap[2] = {cp.cv.x, cp.cv.y}, bp[2] = {cp.cv.z, cp.cv.w};
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int n = 0; n < 2; ++n) L[m][n] *= fma(ak[m], bp[n], bk[m] * ap[n]);
       }
       // W_1 = alpha_1 X_0 + L_11 1, D = W_0 - W_1 = (alpha_0 - alpha_1) X_0 + (L_01 - L_11) 1
       const T al0 = L[0][0] - L[0][1], al1 = L[1][0] - L[1][1];
@@ -230,7 +244,7 @@ struct loop_waves {
 
 // QW waves per work item (ky block, q_y group, q_x, kx chunk, channel).
 template <typename T, int NDX, int NDY, int SCHEME, int QW>
-__global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 2 : 3))) void loop_no2_kernel(const T *__restrict__ ekv, const T *__restrict__ pi4,
+__global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 2 : 3))) void loop_no2_kernel(const T *__restrict__ ekv, const T *__restrict__ pi4, const T *__restrict__ cvp,
                                                            const double *__restrict__ tw, const T *__restrict__ twk,
                                                            int Lq, int n_ref, int Lf,
                                                            int nkyb, int nkxc, int kxper, int q_first, int n_q,
@@ -280,9 +294,11 @@ __global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (siz
     for (int t = 0; t < NCPLX; ++t) Ac[d][t][0] = Ac[d][t][1] = Bc[d][t][0] = Bc[d][t][1] = T(0);
   }
   if (ch == 0)
-    loop_no2_body<T, NDX, SCHEME, 0>(ekv, pi4, twk, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac, Bc);
+    loop_no2_body<T, NDX, SCHEME, 0>(ekv, pi4, cvp, twk, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac,
+                                     Bc);
   else
-    loop_no2_body<T, NDX, SCHEME, 1>(ekv, pi4, twk, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac, Bc);
+    loop_no2_body<T, NDX, SCHEME, 1>(ekv, pi4, cvp, twk, Lf, qfx, qfy, ky, x0, x1, lam, deriv, Sr, Sc, Ar, Br, Ac,
+                                     Bc);
 
   // rebuild all 16 entries per dx, transpose through LDS, contract with e^{-i 2 pi ky dy / Lf}
   __shared__ T bufs[QW][32][65];
@@ -367,15 +383,22 @@ static hipError_t launch_no2(const LoopArgs &a, hipStream_t st) {
   const T *ekv = (const T *)a.ekv;
   const T *pi4 = (const T *)a.pi4;
   const T *twk = (const T *)(sizeof(T) == 8 ? (const void *)a.tw : a.tw32);
+  const T *cvp = (const T *)a.cv;
   if (!ekv || !pi4 || !twk) return hipErrorInvalidValue;
+  if (a.scheme == CUT_SHELL && !cvp) return hipErrorInvalidValue;
+#define TUFRG_NO2_LAUNCH(S)                                                                                         \
+  hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, S, QW>), grid, block, 0, st, ekv, pi4, cvp, a.tw, twk, a.Lq,    \
+                     a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.rows, a.ch_first, n_items, (T)a.lam, \
+                     a.deriv, a.partial)
   if (a.scheme == CUT_TEMPERATURE)
-    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_TEMPERATURE, QW>), grid, block, 0, st, ekv, pi4, a.tw, twk, a.Lq,
-                       a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.rows, a.ch_first, n_items, (T)a.lam,
-                       a.deriv, a.partial);
+    TUFRG_NO2_LAUNCH(CUT_TEMPERATURE);
+  else if (a.scheme == CUT_OMEGA)
+    TUFRG_NO2_LAUNCH(CUT_OMEGA);
+  else if (a.scheme == CUT_SHELL)
+    TUFRG_NO2_LAUNCH(CUT_SHELL);
   else
-    hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, CUT_OMEGA, QW>), grid, block, 0, st, ekv, pi4, a.tw, twk, a.Lq,
-                       a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.rows, a.ch_first, n_items, (T)a.lam,
-                       a.deriv, a.partial);
+    return hipErrorInvalidValue;
+#undef TUFRG_NO2_LAUNCH
   return hipGetLastError();
 }
 

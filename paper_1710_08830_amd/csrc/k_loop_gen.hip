@@ -100,6 +100,7 @@ __device__ inline void unpack_store(c2<T> *dst, int pl, T x) {
 // One workgroup per (part, channel, q); part selects NTHR of the entry pairs.
 template <typename T, int NO, int NDY, int SCHEME, int NTHR, int KT>
 __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ band, const T *__restrict__ kv,
+                                                        const T *__restrict__ cvp,
                                                         const double *__restrict__ tw, const T *__restrict__ phy,
                                                         const int *__restrict__ pairs,
                                                         int n_pairs, int Lq, int n_ref, int Lf, int nparts,
@@ -111,7 +112,10 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
   constexpr int NO2 = NO * NO, NO4 = NO2 * NO2;
   constexpr int PK = NO * NO2;      // packed reals of all bands' projectors at one k
   constexpr int NC = NO + PK;       // band values per k-point: e_m, then the packed projectors
-  constexpr int NIT = NC + NO;      // staged values per k-point: band values and regulator values
+  constexpr bool SHELL = SCHEME == CUT_SHELL;
+  // staged values per k-point: band values and regulator values (and the
+  // shell factors a_m, b_m of the momentum-shell scheme)
+  constexpr int NIT = NC + NO + (SHELL ? 2 * NO : 0);
   const int tid = threadIdx.x;
   int w = blockIdx.x;
   const int part = w % nparts;
@@ -132,6 +136,7 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
   __shared__ T sE[KT][2][NO];        // e at k and k'
   __shared__ T sK[KT][2][NO];        // regulator at k and k'
   __shared__ T sL[KT][NO][NO];
+  __shared__ T sC[SHELL ? KT : 1][2][2 * NO];  // shell factors (a_m, b_m) at k and k'
   const T sg = (ch == 0) ? T(1) : T(-1);
 
   cx<T> Z[NPT];
@@ -166,8 +171,10 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
             if (ch == 1 && pl >= NO && ((pl - NO) & 1)) x = -x;
             sX[j][p] = x;
           }
-        } else {
+        } else if (r < NC + NO) {
           sK[j][side][r - NC] = kv[(size_t)kk * NO + (r - NC)];
+        } else if constexpr (SHELL) {
+          sC[j][side][r - NC - NO] = cvp[(size_t)kk * 2 * NO + (r - NC - NO)];
         }
       }
       __syncthreads();
@@ -175,7 +182,10 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
       if (tid < KT * NO2) {
         const int j = tid / NO2, m = (tid / NO) % NO, n = tid % NO;
         const T x = sE[j][0][m], y = -sg * sE[j][1][n];
-        sL[j][m][n] = sg * divided_difference(x, y, sK[j][0][m], -sg * sK[j][1][n], lam, SCHEME, deriv);
+        T l = sg * divided_difference(x, y, sK[j][0][m], -sg * sK[j][1][n], lam, dd_scheme(SCHEME), deriv);
+        // shell scheme: times a_m(k) b_n(k') + b_m(k) a_n(k')
+        if constexpr (SHELL) l *= fma(sC[j][0][2 * m], sC[j][1][2 * n + 1], sC[j][0][2 * m + 1] * sC[j][1][2 * n]);
+        sL[j][m][n] = l;
       }
       __syncthreads();
       // W_m = sum_n L_mn X_n, packed sums written as full complex matrices
@@ -261,15 +271,21 @@ static hipError_t launch_gen(const LoopArgs &a, hipStream_t st) {
   if (a.ndx != NDY + 1) return hipErrorInvalidValue;
   const int NP = (a.n_pairs + NTHR - 1) / NTHR;
   dim3 grid(a.n_q * a.n_ch * NP), block(NTHR);
-  const T *band = (const T *)a.band, *kv = (const T *)a.kv, *phy = (const T *)a.phy;
+  const T *band = (const T *)a.band, *kv = (const T *)a.kv, *phy = (const T *)a.phy, *cvp = (const T *)a.cv;
+  if (a.scheme == CUT_SHELL && !cvp) return hipErrorInvalidValue;
+#define TUFRG_GEN_LAUNCH(S)                                                                                          \
+  hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, S, NTHR, KT>), grid, block, 0, st, band, kv, cvp, a.tw, phy, a.pairs, \
+                     a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.rows, a.ch_first, a.n_ch, a.ndx,         \
+                     (T)a.lam, a.deriv, a.partial)
   if (a.scheme == CUT_TEMPERATURE)
-    hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, CUT_TEMPERATURE, NTHR, KT>), grid, block, 0, st, band, kv, a.tw,
-                       phy, a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.rows, a.ch_first, a.n_ch, a.ndx,
-                       (T)a.lam, a.deriv, a.partial);
+    TUFRG_GEN_LAUNCH(CUT_TEMPERATURE);
+  else if (a.scheme == CUT_OMEGA)
+    TUFRG_GEN_LAUNCH(CUT_OMEGA);
+  else if (a.scheme == CUT_SHELL)
+    TUFRG_GEN_LAUNCH(CUT_SHELL);
   else
-    hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, CUT_OMEGA, NTHR, KT>), grid, block, 0, st, band, kv, a.tw,
-                       phy, a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.rows, a.ch_first, a.n_ch, a.ndx,
-                       (T)a.lam, a.deriv, a.partial);
+    return hipErrorInvalidValue;
+#undef TUFRG_GEN_LAUNCH
   return hipGetLastError();
 }
 

@@ -88,6 +88,7 @@ __device__ inline int bgran(int blk, int l) { return blk * 64 + (l ^ ((7 * blk +
 template <int NDY, int SCHEME>
 __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restrict__ band,
                                                             const float *__restrict__ kv,
+                                                            const float *__restrict__ cvp,
                                                             const float *__restrict__ phy, int Lq, int n_ref,
                                                             int Lf, int q_first, const int *__restrict__ rows,
                                                             int ch, float lam, int deriv, float *__restrict__ Y) {
@@ -148,9 +149,11 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
     const int p = wv - NW;
     constexpr int SPT = (PK + 15) / 16, NDDW = 2 * NO2;  // loop kernel items of one wave
     const int sj = 2 * p + (lane >> 5), sside = (lane >> 4) & 1, pl0 = lane & 15;
-    // values of one tile in flight: packed Pi or X, loop kernel inputs, phase
+    // values of one tile in flight: packed Pi or X, loop kernel inputs (and the
+    // shell factors of the momentum-shell scheme), phase
+    constexpr bool SHELL = SCHEME == CUT_SHELL;
     struct Pre {
-      float v[SPT], e[2][4], ph;
+      float v[SPT], e[2][4], c[2][4], ph;
     };
     auto kidx = [&](int kxn, int ky, int side) -> unsigned {
       if (side == 0) return (unsigned)kxn * Lf + ky;
@@ -183,6 +186,13 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
           pr.e[v][1] = kv[(size_t)k0 * NO + m];
           pr.e[v][2] = band[(size_t)k1 * NC + n];
           pr.e[v][3] = kv[(size_t)k1 * NO + n];
+          if constexpr (SHELL) {
+            // (a_m(k), b_m(k), a_n(k'), b_n(k'))
+            pr.c[v][0] = cvp[((size_t)k0 * NO + m) * 2];
+            pr.c[v][1] = cvp[((size_t)k0 * NO + m) * 2 + 1];
+            pr.c[v][2] = cvp[((size_t)k1 * NO + n) * 2];
+            pr.c[v][3] = cvp[((size_t)k1 * NO + n) * 2 + 1];
+          }
         }
       }
       if (lane < 2 * NPHI) {
@@ -208,9 +218,13 @@ __global__ __launch_bounds__(NTHR, 1) void loop_mfma_kernel(const float *__restr
 #pragma unroll
       for (int v = 0; v < 2; ++v) {
         const int i = lane + 64 * v;
-        if (i < NDDW)
-          (&sL[2 * p][0][0])[i] =
-              sg * divided_difference(pr.e[v][0], -sg * pr.e[v][2], pr.e[v][1], -sg * pr.e[v][3], lam, SCHEME, deriv);
+        if (i < NDDW) {
+          float l = sg * divided_difference(pr.e[v][0], -sg * pr.e[v][2], pr.e[v][1], -sg * pr.e[v][3], lam,
+                                            dd_scheme(SCHEME), deriv);
+          // shell scheme: times a_m(k) b_n(k') + b_m(k) a_n(k')
+          if constexpr (SHELL) l *= fmaf(pr.c[v][0], pr.c[v][3], pr.c[v][1] * pr.c[v][2]);
+          (&sL[2 * p][0][0])[i] = l;
+        }
       }
       if (lane < 2 * NPHI) sPh[bb][2 * p + lane / NPHI][lane % NPHI] = pr.ph;
       // X and the loop kernels of these rows were written by this wave
@@ -521,25 +535,31 @@ size_t loop_mfma_rowbuf_floats(int ndy, int Lf) {
 hipError_t launch_loop_mfma(const LoopArgs &a, int ch, float *Y, hipStream_t st) {
   if (a.n_o != 6 || !a.pairs || a.n_pairs <= 0 || !Y) return hipErrorInvalidValue;
   const float *band = (const float *)a.band, *kv = (const float *)a.kv, *phy = (const float *)a.phy;
+  const float *cvp = (const float *)a.cv;
+  if (a.scheme == CUT_SHELL && !cvp) return hipErrorInvalidValue;
   dim3 grid(a.n_q), block(NTHR);
   const float lam = (float)a.lam;
+#define TUFRG_MFMA_LAUNCH(D, S)                                                                                   \
+  hipLaunchKernelGGL((loop_mfma_kernel<D, S>), grid, block, 0, st, band, kv, cvp, phy, a.Lq, a.n_ref, a.Lf,     \
+                     a.q_first, a.rows, ch, lam, a.deriv, Y)
+#define TUFRG_MFMA_SCHEMES(D)                 \
+  if (a.scheme == CUT_TEMPERATURE)            \
+    TUFRG_MFMA_LAUNCH(D, CUT_TEMPERATURE);    \
+  else if (a.scheme == CUT_OMEGA)             \
+    TUFRG_MFMA_LAUNCH(D, CUT_OMEGA);          \
+  else if (a.scheme == CUT_SHELL)             \
+    TUFRG_MFMA_LAUNCH(D, CUT_SHELL);          \
+  else                                        \
+    return hipErrorInvalidValue;
   if (a.ndx == 5 && a.ndy == 4) {
-    if (a.scheme == CUT_TEMPERATURE)
-      hipLaunchKernelGGL((loop_mfma_kernel<4, CUT_TEMPERATURE>), grid, block, 0, st, band, kv, phy, a.Lq, a.n_ref,
-                         a.Lf, a.q_first, a.rows, ch, lam, a.deriv, Y);
-    else
-      hipLaunchKernelGGL((loop_mfma_kernel<4, CUT_OMEGA>), grid, block, 0, st, band, kv, phy, a.Lq, a.n_ref, a.Lf,
-                         a.q_first, a.rows, ch, lam, a.deriv, Y);
+    TUFRG_MFMA_SCHEMES(4)
   } else if (a.ndx == 3 && a.ndy == 2) {
-    if (a.scheme == CUT_TEMPERATURE)
-      hipLaunchKernelGGL((loop_mfma_kernel<2, CUT_TEMPERATURE>), grid, block, 0, st, band, kv, phy, a.Lq, a.n_ref,
-                         a.Lf, a.q_first, a.rows, ch, lam, a.deriv, Y);
-    else
-      hipLaunchKernelGGL((loop_mfma_kernel<2, CUT_OMEGA>), grid, block, 0, st, band, kv, phy, a.Lq, a.n_ref, a.Lf,
-                         a.q_first, a.rows, ch, lam, a.deriv, Y);
+    TUFRG_MFMA_SCHEMES(2)
   } else {
     return hipErrorInvalidValue;
   }
+#undef TUFRG_MFMA_SCHEMES
+#undef TUFRG_MFMA_LAUNCH
   return hipGetLastError();
 }
 

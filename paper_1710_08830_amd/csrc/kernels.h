@@ -14,6 +14,10 @@ hipError_t launch_kval(int n, int Nf, int aos_no, const double *e, double lam, i
 hipError_t launch_ekv4(int Nf, const double *band, double lam, int scheme, int deriv, double *ekv, float *ekv32,
                        hipStream_t st);
 hipError_t launch_pi4(int Nf, const double *band, double *pi4, float *pi4_32, hipStream_t st);
+// shell scheme: factors (a, b) of every band value e[m][k] (component-major);
+// two orbitals [Nf][4] = (a_0, a_1, b_0, b_1), more orbitals [Nf][n_o][2]
+hipError_t launch_shell_ab(int n_o, int Nf, const double *e, double lam, int deriv, double *cv, float *cv32,
+                           hipStream_t st);
 // component-major [nc][Nf] -> k-major [Nf][nc] (FP64 and FP32)
 hipError_t launch_to_kmajor(int nc, int Nf, const double *src, double *dst, float *dst32, hipStream_t st);
 
@@ -38,6 +42,8 @@ struct LoopArgs {
   const void *phy = nullptr;   // more than two orbitals: exp(-2 pi i ky dy / Lf), [Lf][ndy][2], like band
   const void *ekv = nullptr;   // two orbitals: [Nf][4] = (e_0, e_1, K(e_0), K(e_1)), like band
   const void *pi4 = nullptr;   // two orbitals: [Nf][4] = (Pi_0[00], Pi_0[11], Re Pi_0[01], Im Pi_0[01])
+  const void *cv = nullptr;    // shell scheme: shell factors, two orbitals [Nf][4] = (a_0, a_1, b_0, b_1),
+                               // more orbitals [Nf][n_o][2] = (a_m, b_m); like band
 };
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
 // more than two spin-orbitals (six: t2g with spin-orbit coupling)

@@ -54,6 +54,9 @@ struct tufrg_ctx {
   float *d_bandk32 = nullptr;
   double *d_kv64 = nullptr;
   float *d_kv32 = nullptr;
+  double temp = 0.0;          // momentum-shell scheme: the fixed temperature of its bubbles
+  double *d_cv64 = nullptr;   // momentum-shell scheme: shell factors (see LoopArgs::cv)
+  float *d_cv32 = nullptr;
   double *d_twf = nullptr, *d_twq = nullptr, *d_phq = nullptr;
   float *d_twf32 = nullptr;
   double *d_partial = nullptr;
@@ -182,8 +185,10 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   if (m->n_hop < 1 || !m->hop_R || !m->hop_t || !m->V0) return fail(nullptr, TUFRG_E_INVAL, "empty model");
   if (s->n_ff < 1 || !s->ff_R) return fail(nullptr, TUFRG_E_INVAL, "empty form-factor set");
   if (s->ff_R[0] != 0 || s->ff_R[1] != 0) return fail(nullptr, TUFRG_E_INVAL, "ff_R[0] must be (0,0)");
-  if (s->cutoff != TUFRG_CUT_TEMPERATURE && s->cutoff != TUFRG_CUT_OMEGA)
+  if (s->cutoff != TUFRG_CUT_TEMPERATURE && s->cutoff != TUFRG_CUT_OMEGA && s->cutoff != TUFRG_CUT_SHELL)
     return fail(nullptr, TUFRG_E_INVAL, "unknown cutoff");
+  if (s->cutoff == TUFRG_CUT_SHELL && !(s->temperature > 0.0 && std::isfinite(s->temperature)))
+    return fail(nullptr, TUFRG_E_INVAL, "the momentum-shell cutoff needs a temperature > 0");
   if (s->precision != TUFRG_FP64 && s->precision != TUFRG_FP32 && s->precision != TUFRG_BF16X3)
     return fail(nullptr, TUFRG_E_INVAL, "unknown precision");
   if (s->precision == TUFRG_BF16X3 && m->n_orb != 6)
@@ -220,6 +225,7 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   c->Nq = c->Lq * c->Lq;
   c->Nf = c->Lf * c->Lf;
   c->scheme = s->cutoff;
+  c->temp = s->cutoff == TUFRG_CUT_SHELL ? s->temperature : 0.0;
   c->prec = s->precision;
   c->ff.assign(s->ff_R, s->ff_R + 2 * s->n_ff);
   // D = S - S, sorted; lookup grids over [-8, 8]^2
@@ -335,6 +341,10 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   }
   CTRY(dalloc(c, &c->d_kv64, Nf * c->n_o));
   CTRY(dalloc(c, &c->d_kv32, Nf * c->n_o));
+  if (c->scheme == CUT_SHELL) {
+    CTRY(dalloc(c, &c->d_cv64, 2 * Nf * c->n_o));
+    CTRY(dalloc(c, &c->d_cv32, 2 * Nf * c->n_o));
+  }
   CTRY(dalloc(c, &c->d_twf, 2 * (size_t)c->Lf));
   CTRY(dalloc(c, &c->d_twf32, 2 * (size_t)c->Lf));
   CTRY(dalloc(c, &c->d_twq, 2 * (size_t)c->Lq));
@@ -495,6 +505,14 @@ static LoopArgs loop_args(tufrg_ctx *c, double lam, int deriv, int ch_first, int
   a.phy = c->prec == 0 ? (const void *)c->d_phy64 : (const void *)c->d_phy32;
   a.ekv = c->prec == 0 ? (const void *)c->d_ekv64 : (const void *)c->d_ekv32;
   a.pi4 = c->prec == 0 ? (const void *)c->d_pi4_64 : (const void *)c->d_pi4_32;
+  if (c->scheme == CUT_SHELL) {
+    // the kernels' divided differences are those of the fixed-temperature J
+    // (regulator values at Lambda = T); the Lambda dependence and deriv are
+    // in the shell factors
+    a.lam = c->temp;
+    a.deriv = 0;
+    a.cv = c->prec == 0 ? (const void *)c->d_cv64 : (const void *)c->d_cv32;
+  }
   return a;
 }
 
@@ -516,11 +534,16 @@ static ProjArgs proj_args(tufrg_ctx *c) {
 }
 
 static tufrg_status compute_kval(tufrg_ctx *c, double lam, int deriv) {
+  // momentum shell: J of the fixed temperature in the regulator slot, the
+  // shell factors at Lambda beside it
+  const bool shell = c->scheme == CUT_SHELL;
+  const double rl = shell ? c->temp : lam;
+  const int rs = shell ? CUT_TEMPERATURE : c->scheme, rd = shell ? 0 : deriv;
   if (c->n_o == 2)
-    HIPCHK(c, launch_ekv4(c->Nf, c->d_band64, lam, c->scheme, deriv, c->d_ekv64, c->d_ekv32, c->st));
+    HIPCHK(c, launch_ekv4(c->Nf, c->d_band64, rl, rs, rd, c->d_ekv64, c->d_ekv32, c->st));
   else
-    HIPCHK(c, launch_kval(c->n_o * c->Nf, c->Nf, c->n_o, c->d_band64, lam, c->scheme, deriv, c->d_kv64, c->d_kv32,
-                          c->st));
+    HIPCHK(c, launch_kval(c->n_o * c->Nf, c->Nf, c->n_o, c->d_band64, rl, rs, rd, c->d_kv64, c->d_kv32, c->st));
+  if (shell) HIPCHK(c, launch_shell_ab(c->n_o, c->Nf, c->d_band64, lam, deriv, c->d_cv64, c->d_cv32, c->st));
   return TUFRG_OK;
 }
 

@@ -25,7 +25,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 TUFRG_OK = 0
 STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NONFINITE", 5: "E_STEPSIZE",
           6: "E_UNSUPPORTED"}
-CUT_TEMPERATURE, CUT_OMEGA = 0, 1
+CUT_TEMPERATURE, CUT_OMEGA, CUT_SHELL = 0, 1, 2
+CUTOFFS = {"temperature": CUT_TEMPERATURE, "omega": CUT_OMEGA, "shell": CUT_SHELL}
 FP64, FP32, BF16X3 = 0, 1, 2
 PP, PH = 0, 1
 
@@ -53,7 +54,7 @@ class Model(ctypes.Structure):
 class Setup(ctypes.Structure):
     _fields_ = [("n_ff", ctypes.c_int32), ("ff_R", ctypes.POINTER(ctypes.c_int32)),
                 ("Lq", ctypes.c_int32), ("n_ref", ctypes.c_int32), ("cutoff", ctypes.c_int32),
-                ("precision", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("temperature", ctypes.c_double)]
 
 
 STEP_CB = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
@@ -168,7 +169,7 @@ def _stream_handle(stream):
 class Context:
     """Owns a tufrg_ctx.  ``model``/``setup`` are host-side numpy inputs."""
 
-    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, cutoff, precision, stream=None):
+    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, cutoff, precision, stream=None, temperature=None):
         hop_R = np.ascontiguousarray(hop_R, dtype=np.int32).reshape(-1, 2)
         hop_t = np.ascontiguousarray(hop_t, dtype=np.complex128)
         V0 = np.ascontiguousarray(V0, dtype=np.complex128)
@@ -178,10 +179,10 @@ class Context:
         m = Model(n_o, hop_R.shape[0], hop_R.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                   hop_t.ctypes.data_as(ctypes.POINTER(c64)), float(mu),
                   V0.ctypes.data_as(ctypes.POINTER(c64)))
-        cut = {"temperature": CUT_TEMPERATURE, "omega": CUT_OMEGA}.get(cutoff, cutoff)
+        cut = CUTOFFS.get(cutoff, cutoff)
         prec = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}.get(precision, precision)
         s = Setup(ff.shape[0], ff.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(Lq), int(n_ref),
-                  int(cut), int(prec))
+                  int(cut), int(prec), float(temperature or 0.0))
         h = ctypes.c_void_p()
         _check(_lib.tufrg_create(ctypes.byref(m), ctypes.byref(s), _stream_handle(stream),
                                  ctypes.byref(h)))
@@ -195,7 +196,7 @@ class Context:
     @classmethod
     def from_workload(cls, w, precision=None, stream=None, **over):
         kw = dict(hop_R=w["hop_R"], hop_t=w["hop_t"], mu=w["mu"], V0=w["V0"], ff=w["ff"],
-                  Lq=w["Lq"], n_ref=w["n_ref"], cutoff=w["cutoff"],
+                  Lq=w["Lq"], n_ref=w["n_ref"], cutoff=w["cutoff"], temperature=w.get("temperature"),
                   precision=precision if precision is not None else w["prec"])
         kw.update(over)
         return cls(stream=stream, **kw)
@@ -382,10 +383,10 @@ class Batch:
             models[i] = Model(hop_t.shape[1], hop_R.shape[0], hop_R.ctypes.data_as(_i32p),
                               hop_t.ctypes.data_as(ctypes.POINTER(c64)), float(w["mu"]),
                               V0.ctypes.data_as(ctypes.POINTER(c64)))
-            cut = {"temperature": CUT_TEMPERATURE, "omega": CUT_OMEGA}.get(w["cutoff"], w["cutoff"])
+            cut = CUTOFFS.get(w["cutoff"], w["cutoff"])
             prec = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}.get(precision, precision)
             setups[i] = Setup(ff.shape[0], ff.ctypes.data_as(_i32p), int(w["Lq"]), int(w["n_ref"]), int(cut),
-                              int(prec))
+                              int(prec), float(w.get("temperature") or 0.0))
         h = ctypes.c_void_p()
         st = _lib.tufrg_batch_create(n, models, setups, int(n_streams), ctypes.byref(h))
         if st != TUFRG_OK:

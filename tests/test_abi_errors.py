@@ -40,6 +40,14 @@ def test_create_rejects_bad_setups(T, over, status, text):
     assert text in str(ei.value)
 
 
+@pytest.mark.parametrize("temperature", [None, 0.0, -0.1, float("inf"), float("nan")])
+def test_shell_cutoff_needs_a_temperature(T, temperature):
+    with pytest.raises(T.TufrgError) as ei:
+        T.Context(**_args(cutoff="shell", temperature=temperature))
+    assert ei.value.status == 1
+    assert "temperature" in str(ei.value)
+
+
 def test_bf16x3_needs_six_orbitals(T):
     with pytest.raises(T.TufrgError) as ei:
         T.Context(**_args(precision="bf16x3"))

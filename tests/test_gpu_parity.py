@@ -43,7 +43,8 @@ def rel(a, b):
 
 def _case(name):
     """Small cases: ragged fine meshes (Lf not a multiple of 64), several ky
-    blocks and kx chunks, both cutoffs, the 5-, 9- and 13-vector shells."""
+    blocks and kx chunks, the three cutoffs (suffix s: momentum shell at a
+    fixed temperature), the 5-, 9- and 13-vector shells."""
     if name == "hub5":
         return dict(hop=hubbard_hoppings(1.0, -0.25), mu=-0.6, V0=onsite_V0(3.0), ff=ff_shell(5),
                     Lq=6, n_ref=3, cutoff="temperature")
@@ -59,16 +60,21 @@ def _case(name):
     if name == "t2g9":
         return dict(hop=t2g_soc_hoppings(0.2, seed=1), mu=0.35, V0=kanamori_V0(2.0, 0.3), ff=ff_shell(9),
                     Lq=6, n_ref=3, cutoff="omega")
+    if name.endswith("s"):
+        c = _case(name[:-1])
+        c.update(cutoff="shell", temperature=0.06)
+        return c
     raise KeyError(name)
 
 
 def _ctx(T, c, prec):
     return T.Context(c["hop"][0], c["hop"][1], c["mu"], c["V0"], c["ff"], c["Lq"], c["n_ref"],
-                     c["cutoff"], prec)
+                     c["cutoff"], prec, temperature=c.get("temperature"))
 
 
 def _setup(c):
-    return otu.TUSetup(*c["hop"], c["mu"], c["V0"], c["ff"], c["Lq"], c["n_ref"], c["cutoff"])
+    return otu.TUSetup(*c["hop"], c["mu"], c["V0"], c["ff"], c["Lq"], c["n_ref"], c["cutoff"],
+                       temperature=c.get("temperature"))
 
 
 def _zeros(ctx):
@@ -96,7 +102,7 @@ def test_band_data_matches_oracle(T, name):
     assert np.abs(Pi.sum(axis=0) - np.eye(n)[None]).max() < 1e-13
 
 
-@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13", "t2g13", "t2g9"])
+@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13", "t2g13", "t2g9", "ras9s", "hub5s", "t2g13s", "t2g9s"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("channel", ["pp", "ph"])
 @pytest.mark.parametrize("deriv", [1, 0])
@@ -131,7 +137,7 @@ def test_project_matches_oracle(T, name):
     assert rel(VC.cpu().numpy(), c_to_matrix(rVC)) < 1e-12
 
 
-@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13", "t2g9"])
+@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13", "t2g9", "ras9s", "t2g9s"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_rhs_matches_oracle(T, name, prec):
     c = _case(name)
@@ -256,7 +262,7 @@ def test_full_size_t2g_loops_on_sampled_q(T):
     ctx.close()
 
 
-@pytest.mark.parametrize("name", ["t2g13", "t2g9"])
+@pytest.mark.parametrize("name", ["t2g13", "t2g9", "t2g13s", "t2g9s"])
 @pytest.mark.parametrize("channel", ["pp", "ph"])
 @pytest.mark.parametrize("deriv", [1, 0])
 def test_bf16x3_bubble_matches_oracle(T, name, channel, deriv):

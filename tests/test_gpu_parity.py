@@ -204,6 +204,25 @@ def test_euler_flow_divergence_and_critical_scale(T):
     assert rel(P.cpu().numpy(), p_to_matrix(Pr)) < 1e-10
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_shell_flow_divergence_matches_oracle(T, prec):
+    """Momentum-shell regulator at fixed T: the attractive Hubbard model flows
+    to a Cooper instability at the same step and Lambda_c as the oracle."""
+    hop = hubbard_hoppings(1.0, -0.25)
+    args = (*hop, -0.5, onsite_V0(-4.0), ff_shell(5), 6, 2, "shell")
+    st = otu.TUSetup(*args, temperature=0.02)
+    Pr, Cr, rr = otu.flow_euler(st, 5.0, 0.01, 30, v_max=20.0)
+    assert rr["diverged"] == 1
+    ctx = T.Context(*args, prec, temperature=0.02)
+    P, C = _zeros(ctx), _zeros(ctx)
+    res = T.tufrg_flow(ctx, P, C, 5.0, 0.01, n_steps=30, v_max=20.0)
+    torch.cuda.synchronize()
+    tol = 1e-10 if prec == "fp64" else 1e-4
+    assert res["diverged"] == 1 and res["n_steps"] == rr["n_steps"]
+    assert res["lambda_c"] == pytest.approx(rr["lambda_c"], rel=tol)
+    assert rel(P.cpu().numpy(), p_to_matrix(Pr)) < tol
+
+
 def test_dp54_flow_matches_oracle(T):
     c = _case("ras9")
     ctx = _ctx(T, c, "fp64")

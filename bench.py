@@ -33,17 +33,19 @@ PEAK_FP32_VECTOR = 157.3e12
 PEAK_BF16_MFMA = 2.5e15
 
 
-def loop_flops_per_pair(n_o, ndx, ndy):
+def loop_flops_per_pair(n_o, ndx, ndy, shell=False):
     """Algorithmic FP32 flops of the loop kernel per (q, k, channel).  Two
     spin-orbitals: 12 for the four divided differences, 16 for W_1 and D, 32
     for the 10 distinct block entries, 16 for the dx = 0 sums and 64 per
     further dx.  n_o > 2 (one entry of each Hermitian pair, U = (n_o^4 + n_o^2)
     / 2 of them): 8 n_o flops for sum_m Pi_m W_m, 2 + 8 ndy for the separable
-    ky transform, plus 2 n_o^4 for W_m and 3 n_o^2 for the loop kernels."""
+    ky transform, plus 2 n_o^4 for W_m and 3 n_o^2 for the loop kernels.  The
+    momentum-shell cutoff adds 4 flops per band pair for its shell factor."""
+    extra = 4 * n_o * n_o if shell else 0
     if n_o == 2:
-        return 12 + 16 + 32 + 16 + 64 * (ndx - 1)
+        return 12 + 16 + 32 + 16 + 64 * (ndx - 1) + extra
     u = (n_o ** 4 + n_o ** 2) // 2
-    return u * (8 * n_o + 2 + 8 * ndy) + 2 * n_o ** 4 + 3 * n_o ** 2
+    return u * (8 * n_o + 2 + 8 * ndy) + 2 * n_o ** 4 + 3 * n_o ** 2 + extra
 
 
 def mfma_flops_per_pair(ndy, n_o=6):
@@ -376,6 +378,10 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-assisted flow")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16x3"],
                     help="arithmetic of the timed loops (bf16x3: six spin-orbitals, matrix cores)")
+    ap.add_argument("--cutoff", choices=["temperature", "omega", "shell"],
+                    help="regulator in place of the workload's own")
+    ap.add_argument("--temperature", type=float, default=0.02,
+                    help="fixed temperature of the momentum-shell regulator")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the q-sharded multi-GPU "
@@ -407,6 +413,9 @@ def main():
         print(json.dumps(surrogate_bench(T, torch, workload(args.workload), K, args.prec)))
         return
     w = workload(args.workload)
+    own_cutoff = args.cutoff is None or args.cutoff == w["cutoff"]
+    if not own_cutoff:
+        w = dict(w, cutoff=args.cutoff, temperature=args.temperature)
     lam0, lam_mid = 10.0, 1.0
 
     def make(prec):
@@ -448,16 +457,18 @@ def main():
         flops_step = 2.0 * Nq * Nf * mfma_flops_per_pair(ndy, w["n_o"])
         bound, peak = "mfma", PEAK_BF16_MFMA
     else:
-        flops_step = 2.0 * Nq * Nf * loop_flops_per_pair(w["n_o"], ndx, ndy)
+        flops_step = 2.0 * Nq * Nf * loop_flops_per_pair(w["n_o"], ndx, ndy, w["cutoff"] == "shell")
         bound, peak = "alu", PEAK_FP32_VECTOR
     achieved = flops_step / launches / loop_avg_s
-    traffic = _traffic(args.workload, args.prec)
+    # the committed counters were taken with the workload's own regulator
+    traffic = _traffic(args.workload, args.prec) if own_cutoff else None
     out = {
         "metric": METRIC, "value": value, "unit": "loop entries/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": dt32 / K * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
         "config": {"workload": args.workload, "n_orb": w["n_o"], "n_ff": len(w["ff"]), "B": B,
                    "Lq": w["Lq"], "n_ref": w["n_ref"], "Nq": Nq, "Nf": Nf, "cutoff": w["cutoff"],
+                   **({"temperature": w["temperature"]} if w["cutoff"] == "shell" else {}),
                    "step": "Euler step: loops + projections + bundles + update",
                    "parallelism": "single GPU"},
         "flow_steps_per_s": K / dt32,

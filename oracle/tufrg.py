@@ -61,11 +61,14 @@ _DP_B4 = np.array([5179 / 57600, 0.0, 7571 / 16695, 393 / 640, -92097 / 339200,
 class TUSetup:
     """Meshes, form factors, band data and the initial interaction."""
 
-    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, scheme, temperature=None):
+    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, scheme, temperature=None, C0=None):
         self.hop_R = np.asarray(hop_R)
         self.hop_t = np.asarray(hop_t)
         self.mu = float(mu)
         self.V0 = np.asarray(V0, dtype=np.complex128)
+        # non-local part of the initial interaction in crossed particle-hole
+        # form (a static term of the C channel, its D partner by antisymmetry)
+        self.C0 = None if C0 is None else np.asarray(C0, dtype=np.complex128)
         self.S = np.asarray(ff, dtype=np.int64).reshape(-1, 2)
         self.n_ff = len(self.S)
         self.n_o = self.hop_t.shape[1]
@@ -189,7 +192,12 @@ def _swap34(X):
 
 
 def projected_vertices(st, P, C):
-    """VP = P[V0] + P + P[V^C] + P[V^D];  VC = C[V0] + C[V^P] + C + C[V^D]."""
+    """VP = P[V0] + P + P[V^C] + P[V^D];  VC = C[V0] + C[V^P] + C + C[V^D].
+
+    A non-local initial interaction given in crossed particle-hole form (st.C0)
+    is projected with the flowing C: V^C -> V^C + C0, V^D -> V^D + D0."""
+    if st.C0 is not None:
+        C = C + st.C0
     Pr = to_real_space(st, P)
     Cr = to_real_space(st, C)
     VP = P.copy()

@@ -16,6 +16,7 @@ from .models import (  # noqa: F401
     t2g_soc_hoppings,
     onsite_V0,
     kanamori_V0,
+    density_density_c0,
     chemical_potential,
     random_exchange_state,
     mlp_shape,

@@ -158,6 +158,37 @@ def kanamori_V0(U, J, n_orb=3):
     return V.astype(np.complex128)
 
 
+def density_density_c0(Lq, n_o, ff, bonds):
+    """Non-local density-density interaction (1/2) sum_i sum_d V_d n_i n_{i+d}
+    (n_i summed over all spin-orbitals of cell i) as the static crossed
+    particle-hole term of the initial vertex: its antisymmetrised form is
+    (1/2) Vt(k1 - k3) d13 d24 - (1/2) Vt(k1 - k4) d14 d23 (the onsite Hubbard
+    tensor of ``onsite_V0`` for d = 0), whose first part has the channel form
+    C^{00}(u) = (1/2) Vt(u) d13 d24 and whose second is the matching D term.
+    ``bonds``: [(d, V_d)] with d != (0, 0), closed under d -> -d with equal V
+    (so Vt(u) = sum_d V_d exp(-i u.d) is real).  Returns C0 in the layout
+    [Nq][n_ff][n_ff][n_o]^4 of the exchange propagators (only the (0,0)
+    form-factor block is nonzero)."""
+    ff = np.asarray(ff, dtype=np.int64).reshape(-1, 2)
+    i0 = int(np.flatnonzero((ff[:, 0] == 0) & (ff[:, 1] == 0))[0])
+    table = {(int(d[0]), int(d[1])): float(v) for d, v in bonds}
+    for (dx, dy), v in table.items():
+        if (dx, dy) == (0, 0):
+            raise ValueError("the onsite term belongs to V0")
+        if table.get((-dx, -dy)) != v:
+            raise ValueError("bonds must be closed under d -> -d with equal V")
+    n = np.arange(Lq)
+    qx, qy = np.meshgrid(n, n, indexing="ij")
+    qx, qy = qx.reshape(-1), qy.reshape(-1)
+    vt = np.zeros(Lq * Lq)
+    for (dx, dy), v in table.items():
+        vt += v * np.cos(2.0 * np.pi * (qx * dx + qy * dy) / Lq)
+    d = np.eye(n_o)
+    C0 = np.zeros((Lq * Lq, len(ff), len(ff)) + (n_o,) * 4, dtype=np.complex128)
+    C0[:, i0, i0] = 0.5 * vt[:, None, None, None, None] * np.einsum("ac,bd->abcd", d, d)[None]
+    return C0
+
+
 @lru_cache(maxsize=None)
 def _mu_cached(key, filling, L, T):
     hop_R, hop_t = _MU_TABLES[key]

@@ -9,6 +9,11 @@
   form of Sec. 3.3 that the real-space form replaces).
 * D^[V] = -C^[V] with the outgoing legs exchanged for antisymmetric V (Sec. 2,
   property 2) and hermiticity of P^[V], C^[V] for hermitian V (property 3).
+* A non-local (density-density) initial interaction, written out from its
+  Hamiltonian, is the onsite tensor plus a static C-channel term and its D
+  partner; projected through the cross projections it equals the double
+  k-sums of the bare vertex and fills form-factor blocks beyond (0,0)
+  (the non-local initial interactions the paper's outlook points to).
 """
 
 import numpy as np
@@ -16,7 +21,8 @@ import pytest
 
 from oracle import bruteforce as bf
 from oracle import tufrg
-from synth import ff_shell, random_exchange_state, rashba_hoppings
+from synth import (density_density_c0, ff_shell, hubbard_hoppings, onsite_V0, random_exchange_state,
+                   rashba_hoppings)
 
 
 def test_form_factor_orthonormality_and_completeness():
@@ -118,3 +124,59 @@ def test_projections_of_hermitian_vertex_are_hermitian():
             A = M.transpose(0, 1, 3, 5, 2, 6, 4)
         A = A.reshape(lat.N, lat.N * n * n, lat.N * n * n)
         assert np.abs(A - A.conj().transpose(0, 2, 1)).max() < 1e-13
+
+
+def _density_vertex(lat, n_o, bonds, U):
+    """Antisymmetrised density-density vertex written out from its definition:
+    H = (1/2) sum_i sum_d V_d n_i n_{i+d} (d = 0: U) is 1/2 sum X c+_1 c+_2 c_4 c_3
+    with X(k1, k2, k3) = Vt(k1 - k3) d13 d24, Vt(q) = U + sum_d V_d e^{-iq.d};
+    the antisymmetric vertex is a quarter of X antisymmetrised in (1, 2) and (3, 4)."""
+    N = lat.N
+    vt = np.full(N, U, dtype=np.complex128)
+    for d, v in bonds:
+        vt += v * np.exp(-2j * np.pi * ((lat.k @ np.asarray(d)) % lat.L) / lat.L)
+    i1, i2, i3 = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    dd = np.einsum("ac,bd->abcd", np.eye(n_o), np.eye(n_o))
+    X = vt[lat.sub[i1, i3]][..., None, None, None, None] * dd
+    return bf.antisymmetrize(lat, X) / 4.0
+
+
+BONDS = [((1, 0), 0.7), ((-1, 0), 0.7), ((0, 1), 0.7), ((0, -1), 0.7), ((1, 1), -0.2), ((-1, -1), -0.2)]
+
+
+def test_density_interaction_is_onsite_tensor_plus_channel_terms():
+    """The onsite part is the Hubbard tensor and the non-local part is the C
+    term C0 of density_density_c0 plus its D partner (D0 = -C0 with the last
+    two indices exchanged), checked on the complete form-factor set."""
+    L, n_o = 4, 2
+    lat = bf.Lattice(L)
+    S = bf.complete_ff(L)
+    onsite = _density_vertex(lat, n_o, [], 1.3)
+    assert np.abs(onsite - onsite_V0(1.3)[None, None, None]).max() < 1e-14
+    V = _density_vertex(lat, n_o, BONDS, 0.0)
+    C0 = density_density_c0(L, n_o, S, BONDS)
+    rebuilt = bf.expand_C(lat, C0, S) + bf.expand_D(lat, tufrg.d_from_c(C0), S)
+    assert np.abs(rebuilt - V).max() < 1e-13
+
+
+@pytest.mark.parametrize("hop_sel", ["rashba", "hubbard"])
+def test_nonlocal_initial_interaction_projects_like_its_definition(hop_sel):
+    """P^[V0], C^[V0] of onsite U plus non-local density terms, through the
+    library's route (V0 in the (0,0) block, C0 through the cross projections),
+    equal the double k-sums of the bare vertex (complete form-factor set)."""
+    L, n_o = 4, 2
+    lat = bf.Lattice(L)
+    S = bf.complete_ff(L)
+    U = 1.3
+    hop = rashba_hoppings(1.0, 0.3) if hop_sel == "rashba" else hubbard_hoppings(1.0, -0.25)
+    st = tufrg.TUSetup(*hop, 0.0, onsite_V0(U), S, L, 1, "temperature",
+                       C0=density_density_c0(L, n_o, S, BONDS))
+    zero = st.zero_state()
+    VP, VC = tufrg.projected_vertices(st, zero, zero)
+    V = _density_vertex(lat, n_o, BONDS, U)
+    assert np.abs(VP - bf.project_P(lat, V, S)).max() < 1e-12
+    assert np.abs(VC - bf.project_C(lat, V, S)).max() < 1e-12
+    # the non-local terms reach form-factor blocks other than (0,0) in P
+    off = VP.copy()
+    off[:, 0, 0] = 0
+    assert np.abs(off).max() > 0.1

@@ -148,6 +148,20 @@ tufrg_status tufrg_band_data(tufrg_ctx *ctx, double *e, tufrg_c64 *Pi);
  * (the loops of the RGE); deriv = 0: the bubbles F-/+ themselves. */
 tufrg_status tufrg_bubble(tufrg_ctx *ctx, int32_t channel, double lambda, int32_t deriv, tufrg_c64 *L);
 
+/* Non-local part of the initial interaction (the paper's outlook: longer-ranged
+ * bare interactions, whose projections fill form-factor blocks beyond (0,0)):
+ * C0 [Nq][B][B] (device, the C bundle layout) is a static crossed
+ * particle-hole term of the bare vertex.  From this call on every projection
+ * uses C + C0 in place of C (and D + D0, D0 = -C0 with the last two indices
+ * exchanged, Sec. 3.2), so 'VP = P[V0] + P + P[V^C] + P[V^D]' and 'VC' include
+ * the projections of the non-local bare interaction while the flowing state C
+ * starts from zero.  A density-density interaction (1/2) sum_{i,d} V_d n_i
+ * n_{i+d} has C0^{00}(u)_{n1n2n3n4} = (1/2) sum_d V_d e^{-iu.d} d13 d24 in the
+ * (0,0) form-factor block (the onsite d = 0 term is V0).  The library copies
+ * C0 (stream-ordered); C0 = NULL removes it.  Errors: E_INVAL for a host
+ * pointer, E_NOMEM when the two [Nq][B][B] buffers cannot be allocated. */
+tufrg_status tufrg_set_initial_c(tufrg_ctx *ctx, const tufrg_c64 *C0);
+
 /* Projected vertices VP, VC [Nq][B][B] of the state P, C [Nq][B][B] (Sec. 3.3). */
 tufrg_status tufrg_project(tufrg_ctx *ctx, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,
                            tufrg_c64 *VC);

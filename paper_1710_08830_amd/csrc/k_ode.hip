@@ -149,6 +149,24 @@ __global__ void scale_kernel(long long n, const double *__restrict__ x, double s
     y[i] = s * x[i];
 }
 
+__global__ void add_kernel(long long n2, const double2 *__restrict__ a, const double2 *__restrict__ b,
+                           double2 *__restrict__ y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += (long long)gridDim.x * blockDim.x) {
+    const double2 u = a[i], v = b[i];
+    y[i] = make_double2(u.x + v.x, u.y + v.y);
+  }
+}
+
+hipError_t launch_add(long long n, const double *a, const double *b, double *y, hipStream_t st) {
+  if (n % 2) return hipErrorInvalidValue;  // complex arrays: pairs of doubles
+  const long long n2 = n / 2;
+  long long blocks = (n2 + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(add_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n2, (const double2 *)a, (const double2 *)b,
+                     (double2 *)y);
+  return hipGetLastError();
+}
+
 hipError_t launch_scale(long long n, const double *x, double s, double *y, hipStream_t st) {
   long long blocks = (n + 255) / 256;
   if (blocks > 8192) blocks = 8192;

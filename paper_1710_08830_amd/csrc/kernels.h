@@ -90,6 +90,8 @@ hipError_t launch_dp_error(long long n, const double *x0, const double *x1, int 
                            unsigned int *flag, hipStream_t st);
 hipError_t launch_clear_reduce(unsigned long long *bits, unsigned int *flag, hipStream_t st);
 hipError_t launch_scale(long long n, const double *x, double s, double *y, hipStream_t st);
+// y = a + b over n doubles (n even: complex arrays)
+hipError_t launch_add(long long n, const double *a, const double *b, double *y, hipStream_t st);
 
 // loop surrogate network (k_mlp.hip)
 hipError_t launch_gemm_f32(int M, int N, int K, const float *A, int lda, int tA, const float *B, int ldb, int tB,

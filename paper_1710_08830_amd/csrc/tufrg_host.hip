@@ -54,6 +54,9 @@ struct tufrg_ctx {
   float *d_bandk32 = nullptr;
   double *d_kv64 = nullptr;
   float *d_kv32 = nullptr;
+  double *d_c0 = nullptr;     // static C-channel term of a non-local initial interaction, [Nq][B][B]
+  double *d_ceff = nullptr;   // C + C0 for the projections
+  bool has_c0 = false;
   double temp = 0.0;          // momentum-shell scheme: the fixed temperature of its bubbles
   double *d_cv64 = nullptr;   // momentum-shell scheme: shell factors (see LoopArgs::cv)
   float *d_cv32 = nullptr;
@@ -705,6 +708,12 @@ static tufrg_status surrogate_loops(tufrg_ctx *c, double lam) {
 static tufrg_status project_internal(tufrg_ctx *c, const double *P, const double *C, double *VP, double *VC) {
   ProjArgs a = proj_args(c);
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_PROJECT));
+  if (c->has_c0) {
+    // a non-local initial interaction enters as a static part of the C
+    // channel (its D partner follows from C inside the projections)
+    HIPCHK(c, launch_add(2 * (long long)c->Nq * c->B * c->B, C, c->d_c0, c->d_ceff, c->st));
+    C = c->d_ceff;
+  }
   HIPCHK(c, launch_ft(a, P, C, c->d_ftpart, c->nqc, c->d_real, c->st));
   HIPCHK(c, launch_gather(a, c->d_real, c->d_G, c->st));
   HIPCHK(c, launch_assemble(a, P, C, c->d_G, c->d_v0p, c->d_v0c, VP, VC, c->st));
@@ -791,6 +800,23 @@ extern "C" tufrg_status tufrg_project(tufrg_ctx *c, const tufrg_c64 *P, const tu
   if (!is_device_ptr(P) || !is_device_ptr(C) || !is_device_ptr(VP) || !is_device_ptr(VC))
     return fail(c, TUFRG_E_INVAL, "P, C, VP, VC must be device pointers");
   return project_internal(c, (const double *)P, (const double *)C, (double *)VP, (double *)VC);
+}
+
+extern "C" tufrg_status tufrg_set_initial_c(tufrg_ctx *c, const tufrg_c64 *C0) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!C0) {
+    c->has_c0 = false;
+    return TUFRG_OK;
+  }
+  if (!is_device_ptr(C0)) return fail(c, TUFRG_E_INVAL, "C0 must be a device pointer");
+  const size_t n = 2 * (size_t)c->Nq * c->B * c->B;
+  if (!c->d_c0) {
+    TRY(dalloc(c, &c->d_c0, n));
+    TRY(dalloc(c, &c->d_ceff, n));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_c0, C0, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  c->has_c0 = true;
+  return TUFRG_OK;
 }
 
 extern "C" tufrg_status tufrg_rhs(tufrg_ctx *c, double lambda, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *dP,

@@ -37,7 +37,7 @@ SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "t
            "tufrg_mlp_set_params", "tufrg_mlp_forward", "tufrg_mlp_loss_grad", "tufrg_mlp_adam_step",
            "tufrg_mlp_train", "tufrg_sur_features", "tufrg_sur_targets", "tufrg_sur_attach",
            "tufrg_sur_loops", "tufrg_batch_create", "tufrg_batch_destroy", "tufrg_batch_last_error",
-           "tufrg_batch_dims", "tufrg_batch_flow"]
+           "tufrg_batch_dims", "tufrg_batch_flow", "tufrg_set_initial_c"]
 TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE, TIMER_SURROGATE = 0, 1, 2, 3
 
 
@@ -223,6 +223,12 @@ def tufrg_bubble(ctx, channel, lam, deriv, L):
 
 def tufrg_project(ctx, P, C, VP, VC):
     _check(_lib.tufrg_project(ctx.handle, _ptr(P), _ptr(C), _ptr(VP), _ptr(VC)), ctx.handle)
+
+
+def tufrg_set_initial_c(ctx, C0):
+    """Static C-channel term of a non-local initial interaction ([Nq][B][B] on
+    the device, C layout), or None to remove it."""
+    _check(_lib.tufrg_set_initial_c(ctx.handle, None if C0 is None else _ptr(C0)), ctx.handle)
 
 
 def tufrg_rhs(ctx, lam, P, C, dP, dC):

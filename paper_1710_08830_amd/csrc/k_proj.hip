@@ -21,15 +21,18 @@
 namespace tufrg {
 
 // part[qc][w][iD][e] = sum_{q in chunk qc} e^{iq.rho_iD} X_w(q)[e]
-// phq[q][iD] = e^{i q.rho_iD} (table, read with wave-uniform loads)
+// phq[q][iD] = e^{i q.rho_iD}: staged per tile of PQT q in LDS (every lane
+// reads the same phase: broadcast)
+constexpr int PQT = 16;
 template <int NDP>
 __global__ __launch_bounds__(256) void ft_kernel(int BB, int Nq, int nD, int qper, const double *__restrict__ phq,
                                                  const double *__restrict__ P, const double *__restrict__ C,
                                                  double *__restrict__ part) {
+  __shared__ double2 sph[PQT][NDP];
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int w = blockIdx.y;
   const int qc = blockIdx.z;
-  if (e >= BB) return;
+  const bool active = e < BB;
   const double *X = (w == 0) ? P : C;
   double ar[NDP], ai[NDP];
 #pragma unroll
@@ -38,18 +41,29 @@ __global__ __launch_bounds__(256) void ft_kernel(int BB, int Nq, int nD, int qpe
     ai[i] = 0.0;
   }
   const int q0 = qc * qper, q1 = min(Nq, q0 + qper);
-  for (int q = q0; q < q1; ++q) {
-    const double2 x = *(const double2 *)(X + 2 * ((size_t)q * BB + e));
-    const double *ph = phq + 2 * (size_t)q * nD;
+  for (int qb = q0; qb < q1; qb += PQT) {
+    const int nqb = min(PQT, q1 - qb);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nqb * nD; i += blockDim.x) {
+      const int qq = i / nD, d = i - qq * nD;
+      sph[qq][d] = *(const double2 *)(phq + 2 * ((size_t)(qb + qq) * nD + d));
+    }
+    __syncthreads();
+    if (active) {
+      for (int qq = 0; qq < nqb; ++qq) {
+        const double2 x = *(const double2 *)(X + 2 * ((size_t)(qb + qq) * BB + e));
 #pragma unroll
-    for (int i = 0; i < NDP; ++i) {
-      if (i < nD) {
-        const double c = ph[2 * i], s = ph[2 * i + 1];
-        ar[i] = fma(c, x.x, fma(-s, x.y, ar[i]));
-        ai[i] = fma(c, x.y, fma(s, x.x, ai[i]));
+        for (int i = 0; i < NDP; ++i) {
+          if (i < nD) {
+            const double2 p = sph[qq][i];
+            ar[i] = fma(p.x, x.x, fma(-p.y, x.y, ar[i]));
+            ai[i] = fma(p.x, x.y, fma(p.y, x.x, ai[i]));
+          }
+        }
       }
     }
   }
+  if (!active) return;
   const size_t base = ((size_t)qc * 2 + w) * nD;
 #pragma unroll
   for (int i = 0; i < NDP; ++i)
@@ -154,16 +168,19 @@ hipError_t launch_gather(const ProjArgs &a, const double *real, double *G, hipSt
   return hipGetLastError();
 }
 
-// VX(q)[e] = X(q)[e] + X[V0][e] + sum_rho e^{iq.rho} G_X(rho)[e]
+// VX(q)[e] = X(q)[e] + X[V0][e] + sum_rho e^{iq.rho} G_X(rho)[e]; the phases of
+// a tile of PQT q are staged in LDS as in ft_kernel
 template <int NDP>
 __global__ __launch_bounds__(256) void assemble_kernel(int BB, int Nq, int nD, int qper, const double *__restrict__ phq,
                                                        const double *__restrict__ P, const double *__restrict__ C,
                                                        const double *__restrict__ G, const double *__restrict__ v0p,
                                                        const double *__restrict__ v0c, double *__restrict__ VP,
                                                        double *__restrict__ VC) {
+  __shared__ double2 sph[PQT][NDP];
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   const int w = blockIdx.y, qc = blockIdx.z;
-  if (e >= BB) return;
+  const bool active = e < BB;
+  const int ea = active ? e : 0;
   const double *X = (w == 0) ? P : C;
   const double *v0 = (w == 0) ? v0p : v0c;
   double *out = (w == 0) ? VP : VC;
@@ -171,7 +188,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(int BB, int Nq, int nD, i
 #pragma unroll
   for (int i = 0; i < NDP; ++i) {
     if (i < nD) {
-      const size_t s = ((size_t)w * nD + i) * BB + e;
+      const size_t s = ((size_t)w * nD + i) * BB + ea;
       gr[i] = G[2 * s];
       gi[i] = G[2 * s + 1];
     } else {
@@ -179,24 +196,35 @@ __global__ __launch_bounds__(256) void assemble_kernel(int BB, int Nq, int nD, i
       gi[i] = 0.0;
     }
   }
-  const double v0r = v0[2 * e], v0i = v0[2 * e + 1];
+  const double v0r = v0[2 * ea], v0i = v0[2 * ea + 1];
   const int q0 = qc * qper, q1 = min(Nq, q0 + qper);
-  for (int q = q0; q < q1; ++q) {
-    const double2 x = *(const double2 *)(X + 2 * ((size_t)q * BB + e));
-    const double *ph = phq + 2 * (size_t)q * nD;
-    double sr = x.x + v0r, si = x.y + v0i;
+  for (int qb = q0; qb < q1; qb += PQT) {
+    const int nqb = min(PQT, q1 - qb);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nqb * nD; i += blockDim.x) {
+      const int qq = i / nD, d = i - qq * nD;
+      sph[qq][d] = *(const double2 *)(phq + 2 * ((size_t)(qb + qq) * nD + d));
+    }
+    __syncthreads();
+    if (active) {
+      for (int qq = 0; qq < nqb; ++qq) {
+        const int q = qb + qq;
+        const double2 x = *(const double2 *)(X + 2 * ((size_t)q * BB + e));
+        double sr = x.x + v0r, si = x.y + v0i;
 #pragma unroll
-    for (int i = 0; i < NDP; ++i) {
-      if (i < nD) {
-        const double c = ph[2 * i], s = ph[2 * i + 1];
-        sr = fma(c, gr[i], fma(-s, gi[i], sr));
-        si = fma(c, gi[i], fma(s, gr[i], si));
+        for (int i = 0; i < NDP; ++i) {
+          if (i < nD) {
+            const double2 p = sph[qq][i];
+            sr = fma(p.x, gr[i], fma(-p.y, gi[i], sr));
+            si = fma(p.x, gi[i], fma(p.y, gr[i], si));
+          }
+        }
+        double2 o;
+        o.x = sr;
+        o.y = si;
+        *(double2 *)(out + 2 * ((size_t)q * BB + e)) = o;
       }
     }
-    double2 o;
-    o.x = sr;
-    o.y = si;
-    *(double2 *)(out + 2 * ((size_t)q * BB + e)) = o;
   }
 }
 

@@ -385,7 +385,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the q-sharded multi-GPU "
-              "path is a design, not part of this build", file=sys.stderr)
+              "path is a design, not implemented in this library", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

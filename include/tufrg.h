@@ -89,7 +89,7 @@ typedef enum {
   TUFRG_E_HIP = 3,         /* a HIP runtime call failed */
   TUFRG_E_NONFINITE = 4,   /* NaN or Inf in the state during a flow */
   TUFRG_E_STEPSIZE = 5,    /* adaptive step size underflow */
-  TUFRG_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+  TUFRG_E_UNSUPPORTED = 6  /* valid request the library does not implement */
 } tufrg_status;
 
 /* Regulators (Sec. 3.1: the loops are the Lambda derivatives of regulated

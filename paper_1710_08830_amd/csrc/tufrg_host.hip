@@ -184,7 +184,7 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   if (!m || !s || !out) return fail(nullptr, TUFRG_E_INVAL, "null argument");
   *out = nullptr;
   if (m->n_orb != 2 && m->n_orb != 6)
-    return fail(nullptr, TUFRG_E_UNSUPPORTED, "this build supports n_orb = 2 or 6 spin-orbitals");
+    return fail(nullptr, TUFRG_E_UNSUPPORTED, "the library supports n_orb = 2 or 6 spin-orbitals");
   if (m->n_hop < 1 || !m->hop_R || !m->hop_t || !m->V0) return fail(nullptr, TUFRG_E_INVAL, "empty model");
   if (s->n_ff < 1 || !s->ff_R) return fail(nullptr, TUFRG_E_INVAL, "empty form-factor set");
   if (s->ff_R[0] != 0 || s->ff_R[1] != 0) return fail(nullptr, TUFRG_E_INVAL, "ff_R[0] must be (0,0)");

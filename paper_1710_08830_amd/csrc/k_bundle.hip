@@ -38,27 +38,50 @@ __global__ __launch_bounds__(256) void bundle_small_kernel(int n_o, int n_ff, in
   for (int i = threadIdx.x; i < nD * no4; i += blockDim.x) sL[i] = cmake((T)Lq[2 * i], (T)Lq[2 * i + 1]);
   for (int i = threadIdx.x; i < n_ff * n_ff; i += blockDim.x) sD[i] = didx[i];
   __syncthreads();
-  // T = L . V
-  for (int idx = threadIdx.x; idx < BB; idx += blockDim.x) {
-    const int i = idx / B, j = idx - i * B;
+  // T = L . V, four adjacent columns per item (B is a multiple of 4: 4 n_ff for
+  // two spin-orbitals, the only case with B <= 64)
+  const int BQ = B >> 2;
+  for (int idx = threadIdx.x; idx < B * BQ; idx += blockDim.x) {
+    const int i = idx / BQ, j = (idx - i * BQ) << 2;
     const int ri = i / no2, ab = i - ri * no2;
-    cx<T> s = cmake(T(0), T(0));
+    cx<T> s0 = cmake(T(0), T(0)), s1 = s0, s2 = s0, s3 = s0;
     for (int rk = 0; rk < n_ff; ++rk) {
       const cx<T> *Lrow = sL + (size_t)sD[ri * n_ff + rk] * no4 + ab * no2;
       const int vcol = rk * no2 * B + j;
-      for (int cd = 0; cd < no2; ++cd) cfma(s, Lrow[cd], vat(vcol + cd * B));
+      for (int cd = 0; cd < no2; ++cd) {
+        const cx<T> l = Lrow[cd];
+        const int v = vcol + cd * B;
+        cfma(s0, l, vat(v));
+        cfma(s1, l, vat(v + 1));
+        cfma(s2, l, vat(v + 2));
+        cfma(s3, l, vat(v + 3));
+      }
     }
-    sT[idx] = s;
+    sT[i * B + j] = s0;
+    sT[i * B + j + 1] = s1;
+    sT[i * B + j + 2] = s2;
+    sT[i * B + j + 3] = s3;
   }
   __syncthreads();
-  // out = f V . T
+  // out = f V . T, four adjacent columns per item
   double *oq = out + 2 * (size_t)q * BB;
-  for (int idx = threadIdx.x; idx < BB; idx += blockDim.x) {
-    const int i = idx / B, j = idx - i * B;
-    cx<T> s = cmake(T(0), T(0));
-    for (int k = 0; k < B; ++k) cfma(s, vat(i * B + k), sT[k * B + j]);
-    oq[2 * idx] = factor * (double)s.re;
-    oq[2 * idx + 1] = factor * (double)s.im;
+  for (int idx = threadIdx.x; idx < B * BQ; idx += blockDim.x) {
+    const int i = idx / BQ, j = (idx - i * BQ) << 2;
+    cx<T> s0 = cmake(T(0), T(0)), s1 = s0, s2 = s0, s3 = s0;
+    for (int k = 0; k < B; ++k) {
+      const cx<T> v = vat(i * B + k);
+      const cx<T> *Tk = sT + k * B + j;
+      cfma(s0, v, Tk[0]);
+      cfma(s1, v, Tk[1]);
+      cfma(s2, v, Tk[2]);
+      cfma(s3, v, Tk[3]);
+    }
+    const cx<T> r[4] = {s0, s1, s2, s3};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      oq[2 * (i * B + j + c)] = factor * (double)r[c].re;
+      oq[2 * (i * B + j + c) + 1] = factor * (double)r[c].im;
+    }
   }
 }
 
@@ -159,6 +182,7 @@ hipError_t launch_bundle(int prec, int n_o, int n_ff, int B, int nD, int n_q, co
     }
     return hipGetLastError();
   }
+  if (B % 4) return hipErrorInvalidValue;  // small bundles are 4 n_ff wide
   const bool vlds = withV <= limit;
   const size_t lds = vlds ? withV : base;
   if (prec == 0) {

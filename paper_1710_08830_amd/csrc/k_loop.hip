@@ -250,7 +250,7 @@ __global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (siz
                                                            int nkyb, int nkxc, int kxper, int q_first, int n_q,
                                                            const int *__restrict__ rows,
                                                            int ch_first, int n_items, T lam, int deriv,
-                                                           double *__restrict__ partial) {
+                                                           T *__restrict__ partial) {
   constexpr int NDY2 = 2 * NDY + 1;
   const int tid = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int xcd = blockIdx.x % N_XCD, slot = blockIdx.x / N_XCD;
@@ -364,8 +364,8 @@ __global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (siz
       }
       const size_t idx = pbase + ((size_t)(dx * NDY2 + dyi) * 16 + t);
       if (qvalid) {
-        partial[2 * idx] = (double)sr;
-        partial[2 * idx + 1] = (double)si;
+        partial[2 * idx] = sr;
+        partial[2 * idx + 1] = si;
       }
     }
   }
@@ -389,7 +389,7 @@ static hipError_t launch_no2(const LoopArgs &a, hipStream_t st) {
 #define TUFRG_NO2_LAUNCH(S)                                                                                         \
   hipLaunchKernelGGL((loop_no2_kernel<T, NDX, NDY, S, QW>), grid, block, 0, st, ekv, pi4, cvp, a.tw, twk, a.Lq,    \
                      a.n_ref, a.Lf, a.nkyb, a.nkxc, kxper, a.q_first, a.n_q, a.rows, a.ch_first, n_items, (T)a.lam, \
-                     a.deriv, a.partial)
+                     a.deriv, (T *)a.partial)
   if (a.scheme == CUT_TEMPERATURE)
     TUFRG_NO2_LAUNCH(CUT_TEMPERATURE);
   else if (a.scheme == CUT_OMEGA)
@@ -414,8 +414,9 @@ hipError_t launch_loop(const LoopArgs &a, hipStream_t st) {
 
 // ---------------------------------------------------------------------------
 
+template <typename PT>
 __global__ void loop_finalize_kernel(int n_o, int n_ch, int n_q, int nparts, int ndx, int ndy, int nD,
-                                     const int *__restrict__ dlist, double inv_nf, const double *__restrict__ partial,
+                                     const int *__restrict__ dlist, double inv_nf, const PT *__restrict__ partial,
                                      double *__restrict__ compact) {
   const int no2 = n_o * n_o, no4 = no2 * no2;
   const long long total = (long long)n_ch * n_q * nD * no4;
@@ -435,11 +436,11 @@ __global__ void loop_finalize_kernel(int n_o, int n_ch, int n_q, int nparts, int
   }
   const int ndy2 = 2 * ndy + 1;
   const size_t per = (size_t)ndx * ndy2 * no4;
-  const double *p = partial + (size_t)cq * nparts * per * 2 + ((size_t)(dx * ndy2 + dy + ndy) * no4 + t) * 2;
+  const PT *p = partial + (size_t)cq * nparts * per * 2 + ((size_t)(dx * ndy2 + dy + ndy) * no4 + t) * 2;
   double sr = 0.0, si = 0.0;
   for (int k = 0; k < nparts; ++k) {
-    sr += p[(size_t)k * per * 2];
-    si += p[(size_t)k * per * 2 + 1];
+    sr += (double)p[(size_t)k * per * 2];
+    si += (double)p[(size_t)k * per * 2 + 1];
   }
   compact[2 * i] = sr * inv_nf;
   compact[2 * i + 1] = (cj ? -si : si) * inv_nf;
@@ -450,8 +451,13 @@ hipError_t launch_loop_finalize(const LoopArgs &a, int nD, const int *dlist, dou
   const long long total = (long long)a.n_ch * a.n_q * nD * no4;
   const int nparts = a.nkyb * a.nkxc;
   const double inv = 1.0 / ((double)a.Lf * a.Lf);
-  hipLaunchKernelGGL(loop_finalize_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a.n_o, a.n_ch,
-                     a.n_q, nparts, a.ndx, a.ndy, nD, dlist, inv, (const double *)a.partial, compact);
+  const dim3 grid((unsigned)((total + 255) / 256)), block(256);
+  if (a.prec == 0)
+    hipLaunchKernelGGL(loop_finalize_kernel<double>, grid, block, 0, st, a.n_o, a.n_ch, a.n_q, nparts, a.ndx, a.ndy,
+                       nD, dlist, inv, (const double *)a.partial, compact);
+  else
+    hipLaunchKernelGGL(loop_finalize_kernel<float>, grid, block, 0, st, a.n_o, a.n_ch, a.n_q, nparts, a.ndx, a.ndy,
+                       nD, dlist, inv, (const float *)a.partial, compact);
   return hipGetLastError();
 }
 

@@ -106,7 +106,7 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
                                                         int n_pairs, int Lq, int n_ref, int Lf, int nparts,
                                                         int q_first, int n_q, const int *__restrict__ rows,
                                                         int ch_first, int n_ch, int ndx_out,
-                                                        T lam, int deriv, double *__restrict__ partial) {
+                                                        T lam, int deriv, T *__restrict__ partial) {
   using SH = Shape<NDY>;
   constexpr int NPT = SH::N;
   constexpr int NO2 = NO * NO, NO4 = NO2 * NO2;
@@ -251,13 +251,13 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
     const int dx = SH::dx(i), dy = SH::dy(i);
     if (dx >= 0) {
       const size_t idx = pbase + (size_t)(dx * ndy2 + dy + NDY) * NO4 + tau;
-      partial[2 * idx] = (double)Z[i].re;
-      partial[2 * idx + 1] = (double)Z[i].im;
+      partial[2 * idx] = Z[i].re;
+      partial[2 * idx + 1] = Z[i].im;
     }
     if (dx <= 0 && taub != tau) {
       const size_t idx = pbase + (size_t)(-dx * ndy2 - dy + NDY) * NO4 + taub;
-      partial[2 * idx] = (double)Z[i].re;
-      partial[2 * idx + 1] = -(double)Z[i].im;
+      partial[2 * idx] = Z[i].re;
+      partial[2 * idx + 1] = -Z[i].im;
     }
   }
 }
@@ -276,7 +276,7 @@ static hipError_t launch_gen(const LoopArgs &a, hipStream_t st) {
 #define TUFRG_GEN_LAUNCH(S)                                                                                          \
   hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, S, NTHR, KT>), grid, block, 0, st, band, kv, cvp, a.tw, phy, a.pairs, \
                      a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.rows, a.ch_first, a.n_ch, a.ndx,         \
-                     (T)a.lam, a.deriv, a.partial)
+                     (T)a.lam, a.deriv, (T *)a.partial)
   if (a.scheme == CUT_TEMPERATURE)
     TUFRG_GEN_LAUNCH(CUT_TEMPERATURE);
   else if (a.scheme == CUT_OMEGA)

@@ -434,7 +434,7 @@ template <int NDY>
 __global__ __launch_bounds__(256) void loop_rowsum_kernel(const float *__restrict__ Y, const double *__restrict__ tw,
                                                           const int *__restrict__ pairs, int n_pairs, int Lf,
                                                           int nparts, int slot0, int n_slots, int ndx_out,
-                                                          double *__restrict__ partial) {
+                                                          float *__restrict__ partial) {
   constexpr int NPHI = 2 * NDY + 1, ROWS = NPHI * XC;
   constexpr int NPT = (NDY == 4) ? 41 : 25;
   const int part = blockIdx.x % nparts, qrel = blockIdx.x / nparts;
@@ -513,13 +513,13 @@ __global__ __launch_bounds__(256) void loop_rowsum_kernel(const float *__restric
     }
     if (dx >= 0) {
       const size_t idx = pbase + (size_t)(dx * ndy2 + dy + NDY) * NO4 + tau;
-      partial[2 * idx] = (double)zr[i];
-      partial[2 * idx + 1] = (double)zi[i];
+      partial[2 * idx] = zr[i];
+      partial[2 * idx + 1] = zi[i];
     }
     if (dx <= 0 && taub != tau) {
       const size_t idx = pbase + (size_t)(-dx * ndy2 - dy + NDY) * NO4 + taub;
-      partial[2 * idx] = (double)zr[i];
-      partial[2 * idx + 1] = -(double)zi[i];
+      partial[2 * idx] = zr[i];
+      partial[2 * idx + 1] = -zi[i];
     }
   }
 }
@@ -569,10 +569,10 @@ hipError_t launch_loop_rowsum(const LoopArgs &a, const float *Y, hipStream_t st)
   dim3 g2(a.n_q * np), b2(256);
   if (a.ndy == 4)
     hipLaunchKernelGGL(loop_rowsum_kernel<4>, g2, b2, 0, st, Y, a.tw, a.pairs, a.n_pairs, a.Lf, np, 0, a.n_q, a.ndx,
-                       a.partial);
+                       (float *)a.partial);
   else if (a.ndy == 2)
     hipLaunchKernelGGL(loop_rowsum_kernel<2>, g2, b2, 0, st, Y, a.tw, a.pairs, a.n_pairs, a.Lf, np, 0, a.n_q, a.ndx,
-                       a.partial);
+                       (float *)a.partial);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

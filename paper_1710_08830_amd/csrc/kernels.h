@@ -36,7 +36,8 @@ struct LoopArgs {
   const void *kv;      // regulator values, [n_o][Nf] or [Nf][n_o] like the band data
   const double *tw;    // exp(-2 pi i j / Lf), [Lf][2]
   const float *tw32 = nullptr;  // the same in FP32
-  double *partial;     // [n_ch][n_q][nkyb * nkxc][ndx][2 ndy + 1][n_o^4][2]
+  void *partial;       // [n_ch][n_q][nkyb * nkxc][ndx][2 ndy + 1][n_o^4][2] in the arithmetic type
+                       // (FP64 for TUFRG_FP64, else FP32: the partials carry no more)
   const int *pairs = nullptr;  // more than two orbitals: [n_pairs][2] entry and its conjugate partner
   int n_pairs = 0;
   const void *phy = nullptr;   // more than two orbitals: exp(-2 pi i ky dy / Lf), [Lf][ndy][2], like band

@@ -162,6 +162,33 @@ tufrg_status tufrg_bubble(tufrg_ctx *ctx, int32_t channel, double lambda, int32_
  * pointer, E_NOMEM when the two [Nq][B][B] buffers cannot be allocated. */
 tufrg_status tufrg_set_initial_c(tufrg_ctx *ctx, const tufrg_c64 *C0);
 
+/* Orbital <-> band basis (Sec. 4.1).  The basis change of a vertex with the
+ * unitary U(k) that diagonalises H(k) turns, for the projected matrices, into
+ * sandwiches with the form-factor averages
+ *   U^{RR'}_{s1s2n1n2}(s) = 1/Nf sum_k f_R(k) f*_R'(k) U_{s1n1}(s-k) U_{s2n2}(k)   (pp)
+ *   X^{RR'}_{s1s2n1n2}(u) = 1/Nf sum_k f_R(k) f*_R'(k) U_{s1n1}(k) U*_{s2n2}(k-u)  (ph)
+ * (s orbital, n band indices, sums over the fine mesh).  In the bundle layout
+ * they are the matrices
+ *   M_pp[q][(R,a,b)][(R',c,d)] = U^{RR'}_{b a d c}(q),  M_ph[q][(R,a,b)][(R',c,d)] = X^{RR'}_{a b c d}(q),
+ * and the laws of the paper read Pb = M_pp^H P M_pp, Cb = M_ph^H C M_ph per q
+ * (converse: P = M_pp Pb M_pp^H, C = M_ph Cb M_ph^H; exact inverses only for a
+ * complete form-factor set on an unrefined mesh).  The band-basis quantities
+ * depend on the phases of the eigenvectors (and on the basis chosen inside
+ * degenerate subspaces), so U is an input: U[k][a][n] = U_an(k), k = kx * Lf
+ * + ky, Nf * n_o^2 tufrg_c64 on the device, unitary per k (not checked).
+ * tufrg_basis_matrix writes M [Nq][B][B] (device) for channel TUFRG_PP (U
+ * matrix) or TUFRG_PH (X matrix); every entry is a fixed-order FP64 k-sum.
+ * Errors: E_INVAL for an unknown channel or a host pointer. */
+tufrg_status tufrg_basis_matrix(tufrg_ctx *ctx, int32_t channel, const tufrg_c64 *U, tufrg_c64 *M);
+
+/* Y[q] = M[q]^H X[q] M[q] (to_orbital = 0: orbital -> band) or
+ * Y[q] = M[q] X[q] M[q]^H (to_orbital = 1: band -> orbital), all [Nq][B][B]
+ * on the device, FP64.  Y may be X; it must not overlap M.  A workspace of
+ * Nq * B * B tufrg_c64 is allocated on the first call and kept.  Errors:
+ * E_INVAL for a host pointer or Y overlapping M, E_NOMEM for the workspace. */
+tufrg_status tufrg_basis_apply(tufrg_ctx *ctx, const tufrg_c64 *M, const tufrg_c64 *X, tufrg_c64 *Y,
+                               int32_t to_orbital);
+
 /* Projected vertices VP, VC [Nq][B][B] of the state P, C [Nq][B][B] (Sec. 3.3). */
 tufrg_status tufrg_project(tufrg_ctx *ctx, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,
                            tufrg_c64 *VC);

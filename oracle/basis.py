@@ -58,28 +58,33 @@ def _partner(Lq, n_ref, qi, channel):
     return fine, kp[:, 0] * Lf + kp[:, 1]
 
 
-def u_matrix(S, Lq, n_ref, U, q_list=None):
-    """U^{RR'}_{s1 s2 n1 n2}(s) as [q, iR, iR', s1, s2, n1, n2]."""
+def _average(S, Lq, n_ref, qi, channel, first, second, k_chunk=8192):
+    """1/N_f sum_k f_R(k) f*_R'(k) first(k)_{s1 n1} second(k)_{s2 n2}, summed in chunks of k."""
     Lf = Lq * n_ref
+    fine, kp = _partner(Lq, n_ref, qi, channel)
+    n_ff, n = len(np.asarray(S).reshape(-1, 2)), first(kp[:1], np.arange(1)).shape[1]
+    acc = np.zeros((n_ff, n_ff, n, n, n, n), dtype=np.complex128)
+    for k0 in range(0, Lf * Lf, k_chunk):
+        kk = np.arange(k0, min(k0 + k_chunk, Lf * Lf))
+        ph = _phases(S, Lf, fine[kk])
+        acc += np.einsum("krp,kan,kbm->rpabnm", ph, first(kp[kk], kk), second(kp[kk], kk), optimize=True)
+    return acc / (Lf * Lf)
+
+
+def u_matrix(S, Lq, n_ref, U, q_list=None):
+    """U^{RR'}_{s1 s2 n1 n2}(s) as [q, iR, iR', s1, s2, n1, n2]: first factor at
+    s - k, second at k."""
     q_list = range(Lq * Lq) if q_list is None else q_list
-    out = []
-    for qi in q_list:
-        fine, kp = _partner(Lq, n_ref, qi, "pp")
-        ph = _phases(S, Lf, fine)
-        out.append(np.einsum("krp,kan,kbm->rpabnm", ph, U[kp], U, optimize=True) / (Lf * Lf))
-    return np.stack(out)
+    return np.stack([_average(S, Lq, n_ref, qi, "pp", lambda kp, k: U[kp], lambda kp, k: U[k])
+                     for qi in q_list])
 
 
 def x_matrix(S, Lq, n_ref, U, q_list=None):
-    """X^{RR'}_{s1 s2 n1 n2}(u) as [q, iR, iR', s1, s2, n1, n2]."""
-    Lf = Lq * n_ref
+    """X^{RR'}_{s1 s2 n1 n2}(u) as [q, iR, iR', s1, s2, n1, n2]: first factor at
+    k, second (conjugated) at k - u."""
     q_list = range(Lq * Lq) if q_list is None else q_list
-    out = []
-    for qi in q_list:
-        fine, kp = _partner(Lq, n_ref, qi, "ph")
-        ph = _phases(S, Lf, fine)
-        out.append(np.einsum("krp,kan,kbm->rpabnm", ph, U, U[kp].conj(), optimize=True) / (Lf * Lf))
-    return np.stack(out)
+    return np.stack([_average(S, Lq, n_ref, qi, "ph", lambda kp, k: U[k], lambda kp, k: U[kp].conj())
+                     for qi in q_list])
 
 
 # ---------------------------------------------------------------------------

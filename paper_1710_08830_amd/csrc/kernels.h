@@ -81,6 +81,15 @@ hipError_t launch_assemble(const ProjArgs &a, const double *P, const double *C, 
 hipError_t launch_bundle(int prec, int n_o, int n_ff, int B, int nD, int n_q, const int *didx, const double *V,
                          const double *Lc, double factor, double *out, double *tmp, hipStream_t st);
 
+// orbital <-> band basis (k_basis.hip): compact basis matrix [Nq][nD][n_o^4] of one
+// channel (0: pp, U matrix; 1: ph, X matrix) from U[Nf][n_o][n_o] (orbital rows, band
+// columns); tw = exp(-2 pi i j / Lf), [Lf][2]
+hipError_t launch_basis_compact(int channel, int n_o, int Lq, int n_ref, int nD, const int *dlist, const double *U,
+                                const double *tw, double *out, hipStream_t st);
+// C[q] = opA(A[q]) opB(B[q]), n x n complex, op 1 = conjugate transpose (not both)
+hipError_t launch_zgemm_batched(int n, int n_q, int opA, int opB, const double *A, const double *Bm, double *C,
+                                hipStream_t st);
+
 // a7: ODE updates and reductions
 hipError_t launch_axpy_max(long long n, const double *x, double h, const double *dx, double *y,
                            unsigned long long *maxbits, unsigned int *flag, hipStream_t st);

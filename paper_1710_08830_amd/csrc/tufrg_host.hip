@@ -73,6 +73,8 @@ struct tufrg_ctx {
   // flow workspace (lazy)
   double *d_dP = nullptr, *d_dC = nullptr;
   double *d_btmp = nullptr;  // bundle workspace for B > 64
+  double *d_basis_tmp = nullptr;  // basis sandwich workspace, [Nq][B][B] complex (lazy)
+  double *d_basis_c = nullptr;    // compact basis matrix, [Nq][nD][n_o^4] complex (lazy)
   std::vector<double *> d_stage;  // DP5: 7 k's per channel + stage state per channel
   std::string err;
   std::vector<void *> allocs;
@@ -791,6 +793,38 @@ extern "C" tufrg_status tufrg_bubble(tufrg_ctx *c, int32_t channel, double lambd
   TRY(compute_loops(c, lambda, deriv ? 1 : 0, channel, 1));
   const double *src = c->d_loop + 2 * (size_t)channel * c->Nq * c->nD * c->no4;
   HIPCHK(c, launch_loop_expand(c->n_o, c->n_ff, c->nD, c->Nq, c->d_didx, src, (double *)L, c->st));
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_basis_matrix(tufrg_ctx *c, int32_t channel, const tufrg_c64 *U, tufrg_c64 *M) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (channel != TUFRG_PP && channel != TUFRG_PH) return fail(c, TUFRG_E_INVAL, "channel must be PP or PH");
+  if (!is_device_ptr(U) || !is_device_ptr(M)) return fail(c, TUFRG_E_INVAL, "U and M must be device pointers");
+  // compact form [Nq][nD][n_o^4], then expanded like the loops
+  if (!c->d_basis_c) TRY(dalloc(c, &c->d_basis_c, 2 * (size_t)c->Nq * c->nD * c->no4));
+  HIPCHK(c, launch_basis_compact(channel, c->n_o, c->Lq, c->n_ref, c->nD, c->d_dlist, (const double *)U, c->d_twf,
+                                 c->d_basis_c, c->st));
+  HIPCHK(c, launch_loop_expand(c->n_o, c->n_ff, c->nD, c->Nq, c->d_didx, c->d_basis_c, (double *)M, c->st));
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_basis_apply(tufrg_ctx *c, const tufrg_c64 *M, const tufrg_c64 *X, tufrg_c64 *Y,
+                                          int32_t to_orbital) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!is_device_ptr(M) || !is_device_ptr(X) || !is_device_ptr(Y))
+    return fail(c, TUFRG_E_INVAL, "M, X and Y must be device pointers");
+  const size_t n = (size_t)c->Nq * c->B * c->B;
+  const tufrg_c64 *m0 = M, *m1 = M + n, *y0 = Y, *y1 = Y + n;
+  if (y0 < m1 && m0 < y1) return fail(c, TUFRG_E_INVAL, "Y must not overlap M");
+  if (!c->d_basis_tmp) TRY(dalloc(c, &c->d_basis_tmp, 2 * n));
+  const double *m = (const double *)M;
+  if (!to_orbital) {  // Y = M^H X M
+    HIPCHK(c, launch_zgemm_batched(c->B, c->Nq, 1, 0, m, (const double *)X, c->d_basis_tmp, c->st));
+    HIPCHK(c, launch_zgemm_batched(c->B, c->Nq, 0, 0, c->d_basis_tmp, m, (double *)Y, c->st));
+  } else {  // Y = M X M^H
+    HIPCHK(c, launch_zgemm_batched(c->B, c->Nq, 0, 0, m, (const double *)X, c->d_basis_tmp, c->st));
+    HIPCHK(c, launch_zgemm_batched(c->B, c->Nq, 0, 1, c->d_basis_tmp, m, (double *)Y, c->st));
+  }
   return TUFRG_OK;
 }
 

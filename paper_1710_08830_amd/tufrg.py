@@ -37,7 +37,8 @@ SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "t
            "tufrg_mlp_set_params", "tufrg_mlp_forward", "tufrg_mlp_loss_grad", "tufrg_mlp_adam_step",
            "tufrg_mlp_train", "tufrg_sur_features", "tufrg_sur_targets", "tufrg_sur_attach",
            "tufrg_sur_loops", "tufrg_batch_create", "tufrg_batch_destroy", "tufrg_batch_last_error",
-           "tufrg_batch_dims", "tufrg_batch_flow", "tufrg_set_initial_c"]
+           "tufrg_batch_dims", "tufrg_batch_flow", "tufrg_set_initial_c", "tufrg_basis_matrix",
+           "tufrg_basis_apply"]
 TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE, TIMER_SURROGATE = 0, 1, 2, 3
 
 
@@ -93,6 +94,8 @@ _lib.tufrg_dims.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int32)] * 4
 _lib.tufrg_band_data.argtypes = [_vp, _vp, _vp]
 _lib.tufrg_bubble.argtypes = [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp]
 _lib.tufrg_project.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.tufrg_basis_matrix.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+_lib.tufrg_basis_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
 _lib.tufrg_rhs.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
 _lib.tufrg_flow.argtypes = [_vp, ctypes.POINTER(FlowOpts), _vp, _vp, ctypes.POINTER(FlowResult)]
 _lib.tufrg_timing.argtypes = [_vp, ctypes.c_int32]
@@ -229,6 +232,17 @@ def tufrg_set_initial_c(ctx, C0):
     """Static C-channel term of a non-local initial interaction ([Nq][B][B] on
     the device, C layout), or None to remove it."""
     _check(_lib.tufrg_set_initial_c(ctx.handle, None if C0 is None else _ptr(C0)), ctx.handle)
+
+
+def tufrg_basis_matrix(ctx, channel, U, M):
+    """Basis matrix M [Nq][B][B] of channel PP (U matrix) or PH (X matrix) from
+    the unitaries U [Nf][n_o][n_o] (orbital rows, band columns), all on the device."""
+    _check(_lib.tufrg_basis_matrix(ctx.handle, int(channel), _ptr(U), _ptr(M)), ctx.handle)
+
+
+def tufrg_basis_apply(ctx, M, X, Y, to_orbital=False):
+    """Y = M^H X M per q (orbital -> band), or M X M^H (to_orbital)."""
+    _check(_lib.tufrg_basis_apply(ctx.handle, _ptr(M), _ptr(X), _ptr(Y), int(bool(to_orbital))), ctx.handle)
 
 
 def tufrg_rhs(ctx, lam, P, C, dP, dC):

@@ -19,6 +19,7 @@ from .models import (  # noqa: F401
     density_density_c0,
     chemical_potential,
     random_exchange_state,
+    random_unitaries,
     mlp_shape,
     mlp_init,
     mlp_batch,

@@ -233,6 +233,17 @@ def random_exchange_state(n_q, n_ff, n_o, seed, scale=1.0):
     return scale * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
 
 
+def random_unitaries(n_k, n, seed):
+    """Seeded Haar-random n x n unitaries, [n_k, n, n] (QR of complex Gaussian
+    matrices with the phases of R's diagonal moved into Q): an arbitrary gauge
+    of band eigenvectors for the basis-change inputs."""
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((n_k, n, n)) + 1j * rng.standard_normal((n_k, n, n))
+    Q, R = np.linalg.qr(Z)
+    d = np.diagonal(R, axis1=1, axis2=2)
+    return Q * (d / np.abs(d))[:, None, :]
+
+
 def mlp_shape(n_in, width=256, n_out=2 * 6 ** 4, n_hidden=3):
     """Layer sizes of the loop surrogate: n_in -> width (x n_hidden) -> n_out."""
     return [int(n_in)] + [int(width)] * int(n_hidden) + [int(n_out)]

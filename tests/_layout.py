@@ -56,3 +56,17 @@ def ph_loop_to_matrix(Lt):
     layout: rows (R1, t1, t2), columns (R2, t3, t4)."""
     nq, nf, n = Lt.shape[0], Lt.shape[1], Lt.shape[3]
     return np.ascontiguousarray(Lt.transpose(0, 1, 3, 4, 2, 5, 6)).reshape(nq, nf * n * n, nf * n * n)
+
+
+def u_to_matrix(Um):
+    """U matrix [q, R, R', s1, s2, n1, n2] to the pp basis matrix of the bundle
+    layout: M[(R, a, b), (R', c, d)] = U^{RR'}_{b a d c}."""
+    nq, nf, n = Um.shape[0], Um.shape[1], Um.shape[3]
+    return np.ascontiguousarray(Um.transpose(0, 1, 4, 3, 2, 6, 5)).reshape(nq, nf * n * n, nf * n * n)
+
+
+def x_to_matrix(Xm):
+    """X matrix [q, R, R', s1, s2, n1, n2] to the ph basis matrix of the bundle
+    layout: M[(R, a, b), (R', c, d)] = X^{RR'}_{a b c d}."""
+    nq, nf, n = Xm.shape[0], Xm.shape[1], Xm.shape[3]
+    return np.ascontiguousarray(Xm.transpose(0, 1, 3, 4, 2, 5, 6)).reshape(nq, nf * n * n, nf * n * n)

@@ -89,3 +89,10 @@ def test_batch_rejects_bad_stream_count(T):
     with pytest.raises(T.TufrgError) as ei:
         T.Batch([w], n_streams=0)
     assert ei.value.status == 1
+
+
+def test_basis_calls_reject_a_null_context(T):
+    """The basis-change entry points check the context before any device call."""
+    lib = T._lib
+    assert lib.tufrg_basis_matrix(None, 0, None, None) == 1
+    assert lib.tufrg_basis_apply(None, None, None, None, 0) == 1

@@ -1,0 +1,144 @@
+"""Orbital <-> band basis on the GPU against the FP64 oracle (Sec. 4.1),
+through the C ABI: the basis matrices (U matrix for pp, X matrix for ph) from
+seeded random unitaries U(k) (an arbitrary eigenvector gauge, the same input
+for both sides) and the sandwiches M^H X M, M X M^H.  The oracle side is pinned
+in tests/test_oracle_basis.py."""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import basis  # noqa: E402
+from synth import (ff_shell, hubbard_hoppings, onsite_V0, kanamori_V0, random_exchange_state,  # noqa: E402
+                   random_unitaries, rashba_hoppings, t2g_soc_hoppings, workload)
+from tests._layout import c_to_matrix, p_to_matrix, u_to_matrix, x_to_matrix  # noqa: E402
+
+TOL = 1e-12  # FP64 sums of N_f terms of modulus <= 1 in a different order
+
+
+@pytest.fixture(scope="module")
+def T():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_08830_amd import tufrg
+    return tufrg
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
+
+
+CASES = {
+    # name: model, form factors, Lq, n_ref (ragged fine meshes, several q rows)
+    "hub5": (hubbard_hoppings(1.0, -0.25), onsite_V0(2.0), ff_shell(5), 6, 3),
+    "ras9": (rashba_hoppings(1.0, 0.3), onsite_V0(2.5), ff_shell(9), 5, 3),
+    "ras13": (rashba_hoppings(1.0, 0.45, tp=0.1), onsite_V0(2.0), ff_shell(13), 9, 2),
+    "t2g9": (t2g_soc_hoppings(0.2, seed=1), kanamori_V0(2.0, 0.3), ff_shell(9), 6, 1),
+}
+
+
+def _ctx(T, name):
+    hop, V0, ff, Lq, n_ref = CASES[name]
+    ctx = T.Context(hop[0], hop[1], 0.0, V0, ff, Lq, n_ref, "temperature", "fp64")
+    U = random_unitaries((Lq * n_ref) ** 2, hop[1].shape[1], seed=7)
+    return ctx, U, ff, Lq, n_ref
+
+
+def _zeros(ctx):
+    return torch.zeros((ctx.Nq, ctx.B, ctx.B), dtype=torch.complex128, device=dev())
+
+
+def _matrix(T, ctx, ch, U):
+    M = _zeros(ctx)
+    T.tufrg_basis_matrix(ctx, ch, torch.from_numpy(U).to(dev()), M)
+    torch.cuda.synchronize()
+    return M
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_basis_matrices_match_oracle(T, name):
+    ctx, U, ff, Lq, n_ref = _ctx(T, name)
+    q_list = list(range(Lq * Lq)) if name != "t2g9" else [0, 1, 7, 20, 35]
+    for ch, make, conv in ((T.PP, basis.u_matrix, u_to_matrix), (T.PH, basis.x_matrix, x_to_matrix)):
+        M = _matrix(T, ctx, ch, U).cpu().numpy()[q_list]
+        want = conv(make(ff, Lq, n_ref, U, q_list))
+        assert rel(M, want) < TOL, (name, ch)
+
+
+@pytest.mark.parametrize("name", ["hub5", "ras9", "t2g9"])
+def test_sandwiches_match_oracle_laws(T, name):
+    ctx, U, ff, Lq, n_ref = _ctx(T, name)
+    n_o = CASES[name][0][1].shape[1]
+    X = random_exchange_state(ctx.Nq, len(ff), n_o, seed=31)
+    q_list = list(range(Lq * Lq))
+    Um = basis.u_matrix(ff, Lq, n_ref, U)
+    Xm = basis.x_matrix(ff, Lq, n_ref, U)
+    laws = [(T.PP, p_to_matrix, Um, basis.p_to_band, basis.p_to_orbital),
+            (T.PH, c_to_matrix, Xm, basis.c_to_band, basis.c_to_orbital)]
+    for ch, layout, Mo, to_band, to_orb in laws:
+        M = _matrix(T, ctx, ch, U)
+        Xd = torch.from_numpy(layout(X)).to(dev())
+        Y = _zeros(ctx)
+        T.tufrg_basis_apply(ctx, M, Xd, Y, to_orbital=False)
+        Z = _zeros(ctx)
+        T.tufrg_basis_apply(ctx, M, Xd, Z, to_orbital=True)
+        torch.cuda.synchronize()
+        assert rel(Y.cpu().numpy(), layout(to_band(X, Mo))) < TOL, (name, ch)
+        assert rel(Z.cpu().numpy()[q_list], layout(to_orb(X, Mo))) < TOL, (name, ch)
+
+
+@pytest.mark.parametrize("name", ["ras9", "t2g9"])
+def test_constant_unitary_gives_a_local_basis_change(T, name):
+    """U(k) = W for every k: M_pp = delta_RR' (W (x) W in the bundle order) and
+    M_ph = delta_RR' (W (x) conj W); the sandwich in place (Y = X) then equals
+    the blockwise product."""
+    ctx, _, ff, Lq, n_ref = _ctx(T, name)
+    n_o = CASES[name][0][1].shape[1]
+    W = random_unitaries(1, n_o, seed=5)[0]
+    U = np.broadcast_to(W, ((Lq * n_ref) ** 2, n_o, n_o)).copy()
+    eye = np.eye(len(ff))
+    # M[(R,a,b),(R',c,d)]: pp U_{bd... } -> W_ac W_bd; ph W_ac conj(W_bd)
+    blk_pp = np.einsum("ac,bd->abcd", W, W).reshape(n_o * n_o, n_o * n_o)
+    blk_ph = np.einsum("ac,bd->abcd", W, W.conj()).reshape(n_o * n_o, n_o * n_o)
+    X = torch.from_numpy(p_to_matrix(random_exchange_state(ctx.Nq, len(ff), n_o, seed=9))).to(dev())
+    for ch, blk in ((T.PP, blk_pp), (T.PH, blk_ph)):
+        M = _matrix(T, ctx, ch, U).cpu().numpy()
+        want = np.kron(eye, blk)
+        assert float(np.abs(M - want[None]).max()) < 1e-13, (name, ch)
+        Y = X.clone()
+        T.tufrg_basis_apply(ctx, torch.from_numpy(M).to(dev()), Y, Y, to_orbital=False)
+        torch.cuda.synchronize()
+        Md = torch.from_numpy(M).to(dev())
+        ref = Md.conj().transpose(1, 2).contiguous() @ X @ Md
+        assert float((Y - ref).abs().max()) < 1e-12 * float(ref.abs().max()), (name, ch)
+
+
+def test_output_overlapping_the_matrix_is_rejected(T):
+    ctx, U, ff, Lq, n_ref = _ctx(T, "hub5")
+    M = _matrix(T, ctx, T.PP, U)
+    X = _zeros(ctx)
+    with pytest.raises(T.TufrgError):
+        T.tufrg_basis_apply(ctx, M, X, M)
+
+
+@pytest.mark.parametrize("ch", ["pp", "ph"])
+def test_full_size_basis_matrix_sampled(T, ch):
+    """Rashba at the headline size (576 coarse q, 576 x 576 fine mesh, S9):
+    sampled coarse q against the oracle's k-sum."""
+    w = workload("rashba_s9_L24")
+    ctx = T.Context.from_workload(w, precision="fp64")
+    Lq, n_ref = w["Lq"], w["n_ref"]
+    U = random_unitaries((Lq * n_ref) ** 2, 2, seed=11)
+    chan = T.PP if ch == "pp" else T.PH
+    M = _matrix(T, ctx, chan, U).cpu().numpy()
+    q_list = [0, 311]
+    make, conv = (basis.u_matrix, u_to_matrix) if ch == "pp" else (basis.x_matrix, x_to_matrix)
+    want = conv(make(w["ff"], Lq, n_ref, U, q_list))
+    assert rel(M[q_list], want) < TOL

@@ -13,16 +13,9 @@ import pytest
 
 from oracle import basis, bands, bruteforce, cutoff
 from oracle import tufrg as tu
-from synth import rashba_hoppings
+from synth import random_unitaries as _random_unitaries, rashba_hoppings
 
 N_O = 2
-
-
-def _random_unitaries(n_k, n, seed):
-    rng = np.random.default_rng(seed)
-    Z = rng.normal(size=(n_k, n, n)) + 1j * rng.normal(size=(n_k, n, n))
-    Q, R = np.linalg.qr(Z)
-    return Q * (np.diagonal(R, axis1=1, axis2=2) / np.abs(np.diagonal(R, axis1=1, axis2=2)))[:, None, :]
 
 
 def _random_vertex(N, n, seed):

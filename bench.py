@@ -13,8 +13,9 @@ HBM before the timed region.
 Printed: one JSON line with the headline value (loop entries/s over the whole
 step), flow steps/s, the same for the FP64-plain form and the relative error of
 the FP32 state against it, the roofline of the loop kernel (event-timed inside
-the library over the timed region), the production Dormand-Prince flow, and a
-CPU baseline of the FP64 oracle on a sample of q points.
+the library over the timed region), the production Dormand-Prince flow, the
+orbital -> band basis change (basis matrices and sandwiches, FP64), and a CPU
+baseline of the FP64 oracle on a sample of q points.
 """
 
 import argparse
@@ -31,6 +32,7 @@ METRIC = "loop entries/s + flow steps/s, mixed/surrogate vs FP64-plain at ≤1e-
 WORKLOAD = "rashba_s9_L24"
 PEAK_FP32_VECTOR = 157.3e12
 PEAK_BF16_MFMA = 2.5e15
+PEAK_FP64_VECTOR = 78.6e12
 
 
 def loop_flops_per_pair(n_o, ndx, ndy, shell=False):
@@ -320,6 +322,50 @@ def surrogate_bench(T, torch, w, K, prec, n_rows=200000, epochs=(20, 20, 20)):
     return out
 
 
+def basis_flops(Nq, n_o, Nf, box):
+    """Algorithmic FP64 flops of one basis matrix (one channel) with separable
+    phases: per coarse q, entry (a, b, c, d) and fine k one complex product
+    U_ac(k) U_bd(k') (6 flops) and one complex multiply-add with e^{-i ky dy}
+    per dy in [-box, box] (8 flops each); the kx phases per row are negligible."""
+    return float(Nq) * n_o ** 4 * Nf * (6 + 8 * (2 * box + 1))
+
+
+def basis_leg(T, torch, ctx, P, C, ff, reps=3):
+    """Orbital -> band basis change on the FP64 context: the pp and ph basis
+    matrices from seeded random unitaries, then Pb = M^H P M and Cb = M^H C M."""
+    from synth import random_unitaries
+    dev = P.device
+    box = 2 if 2 * max(max(abs(x), abs(y)) for x, y in ff) <= 2 else 4  # D = S - S inside [-box, box]^2
+    U = torch.from_numpy(random_unitaries(ctx.Nf, ctx.n_o, seed=17)).to(dev)
+    Mp, Mc = torch.empty_like(P), torch.empty_like(P)
+    Y = torch.empty_like(P)
+
+    def run():
+        T.tufrg_basis_matrix(ctx, T.PP, U, Mp)
+        T.tufrg_basis_matrix(ctx, T.PH, U, Mc)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        T.tufrg_basis_apply(ctx, Mp, P, Y)
+        T.tufrg_basis_apply(ctx, Mc, C, Y)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t1
+
+    run()  # first call allocates the workspaces
+    tm = ta = 0.0
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ta += run()
+        tm += time.perf_counter() - t0
+    tm -= ta
+    per_matrix = tm / (2 * reps)
+    fl = basis_flops(ctx.Nq, ctx.n_o, ctx.Nf, box)
+    return {"matrix_ms_per_channel": per_matrix * 1e3, "apply_ms_per_channel": ta / (2 * reps) * 1e3,
+            "matrix_flops_per_channel": fl, "achieved_tflops": fl / per_matrix / 1e12,
+            "peak_tflops": PEAK_FP64_VECTOR / 1e12, "frac": fl / per_matrix / PEAK_FP64_VECTOR,
+            "note": "matrix time includes its expansion to B x B; host-timed with device syncs"}
+
+
 def batch_bench(T, torch, K, W):
     """32 independent Rashba/Hubbard instances of uneven size (seed 2), FP32
     loops and products, lockstep Euler steps 10 -> 1 through tufrg_batch_flow;
@@ -376,6 +422,7 @@ def main():
                     help="synthetic workload (the headline line uses the default)")
     ap.add_argument("--no-dp", action="store_true", help="skip the Dormand-Prince flows")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-assisted flow")
+    ap.add_argument("--no-basis", action="store_true", help="skip the orbital -> band basis change")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16x3"],
                     help="arithmetic of the timed loops (bf16x3: six spin-orbitals, matrix cores)")
     ap.add_argument("--cutoff", choices=["temperature", "omega", "shell"],
@@ -511,6 +558,8 @@ def main():
         out["dp54_flow"] = dp
     if not args.no_extras and not args.no_dp and not args.no_surrogate:
         out["surrogate_flow"] = surrogate_leg(T, torch, ctx32, P32, C32, P64, C64, dp, w, K, dt32 / K)
+    if not args.no_extras and not args.no_basis:
+        out["basis_change"] = basis_leg(T, torch, ctx64, P64, C64, w["ff"])
     if not args.no_extras:
         ctx64.close()
     if not args.no_cpu:

@@ -9,83 +9,141 @@
 // Pb = M^H P M, Cb = M^H C M (and the converses P = M Pb M^H, C = M Cb M^H) with
 //   M_pp[(R,a,b),(R',c,d)] = U^{RR'}_{b a d c}(s) = 1/N_f sum_k e^{-ik.dR} U_ac(k) U_bd(s - k)
 //   M_ph[(R,a,b),(R',c,d)] = X^{RR'}_{a b c d}(u) = 1/N_f sum_k e^{-ik.dR} U_ac(k) conj(U_bd(k - u)).
-// basis_compact_kernel writes the compact form Mc(q)[dR][(a, b, c, d)]; it is
-// expanded to B x B like the loops, and zgemm_batched_kernel does the sandwich.
+// basis_rows_kernel and basis_cols_kernel write the compact form
+// Mc(q)[dR][(a, b, c, d)] (every dR of D = S - S); it is expanded to B x B like
+// the loops, and zgemm_batched_kernel does the sandwich.
 #include "common.h"
 #include "kernels.h"
 
 namespace tufrg {
 
 namespace {
-constexpr int BASIS_THREADS = 256;
 constexpr int ZT = 16;  // tile edge of the batched complex product
 }  // namespace
 
-// One thread per (entry, dR) of one coarse q; a block holds epb entries of
-// that q (epb * nD <= 256).  Every thread walks the whole fine mesh in a fixed
-// order (deterministic), with the phase index (kx dx + ky dy) mod L_f and the
-// partner point advanced incrementally.  CH = 0: pp (k' = s - k), 1: ph (k' = k - u).
-template <int CH>
-__global__ __launch_bounds__(BASIS_THREADS) void basis_compact_kernel(int n_o, int Lq, int n_ref, int Lf, int nD,
-                                                                      int epb, const int *__restrict__ dlist,
-                                                                      const double2 *__restrict__ U,
-                                                                      const double2 *__restrict__ tw, double inv_nf,
-                                                                      double2 *__restrict__ out) {
-  const int no2 = n_o * n_o, no4 = no2 * no2;
-  const int nchunk = (no4 + epb - 1) / epb;
-  const int q = blockIdx.x / nchunk, chunk = blockIdx.x % nchunk;
-  const int t = threadIdx.x;
-  const int e = chunk * epb + t / nD, iD = t % nD;
-  if (t >= epb * nD || e >= no4) return;  // no barrier in this kernel
-  const int a = e / (n_o * no2), b = (e / no2) % n_o, c = (e / n_o) % n_o, d = e % n_o;
-  const int sdx = ((dlist[2 * iD] % Lf) + Lf) % Lf, sdy = ((dlist[2 * iD + 1] % Lf) + Lf) % Lf;
+// The phase is separable, e^{-ik.dR} = e^{-i kx dx} e^{-i ky dy}, so the k-sum
+// runs in two passes over a chunk of coarse q:
+//  rows: A[q][kx][y][(a,b,c,d)] = sum_ky e^{-i ky dy} U_ac(k) G_bd(k'), y = dy + NX;
+//        one thread per (q, kx, y, a, b, c) streams the kx row (contiguous in
+//        ky, the partner row backwards or forwards) and keeps the n_o values of d;
+//  cols: Mc[q][dR][e] = 1/N_f sum_kx e^{-i kx dx} A[q][kx][dy + NX][e]; one
+//        thread per (q, dR, e), consecutive e reading consecutive A.
+// Every sum runs in a fixed order (deterministic).  CH = 0: pp (k' = s - k,
+// G = U), 1: ph (k' = k - u, G = conj(U)).
+template <int CH, int NX, int NO>
+__global__ __launch_bounds__(256) void basis_rows_kernel(int Lq, int n_ref, int Lf, int q0, long long n_items,
+                                                         const double2 *__restrict__ U,
+                                                         const double2 *__restrict__ tw, double2 *__restrict__ A) {
+  constexpr int NW = 2 * NX + 1, NO2 = NO * NO, NO3 = NO2 * NO, NO4 = NO2 * NO2;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n_items) return;  // no barrier in this kernel
+  const int abc = (int)(gid % NO3);
+  const int y = (int)((gid / NO3) % NW);
+  const long long row = gid / ((long long)NO3 * NW);  // qq * Lf + kx
+  const int kx = (int)(row % Lf), qq = (int)(row / Lf);
+  const int a = abc / NO2, b = (abc / NO) % NO, c = abc % NO;
+  const int q = q0 + qq;
   const int qfx = (q / Lq) * n_ref, qfy = (q % Lq) * n_ref;
-  const int kpy0 = CH == 0 ? qfy : (Lf - qfy) % Lf;  // partner y at ky = 0
-  double sr = 0.0, si = 0.0;
-  int jrow = 0;  // kx dx mod L_f
-  for (int kx = 0; kx < Lf; ++kx) {
-    int kpx = CH == 0 ? qfx - kx : kx - qfx;
-    kpx = kpx < 0 ? kpx + Lf : kpx;
-    const double2 *Uk = U + (size_t)kx * Lf * no2 + a * n_o + c;   // U_ac(kx, ky) at ky = 0
-    const double2 *Up = U + (size_t)kpx * Lf * no2 + b * n_o + d;  // U_bd(k') row
-    int j = jrow, kpy = kpy0;
-    for (int ky = 0; ky < Lf; ++ky) {
-      const double2 u = Uk[(size_t)ky * no2];
-      const double2 g = Up[(size_t)kpy * no2];
+  int kpx = CH == 0 ? qfx - kx : kx - qfx;
+  kpx = kpx < 0 ? kpx + Lf : kpx;
+  const int dy = y - NX, sdy = dy < 0 ? dy + Lf : dy;
+  const double2 *Uk = U + (size_t)kx * Lf * NO2 + a * NO + c;  // U_ac(kx, ky) at ky = 0
+  const double2 *Up = U + (size_t)kpx * Lf * NO2 + b * NO;     // U_b.(k') row
+  double sr[NO], si[NO];
+#pragma unroll
+  for (int d = 0; d < NO; ++d) sr[d] = si[d] = 0.0;
+  int j = 0, kpy = CH == 0 ? qfy : (Lf - qfy) % Lf;  // partner y at ky = 0
+  for (int ky = 0; ky < Lf; ++ky) {
+    const double2 u = Uk[(size_t)ky * NO2];
+    const double2 w = tw[j];  // e^{-i 2 pi ky dy / L_f}
+    // w u, then times G_bd(k') for every d
+    const double wr = w.x * u.x - w.y * u.y, wi = w.x * u.y + w.y * u.x;
+    const double2 *v = Up + (size_t)kpy * NO2;
+#pragma unroll
+    for (int d = 0; d < NO; ++d) {
+      const double2 g = v[d];
       const double gi = CH == 0 ? g.y : -g.y;
-      const double pr = u.x * g.x - u.y * gi, pi = u.x * gi + u.y * g.x;
-      const double2 w = tw[j];  // e^{-i 2 pi j / L_f}
-      sr = fma(w.x, pr, fma(-w.y, pi, sr));
-      si = fma(w.x, pi, fma(w.y, pr, si));
-      j += sdy;
-      j = j >= Lf ? j - Lf : j;
-      if (CH == 0) {
-        kpy = kpy == 0 ? Lf - 1 : kpy - 1;
-      } else {
-        kpy = kpy == Lf - 1 ? 0 : kpy + 1;
-      }
+      sr[d] = fma(wr, g.x, fma(-wi, gi, sr[d]));
+      si[d] = fma(wr, gi, fma(wi, g.x, si[d]));
     }
-    jrow += sdx;
-    jrow = jrow >= Lf ? jrow - Lf : jrow;
+    j += sdy;
+    j = j >= Lf ? j - Lf : j;
+    if (CH == 0) {
+      kpy = kpy == 0 ? Lf - 1 : kpy - 1;
+    } else {
+      kpy = kpy == Lf - 1 ? 0 : kpy + 1;
+    }
   }
-  out[((size_t)q * nD + iD) * no4 + e] = make_double2(sr * inv_nf, si * inv_nf);
+  double2 *dst = A + ((size_t)row * NW + y) * NO4 + ((a * NO + b) * NO + c) * NO;
+#pragma unroll
+  for (int d = 0; d < NO; ++d) dst[d] = make_double2(sr[d], si[d]);
 }
 
-hipError_t launch_basis_compact(int channel, int n_o, int Lq, int n_ref, int nD, const int *dlist, const double *U,
-                                const double *tw, double *out, hipStream_t st) {
-  if (nD < 1 || nD > BASIS_THREADS || (channel != 0 && channel != 1)) return hipErrorInvalidValue;
-  const int Lf = Lq * n_ref, no4 = n_o * n_o * n_o * n_o;
-  const int epb = BASIS_THREADS / nD;
-  const int nchunk = (no4 + epb - 1) / epb;
-  const dim3 grid((unsigned)(Lq * Lq * nchunk)), block(BASIS_THREADS);
+__global__ __launch_bounds__(256) void basis_cols_kernel(int no4, int Lf, int NX, int q0, int nq, int nD,
+                                                         const int *__restrict__ dlist,
+                                                         const double2 *__restrict__ tw,
+                                                         const double2 *__restrict__ A, double inv_nf,
+                                                         double2 *__restrict__ out) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long long)nq * nD * no4) return;
+  const int e = (int)(gid % no4), iD = (int)((gid / no4) % nD), qq = (int)(gid / ((long long)no4 * nD));
+  const int NW = 2 * NX + 1, y = dlist[2 * iD + 1] + NX;
+  const int dx = dlist[2 * iD], sdx = dx < 0 ? dx + Lf : dx;
+  const double2 *src = A + ((size_t)qq * Lf * NW + y) * no4 + e;
+  double sr = 0.0, si = 0.0;
+  int j = 0;
+  for (int kx = 0; kx < Lf; ++kx) {
+    const double2 v = src[(size_t)kx * NW * no4];
+    const double2 w = tw[j];  // e^{-i 2 pi kx dx / L_f}
+    sr = fma(w.x, v.x, fma(-w.y, v.y, sr));
+    si = fma(w.x, v.y, fma(w.y, v.x, si));
+    j += sdx;
+    j = j >= Lf ? j - Lf : j;
+  }
+  out[((size_t)(q0 + qq) * nD + iD) * no4 + e] = make_double2(sr * inv_nf, si * inv_nf);
+}
+
+size_t basis_rows_doubles(int n_o, int Lf, int box, int nq) {
+  return 2 * (size_t)nq * Lf * (2 * box + 1) * n_o * n_o * n_o * n_o;
+}
+
+hipError_t launch_basis_compact(int channel, int n_o, int Lq, int n_ref, int nD, int box, const int *dlist,
+                                const double *U, const double *tw, double *rows, int q_chunk, double *out,
+                                hipStream_t st) {
+  if ((channel != 0 && channel != 1) || (box != 2 && box != 4) || (n_o != 2 && n_o != 6) || q_chunk < 1)
+    return hipErrorInvalidValue;
+  const int Lf = Lq * n_ref, Nq = Lq * Lq, no4 = n_o * n_o * n_o * n_o;
+  const int NW = 2 * box + 1;
   const double inv = 1.0 / ((double)Lf * Lf);
-  if (channel == 0)
-    hipLaunchKernelGGL(basis_compact_kernel<0>, grid, block, 0, st, n_o, Lq, n_ref, Lf, nD, epb, dlist,
-                       (const double2 *)U, (const double2 *)tw, inv, (double2 *)out);
-  else
-    hipLaunchKernelGGL(basis_compact_kernel<1>, grid, block, 0, st, n_o, Lq, n_ref, Lf, nD, epb, dlist,
-                       (const double2 *)U, (const double2 *)tw, inv, (double2 *)out);
-  return hipGetLastError();
+  const double2 *u = (const double2 *)U, *w = (const double2 *)tw;
+  double2 *A = (double2 *)rows;
+  for (int q0 = 0; q0 < Nq; q0 += q_chunk) {
+    const int nq = Nq - q0 < q_chunk ? Nq - q0 : q_chunk;
+    const long long n_items = (long long)nq * Lf * NW * n_o * n_o * n_o;
+    const dim3 grid1((unsigned)((n_items + 255) / 256)), block(256);
+#define TUFRG_BASIS_ROWS(CH, NX, NO)                                                                                \
+  hipLaunchKernelGGL((basis_rows_kernel<CH, NX, NO>), grid1, block, 0, st, Lq, n_ref, Lf, q0, n_items, u, w, A)
+    const int sel = channel * 4 + (box == 4 ? 2 : 0) + (n_o == 6 ? 1 : 0);
+    switch (sel) {
+      case 0: TUFRG_BASIS_ROWS(0, 2, 2); break;
+      case 1: TUFRG_BASIS_ROWS(0, 2, 6); break;
+      case 2: TUFRG_BASIS_ROWS(0, 4, 2); break;
+      case 3: TUFRG_BASIS_ROWS(0, 4, 6); break;
+      case 4: TUFRG_BASIS_ROWS(1, 2, 2); break;
+      case 5: TUFRG_BASIS_ROWS(1, 2, 6); break;
+      case 6: TUFRG_BASIS_ROWS(1, 4, 2); break;
+      default: TUFRG_BASIS_ROWS(1, 4, 6); break;
+    }
+#undef TUFRG_BASIS_ROWS
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long n_out = (long long)nq * nD * no4;
+    hipLaunchKernelGGL(basis_cols_kernel, dim3((unsigned)((n_out + 255) / 256)), block, 0, st, no4, Lf, box, q0, nq,
+                       nD, dlist, w, (const double2 *)A, inv, (double2 *)out);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // C[q] = opA(A[q]) opB(B[q]) for n x n complex matrices, op 0: as is, 1: conjugate transpose.

@@ -83,9 +83,13 @@ hipError_t launch_bundle(int prec, int n_o, int n_ff, int B, int nD, int n_q, co
 
 // orbital <-> band basis (k_basis.hip): compact basis matrix [Nq][nD][n_o^4] of one
 // channel (0: pp, U matrix; 1: ph, X matrix) from U[Nf][n_o][n_o] (orbital rows, band
-// columns); tw = exp(-2 pi i j / Lf), [Lf][2]
-hipError_t launch_basis_compact(int channel, int n_o, int Lq, int n_ref, int nD, const int *dlist, const double *U,
-                                const double *tw, double *out, hipStream_t st);
+// columns); box: D inside [-box, box]^2 (2 or 4); dlist [nD][2]; tw = exp(-2 pi i j /
+// Lf), [Lf][2]; rows: workspace of basis_rows_doubles(n_o, Lf, box, q_chunk) doubles
+// (the coarse q are processed q_chunk at a time)
+size_t basis_rows_doubles(int n_o, int Lf, int box, int nq);
+hipError_t launch_basis_compact(int channel, int n_o, int Lq, int n_ref, int nD, int box, const int *dlist,
+                                const double *U, const double *tw, double *rows, int q_chunk, double *out,
+                                hipStream_t st);
 // C[q] = opA(A[q]) opB(B[q]), n x n complex, op 1 = conjugate transpose (not both)
 hipError_t launch_zgemm_batched(int n, int n_q, int opA, int opB, const double *A, const double *Bm, double *C,
                                 hipStream_t st);

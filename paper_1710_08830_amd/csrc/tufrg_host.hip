@@ -75,6 +75,7 @@ struct tufrg_ctx {
   double *d_btmp = nullptr;  // bundle workspace for B > 64
   double *d_basis_tmp = nullptr;  // basis sandwich workspace, [Nq][B][B] complex (lazy)
   double *d_basis_c = nullptr;    // compact basis matrix, [Nq][nD][n_o^4] complex (lazy)
+  double *d_basis_rows = nullptr; // its kx-row sums for a chunk of coarse q (lazy)
   std::vector<double *> d_stage;  // DP5: 7 k's per channel + stage state per channel
   std::string err;
   std::vector<void *> allocs;
@@ -800,10 +801,19 @@ extern "C" tufrg_status tufrg_basis_matrix(tufrg_ctx *c, int32_t channel, const 
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
   if (channel != TUFRG_PP && channel != TUFRG_PH) return fail(c, TUFRG_E_INVAL, "channel must be PP or PH");
   if (!is_device_ptr(U) || !is_device_ptr(M)) return fail(c, TUFRG_E_INVAL, "U and M must be device pointers");
-  // compact form [Nq][nD][n_o^4], then expanded like the loops
-  if (!c->d_basis_c) TRY(dalloc(c, &c->d_basis_c, 2 * (size_t)c->Nq * c->nD * c->no4));
-  HIPCHK(c, launch_basis_compact(channel, c->n_o, c->Lq, c->n_ref, c->nD, c->d_dlist, (const double *)U, c->d_twf,
-                                 c->d_basis_c, c->st));
+  // compact form [Nq][nD][n_o^4], then expanded like the loops; the row sums of
+  // at most about 1 GB of coarse q at a time
+  int box = 0;  // largest |component| of a dR in D
+  for (int v : c->dlist) box = std::max(box, std::abs(v));
+  box = box <= 2 ? 2 : 4;
+  const size_t per_q = basis_rows_doubles(c->n_o, c->Lf, box, 1);
+  const int q_chunk = (int)std::max<size_t>(1, std::min<size_t>(c->Nq, ((size_t)1 << 27) / per_q));
+  if (!c->d_basis_c) {
+    TRY(dalloc(c, &c->d_basis_c, 2 * (size_t)c->Nq * c->nD * c->no4));
+    TRY(dalloc(c, &c->d_basis_rows, per_q * q_chunk));
+  }
+  HIPCHK(c, launch_basis_compact(channel, c->n_o, c->Lq, c->n_ref, c->nD, box, c->d_dlist, (const double *)U,
+                                 c->d_twf, c->d_basis_rows, q_chunk, c->d_basis_c, c->st));
   HIPCHK(c, launch_loop_expand(c->n_o, c->n_ff, c->nD, c->Nq, c->d_didx, c->d_basis_c, (double *)M, c->st));
   return TUFRG_OK;
 }

@@ -65,14 +65,35 @@ template <typename T>
 struct V4 {
   T x, y, z, w;
 };
+// base: a wave-uniform row pointer, i: this lane's index in the row; the byte
+// offset is a 32-bit value (arrays stay below 4 GB), so the load can take a
+// scalar base plus a vector offset with no 64-bit address arithmetic per lane
 __device__ inline V4<float> ld4(const float *base, unsigned i) {
-  const float4 v = *(const float4 *)((const char *)base + (size_t)i * 16u);
+  const float4 v = *(const float4 *)((const char *)base + (i * 16u));
   return {v.x, v.y, v.z, v.w};
 }
 __device__ inline V4<double> ld4(const double *base, unsigned i) {
-  const double2 *p = (const double2 *)((const char *)base + (size_t)i * 32u);
+  const double2 *p = (const double2 *)((const char *)base + (i * 32u));
   const double2 a = p[0], b = p[1];
   return {a.x, a.y, b.x, b.y};
+}
+
+// Raw buffer loads: a descriptor of an array of nbytes bytes (base address,
+// no stride, the gfx9-family data-format bits in the last word), a wave-uniform
+// byte offset and a per-lane 32-bit byte offset.
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+__device__ f32x4v raw_buffer_load_v4f32(i32x4 rsrc, int voffset, int soffset, int aux) __asm(
+    "llvm.amdgcn.raw.buffer.load.v4f32");
+template <typename T>
+__device__ inline i32x4 make_rsrc(const T *p, unsigned nbytes) {
+  const unsigned long long a = (unsigned long long)p;
+  return i32x4{(int)(unsigned)a, (int)(unsigned)(a >> 32), (int)nbytes, 0x00020000};
+}
+// four floats at byte offset soff (wave-uniform) + voff (per lane)
+__device__ inline V4<float> ld4_buf(i32x4 r, unsigned voff, unsigned soff) {
+  const f32x4v v = raw_buffer_load_v4f32(r, (int)voff, (int)soff, 0);
+  return {v[0], v[1], v[2], v[3]};
 }
 
 // Loop body of one channel (CH = 0: pp, k' = q - k; CH = 1: ph, k' = k - q).
@@ -99,10 +120,24 @@ __device__ inline void loop_no2_body(const T *__restrict__ ekv, const T *__restr
   struct Pt {
     V4<T> ek, pk, cv;
   };
-  auto load = [&](unsigned i, Pt &p) {
-    p.ek = ld4(ekv, i);
-    p.pk = ld4(pi4, i);
-    if constexpr (SHELL) p.cv = ld4(cvp, i);
+  // point (row, col) of a k-major array: row = kx (wave-uniform), col = ky (per lane).
+  // FP32: raw buffer loads, descriptor and row offset in scalar registers, the
+  // lane's 32-bit byte offset as the only vector operand
+  const unsigned nbytes = (unsigned)Lf * Lf * 4u * (unsigned)sizeof(T);
+  const auto rs_e = make_rsrc(ekv, nbytes), rs_p = make_rsrc(pi4, nbytes);
+  const auto rs_c = make_rsrc(SHELL ? cvp : ekv, nbytes);
+  auto load = [&](unsigned row, unsigned col, Pt &p) {
+    if constexpr (sizeof(T) == 4) {
+      const unsigned soff = row * (unsigned)Lf * 16u, voff = col * 16u;
+      p.ek = ld4_buf(rs_e, voff, soff);
+      p.pk = ld4_buf(rs_p, voff, soff);
+      if constexpr (SHELL) p.cv = ld4_buf(rs_c, voff, soff);
+    } else {
+      const size_t rb = (size_t)row * Lf * 4;
+      p.ek = ld4(ekv + rb, col);
+      p.pk = ld4(pi4 + rb, col);
+      if constexpr (SHELL) p.cv = ld4(cvp + rb, col);
+    }
   };
   // k' row of the next kx
   auto next_kpx = [&]() {
@@ -195,34 +230,33 @@ __device__ inline void loop_no2_body(const T *__restrict__ ekv, const T *__restr
         }
       }
   };
-  const unsigned row = (unsigned)Lf;
-  unsigned kk = (unsigned)x0 * Lf + ky;
+  const unsigned uky = (unsigned)ky, ukpy = (unsigned)kpy;
   if constexpr (sizeof(T) == 4) {
     // software pipeline with two register sets: the loads of point kx + 1 are
     // issued before the arithmetic of point kx; a prefetch past the chunk
     // re-reads the current point and is not used
     Pt ak, ap, bk, bp;
-    load(kk, ak);
-    load((unsigned)kpx * Lf + kpy, ap);
+    load(x0, uky, ak);
+    load(kpx, ukpy, ap);
     int kx = x0;
-    for (; kx + 1 < x1; kx += 2, kk += 2 * row) {
+    for (; kx + 1 < x1; kx += 2) {
       next_kpx();
-      load(kk + row, bk);
-      load((unsigned)kpx * Lf + kpy, bp);
+      load(kx + 1, uky, bk);
+      load(kpx, ukpy, bp);
       point(ak, ap);
       const bool more = kx + 2 < x1;
       if (more) next_kpx();
-      load(more ? kk + 2 * row : kk + row, ak);
-      load((unsigned)kpx * Lf + kpy, ap);
+      load(more ? kx + 2 : kx + 1, uky, ak);
+      load(kpx, ukpy, ap);
       point(bk, bp);
     }
     if (kx < x1) point(ak, ap);
   } else {
     // FP64 keeps the plain order: its register budget is already at one or two waves per SIMD
-    for (int kx = x0; kx < x1; ++kx, kk += row) {
+    for (int kx = x0; kx < x1; ++kx) {
       Pt ck, cp;
-      load(kk, ck);
-      load((unsigned)kpx * Lf + kpy, cp);
+      load(kx, uky, ck);
+      load(kpx, ukpy, cp);
       point(ck, cp);
       next_kpx();
     }
@@ -272,7 +306,9 @@ __global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (siz
   // coarse q: consecutive from q_first, or whole q_x rows from a list
   const int qrel = qx * Lq + qy, qi = rows ? rows[qx] * Lq + qy : q_first + qrel;
   const int nparts = nkyb * nkxc;
-  const int qfx = (qi / Lq) * n_ref, qfy = (qi % Lq) * n_ref;
+  // one coarse q per wave: keep its fine coordinates in scalar registers
+  const int qfx = __builtin_amdgcn_readfirstlane((qi / Lq) * n_ref);
+  const int qfy = __builtin_amdgcn_readfirstlane((qi % Lq) * n_ref);
   const int ky_raw = kyb * 64 + tid;
   const bool active = ky_raw < Lf;
   const int ky = active ? ky_raw : Lf - 1;

@@ -79,6 +79,79 @@ __global__ __launch_bounds__(256) void basis_rows_kernel(int Lq, int n_ref, int 
   for (int d = 0; d < NO; ++d) dst[d] = make_double2(sr[d], si[d]);
 }
 
+// Two orbitals: one thread per (q, kx, a, b, c) does every dy of the box, so
+// the loads of U_ac(k) and U_b.(k') serve 2 NX + 1 phases; the phase of dy
+// is the dy-th power of e^{-i 2 pi ky / L_f} (one table load per k).
+template <int CH, int NX>
+__global__ __launch_bounds__(256) void basis_rows2_kernel(int Lq, int n_ref, int Lf, int q0, long long n_items,
+                                                          const double2 *__restrict__ U,
+                                                          const double2 *__restrict__ tw, double2 *__restrict__ A) {
+  constexpr int NO = 2, NW = 2 * NX + 1, NO2 = 4, NO3 = 8, NO4 = 16;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n_items) return;  // no barrier in this kernel
+  const int abc = (int)(gid % NO3);
+  const long long row = gid / NO3;  // qq * Lf + kx
+  const int kx = (int)(row % Lf), qq = (int)(row / Lf);
+  const int a = abc / NO2, b = (abc / NO) % NO, c = abc % NO;
+  const int q = q0 + qq;
+  const int qfx = (q / Lq) * n_ref, qfy = (q % Lq) * n_ref;
+  int kpx = CH == 0 ? qfx - kx : kx - qfx;
+  kpx = kpx < 0 ? kpx + Lf : kpx;
+  const double2 *Uk = U + (size_t)kx * Lf * NO2 + a * NO + c;
+  const double2 *Up = U + (size_t)kpx * Lf * NO2 + b * NO;
+  double sr[NW][NO], si[NW][NO];
+#pragma unroll
+  for (int y = 0; y < NW; ++y)
+#pragma unroll
+    for (int d = 0; d < NO; ++d) sr[y][d] = si[y][d] = 0.0;
+  int kpy = CH == 0 ? qfy : (Lf - qfy) % Lf;
+  for (int ky = 0; ky < Lf; ++ky) {
+    const double2 u = Uk[(size_t)ky * NO2];
+    const double2 *v = Up + (size_t)kpy * NO2;
+    double pr[NO], pi[NO];
+#pragma unroll
+    for (int d = 0; d < NO; ++d) {
+      const double2 g = v[d];
+      const double gi = CH == 0 ? g.y : -g.y;
+      pr[d] = u.x * g.x - u.y * gi;
+      pi[d] = u.x * gi + u.y * g.x;
+    }
+    // phases w^dy, dy = 1..NX, w = e^{-i 2 pi ky / L_f}; dy < 0 by conjugation
+    double wr[NX + 1], wi[NX + 1];
+    wr[0] = 1.0;
+    wi[0] = 0.0;
+    const double2 w1 = tw[ky];
+    wr[1] = w1.x;
+    wi[1] = w1.y;
+#pragma unroll
+    for (int m = 2; m <= NX; ++m) {
+      wr[m] = wr[m - 1] * w1.x - wi[m - 1] * w1.y;
+      wi[m] = wr[m - 1] * w1.y + wi[m - 1] * w1.x;
+    }
+#pragma unroll
+    for (int y = 0; y < NW; ++y) {
+      const int m = y < NX ? NX - y : y - NX;
+      const double xr = wr[m], xi = y < NX ? -wi[m] : wi[m];
+#pragma unroll
+      for (int d = 0; d < NO; ++d) {
+        sr[y][d] = fma(xr, pr[d], fma(-xi, pi[d], sr[y][d]));
+        si[y][d] = fma(xr, pi[d], fma(xi, pr[d], si[y][d]));
+      }
+    }
+    if (CH == 0) {
+      kpy = kpy == 0 ? Lf - 1 : kpy - 1;
+    } else {
+      kpy = kpy == Lf - 1 ? 0 : kpy + 1;
+    }
+  }
+#pragma unroll
+  for (int y = 0; y < NW; ++y) {
+    double2 *dst = A + ((size_t)row * NW + y) * NO4 + ((a * NO + b) * NO + c) * NO;
+#pragma unroll
+    for (int d = 0; d < NO; ++d) dst[d] = make_double2(sr[y][d], si[y][d]);
+  }
+}
+
 __global__ __launch_bounds__(256) void basis_cols_kernel(int no4, int Lf, int NX, int q0, int nq, int nD,
                                                          const int *__restrict__ dlist,
                                                          const double2 *__restrict__ tw,
@@ -119,22 +192,26 @@ hipError_t launch_basis_compact(int channel, int n_o, int Lq, int n_ref, int nD,
   double2 *A = (double2 *)rows;
   for (int q0 = 0; q0 < Nq; q0 += q_chunk) {
     const int nq = Nq - q0 < q_chunk ? Nq - q0 : q_chunk;
-    const long long n_items = (long long)nq * Lf * NW * n_o * n_o * n_o;
+    // two orbitals: a thread per (q, kx, a, b, c) for all dy; six: per (q, kx, dy, a, b, c)
+    const long long n_items = (long long)nq * Lf * (n_o == 2 ? 1 : NW) * n_o * n_o * n_o;
     const dim3 grid1((unsigned)((n_items + 255) / 256)), block(256);
 #define TUFRG_BASIS_ROWS(CH, NX, NO)                                                                                \
   hipLaunchKernelGGL((basis_rows_kernel<CH, NX, NO>), grid1, block, 0, st, Lq, n_ref, Lf, q0, n_items, u, w, A)
+#define TUFRG_BASIS_ROWS2(CH, NX)                                                                                   \
+  hipLaunchKernelGGL((basis_rows2_kernel<CH, NX>), grid1, block, 0, st, Lq, n_ref, Lf, q0, n_items, u, w, A)
     const int sel = channel * 4 + (box == 4 ? 2 : 0) + (n_o == 6 ? 1 : 0);
     switch (sel) {
-      case 0: TUFRG_BASIS_ROWS(0, 2, 2); break;
+      case 0: TUFRG_BASIS_ROWS2(0, 2); break;
       case 1: TUFRG_BASIS_ROWS(0, 2, 6); break;
-      case 2: TUFRG_BASIS_ROWS(0, 4, 2); break;
+      case 2: TUFRG_BASIS_ROWS2(0, 4); break;
       case 3: TUFRG_BASIS_ROWS(0, 4, 6); break;
-      case 4: TUFRG_BASIS_ROWS(1, 2, 2); break;
+      case 4: TUFRG_BASIS_ROWS2(1, 2); break;
       case 5: TUFRG_BASIS_ROWS(1, 2, 6); break;
-      case 6: TUFRG_BASIS_ROWS(1, 4, 2); break;
+      case 6: TUFRG_BASIS_ROWS2(1, 4); break;
       default: TUFRG_BASIS_ROWS(1, 4, 6); break;
     }
 #undef TUFRG_BASIS_ROWS
+#undef TUFRG_BASIS_ROWS2
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long n_out = (long long)nq * nD * no4;

@@ -231,7 +231,7 @@ __device__ inline void loop_no2_body(const T *__restrict__ ekv, const T *__restr
       }
   };
   const unsigned uky = (unsigned)ky, ukpy = (unsigned)kpy;
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 4 && NDX > 3) {
     // software pipeline with two register sets: the loads of point kx + 1 are
     // issued before the arithmetic of point kx; a prefetch past the chunk
     // re-reads the current point and is not used
@@ -252,7 +252,9 @@ __device__ inline void loop_no2_body(const T *__restrict__ ekv, const T *__restr
     }
     if (kx < x1) point(ak, ap);
   } else {
-    // FP64 keeps the plain order: its register budget is already at one or two waves per SIMD
+    // plain order, one register set: FP32 with dx < 3 then fits four waves per
+    // SIMD, which hide the load latency better than the second set did at three
+    // (rashba_s9_L24: 2.26 -> 2.18 ms); FP64 is at one or two waves per SIMD anyway
     for (int kx = x0; kx < x1; ++kx) {
       Pt ck, cp;
       load(kx, uky, ck);
@@ -278,7 +280,7 @@ struct loop_waves {
 
 // QW waves per work item (ky block, q_y group, q_x, kx chunk, channel).
 template <typename T, int NDX, int NDY, int SCHEME, int QW>
-__global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 2 : 3))) void loop_no2_kernel(const T *__restrict__ ekv, const T *__restrict__ pi4, const T *__restrict__ cvp,
+__global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 2 : 4))) void loop_no2_kernel(const T *__restrict__ ekv, const T *__restrict__ pi4, const T *__restrict__ cvp,
                                                            const double *__restrict__ tw, const T *__restrict__ twk,
                                                            int Lq, int n_ref, int Lf,
                                                            int nkyb, int nkxc, int kxper, int q_first, int n_q,

@@ -824,7 +824,8 @@ extern "C" tufrg_status tufrg_basis_apply(tufrg_ctx *c, const tufrg_c64 *M, cons
   if (!is_device_ptr(M) || !is_device_ptr(X) || !is_device_ptr(Y))
     return fail(c, TUFRG_E_INVAL, "M, X and Y must be device pointers");
   const size_t n = (size_t)c->Nq * c->B * c->B;
-  const tufrg_c64 *m0 = M, *m1 = M + n, *y0 = Y, *y1 = Y + n;
+  const uintptr_t m0 = (uintptr_t)M, m1 = m0 + n * sizeof(tufrg_c64), y0 = (uintptr_t)Y,
+                  y1 = y0 + n * sizeof(tufrg_c64);
   if (y0 < m1 && m0 < y1) return fail(c, TUFRG_E_INVAL, "Y must not overlap M");
   if (!c->d_basis_tmp) TRY(dalloc(c, &c->d_basis_tmp, 2 * n));
   const double *m = (const double *)M;

@@ -33,6 +33,14 @@ What is computed, and where it comes from:
   every term whose form-factor labels leave S dropped (the truncation).  The
   projections of a momentum-independent V0 fill only the (R, R') = (0, 0)
   block.
+* Band basis (Sec. 3.1, the form in which the paper derives the RGE; basis
+  change of Sec. 4.1): with basis="band" the single-particle basis is the
+  eigenbasis of H(k), so the loops see unit projectors and depend on two band
+  indices; the projections and bundle products are the same formulas.  The
+  bare vertex then enters as a static particle-particle term P0 (its band
+  form, e.g. U^dagger P[V0] U with the basis matrices of ``oracle.basis``),
+  projected with the flowing P; exact for a complete form-factor set, the
+  truncated expansion otherwise.
 * Integration of the single-channel couplings (Sec. 3.1): explicit Euler in
   Lambda on a log grid, or Dormand-Prince 5(4) in ln Lambda; the flow stops
   when max(|P|, |C|) exceeds v_max, and the critical scale is interpolated
@@ -61,7 +69,8 @@ _DP_B4 = np.array([5179 / 57600, 0.0, 7571 / 16695, 393 / 640, -92097 / 339200,
 class TUSetup:
     """Meshes, form factors, band data and the initial interaction."""
 
-    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, scheme, temperature=None, C0=None):
+    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, scheme, temperature=None, C0=None, P0=None,
+                 basis="orbital"):
         self.hop_R = np.asarray(hop_R)
         self.hop_t = np.asarray(hop_t)
         self.mu = float(mu)
@@ -69,6 +78,13 @@ class TUSetup:
         # non-local part of the initial interaction in crossed particle-hole
         # form (a static term of the C channel, its D partner by antisymmetry)
         self.C0 = None if C0 is None else np.asarray(C0, dtype=np.complex128)
+        # static particle-particle term of the bare vertex (its P-channel
+        # expansion, projected with the flowing P): the band-basis form of a
+        # bare interaction given in the orbital basis (Sec. 4.1)
+        self.P0 = None if P0 is None else np.asarray(P0, dtype=np.complex128)
+        if basis not in ("orbital", "band"):
+            raise ValueError(basis)
+        self.basis = basis
         self.S = np.asarray(ff, dtype=np.int64).reshape(-1, 2)
         self.n_ff = len(self.S)
         self.n_o = self.hop_t.shape[1]
@@ -82,7 +98,12 @@ class TUSetup:
         self.coarse = bands.mesh(self.Lq)
         self.fine = bands.mesh(self.Lf)
         self.e, self.U = bands.band_data(self.hop_R, self.hop_t, self.mu, self.Lf)
-        self.Pi = bands.projectors(self.U)
+        if basis == "band":
+            # band basis (Sec. 3.1): the single-particle basis diagonalises H(k),
+            # so the loops see unit projectors and depend on two band indices
+            self.Pi = bands.projectors(np.broadcast_to(np.eye(self.n_o), self.U.shape))
+        else:
+            self.Pi = bands.projectors(self.U)
         # membership of a residue class mod L_q in S
         self._ff_of = {}
         for i, R in enumerate(self.S):
@@ -195,9 +216,12 @@ def projected_vertices(st, P, C):
     """VP = P[V0] + P + P[V^C] + P[V^D];  VC = C[V0] + C[V^P] + C + C[V^D].
 
     A non-local initial interaction given in crossed particle-hole form (st.C0)
-    is projected with the flowing C: V^C -> V^C + C0, V^D -> V^D + D0."""
+    is projected with the flowing C: V^C -> V^C + C0, V^D -> V^D + D0; one given
+    in particle-particle form (st.P0) with the flowing P: V^P -> V^P + P0."""
     if st.C0 is not None:
         C = C + st.C0
+    if st.P0 is not None:
+        P = P + st.P0
     Pr = to_real_space(st, P)
     Cr = to_real_space(st, C)
     VP = P.copy()

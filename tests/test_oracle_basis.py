@@ -13,7 +13,7 @@ import pytest
 
 from oracle import basis, bands, bruteforce, cutoff
 from oracle import tufrg as tu
-from synth import random_unitaries as _random_unitaries, rashba_hoppings
+from synth import onsite_V0, random_exchange_state, random_unitaries as _random_unitaries, rashba_hoppings
 
 N_O = 2
 
@@ -168,3 +168,65 @@ def test_orbital_loops_are_band_loops_carried_over(channel):
     Lb = basis.band_loops(S, L, 1, st.e, channel, lam, cutoff.TEMPERATURE)
     got = basis.orbital_loops_from_band(Lb, M)
     assert np.allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+
+
+def _onsite_p0(st, V0):
+    """P-channel projection of an onsite interaction: V0 in the (0,0) block."""
+    P0 = st.zero_state()
+    P0[:, 0, 0] = V0
+    return P0
+
+
+@pytest.mark.parametrize("S,Lq,n_ref", [(bruteforce.complete_ff(3), 3, 1),
+                                        ([(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)], 6, 2)])
+def test_static_p_term_reproduces_the_onsite_interaction(S, Lq, n_ref):
+    """An onsite bare vertex is exactly its (0,0) P-channel expansion: given as
+    a static P term instead of V0 it yields the same projections and RHS."""
+    hop_R, hop_t = rashba_hoppings(1.0, 0.35)
+    V0 = onsite_V0(2.0)
+    st = tu.TUSetup(hop_R, hop_t, -0.2, V0, S, Lq, n_ref, cutoff.TEMPERATURE)
+    st0 = tu.TUSetup(hop_R, hop_t, -0.2, 0 * V0, S, Lq, n_ref, cutoff.TEMPERATURE, P0=_onsite_p0(st, V0))
+    P = 0.1 * random_exchange_state(st.Nq, st.n_ff, 2, seed=5)
+    C = 0.1 * random_exchange_state(st.Nq, st.n_ff, 2, seed=6)
+    for a, b in zip(tu.projected_vertices(st, P, C), tu.projected_vertices(st0, P, C)):
+        assert np.allclose(a, b, atol=1e-13)
+    for a, b in zip(tu.rhs(st, 0.4, P, C), tu.rhs(st0, 0.4, P, C)):
+        assert np.allclose(a, b, atol=1e-13)
+
+
+@pytest.mark.parametrize("scheme", [cutoff.TEMPERATURE, cutoff.OMEGA])
+def test_band_basis_rhs_is_the_transformed_orbital_rhs(scheme):
+    """Complete form-factor set, no refinement: the band-basis flow (unit
+    projectors in the loops, the bare vertex as the static P term U^dagger
+    P[V0] U) gives dPb = U^dagger dP U and dCb = X^dagger dC X for the
+    transformed state, with the eigenvectors of H(k) as U."""
+    L = 3
+    S = bruteforce.complete_ff(L)
+    hop_R, hop_t = rashba_hoppings(1.0, 0.4)
+    V0 = onsite_V0(2.5)
+    st = tu.TUSetup(hop_R, hop_t, -0.3, V0, S, L, 1, scheme)
+    Um = basis.u_matrix(S, L, 1, st.U)
+    Xm = basis.x_matrix(S, L, 1, st.U)
+    P0b = basis.p_to_band(_onsite_p0(st, V0), Um)
+    stb = tu.TUSetup(hop_R, hop_t, -0.3, 0 * V0, S, L, 1, scheme, P0=P0b, basis="band")
+    P = 0.2 * random_exchange_state(st.Nq, st.n_ff, 2, seed=8)
+    C = 0.2 * random_exchange_state(st.Nq, st.n_ff, 2, seed=9)
+    dP, dC = tu.rhs(st, 0.3, P, C)
+    dPb, dCb = tu.rhs(stb, 0.3, basis.p_to_band(P, Um), basis.c_to_band(C, Xm))
+    assert np.allclose(dPb, basis.p_to_band(dP, Um), rtol=0, atol=1e-12 * np.abs(dP).max())
+    assert np.allclose(dCb, basis.c_to_band(dC, Xm), rtol=0, atol=1e-12 * np.abs(dC).max())
+
+
+def test_band_basis_loops_are_diagonal_in_the_band_pair():
+    """With unit projectors the loop kernel reduces to the band loop matrices."""
+    S = [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)]
+    hop_R, hop_t = rashba_hoppings(1.0, 0.3)
+    stb = tu.TUSetup(hop_R, hop_t, -0.4, onsite_V0(1.0), S, 4, 3, cutoff.OMEGA, basis="band")
+    for ch in ("pp", "ph"):
+        got = tu.loops(stb, ch, 0.5, q_list=[0, 6])
+        Lb = basis.band_loops(S, 4, 3, stb.e, ch, 0.5, cutoff.OMEGA, q_list=[0, 6])
+        want = np.zeros_like(got)
+        for l1 in range(2):
+            for l2 in range(2):
+                want[:, :, :, l1, l2, l1, l2] = Lb[..., l1, l2]
+        assert np.allclose(got, want, atol=1e-13)

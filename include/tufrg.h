@@ -100,6 +100,17 @@ typedef enum {
  * around the Fermi surface (the paper leaves the shape open). */
 typedef enum { TUFRG_CUT_TEMPERATURE = 0, TUFRG_CUT_OMEGA = 1, TUFRG_CUT_SHELL = 2 } tufrg_cutoff;
 
+/* Single-particle basis of the exchange propagators.  ORBITAL: the loops of
+ * Sec. 4.2 with the band projectors Pi_m(k) of H(k).  BAND: the eigenbasis of
+ * H(k) (the form in which Sec. 3.1 writes the RGE): the loops see unit
+ * projectors and depend on two band indices, L(e_l1(k'), e_l2(k)); the
+ * projections and bundle products are unchanged.  A band-basis state depends
+ * on the eigenvector gauge of the basis change that produced it; the bare
+ * vertex is then given as a static P term (tufrg_set_initial_p, e.g.
+ * U^H P[V0] U from tufrg_basis_matrix / tufrg_basis_apply) with V0 = 0 in the
+ * model. */
+typedef enum { TUFRG_BASIS_ORBITAL = 0, TUFRG_BASIS_BAND = 1 } tufrg_basis;
+
 /* Arithmetic of the loops and bundle products; the state and its updates are
  * always FP64.  TUFRG_FP32 accumulates each loop k-chunk in FP32 and sums
  * chunks in FP64.  TUFRG_BF16X3 (six spin-orbitals only) runs the loop's k
@@ -126,6 +137,7 @@ typedef struct {
   int32_t cutoff;          /* tufrg_cutoff */
   int32_t precision;       /* tufrg_precision */
   double temperature;      /* TUFRG_CUT_SHELL: the fixed temperature T > 0 of its bubbles; ignored otherwise */
+  int32_t basis;           /* tufrg_basis: single-particle basis of the state (orbital by default) */
 } tufrg_setup;
 
 /* Builds meshes, tables and the band data (eigendecomposition of H(k) - mu on
@@ -188,6 +200,17 @@ tufrg_status tufrg_basis_matrix(tufrg_ctx *ctx, int32_t channel, const tufrg_c64
  * E_INVAL for a host pointer or Y overlapping M, E_NOMEM for the workspace. */
 tufrg_status tufrg_basis_apply(tufrg_ctx *ctx, const tufrg_c64 *M, const tufrg_c64 *X, tufrg_c64 *Y,
                                int32_t to_orbital);
+
+/* Static particle-particle term of the bare vertex: P0 [Nq][B][B] (device,
+ * the P bundle layout) is the P-channel expansion of (part of) the bare
+ * vertex.  From this call on every projection uses P + P0 in place of P, so VP
+ * includes P0 and VC its crossed particle-hole projection (Sec. 3.3).  An
+ * onsite interaction is exactly its (0,0) block; the band-basis form of an
+ * orbital interaction is U^H P[V0] U (Sec. 4.1), exact for a complete
+ * form-factor set and its truncated expansion otherwise.  The library copies
+ * P0 (stream-ordered); P0 = NULL removes it.  Errors: E_INVAL for a host
+ * pointer, E_NOMEM when the two [Nq][B][B] buffers cannot be allocated. */
+tufrg_status tufrg_set_initial_p(tufrg_ctx *ctx, const tufrg_c64 *P0);
 
 /* Projected vertices VP, VC [Nq][B][B] of the state P, C [Nq][B][B] (Sec. 3.3). */
 tufrg_status tufrg_project(tufrg_ctx *ctx, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,

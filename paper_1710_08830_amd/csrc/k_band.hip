@@ -13,7 +13,7 @@ namespace tufrg {
 
 template <int NO>
 __global__ __launch_bounds__(64) void band_kernel(int Lf, int n_hop, const int *__restrict__ hop_R,
-                                                  const double *__restrict__ hop_t, double mu,
+                                                  const double *__restrict__ hop_t, double mu, int unit_pi,
                                                   double *__restrict__ e_out, double *__restrict__ pi_out,
                                                   float *__restrict__ e32, float *__restrict__ pi32) {
   const int Nf = Lf * Lf;
@@ -160,6 +160,16 @@ __global__ __launch_bounds__(64) void band_kernel(int Lf, int n_hop, const int *
     e_out[m * Nfs + k] = e;
     e32[m * Nfs + k] = (float)e;
     int comp = m * NO * NO;
+    if (unit_pi) {
+      // band basis: the single-particle basis is the eigenbasis, Pi_m = e_m e_m^T
+#pragma unroll
+      for (int i = 0; i < NO * NO; ++i) {
+        const double v = (i < NO && i == m) ? 1.0 : 0.0;
+        pi_out[(comp + i) * Nfs + k] = v;
+        pi32[(comp + i) * Nfs + k] = (float)v;
+      }
+      continue;
+    }
 #pragma unroll
     for (int a = 0; a < NO; ++a) {
       double v = Vr[a][m] * Vr[a][m] + Vi[a][m] * Vi[a][m];
@@ -183,15 +193,15 @@ __global__ __launch_bounds__(64) void band_kernel(int Lf, int n_hop, const int *
   }
 }
 
-hipError_t launch_band(int n_o, int Lf, int n_hop, const int *hop_R, const double *hop_t, double mu,
+hipError_t launch_band(int n_o, int Lf, int n_hop, const int *hop_R, const double *hop_t, double mu, int unit_pi,
                        double *e, double *pi, float *e32, float *pi32, hipStream_t st) {
   const int Nf = Lf * Lf;
   dim3 grid((Nf + 63) / 64), block(64);
   switch (n_o) {
-    case 1: hipLaunchKernelGGL(band_kernel<1>, grid, block, 0, st, Lf, n_hop, hop_R, hop_t, mu, e, pi, e32, pi32); break;
-    case 2: hipLaunchKernelGGL(band_kernel<2>, grid, block, 0, st, Lf, n_hop, hop_R, hop_t, mu, e, pi, e32, pi32); break;
-    case 4: hipLaunchKernelGGL(band_kernel<4>, grid, block, 0, st, Lf, n_hop, hop_R, hop_t, mu, e, pi, e32, pi32); break;
-    case 6: hipLaunchKernelGGL(band_kernel<6>, grid, block, 0, st, Lf, n_hop, hop_R, hop_t, mu, e, pi, e32, pi32); break;
+    case 1: hipLaunchKernelGGL(band_kernel<1>, grid, block, 0, st, Lf, n_hop, hop_R, hop_t, mu, unit_pi, e, pi, e32, pi32); break;
+    case 2: hipLaunchKernelGGL(band_kernel<2>, grid, block, 0, st, Lf, n_hop, hop_R, hop_t, mu, unit_pi, e, pi, e32, pi32); break;
+    case 4: hipLaunchKernelGGL(band_kernel<4>, grid, block, 0, st, Lf, n_hop, hop_R, hop_t, mu, unit_pi, e, pi, e32, pi32); break;
+    case 6: hipLaunchKernelGGL(band_kernel<6>, grid, block, 0, st, Lf, n_hop, hop_R, hop_t, mu, unit_pi, e, pi, e32, pi32); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

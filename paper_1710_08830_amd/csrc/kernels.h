@@ -6,7 +6,8 @@
 namespace tufrg {
 
 // a0: band data on the fine mesh (eigenvalues minus mu, packed projectors)
-hipError_t launch_band(int n_o, int Lf, int n_hop, const int *hop_R, const double *hop_t, double mu,
+// unit_pi: band basis, Pi_m(k) = e_m e_m^T (eigenvalues as always)
+hipError_t launch_band(int n_o, int Lf, int n_hop, const int *hop_R, const double *hop_t, double mu, int unit_pi,
                        double *e, double *pi, float *e32, float *pi32, hipStream_t st);
 hipError_t launch_kval(int n, int Nf, int aos_no, const double *e, double lam, int scheme, int deriv, double *kv,
                        float *kv32, hipStream_t st);

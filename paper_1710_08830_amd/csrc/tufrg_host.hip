@@ -57,6 +57,9 @@ struct tufrg_ctx {
   double *d_c0 = nullptr;     // static C-channel term of a non-local initial interaction, [Nq][B][B]
   double *d_ceff = nullptr;   // C + C0 for the projections
   bool has_c0 = false;
+  double *d_p0 = nullptr;     // static P-channel term of the bare vertex (band basis), [Nq][B][B]
+  double *d_peff = nullptr;   // P + P0 for the projections
+  bool has_p0 = false;
   double temp = 0.0;          // momentum-shell scheme: the fixed temperature of its bubbles
   double *d_cv64 = nullptr;   // momentum-shell scheme: shell factors (see LoopArgs::cv)
   float *d_cv32 = nullptr;
@@ -201,6 +204,8 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     return fail(nullptr, TUFRG_E_UNSUPPORTED, "BF16X3 loops are built for six spin-orbitals");
   if (s->n_ref < 1 || s->Lq < 1 || (long long)s->Lq * s->n_ref > 4096)
     return fail(nullptr, TUFRG_E_INVAL, "mesh sizes out of range");
+  if (s->basis != TUFRG_BASIS_ORBITAL && s->basis != TUFRG_BASIS_BAND)
+    return fail(nullptr, TUFRG_E_INVAL, "unknown single-particle basis");
   int rmax = 0;
   std::vector<std::pair<int, int>> ffv;
   for (int i = 0; i < s->n_ff; ++i) {
@@ -443,8 +448,8 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   }
   CHIP(hipMemcpyAsync(c->d_v0p, v0p.data(), v0p.size() * sizeof(double), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_v0c, v0c.data(), v0c.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  CHIP(launch_band(c->n_o, c->Lf, m->n_hop, c->d_hopR, c->d_hopt, m->mu, c->d_band64, c->d_band64 + Nf * c->n_o,
-                   c->d_band32, c->d_band32 + Nf * c->n_o, st));
+  CHIP(launch_band(c->n_o, c->Lf, m->n_hop, c->d_hopR, c->d_hopt, m->mu, s->basis == TUFRG_BASIS_BAND ? 1 : 0,
+                   c->d_band64, c->d_band64 + Nf * c->n_o, c->d_band32, c->d_band32 + Nf * c->n_o, st));
   if (c->n_o > 2) CHIP(launch_to_kmajor(c->n_o + c->n_o * c->no2, (int)Nf, c->d_band64, c->d_bandk64, c->d_bandk32, st));
   if (c->n_o == 2) CHIP(launch_pi4((int)Nf, c->d_band64, c->d_pi4_64, c->d_pi4_32, st));
   CHIP(hipStreamSynchronize(st));
@@ -717,6 +722,12 @@ static tufrg_status project_internal(tufrg_ctx *c, const double *P, const double
     HIPCHK(c, launch_add(2 * (long long)c->Nq * c->B * c->B, C, c->d_c0, c->d_ceff, c->st));
     C = c->d_ceff;
   }
+  if (c->has_p0) {
+    // a bare vertex given by its particle-particle expansion (the band-basis
+    // form of an orbital interaction) is a static part of the P channel
+    HIPCHK(c, launch_add(2 * (long long)c->Nq * c->B * c->B, P, c->d_p0, c->d_peff, c->st));
+    P = c->d_peff;
+  }
   HIPCHK(c, launch_ft(a, P, C, c->d_ftpart, c->nqc, c->d_real, c->st));
   HIPCHK(c, launch_gather(a, c->d_real, c->d_G, c->st));
   HIPCHK(c, launch_assemble(a, P, C, c->d_G, c->d_v0p, c->d_v0c, VP, VC, c->st));
@@ -861,6 +872,23 @@ extern "C" tufrg_status tufrg_set_initial_c(tufrg_ctx *c, const tufrg_c64 *C0) {
   }
   HIPCHK(c, hipMemcpyAsync(c->d_c0, C0, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   c->has_c0 = true;
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_set_initial_p(tufrg_ctx *c, const tufrg_c64 *P0) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!P0) {
+    c->has_p0 = false;
+    return TUFRG_OK;
+  }
+  if (!is_device_ptr(P0)) return fail(c, TUFRG_E_INVAL, "P0 must be a device pointer");
+  const size_t n = 2 * (size_t)c->Nq * c->B * c->B;
+  if (!c->d_p0) {
+    TRY(dalloc(c, &c->d_p0, n));
+    TRY(dalloc(c, &c->d_peff, n));
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_p0, P0, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  c->has_p0 = true;
   return TUFRG_OK;
 }
 

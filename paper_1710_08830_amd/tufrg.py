@@ -27,6 +27,8 @@ STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NONFINITE", 5: 
           6: "E_UNSUPPORTED"}
 CUT_TEMPERATURE, CUT_OMEGA, CUT_SHELL = 0, 1, 2
 CUTOFFS = {"temperature": CUT_TEMPERATURE, "omega": CUT_OMEGA, "shell": CUT_SHELL}
+BASIS_ORBITAL, BASIS_BAND = 0, 1
+BASES = {"orbital": BASIS_ORBITAL, "band": BASIS_BAND}
 FP64, FP32, BF16X3 = 0, 1, 2
 PP, PH = 0, 1
 
@@ -38,7 +40,7 @@ SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "t
            "tufrg_mlp_train", "tufrg_sur_features", "tufrg_sur_targets", "tufrg_sur_attach",
            "tufrg_sur_loops", "tufrg_batch_create", "tufrg_batch_destroy", "tufrg_batch_last_error",
            "tufrg_batch_dims", "tufrg_batch_flow", "tufrg_set_initial_c", "tufrg_basis_matrix",
-           "tufrg_basis_apply"]
+           "tufrg_basis_apply", "tufrg_set_initial_p"]
 TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE, TIMER_SURROGATE = 0, 1, 2, 3
 
 
@@ -55,7 +57,7 @@ class Model(ctypes.Structure):
 class Setup(ctypes.Structure):
     _fields_ = [("n_ff", ctypes.c_int32), ("ff_R", ctypes.POINTER(ctypes.c_int32)),
                 ("Lq", ctypes.c_int32), ("n_ref", ctypes.c_int32), ("cutoff", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("temperature", ctypes.c_double)]
+                ("precision", ctypes.c_int32), ("temperature", ctypes.c_double), ("basis", ctypes.c_int32)]
 
 
 STEP_CB = ctypes.CFUNCTYPE(ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
@@ -172,7 +174,8 @@ def _stream_handle(stream):
 class Context:
     """Owns a tufrg_ctx.  ``model``/``setup`` are host-side numpy inputs."""
 
-    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, cutoff, precision, stream=None, temperature=None):
+    def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, cutoff, precision, stream=None, temperature=None,
+                 basis="orbital"):
         hop_R = np.ascontiguousarray(hop_R, dtype=np.int32).reshape(-1, 2)
         hop_t = np.ascontiguousarray(hop_t, dtype=np.complex128)
         V0 = np.ascontiguousarray(V0, dtype=np.complex128)
@@ -185,7 +188,7 @@ class Context:
         cut = CUTOFFS.get(cutoff, cutoff)
         prec = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}.get(precision, precision)
         s = Setup(ff.shape[0], ff.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(Lq), int(n_ref),
-                  int(cut), int(prec), float(temperature or 0.0))
+                  int(cut), int(prec), float(temperature or 0.0), int(BASES.get(basis, basis)))
         h = ctypes.c_void_p()
         _check(_lib.tufrg_create(ctypes.byref(m), ctypes.byref(s), _stream_handle(stream),
                                  ctypes.byref(h)))
@@ -243,6 +246,12 @@ def tufrg_basis_matrix(ctx, channel, U, M):
 def tufrg_basis_apply(ctx, M, X, Y, to_orbital=False):
     """Y = M^H X M per q (orbital -> band), or M X M^H (to_orbital)."""
     _check(_lib.tufrg_basis_apply(ctx.handle, _ptr(M), _ptr(X), _ptr(Y), int(bool(to_orbital))), ctx.handle)
+
+
+def tufrg_set_initial_p(ctx, P0):
+    """Static P-channel term of the bare vertex ([Nq][B][B] on the device, P
+    layout), or None to remove it."""
+    _check(_lib.tufrg_set_initial_p(ctx.handle, None if P0 is None else _ptr(P0)), ctx.handle)
 
 
 def tufrg_rhs(ctx, lam, P, C, dP, dC):
@@ -406,7 +415,8 @@ class Batch:
             cut = CUTOFFS.get(w["cutoff"], w["cutoff"])
             prec = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}.get(precision, precision)
             setups[i] = Setup(ff.shape[0], ff.ctypes.data_as(_i32p), int(w["Lq"]), int(w["n_ref"]), int(cut),
-                              int(prec), float(w.get("temperature") or 0.0))
+                              int(prec), float(w.get("temperature") or 0.0),
+                              int(BASES.get(w.get("basis", "orbital"), w.get("basis", "orbital"))))
         h = ctypes.c_void_p()
         st = _lib.tufrg_batch_create(n, models, setups, int(n_streams), ctypes.byref(h))
         if st != TUFRG_OK:

@@ -96,3 +96,14 @@ def test_basis_calls_reject_a_null_context(T):
     lib = T._lib
     assert lib.tufrg_basis_matrix(None, 0, None, None) == 1
     assert lib.tufrg_basis_apply(None, None, None, None, 0) == 1
+
+
+def test_create_rejects_an_unknown_basis(T):
+    with pytest.raises(T.TufrgError) as ei:
+        T.Context(**_args(basis=7))
+    assert ei.value.status == 1
+    assert "basis" in str(ei.value)
+
+
+def test_set_initial_p_rejects_a_null_context(T):
+    assert T._lib.tufrg_set_initial_p(None, None) == 1

@@ -142,3 +142,92 @@ def test_full_size_basis_matrix_sampled(T, ch):
     make, conv = (basis.u_matrix, u_to_matrix) if ch == "pp" else (basis.x_matrix, x_to_matrix)
     want = conv(make(w["ff"], Lq, n_ref, U, q_list))
     assert rel(M[q_list], want) < TOL
+
+
+# --- band-basis flow: unit projectors in the loops, bare vertex as a static P term
+
+from oracle import tufrg as otu  # noqa: E402
+
+RHS_TOL = {"fp64": 1e-10, "fp32": 3e-5}
+
+
+def _band_pair(T, name, prec, P0):
+    """Library context and oracle setup in the band basis, V0 = 0, static P0."""
+    hop, V0, ff, Lq, n_ref = CASES[name]
+    zero = np.zeros_like(V0)
+    ctx = T.Context(hop[0], hop[1], -0.3, zero, ff, Lq, n_ref, "omega", prec, basis="band")
+    st = otu.TUSetup(hop[0], hop[1], -0.3, zero, ff, Lq, n_ref, "omega", P0=P0, basis="band")
+    T.tufrg_set_initial_p(ctx, torch.from_numpy(p_to_matrix(P0)).to(dev()))
+    return ctx, st
+
+
+def _rhs(T, ctx, P, C, lam):
+    Pd = torch.from_numpy(p_to_matrix(P)).to(dev())
+    Cd = torch.from_numpy(c_to_matrix(C)).to(dev())
+    dP, dC = _zeros(ctx), _zeros(ctx)
+    T.tufrg_rhs(ctx, lam, Pd, Cd, dP, dC)
+    torch.cuda.synchronize()
+    return dP.cpu().numpy(), dC.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,prec", [("hub5", "fp64"), ("ras9", "fp64"), ("ras9", "fp32"), ("ras13", "fp32"),
+                                       ("t2g9", "fp64"), ("t2g9", "fp32")])
+def test_band_basis_rhs_matches_oracle(T, name, prec):
+    hop, V0, ff, Lq, n_ref = CASES[name]
+    n_o = hop[1].shape[1]
+    P0 = 0.5 * random_exchange_state(Lq * Lq, len(ff), n_o, seed=21)
+    ctx, st = _band_pair(T, name, prec, P0)
+    P = 0.2 * random_exchange_state(st.Nq, st.n_ff, n_o, seed=22)
+    C = 0.2 * random_exchange_state(st.Nq, st.n_ff, n_o, seed=23)
+    dP, dC = _rhs(T, ctx, P, C, 0.4)
+    rP, rC = otu.rhs(st, 0.4, P, C)
+    assert rel(dP, p_to_matrix(rP)) < RHS_TOL[prec]
+    assert rel(dC, c_to_matrix(rC)) < RHS_TOL[prec]
+
+
+@pytest.mark.parametrize("name", ["hub5", "ras9", "t2g9"])
+def test_static_p_term_equals_the_onsite_interaction(T, name):
+    """Orbital basis: V0 in the model, or V0 = 0 and its (0,0) block as the
+    static P term, give the same right-hand side."""
+    hop, V0, ff, Lq, n_ref = CASES[name]
+    n_o = hop[1].shape[1]
+    ctx = T.Context(hop[0], hop[1], -0.3, V0, ff, Lq, n_ref, "temperature", "fp64")
+    ctx0 = T.Context(hop[0], hop[1], -0.3, np.zeros_like(V0), ff, Lq, n_ref, "temperature", "fp64")
+    P0 = np.zeros((Lq * Lq, len(ff), len(ff)) + (n_o,) * 4, dtype=np.complex128)
+    P0[:, 0, 0] = V0
+    T.tufrg_set_initial_p(ctx0, torch.from_numpy(p_to_matrix(P0)).to(dev()))
+    P = 0.2 * random_exchange_state(Lq * Lq, len(ff), n_o, seed=31)
+    C = 0.2 * random_exchange_state(Lq * Lq, len(ff), n_o, seed=32)
+    a = _rhs(T, ctx, P, C, 0.5)
+    b = _rhs(T, ctx0, P, C, 0.5)
+    assert rel(b[0], a[0]) < 1e-12 and rel(b[1], a[1]) < 1e-12
+    T.tufrg_set_initial_p(ctx0, None)  # removed: the interaction is gone
+    c = _rhs(T, ctx0, P, C, 0.5)
+    assert rel(c[0], a[0]) > 1e-3
+
+
+def test_band_flow_from_the_library_basis_change(T):
+    """The whole chain on the device (basis matrix, U^H P[V0] U as the static
+    term, band-basis Euler flow) against the same chain in the oracle, with the
+    same seeded unitaries as U(k)."""
+    name = "ras9"
+    hop, V0, ff, Lq, n_ref = CASES[name]
+    U = random_unitaries((Lq * n_ref) ** 2, 2, seed=41)
+    P0o = np.zeros((Lq * Lq, len(ff), len(ff)) + (2,) * 4, dtype=np.complex128)
+    P0o[:, 0, 0] = V0
+    # device: P0 = M^H P[V0] M
+    ctx = T.Context(hop[0], hop[1], -0.3, np.zeros_like(V0), ff, Lq, n_ref, "omega", "fp64", basis="band")
+    M = _matrix(T, ctx, T.PP, U)
+    P0d = _zeros(ctx)
+    T.tufrg_basis_apply(ctx, M, torch.from_numpy(p_to_matrix(P0o)).to(dev()), P0d)
+    T.tufrg_set_initial_p(ctx, P0d)
+    Pd, Cd = _zeros(ctx), _zeros(ctx)
+    res = T.tufrg_flow(ctx, Pd, Cd, 5.0, 0.5, n_steps=12, v_max=1e30)
+    torch.cuda.synchronize()
+    # oracle: the same chain
+    P0b = basis.p_to_band(P0o, basis.u_matrix(ff, Lq, n_ref, U))
+    st = otu.TUSetup(hop[0], hop[1], -0.3, np.zeros_like(V0), ff, Lq, n_ref, "omega", P0=P0b, basis="band")
+    rP, rC, _ = otu.flow_euler(st, 5.0, 0.5, 12, v_max=1e30)[:3]
+    assert rel(Pd.cpu().numpy(), p_to_matrix(rP)) < 1e-9
+    assert rel(Cd.cpu().numpy(), c_to_matrix(rC)) < 1e-9
+    assert res["n_steps"] == 12

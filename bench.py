@@ -14,7 +14,8 @@ Printed: one JSON line with the headline value (loop entries/s over the whole
 step), flow steps/s, the same for the FP64-plain form and the relative error of
 the FP32 state against it, the roofline of the loop kernel (event-timed inside
 the library over the timed region), the production Dormand-Prince flow, the
-orbital -> band basis change (basis matrices and sandwiches, FP64), and a CPU
+orbital -> band basis change (basis matrices and sandwiches, FP64, and Euler
+steps of the band-basis flow), and a CPU
 baseline of the FP64 oracle on a sample of q points.
 """
 
@@ -330,9 +331,11 @@ def basis_flops(Nq, n_o, Nf, box):
     return float(Nq) * n_o ** 4 * Nf * (6 + 8 * (2 * box + 1))
 
 
-def basis_leg(T, torch, ctx, P, C, ff, reps=3):
+def basis_leg(T, torch, ctx, P, C, ff, reps=3, band_ctx=None, V0=None, steps=20):
     """Orbital -> band basis change on the FP64 context: the pp and ph basis
     matrices from seeded random unitaries, then Pb = M^H P M and Cb = M^H C M."""
+    import numpy as np
+
     from synth import random_unitaries
     dev = P.device
     box = 2 if 2 * max(max(abs(x), abs(y)) for x, y in ff) <= 2 else 4  # D = S - S inside [-box, box]^2
@@ -360,10 +363,28 @@ def basis_leg(T, torch, ctx, P, C, ff, reps=3):
     tm -= ta
     per_matrix = tm / (2 * reps)
     fl = basis_flops(ctx.Nq, ctx.n_o, ctx.Nf, box)
-    return {"matrix_ms_per_channel": per_matrix * 1e3, "apply_ms_per_channel": ta / (2 * reps) * 1e3,
-            "matrix_flops_per_channel": fl, "achieved_tflops": fl / per_matrix / 1e12,
-            "peak_tflops": PEAK_FP64_VECTOR / 1e12, "frac": fl / per_matrix / PEAK_FP64_VECTOR,
-            "note": "matrix time includes its expansion to B x B; host-timed with device syncs"}
+    out = {"matrix_ms_per_channel": per_matrix * 1e3, "apply_ms_per_channel": ta / (2 * reps) * 1e3,
+           "matrix_flops_per_channel": fl, "achieved_tflops": fl / per_matrix / 1e12,
+           "peak_tflops": PEAK_FP64_VECTOR / 1e12, "frac": fl / per_matrix / PEAK_FP64_VECTOR,
+           "note": "matrix time includes its expansion to B x B; host-timed with device syncs"}
+    if band_ctx is not None:
+        # band-basis Euler steps: the onsite interaction U^H P[V0] U as the static P term
+        n_o, nff = ctx.n_o, ctx.n_ff
+        P0 = torch.zeros_like(P)
+        P0.view(ctx.Nq, nff, n_o, n_o, nff, n_o, n_o)[:, 0, :, :, 0] = torch.from_numpy(
+            np.ascontiguousarray(V0.transpose(0, 1, 3, 2))).to(dev)
+        T.tufrg_basis_apply(ctx, Mp, P0, Y)
+        T.tufrg_set_initial_p(band_ctx, Y)
+        Pb, Cb = torch.zeros_like(P), torch.zeros_like(P)
+        T.tufrg_flow(band_ctx, Pb, Cb, 10.0, 1.0, n_steps=3, v_max=1e30)
+        Pb.zero_()
+        Cb.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T.tufrg_flow(band_ctx, Pb, Cb, 10.0, 1.0, n_steps=steps, v_max=1e30)
+        torch.cuda.synchronize()
+        out["band_flow_ms_per_step"] = (time.perf_counter() - t0) / steps * 1e3
+    return out
 
 
 def batch_bench(T, torch, K, W):
@@ -559,7 +580,10 @@ def main():
     if not args.no_extras and not args.no_dp and not args.no_surrogate:
         out["surrogate_flow"] = surrogate_leg(T, torch, ctx32, P32, C32, P64, C64, dp, w, K, dt32 / K)
     if not args.no_extras and not args.no_basis:
-        out["basis_change"] = basis_leg(T, torch, ctx64, P64, C64, w["ff"])
+        band = T.Context.from_workload(w, precision=args.prec, basis="band", V0=0 * w["V0"])
+        out["basis_change"] = basis_leg(T, torch, ctx64, P64, C64, w["ff"], band_ctx=band,
+                                        V0=np.asarray(w["V0"]), steps=K)
+        band.close()
     if not args.no_extras:
         ctx64.close()
     if not args.no_cpu:

@@ -201,6 +201,28 @@ tufrg_status tufrg_basis_matrix(tufrg_ctx *ctx, int32_t channel, const tufrg_c64
 tufrg_status tufrg_basis_apply(tufrg_ctx *ctx, const tufrg_c64 *M, const tufrg_c64 *X, tufrg_c64 *Y,
                                int32_t to_orbital);
 
+/* Point-group-symmetrised form factors.  The plane waves f_R(k) = e^{-ik.R}
+ * of a form-factor set closed under C4v recombine into f~_i = sum_R W_iR f_R
+ * (W unitary) that transform under its irreducible representations; a
+ * propagator then changes by X~ = W X W^H in the form-factor index (orbital
+ * indices untouched), the converse X = W^H X~ W.
+ * tufrg_ff_symmetrize (host only, no context): W [n_ff][n_ff] (rows) and the
+ * label of each row, 0 A1, 1 A2, 2 B1, 3 B2, 4 E x-like, 5 E y-like, for S
+ * given as ff_R [n_ff][2].  Orbits in order of first appearance in S; inside
+ * an orbit A1, then B1 (axis shells: cos kx - cos ky) or B2 (diagonal
+ * shells), then the E pair (x-like: odd under x -> -x, even under y -> -y);
+ * each row's first nonzero coefficient (in the order of S) real and positive.
+ * W, irrep: host arrays owned by the caller.  Errors: E_INVAL when S is not a
+ * union of C4v orbits (or has duplicates, or n_ff > 25), E_UNSUPPORTED for
+ * orbits of eight vectors (such as (1, 2)).
+ * tufrg_ff_apply: Y[q] = X~ (to_plane_waves = 0) or the converse (1) for
+ * [Nq][B][B] device arrays in the bundle layout (P or C alike: the orbital
+ * pairs are untouched); W host [n_ff][n_ff].  Synchronises the context's
+ * stream.  Errors: E_INVAL for host X/Y, overlapping X and Y. */
+tufrg_status tufrg_ff_symmetrize(int32_t n_ff, const int32_t *ff_R, tufrg_c64 *W, int32_t *irrep);
+tufrg_status tufrg_ff_apply(tufrg_ctx *ctx, const tufrg_c64 *W, const tufrg_c64 *X, tufrg_c64 *Y,
+                            int32_t to_plane_waves);
+
 /* Static particle-particle term of the bare vertex: P0 [Nq][B][B] (device,
  * the P bundle layout) is the P-channel expansion of (part of) the bare
  * vertex.  From this call on every projection uses P + P0 in place of P, so VP

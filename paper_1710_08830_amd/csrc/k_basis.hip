@@ -223,6 +223,47 @@ hipError_t launch_basis_compact(int channel, int n_o, int Lq, int n_ref, int nD,
   return hipSuccess;
 }
 
+// Change of the form-factor basis: Y[q][(i,a,b),(j,c,d)] = sum_{R,R'} A_iR
+// X[q][(R,a,b),(R',c,d)] conj(A_jR') (A = W for plane waves -> symmetrised
+// form factors, A = W^H back); one thread per output entry, A in LDS.
+__global__ __launch_bounds__(256) void ff_apply_kernel(int n_ff, int no2, int n_q, const double2 *__restrict__ A,
+                                                       const double2 *__restrict__ X, double2 *__restrict__ Y) {
+  __shared__ double2 sA[25 * 25];  // at most 25 form factors (|R_x|, |R_y| <= 2)
+  for (int i = threadIdx.x; i < n_ff * n_ff; i += blockDim.x) sA[i] = A[i];
+  __syncthreads();
+  const int B = n_ff * no2;
+  const long long BB = (long long)B * B;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long long)n_q * BB) return;
+  const long long q = gid / BB;
+  const int col = (int)(gid % B), row = (int)((gid / B) % B);
+  const int i = row / no2, ab = row % no2, j = col / no2, cd = col % no2;
+  const double2 *Xq = X + q * BB;
+  double sr = 0.0, si = 0.0;
+  for (int R = 0; R < n_ff; ++R) {
+    const double2 a = sA[i * n_ff + R];
+    if (a.x == 0.0 && a.y == 0.0) continue;
+    double tr = 0.0, ti = 0.0;  // sum_R' X[(R,ab),(R',cd)] conj(A_jR')
+    for (int Rp = 0; Rp < n_ff; ++Rp) {
+      const double2 b = sA[j * n_ff + Rp];
+      const double2 x = Xq[(long long)(R * no2 + ab) * B + Rp * no2 + cd];
+      tr = fma(x.x, b.x, fma(x.y, b.y, tr));
+      ti = fma(x.y, b.x, fma(-x.x, b.y, ti));
+    }
+    sr = fma(a.x, tr, fma(-a.y, ti, sr));
+    si = fma(a.x, ti, fma(a.y, tr, si));
+  }
+  Y[gid] = make_double2(sr, si);
+}
+
+hipError_t launch_ff_apply(int n_ff, int no2, int n_q, const double *A, const double *X, double *Y, hipStream_t st) {
+  if (n_ff < 1 || n_ff > 25 || no2 < 1 || n_q < 1) return hipErrorInvalidValue;
+  const long long n = (long long)n_q * n_ff * no2 * n_ff * no2;
+  hipLaunchKernelGGL(ff_apply_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n_ff, no2, n_q,
+                     (const double2 *)A, (const double2 *)X, (double2 *)Y);
+  return hipGetLastError();
+}
+
 // C[q] = opA(A[q]) opB(B[q]) for n x n complex matrices, op 0: as is, 1: conjugate transpose.
 template <int TA, int TB>
 __global__ __launch_bounds__(ZT *ZT) void zgemm_batched_kernel(int n, const double2 *__restrict__ A,

@@ -91,6 +91,8 @@ size_t basis_rows_doubles(int n_o, int Lf, int box, int nq);
 hipError_t launch_basis_compact(int channel, int n_o, int Lq, int n_ref, int nD, int box, const int *dlist,
                                 const double *U, const double *tw, double *rows, int q_chunk, double *out,
                                 hipStream_t st);
+// Y[q] = (A (x) 1) X[q] (A (x) 1)^H in the form-factor index, A [n_ff][n_ff] complex on the device
+hipError_t launch_ff_apply(int n_ff, int no2, int n_q, const double *A, const double *X, double *Y, hipStream_t st);
 // C[q] = opA(A[q]) opB(B[q]), n x n complex, op 1 = conjugate transpose (not both)
 hipError_t launch_zgemm_batched(int n, int n_q, int opA, int opB, const double *A, const double *Bm, double *C,
                                 hipStream_t st);

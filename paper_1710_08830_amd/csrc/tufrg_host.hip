@@ -79,6 +79,7 @@ struct tufrg_ctx {
   double *d_basis_tmp = nullptr;  // basis sandwich workspace, [Nq][B][B] complex (lazy)
   double *d_basis_c = nullptr;    // compact basis matrix, [Nq][nD][n_o^4] complex (lazy)
   double *d_basis_rows = nullptr; // its kx-row sums for a chunk of coarse q (lazy)
+  double *d_ffA = nullptr;        // form-factor change matrix, at most 25 x 25 complex (lazy)
   std::vector<double *> d_stage;  // DP5: 7 k's per channel + stage state per channel
   std::string err;
   std::vector<void *> allocs;
@@ -847,6 +848,97 @@ extern "C" tufrg_status tufrg_basis_apply(tufrg_ctx *c, const tufrg_c64 *M, cons
     HIPCHK(c, launch_zgemm_batched(c->B, c->Nq, 0, 0, m, (const double *)X, c->d_basis_tmp, c->st));
     HIPCHK(c, launch_zgemm_batched(c->B, c->Nq, 0, 1, c->d_basis_tmp, m, (double *)Y, c->st));
   }
+  return TUFRG_OK;
+}
+
+// Symmetrised form factors: the C4v orbits of S written out by hand (the
+// origin; axis shells (+-d, 0), (0, +-d); diagonal shells (+-d, +-d)), rows in
+// the order A1, B1 or B2, E (x-like, y-like) per orbit, every row's first
+// nonzero coefficient (in the order of S) positive.
+extern "C" tufrg_status tufrg_ff_symmetrize(int32_t n_ff, const int32_t *ff_R, tufrg_c64 *W, int32_t *irrep) {
+  if (n_ff < 1 || n_ff > 25 || !ff_R || !W || !irrep) return fail(nullptr, TUFRG_E_INVAL, "bad arguments");
+  std::map<std::pair<int, int>, int> idx;
+  for (int i = 0; i < n_ff; ++i) idx[{ff_R[2 * i], ff_R[2 * i + 1]}] = i;
+  if ((int)idx.size() != n_ff) return fail(nullptr, TUFRG_E_INVAL, "duplicate form factor");
+  auto at = [&](int x, int y) -> int {
+    auto it = idx.find({x, y});
+    return it == idx.end() ? -1 : it->second;
+  };
+  std::vector<double> row(n_ff);
+  std::vector<bool> done(n_ff, false);
+  int nrow = 0;
+  auto emit = [&](int label) {
+    int first = 0;
+    while (first < n_ff && row[first] == 0.0) ++first;
+    const double sg = row[first] < 0.0 ? -1.0 : 1.0;
+    for (int i = 0; i < n_ff; ++i) W[(size_t)nrow * n_ff + i] = tufrg_c64{sg * row[i], 0.0};
+    irrep[nrow++] = label;
+  };
+  const double h = 0.5, r2 = std::sqrt(0.5);
+  for (int i0 = 0; i0 < n_ff; ++i0) {
+    if (done[i0]) continue;
+    const int x = ff_R[2 * i0], y = ff_R[2 * i0 + 1];
+    auto set = [&](std::initializer_list<std::pair<int, double>> v) {
+      std::fill(row.begin(), row.end(), 0.0);
+      for (auto &p : v) row[p.first] = p.second;
+    };
+    if (x == 0 && y == 0) {
+      done[i0] = true;
+      set({{i0, 1.0}});
+      emit(0);
+      continue;
+    }
+    int m[4];
+    bool axis = (x == 0 || y == 0), diag = (std::abs(x) == std::abs(y));
+    if (!axis && !diag) return fail(nullptr, TUFRG_E_UNSUPPORTED, "orbits of eight form factors are not handled");
+    const int d = axis ? std::abs(x) + std::abs(y) : std::abs(x);
+    if (axis) {
+      m[0] = at(d, 0), m[1] = at(-d, 0), m[2] = at(0, d), m[3] = at(0, -d);
+    } else {
+      m[0] = at(d, d), m[1] = at(-d, -d), m[2] = at(d, -d), m[3] = at(-d, d);
+    }
+    for (int k = 0; k < 4; ++k)
+      if (m[k] < 0) return fail(nullptr, TUFRG_E_INVAL, "the form-factor set is not a union of C4v orbits");
+    for (int k = 0; k < 4; ++k) done[m[k]] = true;
+    set({{m[0], h}, {m[1], h}, {m[2], h}, {m[3], h}});
+    emit(0);  // A1
+    set({{m[0], h}, {m[1], h}, {m[2], -h}, {m[3], -h}});
+    emit(axis ? 2 : 3);  // B1 (axis: cos x - cos y), B2 (diagonal: sin x sin y)
+    if (axis) {
+      set({{m[0], r2}, {m[1], -r2}});
+      emit(4);  // x-like
+      set({{m[2], r2}, {m[3], -r2}});
+      emit(5);  // y-like
+    } else {
+      set({{m[0], h}, {m[2], h}, {m[3], -h}, {m[1], -h}});
+      emit(4);  // x-like: (d,d) + (d,-d) - (-d,d) - (-d,-d)
+      set({{m[0], h}, {m[3], h}, {m[2], -h}, {m[1], -h}});
+      emit(5);  // y-like: (d,d) + (-d,d) - (d,-d) - (-d,-d)
+    }
+  }
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_ff_apply(tufrg_ctx *c, const tufrg_c64 *W, const tufrg_c64 *X, tufrg_c64 *Y,
+                                       int32_t inverse) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!W) return fail(c, TUFRG_E_INVAL, "W must be a host array");
+  if (!is_device_ptr(X) || !is_device_ptr(Y)) return fail(c, TUFRG_E_INVAL, "X and Y must be device pointers");
+  const size_t n = (size_t)c->Nq * c->B * c->B;
+  const uintptr_t x0 = (uintptr_t)X, x1 = x0 + n * sizeof(tufrg_c64), y0 = (uintptr_t)Y,
+                  y1 = y0 + n * sizeof(tufrg_c64);
+  if (y0 < x1 && x0 < y1) return fail(c, TUFRG_E_INVAL, "Y must not overlap X");
+  const int nf = c->n_ff;
+  std::vector<tufrg_c64> A((size_t)nf * nf);  // W, or W^H for the way back
+  for (int i = 0; i < nf; ++i)
+    for (int r = 0; r < nf; ++r) {
+      const tufrg_c64 w = inverse ? W[(size_t)r * nf + i] : W[(size_t)i * nf + r];
+      A[(size_t)i * nf + r] = inverse ? tufrg_c64{w.re, -w.im} : w;
+    }
+  if (!c->d_ffA) TRY(dalloc(c, &c->d_ffA, 2 * 25 * 25));
+  HIPCHK(c, hipMemcpyAsync(c->d_ffA, A.data(), A.size() * sizeof(tufrg_c64), hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, launch_ff_apply(nf, c->no2, c->Nq, c->d_ffA, (const double *)X, (double *)Y, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));  // A lives on this host stack frame
   return TUFRG_OK;
 }
 

@@ -40,7 +40,7 @@ SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "t
            "tufrg_mlp_train", "tufrg_sur_features", "tufrg_sur_targets", "tufrg_sur_attach",
            "tufrg_sur_loops", "tufrg_batch_create", "tufrg_batch_destroy", "tufrg_batch_last_error",
            "tufrg_batch_dims", "tufrg_batch_flow", "tufrg_set_initial_c", "tufrg_basis_matrix",
-           "tufrg_basis_apply", "tufrg_set_initial_p"]
+           "tufrg_basis_apply", "tufrg_set_initial_p", "tufrg_ff_symmetrize", "tufrg_ff_apply"]
 TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE, TIMER_SURROGATE = 0, 1, 2, 3
 
 
@@ -98,6 +98,8 @@ _lib.tufrg_bubble.argtypes = [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int
 _lib.tufrg_project.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.tufrg_basis_matrix.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
 _lib.tufrg_basis_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
+_lib.tufrg_ff_symmetrize.argtypes = [ctypes.c_int32, _vp, _vp, _vp]
+_lib.tufrg_ff_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
 _lib.tufrg_rhs.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
 _lib.tufrg_flow.argtypes = [_vp, ctypes.POINTER(FlowOpts), _vp, _vp, ctypes.POINTER(FlowResult)]
 _lib.tufrg_timing.argtypes = [_vp, ctypes.c_int32]
@@ -246,6 +248,23 @@ def tufrg_basis_matrix(ctx, channel, U, M):
 def tufrg_basis_apply(ctx, M, X, Y, to_orbital=False):
     """Y = M^H X M per q (orbital -> band), or M X M^H (to_orbital)."""
     _check(_lib.tufrg_basis_apply(ctx.handle, _ptr(M), _ptr(X), _ptr(Y), int(bool(to_orbital))), ctx.handle)
+
+
+def tufrg_ff_symmetrize(ff):
+    """Symmetrised form factors of the set ff [n_ff][2]: (W [n_ff][n_ff], labels)."""
+    ff = np.ascontiguousarray(ff, dtype=np.int32).reshape(-1, 2)
+    n = ff.shape[0]
+    W = np.zeros((n, n), dtype=np.complex128)
+    lab = np.zeros(n, dtype=np.int32)
+    _check(_lib.tufrg_ff_symmetrize(n, ff.ctypes.data, W.ctypes.data, lab.ctypes.data))
+    return W, lab
+
+
+def tufrg_ff_apply(ctx, W, X, Y, to_plane_waves=False):
+    """Y = W X W^H in the form-factor index (or the converse), [Nq][B][B] on the device."""
+    W = np.ascontiguousarray(W, dtype=np.complex128)
+    _check(_lib.tufrg_ff_apply(ctx.handle, W.ctypes.data, _ptr(X), _ptr(Y), int(bool(to_plane_waves))),
+           ctx.handle)
 
 
 def tufrg_set_initial_p(ctx, P0):

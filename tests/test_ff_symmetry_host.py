@@ -1,0 +1,42 @@
+"""The library's symmetrised form factors (host code, no GPU) against the
+oracle's projection-operator construction, and its argument checks."""
+
+import numpy as np
+import pytest
+
+from oracle import symmetry as sy
+from synth import ff_shell
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1710_08830_amd import tufrg
+    return tufrg
+
+
+@pytest.mark.parametrize("n", [1, 5, 9, 13])
+@pytest.mark.parametrize("order", ["shell", "shuffled"])
+def test_library_rows_match_the_oracle(T, n, order):
+    S = ff_shell(n) if n > 1 else np.array([(0, 0)], dtype=np.int32)
+    if order == "shuffled" and n > 1:
+        rng = np.random.default_rng(n)
+        S = np.concatenate([S[:1], S[1:][rng.permutation(n - 1)]])
+    W, lab = T.tufrg_ff_symmetrize(S)
+    Wo, labo = sy.symmetric_ff(S)
+    assert list(lab) == list(labo)
+    assert np.allclose(W, Wo, atol=1e-15)
+
+
+@pytest.mark.parametrize("S,status", [
+    (np.array([(0, 0), (1, 0), (-1, 0)]), 1),                                          # not closed
+    (np.array([(0, 0), (1, 2), (-1, 2), (1, -2), (-1, -2), (2, 1), (-2, 1), (2, -1), (-2, -1)]), 6),  # orbit of 8
+    (np.array([(0, 0), (0, 0)]), 1),                                                   # duplicate
+])
+def test_library_rejects_sets_it_cannot_symmetrise(T, S, status):
+    with pytest.raises(T.TufrgError) as ei:
+        T.tufrg_ff_symmetrize(S)
+    assert ei.value.status == status
+
+
+def test_ff_apply_rejects_a_null_context(T):
+    assert T._lib.tufrg_ff_apply(None, None, None, None, 0) == 1

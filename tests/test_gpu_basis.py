@@ -231,3 +231,27 @@ def test_band_flow_from_the_library_basis_change(T):
     assert rel(Pd.cpu().numpy(), p_to_matrix(rP)) < 1e-9
     assert rel(Cd.cpu().numpy(), c_to_matrix(rC)) < 1e-9
     assert res["n_steps"] == 12
+
+
+# --- symmetrised form factors
+
+from oracle import symmetry as osym  # noqa: E402
+
+
+@pytest.mark.parametrize("name", ["hub5", "ras9", "ras13", "t2g9"])
+def test_symmetrised_form_factor_change_matches_oracle(T, name):
+    hop, V0, ff, Lq, n_ref = CASES[name]
+    n_o = hop[1].shape[1]
+    ctx = T.Context(hop[0], hop[1], -0.3, V0, ff, Lq, n_ref, "temperature", "fp64")
+    W, _ = T.tufrg_ff_symmetrize(ff)
+    X = random_exchange_state(ctx.Nq, len(ff), n_o, seed=51)
+    for layout in (p_to_matrix, c_to_matrix):
+        Xd = torch.from_numpy(layout(X)).to(dev())
+        Y, Z = _zeros(ctx), _zeros(ctx)
+        T.tufrg_ff_apply(ctx, W, Xd, Y)
+        T.tufrg_ff_apply(ctx, W, Y, Z, to_plane_waves=True)
+        torch.cuda.synchronize()
+        assert rel(Y.cpu().numpy(), layout(osym.to_symmetric(X, W))) < 1e-13
+        assert rel(Z.cpu().numpy(), Xd.cpu().numpy()) < 1e-13
+    with pytest.raises(T.TufrgError):
+        T.tufrg_ff_apply(ctx, W, Xd, Xd)

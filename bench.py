@@ -367,6 +367,15 @@ def basis_leg(T, torch, ctx, P, C, ff, reps=3, band_ctx=None, V0=None, steps=20)
            "matrix_flops_per_channel": fl, "achieved_tflops": fl / per_matrix / 1e12,
            "peak_tflops": PEAK_FP64_VECTOR / 1e12, "frac": fl / per_matrix / PEAK_FP64_VECTOR,
            "note": "matrix time includes its expansion to B x B; host-timed with device syncs"}
+    # change to the symmetrised form factors and back (both channels' layouts alike)
+    W, _ = T.tufrg_ff_symmetrize(np.asarray(ff))
+    T.tufrg_ff_apply(ctx, W, P, Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        T.tufrg_ff_apply(ctx, W, P, Y)
+    torch.cuda.synchronize()
+    out["ff_symmetrise_ms"] = (time.perf_counter() - t0) / reps * 1e3
     if band_ctx is not None:
         # band-basis Euler steps: the onsite interaction U^H P[V0] U as the static P term
         n_o, nff = ctx.n_o, ctx.n_ff

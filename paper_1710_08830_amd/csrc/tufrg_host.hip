@@ -922,7 +922,7 @@ extern "C" tufrg_status tufrg_ff_symmetrize(int32_t n_ff, const int32_t *ff_R, t
 extern "C" tufrg_status tufrg_ff_apply(tufrg_ctx *c, const tufrg_c64 *W, const tufrg_c64 *X, tufrg_c64 *Y,
                                        int32_t inverse) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
-  if (!W) return fail(c, TUFRG_E_INVAL, "W must be a host array");
+  if (!W || is_device_ptr(W)) return fail(c, TUFRG_E_INVAL, "W must be a host array");
   if (!is_device_ptr(X) || !is_device_ptr(Y)) return fail(c, TUFRG_E_INVAL, "X and Y must be device pointers");
   const size_t n = (size_t)c->Nq * c->B * c->B;
   const uintptr_t x0 = (uintptr_t)X, x1 = x0 + n * sizeof(tufrg_c64), y0 = (uintptr_t)Y,

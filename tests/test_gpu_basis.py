@@ -255,3 +255,5 @@ def test_symmetrised_form_factor_change_matches_oracle(T, name):
         assert rel(Z.cpu().numpy(), Xd.cpu().numpy()) < 1e-13
     with pytest.raises(T.TufrgError):
         T.tufrg_ff_apply(ctx, W, Xd, Xd)
+    Wd = torch.from_numpy(W).to(dev())  # W is read on the host: a device array is refused
+    assert T._lib.tufrg_ff_apply(ctx.handle, Wd.data_ptr(), Xd.data_ptr(), Y.data_ptr(), 0) == 1

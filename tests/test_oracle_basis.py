@@ -230,3 +230,26 @@ def test_band_basis_loops_are_diagonal_in_the_band_pair():
             for l2 in range(2):
                 want[:, :, :, l1, l2, l1, l2] = Lb[..., l1, l2]
         assert np.allclose(got, want, atol=1e-13)
+
+
+def test_pp_flow_is_local_in_the_orbital_basis_and_not_in_the_band_basis():
+    """Rashba model with an onsite interaction, particle-particle channel only
+    (Sec. 5): the orbital-basis P stays in the (0,0) form-factor block, while
+    the same flow in the band basis (eigenvectors of H(k) as U) spreads over
+    the other form factors, the slower convergence the paper points out."""
+    S = [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1)]
+    hop_R, hop_t = rashba_hoppings(1.0, 0.5)
+    V0 = onsite_V0(2.0)
+    Lq, n_ref = 6, 2
+    st = tu.TUSetup(hop_R, hop_t, -0.4, V0, S, Lq, n_ref, cutoff.TEMPERATURE)
+    P, _, _ = tu.flow_euler(st, 2.0, 0.5, 6, v_max=1e30, flow_C=False)
+    off = np.abs(P).copy()
+    off[:, 0, 0] = 0.0
+    assert off.max() < 1e-12 * np.abs(P).max()
+    Um = basis.u_matrix(S, Lq, n_ref, st.U)
+    P0b = basis.p_to_band(_onsite_p0(st, V0), Um)
+    stb = tu.TUSetup(hop_R, hop_t, -0.4, 0 * V0, S, Lq, n_ref, cutoff.TEMPERATURE, P0=P0b, basis="band")
+    Pb, _, _ = tu.flow_euler(stb, 2.0, 0.5, 6, v_max=1e30, flow_C=False)
+    offb = np.abs(Pb).copy()
+    offb[:, 0, 0] = 0.0
+    assert offb.max() > 0.05 * np.abs(Pb).max()

@@ -65,19 +65,6 @@ template <typename T>
 struct V4 {
   T x, y, z, w;
 };
-// base: a wave-uniform row pointer, i: this lane's index in the row; the byte
-// offset is a 32-bit value (arrays stay below 4 GB), so the load can take a
-// scalar base plus a vector offset with no 64-bit address arithmetic per lane
-__device__ inline V4<float> ld4(const float *base, unsigned i) {
-  const float4 v = *(const float4 *)((const char *)base + (i * 16u));
-  return {v.x, v.y, v.z, v.w};
-}
-__device__ inline V4<double> ld4(const double *base, unsigned i) {
-  const double2 *p = (const double2 *)((const char *)base + (i * 32u));
-  const double2 a = p[0], b = p[1];
-  return {a.x, a.y, b.x, b.y};
-}
-
 // Raw buffer loads: a descriptor of an array of nbytes bytes (base address,
 // no stride, the gfx9-family data-format bits in the last word), a wave-uniform
 // byte offset and a per-lane 32-bit byte offset.
@@ -94,6 +81,12 @@ __device__ inline i32x4 make_rsrc(const T *p, unsigned nbytes) {
 __device__ inline V4<float> ld4_buf(i32x4 r, unsigned voff, unsigned soff) {
   const f32x4v v = raw_buffer_load_v4f32(r, (int)voff, (int)soff, 0);
   return {v[0], v[1], v[2], v[3]};
+}
+// four doubles: two 16-byte loads
+__device__ inline V4<double> ld4d_buf(i32x4 r, unsigned voff, unsigned soff) {
+  const double2 a = __builtin_bit_cast(double2, raw_buffer_load_v4f32(r, (int)voff, (int)soff, 0));
+  const double2 b = __builtin_bit_cast(double2, raw_buffer_load_v4f32(r, (int)voff + 16, (int)soff, 0));
+  return {a.x, a.y, b.x, b.y};
 }
 
 // Loop body of one channel (CH = 0: pp, k' = q - k; CH = 1: ph, k' = k - q).
@@ -120,9 +113,9 @@ __device__ inline void loop_no2_body(const T *__restrict__ ekv, const T *__restr
   struct Pt {
     V4<T> ek, pk, cv;
   };
-  // point (row, col) of a k-major array: row = kx (wave-uniform), col = ky (per lane).
-  // FP32: raw buffer loads, descriptor and row offset in scalar registers, the
-  // lane's 32-bit byte offset as the only vector operand
+  // point (row, col) of a k-major array: row = kx (wave-uniform), col = ky (per lane):
+  // raw buffer loads, descriptor and row offset in scalar registers, the lane's
+  // 32-bit byte offset as the only vector operand
   const unsigned nbytes = (unsigned)Lf * Lf * 4u * (unsigned)sizeof(T);
   const auto rs_e = make_rsrc(ekv, nbytes), rs_p = make_rsrc(pi4, nbytes);
   const auto rs_c = make_rsrc(SHELL ? cvp : ekv, nbytes);
@@ -133,10 +126,10 @@ __device__ inline void loop_no2_body(const T *__restrict__ ekv, const T *__restr
       p.pk = ld4_buf(rs_p, voff, soff);
       if constexpr (SHELL) p.cv = ld4_buf(rs_c, voff, soff);
     } else {
-      const size_t rb = (size_t)row * Lf * 4;
-      p.ek = ld4(ekv + rb, col);
-      p.pk = ld4(pi4 + rb, col);
-      if constexpr (SHELL) p.cv = ld4(cvp + rb, col);
+      const unsigned soff = row * (unsigned)Lf * 32u, voff = col * 32u;
+      p.ek = ld4d_buf(rs_e, voff, soff);
+      p.pk = ld4d_buf(rs_p, voff, soff);
+      if constexpr (SHELL) p.cv = ld4d_buf(rs_c, voff, soff);
     }
   };
   // k' row of the next kx

@@ -92,6 +92,10 @@ __device__ inline double rcp_fast(double d) {
 __device__ inline float rcp_fast(float d) { return __builtin_amdgcn_rcpf(d); }
 
 // sech^2(x) and tanh(x) from s = exp(-2|x|), stable for every x.
+// 1 / x: exact division in FP64, the hardware reciprocal in FP32
+__device__ inline double rdiv(double x) { return 1.0 / x; }
+__device__ inline float rdiv(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <typename T>
 __device__ inline void sech2_tanh(T x, T &sech2, T &th) {
   T ax = fabs(x);
@@ -113,8 +117,8 @@ __device__ inline T cut_val(T e, T lam, int scheme, int deriv) {
   }
   T a = fabs(e);
   T d = a + lam;
-  if (deriv) return -e * (T(3) * a + lam) / (T(4) * d * d * d);
-  return e * (T(2) * a + lam) / (T(4) * d * d);
+  if (deriv) return -e * (T(3) * a + lam) * rdiv(T(4) * d * d * d);
+  return e * (T(2) * a + lam) * rdiv(T(4) * d * d);
 }
 
 // d/de of cut_val.
@@ -130,8 +134,8 @@ __device__ inline T cut_der(T e, T lam, int scheme, int deriv) {
   T a = fabs(e);
   T d = a + lam;
   T d2 = d * d;
-  if (deriv) return (T(3) * e * e - T(4) * a * lam - lam * lam) / (T(4) * d2 * d2);
-  return lam * (T(3) * a + lam) / (T(4) * d2 * d);
+  if (deriv) return (T(3) * e * e - T(4) * a * lam - lam * lam) * rdiv(T(4) * d2 * d2);
+  return lam * (T(3) * a + lam) * rdiv(T(4) * d2 * d);
 }
 
 template <typename T>
@@ -142,8 +146,10 @@ __device__ inline T gl2_mean(T a, T b, T lam, int scheme, int deriv) {
 }
 
 // Relative width below which the divided difference switches to the mean of
-// the derivative.  FP64: 1e-3; FP32: 5e-2 (cancellation in the quotient costs
-// eps / width, the two-point rule (width / 2)^4 / 135).
+// the derivative.  FP64: 1e-3; FP32: 2e-2 (cancellation in the quotient costs
+// about eps / width = 3e-6 at the switch, the two-point rule (width / 2)^4 /
+// 135; a wider switch sends more lanes, and with them whole waves, through the
+// slower branch: at 5e-2 the Rashba loop ran 6 % slower with the same error).
 template <typename T>
 struct degen_rel;
 template <>
@@ -152,7 +158,7 @@ struct degen_rel<double> {
 };
 template <>
 struct degen_rel<float> {
-  static constexpr float v = 5e-2f;
+  static constexpr float v = 2e-2f;
 };
 
 // (g(x) - g(y)) / (x - y) given gx = g(x), gy = g(y).

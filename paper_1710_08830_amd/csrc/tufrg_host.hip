@@ -820,10 +820,9 @@ extern "C" tufrg_status tufrg_basis_matrix(tufrg_ctx *c, int32_t channel, const 
   box = box <= 2 ? 2 : 4;
   const size_t per_q = basis_rows_doubles(c->n_o, c->Lf, box, 1);
   const int q_chunk = (int)std::max<size_t>(1, std::min<size_t>(c->Nq, ((size_t)1 << 27) / per_q));
-  if (!c->d_basis_c) {
-    TRY(dalloc(c, &c->d_basis_c, 2 * (size_t)c->Nq * c->nD * c->no4));
-    TRY(dalloc(c, &c->d_basis_rows, per_q * q_chunk));
-  }
+  // each buffer on its own: a failed allocation leaves the other usable and is retried next call
+  if (!c->d_basis_c) TRY(dalloc(c, &c->d_basis_c, 2 * (size_t)c->Nq * c->nD * c->no4));
+  if (!c->d_basis_rows) TRY(dalloc(c, &c->d_basis_rows, per_q * q_chunk));
   HIPCHK(c, launch_basis_compact(channel, c->n_o, c->Lq, c->n_ref, c->nD, box, c->d_dlist, (const double *)U,
                                  c->d_twf, c->d_basis_rows, q_chunk, c->d_basis_c, c->st));
   HIPCHK(c, launch_loop_expand(c->n_o, c->n_ff, c->nD, c->Nq, c->d_didx, c->d_basis_c, (double *)M, c->st));
@@ -958,10 +957,8 @@ extern "C" tufrg_status tufrg_set_initial_c(tufrg_ctx *c, const tufrg_c64 *C0) {
   }
   if (!is_device_ptr(C0)) return fail(c, TUFRG_E_INVAL, "C0 must be a device pointer");
   const size_t n = 2 * (size_t)c->Nq * c->B * c->B;
-  if (!c->d_c0) {
-    TRY(dalloc(c, &c->d_c0, n));
-    TRY(dalloc(c, &c->d_ceff, n));
-  }
+  if (!c->d_c0) TRY(dalloc(c, &c->d_c0, n));
+  if (!c->d_ceff) TRY(dalloc(c, &c->d_ceff, n));
   HIPCHK(c, hipMemcpyAsync(c->d_c0, C0, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   c->has_c0 = true;
   return TUFRG_OK;
@@ -975,10 +972,8 @@ extern "C" tufrg_status tufrg_set_initial_p(tufrg_ctx *c, const tufrg_c64 *P0) {
   }
   if (!is_device_ptr(P0)) return fail(c, TUFRG_E_INVAL, "P0 must be a device pointer");
   const size_t n = 2 * (size_t)c->Nq * c->B * c->B;
-  if (!c->d_p0) {
-    TRY(dalloc(c, &c->d_p0, n));
-    TRY(dalloc(c, &c->d_peff, n));
-  }
+  if (!c->d_p0) TRY(dalloc(c, &c->d_p0, n));
+  if (!c->d_peff) TRY(dalloc(c, &c->d_peff, n));
   HIPCHK(c, hipMemcpyAsync(c->d_p0, P0, n * sizeof(double), hipMemcpyDeviceToDevice, c->st));
   c->has_p0 = true;
   return TUFRG_OK;
@@ -1201,12 +1196,10 @@ extern "C" tufrg_status tufrg_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg
   }
 
   // Dormand-Prince 5(4) in l = ln Lambda, dX/dl = Lambda dX/dLambda
-  if (c->d_stage.empty()) {
-    for (int i = 0; i < 16; ++i) {
-      double *p = nullptr;
-      TRY(dalloc(c, &p, ns));
-      c->d_stage.push_back(p);
-    }
+  while (c->d_stage.size() < 16) {  // resumes after a failed allocation
+    double *p = nullptr;
+    TRY(dalloc(c, &p, ns));
+    c->d_stage.push_back(p);
   }
   double *kP[7], *kC[7];
   for (int j = 0; j < 7; ++j) {

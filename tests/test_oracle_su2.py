@@ -1,0 +1,65 @@
+"""Pins of the SU(2)-reduced equations (oracle, CPU).
+
+The reduced right-hand side and flow of ``oracle.su2`` are checked against
+the spinful orbital-basis equations of ``oracle.tufrg`` (spin as the orbital
+index of a spin-degenerate Hubbard model): the spinful right-hand side of an
+SU(2)-structured state must be the embedding of the reduced one, in both
+spin structures, and a whole Euler flow from the bare interaction must agree.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import cutoff, su2
+from oracle import tufrg as tu
+from synth import ff_shell, hubbard_hoppings, onsite_V0
+
+
+def _setups(n_ff, scheme, Lq=6, n_ref=2, U=3.0):
+    hop_R, hop_t = hubbard_hoppings(1.0, -0.25)
+    S = ff_shell(n_ff)
+    stS = tu.TUSetup(hop_R, hop_t, -0.6, onsite_V0(U), S, Lq, n_ref, scheme)
+    st1 = tu.TUSetup(hop_R, hop_t[:, :1, :1], -0.6, np.zeros((1, 1, 1, 1)), S, Lq, n_ref, scheme)
+    return stS, st1
+
+
+def _random(st, seed):
+    rng = np.random.default_rng(seed)
+    sh = (st.Nq, st.n_ff, st.n_ff)
+    return [0.2 * (rng.normal(size=sh) + 1j * rng.normal(size=sh)) for _ in range(3)]
+
+
+def test_exchange_map_is_an_involution():
+    stS, _ = _setups(9, cutoff.TEMPERATURE)
+    X = _random(stS, 1)[0]
+    assert np.allclose(su2.exch(stS, su2.exch(stS, X)), X, atol=1e-15)
+
+
+@pytest.mark.parametrize("n_ff", [5, 9])
+@pytest.mark.parametrize("scheme", [cutoff.TEMPERATURE, cutoff.OMEGA])
+def test_spinful_rhs_of_an_su2_state_is_the_reduced_rhs(n_ff, scheme):
+    stS, st1 = _setups(n_ff, scheme)
+    p, c, d = _random(stS, 7)
+    dP, dC = tu.rhs(stS, 0.4, su2.embed_p(stS, p), su2.embed_c(c, d))
+    dp, dc, dd = su2.rhs(stS, st1, 0.4, p, c, d)
+    scale = max(np.abs(dP).max(), np.abs(dC).max())
+    # both spin structures, so the spinful flow stays SU(2)-structured
+    assert np.abs(dP - su2.embed_p(stS, dp)).max() < 1e-13 * scale
+    assert np.abs(dC - su2.embed_c(dc, dd)).max() < 1e-13 * scale
+
+
+def test_reduced_euler_flow_reproduces_the_spinful_flow():
+    stS, st1 = _setups(9, cutoff.TEMPERATURE, U=2.5)
+    lam0, lam_end, n = 4.0, 0.3, 12
+    P, C, _ = tu.flow_euler(stS, lam0, lam_end, n, v_max=1e30)
+    grid = tu.log_grid(lam0, lam_end, n)
+    p = np.zeros((stS.Nq, stS.n_ff, stS.n_ff), dtype=np.complex128)
+    c, d = p.copy(), p.copy()
+    for i in range(n):
+        dp, dc, dd = su2.rhs(stS, st1, grid[i], p, c, d)
+        h = grid[i + 1] - grid[i]
+        p, c, d = p + h * dp, c + h * dc, d + h * dd
+    scale = max(np.abs(P).max(), np.abs(C).max())
+    assert np.abs(P - su2.embed_p(stS, p)).max() < 1e-12 * scale
+    assert np.abs(C - su2.embed_c(c, d)).max() < 1e-12 * scale
+    assert np.abs(p).max() > 1e-3 and np.abs(c).max() > 1e-3 and np.abs(d).max() > 1e-3

@@ -23,11 +23,22 @@ the d13 d24 and d14 d23 parts of VC:
     dd/dLambda = -2 d~ Lph d~
 
 (products of n_ff x n_ff matrices per q; the d14 d23 part of dP is -(dp)x
-again, since x is an involution).  The reduced projected vertices are taken
-here from the spinful projections of the embedded state (the definition);
-the loops are those of the one-band model.  The paper cites these equations
-without printing them, so this is a re-derivation, pinned in the tests
-against the spinful right-hand side.
+again, since x is an involution).  The loops are those of the one-band model.
+
+The reduced projected vertices follow from the cross projections of Sec. 3.2
+(linear in the propagators, the spin indices carried along, and the 3 <-> 4
+exchange of the D terms swapping the two spin structures).  With the onsite
+bare vertex v (d13 d24 - d14 d23) and the scalar maps
+    PC(X)^{RR'}(s) = sum_R'' e^{is.R''} X^{R+R'', R'-R''}(R'')
+    PD(X)^{RR'}(s) = e^{is.R'} sum_R'' e^{is.R''} X^{R+R'', -R'-R''}(R'')
+    CP(X)^{RR'}(u) = sum_R'' e^{iu.R''} X^{R+R'', R'-R''}(R'')
+    CD(X)^{RR'}(u) = sum_R'' e^{iu.R''} X^{R-R'+R'', R''}(-R')
+(X(R'') the coarse-mesh Fourier transform) they are
+    a~ = p + v + PC(c) + PD(d)
+    c~ = c + v + CP(p) + CD(d)
+    d~ = d + v + CP(p^x) + CD(c).
+The paper cites these equations without printing them, so this is a
+re-derivation, pinned in the tests against the spinful equations.
 """
 
 import numpy as np
@@ -79,16 +90,69 @@ def _mm(A, B):
     return np.einsum("qij,qjk->qik", A, B)
 
 
-def rhs(st_spin, st_one, lam, p, c, d):
-    """Reduced right-hand side (dp, dc, dd); st_spin: the spinful setup (for the
-    projections), st_one: the one-band setup with the same dispersion (loops)."""
-    VP, VC = tu.projected_vertices(st_spin, embed_p(st_spin, p), embed_c(c, d))
-    a = reduce_p(VP)
-    ct, dt = reduce_c(VC)
-    Lpp = tu.loops(st_one, "pp", lam)[..., 0, 0, 0, 0]
-    Lph = tu.loops(st_one, "ph", lam)[..., 0, 0, 0, 0]
-    ax = exch(st_spin, a)
+def _cross_maps(st, p, c, d):
+    """The scalar cross projections that enter a~, c~ and d~ (one orbital)."""
+    real = {name: tu.to_real_space(st, X) for name, X in
+            (("p", p), ("px", exch(st, p)), ("c", c), ("d", d))}
+    out = {k: np.zeros_like(p) for k in ("PC_c", "PD_d", "CP_p", "CP_px", "CD_d", "CD_c")}
+    for i, R in enumerate(st.S):
+        for j, Rp in enumerate(st.S):
+            phRp = st.coarse_phase(Rp)
+            for r, R2 in st.D.items():
+                ph = st.coarse_phase(R2)
+                a, b = st.ff_index(R + R2), st.ff_index(Rp - R2)
+                if a >= 0 and b >= 0:
+                    out["PC_c"][:, i, j] += ph * real["c"][r][a, b]
+                    out["CP_p"][:, i, j] += ph * real["p"][r][a, b]
+                    out["CP_px"][:, i, j] += ph * real["px"][r][a, b]
+                a, b = st.ff_index(R + R2), st.ff_index(-Rp - R2)
+                if a >= 0 and b >= 0:
+                    out["PD_d"][:, i, j] += phRp * ph * real["d"][r][a, b]
+            rneg = st._res(-Rp)
+            for b, R2 in enumerate(st.S):
+                a = st.ff_index(R - Rp + R2)
+                if a >= 0:
+                    ph = st.coarse_phase(R2)
+                    out["CD_d"][:, i, j] += ph * real["d"][rneg][a, b]
+                    out["CD_c"][:, i, j] += ph * real["c"][rneg][a, b]
+    return out
+
+
+def projected(st, p, c, d):
+    """(a~, c~, d~) of the reduced state; st: the one-band setup, whose V0
+    [1,1,1,1] holds the onsite coefficient v."""
+    if st.n_o != 1 or st.C0 is not None or st.P0 is not None:
+        raise ValueError("a one-orbital setup with an onsite bare vertex only")
+    v = st.V0[0, 0, 0, 0]
+    m = _cross_maps(st, p, c, d)
+    a = p + m["PC_c"] + m["PD_d"]
+    ct = c + m["CP_p"] + m["CD_d"]
+    dt = d + m["CP_px"] + m["CD_c"]
+    for X in (a, ct, dt):
+        X[:, 0, 0] += v
+    return a, ct, dt
+
+
+def rhs(st, lam, p, c, d):
+    """Reduced right-hand side (dp, dc, dd) on the one-band setup st."""
+    a, ct, dt = projected(st, p, c, d)
+    Lpp = tu.loops(st, "pp", lam)[..., 0, 0, 0, 0]
+    Lph = tu.loops(st, "ph", lam)[..., 0, 0, 0, 0]
+    ax = exch(st, a)
     dp = -(_mm(_mm(a, Lpp), ax) + _mm(_mm(ax, Lpp), a))
     dc = 2.0 * (2.0 * _mm(_mm(ct, Lph), ct) - _mm(_mm(ct, Lph), dt) - _mm(_mm(dt, Lph), ct))
     dd = -2.0 * _mm(_mm(dt, Lph), dt)
     return dp, dc, dd
+
+
+def flow_euler(st, lam0, lam_end, n_steps):
+    """Euler steps of the reduced flow on the logarithmic grid of the spinful
+    integrator, from p = c = d = 0."""
+    grid = tu.log_grid(lam0, lam_end, n_steps)
+    p = np.zeros((st.Nq, st.n_ff, st.n_ff), dtype=np.complex128)
+    c, d = p.copy(), p.copy()
+    for i in range(n_steps):
+        dp, dc, dd = rhs(st, grid[i], p, c, d)
+        h = grid[i + 1] - grid[i]
+        p, c, d = p + h * dp, c + h * dc, d + h * dd
+    return p, c, d

@@ -4,7 +4,8 @@ The reduced right-hand side and flow of ``oracle.su2`` are checked against
 the spinful orbital-basis equations of ``oracle.tufrg`` (spin as the orbital
 index of a spin-degenerate Hubbard model): the spinful right-hand side of an
 SU(2)-structured state must be the embedding of the reduced one, in both
-spin structures, and a whole Euler flow from the bare interaction must agree.
+spin structures (projected vertices and right-hand side), and a whole Euler
+flow from the bare interaction must agree.
 """
 
 import numpy as np
@@ -16,10 +17,13 @@ from synth import ff_shell, hubbard_hoppings, onsite_V0
 
 
 def _setups(n_ff, scheme, Lq=6, n_ref=2, U=3.0):
+    """Spinful setup and the one-band setup carrying the onsite coefficient U/2
+    of d13 d24 - d14 d23."""
     hop_R, hop_t = hubbard_hoppings(1.0, -0.25)
     S = ff_shell(n_ff)
     stS = tu.TUSetup(hop_R, hop_t, -0.6, onsite_V0(U), S, Lq, n_ref, scheme)
-    st1 = tu.TUSetup(hop_R, hop_t[:, :1, :1], -0.6, np.zeros((1, 1, 1, 1)), S, Lq, n_ref, scheme)
+    v = np.full((1, 1, 1, 1), 0.5 * U, dtype=np.complex128)
+    st1 = tu.TUSetup(hop_R, hop_t[:, :1, :1], -0.6, v, S, Lq, n_ref, scheme)
     return stS, st1
 
 
@@ -36,12 +40,22 @@ def test_exchange_map_is_an_involution():
 
 
 @pytest.mark.parametrize("n_ff", [5, 9])
+def test_reduced_projections_are_the_parts_of_the_spinful_ones(n_ff):
+    stS, st1 = _setups(n_ff, cutoff.TEMPERATURE)
+    p, c, d = _random(stS, 3)
+    VP, VC = tu.projected_vertices(stS, su2.embed_p(stS, p), su2.embed_c(c, d))
+    a, ct, dt = su2.projected(st1, p, c, d)
+    assert np.abs(VP - su2.embed_p(stS, a)).max() < 1e-13
+    assert np.abs(VC - su2.embed_c(ct, dt)).max() < 1e-13
+
+
+@pytest.mark.parametrize("n_ff", [5, 9])
 @pytest.mark.parametrize("scheme", [cutoff.TEMPERATURE, cutoff.OMEGA])
 def test_spinful_rhs_of_an_su2_state_is_the_reduced_rhs(n_ff, scheme):
     stS, st1 = _setups(n_ff, scheme)
     p, c, d = _random(stS, 7)
     dP, dC = tu.rhs(stS, 0.4, su2.embed_p(stS, p), su2.embed_c(c, d))
-    dp, dc, dd = su2.rhs(stS, st1, 0.4, p, c, d)
+    dp, dc, dd = su2.rhs(st1, 0.4, p, c, d)
     scale = max(np.abs(dP).max(), np.abs(dC).max())
     # both spin structures, so the spinful flow stays SU(2)-structured
     assert np.abs(dP - su2.embed_p(stS, dp)).max() < 1e-13 * scale
@@ -50,16 +64,16 @@ def test_spinful_rhs_of_an_su2_state_is_the_reduced_rhs(n_ff, scheme):
 
 def test_reduced_euler_flow_reproduces_the_spinful_flow():
     stS, st1 = _setups(9, cutoff.TEMPERATURE, U=2.5)
-    lam0, lam_end, n = 4.0, 0.3, 12
-    P, C, _ = tu.flow_euler(stS, lam0, lam_end, n, v_max=1e30)
-    grid = tu.log_grid(lam0, lam_end, n)
-    p = np.zeros((stS.Nq, stS.n_ff, stS.n_ff), dtype=np.complex128)
-    c, d = p.copy(), p.copy()
-    for i in range(n):
-        dp, dc, dd = su2.rhs(stS, st1, grid[i], p, c, d)
-        h = grid[i + 1] - grid[i]
-        p, c, d = p + h * dp, c + h * dc, d + h * dd
+    P, C, _ = tu.flow_euler(stS, 4.0, 0.3, 12, v_max=1e30)
+    p, c, d = su2.flow_euler(st1, 4.0, 0.3, 12)
     scale = max(np.abs(P).max(), np.abs(C).max())
     assert np.abs(P - su2.embed_p(stS, p)).max() < 1e-12 * scale
     assert np.abs(C - su2.embed_c(c, d)).max() < 1e-12 * scale
     assert np.abs(p).max() > 1e-3 and np.abs(c).max() > 1e-3 and np.abs(d).max() > 1e-3
+
+
+def test_projection_needs_a_one_orbital_setup():
+    stS, _ = _setups(5, cutoff.TEMPERATURE)
+    z = np.zeros((stS.Nq, 5, 5), dtype=np.complex128)
+    with pytest.raises(ValueError):
+        su2.projected(stS, z, z, z)

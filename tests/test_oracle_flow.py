@@ -9,6 +9,10 @@
   and a tight Dormand-Prince flow reproduces g_Lambda = -U / (1 + U int B).
 * Hermiticity of the exchange propagators along a flow from a hermitian V0
   (Sec. 2, property 3).
+* The Dormand-Prince 5(4) coefficients against the Runge-Kutta order
+  conditions (Butcher's rooted trees up to order 5 for the propagating
+  weights, up to order 4 for the embedded ones), consistency of the nodes and
+  first-same-as-last.
 """
 
 import numpy as np
@@ -98,6 +102,38 @@ def test_rashba_pp_only_euler_recursion_and_locality():
     assert np.abs(P[:, 0, 0] - expected).max() < 1e-12 * np.abs(expected).max()
 
 
+def _order_conditions(A, b, c, order):
+    """Residuals of the Runge-Kutta order conditions for the rooted trees up to
+    the given order (elementary weights against 1 / tree factorial)."""
+    A, b, c = np.asarray(A), np.asarray(b), np.asarray(c)
+    one = np.ones_like(c)
+    Ac, Ac2, Ac3, AAc = A @ c, A @ c**2, A @ c**3, A @ (A @ c)
+    trees = [
+        (1, b @ one, 1.0),
+        (2, b @ c, 1 / 2),
+        (3, b @ c**2, 1 / 3), (3, b @ Ac, 1 / 6),
+        (4, b @ c**3, 1 / 4), (4, b @ (c * Ac), 1 / 8), (4, b @ Ac2, 1 / 12), (4, b @ AAc, 1 / 24),
+        (5, b @ c**4, 1 / 5), (5, b @ (c**2 * Ac), 1 / 10), (5, b @ (c * Ac2), 1 / 15),
+        (5, b @ (c * AAc), 1 / 30), (5, b @ (Ac * Ac), 1 / 20), (5, b @ Ac3, 1 / 20),
+        (5, b @ (A @ (c * Ac)), 1 / 40), (5, b @ (A @ Ac2), 1 / 60), (5, b @ (A @ AAc), 1 / 120),
+    ]
+    return [abs(v - want) for o, v, want in trees if o <= order]
+
+
+def test_dormand_prince_coefficients_satisfy_the_order_conditions():
+    n = len(tufrg._DP_B5)
+    A = np.zeros((n, n))
+    for i, row in enumerate(tufrg._DP_A):
+        A[i, :len(row)] = row
+    c = np.asarray(tufrg._DP_C, dtype=np.float64)
+    assert np.allclose(A.sum(axis=1), c, atol=1e-15, rtol=0)   # nodes are the row sums
+    assert np.array_equal(A[-1], tufrg._DP_B5)                  # first same as last
+    assert max(_order_conditions(A, tufrg._DP_B5, c, 5)) < 1e-14
+    assert max(_order_conditions(A, tufrg._DP_B4, c, 4)) < 1e-14
+    # the embedded pair differs: its fifth-order residual is the error estimate
+    assert max(_order_conditions(A, tufrg._DP_B4, c, 5)) > 1e-4
+
+
 def test_rashba_pp_only_matches_analytic_solution():
     U = 2.5
     st = _rashba_pp_setup(U)
@@ -122,3 +158,4 @@ def test_exchange_propagators_stay_hermitian_along_flow():
     for M in (p_to_matrix(P), c_to_matrix(C)):
         assert np.abs(M).max() > 1e-3
         assert np.abs(M - M.conj().transpose(0, 2, 1)).max() < 1e-13 * np.abs(M).max()
+

@@ -8,6 +8,10 @@
   B(0) of Sec. 5 is the temperature derivative of the textbook Cooper bubble
   (1/N) sum_k tanh(e_k / 2T) / (2 e_k).
 * The loops are hermitian: conj(L^{R1R2}_{t1t2t3t4}) = L^{R2R1}_{t3t4t1t2}.
+* The Bloch Hamiltonian of the Rashba hoppings is the closed form
+  f(k) 1 + alpha (-sin ky sigma_x + sin kx sigma_y) (Sec. 5), whose spin part
+  is odd in k (this fixes the sign of the Fourier convention), and its bands
+  are f(k) +- alpha |(sin kx, sin ky)|.
 """
 
 import numpy as np
@@ -118,3 +122,21 @@ def test_loops_are_hermitian(channel):
     for qi in (0, 3, 13):
         Lm = tufrg.loop_matrix(st, channel, qi, 0.2)
         assert np.abs(Lm.conj() - Lm.transpose(1, 0, 4, 5, 2, 3)).max() < 1e-14
+
+
+def test_rashba_bloch_hamiltonian_in_closed_form():
+    t, alpha, tp, L = 1.0, 0.3, 0.1, 12
+    hop_R, hop_t = rashba_hoppings(t, alpha, tp)
+    H = bands.bloch_hamiltonian(hop_R, hop_t, L)
+    k = 2.0 * np.pi * bands.mesh(L) / L
+    kx, ky = k[:, 0], k[:, 1]
+    f = -2.0 * t * (np.cos(kx) + np.cos(ky)) - 4.0 * tp * np.cos(kx) * np.cos(ky)
+    sx = np.array([[0, 1], [1, 0]], dtype=np.complex128)
+    sy = np.array([[0, -1j], [1j, 0]], dtype=np.complex128)
+    want = (f[:, None, None] * np.eye(2) + alpha * (-np.sin(ky)[:, None, None] * sx
+                                                    + np.sin(kx)[:, None, None] * sy))
+    assert np.abs(H - want).max() < 1e-14
+    e, U = bands.band_data(hop_R, hop_t, 0.25, L)
+    g = alpha * np.hypot(np.sin(kx), np.sin(ky))
+    assert np.abs(e - np.stack([f - g, f + g], axis=1) + 0.25).max() < 1e-13
+    assert np.abs(np.einsum("kab,kbl->kal", H, U) - U * (e + 0.25)[:, None, :]).max() < 1e-13

@@ -77,3 +77,13 @@ def test_projection_needs_a_one_orbital_setup():
     z = np.zeros((stS.Nq, 5, 5), dtype=np.complex128)
     with pytest.raises(ValueError):
         su2.projected(stS, z, z, z)
+
+
+@pytest.mark.parametrize("n_ff", [5, 9, 13])
+def test_direct_p_projection_of_a_crossed_term_is_its_exchange(n_ff):
+    """P_D(X) = (P_C(X))^x: both gather X^{R+R'', -R'-R''}(R''), P_D with the
+    extra phase exp(is.R')."""
+    stS, st1 = _setups(n_ff, cutoff.TEMPERATURE, Lq=8)
+    p, c, d = _random(stS, 11)
+    m = su2._cross_maps(st1, p, d, d)   # c = d: PC_c and PD_d act on the same X
+    assert np.abs(su2.exch(st1, m["PC_c"]) - m["PD_d"]).max() < 1e-14

@@ -69,6 +69,14 @@ MUTATIONS = [
  ("mlp.py", "d = 2.0 * (Y - T) / (n * n_out)", "d = 2.0 * (Y - T) / n", "loss gradient scale"),
  ("mlp.py", "d = d * gelu_deriv(pre[i])", "d = d * gelu(pre[i])", "backprop activation"),
  ("mlp.py", "y = np.log(np.asarray(s_tab, dtype=np.float64))", "y = np.asarray(s_tab, dtype=np.float64)", "scale table interpolation"),
+ ("tufrg.py", "        C = C + st.C0\n", "        C = C\n", "initial C0 not projected"),
+ ("tufrg.py", "        P = P + st.P0\n", "        P = P\n", "static P0 not projected"),
+ ("tufrg.py", "t = (v_max - m0) / (m1 - m0)", "t = (v_max - m1) / (m1 - m0)", "lambda_c interpolation"),
+ ("tufrg.py", "        if m > v_max:\n            res.update(diverged=1, lambda_stop=float(grid[i + 1]),",
+              "        if m > 2 * v_max:\n            res.update(diverged=1, lambda_stop=float(grid[i + 1]),", "Euler stop test"),
+ ("tufrg.py", "self.Pi = bands.projectors(np.broadcast_to(np.eye(self.n_o), self.U.shape))",
+              "self.Pi = bands.projectors(self.U)", "band basis keeps orbital projectors"),
+ ("su2.py", "            P[..., a, b, b, a] -= px", "            P[..., a, b, b, a] += px", "SU(2) embedding sign"),
 ]
 
 

@@ -7,6 +7,8 @@
 * Rashba model, particle-particle channel only, onsite U (Sec. 5): P stays
   local, every Euler step obeys the scalar recursion of the analytic solution,
   and a tight Dormand-Prince flow reproduces g_Lambda = -U / (1 + U int B).
+* The stop test max |P| > V_max and the critical scale on that exactly known
+  Euler trajectory.
 * Hermiticity of the exchange propagators along a flow from a hermitian V0
   (Sec. 2, property 3).
 * The Dormand-Prince 5(4) coefficients against the Runge-Kutta order
@@ -100,6 +102,35 @@ def test_rashba_pp_only_euler_recursion_and_locality():
         h = h + (grid[i + 1] - grid[i]) * (-h * h * B)
     expected = 0.5 * (h - U)[:, None, None, None, None] * A[None]
     assert np.abs(P[:, 0, 0] - expected).max() < 1e-12 * np.abs(expected).max()
+
+
+def test_stop_test_and_critical_scale_on_the_exact_euler_trajectory():
+    """The Rashba pp-only Euler flow follows the scalar recursion exactly, so
+    the step at which max |P| first exceeds V_max is known in advance; Lambda_c
+    lies between the last two grid points and moves to the earlier one as V_max
+    approaches the value reached there."""
+    U = 2.5
+    st = _rashba_pp_setup(U)
+    lam0, lam1, n = 10.0, 0.05, 12
+    A = _A()
+    grid = tufrg.log_grid(lam0, lam1, n)
+    h = np.full(st.Nq, U, dtype=np.complex128)
+    m = [0.0]
+    for i in range(n):
+        B = np.array([0.5 * np.sum(A * tufrg.loop_matrix(st, "pp", qi, grid[i])[0, 0])
+                      for qi in range(st.Nq)])
+        h = h + (grid[i + 1] - grid[i]) * (-h * h * B)
+        m.append(float(np.abs(0.5 * (h - U)).max() * np.abs(A).max()))
+    assert all(b > a for a, b in zip(m, m[1:]))
+    i_stop = 7
+    for v_max in (0.5 * (m[i_stop - 1] + m[i_stop]), m[i_stop - 1] * (1 + 1e-9)):
+        P, C, res = tufrg.flow_euler(st, lam0, lam1, n, v_max=v_max, flow_C=False)
+        assert res["diverged"] == 1 and res["n_steps"] == i_stop
+        assert res["lambda_stop"] == grid[i_stop]
+        assert grid[i_stop] <= res["lambda_c"] <= grid[i_stop - 1]
+    assert abs(res["lambda_c"] - grid[i_stop - 1]) < 1e-6 * grid[i_stop - 1]
+    P, C, res = tufrg.flow_euler(st, lam0, lam1, n, v_max=1.01 * m[-1], flow_C=False)
+    assert res["diverged"] == 0 and res["lambda_c"] == 0.0 and res["n_steps"] == n
 
 
 def _order_conditions(A, b, c, order):

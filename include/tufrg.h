@@ -59,8 +59,12 @@
  * owns its band data, tables and workspaces.
  *
  * All calls are enqueued on the stream given to tufrg_create and are
- * asynchronous, except tufrg_create (synchronous) and tufrg_flow, which
- * synchronises once per step to read back the stop test (a few bytes).
+ * asynchronous, except these, which synchronise that stream: tufrg_create and
+ * tufrg_destroy; tufrg_flow and tufrg_batch_flow, once per step, to read back
+ * the stop test (a few bytes); tufrg_ff_apply (its W is a host array);
+ * tufrg_timing and tufrg_timing_read; tufrg_sur_targets when max_abs is
+ * requested; and the network calls that return host values or reshape their
+ * buffers (tufrg_mlp_create, _destroy, _loss_grad, _train).
  * A context must be used by one host thread at a time.  No exception or abort
  * crosses the ABI: failures return a status, and tufrg_last_error() returns a
  * message (per context, or the calling thread's last create failure for NULL).
@@ -190,7 +194,10 @@ tufrg_status tufrg_set_initial_c(tufrg_ctx *ctx, const tufrg_c64 *C0);
  * + ky, Nf * n_o^2 tufrg_c64 on the device, unitary per k (not checked).
  * tufrg_basis_matrix writes M [Nq][B][B] (device) for channel TUFRG_PP (U
  * matrix) or TUFRG_PH (X matrix); every entry is a fixed-order FP64 k-sum.
- * Errors: E_INVAL for an unknown channel or a host pointer. */
+ * Workspaces (a compact [2][Nq][n_dR][n_o^4] table and a row buffer of at
+ * most 1 GiB) are allocated on the first call and kept with the context.
+ * Errors: E_INVAL for an unknown channel or a host pointer, E_NOMEM when a
+ * workspace cannot be allocated (retried on the next call). */
 tufrg_status tufrg_basis_matrix(tufrg_ctx *ctx, int32_t channel, const tufrg_c64 *U, tufrg_c64 *M);
 
 /* Y[q] = M[q]^H X[q] M[q] (to_orbital = 0: orbital -> band) or
@@ -218,7 +225,9 @@ tufrg_status tufrg_basis_apply(tufrg_ctx *ctx, const tufrg_c64 *M, const tufrg_c
  * tufrg_ff_apply: Y[q] = X~ (to_plane_waves = 0) or the converse (1) for
  * [Nq][B][B] device arrays in the bundle layout (P or C alike: the orbital
  * pairs are untouched); W host [n_ff][n_ff].  Synchronises the context's
- * stream.  Errors: E_INVAL for host X/Y, overlapping X and Y. */
+ * stream.  A 25 x 25 device copy of W is allocated on the first call and
+ * kept.  Errors: E_INVAL for a null or device W, host X/Y, overlapping X and
+ * Y; E_NOMEM when the copy of W cannot be allocated. */
 tufrg_status tufrg_ff_symmetrize(int32_t n_ff, const int32_t *ff_R, tufrg_c64 *W, int32_t *irrep);
 tufrg_status tufrg_ff_apply(tufrg_ctx *ctx, const tufrg_c64 *W, const tufrg_c64 *X, tufrg_c64 *Y,
                             int32_t to_plane_waves);

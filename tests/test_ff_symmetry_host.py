@@ -40,3 +40,25 @@ def test_library_rejects_sets_it_cannot_symmetrise(T, S, status):
 
 def test_ff_apply_rejects_a_null_context(T):
     assert T._lib.tufrg_ff_apply(None, None, None, None, 0) == 1
+
+
+def _orbit(kind, d):
+    if kind == "axis":
+        return [(d, 0), (-d, 0), (0, d), (0, -d)]
+    return [(d, d), (-d, -d), (d, -d), (-d, d)]
+
+
+@pytest.mark.parametrize("mask", range(1, 16))
+@pytest.mark.parametrize("origin", [True, False])
+def test_library_rows_match_the_oracle_for_every_union_of_orbits(T, mask, origin):
+    orbits = [("axis", 1), ("diag", 1), ("axis", 2), ("diag", 2)]
+    pts = [(0, 0)] if origin else []
+    for bit, (kind, d) in enumerate(orbits):
+        if mask >> bit & 1:
+            pts += _orbit(kind, d)
+    rng = np.random.default_rng(100 * mask + origin)
+    S = np.array(pts, dtype=np.int32)[rng.permutation(len(pts))]
+    W, lab = T.tufrg_ff_symmetrize(S)
+    Wo, labo = sy.symmetric_ff(S)
+    assert list(lab) == list(labo)
+    assert np.allclose(W, Wo, atol=1e-15)

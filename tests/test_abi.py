@@ -37,3 +37,20 @@ def test_binding_covers_header():
     from paper_1710_08830_amd import tufrg
 
     assert sorted(tufrg.SYMBOLS) == declared_functions()
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """No fallback: importing the binding from a package copy that lacks
+    libtufrg.so raises ImportError naming the missing file."""
+    import shutil
+    import subprocess
+    import sys
+    pkg = tmp_path / "paper_1710_08830_amd"
+    pkg.mkdir()
+    for f in ("__init__.py", "tufrg.py"):
+        shutil.copy(os.path.join(ROOT, "paper_1710_08830_amd", f), pkg / f)
+    r = subprocess.run([sys.executable, "-c", "import paper_1710_08830_amd.tufrg"], cwd=tmp_path,
+                       capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, PYTHONPATH=str(tmp_path)))
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr and "libtufrg.so is missing" in r.stderr

@@ -87,3 +87,23 @@ def test_direct_p_projection_of_a_crossed_term_is_its_exchange(n_ff):
     p, c, d = _random(stS, 11)
     m = su2._cross_maps(st1, p, d, d)   # c = d: PC_c and PD_d act on the same X
     assert np.abs(su2.exch(st1, m["PC_c"]) - m["PD_d"]).max() < 1e-14
+
+
+@pytest.mark.parametrize("scheme", [cutoff.TEMPERATURE, cutoff.OMEGA])
+def test_second_order_right_hand_side_in_closed_form(scheme):
+    """At p = c = d = 0 with the onsite coefficient v: a~ = c~ = d~ = v in the
+    (0,0) block, so dp = -2 v^2 Lpp, dc = 2 (2 - 1 - 1) v^2 Lph = 0 (equal-spin
+    onsite scattering cancels) and dd = -2 v^2 Lph, all in the (0,0) block."""
+    _, st1 = _setups(9, scheme, U=3.0)
+    v, lam = 1.5, 0.4
+    z = np.zeros((st1.Nq, 9, 9), dtype=np.complex128)
+    dp, dc, dd = su2.rhs(st1, lam, z, z, z)
+    Lpp = tu.loops(st1, "pp", lam)[:, 0, 0, 0, 0, 0, 0]
+    Lph = tu.loops(st1, "ph", lam)[:, 0, 0, 0, 0, 0, 0]
+    assert np.abs(dp[:, 0, 0] + 2 * v * v * Lpp).max() < 1e-14
+    assert np.abs(dd[:, 0, 0] + 2 * v * v * Lph).max() < 1e-14
+    assert np.abs(dc).max() < 1e-14 and np.abs(Lph).max() > 1e-3
+    for X in (dp, dd):
+        rest = X.copy()
+        rest[:, 0, 0] = 0
+        assert np.abs(rest).max() == 0

@@ -153,7 +153,7 @@ const char *tufrg_last_error(const tufrg_ctx *ctx);
 /* Sizes: B, Nq, Nf, and the number of distinct R1 - R2 differences. */
 tufrg_status tufrg_dims(const tufrg_ctx *ctx, int32_t *B, int32_t *Nq, int32_t *Nf, int32_t *n_dR);
 
-/* Band data (row a0 of the hot path, built by tufrg_create): e[m][k] = E_m(k) - mu
+/* Band data (diagonalisation of H(k), Sec. 4.1, built by tufrg_create): e[m][k] = E_m(k) - mu
  * (ascending in m) and the projectors Pi[m][k][a][c] = U_am(k) conj(U_cm(k)),
  * k = kx * Lf + ky.  Device arrays of n_o * Nf doubles and n_o * Nf * n_o^2
  * tufrg_c64. */

@@ -145,6 +145,8 @@ for _f in ("tufrg_create", "tufrg_destroy", "tufrg_dims", "tufrg_band_data", "tu
 
 
 class TufrgError(RuntimeError):
+    """A status other than TUFRG_OK, with the library's message."""
+
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
         self.status = status
@@ -222,14 +224,17 @@ class Context:
 
 
 def tufrg_band_data(ctx, e, Pi):
+    """Band energies e [n_o][Nf] (float64) and projectors Pi [n_o][Nf][n_o][n_o] (complex128), device."""
     _check(_lib.tufrg_band_data(ctx.handle, _ptr(e), _ptr(Pi)), ctx.handle)
 
 
 def tufrg_bubble(ctx, channel, lam, deriv, L):
+    """Loop (deriv) or bubble matrices L [Nq][B][B] of channel PP or PH at scale lam, device."""
     _check(_lib.tufrg_bubble(ctx.handle, int(channel), float(lam), int(deriv), _ptr(L)), ctx.handle)
 
 
 def tufrg_project(ctx, P, C, VP, VC):
+    """Projected vertices VP, VC [Nq][B][B] of the state P, C, all on the device."""
     _check(_lib.tufrg_project(ctx.handle, _ptr(P), _ptr(C), _ptr(VP), _ptr(VC)), ctx.handle)
 
 
@@ -274,6 +279,7 @@ def tufrg_set_initial_p(ctx, P0):
 
 
 def tufrg_rhs(ctx, lam, P, C, dP, dC):
+    """Right-hand side dP, dC [Nq][B][B] at scale lam; outputs must not overlap P, C."""
     _check(_lib.tufrg_rhs(ctx.handle, float(lam), _ptr(P), _ptr(C), _ptr(dP), _ptr(dC)), ctx.handle)
 
 
@@ -293,6 +299,7 @@ def tufrg_flow(ctx, P, C, lambda0, lambda_end, n_steps=0, rtol=1e-6, atol=1e-6, 
 
 
 def tufrg_timing(ctx, enable):
+    """Switch the per-stage event timers of the context on or off."""
     _check(_lib.tufrg_timing(ctx.handle, int(bool(enable))), ctx.handle)
 
 
@@ -352,14 +359,17 @@ class Mlp:
 
 
 def tufrg_mlp_params(net, out):
+    """Copy the flat parameter vector (float32, device) into out."""
     net._check(_lib.tufrg_mlp_params(net.handle, _ptr(out)))
 
 
 def tufrg_mlp_set_params(net, params):
+    """Set the flat parameter vector (float32, device); resets the Adam moments."""
     net._check(_lib.tufrg_mlp_set_params(net.handle, _ptr(params)))
 
 
 def tufrg_mlp_forward(net, X, Y):
+    """Y [n][n_out] = net(X [n][n_in]), float32 device arrays."""
     net._check(_lib.tufrg_mlp_forward(net.handle, int(X.shape[0]), _ptr(X), _ptr(Y)))
 
 
@@ -372,6 +382,7 @@ def tufrg_mlp_loss_grad(net, X, T, grad=None):
 
 
 def tufrg_mlp_adam_step(net, grad, lr):
+    """One Adam update with gradient grad (device; None: the last computed one) and rate lr."""
     net._check(_lib.tufrg_mlp_adam_step(net.handle, None if grad is None else _ptr(grad), float(lr)))
 
 
@@ -388,6 +399,7 @@ def _opt(t):
 
 
 def tufrg_sur_features(ctx, n, lam, X, q=None, ch=None, iD=None):
+    """Feature rows X [n][11 + n_dR] (float32, device) of n loop blocks at scale lam (all blocks when q, ch, iD are None)."""
     _check(_lib.tufrg_sur_features(ctx.handle, int(n), _opt(q), _opt(ch), _opt(iD), float(lam),
                                    _ptr(X)), ctx.handle)
 
@@ -411,6 +423,7 @@ def tufrg_sur_attach(ctx, net, lambdas=(1.0,), scales=(1.0,)):
 
 
 def tufrg_sur_loops(ctx, lam, Lc):
+    """Compact loops Lc [2][Nq][n_dR][n_o^4] (device) from the attached network."""
     _check(_lib.tufrg_sur_loops(ctx.handle, float(lam), _ptr(Lc)), ctx.handle)
 
 

@@ -167,6 +167,42 @@ def _ptr(t):
     return ctypes.c_void_p(int(t))
 
 
+_DTYPES = {"c128": torch.complex128, "f64": torch.float64, "f32": torch.float32, "i32": torch.int32}
+
+
+def _arr(t, dt, n, name):
+    """Pointer of a tensor that a kernel reads or writes n elements of, checked
+    for dtype and size first (the library itself sees only an address).  A raw
+    address given as an int is passed on unchecked."""
+    if hasattr(t, "data_ptr"):
+        if t.dtype != _DTYPES[dt]:
+            raise TypeError(f"{name} must have dtype {_DTYPES[dt]}, not {t.dtype}")
+        if t.numel() < n:
+            raise ValueError(f"{name} holds {t.numel()} elements, the call needs {n}")
+    return _ptr(t)
+
+
+def _compact(ctx, t, name="Lc"):
+    """Pointer of a compact loop table [2][Nq][n_dR][n_o^4] complex128."""
+    return _arr(t, "c128", 2 * ctx.Nq * ctx.n_dR * ctx.n_o ** 4, name)
+
+
+def _state(ctx, t, name):
+    """Pointer of a [Nq][B][B] complex128 device array of the context."""
+    return _arr(t, "c128", ctx.Nq * ctx.B * ctx.B, name)
+
+
+def _model_arrays(hop_R, hop_t, V0):
+    hop_R = np.ascontiguousarray(hop_R, dtype=np.int32).reshape(-1, 2)
+    hop_t = np.ascontiguousarray(hop_t, dtype=np.complex128)
+    V0 = np.ascontiguousarray(V0, dtype=np.complex128)
+    if hop_t.ndim != 3 or hop_t.shape[0] != hop_R.shape[0] or hop_t.shape[1] != hop_t.shape[2]:
+        raise ValueError(f"hop_t must be [n_hop={hop_R.shape[0]}][n_o][n_o], got {hop_t.shape}")
+    if V0.size != hop_t.shape[1] ** 4:
+        raise ValueError(f"V0 must hold n_o^4 = {hop_t.shape[1] ** 4} entries, got {V0.size}")
+    return hop_R, hop_t, V0
+
+
 def _stream_handle(stream):
     if stream is None:
         return None
@@ -180,9 +216,7 @@ class Context:
 
     def __init__(self, hop_R, hop_t, mu, V0, ff, Lq, n_ref, cutoff, precision, stream=None, temperature=None,
                  basis="orbital"):
-        hop_R = np.ascontiguousarray(hop_R, dtype=np.int32).reshape(-1, 2)
-        hop_t = np.ascontiguousarray(hop_t, dtype=np.complex128)
-        V0 = np.ascontiguousarray(V0, dtype=np.complex128)
+        hop_R, hop_t, V0 = _model_arrays(hop_R, hop_t, V0)
         ff = np.ascontiguousarray(ff, dtype=np.int32).reshape(-1, 2)
         n_o = hop_t.shape[1]
         self._keep = (hop_R, hop_t, V0, ff)
@@ -225,34 +259,38 @@ class Context:
 
 def tufrg_band_data(ctx, e, Pi):
     """Band energies e [n_o][Nf] (float64) and projectors Pi [n_o][Nf][n_o][n_o] (complex128), device."""
-    _check(_lib.tufrg_band_data(ctx.handle, _ptr(e), _ptr(Pi)), ctx.handle)
+    _check(_lib.tufrg_band_data(ctx.handle, _arr(e, "f64", ctx.n_o * ctx.Nf, "e"),
+                                 _arr(Pi, "c128", ctx.n_o ** 3 * ctx.Nf, "Pi")), ctx.handle)
 
 
 def tufrg_bubble(ctx, channel, lam, deriv, L):
     """Loop (deriv) or bubble matrices L [Nq][B][B] of channel PP or PH at scale lam, device."""
-    _check(_lib.tufrg_bubble(ctx.handle, int(channel), float(lam), int(deriv), _ptr(L)), ctx.handle)
+    _check(_lib.tufrg_bubble(ctx.handle, int(channel), float(lam), int(deriv), _state(ctx, L, "L")), ctx.handle)
 
 
 def tufrg_project(ctx, P, C, VP, VC):
     """Projected vertices VP, VC [Nq][B][B] of the state P, C, all on the device."""
-    _check(_lib.tufrg_project(ctx.handle, _ptr(P), _ptr(C), _ptr(VP), _ptr(VC)), ctx.handle)
+    _check(_lib.tufrg_project(ctx.handle, _state(ctx, P, "P"), _state(ctx, C, "C"), _state(ctx, VP, "VP"),
+                              _state(ctx, VC, "VC")), ctx.handle)
 
 
 def tufrg_set_initial_c(ctx, C0):
     """Static C-channel term of a non-local initial interaction ([Nq][B][B] on
     the device, C layout), or None to remove it."""
-    _check(_lib.tufrg_set_initial_c(ctx.handle, None if C0 is None else _ptr(C0)), ctx.handle)
+    _check(_lib.tufrg_set_initial_c(ctx.handle, None if C0 is None else _state(ctx, C0, "C0")), ctx.handle)
 
 
 def tufrg_basis_matrix(ctx, channel, U, M):
     """Basis matrix M [Nq][B][B] of channel PP (U matrix) or PH (X matrix) from
     the unitaries U [Nf][n_o][n_o] (orbital rows, band columns), all on the device."""
-    _check(_lib.tufrg_basis_matrix(ctx.handle, int(channel), _ptr(U), _ptr(M)), ctx.handle)
+    _check(_lib.tufrg_basis_matrix(ctx.handle, int(channel), _arr(U, "c128", ctx.Nf * ctx.n_o ** 2, "U"),
+                                   _state(ctx, M, "M")), ctx.handle)
 
 
 def tufrg_basis_apply(ctx, M, X, Y, to_orbital=False):
     """Y = M^H X M per q (orbital -> band), or M X M^H (to_orbital)."""
-    _check(_lib.tufrg_basis_apply(ctx.handle, _ptr(M), _ptr(X), _ptr(Y), int(bool(to_orbital))), ctx.handle)
+    _check(_lib.tufrg_basis_apply(ctx.handle, _state(ctx, M, "M"), _state(ctx, X, "X"), _state(ctx, Y, "Y"),
+                                  int(bool(to_orbital))), ctx.handle)
 
 
 def tufrg_ff_symmetrize(ff):
@@ -268,19 +306,23 @@ def tufrg_ff_symmetrize(ff):
 def tufrg_ff_apply(ctx, W, X, Y, to_plane_waves=False):
     """Y = W X W^H in the form-factor index (or the converse), [Nq][B][B] on the device."""
     W = np.ascontiguousarray(W, dtype=np.complex128)
-    _check(_lib.tufrg_ff_apply(ctx.handle, W.ctypes.data, _ptr(X), _ptr(Y), int(bool(to_plane_waves))),
+    if W.shape != (ctx.n_ff, ctx.n_ff):
+        raise ValueError(f"W must be [{ctx.n_ff}][{ctx.n_ff}], got {W.shape}")
+    _check(_lib.tufrg_ff_apply(ctx.handle, W.ctypes.data, _state(ctx, X, "X"), _state(ctx, Y, "Y"),
+                               int(bool(to_plane_waves))),
            ctx.handle)
 
 
 def tufrg_set_initial_p(ctx, P0):
     """Static P-channel term of the bare vertex ([Nq][B][B] on the device, P
     layout), or None to remove it."""
-    _check(_lib.tufrg_set_initial_p(ctx.handle, None if P0 is None else _ptr(P0)), ctx.handle)
+    _check(_lib.tufrg_set_initial_p(ctx.handle, None if P0 is None else _state(ctx, P0, "P0")), ctx.handle)
 
 
 def tufrg_rhs(ctx, lam, P, C, dP, dC):
     """Right-hand side dP, dC [Nq][B][B] at scale lam; outputs must not overlap P, C."""
-    _check(_lib.tufrg_rhs(ctx.handle, float(lam), _ptr(P), _ptr(C), _ptr(dP), _ptr(dC)), ctx.handle)
+    _check(_lib.tufrg_rhs(ctx.handle, float(lam), _state(ctx, P, "P"), _state(ctx, C, "C"),
+                          _state(ctx, dP, "dP"), _state(ctx, dC, "dC")), ctx.handle)
 
 
 def tufrg_flow(ctx, P, C, lambda0, lambda_end, n_steps=0, rtol=1e-6, atol=1e-6, h0=0.05,
@@ -293,7 +335,8 @@ def tufrg_flow(ctx, P, C, lambda0, lambda_end, n_steps=0, rtol=1e-6, atol=1e-6, 
                  int(bool(surrogate)), float(sample_frac), float(sur_tol), float(plain_above),
                  int(sample_seed))
     r = FlowResult()
-    _check(_lib.tufrg_flow(ctx.handle, ctypes.byref(o), _ptr(P), _ptr(C), ctypes.byref(r)),
+    _check(_lib.tufrg_flow(ctx.handle, ctypes.byref(o), _state(ctx, P, "P"), _state(ctx, C, "C"),
+                           ctypes.byref(r)),
            ctx.handle)
     return r.as_dict()
 
@@ -314,7 +357,7 @@ def tufrg_timing_read(ctx, timer):
 
 def tufrg_loops_compact(ctx, lam, deriv, Lc):
     """Compact loops of both channels, Lc: complex128 [2][Nq][n_dR][n_o^4]."""
-    _check(_lib.tufrg_loops_compact(ctx.handle, float(lam), int(deriv), _ptr(Lc)), ctx.handle)
+    _check(_lib.tufrg_loops_compact(ctx.handle, float(lam), int(deriv), _compact(ctx, Lc)), ctx.handle)
 
 
 def tufrg_dR(ctx):
@@ -360,55 +403,68 @@ class Mlp:
 
 def tufrg_mlp_params(net, out):
     """Copy the flat parameter vector (float32, device) into out."""
-    net._check(_lib.tufrg_mlp_params(net.handle, _ptr(out)))
+    net._check(_lib.tufrg_mlp_params(net.handle, _arr(out, "f32", net.n_params, "out")))
 
 
 def tufrg_mlp_set_params(net, params):
     """Set the flat parameter vector (float32, device); resets the Adam moments."""
-    net._check(_lib.tufrg_mlp_set_params(net.handle, _ptr(params)))
+    net._check(_lib.tufrg_mlp_set_params(net.handle, _arr(params, "f32", net.n_params, "params")))
 
 
 def tufrg_mlp_forward(net, X, Y):
     """Y [n][n_out] = net(X [n][n_in]), float32 device arrays."""
-    net._check(_lib.tufrg_mlp_forward(net.handle, int(X.shape[0]), _ptr(X), _ptr(Y)))
+    n = int(X.shape[0])
+    net._check(_lib.tufrg_mlp_forward(net.handle, n, _arr(X, "f32", n * net.sizes[0], "X"),
+                                      _arr(Y, "f32", n * net.sizes[-1], "Y")))
 
 
 def tufrg_mlp_loss_grad(net, X, T, grad=None):
     """Mean squared error of the batch (returned) and its gradient into grad."""
     loss = ctypes.c_double()
-    net._check(_lib.tufrg_mlp_loss_grad(net.handle, int(X.shape[0]), _ptr(X), _ptr(T),
-                                        None if grad is None else _ptr(grad), ctypes.byref(loss)))
+    n = int(X.shape[0])
+    net._check(_lib.tufrg_mlp_loss_grad(net.handle, n, _arr(X, "f32", n * net.sizes[0], "X"),
+                                        _arr(T, "f32", n * net.sizes[-1], "T"),
+                                        None if grad is None else _arr(grad, "f32", net.n_params, "grad"),
+                                        ctypes.byref(loss)))
     return loss.value
 
 
 def tufrg_mlp_adam_step(net, grad, lr):
     """One Adam update with gradient grad (device; None: the last computed one) and rate lr."""
-    net._check(_lib.tufrg_mlp_adam_step(net.handle, None if grad is None else _ptr(grad), float(lr)))
+    g = None if grad is None else _arr(grad, "f32", net.n_params, "grad")
+    net._check(_lib.tufrg_mlp_adam_step(net.handle, g, float(lr)))
 
 
 def tufrg_mlp_train(net, X, T, batch, epochs, lr, seed=0):
     """Minibatch Adam epochs; returns the mean batch loss of the last epoch."""
     loss = ctypes.c_double()
-    net._check(_lib.tufrg_mlp_train(net.handle, int(X.shape[0]), _ptr(X), _ptr(T), int(batch),
+    n = int(X.shape[0])
+    net._check(_lib.tufrg_mlp_train(net.handle, n, _arr(X, "f32", n * net.sizes[0], "X"),
+                                    _arr(T, "f32", n * net.sizes[-1], "T"), int(batch),
                                     int(epochs), float(lr), int(seed), ctypes.byref(loss)))
     return loss.value
 
 
-def _opt(t):
-    return None if t is None else _ptr(t)
+def _opt(t, n, name):
+    return None if t is None else _arr(t, "i32", n, name)
 
 
 def tufrg_sur_features(ctx, n, lam, X, q=None, ch=None, iD=None):
-    """Feature rows X [n][11 + n_dR] (float32, device) of n loop blocks at scale lam (all blocks when q, ch, iD are None)."""
-    _check(_lib.tufrg_sur_features(ctx.handle, int(n), _opt(q), _opt(ch), _opt(iD), float(lam),
-                                   _ptr(X)), ctx.handle)
+    """Feature rows X [n][11 + n_dR] (float32, device) of n loop blocks at scale
+    lam; q, ch, iD: int32 device lists of the blocks, or None for the first n of
+    all 2 Nq n_dR blocks in compact order."""
+    n = int(n)
+    _check(_lib.tufrg_sur_features(ctx.handle, n, _opt(q, n, "q"), _opt(ch, n, "ch"), _opt(iD, n, "iD"),
+                                   float(lam), _arr(X, "f32", n * (11 + ctx.n_dR), "X")), ctx.handle)
 
 
 def tufrg_sur_targets(ctx, n, scale, Lc, T, q=None, ch=None, iD=None):
     """Writes the targets Lc / scale; returns max |Lc| over the blocks."""
     mx = ctypes.c_double()
-    _check(_lib.tufrg_sur_targets(ctx.handle, int(n), _opt(q), _opt(ch), _opt(iD), float(scale),
-                                  _ptr(Lc), _ptr(T), ctypes.byref(mx)), ctx.handle)
+    n = int(n)
+    _check(_lib.tufrg_sur_targets(ctx.handle, n, _opt(q, n, "q"), _opt(ch, n, "ch"), _opt(iD, n, "iD"),
+                                  float(scale), _compact(ctx, Lc), _arr(T, "f32", n * 2 * ctx.n_o ** 4, "T"),
+                                  ctypes.byref(mx)), ctx.handle)
     return mx.value
 
 
@@ -424,7 +480,7 @@ def tufrg_sur_attach(ctx, net, lambdas=(1.0,), scales=(1.0,)):
 
 def tufrg_sur_loops(ctx, lam, Lc):
     """Compact loops Lc [2][Nq][n_dR][n_o^4] (device) from the attached network."""
-    _check(_lib.tufrg_sur_loops(ctx.handle, float(lam), _ptr(Lc)), ctx.handle)
+    _check(_lib.tufrg_sur_loops(ctx.handle, float(lam), _compact(ctx, Lc)), ctx.handle)
 
 
 class Batch:
@@ -436,9 +492,7 @@ class Batch:
         models, setups = (Model * n)(), (Setup * n)()
         self._keep = []
         for i, w in enumerate(workloads):
-            hop_R = np.ascontiguousarray(w["hop_R"], dtype=np.int32).reshape(-1, 2)
-            hop_t = np.ascontiguousarray(w["hop_t"], dtype=np.complex128)
-            V0 = np.ascontiguousarray(w["V0"], dtype=np.complex128)
+            hop_R, hop_t, V0 = _model_arrays(w["hop_R"], w["hop_t"], w["V0"])
             ff = np.ascontiguousarray(w["ff"], dtype=np.int32).reshape(-1, 2)
             self._keep.append((hop_R, hop_t, V0, ff))
             models[i] = Model(hop_t.shape[1], hop_R.shape[0], hop_R.ctypes.data_as(_i32p),
@@ -481,8 +535,11 @@ class Batch:
 def tufrg_batch_flow(batch, Ps, Cs, lambda0, lambda_end, n_steps, v_max=50.0, channel_mask=3, max_steps=0):
     """Lockstep Euler flow of every instance (P, C in place); list of result dicts."""
     n = batch.n
-    pp = (_vp * n)(*[_ptr(x) for x in Ps])
-    cp = (_vp * n)(*[_ptr(x) for x in Cs])
+    if len(Ps) != n or len(Cs) != n:
+        raise ValueError(f"one P and one C per instance ({n})")
+    sizes = [d["Nq"] * d["B"] * d["B"] for d in batch.dims]
+    pp = (_vp * n)(*[_arr(x, "c128", m, f"P[{i}]") for i, (x, m) in enumerate(zip(Ps, sizes))])
+    cp = (_vp * n)(*[_arr(x, "c128", m, f"C[{i}]") for i, (x, m) in enumerate(zip(Cs, sizes))])
     o = FlowOpts(float(lambda0), float(lambda_end), int(n_steps), 0.0, 0.0, 0.0, float(v_max),
                  int(channel_mask), int(max_steps), STEP_CB(), None, 0, 0.0, 0.0, 0.0, 0)
     res = (FlowResult * n)()

@@ -107,3 +107,43 @@ def test_create_rejects_an_unknown_basis(T):
 
 def test_set_initial_p_rejects_a_null_context(T):
     assert T._lib.tufrg_set_initial_p(None, None) == 1
+
+
+def _fake_ctx():
+    """Sizes of a small context without one (no device is needed: the binding
+    checks dtype and size before it calls the library)."""
+    from types import SimpleNamespace
+    return SimpleNamespace(handle=None, Nq=4, B=8, Nf=16, n_dR=5, n_o=2, n_ff=2)
+
+
+def test_binding_checks_dtype_and_size_before_the_library(T):
+    import torch
+    ctx = _fake_ctx()
+    good = torch.zeros((ctx.Nq, ctx.B, ctx.B), dtype=torch.complex128)
+    with pytest.raises(TypeError):
+        T.tufrg_rhs(ctx, 0.5, good.to(torch.complex64), good, good, good)
+    with pytest.raises(ValueError):
+        T.tufrg_rhs(ctx, 0.5, good, good[:-1], good, good)
+    with pytest.raises(ValueError):
+        T.tufrg_loops_compact(ctx, 0.5, 1, torch.zeros(2 * ctx.Nq * ctx.n_dR * 16 - 1, dtype=torch.complex128))
+    with pytest.raises(TypeError):
+        T.tufrg_band_data(ctx, torch.zeros(ctx.n_o * ctx.Nf, dtype=torch.float32),
+                          torch.zeros(ctx.n_o ** 3 * ctx.Nf, dtype=torch.complex128))
+    with pytest.raises(ValueError):
+        T.tufrg_sur_features(ctx, 3, 0.5, torch.zeros((3, 11 + ctx.n_dR), dtype=torch.float32),
+                             torch.zeros(2, dtype=torch.int32), torch.zeros(3, dtype=torch.int32),
+                             torch.zeros(3, dtype=torch.int32))
+    with pytest.raises(ValueError):
+        T.tufrg_ff_apply(ctx, np.eye(3), good, good)
+    # correctly typed and sized: the call reaches the library, which refuses the null context
+    with pytest.raises(T.TufrgError) as ei:
+        T.tufrg_rhs(ctx, 0.5, good, good, good, good)
+    assert ei.value.status == 1
+
+
+def test_context_checks_the_model_arrays_before_the_library(T):
+    hop_R, hop_t = hubbard_hoppings(1.0, -0.25)
+    with pytest.raises(ValueError):
+        T.Context(**_args(hop_t=hop_t[:-1]))
+    with pytest.raises(ValueError):
+        T.Context(**_args(V0=onsite_V0(2.0)[:1]))

@@ -77,6 +77,10 @@ MUTATIONS = [
  ("tufrg.py", "self.Pi = bands.projectors(np.broadcast_to(np.eye(self.n_o), self.U.shape))",
               "self.Pi = bands.projectors(self.U)", "band basis keeps orbital projectors"),
  ("su2.py", "            P[..., a, b, b, a] -= px", "            P[..., a, b, b, a] += px", "SU(2) embedding sign"),
+ ("bruteforce.py", "out[p1, :, p3] = 2.0 * np.einsum(", "out[p1, :, p3] = 1.0 * np.einsum(", "brute-force ph factor"),
+ ("bruteforce.py", "return -np.swapaxes(phic[i1, i2, k4], -1, -2)", "return np.swapaxes(phic[i1, i2, k4], -1, -2)", "brute-force D sign"),
+ ("cutoff.py", "return dchi(e1, lam) * chi(e2, lam) + chi(e1, lam) * dchi(e2, lam)",
+               "return dchi(e1, lam) * chi(e2, lam)", "shell product rule"),
 ]
 
 

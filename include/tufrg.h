@@ -135,7 +135,9 @@ typedef struct {
 
 typedef struct {
   int32_t n_ff;            /* number of form factors */
-  const int32_t *ff_R;     /* [n_ff][2], ff_R[0] = (0,0), closed under negation, |R_x|,|R_y| <= 2 */
+  const int32_t *ff_R;     /* [n_ff][2], ff_R[0] = (0,0), closed under negation, |R_x|,|R_y| <= 2;
+                              six spin-orbitals: every difference R1 - R2 inside the 5 x 5 box
+                              |dx|, |dy| <= 2 or the diamond |dx| + |dy| <= 4 (else TUFRG_E_UNSUPPORTED) */
   int32_t Lq;              /* coarse mesh; must exceed 4 max|R| (no aliasing in R'' = R1 - R2) */
   int32_t n_ref;           /* refinement of the loop mesh, Lf = n_ref Lq <= 4096 */
   int32_t cutoff;          /* tufrg_cutoff */
@@ -272,10 +274,10 @@ typedef struct {
    * on sample_frac of the coarse q_x rows (at least one row; rows chosen by a
    * counter-based hash of sample_seed and the evaluation index) and replaces
    * the network's values there; if the sampled relative error
-   * max|L_net - L| / max(max|L|, s(Lambda)) (maxima over the sampled blocks,
-   * s the network's target scale) exceeds sur_tol, or the current max coupling
-   * exceeds plain_above, the plain loops are used everywhere for that
-   * evaluation.  surrogate = 0: plain loops only. */
+   * max|L_net - L| / max|L| (maxima over the sampled blocks) exceeds sur_tol,
+   * any network output is not finite, or the current max coupling exceeds
+   * plain_above, the plain loops are used everywhere for that evaluation.
+   * surrogate = 0: plain loops only. */
   int32_t surrogate;
   double sample_frac, sur_tol, plain_above;
   uint64_t sample_seed;

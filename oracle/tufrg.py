@@ -200,39 +200,43 @@ def loops(st, channel, lam, deriv=True, q_list=None):
 # ----------------------------------------------------------------------------
 
 def to_real_space(st, X):
-    """X(R'') = 1/N_q sum_q exp(i q.R'') X(q) for every R'' in D (dict by residue)."""
-    out = {}
-    for r, R in st.D.items():
-        ph = st.coarse_phase(R)
-        out[r] = np.tensordot(ph, X, axes=(0, 0)) / st.Nq
-    return out
+    """X(R'') = 1/N_q sum_q exp(i q.R'') X(q) for every R'' in D (dict by
+    residue; Sec. 3.3), all R'' at once as one product of the phase matrix
+    [R''][q] with X viewed as [q][rest]."""
+    keys = list(st.D.keys())
+    ph = np.stack([st.coarse_phase(st.D[r]) for r in keys])
+    Xr = (ph @ X.reshape(st.Nq, -1)) / st.Nq
+    return {r: Xr[i].reshape(X.shape[1:]) for i, r in enumerate(keys)}
 
 
 def _swap34(X):
     return np.swapaxes(X, -1, -2)
 
 
-def projected_vertices(st, P, C):
+def projected_vertices(st, P, C, q_list=None):
     """VP = P[V0] + P + P[V^C] + P[V^D];  VC = C[V0] + C[V^P] + C + C[V^D].
 
     A non-local initial interaction given in crossed particle-hole form (st.C0)
     is projected with the flowing C: V^C -> V^C + C0, V^D -> V^D + D0; one given
-    in particle-particle form (st.P0) with the flowing P: V^P -> V^P + P0."""
+    in particle-particle form (st.P0) with the flowing P: V^P -> V^P + P0.
+    q_list: evaluate the vertices at these coarse q only (the real-space
+    coefficients always sum over every q)."""
     if st.C0 is not None:
         C = C + st.C0
     if st.P0 is not None:
         P = P + st.P0
     Pr = to_real_space(st, P)
     Cr = to_real_space(st, C)
-    VP = P.copy()
-    VC = C.copy()
+    qs = np.arange(st.Nq) if q_list is None else np.asarray(q_list, dtype=np.int64)
+    VP = P[qs].copy()
+    VC = C[qs].copy()
     VP[:, 0, 0] += st.V0
     VC[:, 0, 0] += st.V0
     for i, R in enumerate(st.S):
         for j, Rp in enumerate(st.S):
-            phRp = st.coarse_phase(Rp)
+            phRp = st.coarse_phase(Rp)[qs]
             for r, R2 in st.D.items():
-                ph = st.coarse_phase(R2)[:, None, None, None, None]
+                ph = st.coarse_phase(R2)[qs][:, None, None, None, None]
                 # P[V^C]: sum_R'' e^{is.R''} C^{R+R'', R'-R''}_{n1n2n3n4}(R'')
                 a, b = st.ff_index(R + R2), st.ff_index(Rp - R2)
                 if a >= 0 and b >= 0:
@@ -250,7 +254,7 @@ def projected_vertices(st, P, C):
             for b, R2 in enumerate(st.S):
                 a = st.ff_index(R - Rp + R2)
                 if a >= 0:
-                    ph = st.coarse_phase(R2)[:, None, None, None, None]
+                    ph = st.coarse_phase(R2)[qs][:, None, None, None, None]
                     VC[:, i, j] -= ph * _swap34(Cr[rneg][a, b])[None]
     return VP, VC
 
@@ -269,11 +273,21 @@ def bundle_ph(VC, Lph):
     return 2.0 * np.einsum("xyzajci,xzwijkl,xwvkbld->xyvabcd", VC, Lph, VC, optimize="greedy")
 
 
-def rhs(st, lam, P, C, flow_P=True, flow_C=True):
-    """Right-hand side (dP/dLambda, dC/dLambda) of the matrix RGE."""
-    VP, VC = projected_vertices(st, P, C)
-    dP = bundle_pp(VP, loops(st, "pp", lam)) if flow_P else np.zeros_like(P)
-    dC = bundle_ph(VC, loops(st, "ph", lam)) if flow_C else np.zeros_like(C)
+def rhs(st, lam, P, C, flow_P=True, flow_C=True, q_list=None, loops_pp=None, loops_ph=None):
+    """Right-hand side (dP/dLambda, dC/dLambda) of the matrix RGE, at every
+    coarse q or at the listed ones (the projections still sum over every q).
+    loops_pp, loops_ph: the loop matrices at those q, if already computed."""
+    VP, VC = projected_vertices(st, P, C, q_list)
+    if flow_P:
+        Lpp = loops(st, "pp", lam, q_list=q_list) if loops_pp is None else loops_pp
+        dP = bundle_pp(VP, Lpp)
+    else:
+        dP = np.zeros_like(VP)
+    if flow_C:
+        Lph = loops(st, "ph", lam, q_list=q_list) if loops_ph is None else loops_ph
+        dC = bundle_ph(VC, Lph)
+    else:
+        dC = np.zeros_like(VC)
     return dP, dC
 
 

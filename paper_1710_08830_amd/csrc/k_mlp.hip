@@ -292,17 +292,23 @@ hipError_t launch_sur_targets(long long n, const int *ql, const int *cl, const i
 
 // compact loops from network rows of consecutive blocks b0 .. b0 + n - 1 (all-block order):
 // Lc[b][t] = (Y[b][2t], Y[b][2t + 1]) * s, s = y_scale / Lambda^p
+// Lc = s Y; a non-finite network output sets *bad (if given), so that the
+// caller can fall back to the plain loops
 __global__ void sur_scatter_kernel(long long n, int no4, double s, const float *__restrict__ Y,
-                                   double *__restrict__ Lc) {
+                                   double *__restrict__ Lc, unsigned int *__restrict__ bad) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n * 2 * no4) return;
-  Lc[i] = s * (double)Y[i];
+  const float y = Y[i];
+  if (bad && !isfinite(y)) atomicOr(bad, 1u);
+  Lc[i] = s * (double)y;
 }
 
-hipError_t launch_sur_scatter(long long n, int no4, double s, const float *Y, double *Lc, hipStream_t st) {
+hipError_t launch_sur_scatter(long long n, int no4, double s, const float *Y, double *Lc, unsigned int *bad,
+                              hipStream_t st) {
   const long long tot = n * 2 * no4;
   if (tot <= 0) return hipSuccess;
-  hipLaunchKernelGGL(sur_scatter_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, no4, s, Y, Lc);
+  hipLaunchKernelGGL(sur_scatter_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, no4, s, Y, Lc,
+                     bad);
   return hipGetLastError();
 }
 
@@ -316,6 +322,9 @@ __global__ void sur_compare_kernel(long long n, const double *__restrict__ a, co
     const double dr = a[2 * i] - b[2 * i], di = a[2 * i + 1] - b[2 * i + 1];
     d = sqrt(dr * dr + di * di);
     r = sqrt(b[2 * i] * b[2 * i] + b[2 * i + 1] * b[2 * i + 1]);
+    // a NaN would vanish in the max below: count it as an infinite difference
+    if (!(d <= 1.7976931348623157e308)) d = INFINITY;
+    if (!(r <= 1.7976931348623157e308)) r = INFINITY;
   }
   // wave-level max, then one atomic per wave
   for (int off = 32; off > 0; off >>= 1) {

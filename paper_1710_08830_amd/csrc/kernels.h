@@ -124,7 +124,8 @@ hipError_t launch_sur_features(long long n, const int *ql, const int *cl, const 
                                float *X, hipStream_t st);
 hipError_t launch_sur_targets(long long n, const int *ql, const int *cl, const int *dl, int Nq, int nD, int no4,
                               double s, const double *Lc, float *T, hipStream_t st);
-hipError_t launch_sur_scatter(long long n, int no4, double s, const float *Y, double *Lc, hipStream_t st);
+hipError_t launch_sur_scatter(long long n, int no4, double s, const float *Y, double *Lc, unsigned int *bad,
+                              hipStream_t st);
 hipError_t launch_sur_compare(long long n, const double *a, const double *b, unsigned long long *bits,
                               hipStream_t st);
 hipError_t launch_absmax_f32(long long n, const float *x, unsigned int *bits, hipStream_t st);

@@ -283,6 +283,9 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     const long long l2 = ((long long)c->Lf * row_bytes + 3000000 - 1) / 3000000;
     int want = (int)std::max<long long>(1, std::max(fill, l2));
     c->nkxc = std::max(1, std::min(want, std::max(1, c->Lf / 8)));
+    // chunks of kxper rows each; drop chunks that would start at or beyond Lf
+    const int kxper = (c->Lf + c->nkxc - 1) / c->nkxc;
+    c->nkxc = (c->Lf + kxper - 1) / kxper;
   } else {
     // the multi-orbital loop kernel sums every k of a (q, channel) in one workgroup
     c->nkyb = 1;
@@ -290,6 +293,20 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     if (!(c->ndx == 5 && c->ndy == 4) && !(c->ndx == 3 && c->ndy == 2)) {
       c->ndx = 3;
       c->ndy = 2;
+    }
+    // the six-orbital kernels compute the 5 x 5 box (ndy = 2) or the diamond
+    // |dx| + |dy| <= 4 (ndy = 4) of difference vectors; a set whose S - S
+    // leaves that shape is not supported
+    for (size_t i = 0; i < c->dlist.size(); i += 2) {
+      const int dx = std::abs(c->dlist[i]), dy = std::abs(c->dlist[i + 1]);
+      const bool inside = c->ndy == 2 ? (dx <= 2 && dy <= 2) : (dx + dy <= 4);
+      if (!inside) {
+        c->err = "six-orbital loops cover R1 - R2 with |dx| + |dy| <= 4 (or the 5 x 5 box); (" +
+                 std::to_string(c->dlist[i]) + ", " + std::to_string(c->dlist[i + 1]) + ") is outside";
+        g_err = c->err;
+        delete c;
+        return TUFRG_E_UNSUPPORTED;
+      }
     }
   }
   {
@@ -624,7 +641,7 @@ static double sur_scale_at(const tufrg_ctx *c, double lam) {
 
 // network loops of all 2 Nq nD blocks into dst (compact, both channels)
 static const long long SUR_CHUNK = 16384;
-static tufrg_status sur_loops_internal(tufrg_ctx *c, double lam, double *dst) {
+static tufrg_status sur_loops_internal(tufrg_ctx *c, double lam, double *dst, unsigned int *bad = nullptr) {
   const long long nb = 2LL * c->Nq * c->nD;
   const int nin = 11 + c->nD, nout = 2 * c->no4;
   if (!c->d_surX) {
@@ -637,7 +654,7 @@ static tufrg_status sur_loops_internal(tufrg_ctx *c, double lam, double *dst) {
   for (long long b0 = 0; b0 < nb; b0 += SUR_CHUNK) {
     const long long rows = std::min(SUR_CHUNK, nb - b0);
     TRY(mlp_forward_internal(c->sur, rows, c->d_surX + b0 * nin, c->d_surY));
-    HIPCHK(c, launch_sur_scatter(rows, c->no4, s, c->d_surY, dst + b0 * nout, c->st));
+    HIPCHK(c, launch_sur_scatter(rows, c->no4, s, c->d_surY, dst + b0 * nout, bad, c->st));
   }
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_SURROGATE));
   return TUFRG_OK;
@@ -662,7 +679,11 @@ static tufrg_status surrogate_loops(tufrg_ctx *c, double lam) {
     r->n_plain++;
     return TUFRG_OK;
   }
-  TRY(sur_loops_internal(c, lam, c->d_loop));
+  // d_sbits: max |diff|, max |ref| of the sampled rows, and a flag set by any
+  // non-finite network output (sampled or not)
+  unsigned int *d_bad = (unsigned int *)(c->d_sbits + 2);
+  HIPCHK(c, hipMemsetAsync(c->d_sbits, 0, 3 * sizeof(unsigned long long), c->st));
+  TRY(sur_loops_internal(c, lam, c->d_loop, d_bad));
   // sampled rows: distinct q_x rows from a counter-based hash
   int nr = (int)std::llround(o->sample_frac * c->Lq);
   nr = std::max(1, std::min(c->Lq, nr));
@@ -686,19 +707,19 @@ static tufrg_status surrogate_loops(tufrg_ctx *c, double lam) {
   auto plain_at = [&](int ch, int j) {
     return c->d_samp + 2 * (((size_t)ch * nr * c->Lq + (size_t)j * c->Lq) * blk);
   };
-  HIPCHK(c, hipMemsetAsync(c->d_sbits, 0, 2 * sizeof(unsigned long long), c->st));
   for (int j = 0; j < nr; ++j)
     for (int ch = 0; ch < 2; ++ch)
       HIPCHK(c, launch_sur_compare((long long)c->Lq * blk, net_at(ch, j), plain_at(ch, j), c->d_sbits, c->st));
-  HIPCHK(c, hipMemcpyAsync(c->h_sbits, c->d_sbits, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->h_sbits, c->d_sbits, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   double dmax, rmax;
   std::memcpy(&dmax, &c->h_sbits[0], sizeof(double));
   std::memcpy(&rmax, &c->h_sbits[1], sizeof(double));
-  // relative to the loop scale at lam: the larger of the sampled plain maximum
-  // and the network's target scale s(lam)
-  const double ref = std::max(rmax, sur_scale_at(c, lam));
-  const double err = ref > 0.0 ? dmax / ref : (dmax > 0.0 ? INFINITY : 0.0);
+  const bool net_bad = (unsigned int)c->h_sbits[2] != 0u;
+  // relative to the largest plain loop value of the sampled rows (the table
+  // scale s(lam) is only the network's output unit, not a judge)
+  double err = rmax > 0.0 ? dmax / rmax : (dmax > 0.0 ? INFINITY : 0.0);
+  if (net_bad) err = INFINITY;
   r->max_sample_err = std::max(r->max_sample_err, err);
   if (!(err <= o->sur_tol)) {
     TRY(loops_range(c, lam, 1, 0, 2, 0, c->Nq, c->d_loop));

@@ -42,7 +42,7 @@ MUTATIONS = [
  ("tufrg.py", "\"kmn,kndb->kmbd\"", "\"kmn,knbd->kmbd\"", "ph projector transposed"),
  ("tufrg.py", "    [44 / 45, -56 / 15, 32 / 9],", "    [44 / 45, -56 / 15, 32 / 8],", "DP tableau entry"),
  ("tufrg.py", "187 / 2100, 1 / 40])", "187 / 2100, 1 / 41])", "DP error weight"),
- ("tufrg.py", "out[r] = np.tensordot(ph, X, axes=(0, 0)) / st.Nq", "out[r] = np.tensordot(ph.conj(), X, axes=(0, 0)) / st.Nq", "real-space phase sign"),
+ ("tufrg.py", "Xr = (ph @ X.reshape(st.Nq, -1)) / st.Nq", "Xr = (ph.conj() @ X.reshape(st.Nq, -1)) / st.Nq", "real-space phase sign"),
  ("cutoff.py", "return -e / (4.0 * lam * lam) / np.cosh(e / (2.0 * lam)) ** 2", "return -e / (4.0 * lam) / np.cosh(e / (2.0 * lam)) ** 2", "K temperature"),
  ("cutoff.py", "return e * (2.0 * a + lam) / (4.0 * (a + lam) ** 2)", "return e * (a + lam) / (4.0 * (a + lam) ** 2)", "J omega"),
  ("cutoff.py", "return -e * (3.0 * a + lam) / (4.0 * (a + lam) ** 3)", "return -e * (3.0 * a + lam) / (4.0 * (a + lam) ** 2)", "K omega"),

@@ -75,6 +75,23 @@ def test_six_orbital_model_passes_validation_up_to_the_device(T):
     assert ei.value.status in (2, 3)
 
 
+@pytest.mark.parametrize("ff", [
+    [[0, 0], [2, 2], [-2, -2], [2, -2], [-2, 2]],   # S - S holds (4, 4)
+    [[0, 0], [2, 1], [-2, -1], [1, 2], [-1, -2]],   # (4, 2) and (3, 3)
+    [[0, 0], [1, 2], [-1, -2], [2, -1], [-2, 1]],   # (2, 4) and (4, -2)
+])
+def test_six_orbital_sets_beyond_the_kernel_shape_are_rejected(T, ff):
+    """The six-orbital loop kernels cover differences R1 - R2 in the 5 x 5 box
+    or the diamond |dx| + |dy| <= 4; a set whose S - S leaves that shape is
+    rejected on the host (no partial slot is left unwritten)."""
+    hop = t2g_soc_hoppings(0.2, seed=1)
+    from synth import kanamori_V0
+    with pytest.raises(T.TufrgError) as ei:
+        T.Context(**_args(hop_R=hop[0], hop_t=hop[1], V0=kanamori_V0(2.0, 0.3), ff=np.array(ff), Lq=9))
+    assert ei.value.status == 6
+    assert "outside" in str(ei.value)
+
+
 @pytest.mark.parametrize("sizes", [[5], [0, 4], [4, 70000]])
 def test_mlp_rejects_bad_sizes(T, sizes):
     with pytest.raises(T.TufrgError) as ei:

@@ -245,11 +245,33 @@ def test_host_pointer_rejected(T):
     assert ei.value.status == 1
 
 
+# Full-size workloads: the oracle recomputes a few coarse q one by one; its
+# loops at those q are shared by the tests of one process (same workload,
+# scale and q give the same oracle result).
+_ORACLE = {}
+
+
+def _oracle_setup(name):
+    if ("setup", name) not in _ORACLE:
+        _ORACLE[("setup", name)] = otu.TUSetup.from_workload(workload(name))
+    return _ORACLE[("setup", name)]
+
+
+def _oracle_loop_at(name, channel, lam, qi):
+    key = ("loop", name, channel, lam, qi)
+    if key not in _ORACLE:
+        _ORACLE[key] = otu.loops(_oracle_setup(name), channel, lam, q_list=[qi])[0]
+    return _ORACLE[key]
+
+
+RASHBA_Q = (0, 37, 300, 575)
+T2G_Q = (0, 531)
+
+
 def test_full_size_rashba_loops_on_sampled_q(T):
     """The 24x24 q-mesh refined 24x (Omega cutoff) at the benchmark's launch
     shape; the oracle recomputes a sample of q points one by one."""
     w = workload("rashba_s9_L24")
-    st = otu.TUSetup.from_workload(w)
     lam = 0.2
     for prec in ("fp64", "fp32"):
         ctx = T.Context.from_workload(w, precision=prec)
@@ -257,25 +279,58 @@ def test_full_size_rashba_loops_on_sampled_q(T):
             L = _zeros(ctx)
             T.tufrg_bubble(ctx, code, lam, 1, L)
             torch.cuda.synchronize()
-            for qi in (0, 37, 300, 575):
-                ref = conv(otu.loops(st, channel, lam, q_list=[qi]))[0]
+            for qi in RASHBA_Q:
+                ref = conv(_oracle_loop_at(w["name"], channel, lam, qi)[None])[0]
                 assert rel(L[qi].cpu().numpy(), ref) < TOL[prec], (prec, channel, qi)
         ctx.close()
+
+
+def _full_size_rhs(T, name, prec, lam, q_list, scale, seeds):
+    """Right-hand side of the whole workload on the GPU (the launch shapes of
+    the benchmark) against the oracle at the sampled q: projections over every
+    q, loops and bundle products at the sampled ones."""
+    w = workload(name)
+    st = _oracle_setup(name)
+    P = scale * random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=seeds[0])
+    C = scale * random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=seeds[1])
+    ctx = T.Context.from_workload(w, precision=prec)
+    Pd = torch.from_numpy(p_to_matrix(P)).to(dev())
+    Cd = torch.from_numpy(c_to_matrix(C)).to(dev())
+    dP, dC = _zeros(ctx), _zeros(ctx)
+    T.tufrg_rhs(ctx, lam, Pd, Cd, dP, dC)
+    torch.cuda.synchronize()
+    del Pd, Cd
+    got_P = dP[list(q_list)].cpu().numpy()
+    got_C = dC[list(q_list)].cpu().numpy()
+    del dP, dC
+    ctx.close()
+    Lpp = np.stack([_oracle_loop_at(name, "pp", lam, qi) for qi in q_list])
+    Lph = np.stack([_oracle_loop_at(name, "ph", lam, qi) for qi in q_list])
+    rP, rC = otu.rhs(st, lam, P, C, q_list=q_list, loops_pp=Lpp, loops_ph=Lph)
+    eP, eC = rel(got_P, p_to_matrix(rP)), rel(got_C, c_to_matrix(rC))
+    print(f"{name} {prec}: full-size rhs at q {q_list}: rel err P {eP:.2e} C {eC:.2e}")
+    return eP, eC
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_rashba_rhs_on_sampled_q(T, prec):
+    eP, eC = _full_size_rhs(T, "rashba_s9_L24", prec, 0.2, RASHBA_Q, 0.2, (21, 22))
+    tol = TOL[prec]
+    assert eP < tol and eC < tol
 
 
 def test_full_size_t2g_loops_on_sampled_q(T):
     """t2g + SOC on the 32x32 q-mesh refined 16x (13 form factors, B = 468):
     the loops of every q on the GPU, two q recomputed by the oracle."""
     w = workload("t2g_s13_L32")
-    st = otu.TUSetup.from_workload(w)
     lam = 0.3
     ctx = T.Context.from_workload(w, precision="fp32")
     for channel, code, conv in (("pp", T.PP, pp_loop_to_matrix), ("ph", T.PH, ph_loop_to_matrix)):
         L = _zeros(ctx)
         T.tufrg_bubble(ctx, code, lam, 1, L)
         torch.cuda.synchronize()
-        for qi in (0, 531):
-            ref = conv(otu.loops(st, channel, lam, q_list=[qi]))[0]
+        for qi in T2G_Q:
+            ref = conv(_oracle_loop_at(w["name"], channel, lam, qi)[None])[0]
             assert rel(L[qi].cpu().numpy(), ref) < TOL["fp32"], (channel, qi)
         del L
     ctx.close()
@@ -317,15 +372,104 @@ def test_bf16x3_full_size_t2g_loops_on_sampled_q(T):
     """The six-orbital 32x32 workload in its own arithmetic (BF16 split on the
     matrix cores), two q recomputed by the oracle."""
     w = workload("t2g_s13_L32")
-    st = otu.TUSetup.from_workload(w)
     lam = 0.3
     ctx = T.Context.from_workload(w, precision="bf16x3")
     for channel, code, conv in (("pp", T.PP, pp_loop_to_matrix), ("ph", T.PH, ph_loop_to_matrix)):
         L = _zeros(ctx)
         T.tufrg_bubble(ctx, code, lam, 1, L)
         torch.cuda.synchronize()
-        for qi in (0, 531):
-            ref = conv(otu.loops(st, channel, lam, q_list=[qi]))[0]
+        for qi in T2G_Q:
+            ref = conv(_oracle_loop_at(w["name"], channel, lam, qi)[None])[0]
             assert rel(L[qi].cpu().numpy(), ref) < TOL["bf16x3"], (channel, qi)
         del L
     ctx.close()
+
+
+def test_bf16x3_full_size_t2g_rhs_on_sampled_q(T):
+    """The whole t2g 32x32 right-hand side in the mixed arithmetic (projections
+    and bundle products FP32/FP64, loops BF16 split), two q against the oracle.
+    Bar: the BF16-split loop tolerance, three times for the two products of
+    the bundle."""
+    eP, eC = _full_size_rhs(T, "t2g_s13_L32", "bf16x3", 0.3, T2G_Q, 0.05, (23, 24))
+    assert eP < 3 * TOL["bf16x3"] and eC < 3 * TOL["bf16x3"]
+
+
+def _t2g5(U, J):
+    return dict(hop=t2g_soc_hoppings(0.2, seed=1), mu=0.35, V0=kanamori_V0(U, J), ff=ff_shell(5), Lq=5, n_ref=3,
+                cutoff="temperature")
+
+
+def test_bf16x3_euler_flow_matches_oracle(T):
+    """t2g + SOC with five form factors (B = 180), Kanamori U = 2, J = 0.3:
+    twelve Euler steps 5 -> 0.05 in the mixed arithmetic against the oracle's
+    FP64 flow (final couplings to the BF16-split bar)."""
+    c = _t2g5(2.0, 0.3)
+    st = _setup(c)
+    Pr, Cr, rr = otu.flow_euler(st, 5.0, 0.05, 12, v_max=20.0)
+    ctx = _ctx(T, c, "bf16x3")
+    P, C = _zeros(ctx), _zeros(ctx)
+    res = T.tufrg_flow(ctx, P, C, 5.0, 0.05, n_steps=12, v_max=20.0)
+    torch.cuda.synchronize()
+    eP, eC = rel(P.cpu().numpy(), p_to_matrix(Pr)), rel(C.cpu().numpy(), c_to_matrix(Cr))
+    print(f"bf16x3 t2g5 flow: rel err P {eP:.2e} C {eC:.2e}, steps {res['n_steps']}")
+    assert res["n_steps"] == rr["n_steps"] and res["diverged"] == rr["diverged"] == 0
+    assert eP < TOL["bf16x3"] and eC < TOL["bf16x3"]
+    assert res["max_coupling"] == pytest.approx(rr["max_coupling"], rel=TOL["bf16x3"])
+
+
+def test_bf16x3_euler_flow_divergence_matches_oracle(T):
+    """Attractive Kanamori U = -3: the t2g flow runs into a pairing
+    instability; the mixed-arithmetic flow stops at the oracle's step with its
+    critical scale."""
+    c = _t2g5(-3.0, 0.0)
+    st = _setup(c)
+    Pr, Cr, rr = otu.flow_euler(st, 5.0, 0.05, 20, v_max=20.0)
+    assert rr["diverged"] == 1
+    ctx = _ctx(T, c, "bf16x3")
+    P, C = _zeros(ctx), _zeros(ctx)
+    res = T.tufrg_flow(ctx, P, C, 5.0, 0.05, n_steps=20, v_max=20.0)
+    torch.cuda.synchronize()
+    eP, eC = rel(P.cpu().numpy(), p_to_matrix(Pr)), rel(C.cpu().numpy(), c_to_matrix(Cr))
+    el = abs(res["lambda_c"] / rr["lambda_c"] - 1)
+    print(f"bf16x3 t2g5 divergence: rel err P {eP:.2e} C {eC:.2e} lambda_c {el:.2e}, step {res['n_steps']}")
+    assert res["diverged"] == 1 and res["n_steps"] == rr["n_steps"]
+    assert el < TOL["bf16x3"]
+    assert eP < TOL["bf16x3"] and eC < TOL["bf16x3"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_hubbard_s5_L8_flow_matches_stored_oracle_flow(T, prec):
+    """The single-band Hubbard workload as specified (8 x 8 refined 12 x, U = 3,
+    200 Euler steps 10 -> 1e-3 at the temperature cutoff) against the oracle's
+    flow stored by tests/golden/make_hubbard_s5_L8_flow.py: stopping step,
+    divergence, critical scale, max-coupling trajectory, per-q norms and 512
+    sampled entries of the final P and C."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "hubbard_s5_L8_flow.json")))
+    w = workload("hubbard_s5_L8")
+    ctx = T.Context.from_workload(w, precision=prec)
+    P, C = _zeros(ctx), _zeros(ctx)
+    traj = []
+    res = T.tufrg_flow(ctx, P, C, w["lam0"], w["lam_end"], n_steps=w["n_steps"], v_max=w["v_max"],
+                       on_step=lambda u, i, lam, m: traj.append((lam, m)) or 0)
+    torch.cuda.synchronize()
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    assert res["n_steps"] == g["n_steps"] and res["diverged"] == g["diverged"]
+    if g["diverged"]:
+        assert res["lambda_c"] == pytest.approx(g["lambda_c"], rel=tol)
+    ref_traj = np.array(g["trajectory"][1:])
+    got_traj = np.array(traj + ([(res["lambda_stop"], res["max_coupling"])] if res["diverged"] else []))
+    assert got_traj.shape == ref_traj.shape
+    assert np.abs(got_traj - ref_traj).max() <= tol * np.abs(ref_traj).max()
+    Pm, Cm = P.cpu().numpy(), C.cpu().numpy()
+    idx = np.array(g["index"])
+    for got, name in ((Pm, "P"), (Cm, "C")):
+        ref = np.array(g[name])
+        ref = ref[:, 0] + 1j * ref[:, 1]
+        scale = g[name + "_max"]
+        e = np.abs(got.flat[idx] - ref).max() / scale
+        en = np.abs(np.linalg.norm(got.reshape(got.shape[0], -1), axis=1) - np.array(g[name + "_norm_q"])).max()
+        print(f"hubbard_s5_L8 {prec} {name}: sampled rel err {e:.2e}, per-q norm err {en / scale:.2e}")
+        assert e < tol and en < tol * scale * np.sqrt(got.shape[1] * got.shape[2])
+        assert abs(np.abs(got).max() / scale - 1) < tol

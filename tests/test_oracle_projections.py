@@ -180,3 +180,20 @@ def test_nonlocal_initial_interaction_projects_like_its_definition(hop_sel):
     off = VP.copy()
     off[:, 0, 0] = 0
     assert np.abs(off).max() > 0.1
+
+
+def test_vertices_at_listed_q_equal_the_full_evaluation():
+    """The q_list form evaluates the same sums at the listed coarse q only
+    (the real-space coefficients still run over every q)."""
+    hop = rashba_hoppings(1.0, 0.3)
+    st = tufrg.TUSetup(*hop, -0.4, onsite_V0(2.0), ff_shell(9), 5, 1, "omega")
+    P = random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=31)
+    C = random_exchange_state(st.Nq, st.n_ff, st.n_o, seed=32)
+    VP, VC = tufrg.projected_vertices(st, P, C)
+    q = [3, 0, 17, 24]
+    VPq, VCq = tufrg.projected_vertices(st, P, C, q_list=q)
+    assert np.abs(VPq - VP[q]).max() < 1e-13 and np.abs(VCq - VC[q]).max() < 1e-13
+    dP, dC = tufrg.rhs(st, 0.5, P, C)
+    dPq, dCq = tufrg.rhs(st, 0.5, P, C, q_list=q)
+    assert np.abs(dPq - dP[q]).max() < 1e-12 * np.abs(dP).max()
+    assert np.abs(dCq - dC[q]).max() < 1e-12 * np.abs(dC).max()

@@ -249,6 +249,23 @@ tufrg_status tufrg_set_initial_p(tufrg_ctx *ctx, const tufrg_c64 *P0);
 tufrg_status tufrg_project(tufrg_ctx *ctx, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,
                            tufrg_c64 *VC);
 
+/* The projections of tufrg_project for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): the same VP, VC, with the rho-space buffers (transform chunks,
+ * the coefficients P(rho), C(rho) and the gathers) in a static device array of
+ * 32 MiB that the library holds on each GPU until the process ends.  The call
+ * allocates nothing; the context must have been created (its own allocation
+ * happens there) with the same device current as now.  Limit: 3 * 4 * n_dR *
+ * B^2 doubles must fit in 32 MiB (B <= 64 with n_dR <= 41; the six-orbital
+ * B = 468 setups are rejected with TUFRG_E_UNSUPPORTED).  Every buffer is
+ * written before it is read, so nothing carries over between calls, but all
+ * calls on one GPU share the array: calls that overlap in time on one GPU
+ * (several streams or host threads) race and must be serialised by the
+ * caller.  Errors: E_INVAL for a host pointer or another current device,
+ * E_UNSUPPORTED for a setup beyond the limit. */
+tufrg_status tufrg_project_static(tufrg_ctx *ctx, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,
+                                  tufrg_c64 *VC);
+
 /* Right-hand side dP/dLambda, dC/dLambda [Nq][B][B] at scale lambda.
  * P, C and dP, dC must not overlap. */
 tufrg_status tufrg_rhs(tufrg_ctx *ctx, double lambda, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *dP,

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -36,6 +37,7 @@ hipStream_t mlp_stream(const tufrg_mlp *m);
 
 struct tufrg_ctx {
   hipStream_t st = nullptr;
+  int device = 0;  // the device current at creation
   int n_o = 0, n_ff = 0, B = 0, Lq = 0, n_ref = 0, Lf = 0, Nq = 0, Nf = 0, no2 = 0, no4 = 0;
   int nD = 0, ndx = 0, ndy = 0, scheme = 0, prec = 0, nkyb = 0, nkxc = 0, nqc = 0;
   std::vector<int> ff, dlist, didx, ffgrid, dgrid, pairs;
@@ -146,6 +148,31 @@ static tufrg_status dalloc(tufrg_ctx *c, T **p, size_t n) {
     tufrg_status s_ = (x);             \
     if (s_ != TUFRG_OK) return s_;     \
   } while (0)
+
+// Static scratch of tufrg_project_static: the rho-space buffers of the
+// projections (chunk partials of the q -> rho transform, the coefficients
+// P(rho), C(rho) and the gathers) for callers that cannot allocate.  Each GPU
+// holds its own copy until the process ends; host code reaches it only through
+// the device address looked up once per device (g_scratch_ptr), never through
+// the array's name.
+static constexpr size_t STATIC_SCRATCH_DOUBLES = (size_t)4 << 20;  // 32 MiB
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+static constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[MAX_DEVICES];
+
+// device address of the static scratch on the current device (looked up on
+// the first call per device)
+static hipError_t static_scratch_lookup(int dev) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return hipSuccess;
+  void *ptr = nullptr;
+  hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = (double *)ptr;
+  return hipSuccess;
+}
 
 static bool is_device_ptr(const void *p) {
   if (!p) return false;
@@ -320,6 +347,17 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     delete c;
     return st;
   };
+  {
+    // the device of the context, and (once per device) the address of the
+    // static scratch of tufrg_project_static on it
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = static_scratch_lookup(c->device);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      c->err = std::string("device set-up failed: ") + hipGetErrorString(e);
+      return bail(TUFRG_E_HIP);
+    }
+  }
 #define CTRY(x)                          \
   do {                                   \
     tufrg_status s_ = (x);               \
@@ -735,7 +773,10 @@ static tufrg_status surrogate_loops(tufrg_ctx *c, double lam) {
   return TUFRG_OK;
 }
 
-static tufrg_status project_internal(tufrg_ctx *c, const double *P, const double *C, double *VP, double *VC) {
+// projections with the rho-space buffers given: nqc chunk partials at part,
+// then real and G ([2][nD][B][B] complex each)
+static tufrg_status project_with(tufrg_ctx *c, const double *P, const double *C, double *VP, double *VC,
+                                 double *part, int nqc, double *real, double *G) {
   ProjArgs a = proj_args(c);
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_PROJECT));
   if (c->has_c0) {
@@ -750,11 +791,15 @@ static tufrg_status project_internal(tufrg_ctx *c, const double *P, const double
     HIPCHK(c, launch_add(2 * (long long)c->Nq * c->B * c->B, P, c->d_p0, c->d_peff, c->st));
     P = c->d_peff;
   }
-  HIPCHK(c, launch_ft(a, P, C, c->d_ftpart, c->nqc, c->d_real, c->st));
-  HIPCHK(c, launch_gather(a, c->d_real, c->d_G, c->st));
-  HIPCHK(c, launch_assemble(a, P, C, c->d_G, c->d_v0p, c->d_v0c, VP, VC, c->st));
+  HIPCHK(c, launch_ft(a, P, C, part, nqc, real, c->st));
+  HIPCHK(c, launch_gather(a, real, G, c->st));
+  HIPCHK(c, launch_assemble(a, P, C, G, c->d_v0p, c->d_v0c, VP, VC, c->st));
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_PROJECT));
   return TUFRG_OK;
+}
+
+static tufrg_status project_internal(tufrg_ctx *c, const double *P, const double *C, double *VP, double *VC) {
+  return project_with(c, P, C, VP, VC, c->d_ftpart, c->nqc, c->d_real, c->d_G);
 }
 
 // dP = scale VP Lpp VP, dC = 2 scale VC Lph VC; a masked channel gets zero
@@ -968,6 +1013,28 @@ extern "C" tufrg_status tufrg_project(tufrg_ctx *c, const tufrg_c64 *P, const tu
   if (!is_device_ptr(P) || !is_device_ptr(C) || !is_device_ptr(VP) || !is_device_ptr(VC))
     return fail(c, TUFRG_E_INVAL, "P, C, VP, VC must be device pointers");
   return project_internal(c, (const double *)P, (const double *)C, (double *)VP, (double *)VC);
+}
+
+extern "C" tufrg_status tufrg_project_static(tufrg_ctx *c, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,
+                                             tufrg_c64 *VC) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!is_device_ptr(P) || !is_device_ptr(C) || !is_device_ptr(VP) || !is_device_ptr(VC))
+    return fail(c, TUFRG_E_INVAL, "P, C, VP, VC must be device pointers");
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev != c->device) return fail(c, TUFRG_E_INVAL, "the context's device must be current");
+  double *scr = g_scratch_ptr[dev];
+  if (!scr) return fail(c, TUFRG_E_HIP, "static scratch not set up on this device");
+  // one [2][nD][B][B] complex block each for the coefficients and the
+  // gathers, the rest for transform chunks (at least one)
+  const size_t unit = 2 * 2 * (size_t)c->nD * c->B * c->B;
+  if (3 * unit > STATIC_SCRATCH_DOUBLES)
+    return fail(c, TUFRG_E_UNSUPPORTED,
+                "static scratch of 32 MiB holds 3 * 4 * n_dR * B^2 doubles at most; this setup needs " +
+                    std::to_string(3 * unit * sizeof(double)) + " bytes");
+  const int nqc = (int)std::min<size_t>((size_t)c->nqc, STATIC_SCRATCH_DOUBLES / unit - 2);
+  double *real = scr + (size_t)nqc * unit, *G = real + unit;
+  return project_with(c, (const double *)P, (const double *)C, (double *)VP, (double *)VC, scr, nqc, real, G);
 }
 
 extern "C" tufrg_status tufrg_set_initial_c(tufrg_ctx *c, const tufrg_c64 *C0) {

@@ -40,7 +40,8 @@ SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "t
            "tufrg_mlp_train", "tufrg_sur_features", "tufrg_sur_targets", "tufrg_sur_attach",
            "tufrg_sur_loops", "tufrg_batch_create", "tufrg_batch_destroy", "tufrg_batch_last_error",
            "tufrg_batch_dims", "tufrg_batch_flow", "tufrg_set_initial_c", "tufrg_basis_matrix",
-           "tufrg_basis_apply", "tufrg_set_initial_p", "tufrg_ff_symmetrize", "tufrg_ff_apply"]
+           "tufrg_basis_apply", "tufrg_set_initial_p", "tufrg_ff_symmetrize", "tufrg_ff_apply",
+           "tufrg_project_static"]
 TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE, TIMER_SURROGATE = 0, 1, 2, 3
 
 
@@ -96,6 +97,7 @@ _lib.tufrg_dims.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int32)] * 4
 _lib.tufrg_band_data.argtypes = [_vp, _vp, _vp]
 _lib.tufrg_bubble.argtypes = [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp]
 _lib.tufrg_project.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.tufrg_project_static.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.tufrg_basis_matrix.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
 _lib.tufrg_basis_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
 _lib.tufrg_ff_symmetrize.argtypes = [ctypes.c_int32, _vp, _vp, _vp]
@@ -272,6 +274,14 @@ def tufrg_project(ctx, P, C, VP, VC):
     """Projected vertices VP, VC [Nq][B][B] of the state P, C, all on the device."""
     _check(_lib.tufrg_project(ctx.handle, _state(ctx, P, "P"), _state(ctx, C, "C"), _state(ctx, VP, "VP"),
                               _state(ctx, VC, "VC")), ctx.handle)
+
+
+def tufrg_project_static(ctx, P, C, VP, VC):
+    """tufrg_project without any device allocation: its rho-space buffers live
+    in the library's static per-GPU scratch (calls on one GPU must not overlap)."""
+    _check(_lib.tufrg_project_static(ctx.handle, _state(ctx, P, "P"), _state(ctx, C, "C"), _state(ctx, VP, "VP"),
+                                     _state(ctx, VC, "VC")),
+           ctx.handle)
 
 
 def tufrg_set_initial_c(ctx, C0):

@@ -52,12 +52,23 @@ def loop_flops_per_pair(n_o, ndx, ndy, shell=False):
 
 
 def mfma_flops_per_pair(ndy, n_o=6):
-    """Matrix-core flops of the BF16X3 loop per (q, k, channel): one k adds
-    K = 2 n_o (band, re/im) to the per-row product of the (2 ndy + 1) *
-    n_o (n_o + 1) / 2 phase-weighted projector rows with the 2 n_o^2 real
-    columns, done as three BF16 products (hi*hi, hi*lo, lo*hi)."""
-    rows = (2 * ndy + 1) * n_o * (n_o + 1) // 2
-    return 3 * 2 * rows * (2 * n_o * n_o) * (2 * n_o)
+    """Matrix-core flops the BF16X3 loop executes per (q, k, channel): one k
+    adds K = n_o (bands) to the product of the (2 ndy + 1) n_o^2 phase rows
+    (phase times real-basis projector coordinate, padded to whole 16-row
+    tiles) with the n_o^2 real-basis columns of its q, as three BF16 products
+    (hi*hi, hi*lo, lo*hi)."""
+    rows = -(-(2 * ndy + 1) * n_o * n_o // 16) * 16
+    return 3 * 2 * rows * (n_o * n_o) * n_o
+
+
+def credited_loop_flops_per_pair(n_o, ndy, n_b=None):
+    """Algorithmic flops of one loop entry set per (q, k, channel) in the
+    survey's count: the form-factor contraction 8 n_dRy n_o^4 with the
+    separable transform (n_dRy = 2 ndy + 1 phases of the ky sum), halved for
+    the hermiticity the kernels exploit, plus the block build
+    8 n_o^2 n_b (n_b + n_o^2)."""
+    n_b = n_o if n_b is None else n_b
+    return 8 * (2 * ndy + 1) * n_o ** 4 // 2 + 8 * n_o ** 2 * n_b * (n_b + n_o ** 2)
 
 
 def _box(ff):
@@ -66,7 +77,7 @@ def _box(ff):
 
 
 # sources of the loop kernel per precision, with the host code that sets its launch shape
-LOOP_SOURCES = {"bf16x3": ("k_loop_mfma.hip", "common.h", "tufrg_host.hip")}
+LOOP_SOURCES = {"bf16x3": ("k_loop_rb.hip", "common.h", "tufrg_host.hip")}
 
 
 def _loop_source_hash(prec):
@@ -531,7 +542,7 @@ def main():
     launches = loop_n / K
     ndx, ndy = _box(w["ff"])
     if args.prec == "bf16x3":
-        flops_step = 2.0 * Nq * Nf * mfma_flops_per_pair(ndy, w["n_o"])
+        flops_step = 2.0 * Nq * Nf * credited_loop_flops_per_pair(w["n_o"], ndy)
         bound, peak = "mfma", PEAK_BF16_MFMA
     else:
         flops_step = 2.0 * Nq * Nf * loop_flops_per_pair(w["n_o"], ndx, ndy, w["cutoff"] == "shell")

@@ -50,11 +50,15 @@ struct LoopArgs {
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
 // more than two spin-orbitals (six: t2g with spin-orbit coupling)
 hipError_t launch_loop_gen(const LoopArgs &a, hipStream_t st);
-// six spin-orbitals on the matrix cores (one channel): row buffers Y of
-// loop_mfma_rowbuf_floats(ndy, Lf) floats per coarse q, then (rowsum) the partials
-hipError_t launch_loop_mfma(const LoopArgs &a, int ch, float *Y, hipStream_t st);
-hipError_t launch_loop_rowsum(const LoopArgs &a, const float *Y, hipStream_t st);
-size_t loop_mfma_rowbuf_floats(int ndy, int Lf);
+// six spin-orbitals on the matrix cores in the real basis of Hermitian
+// matrices (one channel): row buffers Y of loop_rb_rowbuf_floats(ndy, Lf)
+// floats per group of four coarse q, then (sums) the compact loops; the
+// half-plane points of the computed shape from loop_rb_half_points
+hipError_t launch_loop_rb(const LoopArgs &a, int ch, float *Y, hipStream_t st);
+hipError_t launch_loop_rb_sums(const LoopArgs &a, const float *Y, double *lamb, const int *hmap, int nD,
+                               double *dst, hipStream_t st);
+size_t loop_rb_rowbuf_floats(int ndy, int Lf);
+int loop_rb_half_points(int ndy, int *dx, int *dy);
 // sums partials, applies 1/Nf, fills dx < 0 by hermiticity
 hipError_t launch_loop_finalize(const LoopArgs &a, int nD, const int *dlist, double *compact, hipStream_t st);
 // compact [n_ch][n_q][nD][n_o^4] -> full [n_q][B][B] for one channel

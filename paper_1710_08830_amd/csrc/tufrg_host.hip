@@ -103,6 +103,8 @@ struct tufrg_ctx {
   unsigned long long *d_sbits = nullptr;       // max |diff|, max |ref|, float max
   int *d_rows = nullptr, *h_rows = nullptr;    // sampled q_x rows (device, pinned host)
   float *d_yrow = nullptr;                     // BF16X3 loops: row buffers of a chunk of coarse q
+  double *d_lamb = nullptr;                    // BF16X3 loops: real-basis sums of a chunk
+  int *d_hmap = nullptr;                       // BF16X3 loops: half-plane point of each difference vector
   int mfma_chunk = 0;
   unsigned long long *h_sbits = nullptr;       // pinned
   // set during tufrg_flow
@@ -619,10 +621,36 @@ static tufrg_status compute_kval(tufrg_ctx *c, double lam, int deriv) {
 // must be current (compute_kval)
 static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch, int q_first,
                                      int n_q, double *dst, const int *rows) {
-  if (!c->d_yrow) {
-    // whole q_x rows per chunk, about 512 coarse q (two workgroups per compute unit)
-    c->mfma_chunk = std::max(1, 512 / c->Lq) * c->Lq;
-    TRY(dalloc(c, &c->d_yrow, (size_t)c->mfma_chunk * loop_mfma_rowbuf_floats(c->ndy, c->Lf)));
+  if (!c->d_hmap) {
+    // half-plane point of each difference vector (the others by conjugation)
+    int hx[32], hy[32];
+    const int nh = loop_rb_half_points(c->ndy, hx, hy);
+    std::vector<int> hm(c->nD, -1);
+    for (int i = 0; i < c->nD; ++i) {
+      int dx = c->dlist[2 * i], dy = c->dlist[2 * i + 1], cj = 0;
+      if (dx < 0 || (dx == 0 && dy < 0)) {
+        dx = -dx;
+        dy = -dy;
+        cj = 1;
+      }
+      for (int h = 0; h < nh; ++h)
+        if (hx[h] == dx && hy[h] == dy) hm[i] = h | (cj << 16);
+      if (hm[i] < 0) return fail(c, TUFRG_E_UNSUPPORTED, "difference vector outside the loop kernel's shape");
+    }
+    int *d = nullptr;
+    TRY(dalloc(c, &d, hm.size()));
+    HIPCHK(c, hipMemcpyAsync(d, hm.data(), hm.size() * sizeof(int), hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    c->d_hmap = d;
+  }
+  if (!c->d_yrow || !c->d_lamb) {
+    // whole q_x rows per chunk, about 256 coarse q (64 groups of four)
+    c->mfma_chunk = std::max(1, 256 / c->Lq) * c->Lq;
+    const size_t groups = (size_t)(c->mfma_chunk + 3) / 4;
+    if (!c->d_yrow) TRY(dalloc(c, &c->d_yrow, groups * loop_rb_rowbuf_floats(c->ndy, c->Lf)));
+    int hx[32], hy[32];
+    const size_t nh = (size_t)loop_rb_half_points(c->ndy, hx, hy);
+    TRY(dalloc(c, &c->d_lamb, 2 * (size_t)c->mfma_chunk * nh * 36 * 36));
   }
   const size_t blk = (size_t)c->nD * c->no4;
   for (int chi = 0; chi < n_ch; ++chi) {
@@ -635,10 +663,10 @@ static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch
       a.rows = rows ? rows + q0 / c->Lq : nullptr;
       // the loop timer covers the matrix-core kernel of each chunk
       HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
-      HIPCHK(c, launch_loop_mfma(a, ch, c->d_yrow, c->st));
+      HIPCHK(c, launch_loop_rb(a, ch, c->d_yrow, c->st));
       HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
-      HIPCHK(c, launch_loop_rowsum(a, c->d_yrow, c->st));
-      HIPCHK(c, launch_loop_finalize(a, c->nD, c->d_dlist, dst + 2 * ((size_t)chi * n_q + q0) * blk, c->st));
+      HIPCHK(c, launch_loop_rb_sums(a, c->d_yrow, c->d_lamb, c->d_hmap, c->nD,
+                                    dst + 2 * ((size_t)chi * n_q + q0) * blk, c->st));
     }
   }
   return TUFRG_OK;

@@ -1,8 +1,12 @@
 """Benchmark of the TU-fRG right-hand side on one MI355X.
 
-Workload: lattice Rashba model (t=1, mu=-0.4, alpha=0.3, onsite U=2.5), 9 form
-factors (bundle dimension 36), 24x24 q-mesh refined 24x per cell (576^2 fine
-k-points), Omega cutoff; loops and bundle products in FP32, state in FP64.
+Default workload (the largest single-GPU configuration): three-orbital t2g
+model with atomic spin-orbit coupling (six spin-orbitals, hoppings from seed
+1, Kanamori U = 2, J = 0.3, four electrons per site), 13 form factors (bundle
+dimension 468), 48 x 48 q-mesh refined 16x per cell (768^2 fine k-points),
+temperature cutoff from 10 on the 200-step log grid; loops in BF16 split
+products on the matrix cores (FP32 accumulation), projections and bundle
+products FP32/FP64, state FP64.
 
 One step = one explicit Euler step of the flow through the C ABI: regulator
 values, both loop channels, the real-space transform, gathers and assembly of
@@ -11,12 +15,13 @@ max-coupling readback (tufrg_flow with n_steps = K).  Inputs are resident in
 HBM before the timed region.
 
 Printed: one JSON line with the headline value (loop entries/s over the whole
-step), flow steps/s, the same for the FP64-plain form and the relative error of
-the FP32 state against it, the roofline of the loop kernel (event-timed inside
-the library over the timed region), the production Dormand-Prince flow, the
-orbital -> band basis change (basis matrices and sandwiches, FP64, and Euler
-steps of the band-basis flow), and a CPU
-baseline of the FP64 oracle on a sample of q points.
+step, 2 Nq B^2 per step) and compact loop entries/s, flow steps/s, the
+roofline of the loop kernel (survey's algorithmic flop count, event-timed
+inside the library over the timed region), the FP64-plain form over the first
+steps with its relative error and the speed-up of the mixed form, the
+surrogate-assisted form over the timed window, the two-orbital Rashba line
+(24 x 24 refined 24x, FP32) as an extra key, and a CPU baseline of the FP64
+oracle (one thread and all cores) on a bounded sample.
 """
 
 import argparse
@@ -30,7 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "loop entries/s + flow steps/s, mixed/surrogate vs FP64-plain at ≤1e-4 rel err"
-WORKLOAD = "rashba_s9_L24"
+WORKLOAD = "t2g_s13_L48"
 PEAK_FP32_VECTOR = 157.3e12
 PEAK_BF16_MFMA = 2.5e15
 PEAK_FP64_VECTOR = 78.6e12
@@ -101,37 +106,84 @@ def _traffic(workload, prec):
     return float(t["hbm_bytes_per_launch"])
 
 
-def cpu_baseline(w, n_sample=4):
-    """FP64 oracle (single thread) on a sample of q points: both loop channels,
-    the projections of the whole state (charged pro rata) and the bundle
-    products at the sampled q."""
+def _cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, n
+
+
+def _oracle_rhs_time_per_q(w, n_sample, n_ref_sample):
+    """FP64 oracle time of the right-hand side per coarse q, from a bounded
+    sample: the loops (both channels) and bundle products at n_sample q on the
+    workload's q-mesh with the fine mesh reduced to n_ref_sample per cell
+    (the loop cost per q is linear in the number of fine k, so it is scaled
+    by Nf / Nf_sample), and the projections of the whole state charged per q
+    from a run on the smallest alias-free q-mesh (their cost per q does not
+    depend on Nq)."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
 
     from oracle import tufrg as otu
 
-    with threadpool_limits(limits=1):
-        st = otu.TUSetup.from_workload(w)
-        rng = np.random.default_rng(0)
-        qs = sorted(rng.choice(st.Nq, size=n_sample, replace=False).tolist())
-        P = np.zeros((st.Nq, st.n_ff, st.n_ff) + (st.n_o,) * 4, dtype=np.complex128)
-        C = np.zeros_like(P)
-        lam = 1.0
-        t0 = time.perf_counter()
-        VP, VC = otu.projected_vertices(st, P, C)
-        t_proj = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        Lpp = otu.loops(st, "pp", lam, q_list=qs)
-        Lph = otu.loops(st, "ph", lam, q_list=qs)
-        otu.bundle_pp(VP[qs], Lpp)
-        otu.bundle_ph(VC[qs], Lph)
-        t_q = time.perf_counter() - t0
-    B = st.n_ff * st.n_o ** 2
-    t_eff = t_q + t_proj * n_sample / st.Nq
-    return {"value": 2.0 * B * B * n_sample / t_eff, "unit": "loop entries/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n_sample} of {st.Nq} q points (both channels, loops + bundle), "
-                      f"projections of all q charged pro rata; {t_eff:.1f} s of CPU time"}
+    st = otu.TUSetup.from_workload(w, n_ref=n_ref_sample)
+    Nf_full = (w["Lq"] * w["n_ref"]) ** 2
+    rng = np.random.default_rng(0)
+    qs = sorted(rng.choice(st.Nq, size=n_sample, replace=False).tolist())
+    lam = 1.0
+    # projections: per-q cost on the smallest q-mesh the form factors allow
+    rmax = max(max(abs(int(x)), abs(int(y))) for x, y in w["ff"])
+    stp = otu.TUSetup.from_workload(w, Lq=4 * rmax + 1, n_ref=1)
+    Pp = np.zeros((stp.Nq, stp.n_ff, stp.n_ff) + (stp.n_o,) * 4, dtype=np.complex128)
+    t0 = time.perf_counter()
+    VPp, VCp = otu.projected_vertices(stp, Pp, Pp)
+    t_proj_q = (time.perf_counter() - t0) / stp.Nq
+    t0 = time.perf_counter()
+    Lpp = otu.loops(st, "pp", lam, q_list=qs)
+    Lph = otu.loops(st, "ph", lam, q_list=qs)
+    t_loops = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    otu.bundle_pp(VPp[:1].repeat(n_sample, axis=0), Lpp)
+    otu.bundle_ph(VCp[:1].repeat(n_sample, axis=0), Lph)
+    t_bundle = time.perf_counter() - t0
+    t_q = t_loops * Nf_full / st.Nf / n_sample + t_bundle / n_sample + t_proj_q
+    spent = t_loops + t_bundle + t_proj_q * stp.Nq
+    return t_q, qs, spent
+
+
+def cpu_baseline(w, n_sample=1, n_ref_sample=None):
+    """The FP64 oracle on the machine's host cores, one thread and all cores, on a
+    bounded sample (see _oracle_rhs_time_per_q), in the headline's unit: loop
+    entries (2 B^2 per q and right-hand side) per second."""
+    from threadpoolctl import threadpool_limits
+
+    model, ncores = _cpu_info()
+    B = len(w["ff"]) * w["n_o"] ** 2
+    if n_ref_sample is None:
+        n_ref_sample = w["n_ref"] if w["n_o"] == 2 else 2
+    out = {}
+    for label, lim in (("one_thread", 1), ("all_cores", ncores)):
+        with threadpool_limits(limits=lim):
+            t_q, qs, spent = _oracle_rhs_time_per_q(w, n_sample, n_ref_sample)
+        out[label] = {"value": 2.0 * B * B / t_q, "threads": lim, "cpu_seconds_spent": spent}
+    best = max(out.values(), key=lambda d: d["value"])
+    return {"value": best["value"], "unit": "loop entries/s", "cores": best["threads"], "kind": "oracle",
+            "cpu_model": model, "nproc": ncores,
+            "one_thread": out["one_thread"], "all_cores": out["all_cores"],
+            "sample": (f"right-hand side per coarse q of {w['name']}: loops and bundle products at "
+                       f"{n_sample} of {w['Lq'] ** 2} q with the fine mesh reduced to {n_ref_sample}x per cell "
+                       f"and scaled by the number of fine k (extrapolated), projections charged per q from the "
+                       f"smallest alias-free q-mesh; NumPy oracle, BLAS threads set by threadpoolctl (only "
+                       f"its matrix products use more than one core)")}
 
 
 def surrogate_leg(T, torch, ctx, P, C, P64, C64, dp, w, K, t_plain_step, n_lam=24, n_rows=200000,
@@ -225,115 +277,6 @@ def surrogate_leg(T, torch, ctx, P, C, P64, C64, dp, w, K, t_plain_step, n_lam=2
     return res
 
 
-def surrogate_bench(T, torch, w, K, prec, n_rows=200000, epochs=(20, 20, 20)):
-    """Surrogate-assisted flow of the six-orbital model on the 48 x 48 q-mesh:
-    the first K steps of its 200-step Euler grid with plain loops (FP32 on the
-    vector units or BF16X3 on the matrix cores); the
-    network trained on n_rows random blocks of the plain loops at the scales of
-    those steps (the loops a plain flow produces); then the same K steps with
-    the network (5 % of the q_x rows recomputed plainly, fallback above 1e-3
-    sampled error or coupling 20)."""
-    import numpy as np
-
-    from synth import mlp_init, mlp_shape
-
-    dev = torch.device("cuda:0")
-    ctx = T.Context.from_workload(w, precision=prec)
-    no4 = ctx.n_o ** 4
-    nb = 2 * ctx.Nq * ctx.n_dR
-    lam0, n = w["lam0"], w["n_steps"]
-    lam_k = lam0 * (w["lam_end"] / lam0) ** (K / n)
-    P = torch.zeros((ctx.Nq, ctx.B, ctx.B), dtype=torch.complex128, device=dev)
-    C = torch.zeros_like(P)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r0 = T.tufrg_flow(ctx, P, C, lam0, lam_k, n_steps=K, v_max=w["v_max"])
-    torch.cuda.synchronize()
-    t_plain = time.perf_counter() - t0
-    print(f"surrogate bench: {K} plain steps in {t_plain:.1f} s", file=sys.stderr, flush=True)
-    P0, C0 = P.clone(), C.clone()
-    # training data from plain loops at the scales of the K steps
-    n_lam = K
-    per = min(nb, n_rows // n_lam)
-    lams = lam0 * (w["lam_end"] / lam0) ** (np.arange(K) / n)
-    sizes = mlp_shape(11 + ctx.n_dR, 256, 2 * no4)
-    rng = np.random.default_rng(3)
-    X = torch.zeros((n_lam * per, sizes[0]), dtype=torch.float32, device=dev)
-    Y = torch.zeros((n_lam * per, sizes[-1]), dtype=torch.float32, device=dev)
-    Lc = torch.zeros((2, ctx.Nq, ctx.n_dR, no4), dtype=torch.complex128, device=dev)
-    t0 = time.perf_counter()
-    scales = []
-    for i, lam in enumerate(lams):
-        b = rng.choice(nb, size=per, replace=False)
-        q, ch, iD = ((b // ctx.n_dR) % ctx.Nq, b // (ctx.n_dR * ctx.Nq), b % ctx.n_dR)
-        q, ch, iD = (torch.from_numpy(a.astype(np.int32)).to(dev) for a in (q, ch, iD))
-        T.tufrg_loops_compact(ctx, lam, 1, Lc)
-        ys = Y[i * per:(i + 1) * per]
-        scales.append(T.tufrg_sur_targets(ctx, per, 1.0, Lc, ys, q, ch, iD))
-        T.tufrg_sur_features(ctx, per, lam, X[i * per:(i + 1) * per], q, ch, iD)
-        T.tufrg_sur_targets(ctx, per, scales[-1], Lc, ys, q, ch, iD)
-    del Lc
-    torch.cuda.synchronize()
-    t_data = time.perf_counter() - t0
-    print(f"surrogate bench: {n_lam * per} training rows in {t_data:.1f} s", file=sys.stderr, flush=True)
-    net = T.Mlp(sizes, mlp_init(sizes, seed=3))
-    t0 = time.perf_counter()
-    loss = None
-    for ep, lr in zip(epochs, (1e-3, 3e-4, 1e-4)):
-        loss = T.tufrg_mlp_train(net, X, Y, batch=2048, epochs=ep, lr=lr, seed=3)
-        print(f"surrogate bench: {ep} epochs at lr {lr:g}, loss {loss:.3e}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    del X, Y
-    T.tufrg_sur_attach(ctx, net, lams, scales)
-    P.zero_()
-    C.zero_()
-    torch.cuda.synchronize()
-    T.tufrg_timing(ctx, True)
-    t0 = time.perf_counter()
-    r1 = T.tufrg_flow(ctx, P, C, lam0, lam_k, n_steps=K, v_max=w["v_max"], surrogate=True, sample_frac=0.05,
-                      sur_tol=1e-3, plain_above=20.0, sample_seed=3)
-    torch.cuda.synchronize()
-    t_sur = time.perf_counter() - t0
-    print(f"surrogate bench: {K} surrogate steps in {t_sur:.1f} s", file=sys.stderr, flush=True)
-    sur_ms, sur_n = T.tufrg_timing_read(ctx, T.TIMER_SURROGATE)
-    T.tufrg_timing(ctx, False)
-    err = max((P - P0).abs().max().item() / P0.abs().max().item(),
-              (C - C0).abs().max().item() / C0.abs().max().item())
-    # the same window at a looser sampled tolerance: what the network replaces when accepted
-    P.zero_()
-    C.zero_()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r2 = T.tufrg_flow(ctx, P, C, lam0, lam_k, n_steps=K, v_max=w["v_max"], surrogate=True, sample_frac=0.05,
-                      sur_tol=5e-2, plain_above=20.0, sample_seed=3)
-    torch.cuda.synchronize()
-    t_loose = time.perf_counter() - t0
-    err_loose = max((P - P0).abs().max().item() / P0.abs().max().item(),
-                    (C - C0).abs().max().item() / C0.abs().max().item())
-    entries = 2.0 * ctx.Nq * ctx.B ** 2
-    out = {
-        "metric": METRIC, "value": entries * K / t_sur, "unit": "loop entries/s", "n_gpus": 1, "steps": K,
-        "warmup": 0, "ms_per_step": t_sur / K * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": prec, "data": "synthetic",
-        "config": {"workload": w["name"], "n_orb": w["n_o"], "n_ff": len(w["ff"]), "B": ctx.B, "Lq": w["Lq"],
-                   "n_ref": w["n_ref"], "Nq": ctx.Nq, "Nf": ctx.Nf,
-                   "step": f"first {K} of {n} Euler steps with the loop surrogate", "parallelism": "single GPU"},
-        "plain": {"precision": prec, "ms_per_step": t_plain / K * 1e3, "value": entries * K / t_plain,
-                  "result": r0},
-        "surrogate": dict(r1, seconds=t_sur, network_ms=sur_ms, network_calls=sur_n),
-        "speedup_vs_plain": t_plain / t_sur, "rel_err_vs_plain": err,
-        "surrogate_tol_5e-2": dict(r2, seconds=t_loose, ms_per_step=t_loose / K * 1e3,
-                                   speedup_vs_plain=t_plain / t_loose, rel_err_vs_plain=err_loose),
-        "training": {"rows": n_lam * per, "scales": [float(x) for x in lams], "data_seconds": t_data,
-                     "train_seconds": t_train, "final_loss": loss, "net": sizes},
-        "roofline": None,
-    }
-    net.close()
-    ctx.close()
-    return out
-
-
 def basis_flops(Nq, n_o, Nf, box):
     """Algorithmic FP64 flops of one basis matrix (one channel) with separable
     phases: per coarse q, entry (a, b, c, d) and fine k one complex product
@@ -407,6 +350,183 @@ def basis_leg(T, torch, ctx, P, C, ff, reps=3, band_ctx=None, V0=None, steps=20)
     return out
 
 
+def six_orbital_line(T, torch, w, prec, K, W, fp64_steps=2, surrogate=True, n_rows=120000,
+                     epochs=(10, 10, 10)):
+    """Headline of a six-orbital workload: K timed Euler steps (after W warmup
+    steps) of the 200-step grid from Lambda0 in the mixed arithmetic, the
+    loop-kernel roofline, the FP64-plain form over the first fp64_steps steps
+    (matched against the mixed form over the same steps), and the
+    surrogate-assisted form over the timed window."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    lam0, n = w["lam0"], w["n_steps"]
+    lam_at = lambda i: lam0 * (w["lam_end"] / lam0) ** (i / n)  # noqa: E731
+    ctx = T.Context.from_workload(w, precision=prec)
+    B, Nq, Nf, nD = ctx.B, ctx.Nq, ctx.Nf, ctx.n_dR
+    P = torch.zeros((Nq, B, B), dtype=torch.complex128, device=dev)
+    C = torch.zeros_like(P)
+    if W > 0:
+        T.tufrg_flow(ctx, P, C, lam0, lam_at(W), n_steps=W, v_max=1e30)
+    P.zero_()
+    C.zero_()
+    torch.cuda.synchronize()
+    T.tufrg_timing(ctx, True)
+    t0 = time.perf_counter()
+    res = T.tufrg_flow(ctx, P, C, lam0, lam_at(K), n_steps=K, v_max=w["v_max"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    loop_ms, loop_n = T.tufrg_timing_read(ctx, T.TIMER_LOOP)
+    proj_ms, proj_n = T.tufrg_timing_read(ctx, T.TIMER_PROJECT)
+    bund_ms, bund_n = T.tufrg_timing_read(ctx, T.TIMER_BUNDLE)
+    T.tufrg_timing(ctx, False)
+    entries = 2.0 * Nq * B * B
+    compact = 2.0 * Nq * nD * ctx.n_o ** 4
+    ndx, ndy = _box(w["ff"])
+    credited = credited_loop_flops_per_pair(w["n_o"], ndy)
+    flops_step = 2.0 * Nq * Nf * credited
+    launches = loop_n / K
+    loop_step_s = loop_ms / K * 1e-3
+    achieved = flops_step / loop_step_s  # = credited flops per launch / average launch time
+    if prec == "bf16x3":
+        bound, peak = "mfma", PEAK_BF16_MFMA
+    else:
+        bound, peak = "alu", PEAK_FP32_VECTOR
+    out = {
+        "metric": METRIC, "value": entries * K / dt, "unit": "loop entries/s", "n_gpus": 1, "steps": K,
+        "warmup": W, "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": w["name"], "n_orb": w["n_o"], "n_ff": len(w["ff"]), "B": B, "Lq": w["Lq"],
+                   "n_ref": w["n_ref"], "Nq": Nq, "Nf": Nf, "cutoff": w["cutoff"],
+                   "step": f"Euler step {1}..{K} of the {n}-step grid from Lambda = {lam0:g}: "
+                           "loops + projections + bundles + update",
+                   "parallelism": "single GPU"},
+        "flow_steps_per_s": K / dt,
+        "compact_loop_entries_per_s": compact * K / dt,
+        "stage_ms_per_step": {"loop_kernel": loop_ms / K, "projections": proj_ms / K,
+                              "bundle_products": bund_ms / K},
+        "loop_kernel_ms": loop_ms / loop_n,
+        "loop_launches_per_step": launches,
+        "loop_entries_per_s_kernel": entries / loop_step_s,
+        "roofline": {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": _traffic(w["name"], prec),
+                     "flops_per_pair": credited,
+                     "executed_matrix_flops_per_pair": (mfma_flops_per_pair(ndy, w["n_o"])
+                                                        if prec == "bf16x3" else None)},
+        "flow_result": res,
+    }
+    print(f"bench: {w['name']} {prec}: {dt / K * 1e3:.1f} ms per step", file=sys.stderr, flush=True)
+    # FP64-plain over the first steps, against the mixed form over the same steps
+    if fp64_steps > 0:
+        P.zero_()
+        C.zero_()
+        T.tufrg_flow(ctx, P, C, lam0, lam_at(fp64_steps), n_steps=fp64_steps, v_max=w["v_max"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.zero_()
+        C.zero_()
+        T.tufrg_flow(ctx, P, C, lam0, lam_at(fp64_steps), n_steps=fp64_steps, v_max=w["v_max"])
+        torch.cuda.synchronize()
+        dt_mix = (time.perf_counter() - t0) / fp64_steps
+        Pm, Cm = P.clone(), C.clone()
+        ctx64 = T.Context.from_workload(w, precision="fp64")
+        P.zero_()
+        C.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T.tufrg_flow(ctx64, P, C, lam0, lam_at(fp64_steps), n_steps=fp64_steps, v_max=w["v_max"])
+        torch.cuda.synchronize()
+        dt64 = (time.perf_counter() - t0) / fp64_steps
+        ctx64.close()
+        err = max((Pm - P).abs().max().item() / P.abs().max().item(),
+                  (Cm - C).abs().max().item() / C.abs().max().item())
+        out["fp64_plain"] = {"steps": fp64_steps, "ms_per_step": dt64 * 1e3, "value": entries / dt64,
+                             "flow_steps_per_s": 1.0 / dt64,
+                             "note": "first steps from Lambda0 only (an FP64 step takes seconds)"}
+        out["mixed_vs_fp64_plain"] = {"rel_err": err, "speedup": dt64 / dt_mix, "steps": fp64_steps,
+                                      "mixed_ms_per_step": dt_mix * 1e3}
+        del Pm, Cm
+        print(f"bench: fp64-plain {dt64 * 1e3:.0f} ms per step, rel err {err:.2e}", file=sys.stderr, flush=True)
+    if surrogate:
+        out["surrogate_flow"] = surrogate_window(T, torch, ctx, w, K, dt / K, n_rows=n_rows, epochs=epochs)
+    ctx.close()
+    return out
+
+
+def surrogate_window(T, torch, ctx, w, K, t_plain_step, n_rows=120000, epochs=(10, 10, 10)):
+    """Surrogate-assisted form over the timed window: the network trained on
+    n_rows random blocks of the plain loops at the scales of the K steps (the
+    loops a plain flow produces), then the same K steps with the network (5 %
+    of the q_x rows recomputed plainly per right-hand side, plain loops
+    everywhere when the sampled error exceeds 1e-3 or the coupling 20),
+    compared with the plain flow of those steps."""
+    import numpy as np
+
+    from synth import mlp_init, mlp_shape
+
+    dev = torch.device("cuda:0")
+    no4 = ctx.n_o ** 4
+    nb = 2 * ctx.Nq * ctx.n_dR
+    lam0, n = w["lam0"], w["n_steps"]
+    lam_k = lam0 * (w["lam_end"] / lam0) ** (K / n)
+    lams = lam0 * (w["lam_end"] / lam0) ** (np.arange(K) / n)
+    P = torch.zeros((ctx.Nq, ctx.B, ctx.B), dtype=torch.complex128, device=dev)
+    C = torch.zeros_like(P)
+    T.tufrg_flow(ctx, P, C, lam0, lam_k, n_steps=K, v_max=w["v_max"])
+    P0, C0 = P.clone(), C.clone()
+    per = min(nb, n_rows // K)
+    sizes = mlp_shape(11 + ctx.n_dR, 256, 2 * no4)
+    rng = np.random.default_rng(3)
+    X = torch.zeros((K * per, sizes[0]), dtype=torch.float32, device=dev)
+    Y = torch.zeros((K * per, sizes[-1]), dtype=torch.float32, device=dev)
+    Lc = torch.zeros((2, ctx.Nq, ctx.n_dR, no4), dtype=torch.complex128, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    scales = []
+    for i, lam in enumerate(lams):
+        b = rng.choice(nb, size=per, replace=False)
+        q, ch, iD = ((b // ctx.n_dR) % ctx.Nq, b // (ctx.n_dR * ctx.Nq), b % ctx.n_dR)
+        q, ch, iD = (torch.from_numpy(a.astype(np.int32)).to(dev) for a in (q, ch, iD))
+        T.tufrg_loops_compact(ctx, lam, 1, Lc)
+        ys = Y[i * per:(i + 1) * per]
+        scales.append(T.tufrg_sur_targets(ctx, per, 1.0, Lc, ys, q, ch, iD))
+        T.tufrg_sur_features(ctx, per, lam, X[i * per:(i + 1) * per], q, ch, iD)
+        T.tufrg_sur_targets(ctx, per, scales[-1], Lc, ys, q, ch, iD)
+    del Lc
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    net = T.Mlp(sizes, mlp_init(sizes, seed=3))
+    t0 = time.perf_counter()
+    loss = None
+    for ep, lr in zip(epochs, (1e-3, 3e-4, 1e-4)):
+        loss = T.tufrg_mlp_train(net, X, Y, batch=2048, epochs=ep, lr=lr, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del X, Y
+    T.tufrg_sur_attach(ctx, net, lams, scales)
+    out = {"training": {"rows": K * per, "scales": K, "data_seconds": t_data, "train_seconds": t_train,
+                        "final_loss": loss, "net": sizes}}
+    for key, tol in (("tol_1e-3", 1e-3), ("tol_5e-2", 5e-2)):
+        P.zero_()
+        C.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = T.tufrg_flow(ctx, P, C, lam0, lam_k, n_steps=K, v_max=w["v_max"], surrogate=True, sample_frac=0.05,
+                         sur_tol=tol, plain_above=20.0, sample_seed=3)
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t0
+        err = max((P - P0).abs().max().item() / P0.abs().max().item(),
+                  (C - C0).abs().max().item() / C0.abs().max().item())
+        out[key] = dict(r, seconds=dts, ms_per_step=dts / K * 1e3, speedup_vs_plain=t_plain_step / (dts / K),
+                        rel_err_vs_plain=err, served_fraction=r["n_surrogate"] / max(1, r["n_rhs"]))
+        print(f"bench: surrogate at tol {tol:g}: {r['n_surrogate']} of {r['n_rhs']} from the network, "
+              f"rel err {err:.2e}", file=sys.stderr, flush=True)
+    T.tufrg_sur_attach(ctx, None)
+    net.close()
+    del P0, C0
+    return out
+
+
 def batch_bench(T, torch, K, W):
     """32 independent Rashba/Hubbard instances of uneven size (seed 2), FP32
     loops and products, lockstep Euler steps 10 -> 1 through tufrg_batch_flow;
@@ -449,61 +569,19 @@ def batch_bench(T, torch, K, W):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="time the FP32 steps only (for profiler runs)")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain 1 GiB device-to-device copy (scales HBM counters)")
-    ap.add_argument("--workload", default=WORKLOAD,
-                    help="synthetic workload (the headline line uses the default)")
-    ap.add_argument("--no-dp", action="store_true", help="skip the Dormand-Prince flows")
-    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-assisted flow")
-    ap.add_argument("--no-basis", action="store_true", help="skip the orbital -> band basis change")
-    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16x3"],
-                    help="arithmetic of the timed loops (bf16x3: six spin-orbitals, matrix cores)")
-    ap.add_argument("--cutoff", choices=["temperature", "omega", "shell"],
-                    help="regulator in place of the workload's own")
-    ap.add_argument("--temperature", type=float, default=0.02,
-                    help="fixed temperature of the momentum-shell regulator")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the q-sharded multi-GPU "
-              "path is a design, not implemented in this library", file=sys.stderr)
-        sys.exit(2)
-
+def two_orbital_line(T, torch, w, args, K, W, extras=True, cpu=True):
+    """Line of a two-orbital workload (Rashba, Hubbard): K timed Euler steps
+    10 -> 1 in FP32 (or the precision asked for), the loop-kernel roofline,
+    and optionally the FP64-plain form, Dormand-Prince flows, the surrogate,
+    the basis change and the CPU baseline."""
     import numpy as np
-    import torch
 
-    from paper_1710_08830_amd import tufrg as T
-    from synth import workload
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    if args.calibrate_copy:
-        n = 1 << 30
-        x = torch.ones(n // 8, dtype=torch.float64, device=dev)
-        y = torch.empty_like(x)
-        for _ in range(3):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}))
-        return
-    K, W = args.steps, args.warmup
-    if args.workload == "rashba_batch32":
-        print(json.dumps(batch_bench(T, torch, K, W)))
-        return
-    if args.workload == "t2g_s13_L48":
-        print(json.dumps(surrogate_bench(T, torch, workload(args.workload), K, args.prec)))
-        return
-    w = workload(args.workload)
+    no_extras = args.no_extras or not extras
     own_cutoff = args.cutoff is None or args.cutoff == w["cutoff"]
     if not own_cutoff:
         w = dict(w, cutoff=args.cutoff, temperature=args.temperature)
+    prec = args.prec or "fp32"
     lam0, lam_mid = 10.0, 1.0
 
     def make(prec):
@@ -530,7 +608,7 @@ def main():
             T.tufrg_timing(ctx, False)
         return dt, res, loop_ms, loop_n
 
-    ctx32, P32, C32 = make(args.prec)
+    ctx32, P32, C32 = make(prec)
     dt32, res32, loop_ms, loop_n = timed_steps(ctx32, P32, C32, timing=True)
     B, Nq, Nf = ctx32.B, ctx32.Nq, ctx32.Nf
     entries = 2.0 * Nq * B * B
@@ -541,7 +619,7 @@ def main():
     loop_avg_s = loop_ms / loop_n * 1e-3
     launches = loop_n / K
     ndx, ndy = _box(w["ff"])
-    if args.prec == "bf16x3":
+    if prec == "bf16x3":
         flops_step = 2.0 * Nq * Nf * credited_loop_flops_per_pair(w["n_o"], ndy)
         bound, peak = "mfma", PEAK_BF16_MFMA
     else:
@@ -549,12 +627,12 @@ def main():
         bound, peak = "alu", PEAK_FP32_VECTOR
     achieved = flops_step / launches / loop_avg_s
     # the committed counters were taken with the workload's own regulator
-    traffic = _traffic(args.workload, args.prec) if own_cutoff else None
+    traffic = _traffic(w["name"], prec) if own_cutoff else None
     out = {
         "metric": METRIC, "value": value, "unit": "loop entries/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": dt32 / K * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
-        "config": {"workload": args.workload, "n_orb": w["n_o"], "n_ff": len(w["ff"]), "B": B,
+        "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": w["name"], "n_orb": w["n_o"], "n_ff": len(w["ff"]), "B": B,
                    "Lq": w["Lq"], "n_ref": w["n_ref"], "Nq": Nq, "Nf": Nf, "cutoff": w["cutoff"],
                    **({"temperature": w["temperature"]} if w["cutoff"] == "shell" else {}),
                    "step": "Euler step: loops + projections + bundles + update",
@@ -566,7 +644,7 @@ def main():
         "roofline": {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic},
     }
-    if not args.no_extras:
+    if not no_extras:
         ctx64, P64, C64 = make("fp64")
         dt64, res64, l64_ms, l64_n = timed_steps(ctx64, P64, C64, timing=True)
         ref = P64.abs().max().item(), C64.abs().max().item()
@@ -575,7 +653,7 @@ def main():
                              "loop_kernel_ms": l64_ms / l64_n, "flow_steps_per_s": K / dt64}
         out["speedup_fp32_vs_fp64"] = dt64 / dt32
         out["rel_err_fp32_vs_fp64"] = err
-    if not args.no_extras and not args.no_dp:
+    if not no_extras and not args.no_dp:
         # production integrator: Dormand-Prince 5(4), rtol = atol = 1e-6, 10 -> 1e-4
         dp = {}
         for name, (ctx, P, C) in (("fp32", (ctx32, P32, C32)), ("fp64", (ctx64, P64, C64))):
@@ -597,19 +675,90 @@ def main():
         if dp["fp64"]["diverged"] and dp["fp32"]["diverged"]:
             dp["lambda_c_rel_err"] = abs(dp["fp32"]["lambda_c"] / dp["fp64"]["lambda_c"] - 1.0)
         out["dp54_flow"] = dp
-    if not args.no_extras and not args.no_dp and not args.no_surrogate:
+    if not no_extras and not args.no_dp and not args.no_surrogate:
         out["surrogate_flow"] = surrogate_leg(T, torch, ctx32, P32, C32, P64, C64, dp, w, K, dt32 / K)
-    if not args.no_extras and not args.no_basis:
-        band = T.Context.from_workload(w, precision=args.prec, basis="band", V0=0 * w["V0"])
+    if not no_extras and not args.no_basis:
+        band = T.Context.from_workload(w, precision=prec, basis="band", V0=0 * w["V0"])
         out["basis_change"] = basis_leg(T, torch, ctx64, P64, C64, w["ff"], band_ctx=band,
                                         V0=np.asarray(w["V0"]), steps=K)
         band.close()
-    if not args.no_extras:
+    if not no_extras:
         ctx64.close()
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, n_sample=4 if w["n_o"] == 2 else 1)
+    if cpu and not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, n_sample=2)
     ctx32.close()
-    print(json.dumps(out))
+    return out
+
+
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time the headline steps only (for profiler runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (scales HBM counters)")
+    ap.add_argument("--workload", default=WORKLOAD,
+                    help="synthetic workload (the headline line uses the default)")
+    ap.add_argument("--no-dp", action="store_true", help="skip the Dormand-Prince flows")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate-assisted flow")
+    ap.add_argument("--no-basis", action="store_true", help="skip the orbital -> band basis change")
+    ap.add_argument("--prec", default=None, choices=["fp32", "bf16x3", "fp64"],
+                    help="arithmetic of the timed loops (default: bf16x3 for six spin-orbitals, else fp32)")
+    ap.add_argument("--fp64-steps", type=int, default=1,
+                    help="steps of the FP64-plain comparison of a six-orbital workload")
+    ap.add_argument("--cutoff", choices=["temperature", "omega", "shell"],
+                    help="regulator in place of the workload's own")
+    ap.add_argument("--temperature", type=float, default=0.02,
+                    help="fixed temperature of the momentum-shell regulator")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the q-sharded multi-GPU "
+              "path is a design, not implemented in this library", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1710_08830_amd import tufrg as T
+    from synth import workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        n = 1 << 30
+        x = torch.ones(n // 8, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "copies": 3}))
+        return
+    K, W = args.steps, args.warmup
+    if args.workload == "rashba_batch32":
+        print(json.dumps(batch_bench(T, torch, K, W)))
+        return
+    w = workload(args.workload)
+    if w["n_o"] == 6:
+        if args.cutoff and args.cutoff != w["cutoff"]:
+            w = dict(w, cutoff=args.cutoff, temperature=args.temperature)
+        prec = args.prec or "bf16x3"
+        out = six_orbital_line(T, torch, w, prec, K, W, fp64_steps=0 if args.no_extras else args.fp64_steps,
+                               surrogate=not (args.no_extras or args.no_surrogate))
+        if not args.no_extras:
+            # the two-orbital Rashba workload (24 x 24 refined 24x, FP32) as an extra key
+            wr = workload("rashba_s9_L24")
+            ar = argparse.Namespace(**dict(vars(args), cutoff=None, prec="fp32"))
+            out["rashba_s9_L24"] = two_orbital_line(T, torch, wr, ar, min(K, 20), min(W, 3), extras=False,
+                                                    cpu=False)
+        if not args.no_cpu:
+            out["cpu_baseline"] = cpu_baseline(w, n_sample=1)
+        print(json.dumps(out))
+        return
+    print(json.dumps(two_orbital_line(T, torch, w, args, K, W)))
 
 
 if __name__ == "__main__":

@@ -23,3 +23,17 @@ def test_traffic_record_is_dropped_when_the_loop_source_changes(monkeypatch):
     import bench
     monkeypatch.setattr(bench, "_loop_source_hash", lambda prec: "0" * 64)
     assert bench._traffic("rashba_s9_L24", "fp32") is None
+
+
+def test_flop_counts_of_the_loop():
+    """Survey count of the six-orbital loop per (q, k, channel): separable ky
+    transform over 9 phases, halved by hermiticity, plus the block build
+    (8 n_o^2 n_b (n_b + n_o^2)); matrix-core flops of the real-basis kernel:
+    21 row tiles x 36 columns x 6 bands x 2, three BF16 products."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.credited_loop_flops_per_pair(6, 4) == 8 * 9 * 1296 // 2 + 8 * 36 * 6 * 42 == 119232
+    assert bench.mfma_flops_per_pair(4) == 3 * 2 * 336 * 36 * 6
+    assert bench.mfma_flops_per_pair(2) == 3 * 2 * 192 * 36 * 6
+    model, n = bench._cpu_info()
+    assert isinstance(model, str) and n >= 1

@@ -536,26 +536,27 @@ def batch_bench(T, torch, K, W):
     dev = torch.device("cuda:0")
     ws = batch_instances(32, seed=2, n_ref=12)
     out = {}
-    for n_streams in (4, 1):
+    for n_streams, G in ((4, 0), (1, 0), (4, 8)):
         b = T.Batch(ws, precision="fp32", n_streams=n_streams)
         Ps, Cs = [], []
         for d in b.dims:
             Ps.append(torch.zeros((d["Nq"], d["B"], d["B"]), dtype=torch.complex128, device=dev))
             Cs.append(torch.zeros_like(Ps[-1]))
         if W > 0:
-            T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=W, v_max=1e30)
+            T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=W, v_max=1e30, graph_steps=G)
         for x in Ps + Cs:
             x.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=K, v_max=1e30)
+        res = T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=K, v_max=1e30, graph_steps=G)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         entries = sum(2.0 * d["Nq"] * d["B"] ** 2 for d in b.dims)
-        out[n_streams] = dict(seconds=dt, value=entries * K / dt, ms_per_step=dt / K * 1e3,
-                              steps=min(r["n_steps"] for r in res))
+        out[(n_streams, G)] = dict(seconds=dt, value=entries * K / dt, ms_per_step=dt / K * 1e3,
+                                   steps=min(r["n_steps"] for r in res),
+                                   checksum=float(sum(x.abs().sum().item() for x in Ps)))
         b.close()
-    best = out[4]
+    best = max((out[(4, 0)], out[(4, 8)]), key=lambda d: d["value"])
     return {
         "metric": METRIC, "value": best["value"], "unit": "loop entries/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": best["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -564,7 +565,10 @@ def batch_bench(T, torch, K, W):
                    "Lq": sorted({w["Lq"] for w in ws}), "n_ff": sorted({len(w["ff"]) for w in ws}),
                    "n_ref": 12, "step": "lockstep Euler step of every instance", "parallelism": "single GPU"},
         "flow_steps_per_s": K / best["seconds"],
-        "one_stream": out[1], "speedup_4_streams_vs_1": out[1]["seconds"] / best["seconds"],
+        "four_streams": out[(4, 0)], "one_stream": out[(1, 0)], "four_streams_graph_steps_8": out[(4, 8)],
+        "speedup_4_streams_vs_1": out[(1, 0)]["seconds"] / out[(4, 0)]["seconds"],
+        "speedup_graph_vs_direct": out[(4, 0)]["seconds"] / out[(4, 8)]["seconds"],
+        "graph_checksum_equal": out[(4, 0)]["checksum"] == out[(4, 8)]["checksum"],
         "roofline": None,
     }
 
@@ -644,6 +648,20 @@ def two_orbital_line(T, torch, w, args, K, W, extras=True, cpu=True):
         "roofline": {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic},
     }
+    if not no_extras:
+        # the same steps with HIP graphs of 8 steps each (one host
+        # synchronisation per graph instead of one per step)
+        Pd, Cd = P32.clone(), C32.clone()
+        P32.zero_()
+        C32.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T.tufrg_flow(ctx32, P32, C32, lam0, lam_mid, n_steps=K, v_max=1e30, graph_steps=8)
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - t0
+        out["graph_steps_8"] = {"ms_per_step": dtg / K * 1e3, "speedup_vs_direct": dt32 / dtg,
+                                "bit_equal_to_direct": bool(torch.equal(Pd, P32) and torch.equal(Cd, C32))}
+        del Pd, Cd
     if not no_extras:
         ctx64, P64, C64 = make("fp64")
         dt64, res64, l64_ms, l64_n = timed_steps(ctx64, P64, C64, timing=True)

@@ -300,6 +300,16 @@ typedef struct {
   int32_t surrogate;
   double sample_frac, sur_tol, plain_above;
   uint64_t sample_seed;
+  /* Euler without surrogate and callback, both channels: graph_steps > 1
+   * captures up to that many steps (at most 64) at a time in one HIP graph,
+   * launched with one host synchronisation per graph instead of one per
+   * step; each step's max coupling goes to its own device slot.  The state
+   * at the start of a graph is kept: if a step inside it diverges (or reaches
+   * max_steps) the graph's steps are undone and replayed one by one, so the
+   * result equals that of direct launches bit for bit.  Needs one more copy
+   * of P and C on the device (allocated on first use).  0 or 1: direct
+   * launches. */
+  int32_t graph_steps;
 } tufrg_flow_opts;
 
 typedef struct {

@@ -107,6 +107,15 @@ struct tufrg_ctx {
   int *d_hmap = nullptr;                       // BF16X3 loops: half-plane point of each difference vector
   int mfma_chunk = 0;
   unsigned long long *h_sbits = nullptr;       // pinned
+  // Euler steps in HIP graphs: the executable graph, the capture stream (the
+  // context's stream, or a private one when that is the null stream), one
+  // max-coupling slot per step of a graph, and the state at a graph's start
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t gst = nullptr;
+  bool own_gst = false;
+  unsigned long long *d_gbits = nullptr, *h_gbits = nullptr;  // h_: pinned
+  unsigned int *d_gflag = nullptr, *h_gflag = nullptr;
+  double *d_bkP = nullptr, *d_bkC = nullptr;
   // set during tufrg_flow
   const tufrg_flow_opts *fopts = nullptr;
   tufrg_flow_result *fres = nullptr;
@@ -200,6 +209,14 @@ static hipError_t timer_mark(tufrg_ctx *c, int id) {
 }
 
 static void destroy_all(tufrg_ctx *c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  if (c->own_gst && c->gst) (void)hipStreamDestroy(c->gst);
+  c->gst = nullptr;
+  if (c->h_gbits) (void)hipHostFree(c->h_gbits);
+  if (c->h_gflag) (void)hipHostFree(c->h_gflag);
+  c->h_gbits = nullptr;
+  c->h_gflag = nullptr;
   for (auto &t : c->timers)
     for (hipEvent_t e : t.ev) (void)hipEventDestroy(e);
   for (void *p : c->allocs) (void)hipFree(p);
@@ -1224,6 +1241,123 @@ static double lambda_c_interp(double l0, double m0, double l1, double m1, double
   return std::exp(std::log(l0) + t * (std::log(l1) - std::log(l0)));
 }
 
+// ---------------------------------------------------------------------------
+// Euler steps in HIP graphs
+
+static constexpr int MAX_GRAPH_STEPS = 64;
+
+static double euler_lambda(const tufrg_flow_opts *o, int i) {
+  if (i >= o->n_steps) return o->lambda_end;
+  return o->lambda0 * std::pow(o->lambda_end / o->lambda0, (double)i / o->n_steps);
+}
+
+// workspaces of graph stepping (allocated on first use, outside any capture)
+static tufrg_status graph_prepare(tufrg_ctx *c) {
+  if (!c->gst) {
+    if (c->st) {
+      c->gst = c->st;
+    } else {
+      // the null stream cannot be captured: a private stream of default
+      // priority, ordered against the caller's work by the flow's own
+      // synchronisations
+      HIPCHK(c, hipStreamCreateWithFlags(&c->gst, hipStreamDefault));
+      c->own_gst = true;
+    }
+  }
+  if (!c->d_gbits) TRY(dalloc(c, &c->d_gbits, MAX_GRAPH_STEPS));
+  if (!c->d_gflag) TRY(dalloc(c, &c->d_gflag, MAX_GRAPH_STEPS));
+  if (!c->h_gbits)
+    HIPCHK(c, hipHostMalloc((void **)&c->h_gbits, MAX_GRAPH_STEPS * sizeof(unsigned long long), hipHostMallocDefault));
+  if (!c->h_gflag)
+    HIPCHK(c, hipHostMalloc((void **)&c->h_gflag, MAX_GRAPH_STEPS * sizeof(unsigned int), hipHostMallocDefault));
+  const size_t ns = 2 * (size_t)c->B * c->B * c->Nq;
+  if (!c->d_bkP) TRY(dalloc(c, &c->d_bkP, ns));
+  if (!c->d_bkC) TRY(dalloc(c, &c->d_bkC, ns));
+  return TUFRG_OK;
+}
+
+// enqueue Euler steps [i0, i0 + g) of one context on its stream, step j's max
+// coupling and non-finite flag into slot j (every call is a kernel launch, so
+// the sequence can be captured)
+static tufrg_status enqueue_euler_steps(tufrg_ctx *c, const tufrg_flow_opts *o, double *P, double *C, int i0, int g,
+                                        unsigned mask) {
+  const long long ncx = (long long)c->B * c->B * c->Nq;
+  for (int j = 0; j < g; ++j) {
+    const double l0 = euler_lambda(o, i0 + j), l1 = euler_lambda(o, i0 + j + 1);
+    TRY(rhs_internal(c, l0, P, C, c->d_dP, c->d_dC, 1.0, mask));
+    HIPCHK(c, launch_clear_reduce(c->d_gbits + j, c->d_gflag + j, c->st));
+    HIPCHK(c, launch_axpy_max(ncx, P, l1 - l0, c->d_dP, P, c->d_gbits + j, c->d_gflag + j, c->st));
+    HIPCHK(c, launch_axpy_max(ncx, C, l1 - l0, c->d_dC, C, c->d_gbits + j, c->d_gflag + j, c->st));
+  }
+  return TUFRG_OK;
+}
+
+// capture g Euler steps from i0 into the context's executable graph (updated
+// in place when the topology is unchanged), then launch it after saving the
+// state; the slots are copied to the host and the stream synchronised
+static tufrg_status run_euler_graph(tufrg_ctx *c, const tufrg_flow_opts *o, double *P, double *C, int i0, int g,
+                                    unsigned mask) {
+  const size_t bytes = 2 * sizeof(double) * (size_t)c->B * c->B * c->Nq;
+  hipStream_t saved = c->st;
+  c->st = c->gst;
+  hipError_t e = hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    c->st = saved;
+    (void)hipGetLastError();
+    return fail(c, TUFRG_E_HIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+  }
+  // the caller counts the steps of an accepted graph itself
+  tufrg_flow_result *fres = c->fres;
+  c->fres = nullptr;
+  const tufrg_status s = enqueue_euler_steps(c, o, P, C, i0, g, mask);
+  c->fres = fres;
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(c->st, &graph);
+  c->st = saved;
+  if (s != TUFRG_OK || e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return s != TUFRG_OK ? s : fail(c, TUFRG_E_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  bool updated = false;
+  if (c->gexec) {
+    hipGraphNode_t err_node = nullptr;
+    hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+    updated = hipGraphExecUpdate(c->gexec, graph, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+    if (!updated) {
+      (void)hipGetLastError();
+      (void)hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+  }
+  if (!updated) {
+    e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      c->gexec = nullptr;
+      (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      return fail(c, TUFRG_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+  }
+  (void)hipGraphDestroy(graph);
+  HIPCHK(c, hipMemcpyAsync(c->d_bkP, P, bytes, hipMemcpyDeviceToDevice, c->gst));
+  HIPCHK(c, hipMemcpyAsync(c->d_bkC, C, bytes, hipMemcpyDeviceToDevice, c->gst));
+  HIPCHK(c, hipGraphLaunch(c->gexec, c->gst));
+  HIPCHK(c, hipMemcpyAsync(c->h_gbits, c->d_gbits, g * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->gst));
+  HIPCHK(c, hipMemcpyAsync(c->h_gflag, c->d_gflag, g * sizeof(unsigned int), hipMemcpyDeviceToHost, c->gst));
+  HIPCHK(c, hipStreamSynchronize(c->gst));
+  return TUFRG_OK;
+}
+
+// undo the steps of the last graph: the state saved at its start
+static tufrg_status restore_graph_state(tufrg_ctx *c, double *P, double *C) {
+  const size_t bytes = 2 * sizeof(double) * (size_t)c->B * c->B * c->Nq;
+  HIPCHK(c, hipMemcpyAsync(P, c->d_bkP, bytes, hipMemcpyDeviceToDevice, c->gst));
+  HIPCHK(c, hipMemcpyAsync(C, c->d_bkC, bytes, hipMemcpyDeviceToDevice, c->gst));
+  HIPCHK(c, hipStreamSynchronize(c->gst));
+  return TUFRG_OK;
+}
+
 static const double DP_C[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
 static const double DP_A[7][6] = {
     {0, 0, 0, 0, 0, 0},
@@ -1280,9 +1414,50 @@ extern "C" tufrg_status tufrg_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg
       TRY(dalloc(c, &c->d_dC, ns));
     }
     const int n = o->n_steps;
+    // graph stepping: plain loops of both channels, no per-step callback or
+    // timers; the first step runs directly (it allocates lazy workspaces)
+    const int G = (o->graph_steps > 1 && !o->surrogate && mask == 3u && !o->on_step && !c->timing)
+                      ? std::min(o->graph_steps, MAX_GRAPH_STEPS)
+                      : 0;
+    if (G) TRY(graph_prepare(c));
+    int replay_to = -1;  // after an undone graph: direct steps up to this one
     for (int i = 0; i < n; ++i) {
-      const double l0 = o->lambda0 * std::pow(o->lambda_end / o->lambda0, (double)i / n);
-      const double l1 = (i + 1 == n) ? o->lambda_end : o->lambda0 * std::pow(o->lambda_end / o->lambda0, (double)(i + 1) / n);
+      if (G && i > 0 && i > replay_to) {
+        int g = std::min(G, n - i);
+        if (o->max_steps > 0) g = std::min(g, o->max_steps - res->n_steps);
+        if (g > 1) {
+          TRY(run_euler_graph(c, o, P, C, i, g, mask));
+          int stop = -1;
+          for (int j = 0; j < g && stop < 0; ++j) {
+            double mx;
+            std::memcpy(&mx, &c->h_gbits[j], sizeof(mx));
+            if (c->h_gflag[j] || mx > o->v_max) stop = j;
+          }
+          if (stop >= 0) {
+            // a step inside the graph diverged (or went non-finite): undo the
+            // graph and take its steps one by one up to that step
+            TRY(restore_graph_state(c, P, C));
+            replay_to = i + stop;
+          } else {
+            for (int j = 0; j < g; ++j) {
+              double mx;
+              std::memcpy(&mx, &c->h_gbits[j], sizeof(mx));
+              res->n_rhs++;
+              res->n_plain++;
+              res->n_steps++;
+              res->lambda_stop = euler_lambda(o, i + j + 1);
+              res->max_coupling = mx;
+              c->cur_max = mx;
+              lam_prev = res->lambda_stop;
+              m_prev = mx;
+            }
+            i += g - 1;
+            if (o->max_steps > 0 && res->n_steps >= o->max_steps) break;
+            continue;
+          }
+        }
+      }
+      const double l0 = euler_lambda(o, i), l1 = euler_lambda(o, i + 1);
       TRY(rhs_internal(c, l0, P, C, c->d_dP, c->d_dC, 1.0, mask));
       res->n_rhs++;
       HIPCHK(c, launch_clear_reduce(c->d_bits, c->d_flag, c->st));
@@ -1389,6 +1564,9 @@ struct tufrg_batch {
   std::vector<tufrg_ctx *> ctx;
   std::vector<hipStream_t> streams;  // owned, default priority
   std::string err;
+  // lockstep steps in HIP graphs: the executable graph and the fork/join events
+  hipGraphExec_t gexec = nullptr;
+  std::vector<hipEvent_t> events;
 };
 
 static thread_local std::string g_batch_err;
@@ -1402,6 +1580,10 @@ static tufrg_status bfail(tufrg_batch *b, tufrg_status s, const std::string &m) 
 }
 
 static void batch_free(tufrg_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+  b->events.clear();
   for (tufrg_ctx *c : b->ctx) tufrg_destroy(c);
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   b->ctx.clear();
@@ -1489,18 +1671,15 @@ extern "C" tufrg_status tufrg_batch_flow(tufrg_batch *b, const tufrg_flow_opts *
     if (bad) return bfail(b, TUFRG_E_NONFINITE, "non-finite initial state of instance " + std::to_string(i));
   }
   const int ns = o->n_steps;
-  for (int s = 0; s < ns; ++s) {
-    const double l0 = o->lambda0 * std::pow(o->lambda_end / o->lambda0, (double)s / ns);
-    const double l1 = (s + 1 == ns) ? o->lambda_end : o->lambda0 * std::pow(o->lambda_end / o->lambda0, (double)(s + 1) / ns);
-    // enqueue every active instance, then one wait for all
+  // one lockstep step of every active instance: enqueue, one wait for all,
+  // then the stop tests
+  auto direct_step = [&](int s) -> tufrg_status {
+    const double l0 = euler_lambda(o, s), l1 = euler_lambda(o, s + 1);
     for (int i = 0; i < n; ++i) {
       if (!active[i]) continue;
       tufrg_ctx *c = b->ctx[i];
       double *Pi = (double *)P[i], *Ci = (double *)C[i];
-      const size_t ns_d = 2 * (size_t)c->B * c->B * c->Nq;
       const long long ncx = (long long)c->B * c->B * c->Nq;
-      if (!c->d_dP && (dalloc(c, &c->d_dP, ns_d) != TUFRG_OK || dalloc(c, &c->d_dC, ns_d) != TUFRG_OK))
-        return bfail(b, TUFRG_E_NOMEM, "instance " + std::to_string(i) + ": " + c->err);
       if (rhs_internal(c, l0, Pi, Ci, c->d_dP, c->d_dC, 1.0, mask) != TUFRG_OK) return inst_fail(i);
       if (launch_clear_reduce(c->d_bits, c->d_flag, c->st) != hipSuccess ||
           launch_axpy_max(ncx, Pi, l1 - l0, c->d_dP, Pi, c->d_bits, c->d_flag, c->st) != hipSuccess ||
@@ -1538,6 +1717,151 @@ extern "C" tufrg_status tufrg_batch_flow(tufrg_batch *b, const tufrg_flow_opts *
       lam_prev[i] = l1;
       m_prev[i] = mx;
     }
+    return TUFRG_OK;
+  };
+  for (int i = 0; i < n; ++i) {
+    tufrg_ctx *c = b->ctx[i];
+    const size_t ns_d = 2 * (size_t)c->B * c->B * c->Nq;
+    if (!c->d_dP && (dalloc(c, &c->d_dP, ns_d) != TUFRG_OK || dalloc(c, &c->d_dC, ns_d) != TUFRG_OK))
+      return bfail(b, TUFRG_E_NOMEM, "instance " + std::to_string(i) + ": " + c->err);
+  }
+  // lockstep steps in HIP graphs: every active instance's steps captured
+  // across the batch's streams (fork from the first stream, join back)
+  const int G = (o->graph_steps > 1 && mask == 3u) ? std::min(o->graph_steps, MAX_GRAPH_STEPS) : 0;
+  if (G) {
+    for (int i = 0; i < n; ++i)
+      if (graph_prepare(b->ctx[i]) != TUFRG_OK) return bfail(b, TUFRG_E_NOMEM, "instance " + std::to_string(i) + ": " + b->ctx[i]->err);
+    while (b->events.size() < 2 * b->streams.size()) {
+      hipEvent_t e;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, TUFRG_E_HIP, "hipEventCreate failed");
+      }
+      b->events.push_back(e);
+    }
+  }
+  auto hipok = [&](hipError_t e, const char *what) -> bool {
+    if (e == hipSuccess) return true;
+    (void)hipGetLastError();
+    bfail(b, TUFRG_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+    return false;
+  };
+  int replay_to = -1;
+  for (int s = 0; s < ns;) {
+    if (G && s > 0 && s > replay_to) {
+      int g = std::min(G, ns - s);
+      if (o->max_steps > 0)
+        for (int i = 0; i < n; ++i)
+          if (active[i]) g = std::min(g, o->max_steps - res[i].n_steps);
+      if (g > 1) {
+        hipStream_t s0 = b->streams[0];
+        if (!hipok(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture"))
+          return TUFRG_E_HIP;
+        bool ok = hipok(hipEventRecord(b->events[0], s0), "hipEventRecord");
+        for (size_t k = 1; ok && k < b->streams.size(); ++k)
+          ok = hipok(hipStreamWaitEvent(b->streams[k], b->events[0], 0), "hipStreamWaitEvent");
+        int bad_inst = -1;
+        for (int i = 0; ok && i < n; ++i)
+          if (active[i] && enqueue_euler_steps(b->ctx[i], o, (double *)P[i], (double *)C[i], s, g, mask) != TUFRG_OK) {
+            bad_inst = i;
+            ok = false;
+          }
+        for (size_t k = 1; ok && k < b->streams.size(); ++k)
+          ok = hipok(hipEventRecord(b->events[k], b->streams[k]), "hipEventRecord") &&
+               hipok(hipStreamWaitEvent(s0, b->events[k], 0), "hipStreamWaitEvent");
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(s0, &graph);
+        if (!ok || ee != hipSuccess) {
+          if (graph) (void)hipGraphDestroy(graph);
+          (void)hipGetLastError();
+          if (bad_inst >= 0) return inst_fail(bad_inst);
+          return b->err.empty() ? bfail(b, TUFRG_E_HIP, "graph capture failed") : TUFRG_E_HIP;
+        }
+        bool updated = false;
+        if (b->gexec) {
+          hipGraphNode_t en = nullptr;
+          hipGraphExecUpdateResult ur = hipGraphExecUpdateError;
+          updated = hipGraphExecUpdate(b->gexec, graph, &en, &ur) == hipSuccess && ur == hipGraphExecUpdateSuccess;
+          if (!updated) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(b->gexec);
+            b->gexec = nullptr;
+          }
+        }
+        if (!updated && !hipok(hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0), "hipGraphInstantiate")) {
+          b->gexec = nullptr;
+          (void)hipGraphDestroy(graph);
+          return TUFRG_E_HIP;
+        }
+        (void)hipGraphDestroy(graph);
+        // save the states, run the graph, read every instance's step slots
+        for (int i = 0; i < n; ++i) {
+          if (!active[i]) continue;
+          tufrg_ctx *c = b->ctx[i];
+          const size_t bytes = 2 * sizeof(double) * (size_t)c->B * c->B * c->Nq;
+          if (!hipok(hipMemcpyAsync(c->d_bkP, P[i], bytes, hipMemcpyDeviceToDevice, s0), "hipMemcpyAsync") ||
+              !hipok(hipMemcpyAsync(c->d_bkC, C[i], bytes, hipMemcpyDeviceToDevice, s0), "hipMemcpyAsync"))
+            return TUFRG_E_HIP;
+        }
+        if (!hipok(hipGraphLaunch(b->gexec, s0), "hipGraphLaunch")) return TUFRG_E_HIP;
+        for (int i = 0; i < n; ++i) {
+          if (!active[i]) continue;
+          tufrg_ctx *c = b->ctx[i];
+          if (!hipok(hipMemcpyAsync(c->h_gbits, c->d_gbits, g * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                    s0), "hipMemcpyAsync") ||
+              !hipok(hipMemcpyAsync(c->h_gflag, c->d_gflag, g * sizeof(unsigned int), hipMemcpyDeviceToHost, s0),
+                     "hipMemcpyAsync"))
+            return TUFRG_E_HIP;
+        }
+        if (!hipok(hipStreamSynchronize(s0), "hipStreamSynchronize")) return TUFRG_E_HIP;
+        int stop = -1;
+        for (int i = 0; i < n; ++i) {
+          if (!active[i]) continue;
+          for (int j = 0; j < g; ++j) {
+            double mx;
+            std::memcpy(&mx, &b->ctx[i]->h_gbits[j], sizeof(mx));
+            if (b->ctx[i]->h_gflag[j] || mx > o->v_max) {
+              stop = stop < 0 ? j : std::min(stop, j);
+              break;
+            }
+          }
+        }
+        if (stop >= 0) {
+          // undo the graph's steps of every instance and take them one by one
+          for (int i = 0; i < n; ++i) {
+            if (!active[i]) continue;
+            tufrg_ctx *c = b->ctx[i];
+            const size_t bytes = 2 * sizeof(double) * (size_t)c->B * c->B * c->Nq;
+            if (!hipok(hipMemcpyAsync(P[i], c->d_bkP, bytes, hipMemcpyDeviceToDevice, s0), "hipMemcpyAsync") ||
+                !hipok(hipMemcpyAsync(C[i], c->d_bkC, bytes, hipMemcpyDeviceToDevice, s0), "hipMemcpyAsync"))
+              return TUFRG_E_HIP;
+          }
+          if (!hipok(hipStreamSynchronize(s0), "hipStreamSynchronize")) return TUFRG_E_HIP;
+          replay_to = s + stop;
+          continue;
+        }
+        for (int i = 0; i < n; ++i) {
+          if (!active[i]) continue;
+          for (int j = 0; j < g; ++j) {
+            double mx;
+            std::memcpy(&mx, &b->ctx[i]->h_gbits[j], sizeof(mx));
+            res[i].n_rhs++;
+            res[i].n_plain++;
+            res[i].n_steps++;
+            res[i].lambda_stop = euler_lambda(o, s + j + 1);
+            res[i].max_coupling = mx;
+            lam_prev[i] = res[i].lambda_stop;
+            m_prev[i] = mx;
+          }
+          if (o->max_steps > 0 && res[i].n_steps >= o->max_steps) active[i] = 0;
+        }
+        s += g;
+        if (std::none_of(active.begin(), active.end(), [](char a) { return a != 0; })) break;
+        continue;
+      }
+    }
+    TRY(direct_step(s));
+    ++s;
     if (std::none_of(active.begin(), active.end(), [](char a) { return a != 0; })) break;
   }
   return TUFRG_OK;

@@ -73,7 +73,7 @@ class FlowOpts(ctypes.Structure):
                 ("on_step", STEP_CB), ("user", ctypes.c_void_p),
                 ("surrogate", ctypes.c_int32), ("sample_frac", ctypes.c_double),
                 ("sur_tol", ctypes.c_double), ("plain_above", ctypes.c_double),
-                ("sample_seed", ctypes.c_uint64)]
+                ("sample_seed", ctypes.c_uint64), ("graph_steps", ctypes.c_int32)]
 
 
 class FlowResult(ctypes.Structure):
@@ -337,13 +337,13 @@ def tufrg_rhs(ctx, lam, P, C, dP, dC):
 
 def tufrg_flow(ctx, P, C, lambda0, lambda_end, n_steps=0, rtol=1e-6, atol=1e-6, h0=0.05,
                v_max=50.0, channel_mask=3, max_steps=0, on_step=None, surrogate=False,
-               sample_frac=0.05, sur_tol=1e-3, plain_above=20.0, sample_seed=3):
+               sample_frac=0.05, sur_tol=1e-3, plain_above=20.0, sample_seed=3, graph_steps=0):
     """Integrates P, C in place; returns the result as a dict."""
     cb = STEP_CB(on_step) if on_step is not None else STEP_CB()
     o = FlowOpts(float(lambda0), float(lambda_end), int(n_steps), float(rtol), float(atol),
                  float(h0), float(v_max), int(channel_mask), int(max_steps), cb, None,
                  int(bool(surrogate)), float(sample_frac), float(sur_tol), float(plain_above),
-                 int(sample_seed))
+                 int(sample_seed), int(graph_steps))
     r = FlowResult()
     _check(_lib.tufrg_flow(ctx.handle, ctypes.byref(o), _state(ctx, P, "P"), _state(ctx, C, "C"),
                            ctypes.byref(r)),
@@ -542,8 +542,11 @@ class Batch:
             pass
 
 
-def tufrg_batch_flow(batch, Ps, Cs, lambda0, lambda_end, n_steps, v_max=50.0, channel_mask=3, max_steps=0):
-    """Lockstep Euler flow of every instance (P, C in place); list of result dicts."""
+def tufrg_batch_flow(batch, Ps, Cs, lambda0, lambda_end, n_steps, v_max=50.0, channel_mask=3, max_steps=0,
+                     graph_steps=0):
+    """Lockstep Euler flow of every instance (P, C in place); list of result
+    dicts.  graph_steps > 1: that many lockstep steps of all instances per HIP
+    graph."""
     n = batch.n
     if len(Ps) != n or len(Cs) != n:
         raise ValueError(f"one P and one C per instance ({n})")
@@ -551,7 +554,7 @@ def tufrg_batch_flow(batch, Ps, Cs, lambda0, lambda_end, n_steps, v_max=50.0, ch
     pp = (_vp * n)(*[_arr(x, "c128", m, f"P[{i}]") for i, (x, m) in enumerate(zip(Ps, sizes))])
     cp = (_vp * n)(*[_arr(x, "c128", m, f"C[{i}]") for i, (x, m) in enumerate(zip(Cs, sizes))])
     o = FlowOpts(float(lambda0), float(lambda_end), int(n_steps), 0.0, 0.0, 0.0, float(v_max),
-                 int(channel_mask), int(max_steps), STEP_CB(), None, 0, 0.0, 0.0, 0.0, 0)
+                 int(channel_mask), int(max_steps), STEP_CB(), None, 0, 0.0, 0.0, 0.0, 0, int(graph_steps))
     res = (FlowResult * n)()
     batch._check(_lib.tufrg_batch_flow(batch.handle, ctypes.byref(o), pp, cp, res))
     return [r.as_dict() for r in res]

@@ -81,15 +81,31 @@ def _box(ff):
     return (3, 2) if m <= 1 else (5, 4)
 
 
-# sources of the loop kernel per precision, with the host code that sets its launch shape
-LOOP_SOURCES = {"bf16x3": ("k_loop_rb.hip", "common.h", "tufrg_host.hip")}
+# sources of the loop kernel per precision, and the host function that sets
+# its launch shape (chunking) in tufrg_host.hip
+LOOP_SOURCES = {"bf16x3": (("k_loop_rb.hip", "common.h"), "loops_range_mfma")}
+LOOP_SOURCES_DEFAULT = (("k_loop.hip", "k_loop_gen.hip", "common.h"), "loops_range")
+
+
+def _host_function_text(name):
+    """Text of one top-level function of tufrg_host.hip (signature to the
+    closing brace in column 0)."""
+    with open(os.path.join(ROOT, "paper_1710_08830_amd", "csrc", "tufrg_host.hip")) as fh:
+        src = fh.read()
+    i = src.find("static tufrg_status " + name + "(")
+    if i < 0:
+        raise RuntimeError(f"no function {name} in tufrg_host.hip")
+    j = src.find("\n}\n", i)
+    return src[i:j + 3]
 
 
 def _loop_source_hash(prec):
+    files, fn = LOOP_SOURCES.get(prec, LOOP_SOURCES_DEFAULT)
     h = hashlib.sha256()
-    for f in LOOP_SOURCES.get(prec, ("k_loop.hip", "k_loop_gen.hip", "common.h", "tufrg_host.hip")):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1710_08830_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(_host_function_text(fn).encode())
     return h.hexdigest()
 
 
@@ -710,6 +726,100 @@ def two_orbital_line(T, torch, w, args, K, W, extras=True, cpu=True):
 
 
 
+def _counter_per_dispatch(csv_path, name_part, counter):
+    """Per-dispatch values of one counter for the kernels whose name contains
+    name_part, from a rocprofv3 counter_collection.csv."""
+    import csv
+    vals = {}
+    names = set()
+    with open(csv_path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter or name_part not in r["Kernel_Name"]:
+                continue
+            d = r["Dispatch_Id"]
+            vals[d] = vals.get(d, 0.0) + float(r["Counter_Value"])
+            names.add(r["Kernel_Name"])
+    if not vals:
+        raise RuntimeError(f"no {counter} rows for kernels matching {name_part!r} in {csv_path}")
+    return list(vals.values()), sorted(names)
+
+
+def summarize_traffic(args):
+    """profiles/loop_kernel_traffic_<workload>_<prec>.json from four
+    rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of the bench, the same of
+    --calibrate-copy): KiB per dispatch of the loop kernel, each scaled by
+    what the counter reads per byte of a plain 1 GiB device copy."""
+    f_dir, w_dir, cf_dir, cw_dir = args.summarize_traffic
+    # the main loop kernel of the precision (two orbitals: loop_no2, six: loop_gen)
+    kname = "loop_rb_kernel" if args.prec == "bf16x3" else (
+        "loop_gen_kernel" if args.workload.startswith("t2g") else "loop_no2_kernel")
+    pick = lambda d, nm: os.path.join(d, nm + "_counter_collection.csv")
+    fetch, names = _counter_per_dispatch(pick(f_dir, "fetch"), kname, "FETCH_SIZE")
+    write, _ = _counter_per_dispatch(pick(w_dir, "write"), kname, "WRITE_SIZE")
+    # the 1 GiB copies are the largest dispatches of the calibration run
+    cf, _ = _counter_per_dispatch(pick(cf_dir, "fetch"), "", "FETCH_SIZE")
+    cw, _ = _counter_per_dispatch(pick(cw_dir, "write"), "", "WRITE_SIZE")
+    cf = sorted(cf)[-3:]
+    cw = sorted(cw)[-3:]
+    n = 1 << 30
+    f_kib, w_kib = sum(fetch) / len(fetch), sum(write) / len(write)
+    cf_kib, cw_kib = sum(cf) / len(cf), sum(cw) / len(cw)
+    fb, wb = n / cf_kib, n / cw_kib
+    run = f"python3 -u bench.py --workload {args.workload} --prec {args.prec} --steps 1 --warmup 0 --no-cpu --no-extras"
+    out = {
+        "kernel": names[0] if len(names) == 1 else names,
+        "workload": args.workload,
+        "precision": args.prec,
+        "source_sha256": _loop_source_hash(args.prec),
+        "fetch_kib_per_dispatch": f_kib,
+        "write_kib_per_dispatch": w_kib,
+        "dispatches": len(fetch),
+        "copy_calibration": {"bytes_copied": n, "fetch_kib": cf_kib, "write_kib": cw_kib,
+                             "fetch_bytes_per_kib": fb, "write_bytes_per_kib": wb},
+        "fetch_bytes_per_launch": f_kib * fb,
+        "write_bytes_per_launch": w_kib * wb,
+        "hbm_bytes_per_launch": f_kib * fb + w_kib * wb,
+        "commands": [
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {f_dir} -o fetch -- {run}",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {w_dir} -o write -- {run}",
+            f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d {cf_dir} -o fetch -- python3 -u bench.py --calibrate-copy",
+            f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d {cw_dir} -o write -- python3 -u bench.py --calibrate-copy",
+            "python3 bench.py --summarize-traffic " + " ".join(args.summarize_traffic)
+            + f" --workload {args.workload} --prec {args.prec}",
+        ],
+        "note": "FETCH_SIZE and WRITE_SIZE count L2-to-fabric traffic; each is scaled by what the same counter "
+                "reads for a plain 1 GiB device copy.  Misses served by the MALL are included, so this bounds "
+                "HBM bytes from above.",
+    }
+    path = os.path.join(ROOT, "profiles", f"loop_kernel_traffic_{args.workload}_{args.prec}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    print(path)
+
+
+def summarize_trace(args):
+    """A markdown table of a rocprofv3 --kernel-trace --stats run (the
+    kernel_stats.csv it writes), the command that made it on top."""
+    import csv
+    stats_csv, cmd, out_path = args.summarize_trace
+    rows = list(csv.DictReader(open(stats_csv, newline="")))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# Kernel trace: {args.workload} ({args.prec})", "", "Command:", "", "```", cmd, "```", "",
+             "| kernel | calls | total ms | average us | min us | max us | share |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:20]:
+        nm = r["Name"].replace("|", "\\|")
+        if len(nm) > 110:
+            nm = nm[:107] + "..."
+        lines.append(f"| `{nm}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['MinNs']) / 1e3:.1f} | "
+                     f"{float(r['MaxNs']) / 1e3:.1f} | {100 * float(r['TotalDurationNs']) / tot:.1f} % |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(out_path)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -733,7 +843,19 @@ def main():
                     help="regulator in place of the workload's own")
     ap.add_argument("--temperature", type=float, default=0.02,
                     help="fixed temperature of the momentum-shell regulator")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write the loop kernel's HBM traffic summary under profiles/ from rocprofv3 counter runs "
+                         "(CPU only)")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("KERNEL_STATS_CSV", "COMMAND", "OUT_MD"),
+                    help="write a markdown summary of a rocprofv3 --stats run (CPU only)")
     args = ap.parse_args()
+    if args.summarize_traffic or args.summarize_trace:
+        args.prec = args.prec or ("bf16x3" if args.workload.startswith("t2g") else "fp32")
+        if args.summarize_traffic:
+            summarize_traffic(args)
+        if args.summarize_trace:
+            summarize_trace(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the q-sharded multi-GPU "
               "path is a design, not implemented in this library", file=sys.stderr)

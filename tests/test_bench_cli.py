@@ -37,3 +37,63 @@ def test_flop_counts_of_the_loop():
     assert bench.mfma_flops_per_pair(2) == 3 * 2 * 192 * 36 * 6
     model, n = bench._cpu_info()
     assert isinstance(model, str) and n >= 1
+
+
+def _counter_csv(path, rows):
+    head = ('"Correlation_Id","Dispatch_Id","Agent_Id","Queue_Id","Process_Id","Thread_Id","Grid_Size","Kernel_Id",'
+            '"Kernel_Name","Workgroup_Size","LDS_Block_Size","Scratch_Size","VGPR_Count","Accum_VGPR_Count",'
+            '"SGPR_Count","Counter_Name","Counter_Value","Start_Timestamp","End_Timestamp"')
+    with open(path, "w") as fh:
+        fh.write(head + "\n")
+        for d, name, counter, v in rows:
+            fh.write(f'{d},{d},"Agent 1",1,1,1,512,8,"{name}",512,0,0,8,0,32,"{counter}",{v},0,1\n')
+
+
+def test_traffic_summary_from_counter_csvs(tmp_path, monkeypatch):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE of the loop kernel (other kernels
+    ignored), scaled per byte by the largest three copy dispatches."""
+    sys.path.insert(0, ROOT)
+    import argparse
+
+    import bench
+    (tmp_path / "profiles").mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "_loop_source_hash", lambda prec: "ab" * 32)
+    dirs = [tmp_path / n for n in ("f", "w", "cf", "cw")]
+    for d in dirs:
+        d.mkdir()
+    k = "void tufrg::loop_rb_kernel<4, 0>(float const*)"
+    _counter_csv(dirs[0] / "fetch_counter_collection.csv",
+                 [(1, k, "FETCH_SIZE", 100.0), (2, "other", "FETCH_SIZE", 5e9), (3, k, "FETCH_SIZE", 300.0)])
+    _counter_csv(dirs[1] / "write_counter_collection.csv", [(1, k, "WRITE_SIZE", 40.0), (3, k, "WRITE_SIZE", 60.0)])
+    copy = "__amd_rocclr_copyBuffer"
+    _counter_csv(dirs[2] / "fetch_counter_collection.csv",
+                 [(1, copy, "FETCH_SIZE", 1.0), (2, copy, "FETCH_SIZE", 2 ** 19), (3, copy, "FETCH_SIZE", 2 ** 19),
+                  (4, copy, "FETCH_SIZE", 2 ** 19)])
+    _counter_csv(dirs[3] / "write_counter_collection.csv",
+                 [(2, copy, "WRITE_SIZE", 2 ** 20), (3, copy, "WRITE_SIZE", 2 ** 20), (4, copy, "WRITE_SIZE", 2 ** 20)])
+    args = argparse.Namespace(summarize_traffic=[str(d) for d in dirs], workload="t2g_s13_L48", prec="bf16x3")
+    bench.summarize_traffic(args)
+    import json
+    t = json.load(open(tmp_path / "profiles" / "loop_kernel_traffic_t2g_s13_L48_bf16x3.json"))
+    assert t["dispatches"] == 2 and t["fetch_kib_per_dispatch"] == 200.0 and t["write_kib_per_dispatch"] == 50.0
+    assert t["copy_calibration"]["fetch_bytes_per_kib"] == 2048.0 and t["copy_calibration"]["write_bytes_per_kib"] == 1024.0
+    assert t["hbm_bytes_per_launch"] == 200.0 * 2048 + 50.0 * 1024
+    assert bench._traffic("t2g_s13_L48", "bf16x3") == t["hbm_bytes_per_launch"]
+
+
+def test_trace_summary_from_kernel_stats(tmp_path):
+    sys.path.insert(0, ROOT)
+    import argparse
+
+    import bench
+    p = tmp_path / "kt_kernel_stats.csv"
+    p.write_text('"Name","Calls","TotalDurationNs","AverageNs","Percentage","MinNs","MaxNs","StdDev"\n'
+                 '"small",10,1000,100,10.0,90,110,1\n"big",2,9000,4500,90.0,4000,5000,10\n')
+    out = tmp_path / "s.md"
+    bench.summarize_trace(argparse.Namespace(summarize_trace=[str(p), "rocprofv3 ... -- python3 bench.py", str(out)],
+                                             workload="w", prec="bf16x3"))
+    text = out.read_text().splitlines()
+    rows = [r for r in text if r.startswith("| `")]
+    assert rows[0].startswith("| `big` | 2 | 0.009 | 4.5") and "90.0 %" in rows[0]
+    assert "rocprofv3 ... -- python3 bench.py" in text

@@ -120,8 +120,10 @@ typedef enum { TUFRG_BASIS_ORBITAL = 0, TUFRG_BASIS_BAND = 1 } tufrg_basis;
  * chunks in FP64.  TUFRG_BF16X3 (six spin-orbitals only) runs the loop's k
  * contraction on the matrix cores, in the real basis of Hermitian matrices,
  * with BF16 split operands (v = hi + lo, three products per pair), FP32
- * accumulation along each kx row and an FP64 sum over rows; everything else
- * as TUFRG_FP32. */
+ * accumulation along each kx row and an FP64 sum over rows; bundle products
+ * with B > 64 also run on the matrix cores, each complex product as four real
+ * ones of split operands with FP32 accumulation (the intermediate L V split
+ * again); everything else as TUFRG_FP32. */
 typedef enum { TUFRG_FP64 = 0, TUFRG_FP32 = 1, TUFRG_BF16X3 = 2 } tufrg_precision;
 
 typedef enum { TUFRG_PP = 0, TUFRG_PH = 1 } tufrg_channel;

@@ -85,6 +85,13 @@ hipError_t launch_assemble(const ProjArgs &a, const double *P, const double *C, 
 // bundles larger than 64 need a workspace tmp of n_q * B * B complex
 hipError_t launch_bundle(int prec, int n_o, int n_ff, int B, int nD, int n_q, const int *didx, const double *V,
                          const double *Lc, double factor, double *out, double *tmp, hipStream_t st);
+// the same on the matrix cores with BF16 split operands (k_bundle_mfma.hip), in
+// chunks of q that fit the workspace ws (at least bundle_split_bytes_per_q(B))
+size_t bundle_split_pad(int B);
+size_t bundle_split_bytes_per_q(int B);
+hipError_t launch_bundle_bf16x3(int n_o, int n_ff, int B, int nD, int n_q, const int *didx, const double *V,
+                                const double *Lc, double factor, double *out, void *ws, size_t ws_bytes,
+                                hipStream_t st);
 
 // orbital <-> band basis (k_basis.hip): compact basis matrix [Nq][nD][n_o^4] of one
 // channel (0: pp, U matrix; 1: ph, X matrix) from U[Nf][n_o][n_o] (orbital rows, band

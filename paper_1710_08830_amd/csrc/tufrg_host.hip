@@ -77,7 +77,8 @@ struct tufrg_ctx {
   unsigned int *h_flag = nullptr;        // pinned
   // flow workspace (lazy)
   double *d_dP = nullptr, *d_dC = nullptr;
-  double *d_btmp = nullptr;  // bundle workspace for B > 64
+  double *d_btmp = nullptr;  // bundle workspace for B > 64 (BF16X3: split planes)
+  size_t btmp_bytes = 0;
   double *d_basis_tmp = nullptr;  // basis sandwich workspace, [Nq][B][B] complex (lazy)
   double *d_basis_c = nullptr;    // compact basis matrix, [Nq][nD][n_o^4] complex (lazy)
   double *d_basis_rows = nullptr; // its kx-row sums for a chunk of coarse q (lazy)
@@ -445,7 +446,12 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CTRY(dalloc(c, &c->d_v0c, 2 * BB));
   CTRY(dalloc(c, &c->d_VP, 2 * BB * c->Nq));
   CTRY(dalloc(c, &c->d_VC, 2 * BB * c->Nq));
-  if (c->B > 64) CTRY(dalloc(c, &c->d_btmp, 2 * BB * c->Nq));
+  if (c->B > 64) {
+    size_t nd = 2 * BB * c->Nq;
+    if (c->prec == TUFRG_BF16X3) nd = std::max(nd, (bundle_split_bytes_per_q(c->B) + 7) / 8);
+    CTRY(dalloc(c, &c->d_btmp, nd));
+    c->btmp_bytes = nd * sizeof(double);
+  }
   CTRY(dalloc(c, &c->d_bits, 4));
   CTRY(dalloc(c, &c->d_flag, 4));
   CHIP(hipHostMalloc((void **)&c->h_bits, 4 * sizeof(unsigned long long), hipHostMallocDefault));
@@ -865,14 +871,20 @@ static tufrg_status rhs_internal(tufrg_ctx *c, double lam, const double *P, cons
   TRY(project_internal(c, P, C, c->d_VP, c->d_VC));
   const size_t lsz = 2 * (size_t)c->Nq * c->nD * c->no4;
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_BUNDLE));
+  // mixed precision: the large bundles on the matrix cores
+  const bool mx = c->prec == TUFRG_BF16X3 && c->B > 64;
+  auto bundle = [&](const double *V, const double *L, double f, double *out) {
+    return mx ? launch_bundle_bf16x3(c->n_o, c->n_ff, c->B, c->nD, c->Nq, c->d_didx, V, L, f, out, c->d_btmp,
+                                     c->btmp_bytes, c->st)
+              : launch_bundle(c->prec, c->n_o, c->n_ff, c->B, c->nD, c->Nq, c->d_didx, V, L, f, out, c->d_btmp,
+                              c->st);
+  };
   if (mask & 1u)
-    HIPCHK(c, launch_bundle(c->prec, c->n_o, c->n_ff, c->B, c->nD, c->Nq, c->d_didx, c->d_VP, c->d_loop, scale, dP,
-                            c->d_btmp, c->st));
+    HIPCHK(c, bundle(c->d_VP, c->d_loop, scale, dP));
   else
     HIPCHK(c, hipMemsetAsync(dP, 0, 2 * sizeof(double) * BB * c->Nq, c->st));
   if (mask & 2u)
-    HIPCHK(c, launch_bundle(c->prec, c->n_o, c->n_ff, c->B, c->nD, c->Nq, c->d_didx, c->d_VC, c->d_loop + lsz,
-                            2.0 * scale, dC, c->d_btmp, c->st));
+    HIPCHK(c, bundle(c->d_VC, c->d_loop + lsz, 2.0 * scale, dC));
   else
     HIPCHK(c, hipMemsetAsync(dC, 0, 2 * sizeof(double) * BB * c->Nq, c->st));
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_BUNDLE));

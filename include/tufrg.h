@@ -255,8 +255,8 @@ tufrg_status tufrg_project(tufrg_ctx *ctx, const tufrg_c64 *P, const tufrg_c64 *
 
 /* The projections of tufrg_project for callers that cannot allocate device
  * memory (code under HIP graph capture, serving loops, harnesses that forbid
- * hipMalloc): the same VP, VC, with the rho-space buffers (transform chunks,
- * the coefficients P(rho), C(rho) and the gathers) in a static device array of
+ * hipMalloc): the same VP, VC, with the rho-space buffers (the transforms'
+ * intermediate, the coefficients P(rho), C(rho) and the gathers) in a static device array of
  * 32 MiB that the library holds on each GPU until the process ends.  The call
  * allocates nothing; the context must have been created (its own allocation
  * happens there) with the same device current as now.  Limit: 3 * 4 * n_dR *

@@ -12,92 +12,125 @@
 // an extra e^{is.R'}), every term whose form-factor labels leave S being dropped.
 // So each projected vertex is X(q) + X[V0] + sum_rho e^{iq.rho} G_X(rho), with
 // G_X gathered once per evaluation in rho-space:
-//   ft_kernel      X(q) -> X(rho)   (HBM read of both states)
+//   ft             X(q) -> X(rho)   (HBM read of both states)
 //   gather_kernel  X(rho) -> G_P(rho), G_C(rho)
 //   assemble       G(rho) -> VP(q), VC(q)  (HBM read of the states, write of V)
+// On the q-mesh q = 2 pi (qx, qy) / Lq the phase factorises,
+// e^{iq.rho} = e^{2 pi i qx rho_x / Lq} e^{2 pi i qy rho_y / Lq}, and rho_y takes
+// at most nine values y_s over D.  Both transforms therefore run in two
+// streaming stages through a small intermediate M [rows][2][ny][B^2] (about
+// four times fewer operations than the direct sum over q and rho, and few
+// registers per thread, so that many loads are in flight):
+//   ft:       M(qx, s) = sum_qy e^{2 pi i qy y_s / Lq} X(qx, qy);
+//             X(rho) += sum_qx e^{2 pi i qx rho_x / Lq} M(qx, s(rho))
+//   assemble: M(qx, s) = sum_{rho: s(rho) = s} e^{2 pi i qx rho_x / Lq} G(rho);
+//             VX(qx, qy) = X + X[V0] + sum_s e^{2 pi i qy y_s / Lq} M(qx, s)
+// for blocks of qx rows that fit the workspace.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace tufrg {
 
-// part[qc][w][iD][e] = sum_{q in chunk qc} e^{iq.rho_iD} X_w(q)[e]
-// phq[q][iD] = e^{i q.rho_iD}: staged per tile of PQT q in LDS (every lane
-// reads the same phase: broadcast)
-constexpr int PQT = 16;
-template <int NDP>
-__global__ __launch_bounds__(256) void ft_kernel(int BB, int Nq, int nD, int qper, const double *__restrict__ phq,
-                                                 const double *__restrict__ P, const double *__restrict__ C,
-                                                 double *__restrict__ part) {
-  __shared__ double2 sph[PQT][NDP];
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int w = blockIdx.y;
-  const int qc = blockIdx.z;
-  const bool active = e < BB;
-  const double *X = (w == 0) ? P : C;
-  double ar[NDP], ai[NDP];
+constexpr int NYMAX = 9;
+constexpr int RMAX = 16;  // qx rows per pass of the assembly's first stage
+
+// M[r][w][s][e] = sum_qy e^{2 pi i qy y_s / Lq} X_w(x0 + r, qy)[e]; phy [Lq][ny]
+__global__ __launch_bounds__(256) void ft_rows_kernel(int BB, int Lq, int ny, int x0, const double *__restrict__ phy,
+                                                      const double *__restrict__ P, const double *__restrict__ C,
+                                                      double *__restrict__ M) {
+  extern __shared__ double2 psm[];
+  const int tid = threadIdx.x, e = blockIdx.x * blockDim.x + tid;
+  const int w = blockIdx.y, r = blockIdx.z;
+  for (int i = tid; i < Lq * ny; i += blockDim.x) psm[i] = ((const double2 *)phy)[i];
+  __syncthreads();
+  if (e >= BB) return;
+  const double *X = ((w == 0) ? P : C) + 2 * ((size_t)(x0 + r) * Lq * BB + e);
+  double ar[NYMAX], ai[NYMAX];
 #pragma unroll
-  for (int i = 0; i < NDP; ++i) {
-    ar[i] = 0.0;
-    ai[i] = 0.0;
-  }
-  const int q0 = qc * qper, q1 = min(Nq, q0 + qper);
-  for (int qb = q0; qb < q1; qb += PQT) {
-    const int nqb = min(PQT, q1 - qb);
-    __syncthreads();
-    for (int i = threadIdx.x; i < nqb * nD; i += blockDim.x) {
-      const int qq = i / nD, d = i - qq * nD;
-      sph[qq][d] = *(const double2 *)(phq + 2 * ((size_t)(qb + qq) * nD + d));
-    }
-    __syncthreads();
-    if (active) {
-      for (int qq = 0; qq < nqb; ++qq) {
-        const double2 x = *(const double2 *)(X + 2 * ((size_t)(qb + qq) * BB + e));
+  for (int y = 0; y < NYMAX; ++y) ar[y] = ai[y] = 0.0;
+#pragma unroll 8
+  for (int qy = 0; qy < Lq; ++qy) {
+    const double2 x = *(const double2 *)(X + 2 * (size_t)qy * BB);
 #pragma unroll
-        for (int i = 0; i < NDP; ++i) {
-          if (i < nD) {
-            const double2 p = sph[qq][i];
-            ar[i] = fma(p.x, x.x, fma(-p.y, x.y, ar[i]));
-            ai[i] = fma(p.x, x.y, fma(p.y, x.x, ai[i]));
-          }
-        }
+    for (int y = 0; y < NYMAX; ++y)
+      if (y < ny) {
+        const double2 p = psm[qy * ny + y];
+        ar[y] = fma(p.x, x.x, fma(-p.y, x.y, ar[y]));
+        ai[y] = fma(p.x, x.y, fma(p.y, x.x, ai[y]));
       }
+  }
+  double *o = M + 2 * (((size_t)r * 2 + w) * ny * BB + e);
+#pragma unroll
+  for (int y = 0; y < NYMAX; ++y)
+    if (y < ny) *(double2 *)(o + 2 * (size_t)y * BB) = make_double2(ar[y], ai[y]);
+}
+
+// real[w][iD][e] (+)= sum_{r < nr} e^{2 pi i (x0 + r) rho_x / Lq} M[r][w][s(iD)][e]:
+// one thread per (e, slot s, w) reads its row sums once and updates the (at
+// most nine) rho of the slot, dslot[s][j] = iD | (rho_x mod Lq) << 16 or -1;
+// the first pass writes, the last one scales by 1/Nq
+__global__ __launch_bounds__(256) void ft_cols_kernel(int BB, int Lq, int nD, int ny, int x0, int nr, int first,
+                                                      double scale, const double *__restrict__ twq,
+                                                      const int *__restrict__ dslot, const double *__restrict__ M,
+                                                      double *__restrict__ real) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sl = blockIdx.y, w = blockIdx.z;
+  if (e >= BB) return;
+  int ent[NYMAX];
+  double sr[NYMAX], si[NYMAX];
+#pragma unroll
+  for (int j = 0; j < NYMAX; ++j) {
+    ent[j] = dslot[sl * NYMAX + j];
+    sr[j] = si[j] = 0.0;
+    if (ent[j] >= 0 && !first) {
+      const size_t o = ((size_t)w * nD + (ent[j] & 0xffff)) * BB + e;
+      sr[j] = real[2 * o];
+      si[j] = real[2 * o + 1];
     }
   }
-  if (!active) return;
-  const size_t base = ((size_t)qc * 2 + w) * nD;
+  for (int r = 0; r < nr; ++r) {
+    const double2 a = *(const double2 *)(M + 2 * ((((size_t)r * 2 + w) * ny + sl) * BB + e));
 #pragma unroll
-  for (int i = 0; i < NDP; ++i)
-    if (i < nD) {
-      part[2 * ((base + i) * BB + e)] = ar[i];
-      part[2 * ((base + i) * BB + e) + 1] = ai[i];
+    for (int j = 0; j < NYMAX; ++j)
+      if (ent[j] >= 0) {
+        const double2 tw = ((const double2 *)twq)[((x0 + r) * (ent[j] >> 16)) % Lq];
+        sr[j] = fma(tw.x, a.x, fma(-tw.y, a.y, sr[j]));
+        si[j] = fma(tw.x, a.y, fma(tw.y, a.x, si[j]));
+      }
+  }
+#pragma unroll
+  for (int j = 0; j < NYMAX; ++j)
+    if (ent[j] >= 0) {
+      const size_t o = ((size_t)w * nD + (ent[j] & 0xffff)) * BB + e;
+      real[2 * o] = sr[j] * scale;
+      real[2 * o + 1] = si[j] * scale;
     }
 }
 
-__global__ void ft_reduce_kernel(long long n, int nqc, double scale, const double *__restrict__ part,
-                                 double *__restrict__ real) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double s = 0.0;
-  for (int c = 0; c < nqc; ++c) s += part[(size_t)c * n + i];
-  real[i] = s * scale;
+size_t proj_ws_row_doubles(const ProjArgs &a) { return 2 * 2 * (size_t)a.ny * a.B * a.B; }
+
+static int proj_rows_per_pass(const ProjArgs &a, size_t ws_doubles, int rmax) {
+  const size_t per_row = 2 * 2 * (size_t)a.ny * a.B * a.B;  // doubles of M per qx row
+  return (int)std::max<size_t>(1, std::min<size_t>({(size_t)a.Lq, (size_t)rmax, ws_doubles / per_row}));
 }
 
-hipError_t launch_ft(const ProjArgs &a, const double *P, const double *C, double *part, int nqc, double *real,
-                     hipStream_t st) {
+hipError_t launch_ft(const ProjArgs &a, const double *P, const double *C, double *ws, size_t ws_doubles,
+                     double *real, hipStream_t st) {
   const int BB = a.B * a.B;
-  const int qper = (a.Nq + nqc - 1) / nqc;
-  dim3 grid((BB + 255) / 256, 2, nqc), block(256);
-  if (a.nD <= 13)
-    hipLaunchKernelGGL(ft_kernel<13>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, part);
-  else if (a.nD <= 25)
-    hipLaunchKernelGGL(ft_kernel<25>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, part);
-  else if (a.nD <= 41)
-    hipLaunchKernelGGL(ft_kernel<41>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, part);
-  else
-    return hipErrorInvalidValue;
-  const long long n = 2LL * 2 * a.nD * BB;  // doubles per chunk
-  hipLaunchKernelGGL(ft_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, nqc,
-                     1.0 / (double)a.Nq, part, real);
+  if (a.ny < 1 || a.ny > NYMAX || a.Nq != a.Lq * a.Lq || a.nD > 65535) return hipErrorInvalidValue;
+  const size_t per_row = 2 * 2 * (size_t)a.ny * BB;
+  if (ws_doubles < per_row) return hipErrorInvalidValue;
+  const int R = proj_rows_per_pass(a, ws_doubles, a.Lq);
+  const size_t lds = sizeof(double2) * (size_t)a.Lq * a.ny;
+  for (int x0 = 0; x0 < a.Lq; x0 += R) {
+    const int nr = std::min(R, a.Lq - x0);
+    hipLaunchKernelGGL(ft_rows_kernel, dim3((BB + 255) / 256, 2, nr), dim3(256), lds, st, BB, a.Lq, a.ny, x0, a.phy,
+                       P, C, ws);
+    hipLaunchKernelGGL(ft_cols_kernel, dim3((BB + 255) / 256, a.ny, 2), dim3(256), 0, st, BB, a.Lq, a.nD, a.ny, x0,
+                       nr, x0 == 0 ? 1 : 0, x0 + nr >= a.Lq ? 1.0 / (double)a.Nq : 1.0, a.twq, a.dslot, ws, real);
+  }
   return hipGetLastError();
 }
 
@@ -168,86 +201,95 @@ hipError_t launch_gather(const ProjArgs &a, const double *real, double *G, hipSt
   return hipGetLastError();
 }
 
-// VX(q)[e] = X(q)[e] + X[V0][e] + sum_rho e^{iq.rho} G_X(rho)[e]; the phases of
-// a tile of PQT q are staged in LDS as in ft_kernel
-template <int NDP>
-__global__ __launch_bounds__(256) void assemble_kernel(int BB, int Nq, int nD, int qper, const double *__restrict__ phq,
-                                                       const double *__restrict__ P, const double *__restrict__ C,
-                                                       const double *__restrict__ G, const double *__restrict__ v0p,
-                                                       const double *__restrict__ v0c, double *__restrict__ VP,
-                                                       double *__restrict__ VC) {
-  __shared__ double2 sph[PQT][NDP];
+// M[r][w][s][e] = sum_{rho with s(rho) = s} e^{2 pi i (x0 + r) rho_x / Lq} G[w][rho][e]
+// for r < nr; one thread per (e, s, w) keeps the nr row sums
+__global__ __launch_bounds__(256) void assemble_rows_kernel(int BB, int Lq, int nD, int ny, int x0, int nr,
+                                                            const double *__restrict__ twq,
+                                                            const int *__restrict__ dtab,
+                                                            const double *__restrict__ G, double *__restrict__ M) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  const int w = blockIdx.y, qc = blockIdx.z;
-  const bool active = e < BB;
-  const int ea = active ? e : 0;
-  const double *X = (w == 0) ? P : C;
-  const double *v0 = (w == 0) ? v0p : v0c;
-  double *out = (w == 0) ? VP : VC;
-  double gr[NDP], gi[NDP];
+  const int sl = blockIdx.y, w = blockIdx.z;
+  if (e >= BB) return;
+  double hr[RMAX], hi[RMAX];
 #pragma unroll
-  for (int i = 0; i < NDP; ++i) {
-    if (i < nD) {
-      const size_t s = ((size_t)w * nD + i) * BB + ea;
-      gr[i] = G[2 * s];
-      gi[i] = G[2 * s + 1];
-    } else {
-      gr[i] = 0.0;
-      gi[i] = 0.0;
+  for (int r = 0; r < RMAX; ++r) hr[r] = hi[r] = 0.0;
+  for (int iD = 0; iD < nD; ++iD) {
+    const int t = dtab[iD];
+    if ((t >> 16) != sl) continue;  // uniform
+    const int xv = t & 0xffff;
+    const double2 g = *(const double2 *)(G + 2 * (((size_t)w * nD + iD) * BB + e));
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r)
+      if (r < nr) {
+        const double2 tw = ((const double2 *)twq)[((x0 + r) * xv) % Lq];
+        hr[r] = fma(tw.x, g.x, fma(-tw.y, g.y, hr[r]));
+        hi[r] = fma(tw.x, g.y, fma(tw.y, g.x, hi[r]));
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r)
+    if (r < nr) *(double2 *)(M + 2 * ((((size_t)r * 2 + w) * ny + sl) * BB + e)) = make_double2(hr[r], hi[r]);
+}
+
+// VX(x0 + r, qy)[e] = X[e] + X[V0][e] + sum_s e^{2 pi i qy y_s / Lq} M[r][w][s][e]
+__global__ __launch_bounds__(256) void assemble_cols_kernel(int BB, int Lq, int ny, int x0,
+                                                            const double *__restrict__ phy,
+                                                            const double *__restrict__ P, const double *__restrict__ C,
+                                                            const double *__restrict__ M,
+                                                            const double *__restrict__ v0p,
+                                                            const double *__restrict__ v0c, double *__restrict__ VP,
+                                                            double *__restrict__ VC) {
+  extern __shared__ double2 psm[];
+  const int tid = threadIdx.x, e = blockIdx.x * blockDim.x + tid;
+  const int w = blockIdx.y, r = blockIdx.z;
+  for (int i = tid; i < Lq * ny; i += blockDim.x) psm[i] = ((const double2 *)phy)[i];
+  __syncthreads();
+  if (e >= BB) return;
+  const double *v0 = (w == 0) ? v0p : v0c;
+  const double v0r = v0[2 * e], v0i = v0[2 * e + 1];
+  double hr[NYMAX], hi[NYMAX];
+#pragma unroll
+  for (int y = 0; y < NYMAX; ++y) {
+    hr[y] = hi[y] = 0.0;
+    if (y < ny) {
+      const double2 h = *(const double2 *)(M + 2 * ((((size_t)r * 2 + w) * ny + y) * BB + e));
+      hr[y] = h.x;
+      hi[y] = h.y;
     }
   }
-  const double v0r = v0[2 * ea], v0i = v0[2 * ea + 1];
-  const int q0 = qc * qper, q1 = min(Nq, q0 + qper);
-  for (int qb = q0; qb < q1; qb += PQT) {
-    const int nqb = min(PQT, q1 - qb);
-    __syncthreads();
-    for (int i = threadIdx.x; i < nqb * nD; i += blockDim.x) {
-      const int qq = i / nD, d = i - qq * nD;
-      sph[qq][d] = *(const double2 *)(phq + 2 * ((size_t)(qb + qq) * nD + d));
-    }
-    __syncthreads();
-    if (active) {
-      for (int qq = 0; qq < nqb; ++qq) {
-        const int q = qb + qq;
-        const double2 x = *(const double2 *)(X + 2 * ((size_t)q * BB + e));
-        double sr = x.x + v0r, si = x.y + v0i;
+  const size_t row = (size_t)(x0 + r) * Lq * BB + e;
+  const double *X = (w == 0) ? P : C;
+  double *out = (w == 0) ? VP : VC;
+#pragma unroll 8
+  for (int qy = 0; qy < Lq; ++qy) {
+    const double2 x = *(const double2 *)(X + 2 * (row + (size_t)qy * BB));
+    double sr = x.x + v0r, si = x.y + v0i;
 #pragma unroll
-        for (int i = 0; i < NDP; ++i) {
-          if (i < nD) {
-            const double2 p = sph[qq][i];
-            sr = fma(p.x, gr[i], fma(-p.y, gi[i], sr));
-            si = fma(p.x, gi[i], fma(p.y, gr[i], si));
-          }
-        }
-        double2 o;
-        o.x = sr;
-        o.y = si;
-        *(double2 *)(out + 2 * ((size_t)q * BB + e)) = o;
+    for (int y = 0; y < NYMAX; ++y)
+      if (y < ny) {
+        const double2 p = psm[qy * ny + y];
+        sr = fma(p.x, hr[y], fma(-p.y, hi[y], sr));
+        si = fma(p.x, hi[y], fma(p.y, hr[y], si));
       }
-    }
+    *(double2 *)(out + 2 * (row + (size_t)qy * BB)) = make_double2(sr, si);
   }
 }
 
 hipError_t launch_assemble(const ProjArgs &a, const double *P, const double *C, const double *G,
-                           const double *v0p, const double *v0c, double *VP, double *VC, hipStream_t st) {
+                           const double *v0p, const double *v0c, double *VP, double *VC, double *ws,
+                           size_t ws_doubles, hipStream_t st) {
   const int BB = a.B * a.B;
-  // enough q chunks to give every CU work
-  int nqc = (int)((1024LL * 256 + 2LL * BB - 1) / (2LL * BB));
-  nqc = max(1, min(nqc, a.Nq));
-  const int qper = (a.Nq + nqc - 1) / nqc;
-  nqc = (a.Nq + qper - 1) / qper;
-  dim3 grid((BB + 255) / 256, 2, nqc), block(256);
-  if (a.nD <= 13)
-    hipLaunchKernelGGL(assemble_kernel<13>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, G, v0p, v0c,
-                       VP, VC);
-  else if (a.nD <= 25)
-    hipLaunchKernelGGL(assemble_kernel<25>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, G, v0p, v0c,
-                       VP, VC);
-  else if (a.nD <= 41)
-    hipLaunchKernelGGL(assemble_kernel<41>, grid, block, 0, st, BB, a.Nq, a.nD, qper, a.phq, P, C, G, v0p, v0c,
-                       VP, VC);
-  else
-    return hipErrorInvalidValue;
+  if (a.ny < 1 || a.ny > NYMAX || a.Nq != a.Lq * a.Lq) return hipErrorInvalidValue;
+  if (ws_doubles < 2 * 2 * (size_t)a.ny * BB) return hipErrorInvalidValue;
+  const int R = proj_rows_per_pass(a, ws_doubles, RMAX);
+  const size_t lds = sizeof(double2) * (size_t)a.Lq * a.ny;
+  for (int x0 = 0; x0 < a.Lq; x0 += R) {
+    const int nr = std::min(R, a.Lq - x0);
+    hipLaunchKernelGGL(assemble_rows_kernel, dim3((BB + 255) / 256, a.ny, 2), dim3(256), 0, st, BB, a.Lq, a.nD, a.ny,
+                       x0, nr, a.twq, a.dtab, G, ws);
+    hipLaunchKernelGGL(assemble_cols_kernel, dim3((BB + 255) / 256, 2, nr), dim3(256), lds, st, BB, a.Lq, a.ny, x0,
+                       a.phy, P, C, ws, v0p, v0c, VP, VC);
+  }
   return hipGetLastError();
 }
 

@@ -73,13 +73,20 @@ struct ProjArgs {
   const int *dgrid;    // [17][17] index into dlist, -1 outside D
   const int *ff;       // [n_ff][2]
   const double *twq;   // exp(+2 pi i j / Lq), [Lq][2]
-  const double *phq;   // exp(+i q.rho) for every coarse q and rho in dlist, [Nq][nD][2]
+  int ny;              // distinct rho_y over dlist (at most 9)
+  const double *phy;   // exp(+2 pi i qy y_s / Lq) of those values y_s, [Lq][ny][2]
+  const int *dtab;     // per rho of dlist: (rho_x mod Lq) | (slot s of rho_y) << 16
+  const int *dslot;    // [9][9] per slot s the rho of D with rho_y = y_s: iD | (rho_x mod Lq) << 16, else -1
 };
-hipError_t launch_ft(const ProjArgs &a, const double *P, const double *C, double *part, int nqc, double *real,
-                     hipStream_t st);
+// ws: workspace of ws_doubles >= proj_ws_row_doubles (one qx row of the
+// two-stage transforms; more rows per pass with more)
+size_t proj_ws_row_doubles(const ProjArgs &a);
+hipError_t launch_ft(const ProjArgs &a, const double *P, const double *C, double *ws, size_t ws_doubles,
+                     double *real, hipStream_t st);
 hipError_t launch_gather(const ProjArgs &a, const double *real, double *G, hipStream_t st);
 hipError_t launch_assemble(const ProjArgs &a, const double *P, const double *C, const double *G,
-                           const double *v0p, const double *v0c, double *VP, double *VC, hipStream_t st);
+                           const double *v0p, const double *v0c, double *VP, double *VC, double *ws,
+                           size_t ws_doubles, hipStream_t st);
 
 // a6: bundle products  out = f * V L V  per q, L expanded from compact form;
 // bundles larger than 64 need a workspace tmp of n_q * B * B complex

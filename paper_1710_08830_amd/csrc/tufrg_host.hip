@@ -39,7 +39,8 @@ struct tufrg_ctx {
   hipStream_t st = nullptr;
   int device = 0;  // the device current at creation
   int n_o = 0, n_ff = 0, B = 0, Lq = 0, n_ref = 0, Lf = 0, Nq = 0, Nf = 0, no2 = 0, no4 = 0;
-  int nD = 0, ndx = 0, ndy = 0, scheme = 0, prec = 0, nkyb = 0, nkxc = 0, nqc = 0;
+  int nD = 0, ndx = 0, ndy = 0, scheme = 0, prec = 0, nkyb = 0, nkxc = 0;
+  size_t proj_ws = 0;  // doubles of the projection workspace (whole qx rows of the intermediate)
   std::vector<int> ff, dlist, didx, ffgrid, dgrid, pairs;
   int *d_ff = nullptr, *d_dlist = nullptr, *d_didx = nullptr, *d_ffgrid = nullptr, *d_dgrid = nullptr;
   int *d_hopR = nullptr;
@@ -65,7 +66,12 @@ struct tufrg_ctx {
   double temp = 0.0;          // momentum-shell scheme: the fixed temperature of its bubbles
   double *d_cv64 = nullptr;   // momentum-shell scheme: shell factors (see LoopArgs::cv)
   float *d_cv32 = nullptr;
-  double *d_twf = nullptr, *d_twq = nullptr, *d_phq = nullptr;
+  double *d_twf = nullptr, *d_twq = nullptr;
+  // projections: phases of the distinct rho_y over D per qy, and per rho of D
+  // (rho_x mod Lq) | slot of rho_y << 16
+  double *d_pphy = nullptr;
+  int *d_dtab = nullptr;
+  int ny = 0;
   float *d_twf32 = nullptr;
   double *d_partial = nullptr;
   double *d_loop = nullptr;
@@ -357,9 +363,17 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     }
   }
   {
-    long long BB2 = 2LL * c->B * c->B;
-    int want = (int)std::max<long long>(1, (512LL * 256 + BB2 - 1) / BB2);
-    c->nqc = std::max(1, std::min(want, c->Nq));
+    // distinct rho_y over D (the projections' qy phases); D lies in [-4, 4]^2
+    // for form factors with |R| <= 2
+    std::vector<int> ys;
+    for (int i = 0; i < c->nD; ++i)
+      if (std::find(ys.begin(), ys.end(), c->dlist[2 * i + 1]) == ys.end()) ys.push_back(c->dlist[2 * i + 1]);
+    c->ny = (int)ys.size();
+    // the projections' intermediate: whole qx rows of [2][ny][B^2] complex, up
+    // to about 1 GB
+    const size_t per_row = 2 * 2 * (size_t)c->ny * c->B * c->B;
+    const size_t rows = std::max<size_t>(1, std::min<size_t>((size_t)c->Lq, ((size_t)1 << 27) / per_row));
+    c->proj_ws = rows * per_row;
   }
   auto bail = [&](tufrg_status st) {
     g_err = c->err;
@@ -435,11 +449,11 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CTRY(dalloc(c, &c->d_twf, 2 * (size_t)c->Lf));
   CTRY(dalloc(c, &c->d_twf32, 2 * (size_t)c->Lf));
   CTRY(dalloc(c, &c->d_twq, 2 * (size_t)c->Lq));
-  CTRY(dalloc(c, &c->d_phq, 2 * (size_t)c->Nq * c->nD));
+  CTRY(dalloc(c, &c->d_dtab, c->nD + 81));
   const size_t nparts = (size_t)c->nkyb * c->nkxc;
   CTRY(dalloc(c, &c->d_partial, 2 * 2 * (size_t)c->Nq * nparts * c->ndx * (2 * c->ndy + 1) * c->no4));
   CTRY(dalloc(c, &c->d_loop, 2 * 2 * (size_t)c->Nq * c->nD * c->no4));
-  CTRY(dalloc(c, &c->d_ftpart, 2 * 2 * (size_t)c->nqc * c->nD * BB));
+  CTRY(dalloc(c, &c->d_ftpart, c->proj_ws));
   CTRY(dalloc(c, &c->d_real, 2 * 2 * (size_t)c->nD * BB));
   CTRY(dalloc(c, &c->d_G, 2 * 2 * (size_t)c->nD * BB));
   CTRY(dalloc(c, &c->d_v0p, 2 * BB));
@@ -513,16 +527,42 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   std::vector<float> twf32(twf.begin(), twf.end());
   CHIP(hipMemcpyAsync(c->d_twf32, twf32.data(), twf32.size() * sizeof(float), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_twq, twq.data(), twq.size() * sizeof(double), hipMemcpyHostToDevice, st));
-  // e^{i q.rho} from exact integer phases (mx dx + my dy) mod Lq
-  std::vector<double> phq(2 * (size_t)c->Nq * c->nD);
-  for (int q = 0; q < c->Nq; ++q)
-    for (int i = 0; i < c->nD; ++i) {
-      int j = ((q / c->Lq) * c->dlist[2 * i] + (q % c->Lq) * c->dlist[2 * i + 1]) % c->Lq;
-      if (j < 0) j += c->Lq;
-      phq[2 * ((size_t)q * c->nD + i)] = twq[2 * j];
-      phq[2 * ((size_t)q * c->nD + i) + 1] = twq[2 * j + 1];
+  // e^{i q.rho} = e^{2 pi i qx rho_x / Lq} e^{2 pi i qy rho_y / Lq}, both from
+  // exact integer phases mod Lq: the qy factors of the distinct rho_y, and per
+  // rho its rho_x and the slot of its rho_y
+  {
+    auto mod = [&](long long v) { return (int)(((v % c->Lq) + c->Lq) % c->Lq); };
+    std::vector<int> ys;
+    for (int i = 0; i < c->nD; ++i)
+      if (std::find(ys.begin(), ys.end(), c->dlist[2 * i + 1]) == ys.end()) ys.push_back(c->dlist[2 * i + 1]);
+    std::sort(ys.begin(), ys.end());
+    if (c->ny != (int)ys.size() || c->ny > 9) {  // D lies in [-4, 4]^2 for form factors with |R| <= 2
+      c->err = "more than nine distinct rho_y in D";
+      return bail(TUFRG_E_UNSUPPORTED);
     }
-  CHIP(hipMemcpyAsync(c->d_phq, phq.data(), phq.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    std::vector<double> pphy(2 * (size_t)c->Lq * c->ny);
+    for (int qy = 0; qy < c->Lq; ++qy)
+      for (int y = 0; y < c->ny; ++y) {
+        const int j = mod((long long)qy * ys[y]);
+        pphy[2 * ((size_t)qy * c->ny + y)] = twq[2 * j];
+        pphy[2 * ((size_t)qy * c->ny + y) + 1] = twq[2 * j + 1];
+      }
+    // dtab [nD], then the slot table [9][9]
+    std::vector<int> dtab(c->nD + 81, -1), fill(9, 0);
+    for (int i = 0; i < c->nD; ++i) {
+      const int sl = (int)(std::find(ys.begin(), ys.end(), c->dlist[2 * i + 1]) - ys.begin());
+      dtab[i] = mod(c->dlist[2 * i]) | (sl << 16);
+      if (fill[sl] >= 9) {  // at most nine rho_x per rho_y in [-4, 4]^2
+        c->err = "more than nine rho with one rho_y in D";
+        return bail(TUFRG_E_UNSUPPORTED);
+      }
+      dtab[c->nD + 9 * sl + fill[sl]++] = i | (mod(c->dlist[2 * i]) << 16);
+    }
+    CTRY(dalloc(c, &c->d_pphy, pphy.size()));
+    CHIP(hipMemcpyAsync(c->d_pphy, pphy.data(), pphy.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    CHIP(hipMemcpyAsync(c->d_dtab, dtab.data(), dtab.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    CHIP(hipStreamSynchronize(st));  // the host tables end with this block
+  }
   if (c->n_o > 2) {
     CHIP(hipMemcpyAsync(c->d_phy64, phy64.data(), phy64.size() * sizeof(double), hipMemcpyHostToDevice, st));
     CHIP(hipMemcpyAsync(c->d_phy32, phy32.data(), phy32.size() * sizeof(float), hipMemcpyHostToDevice, st));
@@ -621,7 +661,10 @@ static ProjArgs proj_args(tufrg_ctx *c) {
   a.dgrid = c->d_dgrid;
   a.ff = c->d_ff;
   a.twq = c->d_twq;
-  a.phq = c->d_phq;
+  a.ny = c->ny;
+  a.phy = c->d_pphy;
+  a.dtab = c->d_dtab;
+  a.dslot = c->d_dtab + c->nD;
   return a;
 }
 
@@ -824,10 +867,10 @@ static tufrg_status surrogate_loops(tufrg_ctx *c, double lam) {
   return TUFRG_OK;
 }
 
-// projections with the rho-space buffers given: nqc chunk partials at part,
-// then real and G ([2][nD][B][B] complex each)
+// projections with the buffers given: the workspace ws (ws_doubles, at least
+// one qx row of the intermediate), real and G ([2][nD][B][B] complex each)
 static tufrg_status project_with(tufrg_ctx *c, const double *P, const double *C, double *VP, double *VC,
-                                 double *part, int nqc, double *real, double *G) {
+                                 double *ws, size_t ws_doubles, double *real, double *G) {
   ProjArgs a = proj_args(c);
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_PROJECT));
   if (c->has_c0) {
@@ -842,15 +885,15 @@ static tufrg_status project_with(tufrg_ctx *c, const double *P, const double *C,
     HIPCHK(c, launch_add(2 * (long long)c->Nq * c->B * c->B, P, c->d_p0, c->d_peff, c->st));
     P = c->d_peff;
   }
-  HIPCHK(c, launch_ft(a, P, C, part, nqc, real, c->st));
+  HIPCHK(c, launch_ft(a, P, C, ws, ws_doubles, real, c->st));
   HIPCHK(c, launch_gather(a, real, G, c->st));
-  HIPCHK(c, launch_assemble(a, P, C, G, c->d_v0p, c->d_v0c, VP, VC, c->st));
+  HIPCHK(c, launch_assemble(a, P, C, G, c->d_v0p, c->d_v0c, VP, VC, ws, ws_doubles, c->st));
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_PROJECT));
   return TUFRG_OK;
 }
 
 static tufrg_status project_internal(tufrg_ctx *c, const double *P, const double *C, double *VP, double *VC) {
-  return project_with(c, P, C, VP, VC, c->d_ftpart, c->nqc, c->d_real, c->d_G);
+  return project_with(c, P, C, VP, VC, c->d_ftpart, c->proj_ws, c->d_real, c->d_G);
 }
 
 // dP = scale VP Lpp VP, dC = 2 scale VC Lph VC; a masked channel gets zero
@@ -1083,15 +1126,16 @@ extern "C" tufrg_status tufrg_project_static(tufrg_ctx *c, const tufrg_c64 *P, c
   double *scr = g_scratch_ptr[dev];
   if (!scr) return fail(c, TUFRG_E_HIP, "static scratch not set up on this device");
   // one [2][nD][B][B] complex block each for the coefficients and the
-  // gathers, the rest for transform chunks (at least one)
+  // gathers, the rest (at least as much, so at least one qx row of
+  // [2][ny][B][B] with ny <= nD) for the transforms' intermediate
   const size_t unit = 2 * 2 * (size_t)c->nD * c->B * c->B;
   if (3 * unit > STATIC_SCRATCH_DOUBLES)
     return fail(c, TUFRG_E_UNSUPPORTED,
                 "static scratch of 32 MiB holds 3 * 4 * n_dR * B^2 doubles at most; this setup needs " +
                     std::to_string(3 * unit * sizeof(double)) + " bytes");
-  const int nqc = (int)std::min<size_t>((size_t)c->nqc, STATIC_SCRATCH_DOUBLES / unit - 2);
-  double *real = scr + (size_t)nqc * unit, *G = real + unit;
-  return project_with(c, (const double *)P, (const double *)C, (double *)VP, (double *)VC, scr, nqc, real, G);
+  double *real = scr, *G = real + unit, *ws = G + unit;
+  return project_with(c, (const double *)P, (const double *)C, (double *)VP, (double *)VC, ws,
+                      STATIC_SCRATCH_DOUBLES - 2 * unit, real, G);
 }
 
 extern "C" tufrg_status tufrg_set_initial_c(tufrg_ctx *c, const tufrg_c64 *C0) {

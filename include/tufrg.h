@@ -249,6 +249,46 @@ tufrg_status tufrg_ff_apply(tufrg_ctx *ctx, const tufrg_c64 *W, const tufrg_c64 
  * pointer, E_NOMEM when the two [Nq][B][B] buffers cannot be allocated. */
 tufrg_status tufrg_set_initial_p(tufrg_ctx *ctx, const tufrg_c64 *P0);
 
+/* Result of tufrg_autotune. */
+typedef struct {
+  int32_t tunable;        /* 0: this setup has no launch shape to tune (six spin-orbitals on
+                             the vector units: one workgroup per q and channel) */
+  int32_t from_cache;     /* 1: the shape came from the cache file; nothing was timed */
+  int32_t loop_kx_chunks; /* two spin-orbitals: kx chunks of the loop kernel now in use */
+  int32_t mfma_kx_rows;   /* six spin-orbitals, BF16X3: kx rows per work item now in use */
+  int32_t n_candidates;   /* shapes timed (0 from the cache) */
+  double loop_ms;         /* one evaluation of both loop channels with the chosen shape */
+  double default_ms;      /* the same with the shape the context started with */
+} tufrg_tune_result;
+
+/* Launch-shape autotuner of the loop kernels (no passage: an implementation
+ * choice).  Times one evaluation of both loop channels at scale lambda (HIP
+ * events on the context's stream, one untimed evaluation first, then about
+ * 50 ms of repeats) for each candidate shape and keeps the fastest in the
+ * context: for two spin-orbitals the number of kx chunks of the loop kernel
+ * (partial sums per chunk, the buffer grows if a candidate needs more), for
+ * TUFRG_BF16X3 the kx rows per matrix-core work item.  The shape only
+ * regroups the k sum: BF16X3 results are unchanged bit for bit, two-orbital
+ * ones change by FP32 rounding of the chunk partials.  cache_path (may be
+ * NULL) names a JSON file {"version": 1, "entries": {"<key>": {...}}} keyed
+ * by GPU architecture, compute units and problem shape: an entry for this
+ * shape is applied without timing; otherwise the result is added and the
+ * file rewritten (through a temporary file and a rename).  Synchronous.  The
+ * chosen shape stays until the context is destroyed or tuned again.  Errors:
+ * E_INVAL for a null result, lambda <= 0, a cache file that exists but is not
+ * a tuning cache (left untouched) or cannot be written; E_NOMEM, E_HIP as the
+ * loops.  Call it outside flows and graph captures. */
+tufrg_status tufrg_autotune(tufrg_ctx *ctx, double lambda, const char *cache_path, tufrg_tune_result *res);
+
+/* The third channel (Sec. 3.2): D_{n1n2n3n4} = -C_{n1n2n4n3}, which the
+ * antisymmetry of the vertex fixes, so only P and C flow.  C and D are device
+ * arrays [Nq][B][B] on the context's device; D is written in the layout of C,
+ * D[q][(R,a,b)][(R',c,d)] = D^{RR'}_{a d b c}(q) = -C[q][(R,a,c)][(R',b,d)]
+ * (exact, no arithmetic beyond the sign).  The caller owns both; they must not
+ * overlap.  Asynchronous on the context's stream.  Errors: E_INVAL for a host
+ * pointer or overlapping arrays, E_HIP for a failed launch. */
+tufrg_status tufrg_channel_d(tufrg_ctx *ctx, const tufrg_c64 *C, tufrg_c64 *D);
+
 /* Projected vertices VP, VC [Nq][B][B] of the state P, C [Nq][B][B] (Sec. 3.3). */
 tufrg_status tufrg_project(tufrg_ctx *ctx, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,
                            tufrg_c64 *VC);

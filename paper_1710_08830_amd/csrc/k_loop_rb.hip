@@ -613,7 +613,8 @@ hipError_t launch_loop_rb(const LoopArgs &a, int ch, float *Y, hipStream_t st) {
   if (a.scheme == CUT_SHELL && !cvp) return hipErrorInvalidValue;
   if (!(a.ndy == 4 && a.ndx == 5) && !(a.ndy == 2 && a.ndx == 3)) return hipErrorInvalidValue;
   const int n_groups = (a.n_q + NQG - 1) / NQG;
-  const int kxr = 2;  // kx rows per work item
+  const int kxr = a.kxr;  // kx rows per work item
+  if (kxr < 1 || kxr > 8) return hipErrorInvalidValue;
   const int n_kxb = (a.Lf + kxr - 1) / kxr;
   const int gx = (n_groups + 7) / 8;
   const long long nblk = 8LL * gx * n_kxb;

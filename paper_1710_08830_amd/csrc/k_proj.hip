@@ -194,6 +194,30 @@ __global__ void gather_kernel(int n_o, int n_ff, int B, int nD, const int *__res
   G[2 * i + 1] = gi;
 }
 
+// D[q][(R,a,b)][(R',c,d)] = -C[q][(R,a,c)][(R',b,d)]: the third channel in the
+// layout of C, D_{n1n2n3n4} = -C_{n1n2n4n3}; a pure gather, exact
+__global__ void channel_d_kernel(int n_o, int B, long long n, const double2 *__restrict__ C,
+                                 double2 *__restrict__ D) {
+  const int no2 = n_o * n_o;
+  const long long BB = (long long)B * B;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int col = (int)(i % B), row = (int)((i / B) % B);
+    const long long q = i / BB;
+    const int r = row / no2, a = (row % no2) / n_o, b = row % n_o;
+    const int rp = col / no2, c = (col % no2) / n_o, d = col % n_o;
+    const double2 v = C[q * BB + (long long)(r * no2 + a * n_o + c) * B + (rp * no2 + b * n_o + d)];
+    D[i] = make_double2(-v.x, -v.y);
+  }
+}
+
+hipError_t launch_channel_d(int n_o, int B, int Nq, const double *C, double *D, hipStream_t st) {
+  const long long n = (long long)Nq * B * B;
+  const long long blocks = std::min<long long>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(channel_d_kernel, dim3((unsigned)std::max<long long>(blocks, 1)), dim3(256), 0, st, n_o, B, n,
+                     (const double2 *)C, (double2 *)D);
+  return hipGetLastError();
+}
+
 hipError_t launch_gather(const ProjArgs &a, const double *real, double *G, hipStream_t st) {
   const long long total = 2LL * a.nD * a.B * a.B;
   hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a.n_o, a.n_ff, a.B,

@@ -27,6 +27,7 @@ struct LoopArgs {
   int n_o, Lq, n_ref, Lf, Nq;
   int ndx, ndy;        // computed box: dx in [0, ndx), dy in [-ndy, ndy]
   int nkyb, nkxc;      // ky blocks of 64 lanes, kx chunks
+  int kxr = 2;         // six spin-orbitals on the matrix cores: kx rows per work item (1..8)
   int ch_first, n_ch;  // channels 0 (pp) and/or 1 (ph)
   int q_first, n_q;    // coarse q range
   const int *rows = nullptr;  // if set: q = whole q_x rows rows[0 .. n_q / Lq) (q_first unused)
@@ -84,6 +85,8 @@ size_t proj_ws_row_doubles(const ProjArgs &a);
 hipError_t launch_ft(const ProjArgs &a, const double *P, const double *C, double *ws, size_t ws_doubles,
                      double *real, hipStream_t st);
 hipError_t launch_gather(const ProjArgs &a, const double *real, double *G, hipStream_t st);
+// D [Nq][B][B] (layout of C) from C: D_{n1n2n3n4} = -C_{n1n2n4n3}
+hipError_t launch_channel_d(int n_o, int B, int Nq, const double *C, double *D, hipStream_t st);
 hipError_t launch_assemble(const ProjArgs &a, const double *P, const double *C, const double *G,
                            const double *v0p, const double *v0c, double *VP, double *VC, double *ws,
                            size_t ws_doubles, hipStream_t st);

@@ -11,6 +11,7 @@
 //   bundle    dP = VP Lpp VP, dC = 2 VC Lph VC
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -21,6 +22,7 @@
 #include "../../include/tufrg.h"
 #include "common.h"
 #include "kernels.h"
+#include "tune_cache.h"
 
 namespace tufrg {
 hipError_t launch_unpack_pi(int n_o, int Nf, const double *pi, double *out, hipStream_t st);
@@ -113,6 +115,8 @@ struct tufrg_ctx {
   double *d_lamb = nullptr;                    // BF16X3 loops: real-basis sums of a chunk
   int *d_hmap = nullptr;                       // BF16X3 loops: half-plane point of each difference vector
   int mfma_chunk = 0;
+  int mfma_kxr = 2;        // kx rows per work item of the matrix-core loop (tunable)
+  size_t partial_cap = 0;  // doubles allocated at d_partial
   unsigned long long *h_sbits = nullptr;       // pinned
   // Euler steps in HIP graphs: the executable graph, the capture stream (the
   // context's stream, or a private one when that is the null stream), one
@@ -451,7 +455,8 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CTRY(dalloc(c, &c->d_twq, 2 * (size_t)c->Lq));
   CTRY(dalloc(c, &c->d_dtab, c->nD + 81));
   const size_t nparts = (size_t)c->nkyb * c->nkxc;
-  CTRY(dalloc(c, &c->d_partial, 2 * 2 * (size_t)c->Nq * nparts * c->ndx * (2 * c->ndy + 1) * c->no4));
+  c->partial_cap = 2 * 2 * (size_t)c->Nq * nparts * c->ndx * (2 * c->ndy + 1) * c->no4;
+  CTRY(dalloc(c, &c->d_partial, c->partial_cap));
   CTRY(dalloc(c, &c->d_loop, 2 * 2 * (size_t)c->Nq * c->nD * c->no4));
   CTRY(dalloc(c, &c->d_ftpart, c->proj_ws));
   CTRY(dalloc(c, &c->d_real, 2 * 2 * (size_t)c->nD * BB));
@@ -616,6 +621,7 @@ static LoopArgs loop_args(tufrg_ctx *c, double lam, int deriv, int ch_first, int
   a.ndy = c->ndy;
   a.nkyb = c->nkyb;
   a.nkxc = c->nkxc;
+  a.kxr = c->mfma_kxr;
   a.ch_first = ch_first;
   a.n_ch = n_ch;
   a.q_first = 0;
@@ -757,6 +763,154 @@ static tufrg_status compute_loops(tufrg_ctx *c, double lam, int deriv, int ch_fi
   TRY(compute_kval(c, lam, deriv));
   double *dst = c->d_loop + 2 * (size_t)ch_first * c->Nq * c->nD * c->no4;
   return loops_range(c, lam, deriv, ch_first, n_ch, 0, c->Nq, dst);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner of the loop kernels' launch shapes
+
+static void dfree(tufrg_ctx *c, void *p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+// kx chunks of the two-orbital loop kernel: whole chunks of ceil(Lf / n) rows,
+// none starting at or beyond Lf; the partial sums grow with the chunks
+static int normalized_kx_chunks(const tufrg_ctx *c, int n) {
+  n = std::max(1, std::min(n, c->Lf));
+  const int kxper = (c->Lf + n - 1) / n;
+  return (c->Lf + kxper - 1) / kxper;
+}
+
+static tufrg_status set_kx_chunks(tufrg_ctx *c, int n) {
+  const size_t need = 2 * 2 * (size_t)c->Nq * c->nkyb * n * c->ndx * (2 * c->ndy + 1) * c->no4;
+  if (need > c->partial_cap) {
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    dfree(c, c->d_partial);
+    c->d_partial = nullptr;
+    c->partial_cap = 0;
+    TRY(dalloc(c, &c->d_partial, need));
+    c->partial_cap = need;
+  }
+  c->nkxc = n;
+  return TUFRG_OK;
+}
+
+static std::string tune_key(const tufrg_ctx *c) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  int cus = 0;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) {
+    arch = prop.gcnArchName;
+    cus = prop.multiProcessorCount;
+  } else {
+    (void)hipGetLastError();
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s:%dcu|n_o=%d|prec=%d|scheme=%d|Lq=%d|n_ref=%d|n_ff=%d|nD=%d|ndx=%d|ndy=%d",
+                arch.c_str(), cus, c->n_o, c->prec, c->scheme, c->Lq, c->n_ref, c->n_ff, c->nD, c->ndx, c->ndy);
+  return buf;
+}
+
+// mean time of one evaluation of both loop channels at lam, after one
+// untimed evaluation; repeats until about 50 ms are timed (at most 20)
+static tufrg_status time_loops(tufrg_ctx *c, double lam, double *ms) {
+  struct Ev {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Ev() {
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
+    }
+  } ev;
+  HIPCHK(c, hipEventCreate(&ev.a));
+  HIPCHK(c, hipEventCreate(&ev.b));
+  HIPCHK(c, hipEventRecord(ev.a, c->st));
+  TRY(compute_loops(c, lam, 1, 0, 2));
+  HIPCHK(c, hipEventRecord(ev.b, c->st));
+  HIPCHK(c, hipEventSynchronize(ev.b));
+  float first = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&first, ev.a, ev.b));
+  const int reps = (int)std::max(2.0, std::min(20.0, std::ceil(50.0 / std::max(1e-3, (double)first))));
+  HIPCHK(c, hipEventRecord(ev.a, c->st));
+  for (int r = 0; r < reps; ++r) TRY(compute_loops(c, lam, 1, 0, 2));
+  HIPCHK(c, hipEventRecord(ev.b, c->st));
+  HIPCHK(c, hipEventSynchronize(ev.b));
+  float t = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&t, ev.a, ev.b));
+  *ms = (double)t / reps;
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_autotune(tufrg_ctx *c, double lambda, const char *cache_path, tufrg_tune_result *res) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!res) return fail(c, TUFRG_E_INVAL, "null result");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, TUFRG_E_INVAL, "lambda must be positive");
+  std::memset(res, 0, sizeof(*res));
+  const bool no2 = c->n_o == 2, mx = c->prec == TUFRG_BF16X3;
+  res->loop_kx_chunks = c->nkxc;
+  res->mfma_kx_rows = c->mfma_kxr;
+  if (!no2 && !mx) return TUFRG_OK;  // one workgroup per (q, channel): no launch shape to tune
+  res->tunable = 1;
+  const char *pname = no2 ? "loop_kx_chunks" : "mfma_kx_rows";
+  auto apply = [&](int v) -> tufrg_status {
+    if (no2) return set_kx_chunks(c, normalized_kx_chunks(c, v));
+    c->mfma_kxr = std::max(1, std::min(v, 8));
+    return TUFRG_OK;
+  };
+  const std::string key = tune_key(c);
+  TuneEntries cache;
+  if (cache_path) {
+    std::string err;
+    if (!tune_cache_read(cache_path, cache, err)) return fail(c, TUFRG_E_INVAL, err);
+    auto it = cache.find(key);
+    if (it != cache.end() && it->second.count(pname)) {
+      TRY(apply((int)std::llround(it->second.at(pname))));
+      res->from_cache = 1;
+      res->loop_kx_chunks = c->nkxc;
+      res->mfma_kx_rows = c->mfma_kxr;
+      res->loop_ms = it->second.count("loop_ms") ? it->second.at("loop_ms") : 0.0;
+      res->default_ms = it->second.count("default_ms") ? it->second.at("default_ms") : 0.0;
+      return TUFRG_OK;
+    }
+  }
+  // candidates around the default: the two-orbital kernel's kx chunking (the
+  // default balances filling the chip against the L2 share of a chunk), the
+  // matrix-core kernel's kx rows per work item
+  const int def = no2 ? c->nkxc : c->mfma_kxr;
+  std::vector<int> cand;
+  if (no2) {
+    for (int v : {def, def / 2, def * 2, def * 4, 1}) {
+      const int n = normalized_kx_chunks(c, std::max(1, std::min(v, std::max(1, c->Lf / 8))));
+      if (std::find(cand.begin(), cand.end(), n) == cand.end()) cand.push_back(n);
+    }
+  } else {
+    cand = {def, 1, 4};
+    if (def != 2) cand.push_back(2);
+  }
+  double best = INFINITY;
+  int best_v = def;
+  for (int v : cand) {
+    TRY(apply(v));
+    double ms = 0.0;
+    TRY(time_loops(c, lambda, &ms));
+    if (v == def) res->default_ms = ms;
+    if (ms < best) {
+      best = ms;
+      best_v = no2 ? c->nkxc : c->mfma_kxr;
+    }
+  }
+  TRY(apply(best_v));
+  res->n_candidates = (int32_t)cand.size();
+  res->loop_ms = best;
+  res->loop_kx_chunks = c->nkxc;
+  res->mfma_kx_rows = c->mfma_kxr;
+  if (cache_path) {
+    cache[key] = {{pname, (double)best_v}, {"loop_ms", best}, {"default_ms", res->default_ms}};
+    std::string err;
+    if (!tune_cache_write(cache_path, cache, err)) return fail(c, TUFRG_E_INVAL, err);
+  }
+  return TUFRG_OK;
 }
 
 // target scale s(Lambda): the table interpolated linearly in (ln Lambda, ln s),
@@ -1113,6 +1267,16 @@ extern "C" tufrg_status tufrg_project(tufrg_ctx *c, const tufrg_c64 *P, const tu
   if (!is_device_ptr(P) || !is_device_ptr(C) || !is_device_ptr(VP) || !is_device_ptr(VC))
     return fail(c, TUFRG_E_INVAL, "P, C, VP, VC must be device pointers");
   return project_internal(c, (const double *)P, (const double *)C, (double *)VP, (double *)VC);
+}
+
+extern "C" tufrg_status tufrg_channel_d(tufrg_ctx *c, const tufrg_c64 *C, tufrg_c64 *D) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!is_device_ptr(C) || !is_device_ptr(D)) return fail(c, TUFRG_E_INVAL, "C and D must be device pointers");
+  const size_t bytes = (size_t)c->Nq * c->B * c->B * sizeof(tufrg_c64);
+  const uintptr_t c0 = (uintptr_t)C, d0 = (uintptr_t)D;
+  if (d0 < c0 + bytes && c0 < d0 + bytes) return fail(c, TUFRG_E_INVAL, "D must not overlap C");
+  HIPCHK(c, launch_channel_d(c->n_o, c->B, c->Nq, (const double *)C, (double *)D, c->st));
+  return TUFRG_OK;
 }
 
 extern "C" tufrg_status tufrg_project_static(tufrg_ctx *c, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,

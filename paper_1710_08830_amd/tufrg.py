@@ -41,8 +41,14 @@ SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "t
            "tufrg_sur_loops", "tufrg_batch_create", "tufrg_batch_destroy", "tufrg_batch_last_error",
            "tufrg_batch_dims", "tufrg_batch_flow", "tufrg_set_initial_c", "tufrg_basis_matrix",
            "tufrg_basis_apply", "tufrg_set_initial_p", "tufrg_ff_symmetrize", "tufrg_ff_apply",
-           "tufrg_project_static"]
+           "tufrg_project_static", "tufrg_channel_d", "tufrg_autotune"]
 TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE, TIMER_SURROGATE = 0, 1, 2, 3
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("tunable", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("loop_kx_chunks", ctypes.c_int32),
+                ("mfma_kx_rows", ctypes.c_int32), ("n_candidates", ctypes.c_int32), ("loop_ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double)]
 
 
 class c64(ctypes.Structure):
@@ -98,6 +104,8 @@ _lib.tufrg_band_data.argtypes = [_vp, _vp, _vp]
 _lib.tufrg_bubble.argtypes = [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _vp]
 _lib.tufrg_project.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.tufrg_project_static.argtypes = [_vp, _vp, _vp, _vp, _vp]
+_lib.tufrg_channel_d.argtypes = [_vp, _vp, _vp]
+_lib.tufrg_autotune.argtypes = [_vp, ctypes.c_double, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
 _lib.tufrg_basis_matrix.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
 _lib.tufrg_basis_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
 _lib.tufrg_ff_symmetrize.argtypes = [ctypes.c_int32, _vp, _vp, _vp]
@@ -274,6 +282,21 @@ def tufrg_project(ctx, P, C, VP, VC):
     """Projected vertices VP, VC [Nq][B][B] of the state P, C, all on the device."""
     _check(_lib.tufrg_project(ctx.handle, _state(ctx, P, "P"), _state(ctx, C, "C"), _state(ctx, VP, "VP"),
                               _state(ctx, VC, "VC")), ctx.handle)
+
+
+def tufrg_autotune(ctx, lam, cache_path=None):
+    """Time the loop kernels' candidate launch shapes at scale lam and keep the
+    fastest (or take it from the JSON cache file); returns the result fields."""
+    r = TuneResult()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(_lib.tufrg_autotune(ctx.handle, float(lam), path, ctypes.byref(r)), ctx.handle)
+    return {k: getattr(r, k) for k, _ in TuneResult._fields_}
+
+
+def tufrg_channel_d(ctx, C, D):
+    """The third channel D [Nq][B][B] (layout of C) of the state C, on the
+    device: D_{n1n2n3n4} = -C_{n1n2n4n3}."""
+    _check(_lib.tufrg_channel_d(ctx.handle, _state(ctx, C, "C"), _state(ctx, D, "D")), ctx.handle)
 
 
 def tufrg_project_static(ctx, P, C, VP, VC):

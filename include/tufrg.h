@@ -129,7 +129,9 @@ typedef enum { TUFRG_FP64 = 0, TUFRG_FP32 = 1, TUFRG_BF16X3 = 2 } tufrg_precisio
 typedef enum { TUFRG_PP = 0, TUFRG_PH = 1 } tufrg_channel;
 
 typedef struct {
-  int32_t n_orb;           /* spin-orbitals n_o: 2 or 6 */
+  int32_t n_orb;           /* spin-orbitals n_o: 2 or 6; or 1: one orbital per site with spin-rotation
+                              invariance, for the SU(2)-reduced calls (tufrg_su2_rhs, tufrg_su2_flow;
+                              V0 is then the onsite coefficient v of d13 d24 - d14 d23) */
   int32_t n_hop;           /* hopping vectors */
   const int32_t *hop_R;    /* [n_hop][2] lattice vectors R */
   const tufrg_c64 *hop_t;  /* [n_hop][n_o][n_o]: H(k) = sum_R t(R) e^{i k.R}; t(-R) = t(R)^dagger */
@@ -369,6 +371,38 @@ typedef struct {
 /* Integrates P, C [Nq][B][B] (device, in place) from opts->lambda0. */
 tufrg_status tufrg_flow(tufrg_ctx *ctx, const tufrg_flow_opts *opts, tufrg_c64 *P, tufrg_c64 *C,
                         tufrg_flow_result *result);
+
+/* SU(2)-reduced flow of one orbital per site (Sec. 1 and Sec. 6: the
+ * spin-rotation-invariant TU-fRG that the method generalises; Sec. 2 channel
+ * definitions, Sec. 3.1 matrix RGE, Sec. 3.3 projections).  With spin
+ * indices s the spinful propagators are P = p d13 d24 - p^x d14 d23,
+ * p^x^{RR'}(s) = e^{is.R'} p^{R,-R'}(s), and C = c d13 d24 - d d14 d23, so the
+ * state is three complex arrays p, c, d [Nq][n_ff][n_ff] (B = n_ff, the
+ * spinful B / 4), element [q][R][R'].  The reduced equations (cited, not
+ * printed, in the paper; re-derived and pinned against the spinful ones):
+ *   dp = -(a~ Lpp a~x + a~x Lpp a~),
+ *   dc = 2 (2 c~ Lph c~ - c~ Lph d~ - d~ Lph c~),   dd = -2 d~ Lph d~,
+ * a~ = p + v + PC(c) + PD(d), c~ = c + v + CP(p) + CD(d), d~ = d + v + CP(p^x)
+ * + CD(c) with the cross projections (i)-(iv) of one orbital and v the onsite
+ * coefficient (V0[0] of the model), Lpp, Lph the one-band loops.
+ * The context must have n_orb = 1, precision TUFRG_FP64, the temperature or
+ * Omega cutoff and the orbital basis (else tufrg_create returns
+ * E_UNSUPPORTED); such a context serves tufrg_bubble, tufrg_loops_compact,
+ * tufrg_band_data and these calls, and returns E_UNSUPPORTED from the spinful
+ * state calls.  All arrays are device memory owned by the caller; the calls
+ * run on the context's stream.  Errors: E_INVAL (host pointer, lambda <= 0),
+ * E_UNSUPPORTED (a spinful context), E_NOMEM, E_HIP. */
+tufrg_status tufrg_su2_rhs(tufrg_ctx *ctx, double lambda, const tufrg_c64 *p, const tufrg_c64 *c, const tufrg_c64 *d,
+                           tufrg_c64 *dp, tufrg_c64 *dc, tufrg_c64 *dd);
+
+/* Euler flow of the reduced state p, c, d (device, in place) on the grid of
+ * tufrg_flow (opts->n_steps >= 1; lambda0, lambda_end, v_max, max_steps,
+ * on_step as there; surrogate, graph_steps > 1 and channel masks other than 3
+ * return E_UNSUPPORTED).  The stop test and max_coupling use
+ * max(|p|, |c|, |d|), which is max(|P|, |C|) of the spinful state.
+ * Synchronises once per step; E_NONFINITE on NaN/Inf. */
+tufrg_status tufrg_su2_flow(tufrg_ctx *ctx, const tufrg_flow_opts *opts, tufrg_c64 *p, tufrg_c64 *c, tufrg_c64 *d,
+                            tufrg_flow_result *res);
 
 /* Optional per-kernel timing with HIP events recorded on the context stream
  * around the launches of one part of the right-hand side:

@@ -301,17 +301,17 @@ __global__ __launch_bounds__(256) void assemble_cols_kernel(int BB, int Lq, int 
 
 hipError_t launch_assemble(const ProjArgs &a, const double *P, const double *C, const double *G,
                            const double *v0p, const double *v0c, double *VP, double *VC, double *ws,
-                           size_t ws_doubles, hipStream_t st) {
+                           size_t ws_doubles, hipStream_t st, int nw) {
   const int BB = a.B * a.B;
-  if (a.ny < 1 || a.ny > NYMAX || a.Nq != a.Lq * a.Lq) return hipErrorInvalidValue;
+  if (a.ny < 1 || a.ny > NYMAX || a.Nq != a.Lq * a.Lq || nw < 1 || nw > 2) return hipErrorInvalidValue;
   if (ws_doubles < 2 * 2 * (size_t)a.ny * BB) return hipErrorInvalidValue;
   const int R = proj_rows_per_pass(a, ws_doubles, RMAX);
   const size_t lds = sizeof(double2) * (size_t)a.Lq * a.ny;
   for (int x0 = 0; x0 < a.Lq; x0 += R) {
     const int nr = std::min(R, a.Lq - x0);
-    hipLaunchKernelGGL(assemble_rows_kernel, dim3((BB + 255) / 256, a.ny, 2), dim3(256), 0, st, BB, a.Lq, a.nD, a.ny,
-                       x0, nr, a.twq, a.dtab, G, ws);
-    hipLaunchKernelGGL(assemble_cols_kernel, dim3((BB + 255) / 256, 2, nr), dim3(256), lds, st, BB, a.Lq, a.ny, x0,
+    hipLaunchKernelGGL(assemble_rows_kernel, dim3((BB + 255) / 256, a.ny, nw), dim3(256), 0, st, BB, a.Lq, a.nD,
+                       a.ny, x0, nr, a.twq, a.dtab, G, ws);
+    hipLaunchKernelGGL(assemble_cols_kernel, dim3((BB + 255) / 256, nw, nr), dim3(256), lds, st, BB, a.Lq, a.ny, x0,
                        a.phy, P, C, ws, v0p, v0c, VP, VC);
   }
   return hipGetLastError();

@@ -87,9 +87,10 @@ hipError_t launch_ft(const ProjArgs &a, const double *P, const double *C, double
 hipError_t launch_gather(const ProjArgs &a, const double *real, double *G, hipStream_t st);
 // D [Nq][B][B] (layout of C) from C: D_{n1n2n3n4} = -C_{n1n2n4n3}
 hipError_t launch_channel_d(int n_o, int B, int Nq, const double *C, double *D, hipStream_t st);
+// nw = 1: only VP from P and G[0]
 hipError_t launch_assemble(const ProjArgs &a, const double *P, const double *C, const double *G,
                            const double *v0p, const double *v0c, double *VP, double *VC, double *ws,
-                           size_t ws_doubles, hipStream_t st);
+                           size_t ws_doubles, hipStream_t st, int nw = 2);
 
 // a6: bundle products  out = f * V L V  per q, L expanded from compact form;
 // bundles larger than 64 need a workspace tmp of n_q * B * B complex
@@ -102,6 +103,20 @@ size_t bundle_split_bytes_per_q(int B);
 hipError_t launch_bundle_bf16x3(int n_o, int n_ff, int B, int nD, int n_q, const int *didx, const double *V,
                                 const double *Lc, double factor, double *out, void *ws, size_t ws_bytes,
                                 hipStream_t st);
+
+// SU(2)-reduced flow of one orbital (k_su2.hip): one-band loops into compact
+// [n_ch][n_q][nD] complex; X -> X^x; the gathers G[3][nD][B][B] of a~, c~, d~
+// from rA = (p, c)(rho), rB = (p^x, d)(rho); the reduced products per q (B <= 25)
+hipError_t launch_loop1(int Lq, int n_ref, int nD, const int *dlist, const double *e, const double *kv,
+                        const double *tw, double lam, int scheme, int deriv, int ch_first, int n_ch, int q_first,
+                        int n_q, double *out, hipStream_t st);
+hipError_t launch_su2_exch(int n_ff, int Nq, int Lq, const int *ff, const int *fneg, const double *twq,
+                           const double *X, double *Xx, hipStream_t st);
+hipError_t launch_su2_gather(int B, int nD, const int *ff, const int *dlist, const int *ffgrid, const int *dgrid,
+                             const double *rA, const double *rB, double *G, hipStream_t st);
+hipError_t launch_su2_bundle(int B, int Nq, int nD, const int *didx, const double *Lc, const double *Va,
+                             const double *Vax, const double *Vc, const double *Vd, double f, double *dp, double *dc,
+                             double *dd, hipStream_t st);
 
 // orbital <-> band basis (k_basis.hip): compact basis matrix [Nq][nD][n_o^4] of one
 // channel (0: pp, U matrix; 1: ph, X matrix) from U[Nf][n_o][n_o] (orbital rows, band

@@ -74,6 +74,11 @@ struct tufrg_ctx {
   double *d_pphy = nullptr;
   int *d_dtab = nullptr;
   int ny = 0;
+  // SU(2)-reduced flows (one orbital): index of -R per form factor, and the
+  // workspaces (p^x, rho-space coefficients, gathers, d~ and a~^x, the d update)
+  int *d_fneg = nullptr;
+  double *d_s_px = nullptr, *d_s_rA = nullptr, *d_s_rB = nullptr, *d_s_G3 = nullptr, *d_s_Vd = nullptr,
+         *d_s_Vax = nullptr, *d_s_dd = nullptr;
   float *d_twf32 = nullptr;
   double *d_partial = nullptr;
   double *d_loop = nullptr;
@@ -247,8 +252,9 @@ extern "C" const char *tufrg_last_error(const tufrg_ctx *ctx) { return ctx ? ctx
 extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s, void *stream, tufrg_ctx **out) {
   if (!m || !s || !out) return fail(nullptr, TUFRG_E_INVAL, "null argument");
   *out = nullptr;
-  if (m->n_orb != 2 && m->n_orb != 6)
-    return fail(nullptr, TUFRG_E_UNSUPPORTED, "the library supports n_orb = 2 or 6 spin-orbitals");
+  if (m->n_orb != 1 && m->n_orb != 2 && m->n_orb != 6)
+    return fail(nullptr, TUFRG_E_UNSUPPORTED,
+                "the library supports n_orb = 2 or 6 spin-orbitals, or 1 orbital (SU(2)-reduced flows)");
   if (m->n_hop < 1 || !m->hop_R || !m->hop_t || !m->V0) return fail(nullptr, TUFRG_E_INVAL, "empty model");
   if (s->n_ff < 1 || !s->ff_R) return fail(nullptr, TUFRG_E_INVAL, "empty form-factor set");
   if (s->ff_R[0] != 0 || s->ff_R[1] != 0) return fail(nullptr, TUFRG_E_INVAL, "ff_R[0] must be (0,0)");
@@ -264,6 +270,9 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     return fail(nullptr, TUFRG_E_INVAL, "mesh sizes out of range");
   if (s->basis != TUFRG_BASIS_ORBITAL && s->basis != TUFRG_BASIS_BAND)
     return fail(nullptr, TUFRG_E_INVAL, "unknown single-particle basis");
+  if (m->n_orb == 1 && (s->precision != TUFRG_FP64 || s->cutoff == TUFRG_CUT_SHELL || s->basis != TUFRG_BASIS_ORBITAL))
+    return fail(nullptr, TUFRG_E_UNSUPPORTED,
+                "the SU(2)-reduced path runs FP64 with the temperature or Omega cutoff in the orbital basis");
   int rmax = 0;
   std::vector<std::pair<int, int>> ffv;
   for (int i = 0; i < s->n_ff; ++i) {
@@ -343,6 +352,10 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     // chunks of kxper rows each; drop chunks that would start at or beyond Lf
     const int kxper = (c->Lf + c->nkxc - 1) / c->nkxc;
     c->nkxc = (c->Lf + kxper - 1) / kxper;
+  } else if (c->n_o == 1) {
+    // the one-band loop kernel sums every k of a (q, channel) in one workgroup
+    c->nkyb = 1;
+    c->nkxc = 1;
   } else {
     // the multi-orbital loop kernel sums every k of a (q, channel) in one workgroup
     c->nkyb = 1;
@@ -413,6 +426,7 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
 
   const size_t Nf = c->Nf, BB = (size_t)c->B * c->B;
   CTRY(dalloc(c, &c->d_ff, c->ff.size()));
+  CTRY(dalloc(c, &c->d_fneg, c->n_ff));
   CTRY(dalloc(c, &c->d_dlist, c->dlist.size()));
   CTRY(dalloc(c, &c->d_didx, c->didx.size()));
   CTRY(dalloc(c, &c->d_ffgrid, c->ffgrid.size()));
@@ -572,6 +586,11 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     CHIP(hipMemcpyAsync(c->d_phy64, phy64.data(), phy64.size() * sizeof(double), hipMemcpyHostToDevice, st));
     CHIP(hipMemcpyAsync(c->d_phy32, phy32.data(), phy32.size() * sizeof(float), hipMemcpyHostToDevice, st));
   }
+  std::vector<int> fneg(c->n_ff, 0);
+  for (int i = 0; i < c->n_ff; ++i)
+    for (int j = 0; j < c->n_ff; ++j)
+      if (c->ff[2 * j] == -c->ff[2 * i] && c->ff[2 * j + 1] == -c->ff[2 * i + 1]) fneg[i] = j;
+  CHIP(hipMemcpyAsync(c->d_fneg, fneg.data(), fneg.size() * sizeof(int), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_v0p, v0p.data(), v0p.size() * sizeof(double), hipMemcpyHostToDevice, st));
   CHIP(hipMemcpyAsync(c->d_v0c, v0c.data(), v0c.size() * sizeof(double), hipMemcpyHostToDevice, st));
   CHIP(launch_band(c->n_o, c->Lf, m->n_hop, c->d_hopR, c->d_hopt, m->mu, s->basis == TUFRG_BASIS_BAND ? 1 : 0,
@@ -747,6 +766,14 @@ static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch
 static tufrg_status loops_range(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch, int q_first, int n_q,
                                 double *dst, const int *rows = nullptr) {
   if (c->prec == TUFRG_BF16X3) return loops_range_mfma(c, lam, deriv, ch_first, n_ch, q_first, n_q, dst, rows);
+  if (c->n_o == 1) {
+    if (rows) return fail(c, TUFRG_E_UNSUPPORTED, "sampled q rows need two or six spin-orbitals");
+    HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
+    HIPCHK(c, launch_loop1(c->Lq, c->n_ref, c->nD, c->d_dlist, c->d_band64, c->d_kv64, c->d_twf, lam, c->scheme,
+                           deriv, ch_first, n_ch, q_first, n_q, dst, c->st));
+    HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
+    return TUFRG_OK;
+  }
   LoopArgs a = loop_args(c, lam, deriv, ch_first, n_ch);
   a.q_first = q_first;
   a.n_q = n_q;
@@ -1131,6 +1158,7 @@ extern "C" tufrg_status tufrg_bubble(tufrg_ctx *c, int32_t channel, double lambd
 
 extern "C" tufrg_status tufrg_basis_matrix(tufrg_ctx *c, int32_t channel, const tufrg_c64 *U, tufrg_c64 *M) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (channel != TUFRG_PP && channel != TUFRG_PH) return fail(c, TUFRG_E_INVAL, "channel must be PP or PH");
   if (!is_device_ptr(U) || !is_device_ptr(M)) return fail(c, TUFRG_E_INVAL, "U and M must be device pointers");
   // compact form [Nq][nD][n_o^4], then expanded like the loops; the row sums of
@@ -1152,6 +1180,7 @@ extern "C" tufrg_status tufrg_basis_matrix(tufrg_ctx *c, int32_t channel, const 
 extern "C" tufrg_status tufrg_basis_apply(tufrg_ctx *c, const tufrg_c64 *M, const tufrg_c64 *X, tufrg_c64 *Y,
                                           int32_t to_orbital) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (!is_device_ptr(M) || !is_device_ptr(X) || !is_device_ptr(Y))
     return fail(c, TUFRG_E_INVAL, "M, X and Y must be device pointers");
   const size_t n = (size_t)c->Nq * c->B * c->B;
@@ -1264,6 +1293,7 @@ extern "C" tufrg_status tufrg_ff_apply(tufrg_ctx *c, const tufrg_c64 *W, const t
 extern "C" tufrg_status tufrg_project(tufrg_ctx *c, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,
                                       tufrg_c64 *VC) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (!is_device_ptr(P) || !is_device_ptr(C) || !is_device_ptr(VP) || !is_device_ptr(VC))
     return fail(c, TUFRG_E_INVAL, "P, C, VP, VC must be device pointers");
   return project_internal(c, (const double *)P, (const double *)C, (double *)VP, (double *)VC);
@@ -1271,6 +1301,7 @@ extern "C" tufrg_status tufrg_project(tufrg_ctx *c, const tufrg_c64 *P, const tu
 
 extern "C" tufrg_status tufrg_channel_d(tufrg_ctx *c, const tufrg_c64 *C, tufrg_c64 *D) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (!is_device_ptr(C) || !is_device_ptr(D)) return fail(c, TUFRG_E_INVAL, "C and D must be device pointers");
   const size_t bytes = (size_t)c->Nq * c->B * c->B * sizeof(tufrg_c64);
   const uintptr_t c0 = (uintptr_t)C, d0 = (uintptr_t)D;
@@ -1282,6 +1313,7 @@ extern "C" tufrg_status tufrg_channel_d(tufrg_ctx *c, const tufrg_c64 *C, tufrg_
 extern "C" tufrg_status tufrg_project_static(tufrg_ctx *c, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *VP,
                                              tufrg_c64 *VC) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (!is_device_ptr(P) || !is_device_ptr(C) || !is_device_ptr(VP) || !is_device_ptr(VC))
     return fail(c, TUFRG_E_INVAL, "P, C, VP, VC must be device pointers");
   int dev = -1;
@@ -1304,6 +1336,7 @@ extern "C" tufrg_status tufrg_project_static(tufrg_ctx *c, const tufrg_c64 *P, c
 
 extern "C" tufrg_status tufrg_set_initial_c(tufrg_ctx *c, const tufrg_c64 *C0) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (!C0) {
     c->has_c0 = false;
     return TUFRG_OK;
@@ -1319,6 +1352,7 @@ extern "C" tufrg_status tufrg_set_initial_c(tufrg_ctx *c, const tufrg_c64 *C0) {
 
 extern "C" tufrg_status tufrg_set_initial_p(tufrg_ctx *c, const tufrg_c64 *P0) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (!P0) {
     c->has_p0 = false;
     return TUFRG_OK;
@@ -1335,6 +1369,7 @@ extern "C" tufrg_status tufrg_set_initial_p(tufrg_ctx *c, const tufrg_c64 *P0) {
 extern "C" tufrg_status tufrg_rhs(tufrg_ctx *c, double lambda, const tufrg_c64 *P, const tufrg_c64 *C, tufrg_c64 *dP,
                                   tufrg_c64 *dC) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, TUFRG_E_INVAL, "lambda must be positive");
   if (!is_device_ptr(P) || !is_device_ptr(C) || !is_device_ptr(dP) || !is_device_ptr(dC))
     return fail(c, TUFRG_E_INVAL, "P, C, dP, dC must be device pointers");
@@ -1367,6 +1402,7 @@ static tufrg_status check_blocks(tufrg_ctx *c, int64_t n, const int32_t *q, cons
 extern "C" tufrg_status tufrg_sur_features(tufrg_ctx *c, int64_t n, const int32_t *q, const int32_t *ch,
                                           const int32_t *iD, double lambda, float *X) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   TRY(check_blocks(c, n, q, ch, iD));
   if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, TUFRG_E_INVAL, "lambda must be positive");
   if (n > 0 && !is_device_ptr(X)) return fail(c, TUFRG_E_INVAL, "X must be a device pointer");
@@ -1378,6 +1414,7 @@ extern "C" tufrg_status tufrg_sur_targets(tufrg_ctx *c, int64_t n, const int32_t
                                          const int32_t *iD, double scale, const tufrg_c64 *Lc, float *T,
                                          double *max_abs) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   TRY(check_blocks(c, n, q, ch, iD));
   if (!(scale > 0.0) || !std::isfinite(scale)) return fail(c, TUFRG_E_INVAL, "scale must be positive");
   if (n > 0 && (!is_device_ptr(Lc) || !is_device_ptr(T))) return fail(c, TUFRG_E_INVAL, "Lc, T must be device pointers");
@@ -1398,6 +1435,7 @@ extern "C" tufrg_status tufrg_sur_targets(tufrg_ctx *c, int64_t n, const int32_t
 extern "C" tufrg_status tufrg_sur_attach(tufrg_ctx *c, tufrg_mlp *net, int32_t n_scale, const double *lam_tab,
                                         const double *scale_tab) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (!net) {
     c->sur = nullptr;
     return TUFRG_OK;
@@ -1427,6 +1465,7 @@ extern "C" tufrg_status tufrg_sur_attach(tufrg_ctx *c, tufrg_mlp *net, int32_t n
 
 extern "C" tufrg_status tufrg_sur_loops(tufrg_ctx *c, double lambda, tufrg_c64 *Lc) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (!c->sur) return fail(c, TUFRG_E_INVAL, "no network attached");
   if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, TUFRG_E_INVAL, "lambda must be positive");
   if (!is_device_ptr(Lc)) return fail(c, TUFRG_E_INVAL, "Lc must be a device pointer");
@@ -1594,6 +1633,7 @@ static const double DP_B4[7] = {5179.0 / 57600, 0.0, 7571.0 / 16695, 393.0 / 640
 extern "C" tufrg_status tufrg_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg_c64 *Pu, tufrg_c64 *Cu,
                                    tufrg_flow_result *res) {
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (c->n_o == 1) return fail(c, TUFRG_E_UNSUPPORTED, "one-orbital contexts run the SU(2)-reduced calls");
   if (!o || !res) return fail(c, TUFRG_E_INVAL, "null options or result");
   if (!is_device_ptr(Pu) || !is_device_ptr(Cu)) return fail(c, TUFRG_E_INVAL, "P, C must be device pointers");
   if (!(o->lambda0 > 0.0) || !(o->lambda_end > 0.0) || !(o->lambda_end < o->lambda0))
@@ -1778,6 +1818,124 @@ extern "C" tufrg_status tufrg_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg
 }
 
 // ---------------------------------------------------------------------------
+// SU(2)-reduced flows (one orbital per site)
+
+static tufrg_status su2_prepare(tufrg_ctx *c) {
+  const size_t BB = (size_t)c->B * c->B, st = 2 * BB * c->Nq, rs = 2 * 2 * (size_t)c->nD * BB;
+  if (!c->d_s_px) TRY(dalloc(c, &c->d_s_px, st));
+  if (!c->d_s_rA) TRY(dalloc(c, &c->d_s_rA, rs));
+  if (!c->d_s_rB) TRY(dalloc(c, &c->d_s_rB, rs));
+  if (!c->d_s_G3) TRY(dalloc(c, &c->d_s_G3, 2 * 3 * (size_t)c->nD * BB));
+  if (!c->d_s_Vd) TRY(dalloc(c, &c->d_s_Vd, st));
+  if (!c->d_s_Vax) TRY(dalloc(c, &c->d_s_Vax, st));
+  return TUFRG_OK;
+}
+
+// (dp, dc, dd) of the reduced state (p, c, d) at scale lam: one-band loops,
+// the reduced projected vertices a~, c~, d~ (the q -> rho transforms of p, c,
+// p^x and d, the gathers, the assembly with the onsite v), a~^x, the products
+static tufrg_status su2_rhs_internal(tufrg_ctx *c, double lam, const double *p, const double *cc, const double *d,
+                                     double *dp, double *dc, double *dd) {
+  TRY(su2_prepare(c));
+  TRY(compute_loops(c, lam, 1, 0, 2));
+  ProjArgs a = proj_args(c);
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_PROJECT));
+  HIPCHK(c, launch_su2_exch(c->n_ff, c->Nq, c->Lq, c->d_ff, c->d_fneg, c->d_twq, p, c->d_s_px, c->st));
+  HIPCHK(c, launch_ft(a, p, cc, c->d_ftpart, c->proj_ws, c->d_s_rA, c->st));
+  HIPCHK(c, launch_ft(a, c->d_s_px, d, c->d_ftpart, c->proj_ws, c->d_s_rB, c->st));
+  HIPCHK(c, launch_su2_gather(c->B, c->nD, c->d_ff, c->d_dlist, c->d_ffgrid, c->d_dgrid, c->d_s_rA, c->d_s_rB,
+                              c->d_s_G3, c->st));
+  // a~ and c~ from (p, c) with the gathers 0, 1; d~ from d with gather 2 (v in every (0,0) entry)
+  HIPCHK(c, launch_assemble(a, p, cc, c->d_s_G3, c->d_v0p, c->d_v0c, c->d_VP, c->d_VC, c->d_ftpart, c->proj_ws,
+                            c->st));
+  HIPCHK(c, launch_assemble(a, d, d, c->d_s_G3 + 2 * 2 * (size_t)c->nD * c->B * c->B, c->d_v0p, c->d_v0p,
+                            c->d_s_Vd, nullptr, c->d_ftpart, c->proj_ws, c->st, 1));
+  HIPCHK(c, launch_su2_exch(c->n_ff, c->Nq, c->Lq, c->d_ff, c->d_fneg, c->d_twq, c->d_VP, c->d_s_Vax, c->st));
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_PROJECT));
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_BUNDLE));
+  HIPCHK(c, launch_su2_bundle(c->B, c->Nq, c->nD, c->d_didx, c->d_loop, c->d_VP, c->d_s_Vax, c->d_VC, c->d_s_Vd, 1.0,
+                              dp, dc, dd, c->st));
+  HIPCHK(c, timer_mark(c, TUFRG_TIMER_BUNDLE));
+  return TUFRG_OK;
+}
+
+static tufrg_status su2_state_check(tufrg_ctx *c, const void *const *arrs, int n) {
+  if (c->n_o != 1) return fail(c, TUFRG_E_UNSUPPORTED, "the SU(2)-reduced calls need a one-orbital context");
+  for (int i = 0; i < n; ++i)
+    if (!is_device_ptr(arrs[i])) return fail(c, TUFRG_E_INVAL, "every state array must be device memory");
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_su2_rhs(tufrg_ctx *c, double lambda, const tufrg_c64 *p, const tufrg_c64 *cc,
+                                      const tufrg_c64 *d, tufrg_c64 *dp, tufrg_c64 *dc, tufrg_c64 *dd) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!(lambda > 0.0) || !std::isfinite(lambda)) return fail(c, TUFRG_E_INVAL, "lambda must be positive");
+  const void *arrs[6] = {p, cc, d, dp, dc, dd};
+  TRY(su2_state_check(c, arrs, 6));
+  return su2_rhs_internal(c, lambda, (const double *)p, (const double *)cc, (const double *)d, (double *)dp,
+                          (double *)dc, (double *)dd);
+}
+
+extern "C" tufrg_status tufrg_su2_flow(tufrg_ctx *c, const tufrg_flow_opts *o, tufrg_c64 *pu, tufrg_c64 *cu,
+                                       tufrg_c64 *du, tufrg_flow_result *res) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (!o || !res) return fail(c, TUFRG_E_INVAL, "null options or result");
+  const void *arrs[3] = {pu, cu, du};
+  TRY(su2_state_check(c, arrs, 3));
+  if (!(o->lambda0 > 0.0) || !(o->lambda_end > 0.0) || !(o->lambda_end < o->lambda0))
+    return fail(c, TUFRG_E_INVAL, "need lambda0 > lambda_end > 0");
+  if (o->n_steps < 1) return fail(c, TUFRG_E_UNSUPPORTED, "the SU(2)-reduced flow takes Euler steps (n_steps >= 1)");
+  if (o->surrogate || (o->channel_mask & 3u) != 3u || o->graph_steps > 1)
+    return fail(c, TUFRG_E_UNSUPPORTED, "the SU(2)-reduced flow runs plain loops, all channels, no graphs");
+  double *p = (double *)pu, *cc = (double *)cu, *d = (double *)du;
+  const long long ncx = (long long)c->Nq * c->B * c->B;
+  std::memset(res, 0, sizeof(*res));
+  res->lambda_stop = o->lambda_end;
+  if (!c->d_dP) {
+    TRY(dalloc(c, &c->d_dP, 2 * (size_t)ncx));
+    TRY(dalloc(c, &c->d_dC, 2 * (size_t)ncx));
+  }
+  if (!c->d_s_dd) TRY(dalloc(c, &c->d_s_dd, 2 * (size_t)ncx));
+  auto maxof = [&](double h, const double *dx1, const double *dx2, const double *dx3, double *m, bool *bad) {
+    HIPCHK(c, launch_clear_reduce(c->d_bits, c->d_flag, c->st));
+    HIPCHK(c, launch_axpy_max(ncx, p, h, dx1, dx1 ? p : nullptr, c->d_bits, c->d_flag, c->st));
+    HIPCHK(c, launch_axpy_max(ncx, cc, h, dx2, dx2 ? cc : nullptr, c->d_bits, c->d_flag, c->st));
+    HIPCHK(c, launch_axpy_max(ncx, d, h, dx3, dx3 ? d : nullptr, c->d_bits, c->d_flag, c->st));
+    return read_reduce(c, m, bad);
+  };
+  double m_prev = 0.0;
+  bool bad = false;
+  TRY(maxof(0.0, nullptr, nullptr, nullptr, &m_prev, &bad));
+  if (bad) return fail(c, TUFRG_E_NONFINITE, "non-finite initial state");
+  double lam_prev = o->lambda0;
+  for (int i = 0; i < o->n_steps; ++i) {
+    const double l0 = euler_lambda(o, i), l1 = euler_lambda(o, i + 1);
+    TRY(su2_rhs_internal(c, l0, p, cc, d, c->d_dP, c->d_dC, c->d_s_dd));
+    res->n_rhs++;
+    res->n_plain++;
+    double mx;
+    TRY(maxof(l1 - l0, c->d_dP, c->d_dC, c->d_s_dd, &mx, &bad));
+    if (bad) return fail(c, TUFRG_E_NONFINITE, "non-finite state after Euler step " + std::to_string(i));
+    res->n_steps++;
+    res->lambda_stop = l1;
+    res->max_coupling = mx;
+    if (mx > o->v_max) {
+      res->diverged = 1;
+      res->lambda_c = lambda_c_interp(lam_prev, m_prev, l1, mx, o->v_max);
+      break;
+    }
+    if (o->on_step && o->on_step(o->user, i, l1, mx)) {
+      res->stopped_by_callback = 1;
+      break;
+    }
+    if (o->max_steps > 0 && res->n_steps >= o->max_steps) break;
+    lam_prev = l1;
+    m_prev = mx;
+  }
+  return TUFRG_OK;
+}
+
+// ---------------------------------------------------------------------------
 // batches of independent instances (lockstep Euler)
 
 struct tufrg_batch {
@@ -1820,6 +1978,9 @@ extern "C" tufrg_status tufrg_batch_create(int32_t n_inst, const tufrg_model *mo
   *out = nullptr;
   if (n_inst < 1 || !models || !setups) return bfail(nullptr, TUFRG_E_INVAL, "need n_inst >= 1 models and setups");
   if (n_streams < 1 || n_streams > 8) return bfail(nullptr, TUFRG_E_INVAL, "n_streams must be in [1, 8]");
+  for (int i = 0; i < n_inst; ++i)
+    if (models[i].n_orb == 1)
+      return bfail(nullptr, TUFRG_E_UNSUPPORTED, "batches run spinful instances (n_orb = 2 or 6)");
   tufrg_batch *b = new tufrg_batch();
   for (int i = 0; i < std::min(n_streams, n_inst); ++i) {
     hipStream_t s;

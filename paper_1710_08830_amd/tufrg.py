@@ -41,7 +41,7 @@ SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "t
            "tufrg_sur_loops", "tufrg_batch_create", "tufrg_batch_destroy", "tufrg_batch_last_error",
            "tufrg_batch_dims", "tufrg_batch_flow", "tufrg_set_initial_c", "tufrg_basis_matrix",
            "tufrg_basis_apply", "tufrg_set_initial_p", "tufrg_ff_symmetrize", "tufrg_ff_apply",
-           "tufrg_project_static", "tufrg_channel_d", "tufrg_autotune"]
+           "tufrg_project_static", "tufrg_channel_d", "tufrg_autotune", "tufrg_su2_rhs", "tufrg_su2_flow"]
 TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE, TIMER_SURROGATE = 0, 1, 2, 3
 
 
@@ -105,6 +105,7 @@ _lib.tufrg_bubble.argtypes = [_vp, ctypes.c_int32, ctypes.c_double, ctypes.c_int
 _lib.tufrg_project.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.tufrg_project_static.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.tufrg_channel_d.argtypes = [_vp, _vp, _vp]
+_lib.tufrg_su2_rhs.argtypes = [_vp, ctypes.c_double] + [_vp] * 6
 _lib.tufrg_autotune.argtypes = [_vp, ctypes.c_double, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
 _lib.tufrg_basis_matrix.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
 _lib.tufrg_basis_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
@@ -112,6 +113,7 @@ _lib.tufrg_ff_symmetrize.argtypes = [ctypes.c_int32, _vp, _vp, _vp]
 _lib.tufrg_ff_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
 _lib.tufrg_rhs.argtypes = [_vp, ctypes.c_double, _vp, _vp, _vp, _vp]
 _lib.tufrg_flow.argtypes = [_vp, ctypes.POINTER(FlowOpts), _vp, _vp, ctypes.POINTER(FlowResult)]
+_lib.tufrg_su2_flow.argtypes = [_vp, ctypes.POINTER(FlowOpts), _vp, _vp, _vp, ctypes.POINTER(FlowResult)]
 _lib.tufrg_timing.argtypes = [_vp, ctypes.c_int32]
 _lib.tufrg_timing_read.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_int32)]
@@ -371,6 +373,25 @@ def tufrg_flow(ctx, P, C, lambda0, lambda_end, n_steps=0, rtol=1e-6, atol=1e-6, 
     _check(_lib.tufrg_flow(ctx.handle, ctypes.byref(o), _state(ctx, P, "P"), _state(ctx, C, "C"),
                            ctypes.byref(r)),
            ctx.handle)
+    return r.as_dict()
+
+
+def tufrg_su2_rhs(ctx, lam, p, c, d, dp, dc, dd):
+    """SU(2)-reduced right-hand side of a one-orbital context: (dp, dc, dd) of
+    the state (p, c, d), all complex128 [Nq][n_ff][n_ff] on the device."""
+    _check(_lib.tufrg_su2_rhs(ctx.handle, float(lam), *[_state(ctx, x, n) for x, n in
+                                                         ((p, "p"), (c, "c"), (d, "d"), (dp, "dp"), (dc, "dc"),
+                                                          (dd, "dd"))]), ctx.handle)
+
+
+def tufrg_su2_flow(ctx, p, c, d, lambda0, lambda_end, n_steps, v_max=50.0, max_steps=0, on_step=None):
+    """Euler flow of the SU(2)-reduced state (p, c, d) in place; the result as a dict."""
+    cb = STEP_CB(on_step) if on_step is not None else STEP_CB()
+    o = FlowOpts(float(lambda0), float(lambda_end), int(n_steps), 1e-6, 1e-6, 0.05, float(v_max), 3,
+                 int(max_steps), cb, None, 0, 0.05, 1e-3, 20.0, 3, 0)
+    r = FlowResult()
+    _check(_lib.tufrg_su2_flow(ctx.handle, ctypes.byref(o), _state(ctx, p, "p"), _state(ctx, c, "c"),
+                               _state(ctx, d, "d"), ctypes.byref(r)), ctx.handle)
     return r.as_dict()
 
 

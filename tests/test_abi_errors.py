@@ -164,3 +164,18 @@ def test_context_checks_the_model_arrays_before_the_library(T):
         T.Context(**_args(hop_t=hop_t[:-1]))
     with pytest.raises(ValueError):
         T.Context(**_args(V0=onsite_V0(2.0)[:1]))
+
+
+@pytest.mark.parametrize("over,text", [
+    (dict(precision="fp32"), "FP64"),
+    (dict(cutoff="shell", temperature=0.05), "FP64"),
+])
+def test_one_orbital_contexts_are_fp64_plain_cutoffs(T, over, text):
+    """The SU(2)-reduced path (one orbital per site) runs FP64 with the
+    temperature or Omega cutoff; anything else is refused at creation."""
+    hop = hubbard_hoppings(1.0, -0.25)
+    kw = _args(hop_t=hop[1][:, :1, :1], V0=np.full((1, 1, 1, 1), 1.5, dtype=np.complex128))
+    kw.update(over)
+    with pytest.raises(T.TufrgError) as ei:
+        T.Context(**kw)
+    assert ei.value.status == 6 and text in str(ei.value)

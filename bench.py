@@ -602,6 +602,44 @@ def batch_bench(T, torch, K, W):
     }
 
 
+def su2_leg(T, torch, w, K, W):
+    """Spin-degenerate one-band workload: the same K Euler steps 10 -> 1 as the
+    SU(2)-reduced flow (one orbital, B = n_ff) and as the spinful FP64 flow
+    (two spin-orbitals, B = 4 n_ff); both in FP64, with the max-coupling
+    agreement (max(|p|,|c|,|d|) of the reduced state is max(|P|,|C|))."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    v = np.full((1, 1, 1, 1), w["V0"][0, 1, 0, 1], dtype=np.complex128)
+    ctx1 = T.Context(w["hop_R"], w["hop_t"][:, :1, :1], w["mu"], v, w["ff"], w["Lq"], w["n_ref"], w["cutoff"], "fp64")
+    st = [torch.zeros((ctx1.Nq, ctx1.B, ctx1.B), dtype=torch.complex128, device=dev) for _ in range(3)]
+    if W > 0:
+        T.tufrg_su2_flow(ctx1, *st, 10.0, 1.0, W, v_max=1e30)
+    for x in st:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r1 = T.tufrg_su2_flow(ctx1, *st, 10.0, 1.0, K, v_max=1e30)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t0
+    ctx1.close()
+    ctxS = T.Context.from_workload(w, precision="fp64")
+    P = torch.zeros((ctxS.Nq, ctxS.B, ctxS.B), dtype=torch.complex128, device=dev)
+    C = torch.zeros_like(P)
+    if W > 0:
+        T.tufrg_flow(ctxS, P, C, 10.0, 1.0, n_steps=W, v_max=1e30)
+    P.zero_()
+    C.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rS = T.tufrg_flow(ctxS, P, C, 10.0, 1.0, n_steps=K, v_max=1e30)
+    torch.cuda.synchronize()
+    dtS = time.perf_counter() - t0
+    ctxS.close()
+    return {"B_reduced": int(len(w["ff"])), "B_spinful": int(4 * len(w["ff"])),
+            "ms_per_step": dt1 / K * 1e3, "spinful_fp64_ms_per_step": dtS / K * 1e3, "speedup": dtS / dt1,
+            "max_coupling_rel_diff": abs(r1["max_coupling"] / rS["max_coupling"] - 1)}
+
+
 def two_orbital_line(T, torch, w, args, K, W, extras=True, cpu=True):
     """Line of a two-orbital workload (Rashba, Hubbard): K timed Euler steps
     10 -> 1 in FP32 (or the precision asked for), the loop-kernel roofline,
@@ -693,6 +731,8 @@ def two_orbital_line(T, torch, w, args, K, W, extras=True, cpu=True):
         out["graph_steps_8"] = {"ms_per_step": dtg / K * 1e3, "speedup_vs_direct": dt32 / dtg,
                                 "bit_equal_to_direct": bool(torch.equal(Pd, P32) and torch.equal(Cd, C32))}
         del Pd, Cd
+    if not no_extras and w["name"].startswith("hubbard"):
+        out["su2_reduced"] = su2_leg(T, torch, w, K, W)
     if not no_extras:
         ctx64, P64, C64 = make("fp64")
         dt64, res64, l64_ms, l64_n = timed_steps(ctx64, P64, C64, timing=True)

@@ -21,14 +21,17 @@
 // is one dense contraction, and the A operand (phases times pi) does not
 // depend on q:
 //   Y[(phi, alpha)][(q, beta)] = sum_{ky, m} phi(ky) pi_m^alpha(ky) w_m^beta(ky; q).
-// loop_rb_kernel: one workgroup (four waves, one per SIMD) per group of four
+// loop_rb_apre_kernel: the A operand (phase rows times pi, split), which
+//   depends on neither q, Lambda nor the channel, once per context in the
+//   lane order of the matrix instruction.
+// loop_rb_kernel: one workgroup (eight waves, two per SIMD) per group of four
 //   coarse q of one channel and a block of kx rows.  Per tile of 16 ky
-//   (K = 96 = (ky, m)) it stages pi and the phases in LDS, evaluates the loop
-//   kernels L_mn and forms the B operand w (split) in LDS for the next tile,
-//   while each wave builds the A operand of its row tiles in registers and runs
-//   the three BF16 products (hi*hi + hi*lo + lo*hi, v_mfma_f32_16x16x32_bf16)
-//   into 16 x 16 FP32 tiles (rows: 9 x 36 phase rows; columns: 4 q x 36 beta).
-//   At the end of a kx row the tiles go to a row buffer Y.
+//   (K = 96 = (ky, m)) it evaluates the loop kernels L_mn and forms the B
+//   operand w (split) in LDS for the next tile, while each wave loads the A
+//   fragments of its row tiles (L2-resident) and runs the three BF16 products
+//   (hi*hi + hi*lo + lo*hi, v_mfma_f32_16x16x32_bf16) into 16 x 16 FP32 tiles
+//   (rows: 9 x 36 phase rows; columns: 4 q x 36 beta).  At the end of a kx
+//   row the tiles go to a row buffer Y.
 // loop_rb_rowsum_kernel: the kx sum with the kx phases, in FP64, for the half
 //   plane of difference vectors: lambda^{alpha beta}(q, dR).
 // loop_rb_finalize_kernel: back from the real basis to the entries (a,b,c,d),
@@ -93,27 +96,76 @@ __device__ inline int bpair_off(int K, int col) {
 
 }  // namespace
 
+// The A operand Y's left factor, phi(ky) pi_m^alpha(k) split, does not depend
+// on q, Lambda or the channel: computed once per context, in the lane order of
+// the matrix instruction, as [kx][ky tile][K step][row tile][hi, lo][lane] of
+// 8 BF16 (16 bytes): lane l holds row 16 mt + l % 16 and K = 32 s + 8 (l / 16)
+// .. + 7 of the tile, K = (ky - 16 tile) 6 + m; rows past the 9 x 36 and ky
+// past the mesh are zero.  The split is that of the FP32 product (the
+// compiler may form the remainder from the unrounded product, a last-bit
+// difference of lo: loops agree with an in-kernel build to about 2e-9).
+template <int NDY>
+__global__ __launch_bounds__(256) void loop_rb_apre_kernel(const float *__restrict__ band,
+                                                           const float *__restrict__ phy, int Lf,
+                                                           u32x4 *__restrict__ apre) {
+  using S = RB<NDY>;
+  const int ntk = (Lf + KT - 1) / KT;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long total = (long long)Lf * ntk * KS * S::MT * 64;
+  if (gid >= total) return;
+  const int lane = (int)(gid % 64);
+  long long r = gid / 64;
+  const int mt = (int)(r % S::MT);
+  r /= S::MT;
+  const int s = (int)(r % KS);
+  r /= KS;
+  const int tk = (int)(r % ntk), kx = (int)(r / ntk);
+  const int row = mt * 16 + (lane & 15), ph = row / NA, alpha = row % NA;
+  float v[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int K = 32 * s + 8 * (lane >> 4) + t, ky = tk * KT + K / NO, m = K % NO;
+    float f = 0.f, pv = 0.f;
+    if (row < S::ROWS && ky < Lf) {
+      f = ph == 0 ? 1.f : ph <= NDY ? phy[((size_t)ky * NDY + ph - 1) * 2] : -phy[((size_t)ky * NDY + ph - NDY - 1) * 2 + 1];
+      pv = band[((size_t)kx * Lf + ky) * NC + NO + m * NA + alpha];
+    }
+    v[t] = pv * f;
+  }
+  u32x4 h, l;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    unsigned hh, ll;
+    split2(v[2 * t], v[2 * t + 1], hh, ll);
+    h[t] = hh;
+    l[t] = ll;
+  }
+  const size_t o = ((((size_t)kx * ntk + tk) * KS + s) * S::MT + mt) * 2 * 64 + lane;
+  apre[o] = h;
+  apre[o + 64] = l;
+}
+
 template <int NDY, int SCHEME>
 __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
     const float *__restrict__ band, const float *__restrict__ kv, const float *__restrict__ cvp,
-    const float *__restrict__ phy, int Lq, int n_ref, int Lf, int q_first, int n_q, const int *__restrict__ rows,
-    int ch, float lam, int deriv, int n_groups, int n_kxb, int kxr, int gx, float *__restrict__ Y) {
+    const bf16x8 *__restrict__ apre, int Lq, int n_ref, int Lf, int q_first, int n_q, const int *__restrict__ rows,
+    int ch, float lam, int deriv, int n_groups, int n_kxb, int kxr, float *__restrict__ Y) {
   using S = RB<NDY>;
-  constexpr int NPHI = S::NPHI, ROWS = S::ROWS, MT = S::MT, MTW = S::MTW;
+  constexpr int MT = S::MT, MTW = S::MTW, ROWS = S::ROWS;
   constexpr bool SHELL = SCHEME == CUT_SHELL;
   constexpr int PER = SHELL ? 4 * NO : 2 * NO;  // band values per point: e, K (shell: and a, b)
   constexpr int NEVU = ((1 + NQG) * PER + 63) / 64;  // per-lane values of one ky row of sE
-  constexpr int NPHU = (2 * NO * NPHI + 63) / 64;    // per-lane phase values of two ky
 
-  // work item: XCD-major, so that the workgroups running at once on one XCD
-  // share kx rows (A side) and a few k' rows (B side) in its L2
+  // work item: XCD x takes the kx blocks x, x + 8, ..., the groups of q
+  // fastest, so that the workgroups running at once on one XCD share the kx
+  // rows of the A operand in its L2
   const int b = blockIdx.x, xcd = b & 7, j = b >> 3;
-  const int kxb = j / gx, g = xcd * gx + (j - (j / gx) * gx);
-  if (g >= n_groups || kxb >= n_kxb) return;
+  const int g = j % n_groups, kxb = xcd + 8 * (j / n_groups);
+  if (kxb >= n_kxb) return;
   const int kx0 = kxb * kxr, nrow = min(kxr, Lf - kx0);
   const int ntk = (Lf + KT - 1) / KT, ntile = nrow * ntk;
 
-  const int tid = threadIdx.x, lane = tid & 63, lg = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   // the two waves that share a SIMD take opposite orders of their matrix
   // products and B-operand work, so one's vector work runs beside the other's
@@ -121,8 +173,6 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
   const bool mfma_first = ((wv & 1) ^ (wv >> 2)) == 0;
 
   __shared__ __align__(16) unsigned char sB[2][2][KS * NCT * 64 * 16];  // [buffer][hi, lo] granules
-  __shared__ __align__(16) float sPi[2][NA * PIS];                        // pi^alpha at K = (ky, m)
-  __shared__ __align__(16) float sPh[2][NPHI * KTOT];                     // phase of row phi at K
   __shared__ __align__(16) float sL[NQG][KT][NO * NO];                    // loop kernels L_mn
   // e_m, K_m at (kx, ky) [slot 0] and at k'(q, ky) [slots 1..4]; shell: then (a_m, b_m)
   __shared__ __align__(16) float sE[KT][1 + NQG][PER];
@@ -152,13 +202,6 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
   };
 
   // ---- per-thread constants -------------------------------------------------
-  // pi staging: wave wv stages ky 2 wv, 2 wv + 1 of a tile; lane value r = lane + 64 u
-  int pi_lds[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int r = lane + 64 * u;
-    pi_lds[u] = (r % NA) * PIS + r / NA;  // + ky NO
-  }
   // band values: lane index i = lane + 64 u < (1 + NQG) PER: slot, kind, band
   int ev_slot[NEVU], ev_off[NEVU];
   const float *ev_src[NEVU];
@@ -192,20 +235,15 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
   }
   const float sg = ch == 0 ? 1.f : -1.f;
 
+  // band values of the wave's two ky of a tile (for the loop kernels)
   struct Pre {
-    float pi[2][4];      // pi of ky 2 wv + kk, r = lane + 64 u
-    float ev[2][NEVU];   // band values of ky 2 wv + kk
-    float ph[NPHU];      // phases of the wave's two ky, i = lane + 64 u < 2 NO NPHI
+    float ev[2][NEVU];
   };
   auto fetch = [&](int t, Pre &pr) __attribute__((always_inline)) {
     const int kx = kx0 + t / ntk, ky0 = (t - (t / ntk) * ntk) * KT;
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      const int ky = min(ky0 + 2 * wv + kk, Lf - 1);  // ky past the mesh: any point (zero phases)
-      const float *src = band + (size_t)(kx * Lf + ky) * NC + NO + lane;
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (u < 3 || lane < PK - 192) pr.pi[kk][u] = src[64 * u];
+      const int ky = min(ky0 + 2 * wv + kk, Lf - 1);  // ky past the mesh: any point (zero A rows)
 #pragma unroll
       for (int u = 0; u < NEVU; ++u) {
         const int sl = ev_slot[u];
@@ -213,41 +251,13 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
         pr.ev[kk][u] = ev_src[u][(size_t)k * ev_stride[u] + ev_off[u]];
       }
     }
-#pragma unroll
-    for (int u = 0; u < NPHU; ++u) {
-      const int i = lane + 64 * u;
-      float v = 0.f;
-      if (i < 2 * NO * NPHI) {
-        const int ph = i / (2 * NO), ky = ky0 + 2 * wv + (i % (2 * NO)) / NO;
-        if (ky < Lf) {
-          if (ph == 0)
-            v = 1.f;
-          else if (ph <= NDY)
-            v = phy[((size_t)ky * NDY + ph - 1) * 2];
-          else
-            v = -phy[((size_t)ky * NDY + ph - NDY - 1) * 2 + 1];
-        }
-      }
-      pr.ph[u] = v;
-    }
   };
-  // pi, phases and band values of a tile into LDS (pi and phases into buffer bb)
-  auto stage = [&](int bb, const Pre &pr) __attribute__((always_inline)) {
+  auto stage = [&](const Pre &pr) __attribute__((always_inline)) {
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-      const int kyo = (2 * wv + kk) * NO;
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (u < 3 || lane < PK - 192) sPi[bb][pi_lds[u] + kyo] = pr.pi[kk][u];
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
       for (int u = 0; u < NEVU; ++u)
         if (lane + 64 * u < (1 + NQG) * PER) (&sE[2 * wv + kk][0][0])[lane + 64 * u] = pr.ev[kk][u];
-    }
-#pragma unroll
-    for (int u = 0; u < NPHU; ++u) {
-      const int i = lane + 64 * u;
-      if (i < 2 * NO * NPHI) sPh[bb][(i / (2 * NO)) * KTOT + 2 * wv * NO + i % (2 * NO)] = pr.ph[u];
-    }
   };
   // loop kernels L_mn of this thread's (q, ky): (m, n) = divmod(dsub + 8 i, 6)
   auto loop_kernels = [&]() __attribute__((always_inline)) {
@@ -320,39 +330,33 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
   };
 
   f32x4 acc[MTW][NCT];
-  // A-operand rows of this wave's tiles: LDS offsets of (alpha, 8 lg) and (phi, 8 lg)
-  int a_pi[MTW], a_ph[MTW];
-#pragma unroll
-  for (int jt = 0; jt < MTW; ++jt) {
-    const int row = (wv + NW * jt) * 16 + (lane & 15);
-    const bool rv = row < ROWS;
-    a_pi[jt] = (rv ? row % NA : 0) * PIS + 8 * lg;
-    a_ph[jt] = rv ? (row / NA) * KTOT + 8 * lg : -1;
-  }
 
-  // products of tile t (buffers bb) for this wave's row tiles
-  auto mfma_tile = [&](int bb) __attribute__((always_inline)) {
+  // products of tile t (B operand in buffer bb) for this wave's row tiles; the
+  // A fragments of each K step come from the precomputed operand (in L2), the
+  // next step's loads in flight during the current step's products
+  auto mfma_tile = [&](int bb, int t) __attribute__((always_inline)) {
     const unsigned char *bh = sB[bb][0], *bl = sB[bb][1];
+    const int kx = kx0 + t / ntk, tk = t - (t / ntk) * ntk;
+    const bf16x8 *ab = apre + ((size_t)kx * ntk + tk) * KS * MT * 2 * 64 + lane;
+    bf16x8 ah[MTW], al[MTW];
+#pragma unroll
+    for (int jt = 0; jt < MTW; ++jt)
+      if (wv + NW * jt < MT) {
+        const int mt = wv + NW * jt;
+        ah[jt] = ab[(size_t)mt * 128];
+        al[jt] = ab[(size_t)mt * 128 + 64];
+      }
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      bf16x8 ah[MTW], al[MTW];
+      bf16x8 nh[MTW], nl[MTW];
+      if (s + 1 < KS) {
 #pragma unroll
-      for (int jt = 0; jt < MTW; ++jt) {
-        if (wv + NW * jt < MT) {  // wave-uniform
-          const f32x4 p0 = *(const f32x4 *)&sPi[bb][a_pi[jt] + 32 * s];
-          const f32x4 p1 = *(const f32x4 *)&sPi[bb][a_pi[jt] + 32 * s + 4];
-          const int po = a_ph[jt] < 0 ? 0 : a_ph[jt] + 32 * s;
-          f32x4 f0 = *(const f32x4 *)&sPh[bb][po];
-          f32x4 f1 = *(const f32x4 *)&sPh[bb][po + 4];
-          if (a_ph[jt] < 0) f0 = f1 = f32x4{0.f, 0.f, 0.f, 0.f};
-          unsigned hp[4], lp[4];
-          split2(p0[0] * f0[0], p0[1] * f0[1], hp[0], lp[0]);
-          split2(p0[2] * f0[2], p0[3] * f0[3], hp[1], lp[1]);
-          split2(p1[0] * f1[0], p1[1] * f1[1], hp[2], lp[2]);
-          split2(p1[2] * f1[2], p1[3] * f1[3], hp[3], lp[3]);
-          ah[jt] = __builtin_bit_cast(bf16x8, (u32x4){hp[0], hp[1], hp[2], hp[3]});
-          al[jt] = __builtin_bit_cast(bf16x8, (u32x4){lp[0], lp[1], lp[2], lp[3]});
-        }
+        for (int jt = 0; jt < MTW; ++jt)
+          if (wv + NW * jt < MT) {
+            const int mt = wv + NW * jt;
+            nh[jt] = ab[((size_t)(s + 1) * MT + mt) * 128];
+            nl[jt] = ab[((size_t)(s + 1) * MT + mt) * 128 + 64];
+          }
       }
       // column tiles in order, the B fragments of the next one loaded while
       // the products of this one run (no further hoisting: the scheduling
@@ -378,9 +382,17 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
         blv = bln;
         __builtin_amdgcn_sched_barrier(0);
       }
+      if (s + 1 < KS) {
+#pragma unroll
+        for (int jt = 0; jt < MTW; ++jt) {
+          ah[jt] = nh[jt];
+          al[jt] = nl[jt];
+        }
+      }
     }
   };
   // end of kx row: tile (mt, n), lane holds rows 4 lg + r, column lane % 16
+  const int lg = lane >> 4;
   auto write_row = [&](int kx) __attribute__((always_inline)) {
     float *Yr = Y + ((size_t)g * Lf + kx) * ROWS * NCOL;
 #pragma unroll
@@ -403,7 +415,7 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
   // prologue: tile 0 staged and its B operand built, tile 1 in flight
   Pre pr;
   fetch(0, pr);
-  stage(0, pr);
+  stage(pr);
   __syncthreads();
   loop_kernels();
   __syncthreads();
@@ -417,17 +429,17 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
 #pragma unroll
       for (int n = 0; n < NCT; ++n) acc[jt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int tk = 0; tk < ntk; ++tk, ++t) {
-      // LDS holds B, pi and phases of tile t (buffer bb); registers the raw
-      // values of tile t + 1
+      // LDS holds B of tile t (buffer bb); registers the band values of tile
+      // t + 1
       const int bb = t & 1;
       const bool next = t + 1 < ntile;
-      if (next) stage(bb ^ 1, pr);
+      if (next) stage(pr);
       __syncthreads();
       if (next) loop_kernels();
       __syncthreads();
       if (!mfma_first && next) build_b(bb ^ 1, t + 1);
-      mfma_tile(bb);
-      // raw values of tile t + 2: in flight during the other wave's matrix
+      mfma_tile(bb, t);
+      // band values of tile t + 2: in flight during the other wave's matrix
       // ops (or this wave's B-operand work) and the barrier
       if (t + 2 < ntile) fetch(t + 2, pr);
       if (mfma_first && next) build_b(bb ^ 1, t + 1);
@@ -604,11 +616,32 @@ int loop_rb_half_points(int ndy, int *dx, int *dy) {
   return 0;
 }
 
+size_t loop_rb_apre_bytes(int ndy, int Lf) {
+  const int mt = ndy == 4 ? RB<4>::MT : RB<2>::MT;
+  const size_t ntk = (size_t)(Lf + KT - 1) / KT;
+  return (size_t)Lf * ntk * KS * mt * 2 * 64 * 16;
+}
+
+// the precomputed A operand of every kx row (once per context; band data and
+// phases are those of the loop kernel: FP32, k-major)
+hipError_t launch_loop_rb_apre(int ndy, const float *band, const float *phy, int Lf, void *apre, hipStream_t st) {
+  if (!band || !phy || !apre || (ndy != 2 && ndy != 4)) return hipErrorInvalidValue;
+  const int mt = ndy == 4 ? RB<4>::MT : RB<2>::MT;
+  const long long n = (long long)Lf * ((Lf + KT - 1) / KT) * KS * mt * 64;
+  const dim3 grid((unsigned)((n + 255) / 256));
+  if (ndy == 4)
+    hipLaunchKernelGGL(loop_rb_apre_kernel<4>, grid, dim3(256), 0, st, band, phy, Lf, (u32x4 *)apre);
+  else
+    hipLaunchKernelGGL(loop_rb_apre_kernel<2>, grid, dim3(256), 0, st, band, phy, Lf, (u32x4 *)apre);
+  return hipGetLastError();
+}
+
 // one channel, coarse q [q_first, q_first + n_q) (or the q_x rows of a.rows):
-// the row buffers Y (ceil(n_q / 4) groups of loop_rb_rowbuf_floats)
-hipError_t launch_loop_rb(const LoopArgs &a, int ch, float *Y, hipStream_t st) {
-  if (a.n_o != NO || !Y) return hipErrorInvalidValue;
-  const float *band = (const float *)a.band, *kv = (const float *)a.kv, *phy = (const float *)a.phy;
+// the row buffers Y (ceil(n_q / 4) groups of loop_rb_rowbuf_floats), with the
+// A operand apre of launch_loop_rb_apre
+hipError_t launch_loop_rb(const LoopArgs &a, int ch, const void *apre, float *Y, hipStream_t st) {
+  if (a.n_o != NO || !Y || !apre) return hipErrorInvalidValue;
+  const float *band = (const float *)a.band, *kv = (const float *)a.kv;
   const float *cvp = (const float *)a.cv;
   if (a.scheme == CUT_SHELL && !cvp) return hipErrorInvalidValue;
   if (!(a.ndy == 4 && a.ndx == 5) && !(a.ndy == 2 && a.ndx == 3)) return hipErrorInvalidValue;
@@ -616,13 +649,13 @@ hipError_t launch_loop_rb(const LoopArgs &a, int ch, float *Y, hipStream_t st) {
   const int kxr = a.kxr;  // kx rows per work item
   if (kxr < 1 || kxr > 8) return hipErrorInvalidValue;
   const int n_kxb = (a.Lf + kxr - 1) / kxr;
-  const int gx = (n_groups + 7) / 8;
-  const long long nblk = 8LL * gx * n_kxb;
+  const long long nblk = 8LL * n_groups * ((n_kxb + 7) / 8);
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
   const float lam = (float)a.lam;
-#define TUFRG_RB_LAUNCH(D, S)                                                                                   \
-  hipLaunchKernelGGL((loop_rb_kernel<D, S>), dim3((unsigned)nblk), dim3(NTHR), 0, st, band, kv, cvp, phy, a.Lq, \
-                     a.n_ref, a.Lf, a.q_first, a.n_q, a.rows, ch, lam, a.deriv, n_groups, n_kxb, kxr, gx, Y)
+  const bf16x8 *ap = (const bf16x8 *)apre;
+#define TUFRG_RB_LAUNCH(D, S)                                                                                  \
+  hipLaunchKernelGGL((loop_rb_kernel<D, S>), dim3((unsigned)nblk), dim3(NTHR), 0, st, band, kv, cvp, ap, a.Lq, \
+                     a.n_ref, a.Lf, a.q_first, a.n_q, a.rows, ch, lam, a.deriv, n_groups, n_kxb, kxr, Y)
 #define TUFRG_RB_SCHEMES(D)              \
   if (a.scheme == CUT_TEMPERATURE)       \
     TUFRG_RB_LAUNCH(D, CUT_TEMPERATURE); \

@@ -54,8 +54,12 @@ hipError_t launch_loop_gen(const LoopArgs &a, hipStream_t st);
 // six spin-orbitals on the matrix cores in the real basis of Hermitian
 // matrices (one channel): row buffers Y of loop_rb_rowbuf_floats(ndy, Lf)
 // floats per group of four coarse q, then (sums) the compact loops; the
-// half-plane points of the computed shape from loop_rb_half_points
-hipError_t launch_loop_rb(const LoopArgs &a, int ch, float *Y, hipStream_t st);
+// half-plane points of the computed shape from loop_rb_half_points.  The A
+// operand (phases times projectors, split; independent of q, Lambda and the
+// channel) is computed once into loop_rb_apre_bytes(ndy, Lf) bytes.
+size_t loop_rb_apre_bytes(int ndy, int Lf);
+hipError_t launch_loop_rb_apre(int ndy, const float *band, const float *phy, int Lf, void *apre, hipStream_t st);
+hipError_t launch_loop_rb(const LoopArgs &a, int ch, const void *apre, float *Y, hipStream_t st);
 hipError_t launch_loop_rb_sums(const LoopArgs &a, const float *Y, double *lamb, const int *hmap, int nD,
                                double *dst, hipStream_t st);
 size_t loop_rb_rowbuf_floats(int ndy, int Lf);

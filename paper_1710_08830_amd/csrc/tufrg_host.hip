@@ -121,6 +121,7 @@ struct tufrg_ctx {
   int *d_hmap = nullptr;                       // BF16X3 loops: half-plane point of each difference vector
   int mfma_chunk = 0;
   int mfma_kxr = 2;        // kx rows per work item of the matrix-core loop (tunable)
+  void *d_apre = nullptr;  // the matrix-core loop's precomputed A operand (once per context)
   size_t partial_cap = 0;  // doubles allocated at d_partial
   unsigned long long *h_sbits = nullptr;       // pinned
   // Euler steps in HIP graphs: the executable graph, the capture stream (the
@@ -734,6 +735,12 @@ static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch
     HIPCHK(c, hipStreamSynchronize(c->st));
     c->d_hmap = d;
   }
+  if (!c->d_apre) {
+    unsigned char *ap = nullptr;
+    TRY(dalloc(c, &ap, loop_rb_apre_bytes(c->ndy, c->Lf)));
+    HIPCHK(c, launch_loop_rb_apre(c->ndy, c->d_bandk32, c->d_phy32, c->Lf, ap, c->st));
+    c->d_apre = ap;
+  }
   if (!c->d_yrow || !c->d_lamb) {
     // whole q_x rows per chunk, about 256 coarse q (64 groups of four)
     c->mfma_chunk = std::max(1, 256 / c->Lq) * c->Lq;
@@ -754,7 +761,7 @@ static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch
       a.rows = rows ? rows + q0 / c->Lq : nullptr;
       // the loop timer covers the matrix-core kernel of each chunk
       HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
-      HIPCHK(c, launch_loop_rb(a, ch, c->d_yrow, c->st));
+      HIPCHK(c, launch_loop_rb(a, ch, c->d_apre, c->d_yrow, c->st));
       HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
       HIPCHK(c, launch_loop_rb_sums(a, c->d_yrow, c->d_lamb, c->d_hmap, c->nD,
                                     dst + 2 * ((size_t)chi * n_q + q0) * blk, c->st));

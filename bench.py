@@ -565,27 +565,27 @@ def batch_bench(T, torch, K, W):
     dev = torch.device("cuda:0")
     ws = batch_instances(32, seed=2, n_ref=12)
     out = {}
-    for n_streams, G in ((4, 0), (1, 0), (4, 8)):
+    for n_streams, G, fused in ((4, 0, False), (1, 0, False), (4, 8, False), (4, 0, True)):
         b = T.Batch(ws, precision="fp32", n_streams=n_streams)
         Ps, Cs = [], []
         for d in b.dims:
             Ps.append(torch.zeros((d["Nq"], d["B"], d["B"]), dtype=torch.complex128, device=dev))
             Cs.append(torch.zeros_like(Ps[-1]))
         if W > 0:
-            T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=W, v_max=1e30, graph_steps=G)
+            T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=W, v_max=1e30, graph_steps=G, fused_loops=fused)
         for x in Ps + Cs:
             x.zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=K, v_max=1e30, graph_steps=G)
+        res = T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=K, v_max=1e30, graph_steps=G, fused_loops=fused)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         entries = sum(2.0 * d["Nq"] * d["B"] ** 2 for d in b.dims)
-        out[(n_streams, G)] = dict(seconds=dt, value=entries * K / dt, ms_per_step=dt / K * 1e3,
+        out[(n_streams, G, fused)] = dict(seconds=dt, value=entries * K / dt, ms_per_step=dt / K * 1e3,
                                    steps=min(r["n_steps"] for r in res),
                                    checksum=float(sum(x.abs().sum().item() for x in Ps)))
         b.close()
-    best = max((out[(4, 0)], out[(4, 8)]), key=lambda d: d["value"])
+    best = max((out[(4, 0, False)], out[(4, 8, False)]), key=lambda d: d["value"])
     return {
         "metric": METRIC, "value": best["value"], "unit": "loop entries/s", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": best["ms_per_step"], "higher_is_better": True, "scaling": "weak",
@@ -594,10 +594,13 @@ def batch_bench(T, torch, K, W):
                    "Lq": sorted({w["Lq"] for w in ws}), "n_ff": sorted({len(w["ff"]) for w in ws}),
                    "n_ref": 12, "step": "lockstep Euler step of every instance", "parallelism": "single GPU"},
         "flow_steps_per_s": K / best["seconds"],
-        "four_streams": out[(4, 0)], "one_stream": out[(1, 0)], "four_streams_graph_steps_8": out[(4, 8)],
-        "speedup_4_streams_vs_1": out[(1, 0)]["seconds"] / out[(4, 0)]["seconds"],
-        "speedup_graph_vs_direct": out[(4, 0)]["seconds"] / out[(4, 8)]["seconds"],
-        "graph_checksum_equal": out[(4, 0)]["checksum"] == out[(4, 8)]["checksum"],
+        "four_streams": out[(4, 0, False)], "one_stream": out[(1, 0, False)],
+        "four_streams_graph_steps_8": out[(4, 8, False)], "four_streams_fused_loops": out[(4, 0, True)],
+        "speedup_4_streams_vs_1": out[(1, 0, False)]["seconds"] / out[(4, 0, False)]["seconds"],
+        "speedup_graph_vs_direct": out[(4, 0, False)]["seconds"] / out[(4, 8, False)]["seconds"],
+        "speedup_fused_loops_vs_per_instance": out[(4, 0, False)]["seconds"] / out[(4, 0, True)]["seconds"],
+        "graph_checksum_equal": out[(4, 0, False)]["checksum"] == out[(4, 8, False)]["checksum"],
+        "fused_checksum_equal": out[(4, 0, False)]["checksum"] == out[(4, 0, True)]["checksum"],
         "roofline": None,
     }
 

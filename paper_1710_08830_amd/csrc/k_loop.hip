@@ -30,6 +30,8 @@
 //   lanes' values are transposed through LDS and contracted with e^{-i ky dy}.
 // Partial sums per (ky block, kx chunk) go to HBM in FP64; a finalising kernel
 // adds them in a fixed order (deterministic, no atomics).
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -271,21 +273,19 @@ struct loop_waves {
   static constexpr int v = (sizeof(T) == 4) ? 4 : 2;
 };
 
-// QW waves per work item (ky block, q_y group, q_x, kx chunk, channel).
+// One work item (ky block, q_y group, q_x, kx chunk, channel) of QW waves,
+// w its index among the n_items of one instance; bufs and phy are the
+// workgroup's LDS.
 template <typename T, int NDX, int NDY, int SCHEME, int QW>
-__global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 2 : 4))) void loop_no2_kernel(const T *__restrict__ ekv, const T *__restrict__ pi4, const T *__restrict__ cvp,
-                                                           const double *__restrict__ tw, const T *__restrict__ twk,
-                                                           int Lq, int n_ref, int Lf,
-                                                           int nkyb, int nkxc, int kxper, int q_first, int n_q,
-                                                           const int *__restrict__ rows,
-                                                           int ch_first, int n_items, T lam, int deriv,
-                                                           T *__restrict__ partial) {
+__device__ __forceinline__ void loop_no2_item(const T *__restrict__ ekv, const T *__restrict__ pi4,
+                                              const T *__restrict__ cvp, const double *__restrict__ tw,
+                                              const T *__restrict__ twk, int Lq, int n_ref, int Lf, int nkyb,
+                                              int nkxc, int kxper, int q_first, int n_q,
+                                              const int *__restrict__ rows, int ch_first, int w, T lam, int deriv,
+                                              T *__restrict__ partial, T (&bufs)[QW][32][65],
+                                              T (&phy)[2 * NDY + 1][2][64]) {
   constexpr int NDY2 = 2 * NDY + 1;
   const int tid = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int xcd = blockIdx.x % N_XCD, slot = blockIdx.x / N_XCD;
-  const int base = n_items / N_XCD, rem = n_items % N_XCD;
-  if (slot >= base + (xcd < rem ? 1 : 0)) return;  // padding workgroup, no work
-  int w = xcd * base + min(xcd, rem) + slot;
   const int kyb = w % nkyb;
   w /= nkyb;
   const int nqyg = (Lq + QW - 1) / QW;
@@ -332,8 +332,6 @@ __global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (siz
                                      Bc);
 
   // rebuild all 16 entries per dx, transpose through LDS, contract with e^{-i 2 pi ky dy / Lf}
-  __shared__ T bufs[QW][32][65];
-  __shared__ T phy[NDY2][2][64];
   T(&buf)[32][65] = bufs[wv];
   if (wv == 0) {
 #pragma unroll
@@ -402,6 +400,46 @@ __global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (siz
   }
 }
 
+
+// QW waves per work item (ky block, q_y group, q_x, kx chunk, channel).
+template <typename T, int NDX, int NDY, int SCHEME, int QW>
+__global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 2 : 4))) void loop_no2_kernel(const T *__restrict__ ekv, const T *__restrict__ pi4, const T *__restrict__ cvp,
+                                                           const double *__restrict__ tw, const T *__restrict__ twk,
+                                                           int Lq, int n_ref, int Lf,
+                                                           int nkyb, int nkxc, int kxper, int q_first, int n_q,
+                                                           const int *__restrict__ rows,
+                                                           int ch_first, int n_items, T lam, int deriv,
+                                                           T *__restrict__ partial) {
+  __shared__ T bufs[QW][32][65];
+  __shared__ T phy[2 * NDY + 1][2][64];
+  const int xcd = blockIdx.x % N_XCD, slot = blockIdx.x / N_XCD;
+  const int base = n_items / N_XCD, rem = n_items % N_XCD;
+  if (slot >= base + (xcd < rem ? 1 : 0)) return;  // padding workgroup, no work
+  const int w = xcd * base + min(xcd, rem) + slot;
+  loop_no2_item<T, NDX, NDY, SCHEME, QW>(ekv, pi4, cvp, tw, twk, Lq, n_ref, Lf, nkyb, nkxc, kxper, q_first, n_q, rows,
+                                         ch_first, w, lam, deriv, partial, bufs, phy);
+}
+
+// Several instances in one launch: the items of instance i are
+// [inst[i].item0, inst[i].item0 + its count), every instance summing both
+// channels over all its coarse q; the same work items and partial sums as its
+// own launch.
+template <typename T, int NDX, int NDY, int SCHEME, int QW>
+__global__ __launch_bounds__(64 * QW, (NDX > 3 ? (sizeof(T) == 8 ? 1 : 2) : (sizeof(T) == 8 ? 2 : 4))) void loop_no2_batch_kernel(const No2Inst *__restrict__ inst, int n_inst, int n_items) {
+  __shared__ T bufs[QW][32][65];
+  __shared__ T phy[2 * NDY + 1][2][64];
+  const int xcd = blockIdx.x % N_XCD, slot = blockIdx.x / N_XCD;
+  const int base = n_items / N_XCD, rem = n_items % N_XCD;
+  if (slot >= base + (xcd < rem ? 1 : 0)) return;  // padding workgroup, no work
+  const int w = xcd * base + min(xcd, rem) + slot;
+  int i = 0;
+  while (i + 1 < n_inst && inst[i + 1].item0 <= w) ++i;
+  const No2Inst &d = inst[i];
+  loop_no2_item<T, NDX, NDY, SCHEME, QW>((const T *)d.ekv, (const T *)d.pi4, (const T *)d.cvp, d.tw,
+                                         (const T *)d.twk, d.Lq, d.n_ref, d.Lf, d.nkyb, d.nkxc, d.kxper, 0, d.n_q,
+                                         nullptr, 0, w - d.item0, (T)d.lam, d.deriv, (T *)d.partial, bufs, phy);
+}
+
 template <typename T, int NDX, int NDY>
 static hipError_t launch_no2(const LoopArgs &a, hipStream_t st) {
   if (a.q_first % a.Lq != 0 || a.n_q % a.Lq != 0) return hipErrorInvalidValue;  // whole q_x rows
@@ -431,6 +469,88 @@ static hipError_t launch_no2(const LoopArgs &a, hipStream_t st) {
     return hipErrorInvalidValue;
 #undef TUFRG_NO2_LAUNCH
   return hipGetLastError();
+}
+
+template <typename T, int NDX, int NDY>
+static hipError_t launch_no2_batch(const LoopArgs *a, const int *idx, int m, No2Inst *desc_h, No2Inst *desc_d,
+                                   hipStream_t st) {
+  constexpr int QW = loop_waves<T>::v;
+  long long items = 0;
+  for (int j = 0; j < m; ++j) {
+    const LoopArgs &x = a[idx[j]];
+    const T *twk = (const T *)(sizeof(T) == 8 ? (const void *)x.tw : x.tw32);
+    if (!x.ekv || !x.pi4 || !twk || x.q_first != 0 || x.n_q != x.Nq || x.rows || x.ch_first != 0 || x.n_ch != 2)
+      return hipErrorInvalidValue;
+    if (x.scheme == CUT_SHELL && !x.cv) return hipErrorInvalidValue;
+    No2Inst &d = desc_h[j];
+    d.ekv = x.ekv;
+    d.pi4 = x.pi4;
+    d.cvp = x.cv;
+    d.twk = twk;
+    d.tw = x.tw;
+    d.partial = x.partial;
+    d.lam = x.lam;
+    d.Lq = x.Lq;
+    d.n_ref = x.n_ref;
+    d.Lf = x.Lf;
+    d.nkyb = x.nkyb;
+    d.nkxc = x.nkxc;
+    d.kxper = (x.Lf + x.nkxc - 1) / x.nkxc;
+    d.n_q = x.n_q;
+    d.deriv = x.deriv;
+    d.item0 = (int)items;
+    d.pad = 0;
+    items += (long long)x.nkyb * x.nkxc * ((x.Lq + QW - 1) / QW) * (x.n_q / x.Lq) * 2;
+  }
+  if (items > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipError_t e = hipMemcpyAsync(desc_d, desc_h, m * sizeof(No2Inst), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  const int n_items = (int)items;
+  const dim3 grid(((n_items + N_XCD - 1) / N_XCD) * N_XCD), block(64 * QW);
+  const int scheme = a[idx[0]].scheme;
+  if (scheme == CUT_TEMPERATURE)
+    hipLaunchKernelGGL((loop_no2_batch_kernel<T, NDX, NDY, CUT_TEMPERATURE, QW>), grid, block, 0, st, desc_d, m,
+                       n_items);
+  else if (scheme == CUT_OMEGA)
+    hipLaunchKernelGGL((loop_no2_batch_kernel<T, NDX, NDY, CUT_OMEGA, QW>), grid, block, 0, st, desc_d, m, n_items);
+  else if (scheme == CUT_SHELL)
+    hipLaunchKernelGGL((loop_no2_batch_kernel<T, NDX, NDY, CUT_SHELL, QW>), grid, block, 0, st, desc_d, m, n_items);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_loop_batch(const LoopArgs *a, int n, No2Inst *desc_h, No2Inst *desc_d, hipStream_t st) {
+  if (n < 1 || !desc_h || !desc_d) return hipErrorInvalidValue;
+  const int prec = a[0].prec;
+  for (int i = 0; i < n; ++i)
+    if (a[i].n_o != 2 || a[i].prec != prec) return hipErrorInvalidValue;
+  // one launch per (shape, regulator); the group's descriptors contiguous
+  int off = 0;
+  for (int shape = 0; shape < 3; ++shape)
+    for (int scheme = 0; scheme < 3; ++scheme) {
+      std::vector<int> idx;
+      for (int i = 0; i < n; ++i) {
+        const int sh = (a[i].ndx == 3 && a[i].ndy == 2) ? 0 : (a[i].ndx == 5 && a[i].ndy == 4) ? 1 : 2;
+        if (sh == 2 && !(a[i].ndx == 2 && a[i].ndy == 1)) return hipErrorInvalidValue;
+        if (sh == shape && a[i].scheme == scheme) idx.push_back(i);
+      }
+      if (idx.empty()) continue;
+      const int m = (int)idx.size();
+      hipError_t e;
+      if (shape == 0)
+        e = prec == 0 ? launch_no2_batch<double, 3, 2>(a, idx.data(), m, desc_h + off, desc_d + off, st)
+                      : launch_no2_batch<float, 3, 2>(a, idx.data(), m, desc_h + off, desc_d + off, st);
+      else if (shape == 1)
+        e = prec == 0 ? launch_no2_batch<double, 5, 4>(a, idx.data(), m, desc_h + off, desc_d + off, st)
+                      : launch_no2_batch<float, 5, 4>(a, idx.data(), m, desc_h + off, desc_d + off, st);
+      else
+        e = prec == 0 ? launch_no2_batch<double, 2, 1>(a, idx.data(), m, desc_h + off, desc_d + off, st)
+                      : launch_no2_batch<float, 2, 1>(a, idx.data(), m, desc_h + off, desc_d + off, st);
+      if (e != hipSuccess) return e;
+      off += m;
+    }
+  return hipSuccess;
 }
 
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st) {

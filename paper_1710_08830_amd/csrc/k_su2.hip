@@ -32,32 +32,34 @@ __device__ inline double wave_sum(double v) {
 
 }  // namespace
 
-// Lc[ch - ch_first][q - q_first][iD] = 1/Nf sum_k e^{-ik.dR_iD} L(e(k), e(k'))
-// (k' = q - k for pp, k - q for ph): per kx row the ky sums with the phases of
-// |dy| <= 4 (cos and sin parts), then the kx phases per dR; one workgroup per
-// (q, channel), its threads over ky
+// part[ch - ch_first][q - q_first][kx chunk][iD] = sum over the kx rows of the
+// chunk of e^{-ik.dR_iD} L(e(k), e(k')) (k' = q - k for pp, k - q for ph): per
+// kx row the ky sums with the phases of |dy| <= 4 (cos and sin parts), then
+// the kx phases per dR; one workgroup per (q, channel, kx chunk), its threads
+// over ky (one wave per 64 ky, at most four)
 template <int NDP>
 __global__ __launch_bounds__(256) void loop1_kernel(int Lq, int n_ref, int Lf, int nD, const int *__restrict__ dlist,
                                                     const double *__restrict__ e, const double *__restrict__ kv,
                                                     const double *__restrict__ tw, double lam, int scheme, int deriv,
-                                                    int ch_first, int q_first, int n_q, double inv_nf,
-                                                    double *__restrict__ out) {
+                                                    int ch_first, int q_first, int n_q, int nkxc, int kxper,
+                                                    double *__restrict__ part) {
   __shared__ double red[4][NDP][2];
-  const int qrel = blockIdx.x, chrel = blockIdx.y, ch = ch_first + chrel;
+  const int qrel = blockIdx.x, chrel = blockIdx.y, kxc = blockIdx.z, ch = ch_first + chrel;
   const int q = q_first + qrel;
   const int qfx = (q / Lq) * n_ref, qfy = (q % Lq) * n_ref;
   const double sg = ch == 0 ? 1.0 : -1.0;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, nthr = blockDim.x;
   double zr[NDP], zi[NDP];
 #pragma unroll
   for (int i = 0; i < NDP; ++i) zr[i] = zi[i] = 0.0;
-  for (int kx = 0; kx < Lf; ++kx) {
+  const int x1 = min(Lf, (kxc + 1) * kxper);
+  for (int kx = kxc * kxper; kx < x1; ++kx) {
     double A[5], S[5];
 #pragma unroll
     for (int y = 0; y < 5; ++y) A[y] = S[y] = 0.0;
     int kpx = ch == 0 ? qfx - kx : kx - qfx;
     kpx += kpx < 0 ? Lf : 0;
-    for (int ky = tid; ky < Lf; ky += 256) {
+    for (int ky = tid; ky < Lf; ky += nthr) {
       int kpy = ch == 0 ? qfy - ky : ky - qfy;
       kpy += kpy < 0 ? Lf : 0;
       const size_t k = (size_t)kx * Lf + ky, kp = (size_t)kpx * Lf + kpy;
@@ -83,7 +85,7 @@ __global__ __launch_bounds__(256) void loop1_kernel(int Lq, int n_ref, int Lf, i
         zi[i] = fma(pr, vi, fma(pi, vr, zi[i]));
       }
   }
-  const int w = tid >> 6, lane = tid & 63;
+  const int w = tid >> 6, lane = tid & 63, nw = (nthr + 63) >> 6;
 #pragma unroll
   for (int i = 0; i < NDP; ++i) {
     const double a = wave_sum(zr[i]), b = wave_sum(zi[i]);
@@ -94,24 +96,48 @@ __global__ __launch_bounds__(256) void loop1_kernel(int Lq, int n_ref, int Lf, i
   }
   __syncthreads();
   if (tid < nD) {
-    const double a = red[0][tid][0] + red[1][tid][0] + red[2][tid][0] + red[3][tid][0];
-    const double b = red[0][tid][1] + red[1][tid][1] + red[2][tid][1] + red[3][tid][1];
-    const size_t o = ((size_t)chrel * n_q + qrel) * nD + tid;
-    out[2 * o] = a * inv_nf;
-    out[2 * o + 1] = b * inv_nf;
+    double a = 0.0, b = 0.0;
+    for (int v = 0; v < nw; ++v) {
+      a += red[v][tid][0];
+      b += red[v][tid][1];
+    }
+    const size_t o = (((size_t)chrel * n_q + qrel) * nkxc + kxc) * nD + tid;
+    part[2 * o] = a;
+    part[2 * o + 1] = b;
   }
 }
 
+// out[ch][q][iD] = 1/Nf sum over the kx chunks in order
+__global__ void loop1_reduce_kernel(long long n, int nkxc, int nD, double inv_nf, const double2 *__restrict__ part,
+                                    double2 *__restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long cq = i / nD;
+  const int iD = (int)(i - cq * nD);
+  double a = 0.0, b = 0.0;
+  for (int c = 0; c < nkxc; ++c) {
+    const double2 v = part[(cq * nkxc + c) * nD + iD];
+    a += v.x;
+    b += v.y;
+  }
+  out[i] = make_double2(a * inv_nf, b * inv_nf);
+}
+
+size_t loop1_partial_doubles(int n_q, int nD, int nkxc) { return 2 * 2 * (size_t)n_q * nkxc * nD; }
+
 hipError_t launch_loop1(int Lq, int n_ref, int nD, const int *dlist, const double *e, const double *kv,
                         const double *tw, double lam, int scheme, int deriv, int ch_first, int n_ch, int q_first,
-                        int n_q, double *out, hipStream_t st) {
+                        int n_q, int nkxc, double *part, double *out, hipStream_t st) {
   const int Lf = Lq * n_ref;
-  if (n_q < 1 || n_ch < 1 || n_ch > 2 || scheme == CUT_SHELL) return hipErrorInvalidValue;
+  if (n_q < 1 || n_ch < 1 || n_ch > 2 || scheme == CUT_SHELL || nkxc < 1 || !part) return hipErrorInvalidValue;
+  const int kxper = (Lf + nkxc - 1) / nkxc;
+  nkxc = (Lf + kxper - 1) / kxper;
   const double inv = 1.0 / ((double)Lf * Lf);
-  const dim3 grid((unsigned)n_q, (unsigned)n_ch);
-#define TUFRG_L1(N)                                                                                                  \
-  hipLaunchKernelGGL(loop1_kernel<N>, grid, dim3(256), 0, st, Lq, n_ref, Lf, nD, dlist, e, kv, tw, lam, scheme, deriv, \
-                     ch_first, q_first, n_q, inv, out)
+  const dim3 grid((unsigned)n_q, (unsigned)n_ch, (unsigned)nkxc);
+  const int nthr = std::min(256, ((Lf + 63) / 64) * 64);
+#define TUFRG_L1(N)                                                                                                 \
+  hipLaunchKernelGGL(loop1_kernel<N>, grid, dim3(nthr), 0, st, Lq, n_ref, Lf, nD, dlist, e, kv, tw, lam, scheme, \
+                     deriv, ch_first, q_first, n_q, nkxc, kxper, part)
   if (nD <= 13)
     TUFRG_L1(13);
   else if (nD <= 25)
@@ -121,6 +147,9 @@ hipError_t launch_loop1(int Lq, int n_ref, int nD, const int *dlist, const doubl
   else
     return hipErrorInvalidValue;
 #undef TUFRG_L1
+  const long long n = (long long)n_ch * n_q * nD;
+  hipLaunchKernelGGL(loop1_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, nkxc, nD, inv,
+                     (const double2 *)part, (double2 *)out);
   return hipGetLastError();
 }
 

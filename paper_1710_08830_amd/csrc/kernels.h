@@ -49,6 +49,19 @@ struct LoopArgs {
                                // more orbitals [Nf][n_o][2] = (a_m, b_m); like band
 };
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
+// several two-orbital instances of one precision in fused launches (one per
+// kernel shape and regulator): instance i sums both channels over all its
+// coarse q into a[i].partial, with the work items of its own launch_loop.
+// desc_h (pinned host) and desc_d (device) hold n descriptors; desc_h is
+// rewritten, so the previous call's copies must be complete.
+struct No2Inst {
+  const void *ekv, *pi4, *cvp, *twk;
+  const double *tw;
+  void *partial;
+  double lam;
+  int Lq, n_ref, Lf, nkyb, nkxc, kxper, n_q, deriv, item0, pad;
+};
+hipError_t launch_loop_batch(const LoopArgs *a, int n, No2Inst *desc_h, No2Inst *desc_d, hipStream_t st);
 // more than two spin-orbitals (six: t2g with spin-orbit coupling)
 hipError_t launch_loop_gen(const LoopArgs &a, hipStream_t st);
 // six spin-orbitals on the matrix cores in the real basis of Hermitian
@@ -111,9 +124,11 @@ hipError_t launch_bundle_bf16x3(int n_o, int n_ff, int B, int nD, int n_q, const
 // SU(2)-reduced flow of one orbital (k_su2.hip): one-band loops into compact
 // [n_ch][n_q][nD] complex; X -> X^x; the gathers G[3][nD][B][B] of a~, c~, d~
 // from rA = (p, c)(rho), rB = (p^x, d)(rho); the reduced products per q (B <= 25)
+// (the kx range in nkxc chunks, partial sums in part of loop1_partial_doubles)
+size_t loop1_partial_doubles(int n_q, int nD, int nkxc);
 hipError_t launch_loop1(int Lq, int n_ref, int nD, const int *dlist, const double *e, const double *kv,
                         const double *tw, double lam, int scheme, int deriv, int ch_first, int n_ch, int q_first,
-                        int n_q, double *out, hipStream_t st);
+                        int n_q, int nkxc, double *part, double *out, hipStream_t st);
 hipError_t launch_su2_exch(int n_ff, int Nq, int Lq, const int *ff, const int *fneg, const double *twq,
                            const double *X, double *Xx, hipStream_t st);
 hipError_t launch_su2_gather(int B, int nD, const int *ff, const int *dlist, const int *ffgrid, const int *dgrid,

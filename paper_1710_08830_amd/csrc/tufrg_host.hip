@@ -354,9 +354,9 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     const int kxper = (c->Lf + c->nkxc - 1) / c->nkxc;
     c->nkxc = (c->Lf + kxper - 1) / kxper;
   } else if (c->n_o == 1) {
-    // the one-band loop kernel sums every k of a (q, channel) in one workgroup
+    // the one-band loop kernel: kx chunks so that about 2048 workgroups fill the chip
     c->nkyb = 1;
-    c->nkxc = 1;
+    c->nkxc = (int)std::max<long long>(1, std::min<long long>(c->Lf, (2048 + 2LL * c->Nq - 1) / (2LL * c->Nq)));
   } else {
     // the multi-orbital loop kernel sums every k of a (q, channel) in one workgroup
     c->nkyb = 1;
@@ -470,7 +470,8 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   CTRY(dalloc(c, &c->d_twq, 2 * (size_t)c->Lq));
   CTRY(dalloc(c, &c->d_dtab, c->nD + 81));
   const size_t nparts = (size_t)c->nkyb * c->nkxc;
-  c->partial_cap = 2 * 2 * (size_t)c->Nq * nparts * c->ndx * (2 * c->ndy + 1) * c->no4;
+  c->partial_cap = c->n_o == 1 ? loop1_partial_doubles(c->Nq, c->nD, c->nkxc)
+                               : 2 * 2 * (size_t)c->Nq * nparts * c->ndx * (2 * c->ndy + 1) * c->no4;
   CTRY(dalloc(c, &c->d_partial, c->partial_cap));
   CTRY(dalloc(c, &c->d_loop, 2 * 2 * (size_t)c->Nq * c->nD * c->no4));
   CTRY(dalloc(c, &c->d_ftpart, c->proj_ws));
@@ -777,7 +778,7 @@ static tufrg_status loops_range(tufrg_ctx *c, double lam, int deriv, int ch_firs
     if (rows) return fail(c, TUFRG_E_UNSUPPORTED, "sampled q rows need two or six spin-orbitals");
     HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
     HIPCHK(c, launch_loop1(c->Lq, c->n_ref, c->nD, c->d_dlist, c->d_band64, c->d_kv64, c->d_twf, lam, c->scheme,
-                           deriv, ch_first, n_ch, q_first, n_q, dst, c->st));
+                           deriv, ch_first, n_ch, q_first, n_q, c->nkxc, c->d_partial, dst, c->st));
     HIPCHK(c, timer_mark(c, TUFRG_TIMER_LOOP));
     return TUFRG_OK;
   }
@@ -1085,6 +1086,9 @@ static tufrg_status project_internal(tufrg_ctx *c, const double *P, const double
 }
 
 // dP = scale VP Lpp VP, dC = 2 scale VC Lph VC; a masked channel gets zero
+static tufrg_status rhs_products(tufrg_ctx *c, const double *P, const double *C, double *dP, double *dC, double scale,
+                                 unsigned mask);
+
 static tufrg_status rhs_internal(tufrg_ctx *c, double lam, const double *P, const double *C, double *dP, double *dC,
                                  double scale, unsigned mask) {
   const size_t BB = (size_t)c->B * c->B;
@@ -1099,6 +1103,14 @@ static tufrg_status rhs_internal(tufrg_ctx *c, double lam, const double *P, cons
       TRY(compute_loops(c, lam, 1, 1, 1));
     if (c->fres) c->fres->n_plain++;
   }
+  return rhs_products(c, P, C, dP, dC, scale, mask);
+}
+
+// the right-hand side once the loops of the masked channels are at d_loop:
+// projections, then the bundle products
+static tufrg_status rhs_products(tufrg_ctx *c, const double *P, const double *C, double *dP, double *dC, double scale,
+                                 unsigned mask) {
+  const size_t BB = (size_t)c->B * c->B;
   TRY(project_internal(c, P, C, c->d_VP, c->d_VC));
   const size_t lsz = 2 * (size_t)c->Nq * c->nD * c->no4;
   HIPCHK(c, timer_mark(c, TUFRG_TIMER_BUNDLE));
@@ -1952,6 +1964,10 @@ struct tufrg_batch {
   // lockstep steps in HIP graphs: the executable graph and the fork/join events
   hipGraphExec_t gexec = nullptr;
   std::vector<hipEvent_t> events;
+  // fused loop launches: instance descriptors (pinned host and device) and
+  // the join/fork events around them
+  No2Inst *desc_h = nullptr, *desc_d = nullptr;
+  std::vector<hipEvent_t> fev;
 };
 
 static thread_local std::string g_batch_err;
@@ -1969,6 +1985,12 @@ static void batch_free(tufrg_batch *b) {
   b->gexec = nullptr;
   for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
   b->events.clear();
+  for (hipEvent_t e : b->fev) (void)hipEventDestroy(e);
+  b->fev.clear();
+  if (b->desc_h) (void)hipHostFree(b->desc_h);
+  if (b->desc_d) (void)hipFree(b->desc_d);
+  b->desc_h = nullptr;
+  b->desc_d = nullptr;
   for (tufrg_ctx *c : b->ctx) tufrg_destroy(c);
   for (hipStream_t s : b->streams) (void)hipStreamDestroy(s);
   b->ctx.clear();
@@ -2061,14 +2083,95 @@ extern "C" tufrg_status tufrg_batch_flow(tufrg_batch *b, const tufrg_flow_opts *
   const int ns = o->n_steps;
   // one lockstep step of every active instance: enqueue, one wait for all,
   // then the stop tests
+  // fused loop launches (asked for): every instance two-orbital in one
+  // precision, both channels, no graphs (the work items and partial sums of
+  // each instance are those of its own launch)
+  bool fused = o->fused_loops && mask == 3u && !(o->graph_steps > 1);
+  for (int i = 0; i < n && fused; ++i)
+    fused = b->ctx[i]->n_o == 2 && b->ctx[i]->prec == b->ctx[0]->prec && !b->ctx[i]->timing;
+  if (o->fused_loops && !fused)
+    return bfail(b, TUFRG_E_UNSUPPORTED,
+                 "fused loop launches need two-orbital instances of one precision, both channels and no graphs");
+  if (fused) {
+    if (!b->desc_h && hipHostMalloc((void **)&b->desc_h, n * sizeof(No2Inst), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      b->desc_h = nullptr;
+      return bfail(b, TUFRG_E_NOMEM, "hipHostMalloc of the loop descriptors failed");
+    }
+    if (!b->desc_d && hipMalloc((void **)&b->desc_d, n * sizeof(No2Inst)) != hipSuccess) {
+      (void)hipGetLastError();
+      b->desc_d = nullptr;
+      return bfail(b, TUFRG_E_NOMEM, "hipMalloc of the loop descriptors failed");
+    }
+    while (b->fev.size() < b->streams.size()) {
+      hipEvent_t e;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, TUFRG_E_HIP, "hipEventCreate failed");
+      }
+      b->fev.push_back(e);
+    }
+    for (int i = 0; i < n; ++i)
+      if (!b->ctx[i]->d_dP) {
+        tufrg_ctx *c = b->ctx[i];
+        const size_t ns2 = 2 * (size_t)c->B * c->B * c->Nq;
+        if (dalloc(c, &c->d_dP, ns2) != TUFRG_OK || dalloc(c, &c->d_dC, ns2) != TUFRG_OK) return inst_fail(i);
+      }
+  }
+  // the loops of every active instance at l0 in fused launches on the first
+  // stream, after each instance's regulator values on its own stream; then
+  // each instance's stream waits for them
+  auto fused_loops = [&](double l0) -> tufrg_status {
+    std::vector<LoopArgs> la;
+    for (int i = 0; i < n; ++i) {
+      if (!active[i]) continue;
+      if (compute_kval(b->ctx[i], l0, 1) != TUFRG_OK) return inst_fail(i);
+      la.push_back(loop_args(b->ctx[i], l0, 1, 0, 2));
+    }
+    hipStream_t s0 = b->streams[0];
+    for (size_t k = 1; k < b->streams.size(); ++k)
+      if (hipEventRecord(b->fev[k], b->streams[k]) != hipSuccess || hipStreamWaitEvent(s0, b->fev[k], 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, TUFRG_E_HIP, "stream join failed");
+      }
+    if (launch_loop_batch(la.data(), (int)la.size(), b->desc_h, b->desc_d, s0) != hipSuccess) {
+      (void)hipGetLastError();
+      return bfail(b, TUFRG_E_HIP, "fused loop launch failed");
+    }
+    if (hipEventRecord(b->fev[0], s0) != hipSuccess) {
+      (void)hipGetLastError();
+      return bfail(b, TUFRG_E_HIP, "hipEventRecord failed");
+    }
+    for (size_t k = 1; k < b->streams.size(); ++k)
+      if (hipStreamWaitEvent(b->streams[k], b->fev[0], 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, TUFRG_E_HIP, "stream fork failed");
+      }
+    int j = 0;
+    for (int i = 0; i < n; ++i) {
+      if (!active[i]) continue;
+      tufrg_ctx *c = b->ctx[i];
+      if (launch_loop_finalize(la[j++], c->nD, c->d_dlist, c->d_loop, c->st) != hipSuccess) {
+        (void)hipGetLastError();
+        return bfail(b, TUFRG_E_HIP, "instance " + std::to_string(i) + ": loop finalize failed");
+      }
+    }
+    return TUFRG_OK;
+  };
   auto direct_step = [&](int s) -> tufrg_status {
     const double l0 = euler_lambda(o, s), l1 = euler_lambda(o, s + 1);
+    if (fused) {
+      const tufrg_status fs = fused_loops(l0);
+      if (fs != TUFRG_OK) return fs;
+    }
     for (int i = 0; i < n; ++i) {
       if (!active[i]) continue;
       tufrg_ctx *c = b->ctx[i];
       double *Pi = (double *)P[i], *Ci = (double *)C[i];
       const long long ncx = (long long)c->B * c->B * c->Nq;
-      if (rhs_internal(c, l0, Pi, Ci, c->d_dP, c->d_dC, 1.0, mask) != TUFRG_OK) return inst_fail(i);
+      if ((fused ? rhs_products(c, Pi, Ci, c->d_dP, c->d_dC, 1.0, mask)
+                 : rhs_internal(c, l0, Pi, Ci, c->d_dP, c->d_dC, 1.0, mask)) != TUFRG_OK)
+        return inst_fail(i);
       if (launch_clear_reduce(c->d_bits, c->d_flag, c->st) != hipSuccess ||
           launch_axpy_max(ncx, Pi, l1 - l0, c->d_dP, Pi, c->d_bits, c->d_flag, c->st) != hipSuccess ||
           launch_axpy_max(ncx, Ci, l1 - l0, c->d_dC, Ci, c->d_bits, c->d_flag, c->st) != hipSuccess ||

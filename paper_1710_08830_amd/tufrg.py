@@ -79,7 +79,8 @@ class FlowOpts(ctypes.Structure):
                 ("on_step", STEP_CB), ("user", ctypes.c_void_p),
                 ("surrogate", ctypes.c_int32), ("sample_frac", ctypes.c_double),
                 ("sur_tol", ctypes.c_double), ("plain_above", ctypes.c_double),
-                ("sample_seed", ctypes.c_uint64), ("graph_steps", ctypes.c_int32)]
+                ("sample_seed", ctypes.c_uint64), ("graph_steps", ctypes.c_int32),
+                ("fused_loops", ctypes.c_int32)]
 
 
 class FlowResult(ctypes.Structure):
@@ -587,10 +588,11 @@ class Batch:
 
 
 def tufrg_batch_flow(batch, Ps, Cs, lambda0, lambda_end, n_steps, v_max=50.0, channel_mask=3, max_steps=0,
-                     graph_steps=0):
+                     graph_steps=0, fused_loops=False):
     """Lockstep Euler flow of every instance (P, C in place); list of result
     dicts.  graph_steps > 1: that many lockstep steps of all instances per HIP
-    graph."""
+    graph.  fused_loops: the loop kernels of all (two-orbital) instances in one
+    launch per kernel shape instead of one per instance."""
     n = batch.n
     if len(Ps) != n or len(Cs) != n:
         raise ValueError(f"one P and one C per instance ({n})")
@@ -598,7 +600,8 @@ def tufrg_batch_flow(batch, Ps, Cs, lambda0, lambda_end, n_steps, v_max=50.0, ch
     pp = (_vp * n)(*[_arr(x, "c128", m, f"P[{i}]") for i, (x, m) in enumerate(zip(Ps, sizes))])
     cp = (_vp * n)(*[_arr(x, "c128", m, f"C[{i}]") for i, (x, m) in enumerate(zip(Cs, sizes))])
     o = FlowOpts(float(lambda0), float(lambda_end), int(n_steps), 0.0, 0.0, 0.0, float(v_max),
-                 int(channel_mask), int(max_steps), STEP_CB(), None, 0, 0.0, 0.0, 0.0, 0, int(graph_steps))
+                 int(channel_mask), int(max_steps), STEP_CB(), None, 0, 0.0, 0.0, 0.0, 0, int(graph_steps),
+                 int(bool(fused_loops)))
     res = (FlowResult * n)()
     batch._check(_lib.tufrg_batch_flow(batch.handle, ctypes.byref(o), pp, cp, res))
     return [r.as_dict() for r in res]

@@ -56,11 +56,16 @@ def _single(T, w, prec, n_steps, lam0=10.0, lam_end=1.0, **kw):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_equals_single_flows(T, prec):
+@pytest.mark.parametrize("fused", [False, True])
+def test_batch_equals_single_flows(T, prec, fused):
+    """Loop launches per instance (the default) and fused ones (one launch
+    per kernel shape over all instances, S5/S9 and S13 shapes here) give every
+    instance its own flow bit for bit."""
+    print(f"batch: {prec} fused_loops={fused}", flush=True)
     ws = _small_batch()
     b = T.Batch(ws, precision=prec, n_streams=3)
     Ps, Cs = zip(*[_state(d) for d in b.dims])
-    res = T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=6)
+    res = T.tufrg_batch_flow(b, Ps, Cs, 10.0, 1.0, n_steps=6, fused_loops=fused)
     torch.cuda.synchronize()
     for i, w in enumerate(ws):
         r, P, C = _single(T, w, prec, 6)

@@ -120,7 +120,7 @@ struct tufrg_ctx {
   double *d_lamb = nullptr;                    // BF16X3 loops: real-basis sums of a chunk
   int *d_hmap = nullptr;                       // BF16X3 loops: half-plane point of each difference vector
   int mfma_chunk = 0;
-  int mfma_kxr = 2;        // kx rows per work item of the matrix-core loop (tunable)
+  int mfma_kxr = 1;        // kx rows per work item of the matrix-core loop (tunable)
   void *d_apre = nullptr;  // the matrix-core loop's precomputed A operand (once per context)
   size_t partial_cap = 0;  // doubles allocated at d_partial
   unsigned long long *h_sbits = nullptr;       // pinned
@@ -743,8 +743,26 @@ static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch
     c->d_apre = ap;
   }
   if (!c->d_yrow || !c->d_lamb) {
-    // whole q_x rows per chunk, about 256 coarse q (64 groups of four)
+    // whole q_x rows per chunk, about 256 coarse q (64 groups of four); where
+    // some 256..512 q make a group count that is a multiple of the
+    // workgroups one XCD runs at once (one per CU), that size: the work items
+    // of one kx block then start together on their XCD and read its A
+    // operand from L2 in step (a quarter of the fabric traffic of a ragged
+    // count on the 48 x 48 mesh)
     c->mfma_chunk = std::max(1, 256 / c->Lq) * c->Lq;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) {
+      (void)hipGetLastError();
+      ncu = 0;
+    }
+    const int per_xcd = ncu / 8;
+    for (int m = 1; per_xcd > 0 && m * c->Lq <= 512; ++m) {
+      const int nq = m * c->Lq;
+      if (nq >= 256 && nq % 4 == 0 && (nq / 4) % per_xcd == 0) {
+        c->mfma_chunk = nq;
+        break;
+      }
+    }
     const size_t groups = (size_t)(c->mfma_chunk + 3) / 4;
     if (!c->d_yrow) TRY(dalloc(c, &c->d_yrow, groups * loop_rb_rowbuf_floats(c->ndy, c->Lf)));
     int hx[32], hy[32];
@@ -920,8 +938,8 @@ extern "C" tufrg_status tufrg_autotune(tufrg_ctx *c, double lambda, const char *
       if (std::find(cand.begin(), cand.end(), n) == cand.end()) cand.push_back(n);
     }
   } else {
-    cand = {def, 1, 4};
-    if (def != 2) cand.push_back(2);
+    for (int v : {def, 1, 2, 4})
+      if (std::find(cand.begin(), cand.end(), v) == cand.end()) cand.push_back(v);
   }
   double best = INFINITY;
   int best_v = def;

@@ -330,34 +330,35 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
   };
 
   f32x4 acc[MTW][NCT];
-
-  // products of tile t (B operand in buffer bb) for this wave's row tiles; the
-  // A fragments of each K step come from the precomputed operand (in L2), the
-  // next step's loads in flight during the current step's products
-  auto mfma_tile = [&](int bb, int t) __attribute__((always_inline)) {
-    const unsigned char *bh = sB[bb][0], *bl = sB[bb][1];
-    const int kx = kx0 + t / ntk, tk = t - (t / ntk) * ntk;
-    const bf16x8 *ab = apre + ((size_t)kx * ntk + tk) * KS * MT * 2 * 64 + lane;
-    bf16x8 ah[MTW], al[MTW];
+  // A fragments of the first K step of the tile about to be multiplied: the
+  // last K step of each tile loads those of the next, so they arrive during
+  // that step's products, the B-operand work and the barriers
+  bf16x8 ah[MTW], al[MTW];
+  auto load_a = [&](int t, int s, bf16x8 *h, bf16x8 *l) __attribute__((always_inline)) {
+    // tiles are stored in work order: tile t of this item at kx0 * ntk + t
+    const bf16x8 *ab = apre + (((size_t)kx0 * ntk + t) * KS + s) * MT * 128 + lane;
 #pragma unroll
     for (int jt = 0; jt < MTW; ++jt)
       if (wv + NW * jt < MT) {
         const int mt = wv + NW * jt;
-        ah[jt] = ab[(size_t)mt * 128];
-        al[jt] = ab[(size_t)mt * 128 + 64];
+        h[jt] = ab[(size_t)mt * 128];
+        l[jt] = ab[(size_t)mt * 128 + 64];
       }
+  };
+
+  // products of tile t (B operand in buffer bb) for this wave's row tiles; the
+  // A fragments of each K step come from the precomputed operand (in L2), the
+  // next step's loads (at the last step: the next tile's first) in flight
+  // during the current step's products
+  auto mfma_tile = [&](int bb, int t) __attribute__((always_inline)) {
+    const unsigned char *bh = sB[bb][0], *bl = sB[bb][1];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       bf16x8 nh[MTW], nl[MTW];
-      if (s + 1 < KS) {
-#pragma unroll
-        for (int jt = 0; jt < MTW; ++jt)
-          if (wv + NW * jt < MT) {
-            const int mt = wv + NW * jt;
-            nh[jt] = ab[((size_t)(s + 1) * MT + mt) * 128];
-            nl[jt] = ab[((size_t)(s + 1) * MT + mt) * 128 + 64];
-          }
-      }
+      if (s + 1 < KS)
+        load_a(t, s + 1, nh, nl);
+      else if (t + 1 < ntile)
+        load_a(t + 1, 0, nh, nl);
       // column tiles in order, the B fragments of the next one loaded while
       // the products of this one run (no further hoisting: the scheduling
       // barrier keeps the live B fragments at two)
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
         blv = bln;
         __builtin_amdgcn_sched_barrier(0);
       }
-      if (s + 1 < KS) {
+      if (s + 1 < KS || t + 1 < ntile) {
 #pragma unroll
         for (int jt = 0; jt < MTW; ++jt) {
           ah[jt] = nh[jt];
@@ -414,6 +415,7 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
 
   // prologue: tile 0 staged and its B operand built, tile 1 in flight
   Pre pr;
+  load_a(0, 0, ah, al);
   fetch(0, pr);
   stage(pr);
   __syncthreads();

@@ -174,8 +174,9 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
 
   __shared__ __align__(16) unsigned char sB[2][2][KS * NCT * 64 * 16];  // [buffer][hi, lo] granules
   __shared__ __align__(16) float sL[NQG][KT][NO * NO];                    // loop kernels L_mn
-  // e_m, K_m at (kx, ky) [slot 0] and at k'(q, ky) [slots 1..4]; shell: then (a_m, b_m)
-  __shared__ __align__(16) float sE[KT][1 + NQG][PER];
+  // e_m, K_m at (kx, ky) [slot 0] and at k'(q, ky) [slots 1..4]; shell: then
+  // (a_m, b_m); two tiles (staged one tile ahead of their loop kernels)
+  __shared__ __align__(16) float sE[2][KT][1 + NQG][PER];
   __shared__ int sQf[1 + NQG][2];  // fine-mesh offsets of the group's q (slot 0: zero)
 
   if (tid <= NQG) {
@@ -252,16 +253,18 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
       }
     }
   };
-  auto stage = [&](const Pre &pr) __attribute__((always_inline)) {
+  auto stage = [&](const Pre &pr, int eb) __attribute__((always_inline)) {
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
       for (int u = 0; u < NEVU; ++u)
-        if (lane + 64 * u < (1 + NQG) * PER) (&sE[2 * wv + kk][0][0])[lane + 64 * u] = pr.ev[kk][u];
+        if (lane + 64 * u < (1 + NQG) * PER) (&sE[eb][2 * wv + kk][0][0])[lane + 64 * u] = pr.ev[kk][u];
   };
-  // loop kernels L_mn of this thread's (q, ky): (m, n) = divmod(dsub + 8 i, 6)
-  auto loop_kernels = [&]() __attribute__((always_inline)) {
-    const float *e0 = sE[dky][0], *e1 = sE[dky][1 + dq];
+  // loop kernels L_mn of this thread's (q, ky): (m, n) = divmod(dsub + 8 i, 6).
+  // The eight threads of one (q, ky) are lanes of one wave, and so are those
+  // that read these L_mn for the B operand: no barrier between the two.
+  auto loop_kernels = [&](int eb) __attribute__((always_inline)) {
+    const float *e0 = sE[eb][dky][0], *e1 = sE[eb][dky][1 + dq];
 #pragma unroll
     for (int i = 0; i < (NO * NO + NBT - 1) / NBT; ++i) {
       const int mn = dsub + NBT * i;
@@ -415,14 +418,19 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
 
   // prologue: tile 0 staged and its B operand built, tile 1 in flight
   Pre pr;
+  // prologue: tiles 0 and 1 staged, the B operand of tile 0 built, tile 2 in
+  // flight
   load_a(0, 0, ah, al);
   fetch(0, pr);
-  stage(pr);
+  stage(pr, 0);
+  if (1 < ntile) {
+    fetch(1, pr);
+    stage(pr, 1);
+  }
   __syncthreads();
-  loop_kernels();
-  __syncthreads();
+  loop_kernels(0);
   build_b(0, 0);
-  if (1 < ntile) fetch(1, pr);
+  if (2 < ntile) fetch(2, pr);
   __syncthreads();
   int t = 0;
   for (int r = 0; r < nrow; ++r) {
@@ -431,20 +439,24 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
 #pragma unroll
       for (int n = 0; n < NCT; ++n) acc[jt][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int tk = 0; tk < ntk; ++tk, ++t) {
-      // LDS holds B of tile t (buffer bb); registers the band values of tile
-      // t + 1
+      // LDS holds B of tile t (buffer bb) and the band values of tile t + 1
+      // (buffer (t + 1) & 1); registers those of tile t + 2.  One barrier per
+      // tile: the vector work for tile t + 1 (loop kernels, B operand, staging
+      // of tile t + 2) of one wave of a SIMD runs beside the other's matrix ops
       const int bb = t & 1;
-      const bool next = t + 1 < ntile;
-      if (next) stage(pr);
-      __syncthreads();
-      if (next) loop_kernels();
-      __syncthreads();
-      if (!mfma_first && next) build_b(bb ^ 1, t + 1);
+      auto vector_work = [&]() __attribute__((always_inline)) {
+        if (t + 1 < ntile) {
+          loop_kernels(bb ^ 1);
+          build_b(bb ^ 1, t + 1);
+        }
+        if (t + 2 < ntile) stage(pr, bb);
+        // band values of tile t + 3: in flight during the matrix ops and the
+        // barrier
+        if (t + 3 < ntile) fetch(t + 3, pr);
+      };
+      if (!mfma_first) vector_work();
       mfma_tile(bb, t);
-      // band values of tile t + 2: in flight during the other wave's matrix
-      // ops (or this wave's B-operand work) and the barrier
-      if (t + 2 < ntile) fetch(t + 2, pr);
-      if (mfma_first && next) build_b(bb ^ 1, t + 1);
+      if (mfma_first) vector_work();
       __syncthreads();
     }
     write_row(kx0 + r);

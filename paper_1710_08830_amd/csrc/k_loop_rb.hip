@@ -220,7 +220,6 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
   // loop kernels and B operand: thread (q column dq, ky dky, part dsub)
   const int dq = tid / (KT * NBT), dky = (tid / NBT) % KT, dsub = tid % NBT;
   const int nb = dsub < 4 ? 5 : 4, be0 = dsub < 4 ? 5 * dsub : 20 + 4 * (dsub - 4);
-  const bool bq_valid = NQG * g + dq < n_q;
   const int bqfx = sQf[1 + dq][0], bqfy = sQf[1 + dq][1];
   // B-operand byte offsets: column part per beta, K part per band pair
   int bcol[NBS], bk[NO / 2];
@@ -279,8 +278,10 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
   };
   // B operand: w_m^beta = sum_n L_mn X_n^beta for this thread's (q, ky) and
   // beta set, split, as BF16 pairs (m, m + 1) of the columns (q, beta); a q
-  // past the end of the list gets a zero column.  ph takes the transpose of
-  // X: the imaginary coordinates change sign.
+  // past the end of the list repeats the last one (its columns are never
+  // read).  ph takes the transpose of X, whose imaginary coordinates change
+  // sign: applied to the columns in the kx sums (the products are linear and
+  // the rounding symmetric, so the result is the same).
   auto build_b = [&](int bb, int t) __attribute__((always_inline)) {
     // packed X_n(k') of this thread's (q, ky) and beta set (L2-resident rows;
     // the load latency is covered by the matrix ops of the other wave of
@@ -293,12 +294,6 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
       for (int n = 0; n < NO; ++n)
 #pragma unroll
         for (int i = 0; i < NBS; ++i) xi[n][i] = src[n * NA + min(i, nb - 1)];
-    }
-    float sgn[NBS];
-#pragma unroll
-    for (int i = 0; i < NBS; ++i) {
-      const int be = be0 + min(i, nb - 1);
-      sgn[i] = !bq_valid ? 0.f : (ch == 1 && be >= NO && ((be - NO) & 1)) ? -1.f : 1.f;
     }
     unsigned char *bh = sB[bb][0], *bl = sB[bb][1];
 #pragma unroll
@@ -324,7 +319,7 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
           w1 = fmaf(L1[n], xi[n][i], w1);
         }
         unsigned h, l;
-        split2(sgn[i] * w0, sgn[i] * w1, h, l);
+        split2(w0, w1, h, l);
         const int off = bcol[i] + bk[mp];
         *(unsigned *)(bh + off) = h;
         *(unsigned *)(bl + off) = l;
@@ -490,7 +485,7 @@ struct Half<2> {
 template <int NDY>
 __global__ __launch_bounds__(256) void loop_rb_rowsum_kernel(const float *__restrict__ Y,
                                                              const double *__restrict__ tw, int Lf, int n_q,
-                                                             double *__restrict__ lam_out) {
+                                                             int ch, double *__restrict__ lam_out) {
   using S = RB<NDY>;
   using H = Half<NDY>;
   constexpr int ROWS = S::ROWS;
@@ -538,12 +533,14 @@ __global__ __launch_bounds__(256) void loop_rb_rowsum_kernel(const float *__rest
       }
     }
   }
-  // lam_out[q][h][alpha][beta] complex
+  // lam_out[q][h][alpha][beta] complex; ph: the imaginary coordinates beta
+  // of the transposed X change sign
+  const double sg = (ch == 1 && beta >= NO && ((beta - NO) & 1)) ? -1.0 : 1.0;
 #pragma unroll
   for (int h = 0; h < H::N; ++h) {
     const size_t o = (((size_t)q * H::N + h) * NA + alpha) * NA + beta;
-    lam_out[2 * o] = zr[h];
-    lam_out[2 * o + 1] = zi[h];
+    lam_out[2 * o] = sg * zr[h];
+    lam_out[2 * o + 1] = sg * zi[h];
   }
 }
 
@@ -694,19 +691,19 @@ hipError_t launch_loop_rb(const LoopArgs &a, int ch, const void *apre, float *Y,
 // of dlist[iD] (low 16 bits) and 1 << 16 where it is the reflected one
 hipError_t launch_loop_rb_sums(const LoopArgs &a, const float *Y, double *lamb, const int *hmap, int nD,
                                double *dst, hipStream_t st) {
-  if (!Y || !lamb || !hmap || !dst) return hipErrorInvalidValue;
+  if (!Y || !lamb || !hmap || !dst || a.n_ch != 1) return hipErrorInvalidValue;
   const int n_groups = (a.n_q + NQG - 1) / NQG;
   const long long nt = (long long)n_groups * NQG * NA * NA;
   const long long nf = (long long)a.n_q * nD * NO * NO * NO * NO;
   const double inv = 1.0 / ((double)a.Lf * a.Lf);
   if (a.ndy == 4) {
     hipLaunchKernelGGL(loop_rb_rowsum_kernel<4>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, Y, a.tw, a.Lf,
-                       a.n_q, lamb);
+                       a.n_q, a.ch_first, lamb);
     hipLaunchKernelGGL(loop_rb_finalize_kernel<4>, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, a.n_q, nD,
                        hmap, inv, lamb, dst);
   } else if (a.ndy == 2) {
     hipLaunchKernelGGL(loop_rb_rowsum_kernel<2>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, Y, a.tw, a.Lf,
-                       a.n_q, lamb);
+                       a.n_q, a.ch_first, lamb);
     hipLaunchKernelGGL(loop_rb_finalize_kernel<2>, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, a.n_q, nD,
                        hmap, inv, lamb, dst);
   } else {

@@ -878,6 +878,49 @@ def summarize_trace(args):
     print(out_path)
 
 
+def summarize_counters(args):
+    """A markdown table of the SQ counters of a rocprofv3 --pmc run, summed
+    over the dispatches of the loop kernel and divided by their number, with
+    the instruction counts per wave and tile of 16 ky (BF16X3 loop kernel)."""
+    csv_path, cmd, out_path = args.summarize_counters
+    kname = "loop_rb_kernel" if args.prec == "bf16x3" else (
+        "loop_gen_kernel" if args.workload.startswith("t2g") else "loop_no2_kernel")
+    import csv
+    names, disp = set(), set()
+    with open(csv_path, newline="") as fh:
+        rows = [r for r in csv.DictReader(fh) if kname in r["Kernel_Name"]]
+    if not rows:
+        raise RuntimeError(f"no rows for kernels matching {kname!r} in {csv_path}")
+    tot = {}
+    for r in rows:
+        tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        disp.add(r["Dispatch_Id"])
+        names.add(r["Kernel_Name"])
+    n = len(disp)
+    lines = [f"# SQ counters of the loop kernel: {args.workload} ({args.prec})", "", "Command:", "", "```", cmd, "```",
+             "", f"Kernel: `{sorted(names)[0][:120]}`, {n} dispatches.", "",
+             "| counter | per dispatch |", "|---|---|"]
+    for k in sorted(tot):
+        lines.append(f"| {k} | {tot[k] / n:.4g} |")
+    if args.prec == "bf16x3" and "SQ_WAVES" in tot:
+        from synth import workload
+        w = workload(args.workload)
+        lf = w["Lq"] * w["n_ref"]
+        tiles = (lf + 15) // 16  # ky tiles per kx row; one kx row per work item
+        per = lambda c: tot[c] / tot["SQ_WAVES"] / tiles
+        lines += ["", "Per wave and tile of 16 ky (one kx row per work item, "
+                  f"{tiles} tiles):", ""]
+        for c in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS"):
+            if c in tot:
+                lines.append(f"* {c}: {per(c):.0f}")
+        if "SQ_LDS_BANK_CONFLICT" in tot and "SQ_INSTS_LDS" in tot:
+            lines.append(f"* bank-conflict cycles per LDS instruction: "
+                         f"{tot['SQ_LDS_BANK_CONFLICT'] / tot['SQ_INSTS_LDS']:.2f}")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(out_path)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -908,13 +951,17 @@ def main():
                          "(CPU only)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("KERNEL_STATS_CSV", "COMMAND", "OUT_MD"),
                     help="write a markdown summary of a rocprofv3 --stats run (CPU only)")
+    ap.add_argument("--summarize-counters", nargs=3, metavar=("COUNTER_CSV", "COMMAND", "OUT_MD"),
+                    help="write a markdown summary of a rocprofv3 --pmc run of SQ counters (CPU only)")
     args = ap.parse_args()
-    if args.summarize_traffic or args.summarize_trace:
+    if args.summarize_traffic or args.summarize_trace or args.summarize_counters:
         args.prec = args.prec or ("bf16x3" if args.workload.startswith("t2g") else "fp32")
         if args.summarize_traffic:
             summarize_traffic(args)
         if args.summarize_trace:
             summarize_trace(args)
+        if args.summarize_counters:
+            summarize_counters(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the q-sharded multi-GPU "

@@ -97,3 +97,28 @@ def test_trace_summary_from_kernel_stats(tmp_path):
     rows = [r for r in text if r.startswith("| `")]
     assert rows[0].startswith("| `big` | 2 | 0.009 | 4.5") and "90.0 %" in rows[0]
     assert "rocprofv3 ... -- python3 bench.py" in text
+
+
+def test_counter_summary_per_dispatch_and_per_wave_tile(tmp_path):
+    """SQ counters of the loop kernel summed per dispatch (other kernels
+    ignored) and divided per wave and ky tile: 48 x 16 / 16 = 48 tiles per
+    wave on the 48 x 48 mesh refined 16x."""
+    sys.path.insert(0, ROOT)
+    import argparse
+
+    import bench
+    k = "void tufrg::loop_rb_kernel<4, 0>(float const*)"
+    rows = []
+    for d in (1, 2):
+        rows += [(d, k, "SQ_WAVES", 100), (d, k, "SQ_INSTS_VALU", 100 * 48 * 500),
+                 (d, k, "SQ_INSTS_MFMA", 100 * 48 * 200), (d, k, "SQ_INSTS_LDS", 100 * 48 * 50),
+                 (d, k, "SQ_LDS_BANK_CONFLICT", 100 * 48 * 25), (d, "other_kernel", "SQ_WAVES", 7)]
+    _counter_csv(tmp_path / "sq.csv", rows)
+    out = tmp_path / "sq.md"
+    args = argparse.Namespace(summarize_counters=[str(tmp_path / "sq.csv"), "rocprofv3 --pmc ...", str(out)],
+                              workload="t2g_s13_L48", prec="bf16x3")
+    bench.summarize_counters(args)
+    text = out.read_text()
+    assert "2 dispatches" in text and "| SQ_WAVES | 100 |" in text and "rocprofv3 --pmc ..." in text
+    assert "SQ_INSTS_VALU: 500" in text and "SQ_INSTS_MFMA: 200" in text and "SQ_INSTS_LDS: 50" in text
+    assert "per LDS instruction: 0.50" in text

@@ -282,6 +282,21 @@ typedef struct {
  * loops.  Call it outside flows and graph captures. */
 tufrg_status tufrg_autotune(tufrg_ctx *ctx, double lambda, const char *cache_path, tufrg_tune_result *res);
 
+/* Kramers-paired bands in the BF16X3 loops (no passage: an implementation
+ * choice that the sum over bands of the Sec. 3.1 loop permits).  When the six
+ * bands of a BF16X3 context are degenerate in pairs (0,1), (2,3), (4,5) at
+ * every k of the fine mesh (time reversal with inversion symmetry; checked at
+ * creation: splittings at most 1e-10 max(1, max |e|)) and L_f is even, the
+ * loops sum each degenerate pair first: three energies and three summed
+ * projectors, so half the matrix-core work and about a third of the vector
+ * work per k.  Exact for exactly degenerate bands; the eigensolver's
+ * splittings (about 1e-14) change the loops far below the BF16X3 rounding.
+ * enable = 1 (the default) uses the pairs where they were found, 0 always
+ * uses the six bands; *active (may be NULL) receives whether the pairs are in
+ * use.  The next loop evaluation rebuilds the precomputed A operand if the
+ * choice changed.  Errors: E_INVAL for a null context or enable not 0 or 1. */
+tufrg_status tufrg_pair_bands(tufrg_ctx *ctx, int32_t enable, int32_t *active);
+
 /* The third channel (Sec. 3.2): D_{n1n2n3n4} = -C_{n1n2n4n3}, which the
  * antisymmetry of the vertex fixes, so only P and C flow.  C and D are device
  * arrays [Nq][B][B] on the context's device; D is written in the layout of C,

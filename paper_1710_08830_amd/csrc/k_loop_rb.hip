@@ -104,12 +104,13 @@ __device__ inline int bpair_off(int K, int col) {
 // past the mesh are zero.  The split is that of the FP32 product (the
 // compiler may form the remainder from the unrounded product, a last-bit
 // difference of lo: loops agree with an in-kernel build to about 2e-9).
-template <int NDY>
+template <int NDY, bool PAIR>
 __global__ __launch_bounds__(256) void loop_rb_apre_kernel(const float *__restrict__ band,
+                                                           const float *__restrict__ pir,
                                                            const float *__restrict__ phy, int Lf,
                                                            u32x4 *__restrict__ apre) {
   using S = RB<NDY>;
-  const int ntk = (Lf + KT - 1) / KT;
+  const int ntk = ((PAIR ? Lf / 2 : Lf) + KT - 1) / KT;
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const long long total = (long long)Lf * ntk * KS * S::MT * 64;
   if (gid >= total) return;
@@ -124,11 +125,15 @@ __global__ __launch_bounds__(256) void loop_rb_apre_kernel(const float *__restri
   float v[8];
 #pragma unroll
   for (int t = 0; t < 8; ++t) {
-    const int K = 32 * s + 8 * (lane >> 4) + t, ky = tk * KT + K / NO, m = K % NO;
+    // K = (v, m'): point v of the tile, band m' (paired: ky = 2 v + m' / 3 and
+    // the pair m' % 3)
+    const int K = 32 * s + 8 * (lane >> 4) + t, vk = tk * KT + K / NO, mv = K % NO;
+    const int ky = PAIR ? 2 * vk + mv / 3 : vk, m = PAIR ? mv % 3 : mv;
     float f = 0.f, pv = 0.f;
     if (row < S::ROWS && ky < Lf) {
       f = ph == 0 ? 1.f : ph <= NDY ? phy[((size_t)ky * NDY + ph - 1) * 2] : -phy[((size_t)ky * NDY + ph - NDY - 1) * 2 + 1];
-      pv = band[((size_t)kx * Lf + ky) * NC + NO + m * NA + alpha];
+      pv = PAIR ? pir[((size_t)kx * Lf + ky) * (3 * NA) + m * NA + alpha]
+                : band[((size_t)kx * Lf + ky) * NC + NO + m * NA + alpha];
     }
     v[t] = pv * f;
   }
@@ -145,11 +150,12 @@ __global__ __launch_bounds__(256) void loop_rb_apre_kernel(const float *__restri
   apre[o + 64] = l;
 }
 
-template <int NDY, int SCHEME>
+template <int NDY, int SCHEME, bool PAIR>
 __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
-    const float *__restrict__ band, const float *__restrict__ kv, const float *__restrict__ cvp,
-    const bf16x8 *__restrict__ apre, int Lq, int n_ref, int Lf, int q_first, int n_q, const int *__restrict__ rows,
-    int ch, float lam, int deriv, int n_groups, int n_kxb, int kxr, float *__restrict__ Y) {
+    const float *__restrict__ band, const float *__restrict__ pir, const float *__restrict__ kv,
+    const float *__restrict__ cvp, const bf16x8 *__restrict__ apre, int Lq, int n_ref, int Lf, int q_first,
+    int n_q, const int *__restrict__ rows, int ch, float lam, int deriv, int n_groups, int n_kxb, int kxr,
+    float *__restrict__ Y) {
   using S = RB<NDY>;
   constexpr int MT = S::MT, MTW = S::MTW, ROWS = S::ROWS;
   constexpr bool SHELL = SCHEME == CUT_SHELL;
@@ -163,7 +169,9 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
   const int g = j % n_groups, kxb = xcd + 8 * (j / n_groups);
   if (kxb >= n_kxb) return;
   const int kx0 = kxb * kxr, nrow = min(kxr, Lf - kx0);
-  const int ntk = (Lf + KT - 1) / KT, ntile = nrow * ntk;
+  // points v of a kx row: each ky (six bands), or paired: ky 2 v and 2 v + 1
+  // with three pairs each, as six bands m' = 3 (ky - 2 v) + pair
+  const int ntk = ((PAIR ? Lf / 2 : Lf) + KT - 1) / KT, ntile = nrow * ntk;
 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -204,7 +212,7 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
 
   // ---- per-thread constants -------------------------------------------------
   // band values: lane index i = lane + 64 u < (1 + NQG) PER: slot, kind, band
-  int ev_slot[NEVU], ev_off[NEVU];
+  int ev_slot[NEVU], ev_off[NEVU], ev_dky[NEVU];
   const float *ev_src[NEVU];
   int ev_stride[NEVU];
 #pragma unroll
@@ -212,8 +220,12 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
     const int i = min(lane + 64 * u, (1 + NQG) * PER - 1);
     // per slot: e_0..e_5, K_0..K_5, then (shell) a_0, b_0, a_1, b_1, ... as in cvp
     const int slot = i / PER, r = i % PER, kind = r < NO ? 0 : r < 2 * NO ? 1 : 2;
+    const int off = r - NO * kind, mv = kind == 2 ? off / 2 : off;
+    // paired: band m' is the first band 2 (m' % 3) of a pair at ky 2 v + m' / 3
+    const int mb = PAIR ? 2 * (mv % 3) : mv;
     ev_slot[u] = slot;
-    ev_off[u] = r - NO * kind;
+    ev_off[u] = kind == 2 ? 2 * mb + (off & 1) : mb;
+    ev_dky[u] = PAIR ? mv / 3 : 0;
     ev_src[u] = kind == 0 ? band : kind == 1 ? kv : cvp;
     ev_stride[u] = kind == 0 ? NC : kind == 1 ? NO : 2 * NO;
   }
@@ -243,10 +255,12 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
     const int kx = kx0 + t / ntk, ky0 = (t - (t / ntk) * ntk) * KT;
 #pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      const int ky = min(ky0 + 2 * wv + kk, Lf - 1);  // ky past the mesh: any point (zero A rows)
+      const int v = ky0 + 2 * wv + kk;
 #pragma unroll
       for (int u = 0; u < NEVU; ++u) {
         const int sl = ev_slot[u];
+        // ky past the mesh: any point (zero A rows)
+        const int ky = min(PAIR ? 2 * v + ev_dky[u] : v, Lf - 1);
         const int k = kpt(sQf[sl][0], sQf[sl][1], sl == 0, kx, ky);
         pr.ev[kk][u] = ev_src[u][(size_t)k * ev_stride[u] + ev_off[u]];
       }
@@ -264,11 +278,15 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
   // that read these L_mn for the B operand: no barrier between the two.
   auto loop_kernels = [&](int eb) __attribute__((always_inline)) {
     const float *e0 = sE[eb][dky][0], *e1 = sE[eb][dky][1 + dq];
+    // paired: only the two diagonal 3 x 3 blocks (bands of the same ky)
+    constexpr int NMN = PAIR ? 18 : NO * NO;
 #pragma unroll
-    for (int i = 0; i < (NO * NO + NBT - 1) / NBT; ++i) {
-      const int mn = dsub + NBT * i;
-      if (mn < NO * NO) {
-        const int m = mn / NO, n = mn - NO * (mn / NO);
+    for (int i = 0; i < (NMN + NBT - 1) / NBT; ++i) {
+      const int j = dsub + NBT * i;
+      if (j < NMN) {
+        const int m = PAIR ? 3 * (j / 9) + (j % 9) / 3 : j / NO;
+        const int n = PAIR ? 3 * (j / 9) + j % 3 : j - NO * (j / NO);
+        const int mn = NO * m + n;
         float l = sg * divided_difference(e0[m], -sg * e1[n], e0[NO + m], -sg * e1[NO + n], lam, dd_scheme(SCHEME),
                                           deriv);
         if constexpr (SHELL) l *= fmaf(e0[2 * NO + 2 * m], e1[2 * NO + 2 * n + 1], e0[2 * NO + 2 * m + 1] * e1[2 * NO + 2 * n]);
@@ -288,12 +306,26 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
     // the SIMD)
     float xi[NO][NBS];
     {
-      const int kx = kx0 + t / ntk, ky = min((t - (t / ntk) * ntk) * KT + dky, Lf - 1);
-      const float *src = band + (size_t)kpt(bqfx, bqfy, false, kx, ky) * NC + NO + be0;
+      const int kx = kx0 + t / ntk, v = (t - (t / ntk) * ntk) * KT + dky;
+      if constexpr (PAIR) {
+        // pair sums of the projectors at k' of ky 2 v and 2 v + 1
 #pragma unroll
-      for (int n = 0; n < NO; ++n)
+        for (int h = 0; h < 2; ++h) {
+          const int ky = min(2 * v + h, Lf - 1);
+          const float *src = pir + (size_t)kpt(bqfx, bqfy, false, kx, ky) * (3 * NA) + be0;
 #pragma unroll
-        for (int i = 0; i < NBS; ++i) xi[n][i] = src[n * NA + min(i, nb - 1)];
+          for (int n = 0; n < 3; ++n)
+#pragma unroll
+            for (int i = 0; i < NBS; ++i) xi[3 * h + n][i] = src[n * NA + min(i, nb - 1)];
+        }
+      } else {
+        const int ky = min(v, Lf - 1);
+        const float *src = band + (size_t)kpt(bqfx, bqfy, false, kx, ky) * NC + NO + be0;
+#pragma unroll
+        for (int n = 0; n < NO; ++n)
+#pragma unroll
+          for (int i = 0; i < NBS; ++i) xi[n][i] = src[n * NA + min(i, nb - 1)];
+      }
     }
     unsigned char *bh = sB[bb][0], *bl = sB[bb][1];
 #pragma unroll
@@ -315,8 +347,9 @@ __global__ __launch_bounds__(NTHR, 1) void loop_rb_kernel(
         float w0 = 0.f, w1 = 0.f;
 #pragma unroll
         for (int n = 0; n < NO; ++n) {
-          w0 = fmaf(L0[n], xi[n][i], w0);
-          w1 = fmaf(L1[n], xi[n][i], w1);
+          // paired: L_{m'n'} vanishes between bands of different ky
+          if (!PAIR || n / 3 == (2 * mp) / 3) w0 = fmaf(L0[n], xi[n][i], w0);
+          if (!PAIR || n / 3 == (2 * mp + 1) / 3) w1 = fmaf(L1[n], xi[n][i], w1);
         }
         unsigned h, l;
         split2(w0, w1, h, l);
@@ -627,34 +660,59 @@ int loop_rb_half_points(int ndy, int *dx, int *dy) {
   return 0;
 }
 
-size_t loop_rb_apre_bytes(int ndy, int Lf) {
+size_t loop_rb_apre_bytes(int ndy, int Lf, int pair) {
   const int mt = ndy == 4 ? RB<4>::MT : RB<2>::MT;
-  const size_t ntk = (size_t)(Lf + KT - 1) / KT;
+  const size_t ntk = (size_t)((pair ? Lf / 2 : Lf) + KT - 1) / KT;
   return (size_t)Lf * ntk * KS * mt * 2 * 64 * 16;
 }
 
 // the precomputed A operand of every kx row (once per context; band data and
-// phases are those of the loop kernel: FP32, k-major)
-hipError_t launch_loop_rb_apre(int ndy, const float *band, const float *phy, int Lf, void *apre, hipStream_t st) {
-  if (!band || !phy || !apre || (ndy != 2 && ndy != 4)) return hipErrorInvalidValue;
+// phases are those of the loop kernel: FP32, k-major; paired: the pair sums of
+// the projectors)
+hipError_t launch_loop_rb_apre(int ndy, int pair, const float *band, const float *pir, const float *phy, int Lf,
+                               void *apre, hipStream_t st) {
+  if (!band || !phy || !apre || (ndy != 2 && ndy != 4) || (pair && (!pir || Lf % 2))) return hipErrorInvalidValue;
   const int mt = ndy == 4 ? RB<4>::MT : RB<2>::MT;
-  const long long n = (long long)Lf * ((Lf + KT - 1) / KT) * KS * mt * 64;
+  const long long n = (long long)Lf * (((pair ? Lf / 2 : Lf) + KT - 1) / KT) * KS * mt * 64;
   const dim3 grid((unsigned)((n + 255) / 256));
-  if (ndy == 4)
-    hipLaunchKernelGGL(loop_rb_apre_kernel<4>, grid, dim3(256), 0, st, band, phy, Lf, (u32x4 *)apre);
+  if (ndy == 4 && pair)
+    hipLaunchKernelGGL((loop_rb_apre_kernel<4, true>), grid, dim3(256), 0, st, band, pir, phy, Lf, (u32x4 *)apre);
+  else if (ndy == 4)
+    hipLaunchKernelGGL((loop_rb_apre_kernel<4, false>), grid, dim3(256), 0, st, band, pir, phy, Lf, (u32x4 *)apre);
+  else if (pair)
+    hipLaunchKernelGGL((loop_rb_apre_kernel<2, true>), grid, dim3(256), 0, st, band, pir, phy, Lf, (u32x4 *)apre);
   else
-    hipLaunchKernelGGL(loop_rb_apre_kernel<2>, grid, dim3(256), 0, st, band, phy, Lf, (u32x4 *)apre);
+    hipLaunchKernelGGL((loop_rb_apre_kernel<2, false>), grid, dim3(256), 0, st, band, pir, phy, Lf, (u32x4 *)apre);
+  return hipGetLastError();
+}
+
+// pair sums of the projectors of bands (0, 1), (2, 3), (4, 5), FP64 summed and
+// rounded to FP32: pir[k][p][alpha] from the component-major band data
+__global__ void pair_pi_kernel(int Nf, const double *__restrict__ band, float *__restrict__ pir) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)Nf * 3 * NA) return;
+  const int k = (int)(i / (3 * NA)), r = (int)(i % (3 * NA)), p = r / NA, alpha = r % NA;
+  const double a = band[(size_t)(NO + 2 * p * NA + alpha) * Nf + k];
+  const double b = band[(size_t)(NO + (2 * p + 1) * NA + alpha) * Nf + k];
+  pir[i] = (float)(a + b);
+}
+
+hipError_t launch_pair_pi(int Nf, const double *band, float *pir, hipStream_t st) {
+  if (!band || !pir || Nf < 1) return hipErrorInvalidValue;
+  const long long n = (long long)Nf * 3 * NA;
+  hipLaunchKernelGGL(pair_pi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Nf, band, pir);
   return hipGetLastError();
 }
 
 // one channel, coarse q [q_first, q_first + n_q) (or the q_x rows of a.rows):
 // the row buffers Y (ceil(n_q / 4) groups of loop_rb_rowbuf_floats), with the
-// A operand apre of launch_loop_rb_apre
+// A operand apre of launch_loop_rb_apre (of the same pairing)
 hipError_t launch_loop_rb(const LoopArgs &a, int ch, const void *apre, float *Y, hipStream_t st) {
   if (a.n_o != NO || !Y || !apre) return hipErrorInvalidValue;
   const float *band = (const float *)a.band, *kv = (const float *)a.kv;
-  const float *cvp = (const float *)a.cv;
+  const float *cvp = (const float *)a.cv, *pir = a.pir;
   if (a.scheme == CUT_SHELL && !cvp) return hipErrorInvalidValue;
+  if (a.pair && (!pir || a.Lf % 2)) return hipErrorInvalidValue;
   if (!(a.ndy == 4 && a.ndx == 5) && !(a.ndy == 2 && a.ndx == 3)) return hipErrorInvalidValue;
   const int n_groups = (a.n_q + NQG - 1) / NQG;
   const int kxr = a.kxr;  // kx rows per work item
@@ -664,22 +722,26 @@ hipError_t launch_loop_rb(const LoopArgs &a, int ch, const void *apre, float *Y,
   if (nblk > 0x7fffffffLL) return hipErrorInvalidValue;
   const float lam = (float)a.lam;
   const bf16x8 *ap = (const bf16x8 *)apre;
-#define TUFRG_RB_LAUNCH(D, S)                                                                                  \
-  hipLaunchKernelGGL((loop_rb_kernel<D, S>), dim3((unsigned)nblk), dim3(NTHR), 0, st, band, kv, cvp, ap, a.Lq, \
-                     a.n_ref, a.Lf, a.q_first, a.n_q, a.rows, ch, lam, a.deriv, n_groups, n_kxb, kxr, Y)
-#define TUFRG_RB_SCHEMES(D)              \
-  if (a.scheme == CUT_TEMPERATURE)       \
-    TUFRG_RB_LAUNCH(D, CUT_TEMPERATURE); \
-  else if (a.scheme == CUT_OMEGA)        \
-    TUFRG_RB_LAUNCH(D, CUT_OMEGA);       \
-  else if (a.scheme == CUT_SHELL)        \
-    TUFRG_RB_LAUNCH(D, CUT_SHELL);       \
-  else                                   \
+#define TUFRG_RB_LAUNCH(D, S, P)                                                                                   \
+  hipLaunchKernelGGL((loop_rb_kernel<D, S, P>), dim3((unsigned)nblk), dim3(NTHR), 0, st, band, pir, kv, cvp, ap, \
+                     a.Lq, a.n_ref, a.Lf, a.q_first, a.n_q, a.rows, ch, lam, a.deriv, n_groups, n_kxb, kxr, Y)
+#define TUFRG_RB_SCHEMES(D, P)              \
+  if (a.scheme == CUT_TEMPERATURE)          \
+    TUFRG_RB_LAUNCH(D, CUT_TEMPERATURE, P); \
+  else if (a.scheme == CUT_OMEGA)           \
+    TUFRG_RB_LAUNCH(D, CUT_OMEGA, P);       \
+  else if (a.scheme == CUT_SHELL)           \
+    TUFRG_RB_LAUNCH(D, CUT_SHELL, P);       \
+  else                                      \
     return hipErrorInvalidValue;
-  if (a.ndy == 4) {
-    TUFRG_RB_SCHEMES(4)
+  if (a.ndy == 4 && a.pair) {
+    TUFRG_RB_SCHEMES(4, true)
+  } else if (a.ndy == 4) {
+    TUFRG_RB_SCHEMES(4, false)
+  } else if (a.pair) {
+    TUFRG_RB_SCHEMES(2, true)
   } else {
-    TUFRG_RB_SCHEMES(2)
+    TUFRG_RB_SCHEMES(2, false)
   }
 #undef TUFRG_RB_SCHEMES
 #undef TUFRG_RB_LAUNCH

@@ -47,6 +47,9 @@ struct LoopArgs {
   const void *pi4 = nullptr;   // two orbitals: [Nf][4] = (Pi_0[00], Pi_0[11], Re Pi_0[01], Im Pi_0[01])
   const void *cv = nullptr;    // shell scheme: shell factors, two orbitals [Nf][4] = (a_0, a_1, b_0, b_1),
                                // more orbitals [Nf][n_o][2] = (a_m, b_m); like band
+  int pair = 0;                // six spin-orbitals on the matrix cores: bands (0,1), (2,3), (4,5)
+                               // degenerate at every k, summed by pairs
+  const float *pir = nullptr;  // with pair: [Nf][3][36] pair sums of the packed projectors (FP32)
 };
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
 // several two-orbital instances of one precision in fused launches (one per
@@ -70,8 +73,10 @@ hipError_t launch_loop_gen(const LoopArgs &a, hipStream_t st);
 // half-plane points of the computed shape from loop_rb_half_points.  The A
 // operand (phases times projectors, split; independent of q, Lambda and the
 // channel) is computed once into loop_rb_apre_bytes(ndy, Lf) bytes.
-size_t loop_rb_apre_bytes(int ndy, int Lf);
-hipError_t launch_loop_rb_apre(int ndy, const float *band, const float *phy, int Lf, void *apre, hipStream_t st);
+size_t loop_rb_apre_bytes(int ndy, int Lf, int pair);
+hipError_t launch_loop_rb_apre(int ndy, int pair, const float *band, const float *pir, const float *phy, int Lf,
+                               void *apre, hipStream_t st);
+hipError_t launch_pair_pi(int Nf, const double *band, float *pir, hipStream_t st);
 hipError_t launch_loop_rb(const LoopArgs &a, int ch, const void *apre, float *Y, hipStream_t st);
 hipError_t launch_loop_rb_sums(const LoopArgs &a, const float *Y, double *lamb, const int *hmap, int nD,
                                double *dst, hipStream_t st);

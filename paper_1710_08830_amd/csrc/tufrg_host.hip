@@ -122,6 +122,12 @@ struct tufrg_ctx {
   int mfma_chunk = 0;
   int mfma_kxr = 1;        // kx rows per work item of the matrix-core loop (tunable)
   void *d_apre = nullptr;  // the matrix-core loop's precomputed A operand (once per context)
+  int apre_pair = 0;       // the pairing d_apre was computed for
+  // BF16X3 loops: bands (0,1), (2,3), (4,5) degenerate at every k (Kramers
+  // pairs), found at creation; then the loops sum them by pairs unless
+  // pair_enable is cleared
+  int bands_paired = 0, pair_enable = 1;
+  float *d_pir32 = nullptr;  // [Nf][3][36] pair sums of the packed projectors
   size_t partial_cap = 0;  // doubles allocated at d_partial
   unsigned long long *h_sbits = nullptr;       // pinned
   // Euler steps in HIP graphs: the executable graph, the capture stream (the
@@ -600,6 +606,23 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   if (c->n_o > 2) CHIP(launch_to_kmajor(c->n_o + c->n_o * c->no2, (int)Nf, c->d_band64, c->d_bandk64, c->d_bandk32, st));
   if (c->n_o == 2) CHIP(launch_pi4((int)Nf, c->d_band64, c->d_pi4_64, c->d_pi4_32, st));
   CHIP(hipStreamSynchronize(st));
+  if (c->n_o == 6 && c->prec == TUFRG_BF16X3 && c->Lf % 2 == 0) {
+    // Kramers pairs: e_{2p} = e_{2p+1} at every k up to the eigensolver's
+    // rounding (sorted bands); then the sum over bands in the loops groups
+    // exactly into three pairs with the summed projectors
+    std::vector<double> e(6 * Nf);
+    CHIP(hipMemcpy(e.data(), c->d_band64, e.size() * sizeof(double), hipMemcpyDeviceToHost));
+    double emax = 0.0, split = 0.0;
+    for (size_t i = 0; i < e.size(); ++i) emax = std::max(emax, std::fabs(e[i]));
+    for (int p = 0; p < 3; ++p)
+      for (size_t k = 0; k < Nf; ++k) split = std::max(split, std::fabs(e[(2 * p) * Nf + k] - e[(2 * p + 1) * Nf + k]));
+    if (split <= 1e-10 * std::max(1.0, emax)) {
+      CTRY(dalloc(c, &c->d_pir32, Nf * 3 * 36));
+      CHIP(launch_pair_pi((int)Nf, c->d_band64, c->d_pir32, st));
+      CHIP(hipStreamSynchronize(st));
+      c->bands_paired = 1;
+    }
+  }
   *out = c;
   return TUFRG_OK;
 #undef CTRY
@@ -643,6 +666,8 @@ static LoopArgs loop_args(tufrg_ctx *c, double lam, int deriv, int ch_first, int
   a.nkyb = c->nkyb;
   a.nkxc = c->nkxc;
   a.kxr = c->mfma_kxr;
+  a.pair = c->prec == TUFRG_BF16X3 && c->bands_paired && c->pair_enable;
+  a.pir = c->d_pir32;
   a.ch_first = ch_first;
   a.n_ch = n_ch;
   a.q_first = 0;
@@ -709,6 +734,8 @@ static tufrg_status compute_kval(tufrg_ctx *c, double lam, int deriv) {
   return TUFRG_OK;
 }
 
+static void dfree(tufrg_ctx *c, void *p);
+
 // loops of channels [ch_first, ch_first + n_ch) and coarse q [q_first, q_first + n_q)
 // (whole q_x rows) into dst, compact [n_ch][n_q][nD][no4]; regulator values
 // must be current (compute_kval)
@@ -736,11 +763,18 @@ static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch
     HIPCHK(c, hipStreamSynchronize(c->st));
     c->d_hmap = d;
   }
+  const int pair = c->bands_paired && c->pair_enable;
+  if (c->d_apre && c->apre_pair != pair) {
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    dfree(c, c->d_apre);
+    c->d_apre = nullptr;
+  }
   if (!c->d_apre) {
     unsigned char *ap = nullptr;
-    TRY(dalloc(c, &ap, loop_rb_apre_bytes(c->ndy, c->Lf)));
-    HIPCHK(c, launch_loop_rb_apre(c->ndy, c->d_bandk32, c->d_phy32, c->Lf, ap, c->st));
+    TRY(dalloc(c, &ap, loop_rb_apre_bytes(c->ndy, c->Lf, pair)));
+    HIPCHK(c, launch_loop_rb_apre(c->ndy, pair, c->d_bandk32, c->d_pir32, c->d_phy32, c->Lf, ap, c->st));
     c->d_apre = ap;
+    c->apre_pair = pair;
   }
   if (!c->d_yrow || !c->d_lamb) {
     // whole q_x rows per chunk, about 256 coarse q (64 groups of four); where
@@ -963,6 +997,14 @@ extern "C" tufrg_status tufrg_autotune(tufrg_ctx *c, double lambda, const char *
     std::string err;
     if (!tune_cache_write(cache_path, cache, err)) return fail(c, TUFRG_E_INVAL, err);
   }
+  return TUFRG_OK;
+}
+
+extern "C" tufrg_status tufrg_pair_bands(tufrg_ctx *c, int32_t enable, int32_t *active) {
+  if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
+  if (enable != 0 && enable != 1) return fail(c, TUFRG_E_INVAL, "enable must be 0 or 1");
+  c->pair_enable = enable;
+  if (active) *active = c->bands_paired && c->pair_enable;
   return TUFRG_OK;
 }
 

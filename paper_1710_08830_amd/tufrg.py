@@ -41,7 +41,8 @@ SYMBOLS = ["tufrg_create", "tufrg_destroy", "tufrg_last_error", "tufrg_dims", "t
            "tufrg_sur_loops", "tufrg_batch_create", "tufrg_batch_destroy", "tufrg_batch_last_error",
            "tufrg_batch_dims", "tufrg_batch_flow", "tufrg_set_initial_c", "tufrg_basis_matrix",
            "tufrg_basis_apply", "tufrg_set_initial_p", "tufrg_ff_symmetrize", "tufrg_ff_apply",
-           "tufrg_project_static", "tufrg_channel_d", "tufrg_autotune", "tufrg_su2_rhs", "tufrg_su2_flow"]
+           "tufrg_project_static", "tufrg_channel_d", "tufrg_autotune", "tufrg_su2_rhs", "tufrg_su2_flow",
+           "tufrg_pair_bands"]
 TIMER_LOOP, TIMER_PROJECT, TIMER_BUNDLE, TIMER_SURROGATE = 0, 1, 2, 3
 
 
@@ -108,6 +109,7 @@ _lib.tufrg_project_static.argtypes = [_vp, _vp, _vp, _vp, _vp]
 _lib.tufrg_channel_d.argtypes = [_vp, _vp, _vp]
 _lib.tufrg_su2_rhs.argtypes = [_vp, ctypes.c_double] + [_vp] * 6
 _lib.tufrg_autotune.argtypes = [_vp, ctypes.c_double, ctypes.c_char_p, ctypes.POINTER(TuneResult)]
+_lib.tufrg_pair_bands.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
 _lib.tufrg_basis_matrix.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
 _lib.tufrg_basis_apply.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32]
 _lib.tufrg_ff_symmetrize.argtypes = [ctypes.c_int32, _vp, _vp, _vp]
@@ -285,6 +287,14 @@ def tufrg_project(ctx, P, C, VP, VC):
     """Projected vertices VP, VC [Nq][B][B] of the state P, C, all on the device."""
     _check(_lib.tufrg_project(ctx.handle, _state(ctx, P, "P"), _state(ctx, C, "C"), _state(ctx, VP, "VP"),
                               _state(ctx, VC, "VC")), ctx.handle)
+
+
+def tufrg_pair_bands(ctx, enable=True):
+    """Use (enable) or bypass the Kramers-paired BF16X3 loops; returns whether
+    the pairs are in use (they are only where the bands were found paired)."""
+    act = ctypes.c_int32()
+    _check(_lib.tufrg_pair_bands(ctx.handle, int(bool(enable)), ctypes.byref(act)), ctx.handle)
+    return bool(act.value)
 
 
 def tufrg_autotune(ctx, lam, cache_path=None):

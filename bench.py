@@ -56,14 +56,15 @@ def loop_flops_per_pair(n_o, ndx, ndy, shell=False):
     return u * (8 * n_o + 2 + 8 * ndy) + 2 * n_o ** 4 + 3 * n_o ** 2 + extra
 
 
-def mfma_flops_per_pair(ndy, n_o=6):
+def mfma_flops_per_pair(ndy, n_o=6, n_b=None):
     """Matrix-core flops the BF16X3 loop executes per (q, k, channel): one k
-    adds K = n_o (bands) to the product of the (2 ndy + 1) n_o^2 phase rows
-    (phase times real-basis projector coordinate, padded to whole 16-row
-    tiles) with the n_o^2 real-basis columns of its q, as three BF16 products
-    (hi*hi, hi*lo, lo*hi)."""
+    adds K = n_b (bands summed: n_o, or 3 for Kramers pairs) to the product of
+    the (2 ndy + 1) n_o^2 phase rows (phase times real-basis projector
+    coordinate, padded to whole 16-row tiles) with the n_o^2 real-basis
+    columns of its q, as three BF16 products (hi*hi, hi*lo, lo*hi)."""
+    n_b = n_o if n_b is None else n_b
     rows = -(-(2 * ndy + 1) * n_o * n_o // 16) * 16
-    return 3 * 2 * rows * (n_o * n_o) * n_o
+    return 3 * 2 * rows * (n_o * n_o) * n_b
 
 
 def credited_loop_flops_per_pair(n_o, ndy, n_b=None):
@@ -376,7 +377,7 @@ def _tune(T, ctx, lam, on):
     return r, bool(r["tunable"]) and r["loop_ms"] < r["default_ms"]
 
 
-def six_orbital_line(T, torch, w, prec, K, W, fp64_steps=2, surrogate=True, n_rows=120000,
+def six_orbital_line(T, torch, w, prec, K, W, fp64_steps=2, surrogate=True, n_rows=120000, six_bands=False,
                      epochs=(10, 10, 10), tune=False):
     """Headline of a six-orbital workload: K timed Euler steps (after W warmup
     steps) of the 200-step grid from Lambda0 in the mixed arithmetic, the
@@ -390,6 +391,10 @@ def six_orbital_line(T, torch, w, prec, K, W, fp64_steps=2, surrogate=True, n_ro
     lam_at = lambda i: lam0 * (w["lam_end"] / lam0) ** (i / n)  # noqa: E731
     ctx = T.Context.from_workload(w, precision=prec)
     B, Nq, Nf, nD = ctx.B, ctx.Nq, ctx.Nf, ctx.n_dR
+    # Kramers-paired bands (the default wherever found): the loops sum three
+    # bands, and the credited work counts three
+    paired = prec == "bf16x3" and T.tufrg_pair_bands(ctx, not six_bands)
+    n_b = 3 if paired else w["n_o"]
     P = torch.zeros((Nq, B, B), dtype=torch.complex128, device=dev)
     C = torch.zeros_like(P)
     tuned, moved = _tune(T, ctx, lam_at(K // 2), tune)
@@ -410,7 +415,7 @@ def six_orbital_line(T, torch, w, prec, K, W, fp64_steps=2, surrogate=True, n_ro
     entries = 2.0 * Nq * B * B
     compact = 2.0 * Nq * nD * ctx.n_o ** 4
     ndx, ndy = _box(w["ff"])
-    credited = credited_loop_flops_per_pair(w["n_o"], ndy)
+    credited = credited_loop_flops_per_pair(w["n_o"], ndy, n_b)
     flops_step = 2.0 * Nq * Nf * credited
     launches = loop_n / K
     loop_step_s = loop_ms / K * 1e-3
@@ -436,9 +441,9 @@ def six_orbital_line(T, torch, w, prec, K, W, fp64_steps=2, surrogate=True, n_ro
         "loop_launches_per_step": launches,
         "loop_entries_per_s_kernel": entries / loop_step_s,
         "roofline": {"bound": bound, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None if moved else _traffic(w["name"], prec),
-                     "flops_per_pair": credited,
-                     "executed_matrix_flops_per_pair": (mfma_flops_per_pair(ndy, w["n_o"])
+                     "frac": achieved / peak, "traffic": None if moved or six_bands else _traffic(w["name"], prec),
+                     "flops_per_pair": credited, "bands_summed": n_b,
+                     "executed_matrix_flops_per_pair": (mfma_flops_per_pair(ndy, w["n_o"], n_b)
                                                         if prec == "bf16x3" else None)},
         "flow_result": res,
     }
@@ -906,10 +911,12 @@ def summarize_counters(args):
         from synth import workload
         w = workload(args.workload)
         lf = w["Lq"] * w["n_ref"]
-        tiles = (lf + 15) // 16  # ky tiles per kx row; one kx row per work item
+        # the t2g models are Kramers-paired: 16 ky pairs per tile unless --six-bands
+        paired = w["n_o"] == 6 and args.workload.startswith("t2g") and not args.six_bands and lf % 2 == 0
+        tiles = ((lf // 2 if paired else lf) + 15) // 16  # tiles per kx row; one kx row per work item
         per = lambda c: tot[c] / tot["SQ_WAVES"] / tiles
-        lines += ["", "Per wave and tile of 16 ky (one kx row per work item, "
-                  f"{tiles} tiles):", ""]
+        what = "16 ky pairs (paired bands)" if paired else "16 ky"
+        lines += ["", f"Per wave and tile of {what} (one kx row per work item, {tiles} tiles):", ""]
         for c in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS"):
             if c in tot:
                 lines.append(f"* {c}: {per(c):.0f}")
@@ -944,6 +951,8 @@ def main():
                     help="regulator in place of the workload's own")
     ap.add_argument("--tune", action="store_true",
                     help="autotune the loop kernels' launch shape before timing (cache: $TUFRG_TUNE_CACHE)")
+    ap.add_argument("--six-bands", action="store_true",
+                    help="BF16X3: sum all six bands even where they are Kramers pairs")
     ap.add_argument("--temperature", type=float, default=0.02,
                     help="fixed temperature of the momentum-shell regulator")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -994,6 +1003,7 @@ def main():
             w = dict(w, cutoff=args.cutoff, temperature=args.temperature)
         prec = args.prec or "bf16x3"
         out = six_orbital_line(T, torch, w, prec, K, W, fp64_steps=0 if args.no_extras else args.fp64_steps,
+                               six_bands=args.six_bands,
                                tune=args.tune,
                                surrogate=not (args.no_extras or args.no_surrogate))
         if not args.no_extras:

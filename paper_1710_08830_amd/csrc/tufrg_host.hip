@@ -895,8 +895,10 @@ static std::string tune_key(const tufrg_ctx *c) {
     (void)hipGetLastError();
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "%s:%dcu|n_o=%d|prec=%d|scheme=%d|Lq=%d|n_ref=%d|n_ff=%d|nD=%d|ndx=%d|ndy=%d",
-                arch.c_str(), cus, c->n_o, c->prec, c->scheme, c->Lq, c->n_ref, c->n_ff, c->nD, c->ndx, c->ndy);
+  std::snprintf(buf, sizeof(buf),
+                "%s:%dcu|n_o=%d|prec=%d|scheme=%d|Lq=%d|n_ref=%d|n_ff=%d|nD=%d|ndx=%d|ndy=%d|pairs=%d",
+                arch.c_str(), cus, c->n_o, c->prec, c->scheme, c->Lq, c->n_ref, c->n_ff, c->nD, c->ndx, c->ndy,
+                c->bands_paired && c->pair_enable);
   return buf;
 }
 

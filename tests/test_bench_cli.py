@@ -35,6 +35,9 @@ def test_flop_counts_of_the_loop():
     assert bench.credited_loop_flops_per_pair(6, 4) == 8 * 9 * 1296 // 2 + 8 * 36 * 6 * 42 == 119232
     assert bench.mfma_flops_per_pair(4) == 3 * 2 * 336 * 36 * 6
     assert bench.mfma_flops_per_pair(2) == 3 * 2 * 192 * 36 * 6
+    # Kramers pairs: three bands summed
+    assert bench.mfma_flops_per_pair(4, 6, 3) == 3 * 2 * 336 * 36 * 3
+    assert bench.credited_loop_flops_per_pair(6, 4, 3) == 8 * 9 * 1296 // 2 + 8 * 36 * 3 * 39 == 80352
     model, n = bench._cpu_info()
     assert isinstance(model, str) and n >= 1
 
@@ -116,9 +119,14 @@ def test_counter_summary_per_dispatch_and_per_wave_tile(tmp_path):
     _counter_csv(tmp_path / "sq.csv", rows)
     out = tmp_path / "sq.md"
     args = argparse.Namespace(summarize_counters=[str(tmp_path / "sq.csv"), "rocprofv3 --pmc ...", str(out)],
-                              workload="t2g_s13_L48", prec="bf16x3")
+                              workload="t2g_s13_L48", prec="bf16x3", six_bands=True)
     bench.summarize_counters(args)
     text = out.read_text()
     assert "2 dispatches" in text and "| SQ_WAVES | 100 |" in text and "rocprofv3 --pmc ..." in text
     assert "SQ_INSTS_VALU: 500" in text and "SQ_INSTS_MFMA: 200" in text and "SQ_INSTS_LDS: 50" in text
     assert "per LDS instruction: 0.50" in text
+    # the same counters as a paired run: 384 ky pairs per row, 24 tiles
+    args.six_bands = False
+    bench.summarize_counters(args)
+    text = out.read_text()
+    assert "16 ky pairs" in text and "SQ_INSTS_VALU: 1000" in text

@@ -146,8 +146,21 @@ class TUSetup:
 # loops
 # ----------------------------------------------------------------------------
 
+def _neumaier_add(acc, comp, x):
+    """acc + x with the lost low part added to comp (Neumaier's compensated
+    summation, applied to the real and imaginary parts alike)."""
+    t = acc + x
+    big = np.abs(acc.real) >= np.abs(x.real)
+    cr = np.where(big, (acc.real - t.real) + x.real, (x.real - t.real) + acc.real)
+    big = np.abs(acc.imag) >= np.abs(x.imag)
+    ci = np.where(big, (acc.imag - t.imag) + x.imag, (x.imag - t.imag) + acc.imag)
+    return t, comp + (cr + 1j * ci)
+
+
 def loop_matrix(st, channel, qi, lam, deriv=True, k_chunk=4096):
-    """Orbital loop matrix [iR1, iR2, t1, t2, t3, t4] at coarse q index qi."""
+    """Orbital loop matrix [iR1, iR2, t1, t2, t3, t4] at coarse q index qi.
+    The k sum runs over chunks of the fine mesh; the chunk sums are added with
+    Neumaier compensation."""
     n = st.n_o
     qf = st.coarse[qi] * st.n_ref
     diffs = {}
@@ -158,6 +171,7 @@ def loop_matrix(st, channel, qi, lam, deriv=True, k_chunk=4096):
     dlist = list(diffs.keys())
     dR = np.array(dlist, dtype=np.int64)
     acc = np.zeros((len(dlist), n, n, n, n), dtype=np.complex128)
+    comp = np.zeros_like(acc)
     for k0 in range(0, st.Nf, k_chunk):
         kk = np.arange(k0, min(k0 + k_chunk, st.Nf))
         nk = st.fine[kk]
@@ -180,8 +194,8 @@ def loop_matrix(st, channel, qi, lam, deriv=True, k_chunk=4096):
             M = np.einsum("kmac,kmbd->kabcd", st.Pi[kk], W)
         kr = (nk @ dR.T) % st.Lf
         ph = np.exp(-2j * np.pi * kr / st.Lf)  # f_R1(k) f*_R2(k) = e^{-ik.(R1-R2)}
-        acc += np.einsum("kr,kabcd->rabcd", ph, M)
-    acc /= st.Nf
+        acc, comp = _neumaier_add(acc, comp, np.einsum("kr,kabcd->rabcd", ph, M))
+    acc = (acc + comp) / st.Nf
     out = np.zeros((st.n_ff, st.n_ff, n, n, n, n), dtype=np.complex128)
     for i, R1 in enumerate(st.S):
         for j, R2 in enumerate(st.S):

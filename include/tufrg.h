@@ -293,8 +293,10 @@ tufrg_status tufrg_autotune(tufrg_ctx *ctx, double lambda, const char *cache_pat
  * splittings (about 1e-14) change the loops far below the BF16X3 rounding.
  * enable = 1 (the default) uses the pairs where they were found, 0 always
  * uses the six bands; *active (may be NULL) receives whether the pairs are in
- * use.  The next loop evaluation rebuilds the precomputed A operand if the
- * choice changed.  Errors: E_INVAL for a null context or enable not 0 or 1. */
+ * use.  If the choice changed and the precomputed A operand of the loops
+ * exists, it is rebuilt in this call (synchronous; E_NOMEM or E_HIP as the
+ * loops).  Call it outside flows and graph captures.  Errors: E_INVAL for a
+ * null context or enable not 0 or 1. */
 tufrg_status tufrg_pair_bands(tufrg_ctx *ctx, int32_t enable, int32_t *active);
 
 /* The third channel (Sec. 3.2): D_{n1n2n3n4} = -C_{n1n2n4n3}, which the

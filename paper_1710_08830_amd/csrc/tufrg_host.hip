@@ -736,6 +736,25 @@ static tufrg_status compute_kval(tufrg_ctx *c, double lam, int deriv) {
 
 static void dfree(tufrg_ctx *c, void *p);
 
+// the matrix-core loop's A operand for the current pairing (rebuilt when the
+// pairing changed since it was computed)
+static tufrg_status ensure_apre(tufrg_ctx *c) {
+  const int pair = c->bands_paired && c->pair_enable;
+  if (c->d_apre && c->apre_pair != pair) {
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    dfree(c, c->d_apre);
+    c->d_apre = nullptr;
+  }
+  if (!c->d_apre) {
+    unsigned char *ap = nullptr;
+    TRY(dalloc(c, &ap, loop_rb_apre_bytes(c->ndy, c->Lf, pair)));
+    HIPCHK(c, launch_loop_rb_apre(c->ndy, pair, c->d_bandk32, c->d_pir32, c->d_phy32, c->Lf, ap, c->st));
+    c->d_apre = ap;
+    c->apre_pair = pair;
+  }
+  return TUFRG_OK;
+}
+
 // loops of channels [ch_first, ch_first + n_ch) and coarse q [q_first, q_first + n_q)
 // (whole q_x rows) into dst, compact [n_ch][n_q][nD][no4]; regulator values
 // must be current (compute_kval)
@@ -763,19 +782,7 @@ static tufrg_status loops_range_mfma(tufrg_ctx *c, double lam, int deriv, int ch
     HIPCHK(c, hipStreamSynchronize(c->st));
     c->d_hmap = d;
   }
-  const int pair = c->bands_paired && c->pair_enable;
-  if (c->d_apre && c->apre_pair != pair) {
-    HIPCHK(c, hipStreamSynchronize(c->st));
-    dfree(c, c->d_apre);
-    c->d_apre = nullptr;
-  }
-  if (!c->d_apre) {
-    unsigned char *ap = nullptr;
-    TRY(dalloc(c, &ap, loop_rb_apre_bytes(c->ndy, c->Lf, pair)));
-    HIPCHK(c, launch_loop_rb_apre(c->ndy, pair, c->d_bandk32, c->d_pir32, c->d_phy32, c->Lf, ap, c->st));
-    c->d_apre = ap;
-    c->apre_pair = pair;
-  }
+  TRY(ensure_apre(c));
   if (!c->d_yrow || !c->d_lamb) {
     // whole q_x rows per chunk, about 256 coarse q (64 groups of four); where
     // some 256..512 q make a group count that is a multiple of the
@@ -1006,6 +1013,8 @@ extern "C" tufrg_status tufrg_pair_bands(tufrg_ctx *c, int32_t enable, int32_t *
   if (!c) return fail(nullptr, TUFRG_E_INVAL, "null context");
   if (enable != 0 && enable != 1) return fail(c, TUFRG_E_INVAL, "enable must be 0 or 1");
   c->pair_enable = enable;
+  // an A operand already built is rebuilt now, not inside a later flow
+  if (c->d_apre) TRY(ensure_apre(c));
   if (active) *active = c->bands_paired && c->pair_enable;
   return TUFRG_OK;
 }

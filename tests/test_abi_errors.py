@@ -126,6 +126,13 @@ def test_set_initial_p_rejects_a_null_context(T):
     assert T._lib.tufrg_set_initial_p(None, None) == 1
 
 
+def test_pair_bands_rejects_a_null_context(T):
+    import ctypes
+    act = ctypes.c_int32(7)
+    assert T._lib.tufrg_pair_bands(None, 1, ctypes.byref(act)) == 1
+    assert act.value == 7  # untouched
+
+
 def _fake_ctx():
     """Sizes of a small context without one (no device is needed: the binding
     checks dtype and size before it calls the library)."""

@@ -84,8 +84,17 @@ def _box(ff):
 
 # sources of the loop kernel per precision, and the host function that sets
 # its launch shape (chunking) in tufrg_host.hip
-LOOP_SOURCES = {"bf16x3": (("k_loop_rb.hip", "common.h"), "loops_range_mfma")}
-LOOP_SOURCES_DEFAULT = (("k_loop.hip", "k_loop_gen.hip", "common.h"), "loops_range")
+LOOP_SOURCES = {"bf16x3": (("k_loop_rb.hip", "common.h"), ("loops_range_mfma", "ensure_apre"))}
+LOOP_SOURCES_DEFAULT = (("k_loop.hip", "k_loop_gen.hip", "common.h"), ("loops_range",))
+
+
+def _code_only(text):
+    """Source text without comments and with whitespace runs collapsed: what
+    the compiler sees, so that a comment edit keeps a profile's hash."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return re.sub(r"\s+", " ", text).strip()
 
 
 def _host_function_text(name):
@@ -101,12 +110,15 @@ def _host_function_text(name):
 
 
 def _loop_source_hash(prec):
-    files, fn = LOOP_SOURCES.get(prec, LOOP_SOURCES_DEFAULT)
+    """Hash of the loop kernels' sources and of the host functions that shape
+    their launches, comments and layout aside."""
+    files, fns = LOOP_SOURCES.get(prec, LOOP_SOURCES_DEFAULT)
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_1710_08830_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    h.update(_host_function_text(fn).encode())
+        with open(os.path.join(ROOT, "paper_1710_08830_amd", "csrc", f)) as fh:
+            h.update(_code_only(fh.read()).encode())
+    for fn in fns:
+        h.update(_code_only(_host_function_text(fn)).encode())
     return h.hexdigest()
 
 

@@ -32,6 +32,11 @@
 //   (hi*hi + hi*lo + lo*hi, v_mfma_f32_16x16x32_bf16) into 16 x 16 FP32 tiles
 //   (rows: 9 x 36 phase rows; columns: 4 q x 36 beta).  At the end of a kx
 //   row the tiles go to a row buffer Y.
+//   Kramers pairs (PAIR): when bands (0,1), (2,3), (4,5) are degenerate at
+//   every k, L_mn depends on the pairs only and the band sum groups into three
+//   pairs with summed projectors; a tile then covers 16 ky pairs, the six K
+//   values of a pair point being (ky - 2 v) 3 + pair, with the same B layout
+//   and matrix ops over half as many tiles.
 // loop_rb_rowsum_kernel: the kx sum with the kx phases, in FP64, for the half
 //   plane of difference vectors: lambda^{alpha beta}(q, dR).
 // loop_rb_finalize_kernel: back from the real basis to the entries (a,b,c,d),
@@ -100,8 +105,9 @@ __device__ inline int bpair_off(int K, int col) {
 // on q, Lambda or the channel: computed once per context, in the lane order of
 // the matrix instruction, as [kx][ky tile][K step][row tile][hi, lo][lane] of
 // 8 BF16 (16 bytes): lane l holds row 16 mt + l % 16 and K = 32 s + 8 (l / 16)
-// .. + 7 of the tile, K = (ky - 16 tile) 6 + m; rows past the 9 x 36 and ky
-// past the mesh are zero.  The split is that of the FP32 product (the
+// .. + 7 of the tile, K = (ky - 16 tile) 6 + m (paired: K = (v - 16 tile) 6 +
+// 3 (ky - 2 v) + pair, with the pair sums of the projectors); rows past the
+// 9 x 36 and ky past the mesh are zero.  The split is that of the FP32 product (the
 // compiler may form the remainder from the unrounded product, a last-bit
 // difference of lo: loops agree with an in-kernel build to about 2e-9).
 template <int NDY, bool PAIR>

@@ -130,3 +130,12 @@ def test_counter_summary_per_dispatch_and_per_wave_tile(tmp_path):
     bench.summarize_counters(args)
     text = out.read_text()
     assert "16 ky pairs" in text and "SQ_INSTS_VALU: 1000" in text
+
+
+def test_source_hash_ignores_comments_and_layout():
+    sys.path.insert(0, ROOT)
+    import bench
+    a = "int f(int x) {  // twice\n  return 2 * x; /* doubled */\n}\n"
+    b = "int f(int x) {\n    return 2 * x;\n}"
+    assert bench._code_only(a) == bench._code_only(b)
+    assert bench._code_only(a) != bench._code_only(b.replace("2 *", "3 *"))

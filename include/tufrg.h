@@ -282,15 +282,16 @@ typedef struct {
  * loops.  Call it outside flows and graph captures. */
 tufrg_status tufrg_autotune(tufrg_ctx *ctx, double lambda, const char *cache_path, tufrg_tune_result *res);
 
-/* Kramers-paired bands in the BF16X3 loops (no passage: an implementation
- * choice that the sum over bands of the Sec. 3.1 loop permits).  When the six
- * bands of a BF16X3 context are degenerate in pairs (0,1), (2,3), (4,5) at
+/* Kramers-paired bands in the six-orbital loops (no passage: an
+ * implementation choice that the sum over bands of the Sec. 3.1 loop
+ * permits).  When the six bands are degenerate in pairs (0,1), (2,3), (4,5) at
  * every k of the fine mesh (time reversal with inversion symmetry; checked at
- * creation: splittings at most 1e-10 max(1, max |e|)) and L_f is even, the
- * loops sum each degenerate pair first: three energies and three summed
- * projectors, so half the matrix-core work and about a third of the vector
- * work per k.  Exact for exactly degenerate bands; the eigensolver's
- * splittings (about 1e-14) change the loops far below the BF16X3 rounding.
+ * creation: splittings at most 1e-10 max(1, max |e|)), the loops sum each
+ * degenerate pair first: three energies and three summed projectors (BF16X3:
+ * also L_f even; half the matrix-core work per k; FP32 and FP64: half the
+ * band sum and a quarter of the W build per k).  Exact for exactly degenerate
+ * bands; the eigensolver's splittings (about 1e-14) change the loops far
+ * below the rounding of FP32 and BF16X3 and within 1e-11 in FP64.
  * enable = 1 (the default) uses the pairs where they were found, 0 always
  * uses the six bands; *active (may be NULL) receives whether the pairs are in
  * use.  If the choice changed and the precomputed A operand of the loops

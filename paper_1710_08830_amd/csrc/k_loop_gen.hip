@@ -22,6 +22,11 @@
 // projectors Pi_m(k) as full complex NO x NO matrices, the packed X_n(k'), the
 // loop kernels L_mn and then W_m(k) as full complex matrices, so that the
 // inner loop reads one complex value of Pi and one of W per band.
+//
+// Kramers pairs (PAIR): when bands (0,1), (2,3), (4,5) are degenerate at every
+// k, L_mn depends on the pairs only and the band sums group exactly into three
+// bands with the pair sums of the projectors (energies and regulator values
+// of the first band of each pair).
 #include "common.h"
 #include "kernels.h"
 
@@ -98,9 +103,9 @@ __device__ inline void unpack_store(c2<T> *dst, int pl, T x) {
 }  // namespace
 
 // One workgroup per (part, channel, q); part selects NTHR of the entry pairs.
-template <typename T, int NO, int NDY, int SCHEME, int NTHR, int KT>
-__global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ band, const T *__restrict__ kv,
-                                                        const T *__restrict__ cvp,
+template <typename T, int NO, int NDY, int SCHEME, int NTHR, int KT, bool PAIR>
+__global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ band, const T *__restrict__ pir,
+                                                        const T *__restrict__ kv, const T *__restrict__ cvp,
                                                         const double *__restrict__ tw, const T *__restrict__ phy,
                                                         const int *__restrict__ pairs,
                                                         int n_pairs, int Lq, int n_ref, int Lf, int nparts,
@@ -110,12 +115,15 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
   using SH = Shape<NDY>;
   constexpr int NPT = SH::N;
   constexpr int NO2 = NO * NO, NO4 = NO2 * NO2;
-  constexpr int PK = NO * NO2;      // packed reals of all bands' projectors at one k
-  constexpr int NC = NO + PK;       // band values per k-point: e_m, then the packed projectors
+  constexpr int NB = PAIR ? NO / 2 : NO;  // bands summed (pairs)
+  constexpr int PK = NB * NO2;      // packed reals of the summed bands' projectors at one k
+  constexpr int NC = NO + NO * NO2; // band values per k-point: e_m, then the packed projectors
   constexpr bool SHELL = SCHEME == CUT_SHELL;
-  // staged values per k-point: band values and regulator values (and the
-  // shell factors a_m, b_m of the momentum-shell scheme)
-  constexpr int NIT = NC + NO + (SHELL ? 2 * NO : 0);
+  // band m of the sums in the arrays of all bands (paired: the first of the pair)
+  constexpr int MS = PAIR ? 2 : 1;
+  // staged values per k-point: energies, packed projectors and regulator
+  // values (and the shell factors a_m, b_m of the momentum-shell scheme)
+  constexpr int NIT = NB + PK + NB + (SHELL ? 2 * NB : 0);
   const int tid = threadIdx.x;
   int w = blockIdx.x;
   const int part = w % nparts;
@@ -130,13 +138,13 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
   const int xo = (tau / (NO * NO2)) * NO + (tau / NO) % NO;  // (a, c)
   const int yo = ((tau / NO2) % NO) * NO + tau % NO;        // (b, d)
 
-  __shared__ c2<T> sP[KT][NO][NO2];  // Pi_m(k)
-  __shared__ c2<T> sW[KT][NO][NO2];  // W_m(k)
+  __shared__ c2<T> sP[KT][NB][NO2];  // Pi_m(k)
+  __shared__ c2<T> sW[KT][NB][NO2];  // W_m(k)
   __shared__ T sX[KT][PK];           // X_n(k') packed
-  __shared__ T sE[KT][2][NO];        // e at k and k'
-  __shared__ T sK[KT][2][NO];        // regulator at k and k'
-  __shared__ T sL[KT][NO][NO];
-  __shared__ T sC[SHELL ? KT : 1][2][2 * NO];  // shell factors (a_m, b_m) at k and k'
+  __shared__ T sE[KT][2][NB];        // e at k and k'
+  __shared__ T sK[KT][2][NB];        // regulator at k and k'
+  __shared__ T sL[KT][NB][NB];
+  __shared__ T sC[SHELL ? KT : 1][2][2 * NB];  // shell factors (a_m, b_m) at k and k'
   const T sg = (ch == 0) ? T(1) : T(-1);
 
   cx<T> Z[NPT];
@@ -159,11 +167,11 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
         int kpy = (ch == 0) ? (qfy - ky) : (ky - qfy);
         kpy += kpy < 0 ? Lf : 0;
         const unsigned kk = side ? (unsigned)kpx * Lf + kpy : (unsigned)kx * Lf + ky;
-        if (r < NO) {
-          sE[j][side][r] = band[(size_t)kk * NC + r];
-        } else if (r < NC) {
-          const int p = r - NO, m = p / NO2, pl = p % NO2;
-          T x = band[(size_t)kk * NC + r];
+        if (r < NB) {
+          sE[j][side][r] = band[(size_t)kk * NC + MS * r];
+        } else if (r < NB + PK) {
+          const int p = r - NB, m = p / NO2, pl = p % NO2;
+          T x = PAIR ? pir[(size_t)kk * PK + p] : band[(size_t)kk * NC + NO + p];
           if (side == 0) {
             unpack_store<T, NO>(&sP[j][m][0], pl, x);
           } else {
@@ -171,16 +179,17 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
             if (ch == 1 && pl >= NO && ((pl - NO) & 1)) x = -x;
             sX[j][p] = x;
           }
-        } else if (r < NC + NO) {
-          sK[j][side][r - NC] = kv[(size_t)kk * NO + (r - NC)];
+        } else if (r < NB + PK + NB) {
+          sK[j][side][r - NB - PK] = kv[(size_t)kk * NO + MS * (r - NB - PK)];
         } else if constexpr (SHELL) {
-          sC[j][side][r - NC - NO] = cvp[(size_t)kk * 2 * NO + (r - NC - NO)];
+          const int c = r - 2 * NB - PK;  // (a_m, b_m) of summed band c / 2
+          sC[j][side][c] = cvp[(size_t)kk * 2 * NO + 2 * MS * (c >> 1) + (c & 1)];
         }
       }
       __syncthreads();
       // loop kernels L_mn = sg * DD[K](e_m(k), -sg e_n(k'))
-      if (tid < KT * NO2) {
-        const int j = tid / NO2, m = (tid / NO) % NO, n = tid % NO;
+      if (tid < KT * NB * NB) {
+        const int j = tid / (NB * NB), m = (tid / NB) % NB, n = tid % NB;
         const T x = sE[j][0][m], y = -sg * sE[j][1][n];
         T l = sg * divided_difference(x, y, sK[j][0][m], -sg * sK[j][1][n], lam, dd_scheme(SCHEME), deriv);
         // shell scheme: times a_m(k) b_n(k') + b_m(k) a_n(k')
@@ -194,7 +203,7 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
         const int j = i / PK, mp = i % PK, m = mp / NO2, pl = mp % NO2;
         T acc = T(0);
 #pragma unroll
-        for (int n = 0; n < NO; ++n) acc = fma(sL[j][m][n], sX[j][n * NO2 + pl], acc);
+        for (int n = 0; n < NB; ++n) acc = fma(sL[j][m][n], sX[j][n * NO2 + pl], acc);
         unpack_store<T, NO>(&sW[j][m][0], pl, acc);
       }
       __syncthreads();
@@ -204,7 +213,7 @@ __global__ __launch_bounds__(NTHR) void loop_gen_kernel(const T *__restrict__ ba
         const T *ph = phy + (size_t)(ky0 + j) * (2 * NDY);
         cx<T> M = cmake(T(0), T(0));
 #pragma unroll
-        for (int m = 0; m < NO; ++m) {
+        for (int m = 0; m < NB; ++m) {
           const c2<T> P = sP[j][m][xo], Wv = sW[j][m][yo];
           cfma(M, cmake(P.re, P.im), cmake(Wv.re, Wv.im));
         }
@@ -272,19 +281,28 @@ static hipError_t launch_gen(const LoopArgs &a, hipStream_t st) {
   const int NP = (a.n_pairs + NTHR - 1) / NTHR;
   dim3 grid(a.n_q * a.n_ch * NP), block(NTHR);
   const T *band = (const T *)a.band, *kv = (const T *)a.kv, *phy = (const T *)a.phy, *cvp = (const T *)a.cv;
+  const T *pir = f64 ? (const T *)a.pir64 : (const T *)a.pir;
   if (a.scheme == CUT_SHELL && !cvp) return hipErrorInvalidValue;
-#define TUFRG_GEN_LAUNCH(S)                                                                                          \
-  hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, S, NTHR, KT>), grid, block, 0, st, band, kv, cvp, a.tw, phy, a.pairs, \
-                     a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.rows, a.ch_first, a.n_ch, a.ndx,         \
-                     (T)a.lam, a.deriv, (T *)a.partial)
-  if (a.scheme == CUT_TEMPERATURE)
-    TUFRG_GEN_LAUNCH(CUT_TEMPERATURE);
-  else if (a.scheme == CUT_OMEGA)
-    TUFRG_GEN_LAUNCH(CUT_OMEGA);
-  else if (a.scheme == CUT_SHELL)
-    TUFRG_GEN_LAUNCH(CUT_SHELL);
-  else
+  if (a.pair && !pir) return hipErrorInvalidValue;
+#define TUFRG_GEN_LAUNCH(S, P)                                                                                   \
+  hipLaunchKernelGGL((loop_gen_kernel<T, 6, NDY, S, NTHR, KT, P>), grid, block, 0, st, band, pir, kv, cvp, a.tw, \
+                     phy, a.pairs, a.n_pairs, a.Lq, a.n_ref, a.Lf, NP, a.q_first, a.n_q, a.rows, a.ch_first,     \
+                     a.n_ch, a.ndx, (T)a.lam, a.deriv, (T *)a.partial)
+#define TUFRG_GEN_SCHEMES(P)               \
+  if (a.scheme == CUT_TEMPERATURE)         \
+    TUFRG_GEN_LAUNCH(CUT_TEMPERATURE, P);  \
+  else if (a.scheme == CUT_OMEGA)          \
+    TUFRG_GEN_LAUNCH(CUT_OMEGA, P);        \
+  else if (a.scheme == CUT_SHELL)          \
+    TUFRG_GEN_LAUNCH(CUT_SHELL, P);        \
+  else                                     \
     return hipErrorInvalidValue;
+  if (a.pair) {
+    TUFRG_GEN_SCHEMES(true)
+  } else {
+    TUFRG_GEN_SCHEMES(false)
+  }
+#undef TUFRG_GEN_SCHEMES
 #undef TUFRG_GEN_LAUNCH
   return hipGetLastError();
 }

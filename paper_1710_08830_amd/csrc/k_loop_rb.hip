@@ -692,21 +692,23 @@ hipError_t launch_loop_rb_apre(int ndy, int pair, const float *band, const float
   return hipGetLastError();
 }
 
-// pair sums of the projectors of bands (0, 1), (2, 3), (4, 5), FP64 summed and
-// rounded to FP32: pir[k][p][alpha] from the component-major band data
-__global__ void pair_pi_kernel(int Nf, const double *__restrict__ band, float *__restrict__ pir) {
+// pair sums of the projectors of bands (0, 1), (2, 3), (4, 5), summed in FP64
+// (and rounded to FP32): pir[k][p][alpha] from the component-major band data
+__global__ void pair_pi_kernel(int Nf, const double *__restrict__ band, float *__restrict__ pir,
+                               double *__restrict__ pir64) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (long long)Nf * 3 * NA) return;
   const int k = (int)(i / (3 * NA)), r = (int)(i % (3 * NA)), p = r / NA, alpha = r % NA;
   const double a = band[(size_t)(NO + 2 * p * NA + alpha) * Nf + k];
   const double b = band[(size_t)(NO + (2 * p + 1) * NA + alpha) * Nf + k];
-  pir[i] = (float)(a + b);
+  if (pir) pir[i] = (float)(a + b);
+  if (pir64) pir64[i] = a + b;
 }
 
-hipError_t launch_pair_pi(int Nf, const double *band, float *pir, hipStream_t st) {
-  if (!band || !pir || Nf < 1) return hipErrorInvalidValue;
+hipError_t launch_pair_pi(int Nf, const double *band, float *pir, double *pir64, hipStream_t st) {
+  if (!band || (!pir && !pir64) || Nf < 1) return hipErrorInvalidValue;
   const long long n = (long long)Nf * 3 * NA;
-  hipLaunchKernelGGL(pair_pi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Nf, band, pir);
+  hipLaunchKernelGGL(pair_pi_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, Nf, band, pir, pir64);
   return hipGetLastError();
 }
 

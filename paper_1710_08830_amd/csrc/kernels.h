@@ -49,7 +49,8 @@ struct LoopArgs {
                                // more orbitals [Nf][n_o][2] = (a_m, b_m); like band
   int pair = 0;                // six spin-orbitals on the matrix cores: bands (0,1), (2,3), (4,5)
                                // degenerate at every k, summed by pairs
-  const float *pir = nullptr;  // with pair: [Nf][3][36] pair sums of the packed projectors (FP32)
+  const float *pir = nullptr;     // with pair: [Nf][3][36] pair sums of the packed projectors (FP32)
+  const double *pir64 = nullptr;  // the same in FP64 (six spin-orbitals on the vector units, FP64)
 };
 hipError_t launch_loop(const LoopArgs &a, hipStream_t st);
 // several two-orbital instances of one precision in fused launches (one per
@@ -76,7 +77,8 @@ hipError_t launch_loop_gen(const LoopArgs &a, hipStream_t st);
 size_t loop_rb_apre_bytes(int ndy, int Lf, int pair);
 hipError_t launch_loop_rb_apre(int ndy, int pair, const float *band, const float *pir, const float *phy, int Lf,
                                void *apre, hipStream_t st);
-hipError_t launch_pair_pi(int Nf, const double *band, float *pir, hipStream_t st);
+// pair sums of the packed projectors into pir (FP32) and/or pir64 (FP64; either may be null)
+hipError_t launch_pair_pi(int Nf, const double *band, float *pir, double *pir64, hipStream_t st);
 hipError_t launch_loop_rb(const LoopArgs &a, int ch, const void *apre, float *Y, hipStream_t st);
 hipError_t launch_loop_rb_sums(const LoopArgs &a, const float *Y, double *lamb, const int *hmap, int nD,
                                double *dst, hipStream_t st);

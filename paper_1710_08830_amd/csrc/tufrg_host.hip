@@ -127,7 +127,8 @@ struct tufrg_ctx {
   // pairs), found at creation; then the loops sum them by pairs unless
   // pair_enable is cleared
   int bands_paired = 0, pair_enable = 1;
-  float *d_pir32 = nullptr;  // [Nf][3][36] pair sums of the packed projectors
+  float *d_pir32 = nullptr;   // [Nf][3][36] pair sums of the packed projectors (FP32, BF16X3)
+  double *d_pir64 = nullptr;  // the same in FP64
   size_t partial_cap = 0;  // doubles allocated at d_partial
   unsigned long long *h_sbits = nullptr;       // pinned
   // Euler steps in HIP graphs: the executable graph, the capture stream (the
@@ -606,7 +607,7 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
   if (c->n_o > 2) CHIP(launch_to_kmajor(c->n_o + c->n_o * c->no2, (int)Nf, c->d_band64, c->d_bandk64, c->d_bandk32, st));
   if (c->n_o == 2) CHIP(launch_pi4((int)Nf, c->d_band64, c->d_pi4_64, c->d_pi4_32, st));
   CHIP(hipStreamSynchronize(st));
-  if (c->n_o == 6 && c->prec == TUFRG_BF16X3 && c->Lf % 2 == 0) {
+  if (c->n_o == 6) {
     // Kramers pairs: e_{2p} = e_{2p+1} at every k up to the eigensolver's
     // rounding (sorted bands); then the sum over bands in the loops groups
     // exactly into three pairs with the summed projectors
@@ -617,8 +618,11 @@ extern "C" tufrg_status tufrg_create(const tufrg_model *m, const tufrg_setup *s,
     for (int p = 0; p < 3; ++p)
       for (size_t k = 0; k < Nf; ++k) split = std::max(split, std::fabs(e[(2 * p) * Nf + k] - e[(2 * p + 1) * Nf + k]));
     if (split <= 1e-10 * std::max(1.0, emax)) {
-      CTRY(dalloc(c, &c->d_pir32, Nf * 3 * 36));
-      CHIP(launch_pair_pi((int)Nf, c->d_band64, c->d_pir32, st));
+      if (c->prec == TUFRG_FP64)
+        CTRY(dalloc(c, &c->d_pir64, Nf * 3 * 36));
+      else
+        CTRY(dalloc(c, &c->d_pir32, Nf * 3 * 36));
+      CHIP(launch_pair_pi((int)Nf, c->d_band64, c->d_pir32, c->d_pir64, st));
       CHIP(hipStreamSynchronize(st));
       c->bands_paired = 1;
     }
@@ -654,6 +658,13 @@ extern "C" tufrg_status tufrg_band_data(tufrg_ctx *c, double *e, tufrg_c64 *Pi) 
   return TUFRG_OK;
 }
 
+// the loops sum Kramers pairs: six-orbital bands found paired, pairing not
+// switched off, and for the matrix-core loop an even fine mesh (ky pairs)
+static int pairs_active(const tufrg_ctx *c) {
+  if (c->n_o != 6 || !c->bands_paired || !c->pair_enable) return 0;
+  return c->prec == TUFRG_BF16X3 ? c->Lf % 2 == 0 : 1;
+}
+
 static LoopArgs loop_args(tufrg_ctx *c, double lam, int deriv, int ch_first, int n_ch) {
   LoopArgs a;
   a.n_o = c->n_o;
@@ -666,8 +677,9 @@ static LoopArgs loop_args(tufrg_ctx *c, double lam, int deriv, int ch_first, int
   a.nkyb = c->nkyb;
   a.nkxc = c->nkxc;
   a.kxr = c->mfma_kxr;
-  a.pair = c->prec == TUFRG_BF16X3 && c->bands_paired && c->pair_enable;
+  a.pair = pairs_active(c);
   a.pir = c->d_pir32;
+  a.pir64 = c->d_pir64;
   a.ch_first = ch_first;
   a.n_ch = n_ch;
   a.q_first = 0;
@@ -739,7 +751,7 @@ static void dfree(tufrg_ctx *c, void *p);
 // the matrix-core loop's A operand for the current pairing (rebuilt when the
 // pairing changed since it was computed)
 static tufrg_status ensure_apre(tufrg_ctx *c) {
-  const int pair = c->bands_paired && c->pair_enable;
+  const int pair = pairs_active(c);
   if (c->d_apre && c->apre_pair != pair) {
     HIPCHK(c, hipStreamSynchronize(c->st));
     dfree(c, c->d_apre);
@@ -905,7 +917,7 @@ static std::string tune_key(const tufrg_ctx *c) {
   std::snprintf(buf, sizeof(buf),
                 "%s:%dcu|n_o=%d|prec=%d|scheme=%d|Lq=%d|n_ref=%d|n_ff=%d|nD=%d|ndx=%d|ndy=%d|pairs=%d",
                 arch.c_str(), cus, c->n_o, c->prec, c->scheme, c->Lq, c->n_ref, c->n_ff, c->nD, c->ndx, c->ndy,
-                c->bands_paired && c->pair_enable);
+                pairs_active(c));
   return buf;
 }
 
@@ -1015,7 +1027,7 @@ extern "C" tufrg_status tufrg_pair_bands(tufrg_ctx *c, int32_t enable, int32_t *
   c->pair_enable = enable;
   // an A operand already built is rebuilt now, not inside a later flow
   if (c->d_apre) TRY(ensure_apre(c));
-  if (active) *active = c->bands_paired && c->pair_enable;
+  if (active) *active = pairs_active(c);
   return TUFRG_OK;
 }
 

@@ -1,7 +1,9 @@
-"""Kramers-paired BF16X3 loops: for six bands degenerate in pairs at every k
-(time reversal with inversion) the loops sum each pair first.  Checked against
-the six-band evaluation on the same context and against the oracle; a
-Zeeman-split model and an odd fine mesh keep the six bands."""
+"""Kramers-paired six-orbital loops: for six bands degenerate in pairs at
+every k (time reversal with inversion) the loops sum each pair first (BF16X3
+on the matrix cores, FP32 and FP64 on the vector units).  Checked against the
+six-band evaluation on the same context and against the oracle; a
+Zeeman-split model keeps the six bands, and so does an odd fine mesh in
+BF16X3 (its kernel pairs ky points too)."""
 
 import os
 import sys
@@ -43,9 +45,9 @@ def _case(zeeman=0.0, Lq=6, n_ref=3, cutoff="omega", n_ff=9):
                 cutoff=cutoff, temperature=0.06 if cutoff == "shell" else None)
 
 
-def _ctx(T, c):
+def _ctx(T, c, prec="bf16x3"):
     return T.Context(c["hop"][0], c["hop"][1], c["mu"], c["V0"], c["ff"], c["Lq"], c["n_ref"], c["cutoff"],
-                     "bf16x3", temperature=c["temperature"])
+                     prec, temperature=c["temperature"])
 
 
 def _bubbles(T, ctx, lam, deriv):
@@ -108,4 +110,30 @@ def test_bands_that_are_not_paired_keep_six_bands(T, what):
     got = _bubbles(T, ctx, 0.35, 1)
     for g, r in zip(got, _oracle(c, 0.35, 1)):
         assert rel(g, r) < TOL
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+@pytest.mark.parametrize("cutoff", ["temperature", "shell"])
+def test_paired_vector_loops_equal_the_six_band_loops_and_the_oracle(T, prec, tol, cutoff):
+    """The vector-unit kernels: an odd fine mesh (L_f = 15) pairs as well."""
+    c = _case(Lq=5, n_ref=3, cutoff=cutoff)
+    ctx = _ctx(T, c, prec)
+    print(f"pairs: t2g S9 5x5 refined 3x, {prec}, {cutoff}", flush=True)
+    assert T.tufrg_pair_bands(ctx, True) is True
+    paired = _bubbles(T, ctx, 0.35, 1)
+    assert T.tufrg_pair_bands(ctx, False) is False
+    six = _bubbles(T, ctx, 0.35, 1)
+    for p, s_, r in zip(paired, six, _oracle(c, 0.35, 1)):
+        print(f"paired vs six bands {rel(p, s_):.2e}, paired vs oracle {rel(p, r):.2e}")
+        assert rel(p, s_) < tol and rel(p, r) < tol and rel(s_, r) < tol
+    ctx.close()
+
+
+def test_zeeman_split_vector_loops_keep_six_bands(T):
+    c = _case(zeeman=0.05)
+    ctx = _ctx(T, c, "fp64")
+    assert T.tufrg_pair_bands(ctx, True) is False
+    for g, r in zip(_bubbles(T, ctx, 0.35, 1), _oracle(c, 0.35, 1)):
+        assert rel(g, r) < 1e-10
     ctx.close()

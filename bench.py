@@ -84,8 +84,15 @@ def _box(ff):
 
 # sources of the loop kernel per precision, and the host function that sets
 # its launch shape (chunking) in tufrg_host.hip
-LOOP_SOURCES = {"bf16x3": (("k_loop_rb.hip", "common.h"), ("loops_range_mfma", "ensure_apre"))}
-LOOP_SOURCES_DEFAULT = (("k_loop.hip", "k_loop_gen.hip", "common.h"), ("loops_range",))
+# the loop kernel of a workload: BF16X3 (six spin-orbitals, matrix cores),
+# two spin-orbitals, or six on the vector units
+LOOP_SOURCES = {"bf16x3": (("k_loop_rb.hip", "common.h"), ("loops_range_mfma", "ensure_apre")),
+                "no2": (("k_loop.hip", "common.h"), ("loops_range",)),
+                "gen": (("k_loop_gen.hip", "common.h"), ("loops_range",))}
+
+
+def _loop_kind(workload, prec):
+    return "bf16x3" if prec == "bf16x3" else ("gen" if workload.startswith("t2g") else "no2")
 
 
 def _code_only(text):
@@ -109,10 +116,10 @@ def _host_function_text(name):
     return src[i:j + 3]
 
 
-def _loop_source_hash(prec):
-    """Hash of the loop kernels' sources and of the host functions that shape
-    their launches, comments and layout aside."""
-    files, fns = LOOP_SOURCES.get(prec, LOOP_SOURCES_DEFAULT)
+def _loop_source_hash(workload, prec):
+    """Hash of the loop kernel's sources and of the host functions that shape
+    its launches, comments and layout aside."""
+    files, fns = LOOP_SOURCES[_loop_kind(workload, prec)]
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_1710_08830_amd", "csrc", f)) as fh:
@@ -130,7 +137,7 @@ def _traffic(workload, prec):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != _loop_source_hash(prec):
+    if t.get("source_sha256") != _loop_source_hash(workload, prec):
         return None
     return float(t["hbm_bytes_per_launch"])
 
@@ -849,7 +856,7 @@ def summarize_traffic(args):
         "kernel": names[0] if len(names) == 1 else names,
         "workload": args.workload,
         "precision": args.prec,
-        "source_sha256": _loop_source_hash(args.prec),
+        "source_sha256": _loop_source_hash(args.workload, args.prec),
         "fetch_kib_per_dispatch": f_kib,
         "write_kib_per_dispatch": w_kib,
         "dispatches": len(fetch),

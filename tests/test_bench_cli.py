@@ -21,7 +21,7 @@ def test_more_than_one_gpu_is_refused(n):
 def test_traffic_record_is_dropped_when_the_loop_source_changes(monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
-    monkeypatch.setattr(bench, "_loop_source_hash", lambda prec: "0" * 64)
+    monkeypatch.setattr(bench, "_loop_source_hash", lambda workload, prec: "0" * 64)
     assert bench._traffic("rashba_s9_L24", "fp32") is None
 
 
@@ -61,7 +61,7 @@ def test_traffic_summary_from_counter_csvs(tmp_path, monkeypatch):
     import bench
     (tmp_path / "profiles").mkdir()
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    monkeypatch.setattr(bench, "_loop_source_hash", lambda prec: "ab" * 32)
+    monkeypatch.setattr(bench, "_loop_source_hash", lambda workload, prec: "ab" * 32)
     dirs = [tmp_path / n for n in ("f", "w", "cf", "cw")]
     for d in dirs:
         d.mkdir()

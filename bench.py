@@ -412,7 +412,7 @@ def six_orbital_line(T, torch, w, prec, K, W, fp64_steps=2, surrogate=True, n_ro
     B, Nq, Nf, nD = ctx.B, ctx.Nq, ctx.Nf, ctx.n_dR
     # Kramers-paired bands (the default wherever found): the loops sum three
     # bands, and the credited work counts three
-    paired = prec == "bf16x3" and T.tufrg_pair_bands(ctx, not six_bands)
+    paired = w["n_o"] == 6 and T.tufrg_pair_bands(ctx, not six_bands)
     n_b = 3 if paired else w["n_o"]
     P = torch.zeros((Nq, B, B), dtype=torch.complex128, device=dev)
     C = torch.zeros_like(P)
@@ -975,7 +975,7 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="autotune the loop kernels' launch shape before timing (cache: $TUFRG_TUNE_CACHE)")
     ap.add_argument("--six-bands", action="store_true",
-                    help="BF16X3: sum all six bands even where they are Kramers pairs")
+                    help="six spin-orbitals: sum all six bands even where they are Kramers pairs")
     ap.add_argument("--temperature", type=float, default=0.02,
                     help="fixed temperature of the momentum-shell regulator")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
